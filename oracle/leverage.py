@@ -1,0 +1,71 @@
+"""QR of a sketch, its triangular inverse, and leverage scores, plain FP64.
+
+Paper passages followed (arXiv 2203.02798):
+
+* Algorithm ``ls_approximate_drineas``: sketch A, factor the sketch, and take
+  squared row norms of A times the inverse factor (Algorithm
+  ``squared_row_norms``).  The paper factors with an SVD (V Sigma^{-1}); here
+  the factor is the R of a QR of the sketch, which spans the same
+  orthogonaliser: A R^{-1} and A V Sigma^{-1} differ by an orthogonal d x d
+  matrix, so the row norms agree.
+* Algorithm ``ls_direct``: exact leverage scores theta_i = ||e_i^T U||^2 for an
+  orthonormal basis U of range(A) (computed here from a thin QR of A).
+
+Reading: full column rank is assumed (the paper's "truncate if needed" is not
+applied); R is normalised to a non-negative diagonal.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from .gram import rownorms_sq
+from .sketch import sketch_gcs
+
+
+def qr_r(c):
+    """Upper-triangular R of C = Q R (LAPACK Householder QR), rows scaled so
+    that diag(R) >= 0."""
+    c = np.asarray(c, dtype=np.float64)
+    r = np.linalg.qr(c, mode="r")
+    r = np.triu(r[: c.shape[1], :])
+    sgn = np.where(np.diag(r) < 0, -1.0, 1.0)
+    return r * sgn[:, None]
+
+
+def tri_inv(r):
+    """R^{-1} for an upper-triangular R (triangular solve against I)."""
+    d = r.shape[0]
+    return sla.solve_triangular(r, np.eye(d), lower=False)
+
+
+def leverage_sketched(a, m, r, seed):
+    """theta~_i = ||e_i^T A R^{-1}||^2 with R from QR(G S A)."""
+    c = sketch_gcs(a, m, r, seed)
+    rr = qr_r(c)
+    return rownorms_sq(1.0, a, tri_inv(rr)), rr
+
+
+def leverage_sketched_svd(a, m, r, seed):
+    """Same quantity by the paper's SVD route: ||e_i^T A V Sigma^{-1}||^2."""
+    c = sketch_gcs(a, m, r, seed)
+    _, s, vt = np.linalg.svd(c, full_matrices=False)
+    return rownorms_sq(1.0, a, vt.T / s[None, :])
+
+
+def leverage_exact(a):
+    """Exact leverage scores from a thin QR of A (dense copy for sparse A)."""
+    if sp.issparse(a):
+        a = a.toarray()
+    q, _ = np.linalg.qr(np.asarray(a, dtype=np.float64), mode="reduced")
+    return np.einsum("ij,ij->i", q, q)
+
+
+def sketch_distortion(a, m, r, seed):
+    """Singular values of G S U for an orthonormal basis U of range(A); the
+    subspace-embedding distortion is max |sigma - 1|."""
+    if sp.issparse(a):
+        a = a.toarray()
+    q, _ = np.linalg.qr(np.asarray(a, dtype=np.float64), mode="reduced")
+    return np.linalg.svd(sketch_gcs(q, m, r, seed), compute_uv=False)

@@ -1,0 +1,226 @@
+"""CountSketch, Gaussian and combined (CountGauss) sketches in plain FP64.
+
+Paper passages followed (arXiv 2203.02798):
+
+* Definition 3 (CountSketch): S in R^{r x n} has, for every column i, the
+  single non-zero S[h(i), i] = sigma_i; h and sigma are treated as fully
+  independent and uniform.
+* Figure ``countsketch_vector_example``: the signed vector representation,
+  v_k = +-|row|, with S[|v_k|, k] = sign(v_k) (1-based rows).
+* Algorithm ``bcs_multiply``: S*A stored as a dense row-major r x d array.
+* Algorithm ``countgauss_multiply``: G*S*A computed in batches of buckets; a
+  batch forms B = S_i*A, draws a fresh Gaussian block G_i and accumulates
+  C += G_i*B.  ``csrcgs``/``rmcgs`` (section "Software") scale G by 1/sqrt(m)
+  and return S*A when m = 0.
+
+Readings where the paper leaves the choice open (it uses per-thread STL
+engines, so its streams are not reproducible across thread counts):
+
+* hash: x = Philox4x32-10(counter=(i mod 2^32, i div 2^32, 0, 0),
+  key=(seed mod 2^32, seed div 2^32)); h(i) = floor((x1*2^32 + x0) * r / 2^64)
+  (a 64-bit multiply-high range reduction, bias at most r/2^64);
+  sigma_i = +1 if x2 is even, else -1.
+* Gaussian: for bucket column b and row a of G, q = b div 4 and
+  x = Philox4x32-10(counter=(q mod 2^32, q div 2^32, a, 1), key as above);
+  u_k = (x_k + 1/2) * 2^-32 lies in (0, 1); Box-Muller gives
+  z0, z1 = sqrt(-2 ln u0) * (cos, sin)(2 pi u1) and
+  z2, z3 = sqrt(-2 ln u2) * (cos, sin)(2 pi u3);  G[a, b] = z_{b mod 4} / sqrt(m)
+  (variance 1/m, i.e. N(0, 1/sqrt(m)) in the paper's (mean, std) notation).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .philox import philox4x32, seed_key
+
+TWO_M32 = 2.0 ** -32
+
+
+# ----------------------------------------------------------------------------
+# CountSketch hash (Definition 3)
+# ----------------------------------------------------------------------------
+def cs_hash(n, r, seed, row0=0):
+    """Bucket h[i] in [0, r) and sign sigma[i] in {+1, -1} for rows
+    row0 .. row0+n-1.  Returns (h int64, sigma int8)."""
+    if r < 1 or r >= 2 ** 32:
+        raise ValueError("r must be in [1, 2^32)")
+    i = np.arange(row0, row0 + n, dtype=np.uint64)
+    ctr = np.zeros((n, 4), dtype=np.uint64)
+    ctr[:, 0] = i & np.uint64(0xFFFFFFFF)
+    ctr[:, 1] = i >> np.uint64(32)
+    x = philox4x32(ctr, seed_key(seed)).astype(np.uint64)
+    # floor((x1*2^32 + x0) * r / 2^64) without 128-bit integers:
+    # = (x1*r + floor(x0*r / 2^32)) div 2^32, all terms below 2^64 for r < 2^32.
+    rr = np.uint64(r)
+    h = (x[:, 1] * rr + ((x[:, 0] * rr) >> np.uint64(32))) >> np.uint64(32)
+    sigma = np.where((x[:, 2] & np.uint64(1)) == 0, 1, -1).astype(np.int8)
+    return h.astype(np.int64), sigma
+
+
+def cs_hash_bigint(i, r, seed):
+    """Same hash for one row with Python integers (exact 128-bit product)."""
+    ctr = np.array([[i & 0xFFFFFFFF, i >> 32, 0, 0]], dtype=np.uint64)
+    x = [int(v) for v in philox4x32(ctr, seed_key(seed))[0]]
+    h = ((x[1] << 32 | x[0]) * r) >> 64
+    return h, (1 if x[2] % 2 == 0 else -1)
+
+
+def vector_representation(h, sigma):
+    """Signed 1-based vector v with S[|v_k|-1, k] = sign(v_k)."""
+    return (np.asarray(h, dtype=np.int64) + 1) * np.asarray(sigma, np.int64)
+
+
+def dense_from_vector(v, r):
+    """Explicit r x n CountSketch from its vector representation."""
+    v = np.asarray(v, dtype=np.int64)
+    s = np.zeros((r, v.size))
+    for k, vk in enumerate(v):
+        s[abs(vk) - 1, k] = 1.0 if vk > 0 else -1.0
+    return s
+
+
+def countsketch_dense(n, r, seed):
+    """Explicit dense S (r x n); for tiny inputs only."""
+    h, sg = cs_hash(n, r, seed)
+    s = np.zeros((r, n))
+    s[h, np.arange(n)] = sg
+    return s
+
+
+def countsketch_sparse(n, r, seed):
+    """S as a SciPy CSR matrix (r x n, exactly n non-zeros)."""
+    h, sg = cs_hash(n, r, seed)
+    return sp.csr_matrix((sg.astype(np.float64), (h, np.arange(n))),
+                         shape=(r, n))
+
+
+def _as_f64(a):
+    if sp.issparse(a):
+        return sp.csr_matrix(a, dtype=np.float64)
+    return np.asarray(a, dtype=np.float64)
+
+
+def sketch_cs(a, r, seed):
+    """S*A in FP64 (Algorithm ``bcs_multiply``); dense r x d result."""
+    a = _as_f64(a)
+    n = a.shape[0]
+    s = countsketch_sparse(n, r, seed)
+    out = s @ a
+    if sp.issparse(out):
+        out = out.toarray()
+    return np.ascontiguousarray(out)
+
+
+def bucket_occupancy(n, r, seed):
+    """Rows per bucket (the length of each bucket's row list)."""
+    h, _ = cs_hash(n, r, seed)
+    return np.bincount(h, minlength=r)
+
+
+# ----------------------------------------------------------------------------
+# Gaussian matrix (generated in column blocks, never whole)
+# ----------------------------------------------------------------------------
+def gaussian_normals(m, b0, b1, seed):
+    """Unscaled standard normals Z[a, b] for rows a < m, buckets b0 <= b < b1."""
+    if b1 <= b0 or m == 0:
+        return np.zeros((m, max(b1 - b0, 0)))
+    q0, q1 = b0 // 4, (b1 + 3) // 4
+    q = np.arange(q0, q1, dtype=np.uint64)
+    a = np.arange(m, dtype=np.uint64)
+    ctr = np.zeros((m, q.size, 4), dtype=np.uint64)
+    ctr[:, :, 0] = (q & np.uint64(0xFFFFFFFF))[None, :]
+    ctr[:, :, 1] = (q >> np.uint64(32))[None, :]
+    ctr[:, :, 2] = a[:, None]
+    ctr[:, :, 3] = 1
+    x = philox4x32(ctr, seed_key(seed)).astype(np.float64)
+    u = (x + 0.5) * TWO_M32
+    rho0 = np.sqrt(-2.0 * np.log(u[..., 0]))
+    rho2 = np.sqrt(-2.0 * np.log(u[..., 2]))
+    z = np.empty((m, q.size, 4))
+    z[..., 0] = rho0 * np.cos(2.0 * np.pi * u[..., 1])
+    z[..., 1] = rho0 * np.sin(2.0 * np.pi * u[..., 1])
+    z[..., 2] = rho2 * np.cos(2.0 * np.pi * u[..., 3])
+    z[..., 3] = rho2 * np.sin(2.0 * np.pi * u[..., 3])
+    z = z.reshape(m, q.size * 4)
+    return z[:, b0 - 4 * q0: b1 - 4 * q0]
+
+
+def gaussian_block(m, b0, b1, seed):
+    """Scaled Gaussian block G[:, b0:b1] = Z / sqrt(m)."""
+    return gaussian_normals(m, b0, b1, seed) / np.sqrt(m)
+
+
+def sketch_gcs(a, m, r, seed, batch=4096):
+    """C = G*(S*A) (Algorithm ``countgauss_multiply``): S*A formed once, then
+    C accumulated over bucket batches with a fresh block of G each.
+    m = 0 returns S*A."""
+    sa = sketch_cs(a, r, seed)
+    if m == 0:
+        return sa
+    c = np.zeros((m, sa.shape[1]))
+    for b0 in range(0, r, batch):
+        b1 = min(r, b0 + batch)
+        c += gaussian_block(m, b0, b1, seed) @ sa[b0:b1]
+    return c
+
+
+# ----------------------------------------------------------------------------
+# Reduced-precision operand formats (for the BF16 / FP8 Gaussian GEMM)
+# ----------------------------------------------------------------------------
+def round_to_bits(x, mant_bits, emin, emax_val=None):
+    """Round-to-nearest-even of FP64 values onto a binary format with
+    ``mant_bits`` fraction bits and minimum normal exponent ``emin``
+    (subnormals below it).  Values beyond ``emax_val`` saturate to it."""
+    x = np.asarray(x, dtype=np.float64)
+    ax = np.abs(x)
+    # exact binary exponent: ax = f * 2^fe with f in [1/2, 1)
+    _, fe = np.frexp(ax)
+    e = np.where(ax > 0, fe - 1, 0).astype(np.float64)
+    e = np.maximum(e, emin)
+    quantum = np.ldexp(1.0, (e - mant_bits).astype(np.int64))
+    y = np.round(x / quantum) * quantum  # np.round: half to even
+    if emax_val is not None:
+        y = np.clip(y, -emax_val, emax_val)
+    return y
+
+
+def to_bf16(x):
+    """Round FP64 to bfloat16 (8-bit exponent, 7 fraction bits), RNE."""
+    return round_to_bits(x, 7, -126)
+
+
+def to_e4m3(x):
+    """Round FP64 to OCP FP8 e4m3fn (bias 7, 3 fraction bits, max 448),
+    RNE with saturation."""
+    return round_to_bits(x, 3, -6, 448.0)
+
+
+def bf16_limbs(x, nlimbs=2):
+    """Split x into ``nlimbs`` bfloat16 limbs: l0 = bf16(x),
+    l1 = bf16(x - l0), ...  (Ozaki-style error-free splitting up to the last
+    limb's rounding)."""
+    x = np.asarray(x, dtype=np.float64)
+    limbs = []
+    rest = x.copy()
+    for _ in range(nlimbs):
+        l = to_bf16(rest)
+        limbs.append(l)
+        rest = rest - l
+    return limbs
+
+
+def sketch_gcs_bf16_reference(a, m, r, seed, nlimbs=2, batch=4096):
+    """Quantisation-aware reference of the BF16 Gaussian GEMM: the exact (FP64)
+    product of the BF16-rounded unscaled normals with the BF16 limb
+    decomposition of S*A, then scaled by 1/sqrt(m).  Comparing the device
+    result with this isolates the kernel's arithmetic from the format loss."""
+    sa = sketch_cs(a, r, seed)
+    limbs = bf16_limbs(sa, nlimbs)
+    saq = np.sum(limbs, axis=0)
+    c = np.zeros((m, sa.shape[1]))
+    for b0 in range(0, r, batch):
+        b1 = min(r, b0 + batch)
+        zq = to_bf16(gaussian_normals(m, b0, b1, seed))
+        c += zq @ saq[b0:b1]
+    return c / np.sqrt(m)

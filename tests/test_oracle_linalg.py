@@ -1,0 +1,121 @@
+"""Pins of the oracle's Gram matrix, squared row norms, QR / leverage scores and
+least-squares solvers: the paper's literal CSR loops on tiny inputs, closed
+forms (trace, B = I, exact leverage), the leverage-score invariants of a
+sketched basis, and LAPACK least squares."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import gram as og
+from oracle import leverage as olev
+from oracle import lsq as olsq
+from oracle import sketch as osk
+
+
+def test_gram_literal_loop_equals_blas():
+    a = synth.csr_integer(40, 9, 0.35, seed=3)
+    np.testing.assert_array_equal(og.gram_csr_literal(a), og.gram(1.0, a))
+    np.testing.assert_array_equal(og.gram(1.0, a), og.gram(1.0, a.toarray()))
+
+
+def test_gram_closed_forms_and_alpha_beta():
+    a = synth.dense_gaussian(100, 6, seed=1)
+    g = og.gram(1.0, a)
+    assert np.allclose(g, g.T, rtol=0, atol=0)
+    assert abs(np.trace(g) - np.linalg.norm(a) ** 2) < 1e-12 * np.trace(g)
+    c = synth.dense_gaussian(6, 6, seed=2)
+    np.testing.assert_allclose(og.gram(2.5, a, -0.5, c), 2.5 * g - 0.5 * c,
+                               rtol=1e-14, atol=1e-12)
+    nan = np.full((6, 6), np.nan)
+    assert np.all(np.isfinite(og.gram(1.0, a, 0.0, nan)))
+    # Gram of an orthonormal basis is the identity
+    q, _ = np.linalg.qr(a)
+    np.testing.assert_allclose(og.gram(1.0, q), np.eye(6), atol=1e-14)
+
+
+def test_rownorms_identity_and_literal():
+    a = synth.csr_integer(50, 8, 0.4, seed=4)
+    ad = a.toarray()
+    np.testing.assert_array_equal(og.rownorms_sq(1.0, a, np.eye(8)),
+                                  (ad ** 2).sum(axis=1))
+    b = synth.dense_integer(8, 5, seed=5)
+    np.testing.assert_array_equal(og.rownorms_sq_csr_literal(1.0, a, b),
+                                  og.rownorms_sq(1.0, ad, b))
+    x = np.arange(50.0)
+    np.testing.assert_array_equal(og.rownorms_sq(2.0, ad, b, 3.0, x),
+                                  2.0 * og.rownorms_sq(1.0, ad, b) + 3.0 * x)
+
+
+def test_rownorms_exact_leverage_via_exact_r():
+    a = synth.dense_gaussian(300, 7, seed=6)
+    r = np.linalg.qr(a, mode="r")
+    theta = og.rownorms_sq(1.0, a, np.linalg.inv(r))
+    np.testing.assert_allclose(theta, olev.leverage_exact(a), rtol=1e-11, atol=1e-14)
+
+
+def test_exact_leverage_sum_is_rank_and_bounded():
+    a = synth.dense_gaussian(400, 11, seed=7)
+    th = olev.leverage_exact(a)
+    assert th.min() >= 0 and th.max() <= 1 + 1e-12
+    assert abs(th.sum() - 11) < 1e-10
+    # a row orthogonal to the others (coherent) has leverage 1
+    b = np.zeros((50, 3)); b[:, :2] = synth.dense_gaussian(50, 2, seed=1)
+    b[17, 2] = 5.0
+    assert abs(olev.leverage_exact(b)[17] - 1.0) < 1e-12
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_sketched_leverage_invariants(sparse):
+    """With U an orthonormal basis of range(A) and sigma_j the singular values
+    of G S U: theta_i / sigma_max^2 <= theta~_i <= theta_i / sigma_min^2 and
+    sum_i theta~_i = sum_j sigma_j^{-2} (A R^{-1} = U (R_U)^{-1} with R_U the
+    triangular factor of G S U)."""
+    n, d, m, r = 2000, 6, 40, 300
+    a = synth.csr_uniform(n, d, 0.5, seed=8) if sparse else synth.dense_gaussian(n, d, seed=8)
+    th = olev.leverage_exact(a)
+    tt, _ = olev.leverage_sketched(a, m, r, seed=5)
+    sv = olev.sketch_distortion(a, m, r, seed=5)
+    assert np.all(tt >= th / sv.max() ** 2 * (1 - 1e-9))
+    assert np.all(tt <= th / sv.min() ** 2 * (1 + 1e-9))
+    assert abs(tt.sum() - (sv ** -2).sum()) < 1e-9 * tt.sum()
+    # QR route equals the paper's SVD route
+    np.testing.assert_allclose(olev.leverage_sketched_svd(a, m, r, seed=5), tt,
+                               rtol=1e-9, atol=1e-15)
+
+
+def test_distortion_within_marchenko_pastur_edges():
+    n, d, m, r = 20000, 8, 400, 4000
+    a = synth.dense_gaussian(n, d, seed=9)
+    sv = olev.sketch_distortion(a, m, r, seed=3)
+    # Gaussian stage edges 1 +- sqrt(d/m) widened for the CountSketch stage
+    e = np.sqrt(d / m)
+    assert sv.max() < 1 + 3 * e and sv.min() > 1 - 3 * e
+
+
+def test_qr_r_and_tri_inv():
+    c = synth.dense_gaussian(30, 5, seed=1)
+    r = olev.qr_r(c)
+    assert np.all(np.diag(r) >= 0) and np.allclose(np.tril(r, -1), 0)
+    np.testing.assert_allclose(r.T @ r, c.T @ c, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(olev.tri_inv(r) @ r, np.eye(5), atol=1e-13)
+
+
+def test_lsq_noise_free_recovers_solution():
+    a, b, xt = synth.lsq_problem(3000, 10, cond=1e4, seed=1, noise=0.0)
+    x, info = olsq.lsq_sketch_precond(a, b, m=40, r=100, seed=2)
+    assert np.linalg.norm(x - xt) / np.linalg.norm(xt) < 1e4 * 1e-12
+    assert info["cond_precond"] > 1e3  # the preconditioner carries kappa(A)
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e6])
+def test_lsq_matches_lapack(cond):
+    a, b, _ = synth.lsq_problem(5000, 16, cond=cond, seed=3)
+    xs = olsq.lstsq(a, b)
+    x, info = olsq.lsq_sketch_precond(a, b, m=64, r=256, seed=4)
+    rs, _ = olsq.lsq_quality(a, b, xs)
+    rn, ne = olsq.lsq_quality(a, b, x)
+    assert (rn - rs) / rs < 1e-10
+    assert ne < 1e-10
+    # a preconditioned LSQR converges in few iterations regardless of cond
+    assert info["iters"][0] < 80

@@ -1,0 +1,185 @@
+"""Pins of the oracle's CountSketch, Gaussian and CountGauss sketches:
+the paper's worked example, structural invariants of Definition 3, the
+workload moments of Lemma 1, associativity, m = 0 semantics, Gaussian
+moments, and the reduced-precision rounding against PyTorch's CPU casts."""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import sketch as osk
+
+
+def _example(golden_dir):
+    vec, mat = None, []
+    with open(os.path.join(golden_dir, "countsketch_example.txt")) as f:
+        lines = [l for l in f if not l.startswith("#") and l.strip()]
+    for l in lines:
+        if l.startswith("vector:"):
+            vec = [int(t) for t in l.split(":")[1].split()]
+        elif l.startswith("matrix:"):
+            continue
+        else:
+            mat.append([int(t) for t in l.split()])
+    return np.array(vec), np.array(mat, dtype=float)
+
+
+def test_worked_example_vector_to_matrix(golden_dir):
+    v, s_fig = _example(golden_dir)
+    s = osk.dense_from_vector(v, 6)
+    assert s.shape == (6, 12)
+    # exactly one +-1 per column (Definition 3) and nnz(S) = n
+    assert np.all((s != 0).sum(axis=0) == 1)
+    assert np.count_nonzero(s) == 12
+    # 11 of 12 columns agree with the printed matrix; column 5 (1-based) is the
+    # printed sign typo recorded with the fixture
+    diff = np.nonzero(np.any(s != s_fig, axis=0))[0]
+    assert list(diff) == [4]
+    assert s[0, 4] == 1.0 and s_fig[0, 4] == -1.0
+
+
+def test_vector_representation_round_trip():
+    h, sg = osk.cs_hash(50, 7, seed=3)
+    v = osk.vector_representation(h, sg)
+    s = osk.dense_from_vector(v, 7)
+    np.testing.assert_array_equal(s, osk.countsketch_dense(50, 7, seed=3))
+
+
+def test_countsketch_structure():
+    s = osk.countsketch_dense(300, 40, seed=11)
+    assert np.all((s != 0).sum(axis=0) == 1)
+    assert set(np.unique(s[s != 0])) <= {-1.0, 1.0}
+    assert np.count_nonzero(s) == 300
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_sketch_cs_sum_identity_integer(sparse):
+    """1^T (S A) = sigma^T A holds exactly for integer A (every column of S has
+    one entry, so summing the rows of S A re-adds every signed row of A)."""
+    n, d, r = 500, 9, 37
+    a = (synth.csr_integer(n, d, 0.3, seed=1) if sparse
+         else synth.dense_integer(n, d, seed=1))
+    sa = osk.sketch_cs(a, r, seed=8)
+    _, sg = osk.cs_hash(n, r, seed=8)
+    ad = a.toarray() if sparse else a
+    np.testing.assert_array_equal(sa.sum(axis=0), sg.astype(float) @ ad)
+
+
+def test_sketch_cs_row_lists_brute_force():
+    """Each row of S A is the signed sum of the rows of A hashed to it."""
+    n, d, r = 200, 5, 13
+    a = synth.dense_integer(n, d, seed=4)
+    sa = osk.sketch_cs(a, r, seed=21)
+    for b in range(r):
+        acc = np.zeros(d)
+        for i in range(n):
+            hb, sb = osk.cs_hash_bigint(i, r, 21)
+            if hb == b:
+                acc += sb * a[i]
+        np.testing.assert_array_equal(sa[b], acc)
+
+
+def test_sketch_norm_preserved_in_expectation():
+    """E ||S A||_F^2 = ||A||_F^2 (cross terms vanish in expectation)."""
+    n, d, r = 60, 4, 10
+    a = synth.dense_gaussian(n, d, seed=2)
+    vals = [np.linalg.norm(osk.sketch_cs(a, r, seed=s)) ** 2 for s in range(600)]
+    ref = np.linalg.norm(a) ** 2
+    se = np.std(vals) / np.sqrt(len(vals))
+    assert abs(np.mean(vals) - ref) < 5 * se
+
+
+def test_lemma1_bucket_set_workload_moments():
+    """Lemma 1: for a fixed set of B of the r buckets, the work
+    Y = sum_i eps_i w_i has mean q nnz(A) and variance q(1-q) nnz_2(A), q=B/r."""
+    n, r, B = 3000, 64, 16
+    w = synth.csr_zipf(n, 200, 0.02, seed=3).getnnz(axis=1).astype(float)
+    nnz, nnz2 = w.sum(), (w ** 2).sum()
+    q = B / r
+    ys = []
+    for s in range(400):
+        h, _ = osk.cs_hash(n, r, seed=1000 + s)
+        ys.append(w[h < B].sum())
+    ys = np.array(ys)
+    mu, var = q * nnz, q * (1 - q) * nnz2
+    assert abs(ys.mean() - mu) < 5 * np.sqrt(var / ys.size)
+    # sample variance within 25% (400 samples: relative s.e. ~ 7-15%)
+    assert abs(ys.var(ddof=1) / var - 1) < 0.3
+
+
+def test_gaussian_moments_and_normality():
+    from scipy import stats
+    m, r = 64, 4000
+    z = osk.gaussian_normals(m, 0, r, seed=9).ravel()
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1) < 5 * np.sqrt(2 / z.size)
+    assert stats.kstest(z, "norm").pvalue > 1e-4
+    g = osk.gaussian_block(m, 0, r, seed=9)
+    np.testing.assert_allclose(g, z.reshape(m, r) / 8.0, rtol=0, atol=0)
+
+
+def test_gaussian_column_blocks_consistent():
+    """Any bucket range gives the same columns (blocks are only batching)."""
+    full = osk.gaussian_normals(11, 0, 103, seed=4)
+    for b0, b1 in [(0, 1), (1, 5), (3, 4), (5, 103), (50, 77)]:
+        np.testing.assert_array_equal(osk.gaussian_normals(11, b0, b1, seed=4),
+                                      full[:, b0:b1])
+
+
+def test_gaussian_embedding_isotropic():
+    """E[(G S)^T (G S)] = I: G with variance 1/m, S with +-1 entries."""
+    n, m, r = 6, 8, 16
+    acc = np.zeros((n, n))
+    T = 1500
+    for s in range(T):
+        gs = osk.gaussian_block(m, 0, r, seed=s) @ osk.countsketch_dense(n, r, s)
+        acc += gs.T @ gs
+    np.testing.assert_allclose(acc / T, np.eye(n), atol=0.12)
+
+
+@pytest.mark.parametrize("sparse", [False, True])
+def test_countgauss_associativity_and_batching(sparse):
+    n, d, m, r = 300, 7, 12, 50
+    a = (synth.csr_uniform(n, d, 0.4, seed=5) if sparse
+         else synth.dense_gaussian(n, d, seed=5))
+    c = osk.sketch_gcs(a, m, r, seed=77)
+    s = osk.countsketch_dense(n, r, 77)
+    g = osk.gaussian_block(m, 0, r, seed=77)
+    ad = a.toarray() if sparse else a
+    np.testing.assert_allclose(c, (g @ s) @ ad, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(osk.sketch_gcs(a, m, r, 77, batch=7), c,
+                               rtol=1e-12, atol=1e-12)
+    np.testing.assert_array_equal(osk.sketch_gcs(a, 0, r, 77),
+                                  osk.sketch_cs(a, r, 77))
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000),
+                        [0.0, 1.0, -1.0, 1.00390625, 1.01171875, 3e38, 1e-40]])
+    x32 = x.astype(np.float32)
+    want = torch.from_numpy(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(osk.to_bf16(x32.astype(np.float64)), want)
+
+
+def test_e4m3_rounding_matches_torch_in_range():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    x = rng.uniform(-440, 440, 20000) * 10.0 ** rng.integers(-4, 1, 20000)
+    x = np.concatenate([x, [0.0, 448.0, -448.0, 2 ** -9, 2 ** -10, 3 * 2 ** -10, 0.5 + 2 ** -5]])
+    x32 = x.astype(np.float32)
+    want = torch.from_numpy(x32).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    np.testing.assert_array_equal(osk.to_e4m3(x32.astype(np.float64)), want)
+    # saturation beyond the largest finite e4m3 value
+    assert osk.to_e4m3(np.array([1e6, -500.0])).tolist() == [448.0, -448.0]
+
+
+def test_bf16_limbs_refine():
+    x = np.random.default_rng(2).standard_normal(1000)
+    l = osk.bf16_limbs(x, 2)
+    e1 = np.abs(x - l[0]).max() / np.abs(x).max()
+    e2 = np.abs(x - l[0] - l[1]).max() / np.abs(x).max()
+    assert e1 < 2 ** -8 and e2 < 2 ** -15
