@@ -1,0 +1,219 @@
+/*
+ * psk.h -- C ABI of libpsk: randomized sketching of tall-and-skinny matrices
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Operations follow "pylspack: Parallel algorithms and data structures for
+ * sketching, column subset selection, regression and leverage scores"
+ * (Sobczyk & Gallopoulos, arXiv 2203.02798):
+ *
+ *   cs_hash      the CountSketch hash h(i), sigma_i          (Definition 3)
+ *   sketch_cs    S*A                                         (Alg. bcs_multiply)
+ *   sketch_gcs   G*S*A, G Gaussian scaled by 1/sqrt(m)       (Alg. countgauss_multiply,
+ *                                                             csrcgs / rmcgs)
+ *   gram         C <- alpha*A^T*A + beta*C                   (Alg. gram, csrrk)
+ *   rownorms_sq  x <- alpha*||e_i^T A B||^2 + beta*x         (Alg. squared_row_norms,
+ *                                                             csrsqn / rmsqn)
+ *   sketch_qr    R and R^{-1} of a sketch C = Q*R            (the orthogonaliser of
+ *                                                             Alg. ls_approximate_drineas
+ *                                                             and least_squares_precondition)
+ *   lsq_solve    min ||A x - b|| by sketch-and-precondition  (Alg. least_squares_precondition)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All matrix/vector pointers are DEVICE pointers on the current HIP device,
+ *   owned by the caller; the library never frees them and never allocates
+ *   device memory.  Scratch space is passed in as (ws, ws_bytes); its minimum
+ *   size comes from psk_workspace_size().  Its contents on entry do not matter.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *   enqueues work on that stream and returns; outputs are valid once the
+ *   stream has reached that point.  lsq_solve is the one exception: it
+ *   synchronises the stream to test convergence (documented there).
+ * - Every call returns PSK_OK (0) or a negative psk_status; on error no work
+ *   has been enqueued (argument checks happen first) unless the status is
+ *   PSK_EDEVICE.  psk_last_error() gives a message for the calling thread.
+ * - Results are deterministic: identical inputs give bit-identical outputs,
+ *   independent of other work on the device (no floating-point atomics; all
+ *   reduction orders are fixed by the shapes).
+ * - Random quantities are pure functions of (seed, index) through
+ *   Philox4x32-10 (Salmon et al., SC'11):
+ *     hash of row i:   x = Philox(ctr=(i lo32, i hi32, 0, 0), key=(seed lo32, seed hi32)),
+ *                      h(i) = floor((x1*2^32 + x0) * r / 2^64), sigma_i = x2 even ? +1 : -1;
+ *     Gaussian G[a,b]: x = Philox(ctr=(q lo32, q hi32, a, 1), key as above), q = b div 4,
+ *                      u_k = (x_k + 1/2) 2^-32, Box-Muller on (u0,u1) and (u2,u3) gives
+ *                      z0..z3, G[a,b] = z_{b mod 4} / sqrt(m).
+ * - Limits: n < 2^31 rows, r < 2^31 buckets, CSR nnz < 2^62.
+ */
+#ifndef PSK_H
+#define PSK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+typedef enum {
+  PSK_OK = 0,
+  PSK_EINVAL = -1,       /* bad argument (shape, pointer, range, descriptor) */
+  PSK_EDTYPE = -2,       /* unsupported dtype / precision combination         */
+  PSK_ENOMEM = -3,       /* workspace smaller than psk_workspace_size()       */
+  PSK_EDEVICE = -4,      /* a HIP runtime call failed                         */
+  PSK_ENOCONV = -5,      /* lsq_solve reached max_iter before its tolerance   */
+  PSK_ERANK = -6,        /* sketch numerically rank deficient (R_jj tiny)     */
+  PSK_EUNSUPPORTED = -7  /* shape outside the limits documented per call      */
+} psk_status;
+
+/* ---- matrix descriptor ------------------------------------------------- */
+enum { PSK_DENSE = 0, PSK_CSR = 1 };   /* psk_mat.format */
+enum { PSK_F64 = 0, PSK_F32 = 1 };     /* psk_mat.dtype  */
+
+/* A tall matrix A (n x d).
+ * Dense: row-major, element (i,j) at values[i*ld + j], ld >= d.
+ * CSR:   0-based; row i holds entries indptr[i] .. indptr[i+1]-1 with column
+ *        indices[k] in [0, d) and value values[k].  Columns inside a row may be
+ *        in any order.  Duplicate columns inside a row are summed, but then
+ *        bit-reproducibility of the affected outputs is not guaranteed.
+ *        indptr[0] must be 0 and indptr[n] == nnz (checked on the host from
+ *        the descriptor only; row contents are trusted). */
+typedef struct psk_mat {
+  int32_t format;          /* PSK_DENSE or PSK_CSR              */
+  int32_t dtype;           /* PSK_F64 or PSK_F32                */
+  int64_t n;               /* rows    (>= 1)                    */
+  int64_t d;               /* columns (>= 1)                    */
+  int64_t ld;              /* dense: row stride in elements     */
+  int64_t nnz;             /* CSR: stored entries               */
+  const void *values;      /* dense: >= (n-1)*ld+d elements; CSR: nnz elements */
+  const int64_t *indptr;   /* CSR: n+1 row offsets              */
+  const int32_t *indices;  /* CSR: nnz column indices           */
+} psk_mat;
+
+/* ---- precision of the Gaussian GEMM of sketch_gcs / lsq_solve ---------- */
+enum {
+  PSK_PREC_F64 = 0,   /* G and S*A in FP64, FP64 MFMA, FP64 accumulation      */
+  PSK_PREC_BF16 = 1   /* G rounded to bfloat16, S*A split into two bfloat16   *
+                       * limbs (hi + lo), BF16 MFMA with FP32 accumulation,   *
+                       * FP64 reduction of the K-split partial products        */
+};
+
+/* ---- operations for psk_workspace_size --------------------------------- */
+enum {
+  PSK_OP_SKETCH_CS = 0,
+  PSK_OP_SKETCH_GCS = 1,
+  PSK_OP_GRAM = 2,
+  PSK_OP_ROWNORMS = 3,
+  PSK_OP_QR = 4,
+  PSK_OP_LSQ = 5
+};
+
+/* Library version string (static storage). */
+const char *psk_version(void);
+
+/* Message describing the last error returned on the calling thread
+ * (thread-local storage, valid until the next psk call on this thread). */
+const char *psk_last_error(void);
+
+/* Minimum workspace, in bytes, for one call of `op`.
+ *   A    : the matrix the call will get (for PSK_OP_QR only A->n = m rows and
+ *          A->d = d columns of the sketch are read);
+ *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ);
+ *   k    : columns of B (ROWNORMS);
+ *   prec : PSK_PREC_* (SKETCH_GCS, LSQ).
+ * Arguments an op does not use are ignored. */
+int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r,
+                       int64_t k, int prec, size_t *bytes);
+
+/* CountSketch hash of rows row0 .. row0+count-1 (Definition 3 of the paper;
+ * the hash and sign are drawn as stated in the header comment).
+ *   h    : count int32 buckets in [0, r)          (device, may be NULL)
+ *   sign : count int8 signs in {+1, -1}           (device, may be NULL)
+ * Errors: PSK_EINVAL if count < 0, row0 < 0, or r < 1 or r >= 2^31. */
+int cs_hash(int64_t row0, int64_t count, int64_t r, uint64_t seed,
+            int32_t *h, int8_t *sign, void *stream);
+
+/* S*A: the r x d CountSketch of A (Algorithm bcs_multiply).
+ *   SA : r x d row-major, leading dimension d, dtype of A (device, written
+ *        entirely; rows of empty buckets are zero).
+ * Row i of A is added to row h(i) of SA with sign sigma_i; the rows of one
+ * bucket are summed in increasing row order in the dtype of A.
+ * Errors: PSK_EINVAL (shapes, r < 1, NULL pointers), PSK_EUNSUPPORTED (CSR
+ * with d > 8192 for FP64 / 16384 for FP32), PSK_ENOMEM. */
+int sketch_cs(const psk_mat *A, int64_t r, uint64_t seed, void *SA,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* C = G*(S*A) (Algorithm countgauss_multiply; csrcgs / rmcgs), G the m x r
+ * Gaussian matrix with entries of variance 1/m.
+ *   m    : rows of G; m == 0 returns S*A as sketch_cs does.
+ *   prec : PSK_PREC_F64 or PSK_PREC_BF16 (ignored when m == 0).
+ *   C    : m x d row-major FP64 (m > 0), or r x d in the dtype of A (m == 0).
+ * G is generated inside the GEMM and never stored.
+ * Errors: as sketch_cs, plus PSK_EDTYPE for an unknown prec. */
+int sketch_gcs(const psk_mat *A, int64_t m, int64_t r, uint64_t seed,
+               int prec, void *C, void *ws, size_t ws_bytes, void *stream);
+
+/* C <- alpha*A^T*A + beta*C (Algorithm gram; csrrk).  C is d x d row-major in
+ * the dtype of A, both triangles written.  beta == 0 ignores C's previous
+ * contents (NaN-safe).  Products are accumulated in FP64.
+ * Errors: PSK_EINVAL, PSK_EUNSUPPORTED (CSR with d > 8192), PSK_ENOMEM. */
+int gram(double alpha, const psk_mat *A, double beta, void *C,
+         void *ws, size_t ws_bytes, void *stream);
+
+/* x <- alpha*q + beta*x with q_i = ||e_i^T A B||^2 (Algorithm
+ * squared_row_norms; csrsqn / rmsqn).
+ *   B : d x k row-major FP64 (device).
+ *   x : n FP64 (device, in/out; beta == 0 ignores its previous contents).
+ * Dense A: fused product-and-norm (A*B is never stored).  CSR A: B*B^T is
+ * formed first and the row sums run over pairs of each row's entries.
+ * Computation in FP64.
+ * Errors: PSK_EINVAL, PSK_EUNSUPPORTED (CSR with d > 8192), PSK_ENOMEM. */
+int rownorms_sq(double alpha, const psk_mat *A, const double *B, int64_t k,
+                double beta, double *x, void *ws, size_t ws_bytes,
+                void *stream);
+
+/* R and R^{-1} of an FP64 sketch C (m x d row-major, m >= d): C = Q*R with R
+ * upper triangular, diag(R) > 0.  Computed by shifted Cholesky-QR (three
+ * passes), so Q is never returned.  R and Rinv are d x d row-major FP64
+ * (strict lower triangles written as zero).
+ * Errors: PSK_EINVAL (m < d, NULL pointers), PSK_EUNSUPPORTED (d > 4096),
+ * PSK_ENOMEM.  Rank deficiency is reported by lsq_solve, not here. */
+int sketch_qr(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
+              void *ws, size_t ws_bytes, void *stream);
+
+/* Options and report of lsq_solve. */
+typedef struct psk_lsq_opts {
+  int64_t m;          /* Gaussian rows of the sketch (>= d)          */
+  int64_t r;          /* CountSketch buckets (>= m)                  */
+  uint64_t seed;
+  int32_t prec;       /* PSK_PREC_* of the sketch GEMM               */
+  int32_t max_iter;   /* LSQR iteration limit per solve (>= 1)       */
+  int32_t refine;     /* refinement passes after the first solve     */
+  int32_t check_every;/* iterations between convergence checks (>=1) */
+  double atol;        /* stop when ||(AN)^T r|| <= atol*||AN||*||r|| */
+  double btol;        /* or when ||r|| <= btol*||b||                  */
+} psk_lsq_opts;
+
+typedef struct psk_lsq_info {
+  int32_t iters;      /* LSQR iterations, all passes                 */
+  int32_t status;     /* PSK_OK or PSK_ENOCONV                        */
+  double resid;       /* ||b - A x|| estimate from the recurrences   */
+  double ne_resid;    /* ||(AN)^T r|| / (||AN||_F ||r||) estimate    */
+} psk_lsq_info;
+
+/* x = argmin ||A x - b|| by sketch-and-precondition (Algorithm
+ * least_squares_precondition): C = G*S*A, R from sketch_qr(C), LSQR on the
+ * operator A*R^{-1} (Paige & Saunders 1982) in FP64, x = R^{-1} y, then
+ * `refine` passes that solve for the residual and add the correction.
+ *   b : n FP64 (device);  x : d FP64 (device, output).
+ * The call enqueues LSQR iterations in groups of check_every and
+ * synchronises `stream` after each group to read the convergence flag, so
+ * it returns with the stream idle.
+ * Errors: PSK_EINVAL, PSK_ENOMEM, PSK_ENOCONV (x still written), PSK_ERANK. */
+int lsq_solve(const psk_mat *A, const double *b, double *x,
+              const psk_lsq_opts *opts, psk_lsq_info *info,
+              void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PSK_H */

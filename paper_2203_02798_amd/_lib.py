@@ -1,0 +1,118 @@
+"""ctypes loader for libpsk.so (the C ABI declared in include/psk.h).
+
+Argument marshalling only: no arithmetic of the method happens in Python.
+Importing this module does not load the library; ``lib()`` does, and raises
+if the in-tree build is missing (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsk.so")
+
+PSK_OK = 0
+STATUS_NAMES = {
+    0: "PSK_OK", -1: "PSK_EINVAL", -2: "PSK_EDTYPE", -3: "PSK_ENOMEM",
+    -4: "PSK_EDEVICE", -5: "PSK_ENOCONV", -6: "PSK_ERANK", -7: "PSK_EUNSUPPORTED",
+}
+PSK_DENSE, PSK_CSR = 0, 1
+PSK_F64, PSK_F32 = 0, 1
+PSK_PREC_F64, PSK_PREC_BF16 = 0, 1
+(PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
+ PSK_OP_LSQ) = range(6)
+
+EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
+            "sketch_cs", "sketch_gcs", "gram", "rownorms_sq", "sketch_qr",
+            "lsq_solve"]
+
+
+class PskMat(ctypes.Structure):
+    _fields_ = [
+        ("format", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_int64),
+        ("ld", ctypes.c_int64),
+        ("nnz", ctypes.c_int64),
+        ("values", ctypes.c_void_p),
+        ("indptr", ctypes.c_void_p),
+        ("indices", ctypes.c_void_p),
+    ]
+
+
+class PskLsqOpts(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64),
+        ("r", ctypes.c_int64),
+        ("seed", ctypes.c_uint64),
+        ("prec", ctypes.c_int32),
+        ("max_iter", ctypes.c_int32),
+        ("refine", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("atol", ctypes.c_double),
+        ("btol", ctypes.c_double),
+    ]
+
+
+class PskLsqInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("resid", ctypes.c_double),
+        ("ne_resid", ctypes.c_double),
+    ]
+
+
+class PskError(RuntimeError):
+    def __init__(self, status, where, message):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+
+
+_LIB = None
+
+_vp, _i64, _u64, _i32, _dbl = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64,
+                               ctypes.c_int32, ctypes.c_double)
+_PM = ctypes.POINTER(PskMat)
+
+_SIGS = {
+    "psk_version": ([], ctypes.c_char_p),
+    "psk_last_error": ([], ctypes.c_char_p),
+    "psk_workspace_size": ([ctypes.c_int, _PM, _i64, _i64, _i64, ctypes.c_int,
+                            ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "cs_hash": ([_i64, _i64, _i64, _u64, _vp, _vp, _vp], ctypes.c_int),
+    "sketch_cs": ([_PM, _i64, _u64, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "sketch_gcs": ([_PM, _i64, _i64, _u64, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp],
+                   ctypes.c_int),
+    "gram": ([_dbl, _PM, _dbl, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "rownorms_sq": ([_dbl, _PM, _vp, _i64, _dbl, _vp, _vp, ctypes.c_size_t, _vp],
+                    ctypes.c_int),
+    "sketch_qr": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "lsq_solve": ([_PM, _vp, _vp, ctypes.POINTER(PskLsqOpts), ctypes.POINTER(PskLsqInfo),
+                   _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+}
+
+
+def lib():
+    """The loaded libpsk.so (loaded once).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"libpsk.so not found at {LIB_PATH}; build it with "
+                "`python -m paper_2203_02798_amd.build` (there is no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _LIB = L
+    return _LIB
+
+
+def check(status, where):
+    if status != PSK_OK:
+        msg = lib().psk_last_error().decode(errors="replace")
+        raise PskError(status, where, msg)

@@ -1,0 +1,222 @@
+"""Python binding of libpsk over PyTorch device tensors.
+
+Every function marshals tensors into the C ABI of include/psk.h and calls it
+on the current HIP stream; PyTorch only supplies device memory (outputs and
+workspace) and the stream.  Names and semantics follow the C entry points.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+__all__ = [
+    "CsrMatrix", "cs_hash", "sketch_cs", "sketch_gcs", "gram", "rownorms_sq",
+    "sketch_qr", "lsq_solve", "workspace_size", "version", "PskError",
+]
+
+PskError = L.PskError
+_PREC = {"f64": L.PSK_PREC_F64, "bf16": L.PSK_PREC_BF16}
+
+
+@dataclass
+class CsrMatrix:
+    """CSR matrix on the device: int64 indptr (n+1), int32 indices, values
+    (float64 or float32), 0-based."""
+    indptr: torch.Tensor
+    indices: torch.Tensor
+    values: torch.Tensor
+    shape: tuple
+
+    @property
+    def device(self):
+        return self.values.device
+
+    @property
+    def dtype(self):
+        return self.values.dtype
+
+    @staticmethod
+    def from_scipy(m, device="cuda", dtype=None):
+        dt = dtype if dtype is not None else (
+            torch.float32 if m.dtype.name == "float32" else torch.float64)
+        return CsrMatrix(
+            torch.as_tensor(m.indptr.astype("int64"), device=device),
+            torch.as_tensor(m.indices.astype("int32"), device=device),
+            torch.as_tensor(m.data, device=device).to(dt),
+            (int(m.shape[0]), int(m.shape[1])))
+
+
+def _dtype_code(dt):
+    if dt == torch.float64:
+        return L.PSK_F64
+    if dt == torch.float32:
+        return L.PSK_F32
+    raise TypeError(f"A must be float64 or float32, got {dt}")
+
+
+def _mat(A):
+    m = L.PskMat()
+    if isinstance(A, CsrMatrix):
+        if A.indptr.dtype != torch.int64 or A.indices.dtype != torch.int32:
+            raise TypeError("CSR indptr must be int64 and indices int32")
+        m.format = L.PSK_CSR
+        m.dtype = _dtype_code(A.values.dtype)
+        m.n, m.d = A.shape
+        m.ld = A.shape[1]
+        m.nnz = int(A.values.numel())
+        m.values = A.values.data_ptr() if m.nnz else None
+        m.indptr = A.indptr.data_ptr()
+        m.indices = A.indices.data_ptr() if m.nnz else None
+        return m
+    if not isinstance(A, torch.Tensor) or A.dim() != 2:
+        raise TypeError("A must be a 2-D device tensor or a CsrMatrix")
+    if A.stride(1) != 1:
+        raise ValueError("dense A must be row-major (unit column stride)")
+    m.format = L.PSK_DENSE
+    m.dtype = _dtype_code(A.dtype)
+    m.n, m.d = A.shape
+    m.ld = A.stride(0)
+    m.nnz = 0
+    m.values = A.data_ptr()
+    return m
+
+
+def _device(A):
+    return A.device if isinstance(A, (torch.Tensor, CsrMatrix)) else torch.device("cuda")
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace_size(op, A, m=0, r=1, k=1, prec="f64"):
+    """Minimum workspace bytes of one call (psk_workspace_size)."""
+    out = ctypes.c_size_t(0)
+    if isinstance(A, tuple):  # (m_rows, d) for the QR op
+        mm = L.PskMat()
+        mm.n, mm.d = A
+        pm = mm
+    else:
+        pm = _mat(A)
+    L.check(L.lib().psk_workspace_size(op, ctypes.byref(pm), m, r, k, _PREC[prec],
+                                       ctypes.byref(out)), "psk_workspace_size")
+    return int(out.value)
+
+
+def _ws(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def version():
+    return L.lib().psk_version().decode()
+
+
+def cs_hash(count, r, seed, row0=0, device="cuda"):
+    """(h int32[count], sign int8[count]) for rows row0 .. row0+count-1."""
+    h = torch.empty(count, dtype=torch.int32, device=device)
+    s = torch.empty(count, dtype=torch.int8, device=device)
+    L.check(L.lib().cs_hash(row0, count, r, seed, h.data_ptr() if count else None,
+                            s.data_ptr() if count else None,
+                            _stream(torch.device(device))), "cs_hash")
+    return h, s
+
+
+def sketch_cs(A, r, seed, out=None):
+    """S*A (r x d, dtype of A)."""
+    pm = _mat(A)
+    dev = _device(A)
+    dt = A.dtype
+    if out is None:
+        out = torch.empty((r, pm.d), dtype=dt, device=dev)
+    nbytes = workspace_size(L.PSK_OP_SKETCH_CS, A, r=r)
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().sketch_cs(ctypes.byref(pm), r, seed, out.data_ptr(), ws.data_ptr(),
+                              ws.numel(), _stream(dev)), "sketch_cs")
+    return out
+
+
+def sketch_gcs(A, m, r, seed, prec="f64", out=None):
+    """G*S*A (m x d, float64); m == 0 gives S*A."""
+    if m == 0:
+        return sketch_cs(A, r, seed, out)
+    pm = _mat(A)
+    dev = _device(A)
+    if out is None:
+        out = torch.empty((m, pm.d), dtype=torch.float64, device=dev)
+    nbytes = workspace_size(L.PSK_OP_SKETCH_GCS, A, m=m, r=r, prec=prec)
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().sketch_gcs(ctypes.byref(pm), m, r, seed, _PREC[prec], out.data_ptr(),
+                               ws.data_ptr(), ws.numel(), _stream(dev)), "sketch_gcs")
+    return out
+
+
+def gram(A, alpha=1.0, beta=0.0, C=None):
+    """alpha*A^T A + beta*C (d x d, dtype of A)."""
+    pm = _mat(A)
+    dev = _device(A)
+    if C is None:
+        C = torch.empty((pm.d, pm.d), dtype=A.dtype, device=dev)
+        beta = 0.0
+    nbytes = workspace_size(L.PSK_OP_GRAM, A)
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().gram(alpha, ctypes.byref(pm), beta, C.data_ptr(), ws.data_ptr(),
+                         ws.numel(), _stream(dev)), "gram")
+    return C
+
+
+def rownorms_sq(A, B, alpha=1.0, beta=0.0, x=None):
+    """alpha*||e_i^T A B||^2 + beta*x_i (float64 n-vector)."""
+    pm = _mat(A)
+    dev = _device(A)
+    B = B.contiguous()
+    if B.dtype != torch.float64:
+        raise TypeError("B must be float64")
+    k = B.shape[1]
+    if x is None:
+        x = torch.empty(pm.n, dtype=torch.float64, device=dev)
+        beta = 0.0
+    nbytes = workspace_size(L.PSK_OP_ROWNORMS, A, k=k)
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().rownorms_sq(alpha, ctypes.byref(pm), B.data_ptr(), k, beta,
+                                x.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)),
+            "rownorms_sq")
+    return x
+
+
+def sketch_qr(C):
+    """(R, R^{-1}) of an FP64 m x d sketch (m >= d)."""
+    C = C.contiguous()
+    m, d = C.shape
+    dev = C.device
+    R = torch.empty((d, d), dtype=torch.float64, device=dev)
+    Ri = torch.empty((d, d), dtype=torch.float64, device=dev)
+    nbytes = workspace_size(L.PSK_OP_QR, (m, d))
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().sketch_qr(C.data_ptr(), m, d, R.data_ptr(), Ri.data_ptr(),
+                              ws.data_ptr(), ws.numel(), _stream(dev)), "sketch_qr")
+    return R, Ri
+
+
+def lsq_solve(A, b, m, r, seed, prec="f64", max_iter=300, refine=1, check_every=8,
+              atol=1e-14, btol=1e-14, raise_on_noconv=False):
+    """x = argmin ||A x - b|| by sketch-and-precondition LSQR.
+    Returns (x float64[d], info dict)."""
+    pm = _mat(A)
+    dev = _device(A)
+    b = b.contiguous()
+    x = torch.empty(pm.d, dtype=torch.float64, device=dev)
+    o = L.PskLsqOpts(m=m, r=r, seed=seed, prec=_PREC[prec], max_iter=max_iter,
+                     refine=refine, check_every=check_every, atol=atol, btol=btol)
+    info = L.PskLsqInfo()
+    nbytes = workspace_size(L.PSK_OP_LSQ, A, m=m, r=r, prec=prec)
+    ws = _ws(nbytes, dev)
+    st = L.lib().lsq_solve(ctypes.byref(pm), b.data_ptr(), x.data_ptr(), ctypes.byref(o),
+                           ctypes.byref(info), ws.data_ptr(), ws.numel(), _stream(dev))
+    if st != L.PSK_OK and (st != -5 or raise_on_noconv):
+        L.check(st, "lsq_solve")
+    return x, dict(iters=info.iters, status=L.STATUS_NAMES.get(info.status, info.status),
+                   resid=info.resid, ne_resid=info.ne_resid)

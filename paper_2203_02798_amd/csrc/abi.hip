@@ -1,0 +1,236 @@
+// C-ABI layer of libpsk: argument validation, workspace planning and
+// dispatch to the kernel files.  Every entry point checks its arguments on
+// the host before anything is enqueued and reports failures as psk_status
+// codes with a thread-local message; no C++ exception crosses the boundary.
+#include <math.h>
+
+#include <string>
+
+#include "internal.hpp"
+
+namespace psk {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int status, const std::string &msg) {
+  g_last_error = msg;
+  return status;
+}
+
+namespace {
+
+int check_mat(const psk_mat *A) {
+  if (!A) return fail(PSK_EINVAL, "A is NULL");
+  if (A->format != PSK_DENSE && A->format != PSK_CSR)
+    return fail(PSK_EINVAL, "A->format must be PSK_DENSE or PSK_CSR");
+  if (A->dtype != PSK_F64 && A->dtype != PSK_F32)
+    return fail(PSK_EDTYPE, "A->dtype must be PSK_F64 or PSK_F32");
+  if (A->n < 1 || A->d < 1) return fail(PSK_EINVAL, "A must have n >= 1 and d >= 1");
+  if (A->n >= ((int64_t)1 << 31)) return fail(PSK_EUNSUPPORTED, "n must be < 2^31");
+  if (A->format == PSK_DENSE) {
+    if (A->ld < A->d) return fail(PSK_EINVAL, "dense A needs ld >= d");
+    if (!A->values) return fail(PSK_EINVAL, "A->values is NULL");
+  } else {
+    if (A->nnz < 0) return fail(PSK_EINVAL, "CSR A needs nnz >= 0");
+    if (!A->indptr) return fail(PSK_EINVAL, "CSR A->indptr is NULL");
+    if (A->nnz > 0 && (!A->values || !A->indices))
+      return fail(PSK_EINVAL, "CSR A->values/indices is NULL");
+    if (A->d > INT32_MAX) return fail(PSK_EUNSUPPORTED, "CSR d must fit int32");
+  }
+  return 0;
+}
+
+int check_r(int64_t r) {
+  if (r < 1 || r >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "r must be in [1, 2^31)");
+  return 0;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// plan + run helpers shared by the entry points and psk_workspace_size
+int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws,
+                 hipStream_t st) {
+  uint32_t *perm = nullptr, *bptr = nullptr;
+  int rc = cs_bin(A.n, (uint32_t)r, seed, ws, st, &perm, &bptr);
+  if (rc) return rc;
+  return cs_apply(A, (uint32_t)r, perm, bptr, SA, ws, st);
+}
+
+int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec,
+                  void *C, Arena &ws, hipStream_t st) {
+  if (m == 0) return do_sketch_cs(A, r, seed, C, ws, st);
+  void *SA = ws.take<unsigned char>((size_t)r * A.d * elem_size(A.dtype));
+  int rc = do_sketch_cs(A, r, seed, SA, ws, st);
+  if (rc) return rc;
+  return gauss_gemm(m, r, A.d, seed, prec, SA, A.dtype, (double *)C, ws, st);
+}
+
+}  // namespace
+}  // namespace psk
+
+using namespace psk;
+
+extern "C" {
+
+const char *psk_version(void) { return "psk 0.1.0 (gfx950)"; }
+
+const char *psk_last_error(void) { return g_last_error.c_str(); }
+
+int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k,
+                       int prec, size_t *bytes) {
+  if (!bytes) return fail(PSK_EINVAL, "bytes is NULL");
+  if (!A) return fail(PSK_EINVAL, "A is NULL");
+  Arena ws;  // dry run
+  int rc = 0;
+  switch (op) {
+    case PSK_OP_SKETCH_CS:
+      if ((rc = check_r(r))) return rc;
+      rc = do_sketch_cs(*A, r, 0, nullptr, ws, nullptr);
+      break;
+    case PSK_OP_SKETCH_GCS:
+      if ((rc = check_r(r))) return rc;
+      if (m < 0) return fail(PSK_EINVAL, "m must be >= 0");
+      rc = do_sketch_gcs(*A, m, r, 0, prec, nullptr, ws, nullptr);
+      break;
+    case PSK_OP_GRAM:
+      rc = A->format == PSK_DENSE ? gram_dense(1.0, *A, 0.0, nullptr, ws, nullptr)
+                                  : gram_csr(1.0, *A, 0.0, nullptr, ws, nullptr);
+      break;
+    case PSK_OP_ROWNORMS:
+      if (k < 1) return fail(PSK_EINVAL, "k must be >= 1");
+      rc = A->format == PSK_DENSE
+               ? rownorms_dense(1.0, *A, nullptr, k, 0.0, nullptr, ws, nullptr)
+               : rownorms_csr(1.0, *A, nullptr, k, 0.0, nullptr, ws, nullptr);
+      break;
+    case PSK_OP_QR:
+      rc = sketch_qr_impl(nullptr, A->n, A->d, nullptr, nullptr, ws, nullptr);
+      break;
+    case PSK_OP_LSQ: {
+      psk_lsq_opts o{};
+      o.m = m;
+      o.r = r;
+      o.prec = prec;
+      o.max_iter = 1;
+      o.check_every = 1;
+      rc = lsq_impl(*A, nullptr, nullptr, o, nullptr, ws, nullptr);
+      break;
+    }
+    default:
+      return fail(PSK_EINVAL, "unknown op");
+  }
+  if (rc) return rc;
+  *bytes = ws.peak + 256;
+  return PSK_OK;
+}
+
+int cs_hash(int64_t row0, int64_t count, int64_t r, uint64_t seed, int32_t *h,
+            int8_t *sign, void *stream) {
+  if (count < 0 || row0 < 0) return fail(PSK_EINVAL, "count and row0 must be >= 0");
+  int rc = check_r(r);
+  if (rc) return rc;
+  return cs_hash_export(row0, count, (uint32_t)r, seed, h, sign, as_stream(stream));
+}
+
+int sketch_cs(const psk_mat *A, int64_t r, uint64_t seed, void *SA, void *wsp,
+              size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if ((rc = check_r(r))) return rc;
+  if (!SA) return fail(PSK_EINVAL, "SA is NULL");
+  Arena plan;
+  if ((rc = do_sketch_cs(*A, r, seed, nullptr, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_CS)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return do_sketch_cs(*A, r, seed, SA, ws, as_stream(stream));
+}
+
+int sketch_gcs(const psk_mat *A, int64_t m, int64_t r, uint64_t seed, int prec,
+               void *C, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if ((rc = check_r(r))) return rc;
+  if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "m must be in [0, 2^31)");
+  if (m > 0 && prec != PSK_PREC_F64 && prec != PSK_PREC_BF16)
+    return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64 or PSK_PREC_BF16");
+  if (!C) return fail(PSK_EINVAL, "C is NULL");
+  Arena plan;
+  if ((rc = do_sketch_gcs(*A, m, r, seed, prec, nullptr, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_GCS)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return do_sketch_gcs(*A, m, r, seed, prec, C, ws, as_stream(stream));
+}
+
+int gram(double alpha, const psk_mat *A, double beta, void *C, void *wsp,
+         size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if (!C) return fail(PSK_EINVAL, "C is NULL");
+  Arena plan;
+  rc = A->format == PSK_DENSE ? gram_dense(alpha, *A, beta, nullptr, plan, nullptr)
+                              : gram_csr(alpha, *A, beta, nullptr, plan, nullptr);
+  if (rc) return rc;
+  if (ws_bytes < plan.peak || (plan.peak > 0 && !wsp))
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_GRAM)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return A->format == PSK_DENSE ? gram_dense(alpha, *A, beta, C, ws, as_stream(stream))
+                                : gram_csr(alpha, *A, beta, C, ws, as_stream(stream));
+}
+
+int rownorms_sq(double alpha, const psk_mat *A, const double *B, int64_t k,
+                double beta, double *x, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if (k < 1) return fail(PSK_EINVAL, "k must be >= 1");
+  if (!B || !x) return fail(PSK_EINVAL, "B and x must be non-NULL");
+  Arena plan;
+  rc = A->format == PSK_DENSE
+           ? rownorms_dense(alpha, *A, nullptr, k, beta, nullptr, plan, nullptr)
+           : rownorms_csr(alpha, *A, nullptr, k, beta, nullptr, plan, nullptr);
+  if (rc) return rc;
+  if (ws_bytes < plan.peak || (plan.peak > 0 && !wsp))
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_ROWNORMS)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return A->format == PSK_DENSE
+             ? rownorms_dense(alpha, *A, B, k, beta, x, ws, as_stream(stream))
+             : rownorms_csr(alpha, *A, B, k, beta, x, ws, as_stream(stream));
+}
+
+int sketch_qr(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
+              void *wsp, size_t ws_bytes, void *stream) {
+  if (d < 1 || m < d) return fail(PSK_EINVAL, "sketch_qr needs m >= d >= 1");
+  if (!C || !R || !Rinv) return fail(PSK_EINVAL, "C, R and Rinv must be non-NULL");
+  Arena plan;
+  int rc = sketch_qr_impl(nullptr, m, d, nullptr, nullptr, plan, nullptr);
+  if (rc) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_QR)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return sketch_qr_impl(C, m, d, R, Rinv, ws, as_stream(stream));
+}
+
+int lsq_solve(const psk_mat *A, const double *b, double *x, const psk_lsq_opts *opts,
+              psk_lsq_info *info, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if (!opts || !b || !x) return fail(PSK_EINVAL, "opts, b and x must be non-NULL");
+  const psk_lsq_opts &o = *opts;
+  if (o.m < A->d) return fail(PSK_EINVAL, "lsq_solve needs opts->m >= d");
+  if ((rc = check_r(o.r))) return rc;
+  if (o.r < o.m) return fail(PSK_EINVAL, "lsq_solve needs opts->r >= opts->m");
+  if (o.max_iter < 1 || o.check_every < 1 || o.refine < 0)
+    return fail(PSK_EINVAL, "lsq_solve needs max_iter >= 1, check_every >= 1, refine >= 0");
+  if (o.prec != PSK_PREC_F64 && o.prec != PSK_PREC_BF16)
+    return fail(PSK_EDTYPE, "opts->prec must be PSK_PREC_F64 or PSK_PREC_BF16");
+  Arena plan;
+  if ((rc = lsq_impl(*A, nullptr, nullptr, o, nullptr, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LSQ)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return lsq_impl(*A, b, x, o, info, ws, as_stream(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal interfaces between the C-ABI layer and the kernel files of libpsk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/psk.h"
+#include "common.hpp"
+
+namespace psk {
+
+// Bump allocator over the caller's workspace.  A default-constructed arena
+// only measures (psk_workspace_size runs the same planning code).
+struct Arena {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  size_t peak = 0;      // high-water mark (regions may be reused, see mark())
+  bool measure = true;  // planning pass: hand out nothing, launch nothing
+  static Arena over(void *p, size_t bytes) {
+    Arena a;
+    a.base = (char *)p;
+    a.cap = bytes;
+    a.measure = false;
+    return a;
+  }
+  bool dry() const { return measure; }
+  template <typename T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = measure ? nullptr : reinterpret_cast<T *>(base + off);
+    off += count * sizeof(T);
+    if (off > peak) peak = off;
+    return p;
+  }
+  // Scratch taken after mark() can be released with release(mark) and
+  // handed out again: all work of one call is ordered on one stream.
+  size_t mark() const { return off; }
+  void release(size_t m) { off = m; }
+  bool ok() const { return measure || peak <= cap; }
+};
+
+inline size_t elem_size(int dtype) { return dtype == PSK_F64 ? 8 : 4; }
+
+// ---- CountSketch (k_sketch.hip) ---------------------------------------------
+// Bins rows 0..n-1 by bucket: perm[j] (row | sign<<31) sorted by bucket,
+// stable; bptr[b] .. bptr[b+1] is bucket b's range.  Returns 0 or a status.
+int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
+           uint32_t **perm, uint32_t **bptr);
+int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
+                   int32_t *h, int8_t *sign, hipStream_t st);
+// S*A into SA (r x d row-major, dtype of A).
+int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
+             const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st);
+
+// ---- Gaussian GEMM (k_gauss_gemm.hip) --------------------------------------
+// C (m x d, FP64) = G (m x r) * SA (r x d, dtype sa_dtype), G generated.
+int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
+               const void *SA, int sa_dtype, double *C, Arena &ws,
+               hipStream_t st);
+
+// ---- FP64 dense kernels (k_dense.hip) --------------------------------------
+// C (d x d, out_dtype) = alpha * A^T A + beta * C for dense A.
+int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
+               hipStream_t st);
+// x = alpha * rownorm^2(A B) + beta * x, dense A, B d x k FP64.
+int rownorms_dense(double alpha, const psk_mat &A, const double *B, int64_t k,
+                   double beta, double *x, Arena &ws, hipStream_t st);
+// General FP64 product C = alpha*op(A)*op(B) + beta*C, all row-major.
+int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+          const double *A, int64_t lda, const double *B, int64_t ldb,
+          double beta, double *C, int64_t ldc, Arena &ws, hipStream_t st);
+
+// ---- CSR kernels (k_csr.hip) -----------------------------------------------
+int gram_csr(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
+             hipStream_t st);
+int rownorms_csr(double alpha, const psk_mat &A, const double *B, int64_t k,
+                 double beta, double *x, Arena &ws, hipStream_t st);
+
+// ---- small dense factorizations (k_chol.hip) -------------------------------
+// flag_out (optional) receives the device address of an int set non-zero
+// when a Cholesky pivot was not positive (numerically rank deficient C).
+int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R,
+                   double *Rinv, Arena &ws, hipStream_t st,
+                   int **flag_out = nullptr);
+
+// ---- LSQR (k_lsqr.hip) -----------------------------------------------------
+int lsq_impl(const psk_mat &A, const double *b, double *x,
+             const psk_lsq_opts &o, psk_lsq_info *info, Arena &ws,
+             hipStream_t st);
+
+}  // namespace psk

@@ -1,0 +1,532 @@
+// CountSketch on gfx950: hash, stable binning of rows by bucket, and the
+// bucket-owned row reduction that forms S*A.
+//
+// Paper mapping (arXiv 2203.02798): the hash is Definition 3; the binned row
+// list is the Block-Column CountSketch of section 2.3 (b_r = r: per bucket a
+// list of signed row indices, n indices in total); the reduction is Algorithm
+// bcs_multiply with one bucket's rows summed by one wavefront, so no two
+// workers ever write the same output row (no atomics, deterministic order).
+//
+// Binning is a stable LSD radix sort of (bucket, row|sign) pairs with 8-bit
+// digits: per 2048-key tile a digit histogram, one exclusive scan over
+// (digit, tile), then a stable scatter whose in-tile ranks come from
+// wavefront ballots.  Stability keeps each bucket's rows in increasing row
+// order, which fixes the summation order.
+#include "internal.hpp"
+
+namespace psk {
+namespace {
+
+constexpr int kRadix = 256;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per block
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096 per block
+
+// ---------------------------------------------------------------------------
+// hash
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_hash_export(int64_t row0, int64_t count,
+                                                     uint32_t r, uint64_t seed,
+                                                     int32_t *__restrict__ h,
+                                                     int8_t *__restrict__ sign) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= count) return;
+  uint32_t b, neg;
+  cs_hash_row((uint64_t)(row0 + j), r, seed, b, neg);
+  if (h) h[j] = (int32_t)b;
+  if (sign) sign[j] = neg ? (int8_t)-1 : (int8_t)1;
+}
+
+__global__ __launch_bounds__(256) void k_hash_keys(int64_t n, uint32_t r,
+                                                   uint64_t seed,
+                                                   uint32_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t b, neg;
+  cs_hash_row((uint64_t)i, r, seed, b, neg);
+  keys[i] = b;
+  vals[i] = (uint32_t)i | (neg << 31);
+}
+
+// ---------------------------------------------------------------------------
+// radix sort pass: per-tile digit histogram (digit-major layout)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(
+    const uint32_t *__restrict__ keys, int64_t n, int shift, uint32_t mask,
+    uint32_t *__restrict__ hist, int64_t ntiles) {
+  __shared__ uint32_t h[kRadix];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t idx = base + it * kSortThreads + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & mask], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// stable scatter of one tile, ranks from ballots
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    int64_t n, int shift, int nbits, const uint32_t *__restrict__ offs,
+    int64_t ntiles, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+  __shared__ uint32_t run[kRadix];
+  __shared__ uint32_t wc[4][kRadix];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
+  run[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wc[q][tid] = 0;
+  __syncthreads();
+  const uint32_t mask = (1u << nbits) - 1u;
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t idx = base + it * kSortThreads + tid;
+    const bool valid = idx < n;
+    const uint32_t k = valid ? kin[idx] : 0u;
+    const uint32_t v = valid ? vin[idx] : 0u;
+    const uint32_t dg = (k >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wc[w][dg] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[dg] + rank;
+      for (int q = 0; q < w; ++q) pos += wc[q][dg];
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wc[q][tid] = 0;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of uint32 (three kernels: tile scan, scan of tile sums, add)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t t, uint32_t &total) {
+  __shared__ uint32_t wsum[kScanThreads / 64];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  uint32_t inc = t;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  total = 0;
+#pragma unroll
+  for (int q = 0; q < kScanThreads / 64; ++q) {
+    if (q < w) pre += wsum[q];
+    total += wsum[q];
+  }
+  __syncthreads();
+  return pre + inc - t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint32_t *__restrict__ data,
+                                                             int64_t L,
+                                                             uint32_t *__restrict__ sums) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t t = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < L) ? data[base + i] : 0u;
+    t += v[i];
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan(t, total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < L) data[base + i] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(uint32_t *__restrict__ sums,
+                                                            int64_t nb) {
+  uint32_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kScanTile) {
+    const int64_t base = c0 + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t t = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      v[i] = (base + i < nb) ? sums[base + i] : 0u;
+      t += v[i];
+    }
+    uint32_t total;
+    uint32_t run = carry + block_excl_scan(t, total);
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (base + i < nb) sums[base + i] = run;
+      run += v[i];
+    }
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(uint32_t *__restrict__ data, int64_t L,
+                                                  const uint32_t *__restrict__ sums) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < L) data[i] += sums[i / kScanTile];
+}
+
+int scan_plan(int64_t L, Arena &ws, uint32_t **sums) {
+  *sums = ws.take<uint32_t>((size_t)ceil_div(L, kScanTile) + 1);
+  return 0;
+}
+
+void scan_run(uint32_t *data, int64_t L, uint32_t *sums, hipStream_t st) {
+  const int64_t nb = ceil_div(L, kScanTile);
+  k_scan_tiles<<<(unsigned)nb, kScanThreads, 0, st>>>(data, L, sums);
+  k_scan_sums<<<1, kScanThreads, 0, st>>>(sums, nb);
+  k_scan_add<<<(unsigned)ceil_div(L, 256), 256, 0, st>>>(data, L, sums);
+}
+
+// bucket b's range starts at the first sorted position whose key is >= b
+__global__ __launch_bounds__(256) void k_bucket_ptr(const uint32_t *__restrict__ skeys,
+                                                    int64_t n, uint32_t r,
+                                                    uint32_t *__restrict__ bptr) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > n) return;
+  const int64_t prev = j > 0 ? (int64_t)skeys[j - 1] : -1;
+  const int64_t cur = j < n ? (int64_t)skeys[j] : (int64_t)r;
+  for (int64_t b = prev + 1; b <= cur; ++b) bptr[b] = (uint32_t)j;
+}
+
+__global__ void k_fill_identity_ptr(uint32_t *bptr, int64_t n) {
+  bptr[0] = 0;
+  bptr[1] = (uint32_t)n;
+}
+
+// ---------------------------------------------------------------------------
+// S*A, dense A: one wavefront per (bucket, split); each lane owns VW adjacent
+// columns in each of CH column groups, accumulating in registers.
+// ---------------------------------------------------------------------------
+template <typename T, int VW>
+struct Vec;
+template <>
+struct Vec<double, 1> { typedef double type; };
+template <>
+struct Vec<double, 2> { typedef double2 type; };
+template <>
+struct Vec<float, 1> { typedef float type; };
+template <>
+struct Vec<float, 2> { typedef float2 type; };
+template <>
+struct Vec<float, 4> { typedef float4 type; };
+
+template <typename T, int VW>
+__device__ __forceinline__ void vload(const T *p, T (&x)[VW]) {
+  typedef typename Vec<T, VW>::type V;
+  const V v = *reinterpret_cast<const V *>(p);
+  const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+  for (int q = 0; q < VW; ++q) x[q] = e[q];
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void vstore(T *p, const T (&x)[VW]) {
+  typedef typename Vec<T, VW>::type V;
+  V v;
+  T *e = reinterpret_cast<T *>(&v);
+#pragma unroll
+  for (int q = 0; q < VW; ++q) e[q] = x[q];
+  *reinterpret_cast<V *>(p) = v;
+}
+
+template <typename T, int VW, int CH, int U>
+__global__ __launch_bounds__(256) void k_scatter_dense(
+    const T *__restrict__ A, int64_t ld, int64_t d, int64_t r,
+    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
+    int splits, T *__restrict__ out) {
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= r * splits) return;
+  const int64_t b = wave / splits;
+  const int s = (int)(wave - b * splits);
+  const uint32_t lo = bptr[b];
+  const uint32_t len = bptr[b + 1] - lo;
+  const uint32_t j0 = lo + (uint32_t)(((uint64_t)len * s) / splits);
+  const uint32_t j1 = lo + (uint32_t)(((uint64_t)len * (s + 1)) / splits);
+  T *orow = out + ((int64_t)s * r + b) * d;
+  const int lane = threadIdx.x & 63;
+  constexpr int64_t kSpan = 64 * VW * CH;
+  for (int64_t c0 = 0; c0 < d; c0 += kSpan) {
+    T acc[CH][VW];
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+#pragma unroll
+      for (int q = 0; q < VW; ++q) acc[c][q] = T(0);
+    uint32_t j = j0;
+    for (; j + U <= j1; j += U) {
+      T x[U][CH][VW];
+      uint32_t neg[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t pv = perm[j + u];
+        const int64_t row = (int64_t)(pv & 0x7fffffffu);
+        neg[u] = pv >> 31;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          const int64_t col = c0 + (int64_t)(c * 64 + lane) * VW;
+          if (col < d) {
+            vload<T, VW>(A + row * ld + col, x[u][c]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < VW; ++q) x[u][c][q] = T(0);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+#pragma unroll
+          for (int q = 0; q < VW; ++q)
+            acc[c][q] += neg[u] ? -x[u][c][q] : x[u][c][q];
+    }
+    for (; j < j1; ++j) {
+      const uint32_t pv = perm[j];
+      const int64_t row = (int64_t)(pv & 0x7fffffffu);
+      const uint32_t ng = pv >> 31;
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        const int64_t col = c0 + (int64_t)(c * 64 + lane) * VW;
+        if (col < d) {
+          T xv[VW];
+          vload<T, VW>(A + row * ld + col, xv);
+#pragma unroll
+          for (int q = 0; q < VW; ++q) acc[c][q] += ng ? -xv[q] : xv[q];
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t col = c0 + (int64_t)(c * 64 + lane) * VW;
+      if (col < d) vstore<T, VW>(orow + col, acc[c]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// S*A, CSR A: one wavefront per (bucket, split) with a private LDS row of d
+// accumulators; rows of the bucket are applied one after another, a row's
+// entries spread over the lanes.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_csr(
+    const T *__restrict__ vals, const int64_t *__restrict__ indptr,
+    const int32_t *__restrict__ indices, int64_t d, int64_t dpad, int64_t r,
+    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
+    int splits, T *__restrict__ out) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *acc = reinterpret_cast<T *>(smem_raw) + (threadIdx.x >> 6) * dpad;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= r * splits) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t b = wave / splits;
+  const int s = (int)(wave - b * splits);
+  const uint32_t lo = bptr[b];
+  const uint32_t len = bptr[b + 1] - lo;
+  const uint32_t j0 = lo + (uint32_t)(((uint64_t)len * s) / splits);
+  const uint32_t j1 = lo + (uint32_t)(((uint64_t)len * (s + 1)) / splits);
+  for (int64_t c = lane; c < d; c += 64) acc[c] = T(0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t j = j0; j < j1; ++j) {
+    const uint32_t pv = perm[j];
+    const int64_t row = (int64_t)(pv & 0x7fffffffu);
+    const bool ng = (pv >> 31) != 0;
+    const int64_t p0 = indptr[row];
+    const int64_t p1 = indptr[row + 1];
+    for (int64_t p = p0 + lane; p < p1; p += 64) {
+      const int32_t col = indices[p];
+      const T v = vals[p];
+      atomicAdd(&acc[col], ng ? -v : v);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  T *orow = out + ((int64_t)s * r + b) * d;
+  for (int64_t c = lane; c < d; c += 64) orow[c] = acc[c];
+}
+
+// SA[b, c] = sum over splits of partial[s, b, c], splits in increasing order
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine_splits(const T *__restrict__ part,
+                                                        int64_t rd, int splits,
+                                                        T *__restrict__ SA) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rd) return;
+  T acc = part[e];
+  for (int s = 1; s < splits; ++s) acc += part[(int64_t)s * rd + e];
+  SA[e] = acc;
+}
+
+int choose_splits(int64_t n, int64_t r) {
+  // Enough wavefronts to cover the chip when buckets are few and long;
+  // at least ~32 rows per split on average.
+  const int64_t target_waves = 8192;
+  if (r >= target_waves) return 1;
+  int64_t s = ceil_div(target_waves, r);
+  const int64_t by_rows = n / (r * 32);
+  if (s > by_rows) s = by_rows;
+  if (s > 64) s = 64;
+  return s < 1 ? 1 : (int)s;
+}
+
+template <typename T, int VW>
+void launch_dense(const psk_mat &A, int64_t r, const uint32_t *perm,
+                  const uint32_t *bptr, int splits, T *out, hipStream_t st) {
+  const int64_t waves = r * splits;
+  const unsigned blocks = (unsigned)ceil_div(waves, 4);
+  const int64_t span1 = 64 * VW;  // columns per lane group
+  if (A.d <= span1)
+    k_scatter_dense<T, VW, 1, 8><<<blocks, 256, 0, st>>>(
+        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
+  else if (A.d <= 2 * span1)
+    k_scatter_dense<T, VW, 2, 4><<<blocks, 256, 0, st>>>(
+        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
+  else
+    k_scatter_dense<T, VW, 4, 4><<<blocks, 256, 0, st>>>(
+        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host entry points
+// ---------------------------------------------------------------------------
+int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
+                   int32_t *h, int8_t *sign, hipStream_t st) {
+  if (count == 0) return 0;
+  k_hash_export<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(row0, count, r,
+                                                                 seed, h, sign);
+  PSK_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
+           uint32_t **perm, uint32_t **bptr) {
+  int bits = 0;
+  while (bits < 32 && ((uint64_t)1 << bits) < (uint64_t)r) ++bits;
+  const int passes = (bits + 7) / 8;
+  const int64_t ntiles = ceil_div(n, kSortTile);
+  const int64_t L = (int64_t)kRadix * ntiles;
+  uint32_t *k0 = ws.take<uint32_t>(n);
+  uint32_t *v0 = ws.take<uint32_t>(n);
+  uint32_t *k1 = passes ? ws.take<uint32_t>(n) : nullptr;
+  uint32_t *v1 = passes ? ws.take<uint32_t>(n) : nullptr;
+  uint32_t *hist = passes ? ws.take<uint32_t>(L) : nullptr;
+  uint32_t *sums = nullptr;
+  if (passes) scan_plan(L, ws, &sums);
+  uint32_t *bp = ws.take<uint32_t>((size_t)r + 1);
+  if (ws.dry()) return 0;
+  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for CountSketch binning");
+
+  k_hash_keys<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, r, seed, k0, v0);
+  uint32_t *kin = k0, *vin = v0, *kout = k1, *vout = v1;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
+    const uint32_t mask = (1u << nb) - 1u;
+    k_radix_hist<<<(unsigned)ntiles, kSortThreads, 0, st>>>(kin, n, shift, mask, hist,
+                                                            ntiles);
+    scan_run(hist, L, sums, st);
+    k_radix_scatter<<<(unsigned)ntiles, kSortThreads, 0, st>>>(kin, vin, n, shift, nb,
+                                                               hist, ntiles, kout, vout);
+    uint32_t *t;
+    t = kin; kin = kout; kout = t;
+    t = vin; vin = vout; vout = t;
+  }
+  if (passes)
+    k_bucket_ptr<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(kin, n, r, bp);
+  else
+    k_fill_identity_ptr<<<1, 1, 0, st>>>(bp, n);
+  PSK_HIP_TRY(hipGetLastError());
+  *perm = vin;
+  *bptr = bp;
+  return 0;
+}
+
+int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
+             const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st) {
+  const int splits = choose_splits(A.n, r);
+  const size_t es = elem_size(A.dtype);
+  void *part = nullptr;
+  if (splits > 1) part = ws.take<unsigned char>((size_t)splits * r * A.d * es);
+  if (ws.dry()) return 0;
+  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for S*A");
+  void *out = splits > 1 ? part : SA;
+  if (A.format == PSK_DENSE) {
+    const uintptr_t addr = (uintptr_t)A.values;
+    if (A.dtype == PSK_F64) {
+      const bool v2 = (A.d % 2 == 0) && (A.ld % 2 == 0) && (addr % 16 == 0);
+      if (v2)
+        launch_dense<double, 2>(A, r, perm, bptr, splits, (double *)out, st);
+      else
+        launch_dense<double, 1>(A, r, perm, bptr, splits, (double *)out, st);
+    } else {
+      const bool v4 = (A.d % 4 == 0) && (A.ld % 4 == 0) && (addr % 16 == 0);
+      const bool v2 = (A.d % 2 == 0) && (A.ld % 2 == 0) && (addr % 8 == 0);
+      if (v4)
+        launch_dense<float, 4>(A, r, perm, bptr, splits, (float *)out, st);
+      else if (v2)
+        launch_dense<float, 2>(A, r, perm, bptr, splits, (float *)out, st);
+      else
+        launch_dense<float, 1>(A, r, perm, bptr, splits, (float *)out, st);
+    }
+  } else {
+    const int64_t dpad = (A.d + 3) & ~(int64_t)3;
+    int wpb = 4;
+    while (wpb > 1 && (size_t)wpb * dpad * es > 65536) --wpb;
+    if ((size_t)dpad * es > 65536)
+      return fail(PSK_EUNSUPPORTED, "CSR S*A supports d*elem <= 64 KiB");
+    const size_t lds = (size_t)wpb * dpad * es;
+    const int64_t waves = (int64_t)r * splits;
+    const unsigned blocks = (unsigned)ceil_div(waves, wpb);
+    if (A.dtype == PSK_F64)
+      k_scatter_csr<double><<<blocks, 64 * wpb, lds, st>>>(
+          (const double *)A.values, A.indptr, A.indices, A.d, dpad, r, perm, bptr,
+          splits, (double *)out);
+    else
+      k_scatter_csr<float><<<blocks, 64 * wpb, lds, st>>>(
+          (const float *)A.values, A.indptr, A.indices, A.d, dpad, r, perm, bptr,
+          splits, (float *)out);
+  }
+  if (splits > 1) {
+    const int64_t rd = (int64_t)r * A.d;
+    if (A.dtype == PSK_F64)
+      k_combine_splits<double><<<(unsigned)ceil_div(rd, 256), 256, 0, st>>>(
+          (const double *)part, rd, splits, (double *)SA);
+    else
+      k_combine_splits<float><<<(unsigned)ceil_div(rd, 256), 256, 0, st>>>(
+          (const float *)part, rd, splits, (float *)SA);
+  }
+  PSK_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace psk

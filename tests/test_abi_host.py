@@ -1,0 +1,120 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/psk.h declares, plans workspaces, and rejects bad
+arguments with the documented status codes before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2203_02798_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "psk.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libpsk.so is not built; run `python -m paper_2203_02798_amd.build`")
+    return L.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared_functions()
+    assert set(declared) == set(L.EXPORTED), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_version(lib):
+    assert b"gfx950" in lib.psk_version()
+
+
+def _dense(n, d, dtype=L.PSK_F64, ld=None):
+    m = L.PskMat()
+    m.format, m.dtype, m.n, m.d = L.PSK_DENSE, dtype, n, d
+    m.ld = ld if ld is not None else d
+    m.values = 0x1000  # never dereferenced by planning/validation
+    return m
+
+
+def _csr(n, d, nnz):
+    m = L.PskMat()
+    m.format, m.dtype, m.n, m.d, m.ld, m.nnz = L.PSK_CSR, L.PSK_F64, n, d, d, nnz
+    m.values, m.indptr, m.indices = 0x1000, 0x2000, 0x3000
+    return m
+
+
+def _ws(op, mat, m=0, r=1, k=1, prec=0):
+    out = ctypes.c_size_t(0)
+    st = L.lib().psk_workspace_size(op, ctypes.byref(mat), m, r, k, prec, ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_planning(lib):
+    st, b1 = _ws(L.PSK_OP_SKETCH_CS, _dense(20000, 50), r=2500)
+    assert st == 0 and b1 >= 20000 * 4 * 2
+    st, b2 = _ws(L.PSK_OP_SKETCH_GCS, _dense(20000, 50), m=200, r=2500)
+    assert st == 0 and b2 > b1 + 2500 * 50 * 8
+    st, b3 = _ws(L.PSK_OP_SKETCH_GCS, _csr(1_000_000, 500, 500_000), m=2000, r=250_000)
+    assert st == 0 and b3 > 250_000 * 500 * 8  # S*A is staged in the workspace
+    st, b4 = _ws(L.PSK_OP_GRAM, _dense(1000, 64))
+    assert st == 0 and b4 > 0
+    st, b5 = _ws(L.PSK_OP_ROWNORMS, _csr(1000, 64, 100), k=64)
+    assert st == 0 and b5 >= 64 * 64 * 8
+    q = L.PskMat(); q.n, q.d = 400, 100
+    st, b6 = _ws(L.PSK_OP_QR, q)
+    assert st == 0 and b6 >= 2 * 400 * 100 * 8
+    st, b7 = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=128, r=1024)
+    assert st == 0 and b7 > 5000 * 8
+
+
+def test_rejects_bad_arguments_without_device_work(lib):
+    stream = None
+    sa = ctypes.c_void_p(0x4000)
+    ws = ctypes.c_void_p(0x5000)
+    assert lib.sketch_cs(None, 10, 0, sa, ws, 1 << 20, stream) == -1
+    bad = _dense(10, 5)
+    assert lib.sketch_cs(ctypes.byref(bad), 0, 0, sa, ws, 1 << 20, stream) == -1
+    assert b"r must be" in lib.psk_last_error()
+    bad.ld = 3
+    assert lib.sketch_cs(ctypes.byref(bad), 4, 0, sa, ws, 1 << 20, stream) == -1
+    bad = _dense(10, 5, dtype=7)
+    assert lib.sketch_cs(ctypes.byref(bad), 4, 0, sa, ws, 1 << 20, stream) == -2
+    good = _dense(10, 5)
+    assert lib.sketch_cs(ctypes.byref(good), 4, 0, sa, ws, 16, stream) == -3
+    assert lib.sketch_gcs(ctypes.byref(good), -1, 4, 0, 0, sa, ws, 1 << 20, stream) == -1
+    assert lib.sketch_gcs(ctypes.byref(good), 3, 4, 0, 9, sa, ws, 1 << 20, stream) == -2
+    assert lib.cs_hash(0, 10, 0, 0, None, None, stream) == -1
+    assert lib.cs_hash(-1, 10, 5, 0, None, None, stream) == -1
+    assert lib.sketch_qr(sa, 3, 5, sa, sa, ws, 1 << 20, stream) == -1
+    assert lib.rownorms_sq(1.0, ctypes.byref(good), None, 3, 0.0, sa, ws, 1 << 20,
+                           stream) == -1
+    big = _dense(1 << 31, 5)
+    assert lib.sketch_cs(ctypes.byref(big), 4, 0, sa, ws, 1 << 20, stream) == -7
+    csr = _csr(10, 5, 3)
+    csr.indptr = None
+    assert lib.gram(1.0, ctypes.byref(csr), 0.0, sa, ws, 1 << 20, stream) == -1
+    o = L.PskLsqOpts(m=2, r=8, seed=0, prec=0, max_iter=10, refine=0, check_every=1,
+                     atol=1e-12, btol=1e-12)
+    info = L.PskLsqInfo()
+    assert lib.lsq_solve(ctypes.byref(good), sa, sa, ctypes.byref(o), ctypes.byref(info),
+                         ws, 1 << 20, stream) == -1  # m < d
+    o.m, o.r = 8, 4
+    assert lib.lsq_solve(ctypes.byref(good), sa, sa, ctypes.byref(o), ctypes.byref(info),
+                         ws, 1 << 20, stream) == -1  # r < m
+
+
+def test_python_binding_reports_missing_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(L, "_LIB", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        L.lib()

@@ -1,0 +1,293 @@
+"""Device path vs the FP64 oracle, element by element, on seeded inputs that
+span several tiles with ragged tails.  Every call goes through the C ABI of
+libpsk.so (via the ctypes binding)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from helpers import U32, U64, gamma, rel_fro, sketch_abs_bound, to_device
+from oracle import gram as og
+from oracle import leverage as olev
+from oracle import lsq as olsq
+from oracle import sketch as osk
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2203_02798_amd import api as a
+    return a
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# hash
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("row0,count,r,seed", [
+    (0, 20000, 2500, 0), (0, 100000, 250000, 1), (123456789, 50000, 1_000_000, 7),
+    (0, 4096, 1, 3), (2 ** 31 - 4096, 4096, 2 ** 31 - 1, 0xFFFFFFFFFFFFFFFF),
+    (5, 0, 10, 2), (0, 777, 3, 0xDEADBEEF)])
+def test_cs_hash_bit_exact(api, row0, count, r, seed):
+    _say(f"cs_hash row0={row0} count={count} r={r}")
+    h, s = api.cs_hash(count, r, seed, row0=row0)
+    ho, so = osk.cs_hash(count, r, seed, row0=row0)
+    np.testing.assert_array_equal(h.cpu().numpy().astype(np.int64), ho)
+    np.testing.assert_array_equal(s.cpu().numpy(), so)
+
+
+# ---------------------------------------------------------------------------
+# S*A
+# ---------------------------------------------------------------------------
+DENSE_CASES = [  # n, d, r
+    (20000, 50, 2500), (3001, 37, 97), (4000, 257, 64), (5000, 512, 5000),
+    (20000, 8, 4), (1000, 1, 2000), (777, 130, 1)]
+
+
+@pytest.mark.parametrize("n,d,r", DENSE_CASES)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_sketch_cs_dense_integer_bit_exact(api, n, d, r, dt):
+    _say(f"sketch_cs dense int n={n} d={d} r={r} {dt}")
+    npdt = np.float64 if dt == "f64" else np.float32
+    a = synth.dense_integer(n, d, seed=n + d, lo=-4, hi=4, dtype=npdt)
+    sa = api.sketch_cs(to_device(a), r, seed=11).cpu().numpy()
+    np.testing.assert_array_equal(sa.astype(np.float64), osk.sketch_cs(a, r, 11))
+
+
+@pytest.mark.parametrize("n,d,r", [(20000, 50, 2500), (3001, 37, 97), (4000, 257, 64),
+                                   (20000, 8, 4), (777, 130, 1)])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_sketch_cs_dense_real_within_bound(api, n, d, r, dt):
+    _say(f"sketch_cs dense real n={n} d={d} r={r} {dt}")
+    npdt = np.float64 if dt == "f64" else np.float32
+    a = synth.dense_gaussian(n, d, seed=3, dtype=npdt)
+    sa = api.sketch_cs(to_device(a), r, seed=5).cpu().numpy().astype(np.float64)
+    ref = osk.sketch_cs(a, r, 5)
+    bound = sketch_abs_bound(a, r, 5, U64 if dt == "f64" else U32)
+    assert np.all(np.abs(sa - ref) <= bound + 1e-300)
+
+
+def test_sketch_cs_strided_rows(api):
+    a = synth.dense_integer(3000, 64, seed=2)
+    full = to_device(a)
+    view = full[:, :50]  # ld = 64 > d = 50
+    sa = api.sketch_cs(view, 301, seed=4).cpu().numpy()
+    np.testing.assert_array_equal(sa, osk.sketch_cs(a[:, :50], 301, 4))
+
+
+CSR_CASES = [  # n, d, density, r
+    (20000, 500, 1e-3, 2500), (50000, 64, 0.05, 4096), (3000, 33, 0.2, 7),
+    (1000, 700, 0.01, 100000), (4000, 16, 0.5, 1)]
+
+
+@pytest.mark.parametrize("n,d,dens,r", CSR_CASES)
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_sketch_cs_csr_integer_bit_exact(api, n, d, dens, r, dt):
+    _say(f"sketch_cs csr int n={n} d={d} r={r} {dt}")
+    a = synth.csr_integer(n, d, dens, seed=9, dtype=np.float64)
+    if dt == "f32":
+        a = a.astype(np.float32)
+    sa = api.sketch_cs(to_device(a), r, seed=13).cpu().numpy().astype(np.float64)
+    np.testing.assert_array_equal(sa, osk.sketch_cs(a, r, 13))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_sketch_cs_csr_zipf_real_within_bound(api, dt):
+    npdt = np.float64 if dt == "f64" else np.float32
+    a = synth.csr_zipf(100000, 300, 2e-3, seed=4, dtype=npdt)
+    r = 20000
+    sa = api.sketch_cs(to_device(a), r, seed=6).cpu().numpy().astype(np.float64)
+    ref = osk.sketch_cs(a, r, 6)
+    # CSR accumulation: per output entry at most (bucket rows) additions
+    bound = sketch_abs_bound(a, r, 6, U64 if dt == "f64" else U32)
+    assert np.all(np.abs(sa - ref) <= bound + 1e-300)
+
+
+def test_sketch_cs_csr_empty_rows_and_empty_matrix(api):
+    a = synth.csr_from_parts(1000, 20, [3, 3, 999], [1, 5, 19], [1.0, -2.0, 4.0])
+    sa = api.sketch_cs(to_device(a), 50, seed=1).cpu().numpy()
+    np.testing.assert_array_equal(sa, osk.sketch_cs(a, 50, 1))
+    z = synth.csr_from_parts(500, 10, [], [], [])
+    sa = api.sketch_cs(to_device(z), 40, seed=1).cpu().numpy()
+    assert np.all(sa == 0)
+
+
+# ---------------------------------------------------------------------------
+# G*S*A (FP64)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,n,d,m,r", [
+    ("dense", 20000, 50, 200, 2500),      # the small dense FP64 workload
+    ("dense", 6000, 130, 77, 3001),
+    ("csr", 100000, 500, 300, 25000),
+    ("dense32", 8000, 96, 129, 1024)])
+def test_sketch_gcs_f64(api, kind, n, d, m, r):
+    _say(f"sketch_gcs {kind} n={n} d={d} m={m} r={r}")
+    if kind == "csr":
+        a = synth.csr_uniform(n, d, 1e-3, seed=1)
+    elif kind == "dense32":
+        a = synth.dense_gaussian(n, d, seed=1, dtype=np.float32)
+    else:
+        a = synth.dense_gaussian(n, d, seed=1)
+    c = api.sketch_gcs(to_device(a), m, r, seed=21).cpu().numpy()
+    ref = osk.sketch_gcs(a, m, r, 21)
+    err = rel_fro(c, ref)
+    _say(f"  rel err {err:.3e}")
+    if kind == "dense32":
+        # S*A is accumulated in FP32 for FP32 input: the GEMM (FP64) propagates
+        # that rounding, |dC| <= |G| gamma_k (|S||A|), plus the FP64 GEMM's own
+        bound = np.abs(osk.gaussian_block(m, 0, r, 21)) @ sketch_abs_bound(a, r, 21, U32)
+        assert np.all(np.abs(c - ref) <= bound + 1e-12 * np.abs(ref).max())
+    else:
+        assert err <= 1e-12
+
+
+def test_sketch_gcs_m0_is_sketch_cs(api):
+    a = synth.dense_gaussian(3000, 20, seed=2)
+    x = api.sketch_gcs(to_device(a), 0, 300, seed=3).cpu().numpy()
+    y = api.sketch_cs(to_device(a), 300, seed=3).cpu().numpy()
+    np.testing.assert_array_equal(x, y)
+
+
+def test_sketch_gcs_deterministic(api):
+    a = to_device(synth.csr_uniform(50000, 200, 5e-3, seed=3))
+    c1 = api.sketch_gcs(a, 150, 8000, seed=5)
+    c2 = api.sketch_gcs(a, 150, 8000, seed=5)
+    assert torch.equal(c1, c2)
+
+
+# ---------------------------------------------------------------------------
+# Gram
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,n,d", [("dense", 20000, 50), ("dense", 3001, 130),
+                                      ("csr", 100000, 500), ("csr", 20000, 70)])
+def test_gram_f64(api, kind, n, d):
+    _say(f"gram {kind} n={n} d={d}")
+    a = synth.csr_uniform(n, d, 2e-3 if d > 100 else 0.05, seed=7) if kind == "csr" \
+        else synth.dense_gaussian(n, d, seed=7)
+    g = api.gram(to_device(a)).cpu().numpy()
+    ref = og.gram(1.0, a)
+    assert rel_fro(g, ref) <= 1e-13
+    np.testing.assert_array_equal(g, g.T)
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_gram_integer_exact_and_alpha_beta(api, kind):
+    a = synth.csr_integer(5000, 40, 0.1, seed=1) if kind == "csr" \
+        else synth.dense_integer(5000, 40, seed=1)
+    g = api.gram(to_device(a)).cpu().numpy()
+    np.testing.assert_array_equal(g, og.gram(1.0, a))
+    c0 = synth.dense_integer(40, 40, seed=2)
+    c = to_device(c0)
+    api.gram(to_device(a), alpha=2.0, beta=-3.0, C=c)
+    np.testing.assert_array_equal(c.cpu().numpy(), og.gram(2.0, a, -3.0, c0))
+    cn = torch.full((40, 40), float("nan"), dtype=torch.float64, device="cuda")
+    api.gram(to_device(a), alpha=1.0, beta=0.0, C=cn)
+    assert torch.isfinite(cn).all()
+
+
+def test_gram_f32_input(api):
+    a = synth.dense_gaussian(10000, 64, seed=3, dtype=np.float32)
+    g = api.gram(to_device(a)).cpu().numpy().astype(np.float64)
+    assert rel_fro(g, og.gram(1.0, a)) <= 1e-6
+
+
+# ---------------------------------------------------------------------------
+# squared row norms
+# ---------------------------------------------------------------------------
+def _rownorm_check(xh, a, b, alpha=1.0, beta=0.0, x0=None):
+    ref = og.rownorms_sq(alpha, a, b, beta, x0)
+    z = og.rownorm_bound_terms(a, b)
+    nnz_row = a.getnnz(axis=1) if sp.issparse(a) else np.full(a.shape[0], a.shape[1])
+    N = np.maximum(b.shape[1], nnz_row.max() ** 2) + a.shape[1] + 2
+    bound = 3 * gamma(N, U64) * abs(alpha) * z + 1e-300
+    if beta != 0.0:
+        bound = bound + 2 * U64 * np.abs(beta * x0)
+    assert np.all(np.abs(xh - ref) <= bound + 4 * U64 * np.abs(ref))
+
+
+@pytest.mark.parametrize("kind,n,d,k", [("dense", 20000, 50, 50), ("dense", 5000, 130, 257),
+                                        ("dense32", 7000, 256, 256), ("csr", 100000, 500, 500),
+                                        ("csrzipf", 20000, 300, 64)])
+def test_rownorms_sq(api, kind, n, d, k):
+    _say(f"rownorms {kind} n={n} d={d} k={k}")
+    if kind == "csr":
+        a = synth.csr_uniform(n, d, 1e-3, seed=2)
+    elif kind == "csrzipf":
+        a = synth.csr_zipf(n, d, 1e-2, seed=2, dtype=np.float64)
+    elif kind == "dense32":
+        a = synth.dense_gaussian(n, d, seed=2, dtype=np.float32)
+    else:
+        a = synth.dense_gaussian(n, d, seed=2)
+    b = synth.dense_gaussian(d, k, seed=3)
+    x = api.rownorms_sq(to_device(a), torch.from_numpy(b).cuda()).cpu().numpy()
+    _rownorm_check(x, a, b)
+
+
+def test_rownorms_alpha_beta(api):
+    a = synth.dense_gaussian(3000, 20, seed=4)
+    b = synth.dense_gaussian(20, 20, seed=5)
+    x0 = synth.dense_gaussian(3000, 1, seed=6)[:, 0]
+    xd = torch.from_numpy(x0.copy()).cuda()
+    api.rownorms_sq(to_device(a), torch.from_numpy(b).cuda(), alpha=0.5, beta=2.0, x=xd)
+    _rownorm_check(xd.cpu().numpy(), a, b, 0.5, 2.0, x0)
+
+
+# ---------------------------------------------------------------------------
+# QR of the sketch, leverage scores, least squares
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m,d,cond", [(200, 50, 1e2), (1030, 257, 1e6), (96, 96, 1e3)])
+def test_sketch_qr(api, m, d, cond):
+    _say(f"sketch_qr m={m} d={d} cond={cond}")
+    c, _, _ = synth.lsq_problem(m, d, cond, seed=1, noise=0.0)
+    r, ri = api.sketch_qr(torch.from_numpy(c).cuda())
+    r, ri = r.cpu().numpy(), ri.cpu().numpy()
+    assert np.all(np.tril(r, -1) == 0) and np.all(np.diag(r) > 0)
+    # backward error of the factorization: R^T R = C^T C
+    assert np.linalg.norm(r.T @ r - c.T @ c) / np.linalg.norm(c.T @ c) <= 1e-13
+    ro = olev.qr_r(c)
+    assert rel_fro(r, ro) <= 50 * cond * U64
+    assert np.linalg.norm(ri @ r - np.eye(d)) <= 1e3 * cond * d * U64
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_leverage_pipeline(api, kind):
+    n, d, m, r = (20000, 50, 200, 2500) if kind == "dense" else (100000, 64, 256, 8192)
+    a = synth.dense_gaussian(n, d, seed=5) if kind == "dense" \
+        else synth.csr_uniform(n, d, 0.05, seed=5)
+    ad = to_device(a)
+    c = api.sketch_gcs(ad, m, r, seed=9)
+    _, ri = api.sketch_qr(c)
+    th = api.rownorms_sq(ad, ri).cpu().numpy()
+    tt, _ = olev.leverage_sketched(a, m, r, 9)
+    # empty CSR rows have leverage exactly 0 on both sides
+    assert np.all(np.abs(th - tt) <= 1e-9 * tt + 1e-300)
+    # sketched leverage scores bracket the exact ones (OSE distortion)
+    ex = olev.leverage_exact(a)
+    assert abs(th.sum() - d) < 0.5 * d
+
+
+@pytest.mark.parametrize("kind,cond", [("dense", 1e3), ("dense", 1e8), ("csr", 1e2)])
+def test_lsq_solve_matches_lapack(api, kind, cond):
+    n, d = 20000, 32
+    if kind == "csr":
+        a = synth.csr_uniform(n, d, 0.2, seed=2)
+        xt = np.random.default_rng(0).standard_normal(d)
+        b = a @ xt + 1e-3 * np.random.default_rng(1).standard_normal(n)
+    else:
+        a, b, _ = synth.lsq_problem(n, d, cond, seed=2)
+    x, info = api.lsq_solve(to_device(a), torch.from_numpy(b).cuda(), m=4 * d, r=d * d,
+                            seed=3)
+    _say(f"lsq {kind} cond={cond}: {info}")
+    x = x.cpu().numpy()
+    xs = olsq.lstsq(a, b)
+    rs, _ = olsq.lsq_quality(a, b, xs)
+    rn, ne = olsq.lsq_quality(a, b, x)
+    assert (rn - rs) / rs <= 1e-10
+    assert ne <= 1e-10
+    assert info["status"] == "PSK_OK"
