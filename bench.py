@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark of the sketch / Gram / leverage / least-squares hot path on one
+MI355X.
+
+One step is one pass of the whole path over the sparse workload (CSR A,
+1,000,000 x 500, density 1e-3, FP64; CountSketch r = 250,000 buckets then a
+Gaussian with m = 2,000 rows):
+
+    C     = G*S*A                  sketch_gcs   (hash, binning, S*A, Gaussian GEMM)
+    Gram  = A^T A                  gram
+    R, R^-1 of C                   sketch_qr
+    theta = rownorm^2(A R^-1)      rownorms_sq  (sketched leverage scores)
+    x     = argmin ||A x - b||     lsq_solve    (LSQR preconditioned by R^-1)
+
+Inputs are synthetic and seeded (the paper's matrices are random with
+unstated distributions) and are resident in HBM before timing starts.
+Prints ONE JSON line.  ``value`` is GB/s of A through the whole step
+(bytes of A = values + column indices + row pointers, per step, divided by
+the step time).  The dominant kernel (the Gaussian GEMM) is timed with HIP
+events on its own stream inside the library and reported as a roofline
+fraction; the CPU oracle is timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+if HERE not in sys.path:
+    sys.path.insert(0, HERE)
+
+WORKLOADS = {
+    # name: (kind, n, d, density, r, m)
+    "csr-1e6x500": ("csr", 1_000_000, 500, 1e-3, 250_000, 2000),
+    "dense-20000x50": ("dense", 20_000, 50, None, 2500, 200),
+}
+PEAK_FP64_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def a_bytes(a, kind):
+    if kind == "csr":
+        return a.nnz * (a.data.itemsize + 4) + (a.shape[0] + 1) * 8
+    return a.size * a.itemsize
+
+
+def make_inputs(name):
+    import synth
+    kind, n, d, dens, r, m = WORKLOADS[name]
+    if kind == "csr":
+        a = synth.csr_uniform(n, d, dens, seed=0)
+    else:
+        a = synth.dense_gaussian(n, d, seed=0)
+    rng = np.random.default_rng(1)
+    xt = rng.standard_normal(d)
+    b = a @ xt + 1e-3 * rng.standard_normal(n)
+    return kind, a, b, r, m
+
+
+def cpu_baseline(kind, a, b, r, m, seed, budget_s=12.0):
+    """The oracle on the host: every stage in full except the Gaussian GEMM,
+    whose bucket batches (Algorithm countgauss_multiply) are timed on a
+    prefix until ~budget_s and scaled by the batch count."""
+    from oracle import gram as og
+    from oracle import leverage as olev
+    from oracle import sketch as osk
+    import scipy.linalg as sla
+    from scipy.sparse.linalg import LinearOperator, lsqr
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count() or 1
+    t = {}
+    t0 = time.perf_counter()
+    sa = osk.sketch_cs(a, r, seed)
+    t["sketch_cs"] = time.perf_counter() - t0
+    batch = 4096
+    nb = (r + batch - 1) // batch
+    c = np.zeros((m, sa.shape[1]))
+    t0 = time.perf_counter()
+    done = 0
+    for b0 in range(0, r, batch):
+        b1 = min(r, b0 + batch)
+        c += osk.gaussian_block(m, b0, b1, seed) @ sa[b0:b1]
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t["gauss_gemm"] = (time.perf_counter() - t0) * nb / done
+    t0 = time.perf_counter()
+    og.gram(1.0, a)
+    t["gram"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rr = olev.qr_r(c)  # C from the sampled batches: same shape, same QR cost
+    ri = olev.tri_inv(rr)
+    t["qr"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    n = a.shape[0]
+    for i0 in range(0, n, 200_000):
+        og.rownorms_sq(1.0, a[i0:i0 + 200_000], ri)
+    t["rownorms"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    op = LinearOperator(a.shape, matvec=lambda y: a @ (ri @ y),
+                        rmatvec=lambda u: ri.T @ (a.T @ u), dtype=np.float64)
+    y = lsqr(op, b, atol=1e-14, btol=1e-14, iter_lim=100)[0]
+    _ = ri @ y
+    t["lsq"] = time.perf_counter() - t0
+    total = sum(t.values())
+    sample = (f"all stages in full except the Gaussian GEMM: {done} of {nb} bucket "
+              f"batches of {batch} timed and scaled")
+    return total, cores, sample, t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="csr-1e6x500", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default="f64", choices=["f64", "bf16"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the path shards by rows of A; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2203_02798_amd import api
+
+    log(f"generating workload {args.workload}")
+    kind, a, b, r, m = make_inputs(args.workload)
+    n, d = a.shape
+    nbytes = a_bytes(a, kind)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if kind == "csr":
+        A = api.CsrMatrix.from_scipy(a, device=dev)
+    else:
+        A = torch.from_numpy(a).to(dev)
+    bd = torch.from_numpy(b).to(dev)
+    torch.cuda.synchronize()
+
+    seed = args.seed
+
+    def step():
+        C = api.sketch_gcs(A, m, r, seed, prec=args.prec)
+        Gm = api.gram(A)
+        R, Ri = api.sketch_qr(C)
+        th = api.rownorms_sq(A, Ri)
+        x, info = api.lsq_solve(A, bd, Rinv=Ri, max_iter=200, refine=1, check_every=8)
+        return C, Gm, th, x, info
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        out = step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    lat = []
+    stream = torch.cuda.current_stream(dev)
+    with api.kernel_timing() as kt:
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            out = step()
+            e1.record(stream)
+            e1.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t_start
+        stats = kt.stats()
+    info = out[4]
+    ms_step = 1e3 * t_total / args.steps
+    lat = np.array(lat)
+    per = {k: v[0] / args.steps for k, v in stats.items()}
+    gg_ms, gg_n = stats.get("gauss_gemm", (0.0, 0))
+    gg_avg = gg_ms / max(gg_n, 1)
+    flops = (2.0 * r - 1.0) * m * d
+    peak = PEAK_FP64_TFLOPS if args.prec == "f64" else PEAK_BF16_TFLOPS
+    achieved = flops / (gg_avg * 1e-3) / 1e12 if gg_avg > 0 else 0.0
+    sketch_ms = sum(per.get(k, 0.0) for k in ("cs_bin", "cs_scatter", "gauss_gemm",
+                                               "gemm_reduce"))
+    rec = {
+        "metric": "GB/s of A sketched (G·S·A) + LSQ solves/s, p50/p99 latency vs FP64 plain path",
+        "value": nbytes * args.steps / t_total / 1e9,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "f64" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "d": d,
+                   "nnz": int(a.nnz) if kind == "csr" else n * d,
+                   "density": WORKLOADS[args.workload][3], "r": r, "m": m,
+                   "a_bytes": nbytes, "parallelism": "single-gpu"},
+        "solves_per_s": args.steps / t_total,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "sketch_gcs_gbs": nbytes / (sketch_ms * 1e-3) / 1e9 if sketch_ms > 0 else None,
+        "stage_ms": {k: round(v, 4) for k, v in sorted(per.items())},
+        "lsq": {"iters": info["iters"], "status": info["status"]},
+        "roofline": {"bound": "mfma", "kernel": "gauss_gemm", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "launch_ms": gg_avg,
+                     "flops_per_launch": flops},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        tot, cores, sample, parts = cpu_baseline(kind, a, b, r, m, seed)
+        rec["cpu_baseline"] = {"value": nbytes / tot / 1e9, "unit": "GB/s", "cores": cores,
+                               "kind": "oracle", "sample": sample,
+                               "stage_s": {k: round(v, 3) for k, v in parts.items()}}
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -120,6 +120,7 @@ const char *psk_last_error(void);
  *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ);
  *   k    : columns of B (ROWNORMS);
  *   prec : PSK_PREC_* (SKETCH_GCS, LSQ).
+ * For PSK_OP_LSQ, m == 0 sizes a call that passes its own opts->Rinv.
  * Arguments an op does not use are ignored. */
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r,
                        int64_t k, int prec, size_t *bytes);
@@ -182,6 +183,10 @@ int sketch_qr(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
 
 /* Options and report of lsq_solve. */
 typedef struct psk_lsq_opts {
+  const double *Rinv; /* optional d x d row-major FP64 R^{-1} of a   *
+                       * sketch of A (device), e.g. from sketch_qr;  *
+                       * when non-NULL the sketch and factorization  *
+                       * are skipped and m, r, seed, prec ignored    */
   int64_t m;          /* Gaussian rows of the sketch (>= d)          */
   int64_t r;          /* CountSketch buckets (>= m)                  */
   uint64_t seed;
@@ -212,6 +217,23 @@ typedef struct psk_lsq_info {
 int lsq_solve(const psk_mat *A, const double *b, double *x,
               const psk_lsq_opts *opts, psk_lsq_info *info,
               void *ws, size_t ws_bytes, void *stream);
+
+/* ---- kernel timing (diagnostics) ----------------------------------------
+ * When enabled, the library brackets its main kernels (and a few multi-kernel
+ * regions) with HIP events recorded on the stream each one is launched on.
+ * Names: "cs_bin" (hash + radix binning region), "cs_scatter" (S*A),
+ * "gauss_gemm" (Gaussian GEMM kernel), "gemm_reduce" (its K-split sum),
+ * "gram" (Gram kernel), "rownorm" (row-norm kernel), "sketch_qr" (whole
+ * factorization region), "lsqr_pass" (one LSQR pass over A).
+ * psk_timing_collect waits for the recorded events and returns the summed
+ * elapsed milliseconds and launch count of one name (0 and 0 if unseen).
+ * psk_timing_names lists the names seen so far, comma separated (static
+ * storage, valid until the next timing call).  Not thread-safe against
+ * concurrent psk calls that record events. */
+int psk_timing_enable(int on);
+int psk_timing_reset(void);
+int psk_timing_collect(const char *name, double *total_ms, int64_t *launches);
+const char *psk_timing_names(void);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,8 @@ PSK_PREC_F64, PSK_PREC_BF16 = 0, 1
 
 EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "gram", "rownorms_sq", "sketch_qr",
-            "lsq_solve"]
+            "lsq_solve", "psk_timing_enable", "psk_timing_reset",
+            "psk_timing_collect", "psk_timing_names"]
 
 
 class PskMat(ctypes.Structure):
@@ -44,6 +45,7 @@ class PskMat(ctypes.Structure):
 
 class PskLsqOpts(ctypes.Structure):
     _fields_ = [
+        ("Rinv", ctypes.c_void_p),
         ("m", ctypes.c_int64),
         ("r", ctypes.c_int64),
         ("seed", ctypes.c_uint64),
@@ -92,6 +94,11 @@ _SIGS = {
     "sketch_qr": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "lsq_solve": ([_PM, _vp, _vp, ctypes.POINTER(PskLsqOpts), ctypes.POINTER(PskLsqInfo),
                    _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "psk_timing_enable": ([ctypes.c_int], ctypes.c_int),
+    "psk_timing_reset": ([], ctypes.c_int),
+    "psk_timing_collect": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "psk_timing_names": ([], ctypes.c_char_p),
 }
 
 

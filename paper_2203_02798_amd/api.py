@@ -201,18 +201,25 @@ def sketch_qr(C):
     return R, Ri
 
 
-def lsq_solve(A, b, m, r, seed, prec="f64", max_iter=300, refine=1, check_every=8,
-              atol=1e-14, btol=1e-14, raise_on_noconv=False):
-    """x = argmin ||A x - b|| by sketch-and-precondition LSQR.
-    Returns (x float64[d], info dict)."""
+def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,
+              check_every=8, atol=1e-14, btol=1e-14, Rinv=None, raise_on_noconv=False):
+    """x = argmin ||A x - b|| by sketch-and-precondition LSQR.  With ``Rinv``
+    (d x d FP64 device tensor, e.g. from sketch_qr) the preconditioner is
+    reused and m, r, seed, prec are ignored.  Returns (x float64[d], info)."""
     pm = _mat(A)
     dev = _device(A)
     b = b.contiguous()
     x = torch.empty(pm.d, dtype=torch.float64, device=dev)
-    o = L.PskLsqOpts(m=m, r=r, seed=seed, prec=_PREC[prec], max_iter=max_iter,
-                     refine=refine, check_every=check_every, atol=atol, btol=btol)
+    if Rinv is not None:
+        Rinv = Rinv.contiguous()
+        if Rinv.dtype != torch.float64 or tuple(Rinv.shape) != (pm.d, pm.d):
+            raise ValueError("Rinv must be a float64 d x d tensor")
+    o = L.PskLsqOpts(Rinv=Rinv.data_ptr() if Rinv is not None else None, m=m, r=r,
+                     seed=seed, prec=_PREC[prec], max_iter=max_iter, refine=refine,
+                     check_every=check_every, atol=atol, btol=btol)
     info = L.PskLsqInfo()
-    nbytes = workspace_size(L.PSK_OP_LSQ, A, m=m, r=r, prec=prec)
+    nbytes = workspace_size(L.PSK_OP_LSQ, A, m=0 if Rinv is not None else m, r=r,
+                            prec=prec)
     ws = _ws(nbytes, dev)
     st = L.lib().lsq_solve(ctypes.byref(pm), b.data_ptr(), x.data_ptr(), ctypes.byref(o),
                            ctypes.byref(info), ws.data_ptr(), ws.numel(), _stream(dev))
@@ -220,3 +227,29 @@ def lsq_solve(A, b, m, r, seed, prec="f64", max_iter=300, refine=1, check_every=
         L.check(st, "lsq_solve")
     return x, dict(iters=info.iters, status=L.STATUS_NAMES.get(info.status, info.status),
                    resid=info.resid, ne_resid=info.ne_resid)
+
+
+class kernel_timing:
+    """Context manager that enables the library's event brackets around its
+    main kernels; ``stats()`` returns {name: (total_ms, launches)}."""
+
+    def __enter__(self):
+        L.lib().psk_timing_reset()
+        L.lib().psk_timing_enable(1)
+        return self
+
+    def __exit__(self, *exc):
+        L.lib().psk_timing_enable(0)
+        return False
+
+    @staticmethod
+    def stats():
+        names = L.lib().psk_timing_names().decode()
+        out = {}
+        for nm in filter(None, names.split(",")):
+            ms = ctypes.c_double(0.0)
+            n = ctypes.c_int64(0)
+            L.check(L.lib().psk_timing_collect(nm.encode(), ctypes.byref(ms),
+                                               ctypes.byref(n)), "psk_timing_collect")
+            out[nm] = (ms.value, n.value)
+        return out

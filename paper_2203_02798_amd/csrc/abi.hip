@@ -4,13 +4,68 @@
 // codes with a thread-local message; no C++ exception crosses the boundary.
 #include <math.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
 namespace psk {
 
 static thread_local std::string g_last_error;
+
+// ---- kernel timing -----------------------------------------------------------
+namespace {
+struct Pending {
+  std::string name;
+  hipEvent_t a, b;
+};
+struct Agg {
+  double ms = 0.0;
+  int64_t n = 0;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<Pending> g_pending;
+std::map<std::string, Agg> g_agg;
+std::string g_names;
+
+void drain_locked() {
+  for (auto &p : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      Agg &g = g_agg[p.name];
+      g.ms += ms;
+      g.n += 1;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_pending.clear();
+}
+}  // namespace
+
+bool timing_enabled() { return g_timing; }
+
+int timing_begin(const char *name, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  Pending p;
+  p.name = name;
+  if (hipEventCreate(&p.a) != hipSuccess) return -1;
+  if (hipEventCreate(&p.b) != hipSuccess) {
+    (void)hipEventDestroy(p.a);
+    return -1;
+  }
+  (void)hipEventRecord(p.a, st);
+  g_pending.push_back(p);
+  return (int)g_pending.size() - 1;
+}
+
+void timing_end(int slot, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (slot >= 0 && slot < (int)g_pending.size()) (void)hipEventRecord(g_pending[slot].b, st);
+}
 
 void set_error(const std::string &msg) { g_last_error = msg; }
 
@@ -76,6 +131,40 @@ extern "C" {
 
 const char *psk_version(void) { return "psk 0.1.0 (gfx950)"; }
 
+int psk_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_timing = on != 0;
+  return PSK_OK;
+}
+
+int psk_timing_reset(void) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  drain_locked();
+  g_agg.clear();
+  return PSK_OK;
+}
+
+int psk_timing_collect(const char *name, double *total_ms, int64_t *launches) {
+  if (!name || !total_ms || !launches) return fail(PSK_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_tmu);
+  drain_locked();
+  auto it = g_agg.find(name);
+  *total_ms = it == g_agg.end() ? 0.0 : it->second.ms;
+  *launches = it == g_agg.end() ? 0 : it->second.n;
+  return PSK_OK;
+}
+
+const char *psk_timing_names(void) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  drain_locked();
+  g_names.clear();
+  for (auto &kv : g_agg) {
+    if (!g_names.empty()) g_names += ",";
+    g_names += kv.first;
+  }
+  return g_names.c_str();
+}
+
 const char *psk_last_error(void) { return g_last_error.c_str(); }
 
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k,
@@ -109,6 +198,14 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
       break;
     case PSK_OP_LSQ: {
       psk_lsq_opts o{};
+      if (m == 0) {
+        // the caller passes its own R^{-1}: no sketch, no factorization
+        static const double dummy = 0.0;
+        o.Rinv = &dummy;
+      } else {
+        if ((rc = check_r(r))) return rc;
+        if (m < A->d || r < m) return fail(PSK_EINVAL, "LSQ workspace needs d <= m <= r");
+      }
       o.m = m;
       o.r = r;
       o.prec = prec;
@@ -218,12 +315,14 @@ int lsq_solve(const psk_mat *A, const double *b, double *x, const psk_lsq_opts *
   if (rc) return rc;
   if (!opts || !b || !x) return fail(PSK_EINVAL, "opts, b and x must be non-NULL");
   const psk_lsq_opts &o = *opts;
-  if (o.m < A->d) return fail(PSK_EINVAL, "lsq_solve needs opts->m >= d");
-  if ((rc = check_r(o.r))) return rc;
-  if (o.r < o.m) return fail(PSK_EINVAL, "lsq_solve needs opts->r >= opts->m");
+  if (!o.Rinv) {
+    if (o.m < A->d) return fail(PSK_EINVAL, "lsq_solve needs opts->m >= d");
+    if ((rc = check_r(o.r))) return rc;
+    if (o.r < o.m) return fail(PSK_EINVAL, "lsq_solve needs opts->r >= opts->m");
+  }
   if (o.max_iter < 1 || o.check_every < 1 || o.refine < 0)
     return fail(PSK_EINVAL, "lsq_solve needs max_iter >= 1, check_every >= 1, refine >= 0");
-  if (o.prec != PSK_PREC_F64 && o.prec != PSK_PREC_BF16)
+  if (!o.Rinv && o.prec != PSK_PREC_F64 && o.prec != PSK_PREC_BF16)
     return fail(PSK_EDTYPE, "opts->prec must be PSK_PREC_F64 or PSK_PREC_BF16");
   Arena plan;
   if ((rc = lsq_impl(*A, nullptr, nullptr, o, nullptr, plan, nullptr))) return rc;

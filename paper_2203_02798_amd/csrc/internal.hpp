@@ -43,6 +43,22 @@ struct Arena {
 
 inline size_t elem_size(int dtype) { return dtype == PSK_F64 ? 8 : 4; }
 
+// Event bracket around a launch (or region) when timing is enabled:
+//   { KTimer t("gauss_gemm", st); kernel<<<..., st>>>(...); }
+bool timing_enabled();
+int timing_begin(const char *name, hipStream_t st);
+void timing_end(int slot, hipStream_t st);
+struct KTimer {
+  int slot;
+  hipStream_t st;
+  KTimer(const char *name, hipStream_t s) : slot(-1), st(s) {
+    if (timing_enabled()) slot = timing_begin(name, s);
+  }
+  ~KTimer() {
+    if (slot >= 0) timing_end(slot, st);
+  }
+};
+
 // ---- CountSketch (k_sketch.hip) ---------------------------------------------
 // Bins rows 0..n-1 by bucket: perm[j] (row | sign<<31) sorted by bucket,
 // stable; bptr[b] .. bptr[b+1] is bucket b's range.  Returns 0 or a status.

@@ -139,6 +139,7 @@ int gram_csr(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for CSR gram");
   const size_t lds = (size_t)rb * d * sizeof(double);
   const unsigned blocks = (unsigned)(nranges * chunks);
+  KTimer timer("gram", st);
   if (A.dtype == PSK_F64)
     k_gram_csr<double><<<blocks, 256, lds, st>>>((const double *)A.values, A.indptr,
                                                  A.indices, A.n, d, rb, rows_per_chunk,
@@ -169,6 +170,7 @@ int rownorms_csr(double alpha, const psk_mat &A, const double *B, int64_t k,
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for CSR row norms");
   const unsigned blocks = (unsigned)ceil_div(A.n, 256);
+  KTimer timer("rownorm", st);
   if (A.dtype == PSK_F64)
     k_rownorm_csr<double><<<blocks, 256, 0, st>>>((const double *)A.values, A.indptr,
                                                   A.indices, A.n, d, Bt, alpha, beta, x);

@@ -330,6 +330,7 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
 
 int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
                hipStream_t st) {
+  KTimer timer("gram", st);
   const bool f32 = A.dtype == PSK_F32;
   if (f32)
     return gemm_partial_launch<float, float, true, false, 2, 2, 2, 2, true>(
@@ -342,6 +343,7 @@ int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
 
 int rownorms_dense(double alpha, const psk_mat &A, const double *B, int64_t k,
                    double beta, double *x, Arena &ws, hipStream_t st) {
+  KTimer timer("rownorm", st);
   if (A.dtype == PSK_F32) return rownorm_launch<float>(A, B, k, alpha, beta, x, ws, st);
   return rownorm_launch<double>(A, B, k, alpha, beta, x, ws, st);
 }

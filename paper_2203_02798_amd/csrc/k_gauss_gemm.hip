@@ -167,15 +167,21 @@ int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the Gaussian GEMM");
   const int64_t nblk = tiles * splits;
-  if (sa_dtype == PSK_F64)
-    k_gauss_gemm_f64<double><<<(unsigned)nblk, 256, 0, st>>>(
-        m, r, d, seed, (const double *)SA, tiles_m, tiles_n, (int)splits, kper, part);
-  else
-    k_gauss_gemm_f64<float><<<(unsigned)nblk, 256, 0, st>>>(
-        m, r, d, seed, (const float *)SA, tiles_m, tiles_n, (int)splits, kper, part);
+  {
+    KTimer t("gauss_gemm", st);
+    if (sa_dtype == PSK_F64)
+      k_gauss_gemm_f64<double><<<(unsigned)nblk, 256, 0, st>>>(
+          m, r, d, seed, (const double *)SA, tiles_m, tiles_n, (int)splits, kper, part);
+    else
+      k_gauss_gemm_f64<float><<<(unsigned)nblk, 256, 0, st>>>(
+          m, r, d, seed, (const float *)SA, tiles_m, tiles_n, (int)splits, kper, part);
+  }
   const int64_t len = m * d;
-  k_reduce_splits<<<(unsigned)ceil_div(len, 256), 256, 0, st>>>(
-      part, len, (int)splits, 1.0 / sqrt((double)m), C);
+  {
+    KTimer t("gemm_reduce", st);
+    k_reduce_splits<<<(unsigned)ceil_div(len, 256), 256, 0, st>>>(
+        part, len, (int)splits, 1.0 / sqrt((double)m), C);
+  }
   PSK_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -311,10 +311,13 @@ void one_step(const psk_mat &A, bool init, const LsqBufs &B, const double *Rinv,
               const double *rhs, const psk_lsq_opts &o, hipStream_t stream) {
   const int64_t d = A.d;
   const unsigned db = (unsigned)ceil_div(d, 256);
-  if (A.dtype == PSK_F64)
-    launch_pass<double>(A, init, B, rhs, stream);
-  else
-    launch_pass<float>(A, init, B, rhs, stream);
+  {
+    KTimer t("lsqr_pass", stream);
+    if (A.dtype == PSK_F64)
+      launch_pass<double>(A, init, B, rhs, stream);
+    else
+      launch_pass<float>(A, init, B, rhs, stream);
+  }
   k_reduce_t<<<db, 256, 0, stream>>>(B.part_t, B.part_b2, kPassBlocks, d, B.st, B.tv,
                                      init ? 1 : 0);
   k_vnew<<<db, 256, 0, stream>>>(Rinv, d, B.tv, B.v, B.st, B.vnew, B.part_a2, init ? 1 : 0);
@@ -329,9 +332,10 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
              psk_lsq_info *info, Arena &ws, hipStream_t st) {
   const int64_t n = A.n, d = A.d, m = o.m;
   if (d > 1024) return fail(PSK_EUNSUPPORTED, "lsq_solve supports d <= 1024");
-  double *C = ws.take<double>((size_t)m * d);
-  double *R = ws.take<double>((size_t)d * d);
-  double *Rinv = ws.take<double>((size_t)d * d);
+  const bool own = o.Rinv == nullptr;  // sketch and factor here
+  double *C = own ? ws.take<double>((size_t)m * d) : nullptr;
+  double *R = own ? ws.take<double>((size_t)d * d) : nullptr;
+  double *Rinv = own ? ws.take<double>((size_t)d * d) : const_cast<double *>(o.Rinv);
   LsqBufs B;
   B.RinvT = ws.take<double>((size_t)d * d);
   B.u = ws.take<double>((size_t)n);
@@ -347,23 +351,27 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   double *res = ws.take<double>((size_t)n);
   B.st = ws.take<LsqrState>(1);
   const size_t mk = ws.mark();
-  // sketch and factor (their scratch is released afterwards)
-  void *SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
-  uint32_t *perm = nullptr, *bptr = nullptr;
-  int rc = cs_bin(n, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr);
-  if (rc) return rc;
-  if ((rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return rc;
-  if ((rc = gauss_gemm(m, o.r, d, o.seed, o.prec, SA, A.dtype, C, ws, st))) return rc;
+  int rc = 0;
   int *flag = nullptr;
-  if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;
+  if (own) {
+    // sketch and factor (their scratch is released afterwards)
+    void *SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
+    uint32_t *perm = nullptr, *bptr = nullptr;
+    if ((rc = cs_bin(n, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr))) return rc;
+    if ((rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return rc;
+    if ((rc = gauss_gemm(m, o.r, d, o.seed, o.prec, SA, A.dtype, C, ws, st))) return rc;
+    if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;
+  }
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for lsq_solve");
   ws.release(mk);
   k_transpose<<<(unsigned)ceil_div(d * d, 256), 256, 0, st>>>(Rinv, d, B.RinvT);
-  int hflag = 0;
-  PSK_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  PSK_HIP_TRY(hipStreamSynchronize(st));
-  if (hflag) return fail(PSK_ERANK, "sketch is numerically rank deficient");
+  if (own) {
+    int hflag = 0;
+    PSK_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    PSK_HIP_TRY(hipStreamSynchronize(st));
+    if (hflag) return fail(PSK_ERANK, "sketch is numerically rank deficient");
+  }
 
   const unsigned db = (unsigned)ceil_div(d, 256);
   k_zero<<<(unsigned)ceil_div(d, 256), 256, 0, st>>>(x, d);

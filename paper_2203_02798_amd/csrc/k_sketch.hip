@@ -446,6 +446,7 @@ int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for CountSketch binning");
 
+  KTimer timer("cs_bin", st);
   k_hash_keys<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, r, seed, k0, v0);
   uint32_t *kin = k0, *vin = v0, *kout = k1, *vout = v1;
   for (int p = 0; p < passes; ++p) {
@@ -480,6 +481,7 @@ int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for S*A");
   void *out = splits > 1 ? part : SA;
+  KTimer timer("cs_scatter", st);
   if (A.format == PSK_DENSE) {
     const uintptr_t addr = (uintptr_t)A.values;
     if (A.dtype == PSK_F64) {

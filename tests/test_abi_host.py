@@ -75,6 +75,12 @@ def test_workspace_planning(lib):
     assert st == 0 and b6 >= 2 * 400 * 100 * 8
     st, b7 = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=128, r=1024)
     assert st == 0 and b7 > 5000 * 8
+    st, b8 = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=0, r=0)  # caller's own R^{-1}
+    assert st == 0 and 5000 * 8 < b8 < b7
+    st, _ = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=16, r=1024)  # m < d
+    assert st == -1
+    st, _ = _ws(L.PSK_OP_SKETCH_CS, _dense(5000, 32), r=0)
+    assert st == -1
 
 
 def test_rejects_bad_arguments_without_device_work(lib):

@@ -272,6 +272,26 @@ def test_leverage_pipeline(api, kind):
     assert abs(th.sum() - d) < 0.5 * d
 
 
+def test_lsq_solve_with_precomputed_preconditioner(api):
+    a, b, _ = synth.lsq_problem(20000, 40, 1e5, seed=4)
+    ad = to_device(a)
+    _, ri = api.sketch_qr(api.sketch_gcs(ad, 160, 1600, seed=1))
+    x, info = api.lsq_solve(ad, torch.from_numpy(b).cuda(), Rinv=ri)
+    rs, _ = olsq.lsq_quality(a, b, olsq.lstsq(a, b))
+    rn, ne = olsq.lsq_quality(a, b, x.cpu().numpy())
+    assert (rn - rs) / rs <= 1e-10 and ne <= 1e-10 and info["status"] == "PSK_OK"
+
+
+def test_kernel_timing_records_launches(api):
+    a = to_device(synth.dense_gaussian(5000, 64, seed=1))
+    with api.kernel_timing() as kt:
+        api.sketch_gcs(a, 64, 512, seed=2)
+        torch.cuda.synchronize()
+        st = kt.stats()
+    assert st["gauss_gemm"][1] == 1 and st["gauss_gemm"][0] > 0
+    assert st["cs_scatter"][1] == 1 and st["cs_bin"][1] == 1
+
+
 @pytest.mark.parametrize("kind,cond", [("dense", 1e3), ("dense", 1e8), ("csr", 1e2)])
 def test_lsq_solve_matches_lapack(api, kind, cond):
     n, d = 20000, 32
