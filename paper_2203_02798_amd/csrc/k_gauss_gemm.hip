@@ -9,14 +9,18 @@
 // buckets) is split over workgroups whose FP64 partial products are summed
 // in a fixed order by a second kernel, which also applies 1/sqrt(m).
 //
-// Tiling: 256 threads = 4 wavefronts; workgroup tile 128 (rows of G / C) x
-// 128 (columns of C); each wavefront owns 32 rows x 128 columns = 2 x 8
-// MFMA blocks (64 FP64 accumulators per lane).  K advances 16 buckets per
-// chunk: a lane with quad kq = lane/16 draws one Philox block for buckets
-// k0+4kq .. k0+4kq+3 of its row, and k-step s (0..3) pairs bucket
-// k0+4kq+s of G with the same bucket row of S*A from LDS, so one Philox call
-// feeds four matrix instructions and every Gaussian value is generated once
-// per 128 output columns.
+// Tiling: 512 threads = 8 wavefronts; workgroup tile 128 (rows of G / C) x
+// 256 (columns of C); each wavefront owns 16 rows x 256 columns = 16 MFMA
+// blocks (64 FP64 accumulators per lane).  Generating a Gaussian value costs
+// about as much FP64 vector work as a few matrix instructions, so the wide
+// column tile matters: each value feeds 256 output columns.  K advances 16
+// buckets per chunk: the lane with quad kq = lane/16 draws one Philox block
+// for buckets k0+4kq .. k0+4kq+3 of its row, and k-step s (0..3) pairs bucket
+// k0+4kq+s of G with the same bucket row of S*A from LDS (any fixed
+// permutation of k inside a chunk leaves the contraction unchanged).
+// The S*A chunk is staged through double-buffered LDS with a register
+// prefetch of the next chunk; the LDS row stride (272 doubles) puts the four
+// k rows of one read into two distinct bank halves.
 #include "internal.hpp"
 
 namespace psk {
@@ -24,13 +28,17 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 128;
-constexpr int kBN = 128;
+constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kBM = 16 * kWaves;  // 128
+constexpr int kBN = 256;
+constexpr int kNB = kBN / 16;      // 16 MFMA blocks per wavefront
 constexpr int kBK = 16;
-constexpr int kLdsStride = kBN + 4;  // doubles; staggers the four k rows of a read
+constexpr int kLdsStride = kBN + 16;
+constexpr int kPf = kBK * kBN / kThreads;  // 8 prefetched values per thread
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gauss_gemm_f64(
+__global__ __launch_bounds__(kThreads) void k_gauss_gemm_f64(
     int64_t m, int64_t r, int64_t d, uint64_t seed, const T *__restrict__ SA,
     int tiles_m, int tiles_n, int splits, int64_t kper,
     double *__restrict__ out /* [splits][m][d] */) {
@@ -59,32 +67,30 @@ __global__ __launch_bounds__(256) void k_gauss_gemm_f64(
   const int kq = lane >> 4;
   const int li = lane & 15;
 
-  v4d acc[2][8];
+  v4d acc[kNB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < kNB; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  // S*A staging: thread covers column n0 + (tid % 128), rows tid/128 + 2p
+  // S*A staging: thread covers column n0 + (tid % 256), rows tid/256 + 2p
   const int lcol = tid & (kBN - 1);
-  const int lrow = tid >> 7;
+  const int lrow = tid >> 8;
   const bool col_ok = (n0 + lcol) < d;
-  double pf[8];
+  double pf[kPf];
 
   auto load_chunk = [&](int64_t k0) {
 #pragma unroll
-    for (int p = 0; p < 8; ++p) {
+    for (int p = 0; p < kPf; ++p) {
       const int64_t k = k0 + lrow + 2 * p;
       pf[p] = (col_ok && k < ke) ? (double)SA[k * d + n0 + lcol] : 0.0;
     }
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
-    for (int p = 0; p < 8; ++p) tile[buf][lrow + 2 * p][lcol] = pf[p];
+    for (int p = 0; p < kPf; ++p) tile[buf][lrow + 2 * p][lcol] = pf[p];
   };
 
   const int64_t nchunks = (ke > kb) ? ceil_div(ke - kb, kBK) : 0;
-  const uint32_t row_a0 = (uint32_t)(m0 + wave * 32 + li);
+  const uint32_t row_a = (uint32_t)(m0 + wave * 16 + li);
 
   if (nchunks > 0) {
     load_chunk(kb);
@@ -95,39 +101,32 @@ __global__ __launch_bounds__(256) void k_gauss_gemm_f64(
     const int buf = (int)(c & 1);
     const int64_t k0 = kb + c * kBK;
     if (c + 1 < nchunks) load_chunk(k0 + kBK);
-    // Gaussian values for this lane's two rows and four consecutive buckets
-    double g[2][4];
-    const uint64_t q = (uint64_t)(k0 >> 2) + (uint64_t)kq;
-    gauss4_f64(q, row_a0, seed, g[0]);
-    gauss4_f64(q, row_a0 + 16u, seed, g[1]);
+    // Gaussian values of this lane's row for four consecutive buckets
+    double g[4];
+    gauss4_f64((uint64_t)(k0 >> 2) + (uint64_t)kq, row_a, seed, g);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      double bv[8];
+      double bv[kNB];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb) bv[nb] = tile[buf][4 * kq + s][nb * 16 + li];
+      for (int nb = 0; nb < kNB; ++nb) bv[nb] = tile[buf][4 * kq + s][nb * 16 + li];
 #pragma unroll
-      for (int nb = 0; nb < 8; ++nb) {
-        acc[0][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[0][s], bv[nb], acc[0][nb], 0, 0, 0);
-        acc[1][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[1][s], bv[nb], acc[1][nb], 0, 0, 0);
-      }
+      for (int nb = 0; nb < kNB; ++nb)
+        acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[s], bv[nb], acc[nb], 0, 0, 0);
     }
     if (c + 1 < nchunks) store_chunk(buf ^ 1);
     __syncthreads();
   }
 
-  // accumulator element e of block (a, nb): row kq + 4*e, column li
+  // accumulator element e of block nb: row kq + 4*e, column li
   double *o = out + (int64_t)ks * m * d;
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
+  for (int e = 0; e < 4; ++e) {
+    const int64_t row = m0 + wave * 16 + kq + 4 * e;
+    if (row >= m) continue;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t row = m0 + wave * 32 + a * 16 + kq + 4 * e;
-      if (row >= m) continue;
-#pragma unroll
-      for (int nb = 0; nb < 8; ++nb) {
-        const int64_t col = n0 + nb * 16 + li;
-        if (col < d) o[row * d + col] = acc[a][nb][e];
-      }
+    for (int nb = 0; nb < kNB; ++nb) {
+      const int64_t col = n0 + nb * 16 + li;
+      if (col < d) o[row * d + col] = acc[nb][e];
     }
   }
 }
@@ -154,10 +153,10 @@ int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
   const int tiles_m = (int)ceil_div(m, kBM);
   const int tiles_n = (int)ceil_div(d, kBN);
   const int64_t tiles = (int64_t)tiles_m * tiles_n;
-  // about two waves of resident workgroups (2 per CU x 256 CUs), K chunks
-  // of whole 16-bucket batches, at least 64 batches per split
+  // about two rounds of resident workgroups (one 512-thread workgroup per
+  // CU), whole 16-bucket batches, at least 64 batches per split
   const int64_t kchunks = ceil_div(r, kBK);
-  int64_t splits = ceil_div(1024, tiles);
+  int64_t splits = ceil_div(512, tiles);
   const int64_t max_splits = kchunks / 64 > 0 ? kchunks / 64 : 1;
   if (splits > max_splits) splits = max_splits;
   if (splits < 1) splits = 1;
@@ -170,10 +169,10 @@ int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
   {
     KTimer t("gauss_gemm", st);
     if (sa_dtype == PSK_F64)
-      k_gauss_gemm_f64<double><<<(unsigned)nblk, 256, 0, st>>>(
+      k_gauss_gemm_f64<double><<<(unsigned)nblk, kThreads, 0, st>>>(
           m, r, d, seed, (const double *)SA, tiles_m, tiles_n, (int)splits, kper, part);
     else
-      k_gauss_gemm_f64<float><<<(unsigned)nblk, 256, 0, st>>>(
+      k_gauss_gemm_f64<float><<<(unsigned)nblk, kThreads, 0, st>>>(
           m, r, d, seed, (const float *)SA, tiles_m, tiles_n, (int)splits, kper, part);
   }
   const int64_t len = m * d;

@@ -10,10 +10,16 @@
 // One LSQR iteration reads A once: for every row, u_i <- A_i vhat - alpha u_i
 // and A_i^T u_i is accumulated immediately (the normalisation by beta is a
 // scalar applied afterwards), so the two products A v and A^T u of the
-// bidiagonalisation share one pass over A.  The scalar recurrences run in a
-// one-workgroup kernel; all state stays on the device, and a `done` flag set
-// by the convergence test turns the remaining enqueued iterations into
-// no-ops, so the host only synchronises every `check_every` iterations.
+// bidiagonalisation share one pass over A.  An iteration is five kernels:
+//   pass   (1024 workgroups) per-workgroup partial A^T u and ||u||^2;
+//   reduce (d/64 x 16)       first level of the partial sums;
+//   vnew   (d/16)            t = A^T u / beta, vnew = R^{-T} t - beta v;
+//   update (1 workgroup)     scalar recurrences, v, w, y, stopping test;
+//   vhat   (d/16)            vhat = R^{-1} v for the next pass.
+// All state stays on the device; a `done` flag set by the stopping test turns
+// the remaining enqueued iterations into no-ops, so the host synchronises
+// only every `check_every` iterations.  Every sum has a fixed order (CSR rows
+// scatter A_i^T u_i into per-wavefront LDS rows in row order).
 #include <math.h>
 
 #include "internal.hpp"
@@ -27,114 +33,263 @@ struct LsqrState {
   int done, iters, pad0, pad1;
 };
 
-constexpr int kPassBlocks = 512;
+constexpr int kPassBlocks = 1024;
+constexpr int kRedGroups = 16;  // kPassBlocks / kRedGroups = 64 partials per group
+constexpr int kShortRow = 16;   // CSR rows up to this length take one lane each
 
-template <typename T, bool CSR, bool INIT>
-__global__ __launch_bounds__(256) void k_pass(
+__device__ __forceinline__ void block_rows(int64_t n, int64_t &r0, int64_t &r1) {
+  const int64_t per = ceil_div(n, (int64_t)gridDim.x);
+  r0 = (int64_t)blockIdx.x * per;
+  r1 = r0 + per;
+  if (r1 > n) r1 = n;
+}
+
+// partial A^T u and ||u||^2 of this workgroup's rows, u_i updated in place
+template <typename T, bool INIT>
+__global__ __launch_bounds__(256) void k_pass_csr(
     const T *__restrict__ vals, const int64_t *__restrict__ indptr,
-    const int32_t *__restrict__ indices, int64_t n, int64_t d, int64_t ld,
+    const int32_t *__restrict__ indices, int64_t n, int64_t d,
     const double *__restrict__ vhat, const double *__restrict__ rhs,
     double *__restrict__ u, const LsqrState *__restrict__ st,
     double *__restrict__ part_t, double *__restrict__ part_b2) {
   if (!INIT && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *tl = reinterpret_cast<double *>(smem_raw);
+  __shared__ double b2s[4];
+  for (int64_t c = threadIdx.x; c < 4 * d; c += 256) tl[c] = 0.0;
+  __syncthreads();
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  double *tl = reinterpret_cast<double *>(smem_raw) + (int64_t)wave * d;
-  __shared__ double b2s[4];
-  for (int64_t c = lane; c < d; c += 64) tl[c] = 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  double *tw = tl + (int64_t)wave * d;
   const double au = INIT ? 0.0 : st->alpha * st->ufac;
-  const int64_t rows_per_blk = ceil_div(n, (int64_t)gridDim.x);
-  const int64_t rb0 = (int64_t)blockIdx.x * rows_per_blk;
-  int64_t rb1 = rb0 + rows_per_blk;
-  if (rb1 > n) rb1 = n;
-  const int64_t rows_per_wave = ceil_div(rb1 - rb0 > 0 ? rb1 - rb0 : 0, 4);
-  const int64_t i0 = rb0 + wave * rows_per_wave;
-  int64_t i1 = i0 + rows_per_wave;
-  if (i1 > rb1) i1 = rb1;
+  int64_t rb0, rb1;
+  block_rows(n, rb0, rb1);
   double b2 = 0.0;
-  for (int64_t i = i0; i < i1; ++i) {
-    double ui;
-    if (CSR) {
-      const int64_t p0 = indptr[i], p1 = indptr[i + 1];
-      if (INIT) {
-        ui = rhs[i];
-      } else {
-        double dot = 0.0;
-        for (int64_t p = p0 + lane; p < p1; p += 64) dot += (double)vals[p] * vhat[indices[p]];
-        ui = wave_sum(dot) - au * u[i];
-      }
-      for (int64_t p = p0 + lane; p < p1; p += 64)
-        atomicAdd(&tl[indices[p]], (double)vals[p] * ui);
-    } else {
-      const T *row = vals + i * ld;
-      if (INIT) {
-        ui = rhs[i];
-      } else {
-        double dot = 0.0;
-        for (int64_t c = lane; c < d; c += 64) dot += (double)row[c] * vhat[c];
-        ui = wave_sum(dot) - au * u[i];
-      }
-      for (int64_t c = lane; c < d; c += 64) tl[c] += (double)row[c] * ui;
+  for (int64_t base = rb0 + wave * 64; base < rb1; base += 256) {
+    const int64_t i = base + lane;
+    const bool have = i < rb1;
+    int64_t p0 = 0, p1 = 0;
+    if (have) {
+      p0 = indptr[i];
+      p1 = indptr[i + 1];
     }
-    if (lane == 0) u[i] = ui;
-    b2 += ui * ui;
+    const bool longrow = have && (p1 - p0) > kShortRow;
+    if (have && !longrow) {
+      double ui;
+      if (INIT) {
+        ui = rhs[i];
+      } else {
+        double dot = 0.0;
+        for (int64_t p = p0; p < p1; ++p) dot += (double)vals[p] * vhat[indices[p]];
+        ui = dot - au * u[i];
+      }
+      u[i] = ui;
+      b2 += ui * ui;
+      for (int64_t p = p0; p < p1; ++p) atomicAdd(&tw[indices[p]], (double)vals[p] * ui);
+    }
+    uint64_t pending = __ballot(longrow);
+    while (pending) {
+      const int src = __ffsll((unsigned long long)pending) - 1;
+      pending &= pending - 1;
+      const int64_t q0 = __shfl(p0, src, 64);
+      const int64_t q1 = __shfl(p1, src, 64);
+      const int64_t row = __shfl(i, src, 64);
+      double ui;
+      if (INIT) {
+        ui = rhs[row];
+      } else {
+        double dot = 0.0;
+        for (int64_t p = q0 + lane; p < q1; p += 64) dot += (double)vals[p] * vhat[indices[p]];
+        ui = wave_sum(dot) - au * u[row];
+      }
+      if (lane == 0) {
+        u[row] = ui;
+        b2 += ui * ui;
+      }
+      for (int64_t p = q0 + lane; p < q1; p += 64)
+        atomicAdd(&tw[indices[p]], (double)vals[p] * ui);
+    }
   }
+  b2 = wave_sum(b2);
   if (lane == 0) b2s[wave] = b2;
   __syncthreads();
-  const double *t0 = reinterpret_cast<const double *>(smem_raw);
   for (int64_t c = threadIdx.x; c < d; c += 256)
-    part_t[(int64_t)blockIdx.x * d + c] = ((t0[c] + t0[d + c]) + t0[2 * d + c]) + t0[3 * d + c];
+    part_t[(int64_t)blockIdx.x * d + c] =
+        ((tl[c] + tl[d + c]) + tl[2 * d + c]) + tl[3 * d + c];
   if (threadIdx.x == 0) part_b2[blockIdx.x] = ((b2s[0] + b2s[1]) + b2s[2]) + b2s[3];
 }
 
-// beta = sqrt(sum part_b2); tv = (sum_blocks part_t) / beta
-__global__ __launch_bounds__(256) void k_reduce_t(const double *__restrict__ part_t,
-                                                  const double *__restrict__ part_b2,
-                                                  int nb, int64_t d, LsqrState *__restrict__ st,
-                                                  double *__restrict__ tv, int init) {
-  if (!init && st->done) return;
-  __shared__ double bsh;
-  if (threadIdx.x < 64) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += 64) s += part_b2[b];
-    s = wave_sum(s);
-    if (threadIdx.x == 0) bsh = sqrt(s);
+// dense rows: wavefront per row, lane owns columns lane + 64k (k < KC)
+template <typename T, bool INIT, int KC>
+__global__ __launch_bounds__(256) void k_pass_dense(
+    const T *__restrict__ A, int64_t ld, int64_t n, int64_t d,
+    const double *__restrict__ vhat, const double *__restrict__ rhs,
+    double *__restrict__ u, const LsqrState *__restrict__ st,
+    double *__restrict__ part_t, double *__restrict__ part_b2) {
+  if (!INIT && st->done) return;
+  __shared__ double tl[4][64 * KC];
+  __shared__ double b2s[4];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const double au = INIT ? 0.0 : st->alpha * st->ufac;
+  int64_t rb0, rb1;
+  block_rows(n, rb0, rb1);
+  double vh[KC], tacc[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int64_t c = lane + 64 * k;
+    vh[k] = (!INIT && c < d) ? vhat[c] : 0.0;
+    tacc[k] = 0.0;
   }
+  double b2 = 0.0;
+  int64_t i = rb0 + wave;
+  for (; i + 4 < rb1; i += 8) {
+    double x0[KC], x1[KC];
+    const T *ra = A + i * ld;
+    const T *rb = A + (i + 4) * ld;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int64_t c = lane + 64 * k;
+      x0[k] = c < d ? (double)ra[c] : 0.0;
+      x1[k] = c < d ? (double)rb[c] : 0.0;
+    }
+    double u0, u1;
+    if (INIT) {
+      u0 = rhs[i];
+      u1 = rhs[i + 4];
+    } else {
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) {
+        d0 += x0[k] * vh[k];
+        d1 += x1[k] * vh[k];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        d0 += __shfl_xor(d0, off, 64);
+        d1 += __shfl_xor(d1, off, 64);
+      }
+      u0 = d0 - au * u[i];
+      u1 = d1 - au * u[i + 4];
+    }
+    if (lane == 0) {
+      u[i] = u0;
+      u[i + 4] = u1;
+    }
+    b2 += u0 * u0 + u1 * u1;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) tacc[k] += x0[k] * u0 + x1[k] * u1;
+  }
+  for (; i < rb1; i += 4) {
+    double x0[KC];
+    const T *ra = A + i * ld;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int64_t c = lane + 64 * k;
+      x0[k] = c < d ? (double)ra[c] : 0.0;
+    }
+    double u0;
+    if (INIT) {
+      u0 = rhs[i];
+    } else {
+      double d0 = 0.0;
+#pragma unroll
+      for (int k = 0; k < KC; ++k) d0 += x0[k] * vh[k];
+      u0 = wave_sum(d0) - au * u[i];
+    }
+    if (lane == 0) u[i] = u0;
+    b2 += u0 * u0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) tacc[k] += x0[k] * u0;
+  }
+#pragma unroll
+  for (int k = 0; k < KC; ++k) tl[wave][lane + 64 * k] = tacc[k];
+  if (lane == 0) b2s[wave] = b2;  // every lane holds the same b2
   __syncthreads();
-  const double beta = bsh;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < d) {
-    double t = 0.0;
-    for (int b = 0; b < nb; ++b) t += part_t[(int64_t)b * d + j];
-    tv[j] = beta > 0.0 ? t / beta : 0.0;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->beta_new = beta;
+  for (int64_t c = threadIdx.x; c < d; c += 256)
+    part_t[(int64_t)blockIdx.x * d + c] =
+        ((tl[0][c] + tl[1][c]) + tl[2][c]) + tl[3][c];
+  if (threadIdx.x == 0) part_b2[blockIdx.x] = ((b2s[0] + b2s[1]) + b2s[2]) + b2s[3];
 }
 
-// vnew_j = sum_{i<=j} Rinv[i][j] tv_i - beta v_j ; part_a2[block] = sum vnew^2
-__global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ Rinv, int64_t d,
-                                              const double *__restrict__ tv,
+// part2[g][c] = sum of the 64 pass partials of group g, column c
+__global__ __launch_bounds__(256) void k_reduce1(const double *__restrict__ part_t, int64_t d,
+                                                 const LsqrState *__restrict__ st,
+                                                 double *__restrict__ part2, int init) {
+  if (!init && st->done) return;
+  __shared__ double red[4][64];
+  const int sub = threadIdx.x >> 6;
+  const int c = threadIdx.x & 63;
+  const int64_t col = (int64_t)blockIdx.x * 64 + c;
+  const int g = blockIdx.y;
+  constexpr int per = kPassBlocks / kRedGroups;
+  double s = 0.0;
+  if (col < d) {
+#pragma unroll 4
+    for (int q = 0; q < per / 4; ++q) s += part_t[(int64_t)(g * per + sub + 4 * q) * d + col];
+  }
+  red[sub][c] = s;
+  __syncthreads();
+  if (sub == 0 && col < d)
+    part2[(int64_t)g * d + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+// beta = ||u||, t = (A^T u) / beta, vnew_j = sum_{i<=j} Rinv[i][j] t_i - beta v_j
+__global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
+                                              const double *__restrict__ part_b2,
+                                              const double *__restrict__ Rinv, int64_t d,
                                               const double *__restrict__ v,
-                                              const LsqrState *__restrict__ st,
+                                              LsqrState *__restrict__ st,
                                               double *__restrict__ vnew,
                                               double *__restrict__ part_a2, int init) {
   if (!init && st->done) return;
-  __shared__ double red[4];
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double val = 0.0;
-  if (j < d) {
-    double s = 0.0;
-    for (int64_t i = 0; i <= j; ++i) s += Rinv[i * d + j] * tv[i];
-    val = init ? s : s - st->beta_new * v[j];
-    vnew[j] = val;
-  }
-  double a2 = wave_sum(val * val);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *tvs = reinterpret_cast<double *>(smem_raw);  // d doubles
+  __shared__ double red[16][17];
+  __shared__ double bred[4];
+  const int tid = threadIdx.x;
+  // beta from the kPassBlocks partial squares (same fixed order in every block)
+  double s = 0.0;
+  for (int b = tid; b < kPassBlocks; b += 256) s += part_b2[b];
+  s = wave_sum(s);
+  if ((tid & 63) == 0) bred[tid >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) part_a2[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+  const double beta = sqrt(((bred[0] + bred[1]) + bred[2]) + bred[3]);
+  const double binv = beta > 0.0 ? 1.0 / beta : 0.0;
+  const int64_t j0 = (int64_t)blockIdx.x * 16;
+  int64_t ilim = j0 + 16;
+  if (ilim > d) ilim = d;
+  for (int64_t i = tid; i < ilim; i += 256) {
+    double t = 0.0;
+#pragma unroll
+    for (int g = 0; g < kRedGroups; ++g) t += part2[(int64_t)g * d + i];
+    tvs[i] = t * binv;
+  }
+  __syncthreads();
+  const int g = tid >> 4;
+  const int c = tid & 15;
+  const int64_t j = j0 + c;
+  double acc = 0.0;
+  if (j < d)
+    for (int64_t i = g; i <= j; i += 16) acc += Rinv[i * d + j] * tvs[i];
+  red[g][c] = acc;
+  __syncthreads();
+  if (tid < 16) {
+    double sj = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sj += red[q][tid];
+    const int64_t jj = j0 + tid;
+    double val = 0.0;
+    if (jj < d) {
+      val = init ? sj : sj - beta * v[jj];
+      vnew[jj] = val;
+    }
+    double a2 = val * val;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) a2 += __shfl_xor(a2, off, 64);
+    if (tid == 0) part_a2[blockIdx.x] = a2;
+  }
+  if (blockIdx.x == 0 && tid == 0) st->beta_new = beta;
 }
 
 // scalar recurrences, v/w/y updates and the stopping test (one workgroup)
@@ -216,25 +371,32 @@ __global__ __launch_bounds__(256) void k_update(LsqrState *__restrict__ st, int6
   }
 }
 
-// out_i = (accumulate ? out_i : 0) + sum_{j>=i} Rinv[i][j] vec_j  (RinvT = Rinv^T)
-__global__ __launch_bounds__(256) void k_trmv(const double *__restrict__ RinvT, int64_t d,
+// out_i = (accumulate ? out_i : 0) + sum_{j>=i} Rinv[i][j] vec_j; 16 rows per block
+__global__ __launch_bounds__(256) void k_trmv(const double *__restrict__ Rinv, int64_t d,
                                               const double *__restrict__ vec,
                                               double *__restrict__ out,
                                               const LsqrState *__restrict__ st,
                                               int check_done, int accumulate) {
   if (check_done && st->done) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d) return;
+  __shared__ double red[16][17];
+  const int tid = threadIdx.x;
+  const int c = tid >> 4;  // row within the block
+  const int g = tid & 15;  // column phase
+  const int64_t i = (int64_t)blockIdx.x * 16 + c;
   double s = 0.0;
-  for (int64_t j = i; j < d; ++j) s += RinvT[j * d + i] * vec[j];
-  out[i] = accumulate ? out[i] + s : s;
-}
-
-__global__ void k_transpose(const double *__restrict__ A, int64_t d, double *__restrict__ T) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= d * d) return;
-  const int64_t i = e / d, j = e % d;
-  T[j * d + i] = A[i * d + j];
+  if (i < d) {
+    const int64_t jstart = i + ((g - (i & 15)) & 15);  // first j >= i with j = g mod 16
+    for (int64_t j = jstart; j < d; j += 16) s += Rinv[i * d + j] * vec[j];
+  }
+  red[c][g] = s;
+  __syncthreads();
+  if (tid < 16) {
+    const int64_t ii = (int64_t)blockIdx.x * 16 + tid;
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[tid][q];
+    if (ii < d) out[ii] = accumulate ? out[ii] + t : t;
+  }
 }
 
 __global__ void k_state_reset(LsqrState *st) {
@@ -276,54 +438,66 @@ __global__ __launch_bounds__(256) void k_resid(const T *__restrict__ vals,
 }
 
 struct LsqBufs {
-  double *u, *part_t, *part_b2, *tv, *vnew, *part_a2, *v, *w, *y, *vhat;
-  double *RinvT;
+  double *u, *part_t, *part2, *part_b2, *vnew, *part_a2, *v, *w, *y, *vhat;
   LsqrState *st;
 };
 
+template <typename T, bool INIT>
+void launch_dense_pass(const psk_mat &A, const LsqBufs &B, const double *rhs,
+                       hipStream_t s) {
+  const T *a = (const T *)A.values;
+  const int64_t d = A.d;
+#define PSK_DP(KC)                                                                      \
+  k_pass_dense<T, INIT, KC><<<kPassBlocks, 256, 0, s>>>(a, A.ld, A.n, d, B.vhat, rhs, B.u, \
+                                                        B.st, B.part_t, B.part_b2)
+  if (d <= 64) PSK_DP(1);
+  else if (d <= 128) PSK_DP(2);
+  else if (d <= 256) PSK_DP(4);
+  else if (d <= 512) PSK_DP(8);
+  else PSK_DP(16);
+#undef PSK_DP
+}
+
 template <typename T>
 void launch_pass(const psk_mat &A, bool init, const LsqBufs &B, const double *rhs,
-                 hipStream_t stream) {
-  const size_t lds = (size_t)4 * A.d * sizeof(double);
-  const T *vals = (const T *)A.values;
+                 hipStream_t s) {
   if (A.format == PSK_CSR) {
+    const size_t lds = (size_t)4 * A.d * sizeof(double);
+    const T *vals = (const T *)A.values;
     if (init)
-      k_pass<T, true, true><<<kPassBlocks, 256, lds, stream>>>(
-          vals, A.indptr, A.indices, A.n, A.d, A.ld, B.vhat, rhs, B.u, B.st, B.part_t,
-          B.part_b2);
+      k_pass_csr<T, true><<<kPassBlocks, 256, lds, s>>>(vals, A.indptr, A.indices, A.n, A.d,
+                                                        B.vhat, rhs, B.u, B.st, B.part_t,
+                                                        B.part_b2);
     else
-      k_pass<T, true, false><<<kPassBlocks, 256, lds, stream>>>(
-          vals, A.indptr, A.indices, A.n, A.d, A.ld, B.vhat, rhs, B.u, B.st, B.part_t,
-          B.part_b2);
+      k_pass_csr<T, false><<<kPassBlocks, 256, lds, s>>>(vals, A.indptr, A.indices, A.n, A.d,
+                                                         B.vhat, rhs, B.u, B.st, B.part_t,
+                                                         B.part_b2);
   } else {
     if (init)
-      k_pass<T, false, true><<<kPassBlocks, 256, lds, stream>>>(
-          vals, A.indptr, A.indices, A.n, A.d, A.ld, B.vhat, rhs, B.u, B.st, B.part_t,
-          B.part_b2);
+      launch_dense_pass<T, true>(A, B, rhs, s);
     else
-      k_pass<T, false, false><<<kPassBlocks, 256, lds, stream>>>(
-          vals, A.indptr, A.indices, A.n, A.d, A.ld, B.vhat, rhs, B.u, B.st, B.part_t,
-          B.part_b2);
+      launch_dense_pass<T, false>(A, B, rhs, s);
   }
 }
 
 void one_step(const psk_mat &A, bool init, const LsqBufs &B, const double *Rinv,
-              const double *rhs, const psk_lsq_opts &o, hipStream_t stream) {
+              const double *rhs, const psk_lsq_opts &o, hipStream_t s) {
   const int64_t d = A.d;
-  const unsigned db = (unsigned)ceil_div(d, 256);
+  const unsigned nb16 = (unsigned)ceil_div(d, 16);
   {
-    KTimer t("lsqr_pass", stream);
+    KTimer t("lsqr_pass", s);
     if (A.dtype == PSK_F64)
-      launch_pass<double>(A, init, B, rhs, stream);
+      launch_pass<double>(A, init, B, rhs, s);
     else
-      launch_pass<float>(A, init, B, rhs, stream);
+      launch_pass<float>(A, init, B, rhs, s);
   }
-  k_reduce_t<<<db, 256, 0, stream>>>(B.part_t, B.part_b2, kPassBlocks, d, B.st, B.tv,
-                                     init ? 1 : 0);
-  k_vnew<<<db, 256, 0, stream>>>(Rinv, d, B.tv, B.v, B.st, B.vnew, B.part_a2, init ? 1 : 0);
-  k_update<<<1, 256, 0, stream>>>(B.st, d, B.v, B.vnew, B.w, B.y, B.part_a2, (int)db,
-                                  o.atol, o.btol, init ? 1 : 0);
-  k_trmv<<<db, 256, 0, stream>>>(B.RinvT, d, B.v, B.vhat, B.st, init ? 0 : 1, 0);
+  k_reduce1<<<dim3((unsigned)ceil_div(d, 64), kRedGroups), 256, 0, s>>>(B.part_t, d, B.st,
+                                                                         B.part2, init ? 1 : 0);
+  k_vnew<<<nb16, 256, (size_t)d * sizeof(double), s>>>(B.part2, B.part_b2, Rinv, d, B.v, B.st,
+                                                       B.vnew, B.part_a2, init ? 1 : 0);
+  k_update<<<1, 256, 0, s>>>(B.st, d, B.v, B.vnew, B.w, B.y, B.part_a2, (int)nb16, o.atol,
+                             o.btol, init ? 1 : 0);
+  k_trmv<<<nb16, 256, 0, s>>>(Rinv, d, B.v, B.vhat, B.st, init ? 0 : 1, 0);
 }
 
 }  // namespace
@@ -337,18 +511,17 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   double *R = own ? ws.take<double>((size_t)d * d) : nullptr;
   double *Rinv = own ? ws.take<double>((size_t)d * d) : const_cast<double *>(o.Rinv);
   LsqBufs B;
-  B.RinvT = ws.take<double>((size_t)d * d);
   B.u = ws.take<double>((size_t)n);
   B.part_t = ws.take<double>((size_t)kPassBlocks * d);
+  B.part2 = ws.take<double>((size_t)kRedGroups * d);
   B.part_b2 = ws.take<double>(kPassBlocks);
-  B.tv = ws.take<double>((size_t)d);
   B.vnew = ws.take<double>((size_t)d);
-  B.part_a2 = ws.take<double>((size_t)ceil_div(d, 256));
+  B.part_a2 = ws.take<double>((size_t)ceil_div(d, 16));
   B.v = ws.take<double>((size_t)d);
   B.w = ws.take<double>((size_t)d);
   B.y = ws.take<double>((size_t)d);
   B.vhat = ws.take<double>((size_t)d);
-  double *res = ws.take<double>((size_t)n);
+  double *res = ws.take<double>((size_t)n);  // residual of the refinement passes
   B.st = ws.take<LsqrState>(1);
   const size_t mk = ws.mark();
   int rc = 0;
@@ -365,7 +538,6 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for lsq_solve");
   ws.release(mk);
-  k_transpose<<<(unsigned)ceil_div(d * d, 256), 256, 0, st>>>(Rinv, d, B.RinvT);
   if (own) {
     int hflag = 0;
     PSK_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -374,7 +546,8 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   }
 
   const unsigned db = (unsigned)ceil_div(d, 256);
-  k_zero<<<(unsigned)ceil_div(d, 256), 256, 0, st>>>(x, d);
+  const unsigned nb16 = (unsigned)ceil_div(d, 16);
+  k_zero<<<db, 256, 0, st>>>(x, d);
   int total_iters = 0;
   bool converged = true;
   LsqrState hs{};
@@ -419,7 +592,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     if (!done) converged = false;
     total_iters += hs.iters;
     // x += R^{-1} y
-    k_trmv<<<db, 256, 0, st>>>(B.RinvT, d, B.y, x, B.st, 0, 1);
+    k_trmv<<<nb16, 256, 0, st>>>(Rinv, d, B.y, x, B.st, 0, 1);
   }
   PSK_HIP_TRY(hipGetLastError());
   PSK_HIP_TRY(hipStreamSynchronize(st));
