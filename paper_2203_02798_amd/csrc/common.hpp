@@ -32,7 +32,7 @@ struct u32x4 {
   uint32_t x0, x1, x2, x3;
 };
 
-__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1,
+__host__ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1,
                                                uint32_t c2, uint32_t c3,
                                                uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -55,18 +55,84 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1,
 }
 
 // CountSketch hash of global row i: bucket in [0, r), sign bit (1 = -1).
-__device__ __forceinline__ void cs_hash_row(uint64_t i, uint32_t r, uint64_t seed,
+__host__ __device__ __forceinline__ void cs_hash_row(uint64_t i, uint32_t r, uint64_t seed,
                                             uint32_t &h, uint32_t &neg) {
   const u32x4 x = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u,
                                 (uint32_t)seed, (uint32_t)(seed >> 32));
   const uint64_t X = ((uint64_t)x.x1 << 32) | x.x0;
-  h = (uint32_t)__umul64hi(X, (uint64_t)r);
+  h = (uint32_t)(((unsigned __int128)X * (uint64_t)r) >> 64);
   neg = x.x2 & 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Lean FP64 elementary functions for Box-Muller, on the ranges it needs.
+// Accuracy about 1e-16 relative; no branches.
+// ---------------------------------------------------------------------------
+// ln(x) for x in (0, 1]: x = f 2^e with f in [1/sqrt2, sqrt2),
+// ln f = 2 atanh(s), s = (f-1)/(f+1), |s| <= 0.1716, atanh by its power
+// series s + s^3/3 + ... + s^19/19 (truncation below 1e-17); ln 2 is split so
+// that e * ln2_hi is exact.
+__host__ __device__ __forceinline__ double bm_log(double x) {
+  int e;
+  double f = frexp(x, &e);  // f in [1/2, 1)
+  const bool lo = f < 0.70710678118654752440;
+  f = lo ? 2.0 * f : f;
+  e = lo ? e - 1 : e;
+  const double s = (f - 1.0) / (f + 1.0);
+  const double s2 = s * s;
+  double p = 1.0 / 19.0;
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  const double lnf = fma(2.0 * s * s2, p, 2.0 * s);
+  const double ln2_hi = 0.6931467056274414;       // ln 2 to 21 bits
+  const double ln2_lo = 4.7493250390316726e-07;   // ln 2 - ln2_hi
+  return fma((double)e, ln2_hi, fma((double)e, ln2_lo, lnf));
+}
+
+// sin(pi z) and cos(pi z) for z in [0, 2]: z = k/2 + y with |y| <= 1/4 (exact
+// split), Taylor series of sin(pi y) (9 terms) and cos(pi y) (10 terms),
+// truncation below 1e-19, then the quarter-turn k mod 4 picks and signs.
+__host__ __device__ __forceinline__ void bm_sincospi(double z, double &sn, double &cs) {
+  const double k = rint(2.0 * z);
+  const double y = fma(-0.5, k, z);
+  const double y2 = y * y;
+  double ps = 7.952054001475513e-07;
+  ps = fma(ps, y2, -2.1915353447830217e-05);
+  ps = fma(ps, y2, 0.00046630280576761255);
+  ps = fma(ps, y2, -0.0073704309457143504);
+  ps = fma(ps, y2, 0.08214588661112823);
+  ps = fma(ps, y2, -0.5992645293207921);
+  ps = fma(ps, y2, 2.5501640398773455);
+  ps = fma(ps, y2, -5.16771278004997);
+  ps = fma(ps, y2, 3.141592653589793);
+  const double sp = ps * y;
+  double pc = -1.3878952462213771e-07;
+  pc = fma(pc, y2, 4.303069587032947e-06);
+  pc = fma(pc, y2, -0.0001046381049248457);
+  pc = fma(pc, y2, 0.0019295743094039231);
+  pc = fma(pc, y2, -0.02580689139001406);
+  pc = fma(pc, y2, 0.2353306303588932);
+  pc = fma(pc, y2, -1.3352627688545895);
+  pc = fma(pc, y2, 4.0587121264167685);
+  pc = fma(pc, y2, -4.934802200544679);
+  const double cp = fma(pc, y2, 1.0);
+  const int q = ((int)k) & 3;
+  // sin(pi(k/2 + y)) = sp, cp, -sp, -cp ; cos(...) = cp, -sp, -cp, sp
+  const double a = (q & 1) ? cp : sp;
+  const double b = (q & 1) ? sp : cp;
+  sn = (q & 2) ? -a : a;
+  cs = ((q + 1) & 2) ? -b : b;
 }
 
 // Four unscaled standard normals z0..z3 for buckets 4q .. 4q+3 of Gaussian
 // row a (Box-Muller on two pairs of uniforms in (0,1)), FP64.
-__device__ __forceinline__ void gauss4_f64(uint64_t q, uint32_t a, uint64_t seed,
+__host__ __device__ __forceinline__ void gauss4_f64(uint64_t q, uint32_t a, uint64_t seed,
                                            double z[4]) {
   const u32x4 x = philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), a, 1u,
                                 (uint32_t)seed, (uint32_t)(seed >> 32));
@@ -75,11 +141,11 @@ __device__ __forceinline__ void gauss4_f64(uint64_t q, uint32_t a, uint64_t seed
   const double u1 = ((double)x.x1 + 0.5) * s;
   const double u2 = ((double)x.x2 + 0.5) * s;
   const double u3 = ((double)x.x3 + 0.5) * s;
-  const double r0 = sqrt(-2.0 * log(u0));
-  const double r2 = sqrt(-2.0 * log(u2));
+  const double r0 = sqrt(-2.0 * bm_log(u0));
+  const double r2 = sqrt(-2.0 * bm_log(u2));
   double s1, c1, s3, c3;
-  sincospi(2.0 * u1, &s1, &c1);
-  sincospi(2.0 * u3, &s3, &c3);
+  bm_sincospi(2.0 * u1, s1, c1);
+  bm_sincospi(2.0 * u3, s3, c3);
   z[0] = r0 * c1;
   z[1] = r0 * s1;
   z[2] = r2 * c3;

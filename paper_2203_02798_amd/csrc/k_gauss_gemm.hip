@@ -37,12 +37,21 @@ constexpr int kBK = 16;
 constexpr int kLdsStride = kBN + 16;
 constexpr int kPf = kBK * kBN / kThreads;  // 8 prefetched values per thread
 
-template <typename T>
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// DIRECT (FP64 S*A, even d, split slice below 2 GiB): each chunk of S*A is
+// copied from memory straight into LDS by buffer loads (16 bytes per lane,
+// no registers, no LDS stores), issued one chunk ahead.  The buffer
+// descriptor covers exactly this workgroup's K slice, so rows past the
+// slice read as zero (hardware range check); columns past d of a row read
+// the next row's values, which only reach output columns >= d (discarded).
+// Otherwise S*A goes through registers (converted to FP64, masked).
+template <typename T, bool DIRECT>
 __global__ __launch_bounds__(kThreads) void k_gauss_gemm_f64(
     int64_t m, int64_t r, int64_t d, uint64_t seed, const T *__restrict__ SA,
     int tiles_m, int tiles_n, int splits, int64_t kper,
     double *__restrict__ out /* [splits][m][d] */) {
-  __shared__ double tile[2][kBK][kLdsStride];
+  __shared__ __align__(16) double tile[2][kBK][kLdsStride];
 
   // XCD-aware order: blocks are dealt round-robin to the 8 XCDs; renumber so
   // that one XCD runs consecutive tiles of the same (column tile, K split),
@@ -77,11 +86,17 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_f64(
   const bool col_ok = (n0 + lcol) < d;
   double pf[kPf];
 
+  // Branch-free loads (clamped in-bounds address, then a select) keep the
+  // whole K iteration one basic block, so the scheduler can interleave the
+  // Gaussian generation with the matrix instructions.
+  const int64_t ccol = col_ok ? n0 + lcol : d - 1;
   auto load_chunk = [&](int64_t k0) {
 #pragma unroll
     for (int p = 0; p < kPf; ++p) {
       const int64_t k = k0 + lrow + 2 * p;
-      pf[p] = (col_ok && k < ke) ? (double)SA[k * d + n0 + lcol] : 0.0;
+      const int64_t kc = k < ke ? k : ke - 1;
+      const double v = (double)SA[kc * d + ccol];
+      pf[p] = (col_ok && k < ke) ? v : 0.0;
     }
   };
   auto store_chunk = [&](int buf) {
@@ -89,21 +104,57 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_f64(
     for (int p = 0; p < kPf; ++p) tile[buf][lrow + 2 * p][lcol] = pf[p];
   };
 
+  // direct path: wave w copies rows 2w, 2w+1 of a chunk, 128 doubles per
+  // buffer load (64 lanes x 16 bytes), two loads per row
+  __amdgpu_buffer_rsrc_t rsrc;
+  if (DIRECT) {
+    const int nbytes = (int)((ke > kb ? ke - kb : 0) * d * (int64_t)sizeof(double));
+    rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)(SA + kb * d), (short)0, nbytes,
+                                             0x00020000);
+  }
+  auto direct_chunk = [&](int64_t crel, int buf) {
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const int row = 2 * wave + rr;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh) {
+        const int voff =
+            (int)(((crel * kBK + row) * d + n0 + hh * 128 + 2 * lane) * (int64_t)sizeof(double));
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, (lds_ptr_t)&tile[buf][row][hh * 128],
+                                                 16, voff, 0, 0, 0);
+      }
+    }
+  };
+
   const int64_t nchunks = (ke > kb) ? ceil_div(ke - kb, kBK) : 0;
   const uint32_t row_a = (uint32_t)(m0 + wave * 16 + li);
 
+  // Gaussian values of this lane's row for the four consecutive buckets of a
+  // chunk; the values for chunk c+1 are generated while chunk c's matrix
+  // instructions run (the vector and matrix pipes work concurrently).
+  double g[4];
   if (nchunks > 0) {
-    load_chunk(kb);
-    store_chunk(0);
+    if (DIRECT) {
+      direct_chunk(0, 0);
+      __builtin_amdgcn_s_waitcnt(0);
+    } else {
+      load_chunk(kb);
+      store_chunk(0);
+    }
+    gauss4_f64((uint64_t)(kb >> 2) + (uint64_t)kq, row_a, seed, g);
   }
   __syncthreads();
   for (int64_t c = 0; c < nchunks; ++c) {
     const int buf = (int)(c & 1);
     const int64_t k0 = kb + c * kBK;
-    if (c + 1 < nchunks) load_chunk(k0 + kBK);
-    // Gaussian values of this lane's row for four consecutive buckets
-    double g[4];
-    gauss4_f64((uint64_t)(k0 >> 2) + (uint64_t)kq, row_a, seed, g);
+    // the last iteration loads one unused chunk (in bounds or zero-filled)
+    // rather than branching
+    if (DIRECT)
+      direct_chunk(c + 1, buf ^ 1);
+    else
+      load_chunk(k0 + kBK);
+    double gn[4];
+    gauss4_f64((uint64_t)((k0 + kBK) >> 2) + (uint64_t)kq, row_a, seed, gn);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       double bv[kNB];
@@ -113,8 +164,13 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_f64(
       for (int nb = 0; nb < kNB; ++nb)
         acc[nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[s], bv[nb], acc[nb], 0, 0, 0);
     }
-    if (c + 1 < nchunks) store_chunk(buf ^ 1);
+    if (DIRECT)
+      __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into buf^1 landed
+    else
+      store_chunk(buf ^ 1);
     __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) g[s] = gn[s];
   }
 
   // accumulator element e of block nb: row kq + 4*e, column li
@@ -168,11 +224,19 @@ int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
   const int64_t nblk = tiles * splits;
   {
     KTimer t("gauss_gemm", st);
-    if (sa_dtype == PSK_F64)
-      k_gauss_gemm_f64<double><<<(unsigned)nblk, kThreads, 0, st>>>(
+    // direct copies need 16-byte aligned rows and a K slice addressable with
+    // 32-bit byte offsets (plus one chunk of read-ahead)
+    const bool direct = sa_dtype == PSK_F64 && (d % 2) == 0 &&
+                        ((uintptr_t)SA % 16) == 0 &&
+                        (kper + kBK) * d * (int64_t)sizeof(double) + 65536 < ((int64_t)1 << 31);
+    if (direct)
+      k_gauss_gemm_f64<double, true><<<(unsigned)nblk, kThreads, 0, st>>>(
+          m, r, d, seed, (const double *)SA, tiles_m, tiles_n, (int)splits, kper, part);
+    else if (sa_dtype == PSK_F64)
+      k_gauss_gemm_f64<double, false><<<(unsigned)nblk, kThreads, 0, st>>>(
           m, r, d, seed, (const double *)SA, tiles_m, tiles_n, (int)splits, kper, part);
     else
-      k_gauss_gemm_f64<float><<<(unsigned)nblk, kThreads, 0, st>>>(
+      k_gauss_gemm_f64<float, false><<<(unsigned)nblk, kThreads, 0, st>>>(
           m, r, d, seed, (const float *)SA, tiles_m, tiles_n, (int)splits, kper, part);
   }
   const int64_t len = m * d;
