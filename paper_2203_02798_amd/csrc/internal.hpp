@@ -51,8 +51,8 @@ void timing_end(int slot, hipStream_t st);
 struct KTimer {
   int slot;
   hipStream_t st;
-  KTimer(const char *name, hipStream_t s) : slot(-1), st(s) {
-    if (timing_enabled()) slot = timing_begin(name, s);
+  KTimer(const char *name, hipStream_t s, bool on = true) : slot(-1), st(s) {
+    if (on && timing_enabled()) slot = timing_begin(name, s);
   }
   ~KTimer() {
     if (slot >= 0) timing_end(slot, st);
@@ -64,6 +64,12 @@ struct KTimer {
 // stable; bptr[b] .. bptr[b+1] is bucket b's range.  Returns 0 or a status.
 int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
            uint32_t **perm, uint32_t **bptr);
+// Stable LSD radix sort (8-bit digits) of (key, val) pairs with keys < r;
+// keys/vals are consumed (used as the first ping-pong buffers).  On return
+// *skeys/*svals point at the sorted arrays; with ptr != NULL, ptr[0..r] gets
+// the start of each key's run (ptr[r] = n).
+int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
+               hipStream_t st, uint32_t **skeys, uint32_t **svals, uint32_t *ptr);
 int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
                    int32_t *h, int8_t *sign, hipStream_t st);
 // S*A into SA (r x d row-major, dtype of A).

@@ -13,7 +13,7 @@
 // the first pass keeps the Cholesky factorization defined for condition
 // numbers up to about 1/u, and two unshifted passes restore orthogonality.
 //
-// The d x d Cholesky is blocked (32 columns): a one-workgroup kernel factors
+// The d x d Cholesky is blocked (64 columns): a one-workgroup kernel factors
 // the diagonal block in LDS and inverts it, then two GEMMs form the block
 // row of R and update the trailing matrix.  R^{-1} is assembled by block
 // columns: X[0:j, j] = -X[0:j, 0:j] R[0:j, j] X[j, j].
@@ -22,7 +22,7 @@
 namespace psk {
 namespace {
 
-constexpr int kNB = 32;
+constexpr int kNB = 64;
 
 __global__ void k_fill(double *__restrict__ p, int64_t count, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,55 +42,81 @@ __global__ __launch_bounds__(256) void k_shift_diag(double *__restrict__ W, int6
   for (int64_t i = threadIdx.x; i < d; i += 256) W[i * d + i] += coef * tr;
 }
 
-// Upper Cholesky U^T U = W[j0:j0+nb, j0:j0+nb] and its inverse, in LDS.
-__global__ __launch_bounds__(256) void k_potrf_block(const double *__restrict__ W,
-                                                     int64_t d, int64_t j0, int nb,
-                                                     double *__restrict__ R,
-                                                     double *__restrict__ X,
-                                                     int *__restrict__ flag) {
-  __shared__ double U[kNB][kNB + 1];
-  __shared__ double V[kNB][kNB + 1];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int i = e / nb, j = e % nb;
-    U[i][j] = W[(j0 + i) * d + j0 + j];
+// Upper Cholesky U^T U = W[j0:j0+nb, j0:j0+nb] and its inverse by one
+// wavefront: lane j keeps column j of the block in registers; each step
+// publishes one row through a 64-entry LDS buffer that every lane reads with
+// broadcast loads (no barriers beyond the wavefront).  Rows stay unscaled
+// during elimination (step k subtracts U[k][i] U[k][j] / U[k][k]) and are
+// scaled by 1/sqrt(U[k][k]) at the end.  A block narrower than 64 is padded
+// with the identity.  The inverse is back substitution on each column:
+// x_i = (e_j[i] - sum_{k>i} U[i][k] x_k) / U[i][i].
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(64) void k_potrf_block(const double *__restrict__ W,
+                                                    int64_t d, int64_t j0, int nb,
+                                                    double *__restrict__ R,
+                                                    double *__restrict__ X,
+                                                    int *__restrict__ flag) {
+  __shared__ double rowbuf[kNB];
+  const int j = threadIdx.x;
+  double c[kNB];
+#pragma unroll
+  for (int i = 0; i < kNB; ++i)
+    c[i] = (i < nb && j < nb) ? W[(j0 + i) * d + j0 + j] : (i == j ? 1.0 : 0.0);
+  bool bad = false;
+  double mypiv = 1.0;  // this lane's pivot U[j][j] once step j is reached
+#pragma clang loop unroll(full)
+  for (int k = 0; k < kNB; ++k) {
+    rowbuf[j] = c[k];  // row k of the (unscaled) factor
+    wave_sync_lds();
+    double piv = rowbuf[k];
+    mypiv = (k == j) ? piv : mypiv;
+    bad |= !(piv > 0.0);
+    piv = piv > 0.0 ? piv : 1.0;
+    const double f = c[k] / piv;  // U[k][j] / U[k][k]
+#pragma clang loop unroll(full)
+    for (int i = k + 1; i < kNB; ++i) c[i] -= rowbuf[i] * f;
+    wave_sync_lds();
   }
-  __syncthreads();
-  for (int k = 0; k < nb; ++k) {
-    if (tid == 0) {
-      double piv = U[k][k];
-      if (!(piv > 0.0)) {
-        atomicOr(flag, 1);
-        piv = 1e-300;
-      }
-      U[k][k] = sqrt(piv);
-    }
-    __syncthreads();
-    for (int j = k + 1 + tid; j < nb; j += 256) U[k][j] /= U[k][k];
-    __syncthreads();
-    const int rem = nb - k - 1;
-    for (int e = tid; e < rem * rem; e += 256) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (i <= j) U[i][j] -= U[k][i] * U[k][j];
-    }
-    __syncthreads();
+  // scale row k by 1/sqrt(U[k][k]) (the diagonal entries sit in lane k)
+  rowbuf[j] = sqrt(mypiv > 0.0 ? mypiv : 1.0);
+  wave_sync_lds();
+#pragma unroll
+  for (int k = 0; k < kNB; ++k) {
+    const double v = (k <= j) ? c[k] / rowbuf[k] : 0.0;
+    if (k < nb && j < nb) R[(j0 + k) * d + j0 + j] = v;
   }
-  // inverse of the upper-triangular U, one column per thread
-  if (tid < nb) {
-    const int j = tid;
-    for (int i = 0; i < nb; ++i) V[i][j] = 0.0;
-    V[j][j] = 1.0 / U[j][j];
-    for (int i = j - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int k = i + 1; k <= j; ++k) s += U[i][k] * V[k][j];
-      V[i][j] = -s / U[i][i];
-    }
+  if (bad && j == 0) atomicOr(flag, 1);
+}
+
+// Inverse of the upper-triangular diagonal block R[j0:j0+nb, j0:j0+nb] into
+// the same block of X: lane j solves U x = e_j by back substitution,
+// x_i = (e_j[i] - sum_{k>i} U[i][k] x_k) / U[i][i], reading U from LDS
+// (broadcast loads).  Padding beyond nb is the identity.
+__global__ __launch_bounds__(64) void k_trinv_block(const double *__restrict__ R, int64_t d,
+                                                    int64_t j0, int nb,
+                                                    double *__restrict__ X) {
+  __shared__ double Ul[kNB][kNB + 1];
+  const int j = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < kNB; ++i)
+    Ul[i][j] = (i < nb && j < nb) ? R[(j0 + i) * d + j0 + j] : (i == j ? 1.0 : 0.0);
+  wave_sync_lds();
+  double x[kNB];
+#pragma clang loop unroll(full)
+  for (int i = kNB - 1; i >= 0; --i) {
+    double s = (i == j) ? 1.0 : 0.0;
+#pragma clang loop unroll(full)
+    for (int k = i + 1; k < kNB; ++k) s -= Ul[i][k] * x[k];
+    x[i] = s / Ul[i][i];
   }
-  __syncthreads();
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int i = e / nb, j = e % nb;
-    R[(j0 + i) * d + j0 + j] = (i <= j) ? U[i][j] : 0.0;
-    X[(j0 + i) * d + j0 + j] = (i <= j) ? V[i][j] : 0.0;
+  if (j < nb) {
+#pragma unroll
+    for (int i = 0; i < kNB; ++i)
+      if (i < nb) X[(j0 + i) * d + j0 + j] = (i <= j) ? x[i] : 0.0;
   }
 }
 
@@ -109,7 +135,10 @@ int chol_inv(double *W, int64_t d, double *R, double *X, double *T, int *flag,
   const size_t mk = ws.mark();
   for (int64_t j0 = 0; j0 < d; j0 += kNB) {
     const int nb = (int)((d - j0) < kNB ? (d - j0) : kNB);
-    if (run) k_potrf_block<<<1, 256, 0, st>>>(W, d, j0, nb, R, X, flag);
+    if (run) {
+      k_potrf_block<<<1, 64, 0, st>>>(W, d, j0, nb, R, X, flag);
+      k_trinv_block<<<1, 64, 0, st>>>(R, d, j0, nb, X);
+    }
     const int64_t rest = d - j0 - nb;
     if (rest > 0) {
       int rc = dgemm(true, false, nb, rest, nb, 1.0, X + j0 * d + j0, d,

@@ -2,14 +2,14 @@
 //
 // Paper mapping (arXiv 2203.02798):
 // * Gram: Algorithm gram_serial's outer-product loop (B[J_k, J_j] +=
-//   V_k V_j over pairs of a row's entries), parallelised by combining the two
-//   parallel algorithms of section 3: like Algorithm
-//   gram_parallel_memory_effcient a workgroup owns a range of output rows
-//   (kept in LDS) and filters each row's entries against that range; like
-//   Algorithm gram the rows of A are split into chunks whose partial results
-//   are summed afterwards (in a fixed order).  Inside a workgroup each
-//   output row belongs to one wavefront, so every LDS element is updated by
-//   one wavefront in row order.
+//   V_k V_j over pairs of a row's entries), parallelised by output rows as
+//   Algorithm gram_parallel_memory_effcient does (each worker owns output
+//   rows, so no partial Grams and no reduction), but where that algorithm
+//   scans every row of A and filters its entries, here the entries are first
+//   sorted by column (a stable radix sort: the column index of A), so the
+//   wavefront owning output row j visits exactly the rows with an entry in
+//   column j: nnz_2(A) work in total.  Only k >= j is accumulated and the
+//   other triangle is mirrored, so C is exactly symmetric.
 // * Row norms: Algorithm squared_row_norms: Bt = B B^T once, then per row
 //   sum_{k,j} V_k V_j Bt[J_j, J_k].  Short rows take one lane each; rows
 //   longer than 32 entries are taken by the whole wavefront (lanes over k).
@@ -18,59 +18,62 @@
 namespace psk {
 namespace {
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_gram_csr(
+// rowidx[p] = row of stored entry p
+__global__ __launch_bounds__(256) void k_row_of_entry(const int64_t *__restrict__ indptr,
+                                                      int64_t n, uint32_t *__restrict__ rowidx) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t p = indptr[i]; p < indptr[i + 1]; ++p) rowidx[p] = (uint32_t)i;
+}
+
+// (column, position) pairs of the stored entries, to be sorted by column
+__global__ __launch_bounds__(256) void k_col_keys(const int32_t *__restrict__ indices,
+                                                  int64_t nnz, uint32_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nnz) return;
+  keys[p] = (uint32_t)indices[p];
+  vals[p] = (uint32_t)p;
+}
+
+// One wavefront per output row j: for every entry A[i, j] of column j (rows
+// in increasing order), add A[i, j] * A[i, k] over the entries of row i with
+// k >= j into a private LDS row; then write C[j, k] and its mirror C[k, j].
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void k_gram_csc(
     const T *__restrict__ vals, const int64_t *__restrict__ indptr,
-    const int32_t *__restrict__ indices, int64_t n, int64_t d, int rb,
-    int64_t rows_per_chunk, int nranges, double *__restrict__ part) {
+    const int32_t *__restrict__ indices, const uint32_t *__restrict__ rowidx,
+    const uint32_t *__restrict__ cperm, const uint32_t *__restrict__ cptr, int64_t d,
+    int64_t dpad, double alpha, double beta, TO *__restrict__ C) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *acc = reinterpret_cast<double *>(smem_raw);  // [rb][d]
-  const int range = (int)(blockIdx.x % nranges);
-  const int chunk = (int)(blockIdx.x / nranges);
-  const int64_t r0 = (int64_t)range * rb;
-  const int rows_here = (int)((r0 + rb <= d) ? rb : (d - r0));
-  for (int64_t e = threadIdx.x; e < (int64_t)rb * d; e += blockDim.x) acc[e] = 0.0;
-  __syncthreads();
-  const int wave = threadIdx.x >> 6;
+  double *acc = reinterpret_cast<double *>(smem_raw) + (threadIdx.x >> 6) * dpad;
+  const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (j >= d) return;
   const int lane = threadIdx.x & 63;
-  const int64_t i0 = (int64_t)chunk * rows_per_chunk;
-  int64_t i1 = i0 + rows_per_chunk;
-  if (i1 > n) i1 = n;
-  for (int64_t g = i0; g < i1; g += 64) {
-    const int64_t i = g + lane;
-    if (i < i1) {
-      const int64_t p0 = indptr[i], p1 = indptr[i + 1];
-      for (int64_t kk = p0; kk < p1; ++kk) {
-        const int64_t c = (int64_t)indices[kk] - r0;
-        if (c < 0 || c >= rows_here || (int)(c & 3) != wave) continue;
-        const double vk = (double)vals[kk];
-        double *arow = acc + c * d;
-        for (int64_t h = p0; h < p1; ++h)
-          atomicAdd(&arow[indices[h]], vk * (double)vals[h]);
+  for (int64_t c = j + lane; c < d; c += 64) acc[c] = 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t e1 = cptr[j + 1];
+  for (uint32_t e0 = cptr[j]; e0 < e1; e0 += 64) {
+    const uint32_t e = e0 + lane;
+    if (e < e1) {
+      const uint32_t p = cperm[e];
+      const double v = (double)vals[p];
+      const uint32_t i = rowidx[p];
+      for (int64_t h = indptr[i]; h < indptr[i + 1]; ++h) {
+        const int32_t c = indices[h];
+        if (c >= j) atomicAdd(&acc[c], v * (double)vals[h]);
       }
     }
   }
-  __syncthreads();
-  double *o = part + (int64_t)chunk * d * d + r0 * d;
-  for (int64_t e = threadIdx.x; e < (int64_t)rows_here * d; e += blockDim.x) o[e] = acc[e];
-}
-
-// C = alpha * sum_chunks part + beta * C; both (i, j) and (j, i) take the
-// upper-triangle entry (min, max), so C is exactly symmetric.
-template <typename TO>
-__global__ __launch_bounds__(256) void k_gram_reduce(const double *__restrict__ part,
-                                                     int64_t d, int chunks, double alpha,
-                                                     double beta, TO *__restrict__ C) {
-  const int64_t dd = d * d;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= dd) return;
-  const int64_t i = e / d, j = e % d;
-  const int64_t src = i <= j ? e : j * d + i;
-  double s = part[src];
-  for (int c = 1; c < chunks; ++c) s += part[(int64_t)c * dd + src];
-  double v = alpha * s;
-  if (beta != 0.0) v += beta * (double)C[e];
-  C[e] = (TO)v;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int64_t k = j + lane; k < d; k += 64) {
+    const double g = alpha * acc[k];
+    const int64_t up = j * d + k, lo = k * d + j;
+    C[up] = (TO)(beta != 0.0 ? g + beta * (double)C[up] : g);
+    if (k > j) C[lo] = (TO)(beta != 0.0 ? g + beta * (double)C[lo] : g);
+  }
 }
 
 template <typename T>
@@ -122,39 +125,37 @@ __global__ __launch_bounds__(256) void k_rownorm_csr(
 
 int gram_csr(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
              hipStream_t st) {
-  const int64_t d = A.d;
+  const int64_t d = A.d, n = A.n, nnz = A.nnz;
   if (d > 8192) return fail(PSK_EUNSUPPORTED, "CSR gram supports d <= 8192");
-  int rb = (int)(8192 / d);  // rb x d FP64 rows in 64 KiB of LDS
-  if (rb > 64) rb = 64;
-  if (rb < 1) rb = 1;
-  const int nranges = (int)ceil_div(d, rb);
-  int64_t chunks = ceil_div(1024, nranges);
-  if (chunks > 16) chunks = 16;
-  if (chunks > A.n) chunks = A.n;
-  if (chunks < 1) chunks = 1;
-  const int64_t rows_per_chunk = ceil_div(A.n, chunks);
-  chunks = ceil_div(A.n, rows_per_chunk);
-  double *part = ws.take<double>((size_t)chunks * d * d);
+  if (nnz >= ((int64_t)1 << 32)) return fail(PSK_EUNSUPPORTED, "CSR gram needs nnz < 2^32");
+  const int64_t cnt = nnz > 0 ? nnz : 1;
+  uint32_t *keys = ws.take<uint32_t>(cnt);
+  uint32_t *vals = ws.take<uint32_t>(cnt);
+  uint32_t *rowidx = ws.take<uint32_t>(cnt);
+  uint32_t *cptr = ws.take<uint32_t>((size_t)d + 1);
+  if (!ws.dry()) {
+    k_col_keys<<<(unsigned)ceil_div(cnt, 256), 256, 0, st>>>(A.indices, nnz, keys, vals);
+    k_row_of_entry<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(A.indptr, n, rowidx);
+  }
+  uint32_t *skeys = nullptr, *cperm = nullptr;
+  int rc = sort_pairs(keys, vals, nnz, (uint32_t)d, ws, st, &skeys, &cperm, cptr);
+  if (rc) return rc;
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for CSR gram");
-  const size_t lds = (size_t)rb * d * sizeof(double);
-  const unsigned blocks = (unsigned)(nranges * chunks);
+  const int64_t dpad = (d + 1) & ~(int64_t)1;
+  int wpb = 4;
+  while (wpb > 1 && (size_t)wpb * dpad * sizeof(double) > 65536) --wpb;
+  const size_t lds = (size_t)wpb * dpad * sizeof(double);
+  const unsigned blocks = (unsigned)ceil_div(d, wpb);
   KTimer timer("gram", st);
   if (A.dtype == PSK_F64)
-    k_gram_csr<double><<<blocks, 256, lds, st>>>((const double *)A.values, A.indptr,
-                                                 A.indices, A.n, d, rb, rows_per_chunk,
-                                                 nranges, part);
+    k_gram_csc<double, double><<<blocks, 64 * wpb, lds, st>>>(
+        (const double *)A.values, A.indptr, A.indices, rowidx, cperm, cptr, d, dpad, alpha,
+        beta, (double *)C);
   else
-    k_gram_csr<float><<<blocks, 256, lds, st>>>((const float *)A.values, A.indptr,
-                                                A.indices, A.n, d, rb, rows_per_chunk,
-                                                nranges, part);
-  const int64_t dd = d * d;
-  if (A.dtype == PSK_F64)
-    k_gram_reduce<double><<<(unsigned)ceil_div(dd, 256), 256, 0, st>>>(
-        part, d, (int)chunks, alpha, beta, (double *)C);
-  else
-    k_gram_reduce<float><<<(unsigned)ceil_div(dd, 256), 256, 0, st>>>(
-        part, d, (int)chunks, alpha, beta, (float *)C);
+    k_gram_csc<float, float><<<blocks, 64 * wpb, lds, st>>>(
+        (const float *)A.values, A.indptr, A.indices, rowidx, cperm, cptr, d, dpad, alpha,
+        beta, (float *)C);
   PSK_HIP_TRY(hipGetLastError());
   return 0;
 }

@@ -23,7 +23,7 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kBK = 16;
 
-enum { EPI_PARTIAL = 0, EPI_ROWNORM = 1 };
+enum { EPI_PARTIAL = 0, EPI_ROWNORM = 1, EPI_DIRECT = 2 };
 
 template <typename T, bool KMAJOR, int BX>
 struct TileLoader {
@@ -106,7 +106,7 @@ template <typename TA, typename TB, bool TRA, bool TRB, int WM, int WN, int MB, 
 __global__ __launch_bounds__(256) void k_dgemm(
     int64_t M, int64_t N, int64_t K, const TA *__restrict__ A, int64_t lda,
     const TB *__restrict__ B, int64_t ldb, int tiles_m, int tiles_n, int64_t kper,
-    double *__restrict__ out, int64_t ldo) {
+    double *__restrict__ out, int64_t ldo, double alpha, double beta) {
   constexpr int BM = WM * MB * 16;
   constexpr int BN = WN * NB * 16;
   __shared__ double As[kBK][BM + 4];
@@ -166,7 +166,24 @@ __global__ __launch_bounds__(256) void k_dgemm(
     }
   }
 
-  if (EPI == EPI_PARTIAL) {
+  if (EPI == EPI_DIRECT) {
+    // no K split: out = alpha * acc + beta * out (beta == 0 ignores out)
+#pragma unroll
+    for (int a = 0; a < MB; ++a)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + (wm * MB + a) * 16 + kq + 4 * e;
+        if (row >= M) continue;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int64_t col = n0 + (wn * NB + b) * 16 + li;
+          if (col < N) {
+            double *po = out + row * ldo + col;
+            *po = beta != 0.0 ? alpha * acc[a][b][e] + beta * *po : alpha * acc[a][b][e];
+          }
+        }
+      }
+  } else if (EPI == EPI_PARTIAL) {
     double *o = out + (int64_t)tc.ks * M * ldo;
 #pragma unroll
     for (int a = 0; a < MB; ++a)
@@ -262,12 +279,20 @@ int gemm_partial_launch(int64_t M, int64_t N, int64_t K, const TA *A, int64_t ld
   int64_t splits = pick_splits(tiles, K, 1024);
   const int64_t kper = ceil_div(ceil_div(K, kBK), splits) * kBK;
   splits = K > 0 ? ceil_div(K, kper) : 1;
+  if (splits == 1 && !UPPER && !out_f32) {
+    if (ws.dry()) return 0;
+    k_dgemm<TA, TB, TRA, TRB, WM, WN, MB, NB, EPI_DIRECT, false>
+        <<<(unsigned)tiles, 256, 0, st>>>(M, N, K, A, lda, B, ldb, tm, tn, kper,
+                                          (double *)C, ldc, alpha, beta);
+    PSK_HIP_TRY(hipGetLastError());
+    return 0;
+  }
   double *part = ws.take<double>((size_t)splits * M * N);
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for a GEMM");
   k_dgemm<TA, TB, TRA, TRB, WM, WN, MB, NB, EPI_PARTIAL, UPPER>
       <<<(unsigned)(tiles * splits), 256, 0, st>>>(M, N, K, A, lda, B, ldb, tm, tn,
-                                                    kper, part, N);
+                                                    kper, part, N, 1.0, 0.0);
   const int64_t len = M * N;
   if (out_f32)
     k_splitk_reduce<float><<<(unsigned)ceil_div(len, 256), 256, 0, st>>>(
@@ -292,7 +317,7 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
     if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for row norms");
     k_dgemm<TA, double, false, false, 4, 1, 1, 4, EPI_ROWNORM, false>
         <<<(unsigned)((int64_t)tm * tn), 256, 0, st>>>(n, k, d, A, Am.ld, B, k, tm, tn, d,
-                                                       part, n);
+                                                       part, n, 1.0, 0.0);
     k_rownorm_reduce<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(part, n, tn, alpha,
                                                                   beta, x);
   } else {
@@ -303,7 +328,7 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
     if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for row norms");
     k_dgemm<TA, double, false, false, 4, 1, 1, 16, EPI_ROWNORM, false>
         <<<(unsigned)((int64_t)tm * tn), 256, 0, st>>>(n, k, d, A, Am.ld, B, k, tm, tn, d,
-                                                       part, n);
+                                                       part, n, 1.0, 0.0);
     k_rownorm_reduce<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(part, n, tn, alpha,
                                                                   beta, x);
   }

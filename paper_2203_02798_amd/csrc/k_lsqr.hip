@@ -13,9 +13,9 @@
 // bidiagonalisation share one pass over A.  An iteration is five kernels:
 //   pass   (1024 workgroups) per-workgroup partial A^T u and ||u||^2;
 //   reduce (d/64 x 16)       first level of the partial sums;
-//   vnew   (d/16)            t = A^T u / beta, vnew = R^{-T} t - beta v;
+//   vnew   (d/8)             t = A^T u / beta, vnew = R^{-T} t - beta v;
 //   update (1 workgroup)     scalar recurrences, v, w, y, stopping test;
-//   vhat   (d/16)            vhat = R^{-1} v for the next pass.
+//   vhat   (d/8)             vhat = R^{-1} v for the next pass.
 // All state stays on the device; a `done` flag set by the stopping test turns
 // the remaining enqueued iterations into no-ops, so the host synchronises
 // only every `check_every` iterations.  Every sum has a fixed order (CSR rows
@@ -234,7 +234,12 @@ __global__ __launch_bounds__(256) void k_reduce1(const double *__restrict__ part
     part2[(int64_t)g * d + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
-// beta = ||u||, t = (A^T u) / beta, vnew_j = sum_{i<=j} Rinv[i][j] t_i - beta v_j
+// beta = ||u||, t = (A^T u) / beta, vnew_j = sum_{i<=j} Rinv[i][j] t_i - beta v_j.
+// A workgroup owns 8 columns; its 256 threads split the i range into 32
+// phases (four independent accumulators each), combined in a fixed order.
+constexpr int kColsPerBlk = 8;
+constexpr int kPhases = 32;
+
 __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
                                               const double *__restrict__ part_b2,
                                               const double *__restrict__ Rinv, int64_t d,
@@ -245,7 +250,7 @@ __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
   if (!init && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *tvs = reinterpret_cast<double *>(smem_raw);  // d doubles
-  __shared__ double red[16][17];
+  __shared__ double red[kPhases][kColsPerBlk + 1];
   __shared__ double bred[4];
   const int tid = threadIdx.x;
   // beta from the kPassBlocks partial squares (same fixed order in every block)
@@ -256,8 +261,8 @@ __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
   __syncthreads();
   const double beta = sqrt(((bred[0] + bred[1]) + bred[2]) + bred[3]);
   const double binv = beta > 0.0 ? 1.0 / beta : 0.0;
-  const int64_t j0 = (int64_t)blockIdx.x * 16;
-  int64_t ilim = j0 + 16;
+  const int64_t j0 = (int64_t)blockIdx.x * kColsPerBlk;
+  int64_t ilim = j0 + kColsPerBlk;
   if (ilim > d) ilim = d;
   for (int64_t i = tid; i < ilim; i += 256) {
     double t = 0.0;
@@ -266,28 +271,36 @@ __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
     tvs[i] = t * binv;
   }
   __syncthreads();
-  const int g = tid >> 4;
-  const int c = tid & 15;
+  const int g = tid >> 3;
+  const int c = tid & 7;
   const int64_t j = j0 + c;
-  double acc = 0.0;
-  if (j < d)
-    for (int64_t i = g; i <= j; i += 16) acc += Rinv[i * d + j] * tvs[i];
-  red[g][c] = acc;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (j < d) {
+    int64_t i = g;
+    for (; i + 3 * kPhases <= j; i += 4 * kPhases) {
+      a0 += Rinv[i * d + j] * tvs[i];
+      a1 += Rinv[(i + kPhases) * d + j] * tvs[i + kPhases];
+      a2 += Rinv[(i + 2 * kPhases) * d + j] * tvs[i + 2 * kPhases];
+      a3 += Rinv[(i + 3 * kPhases) * d + j] * tvs[i + 3 * kPhases];
+    }
+    for (; i <= j; i += kPhases) a0 += Rinv[i * d + j] * tvs[i];
+  }
+  red[g][c] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  if (tid < 16) {
+  if (tid < kColsPerBlk) {
     double sj = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) sj += red[q][tid];
+    for (int q = 0; q < kPhases; ++q) sj += red[q][tid];
     const int64_t jj = j0 + tid;
     double val = 0.0;
     if (jj < d) {
       val = init ? sj : sj - beta * v[jj];
       vnew[jj] = val;
     }
-    double a2 = val * val;
+    double a2s = val * val;
 #pragma unroll
-    for (int off = 8; off > 0; off >>= 1) a2 += __shfl_xor(a2, off, 64);
-    if (tid == 0) part_a2[blockIdx.x] = a2;
+    for (int off = 4; off > 0; off >>= 1) a2s += __shfl_xor(a2s, off, 64);
+    if (tid == 0) part_a2[blockIdx.x] = a2s;
   }
   if (blockIdx.x == 0 && tid == 0) st->beta_new = beta;
 }
@@ -371,30 +384,38 @@ __global__ __launch_bounds__(256) void k_update(LsqrState *__restrict__ st, int6
   }
 }
 
-// out_i = (accumulate ? out_i : 0) + sum_{j>=i} Rinv[i][j] vec_j; 16 rows per block
+// out_i = (accumulate ? out_i : 0) + sum_{j>=i} Rinv[i][j] vec_j; a workgroup
+// owns 8 rows, 32 column phases per row (four accumulators each)
 __global__ __launch_bounds__(256) void k_trmv(const double *__restrict__ Rinv, int64_t d,
                                               const double *__restrict__ vec,
                                               double *__restrict__ out,
                                               const LsqrState *__restrict__ st,
                                               int check_done, int accumulate) {
   if (check_done && st->done) return;
-  __shared__ double red[16][17];
+  __shared__ double red[kColsPerBlk][kPhases + 1];
   const int tid = threadIdx.x;
-  const int c = tid >> 4;  // row within the block
-  const int g = tid & 15;  // column phase
-  const int64_t i = (int64_t)blockIdx.x * 16 + c;
-  double s = 0.0;
+  const int c = tid >> 5;  // row within the block
+  const int g = tid & 31;  // column phase
+  const int64_t i = (int64_t)blockIdx.x * kColsPerBlk + c;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (i < d) {
-    const int64_t jstart = i + ((g - (i & 15)) & 15);  // first j >= i with j = g mod 16
-    for (int64_t j = jstart; j < d; j += 16) s += Rinv[i * d + j] * vec[j];
+    int64_t jj = i + ((g - (i & 31)) & 31);  // first j >= i with j = g mod 32
+    const double *row = Rinv + i * d;
+    for (; jj + 3 * kPhases < d; jj += 4 * kPhases) {
+      a0 += row[jj] * vec[jj];
+      a1 += row[jj + kPhases] * vec[jj + kPhases];
+      a2 += row[jj + 2 * kPhases] * vec[jj + 2 * kPhases];
+      a3 += row[jj + 3 * kPhases] * vec[jj + 3 * kPhases];
+    }
+    for (; jj < d; jj += kPhases) a0 += row[jj] * vec[jj];
   }
-  red[c][g] = s;
+  red[c][g] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  if (tid < 16) {
-    const int64_t ii = (int64_t)blockIdx.x * 16 + tid;
+  if (tid < kColsPerBlk) {
+    const int64_t ii = (int64_t)blockIdx.x * kColsPerBlk + tid;
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) t += red[tid][q];
+    for (int q = 0; q < kPhases; ++q) t += red[tid][q];
     if (ii < d) out[ii] = accumulate ? out[ii] + t : t;
   }
 }
@@ -483,7 +504,7 @@ void launch_pass(const psk_mat &A, bool init, const LsqBufs &B, const double *rh
 void one_step(const psk_mat &A, bool init, const LsqBufs &B, const double *Rinv,
               const double *rhs, const psk_lsq_opts &o, hipStream_t s) {
   const int64_t d = A.d;
-  const unsigned nb16 = (unsigned)ceil_div(d, 16);
+  const unsigned nb16 = (unsigned)ceil_div(d, kColsPerBlk);
   {
     KTimer t("lsqr_pass", s);
     if (A.dtype == PSK_F64)
@@ -516,7 +537,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   B.part2 = ws.take<double>((size_t)kRedGroups * d);
   B.part_b2 = ws.take<double>(kPassBlocks);
   B.vnew = ws.take<double>((size_t)d);
-  B.part_a2 = ws.take<double>((size_t)ceil_div(d, 16));
+  B.part_a2 = ws.take<double>((size_t)ceil_div(d, kColsPerBlk));
   B.v = ws.take<double>((size_t)d);
   B.w = ws.take<double>((size_t)d);
   B.y = ws.take<double>((size_t)d);
@@ -546,7 +567,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   }
 
   const unsigned db = (unsigned)ceil_div(d, 256);
-  const unsigned nb16 = (unsigned)ceil_div(d, 16);
+  const unsigned nb16 = (unsigned)ceil_div(d, kColsPerBlk);
   k_zero<<<db, 256, 0, st>>>(x, d);
   int total_iters = 0;
   bool converged = true;

@@ -428,28 +428,22 @@ int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
   return 0;
 }
 
-int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
-           uint32_t **perm, uint32_t **bptr) {
+int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
+               hipStream_t st, uint32_t **skeys, uint32_t **svals, uint32_t *ptr) {
   int bits = 0;
   while (bits < 32 && ((uint64_t)1 << bits) < (uint64_t)r) ++bits;
   const int passes = (bits + 7) / 8;
   const int64_t ntiles = ceil_div(n, kSortTile);
   const int64_t L = (int64_t)kRadix * ntiles;
-  uint32_t *k0 = ws.take<uint32_t>(n);
-  uint32_t *v0 = ws.take<uint32_t>(n);
   uint32_t *k1 = passes ? ws.take<uint32_t>(n) : nullptr;
   uint32_t *v1 = passes ? ws.take<uint32_t>(n) : nullptr;
   uint32_t *hist = passes ? ws.take<uint32_t>(L) : nullptr;
   uint32_t *sums = nullptr;
   if (passes) scan_plan(L, ws, &sums);
-  uint32_t *bp = ws.take<uint32_t>((size_t)r + 1);
   if (ws.dry()) return 0;
-  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for CountSketch binning");
-
-  KTimer timer("cs_bin", st);
-  k_hash_keys<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, r, seed, k0, v0);
-  uint32_t *kin = k0, *vin = v0, *kout = k1, *vout = v1;
-  for (int p = 0; p < passes; ++p) {
+  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for a radix sort");
+  uint32_t *kin = keys, *vin = vals, *kout = k1, *vout = v1;
+  for (int p = 0; p < passes && n > 0; ++p) {
     const int shift = 8 * p;
     const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
     const uint32_t mask = (1u << nb) - 1u;
@@ -462,12 +456,29 @@ int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
     t = kin; kin = kout; kout = t;
     t = vin; vin = vout; vout = t;
   }
-  if (passes)
-    k_bucket_ptr<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(kin, n, r, bp);
-  else
-    k_fill_identity_ptr<<<1, 1, 0, st>>>(bp, n);
+  if (ptr) {
+    if (passes)
+      k_bucket_ptr<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(kin, n, r, ptr);
+    else
+      k_fill_identity_ptr<<<1, 1, 0, st>>>(ptr, n);
+  }
   PSK_HIP_TRY(hipGetLastError());
-  *perm = vin;
+  *skeys = kin;
+  *svals = vin;
+  return 0;
+}
+
+int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
+           uint32_t **perm, uint32_t **bptr) {
+  uint32_t *k0 = ws.take<uint32_t>(n);
+  uint32_t *v0 = ws.take<uint32_t>(n);
+  uint32_t *bp = ws.take<uint32_t>((size_t)r + 1);
+  KTimer timer("cs_bin", st, !ws.dry());
+  if (!ws.dry())
+    k_hash_keys<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, r, seed, k0, v0);
+  uint32_t *sk = nullptr;
+  int rc = sort_pairs(k0, v0, n, r, ws, st, &sk, perm, bp);
+  if (rc) return rc;
   *bptr = bp;
   return 0;
 }
