@@ -94,7 +94,10 @@ enum {
   PSK_PREC_F64 = 0,   /* G and S*A in FP64, FP64 MFMA, FP64 accumulation      */
   PSK_PREC_BF16 = 1   /* G rounded to bfloat16, S*A split into two bfloat16   *
                        * limbs (hi + lo), BF16 MFMA with FP32 accumulation,   *
-                       * FP64 reduction of the K-split partial products        */
+                       * FP64 reduction of the K-split partial products.      *
+                       * The normals are evaluated in FP32 (a few ulps from   *
+                       * the FP64 ones) before the RNE rounding; entries of   *
+                       * S*A must lie in the bfloat16 range.                  */
 };
 
 /* ---- operations for psk_workspace_size --------------------------------- */

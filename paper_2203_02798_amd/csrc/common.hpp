@@ -152,23 +152,53 @@ __host__ __device__ __forceinline__ void gauss4_f64(uint64_t q, uint32_t a, uint
   z[3] = r2 * s3;
 }
 
-// Same normals computed in FP32 (for the reduced-precision GEMM, where the
-// values are rounded to bfloat16 afterwards).  Uniforms keep the top 24 bits
-// of each word: u = (floor(x / 2^8) + 1/2) * 2^-24.
+// sin(2 pi u) and cos(2 pi u) in FP32 for u in [0, 1]: u = k/4 + y with
+// |y| <= 1/8 (exact split), Taylor series in y of sin(2 pi y) to y^9 and of
+// cos(2 pi y) to y^10 (truncation below 2e-9), quarter turn k mod 4.
+__device__ __forceinline__ void sincos_turns_f32(float u, float &sn, float &cs) {
+  const float k = rintf(4.0f * u);
+  const float y = fmaf(-0.25f, k, u);
+  const float y2 = y * y;
+  float ps = 42.058693944897634f;
+  ps = fmaf(ps, y2, -76.70585975306136f);
+  ps = fmaf(ps, y2, 81.60524927607504f);
+  ps = fmaf(ps, y2, -41.341702240399755f);
+  ps = fmaf(ps, y2, 6.283185307179586f);
+  const float sp = ps * y;
+  float pc = -26.426256783374388f;
+  pc = fmaf(pc, y2, 60.24464137187664f);
+  pc = fmaf(pc, y2, -85.45681720669371f);
+  pc = fmaf(pc, y2, 64.93939402266828f);
+  pc = fmaf(pc, y2, -19.739208802178716f);
+  const float cp = fmaf(pc, y2, 1.0f);
+  const int q = ((int)k) & 3;
+  const float a = (q & 1) ? cp : sp;
+  const float b = (q & 1) ? sp : cp;
+  sn = (q & 2) ? -a : a;
+  cs = ((q + 1) & 2) ? -b : b;
+}
+
+// The same four normals as gauss4_f64 evaluated in FP32 (for the bfloat16
+// GEMM, which rounds them to 8 significant bits afterwards): u = x 2^-32 +
+// 2^-33 in FP32 (exact for small x, so the tail is kept), ln u through the
+// hardware base-2 logarithm, sin/cos by sincos_turns_f32.  Error a few FP32
+// ulps against the FP64 values.
 __device__ __forceinline__ void gauss4_f32(uint64_t q, uint32_t a, uint64_t seed,
                                            float z[4]) {
   const u32x4 x = philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), a, 1u,
                                 (uint32_t)seed, (uint32_t)(seed >> 32));
-  const float s = 5.9604644775390625e-08f;  // 2^-24
-  const float u0 = ((float)(x.x0 >> 8) + 0.5f) * s;
-  const float u1 = ((float)(x.x1 >> 8) + 0.5f) * s;
-  const float u2 = ((float)(x.x2 >> 8) + 0.5f) * s;
-  const float u3 = ((float)(x.x3 >> 8) + 0.5f) * s;
-  const float r0 = sqrtf(-2.0f * __logf(u0));
-  const float r2 = sqrtf(-2.0f * __logf(u2));
+  const float s = 2.3283064365386963e-10f;  // 2^-32
+  const float h = 1.1641532182693481e-10f;  // 2^-33
+  const float u0 = fmaf((float)x.x0, s, h);
+  const float u1 = fmaf((float)x.x1, s, h);
+  const float u2 = fmaf((float)x.x2, s, h);
+  const float u3 = fmaf((float)x.x3, s, h);
+  const float m2ln2 = -1.3862943611198906f;  // -2 ln 2
+  const float r0 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+  const float r2 = __builtin_amdgcn_sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
   float s1, c1, s3, c3;
-  sincospif(2.0f * u1, &s1, &c1);
-  sincospif(2.0f * u3, &s3, &c3);
+  sincos_turns_f32(u1, s1, c1);
+  sincos_turns_f32(u3, s3, c3);
   z[0] = r0 * c1;
   z[1] = r0 * s1;
   z[2] = r2 * c3;

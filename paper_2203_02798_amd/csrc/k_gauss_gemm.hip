@@ -204,8 +204,8 @@ __global__ __launch_bounds__(256) void k_reduce_splits(const double *__restrict_
 int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
                const void *SA, int sa_dtype, double *C, Arena &ws,
                hipStream_t st) {
-  if (prec != PSK_PREC_F64)
-    return fail(PSK_EDTYPE, "this build's Gaussian GEMM supports PSK_PREC_F64");
+  if (prec == PSK_PREC_BF16) return gauss_gemm_bf16(m, r, d, seed, SA, sa_dtype, C, ws, st);
+  if (prec != PSK_PREC_F64) return fail(PSK_EDTYPE, "unknown Gaussian GEMM precision");
   const int tiles_m = (int)ceil_div(m, kBM);
   const int tiles_n = (int)ceil_div(d, kBN);
   const int64_t tiles = (int64_t)tiles_m * tiles_n;

@@ -162,6 +162,62 @@ def test_sketch_gcs_deterministic(api):
 
 
 # ---------------------------------------------------------------------------
+# G*S*A with bfloat16 operands (FP32 accumulation, FP64 split-K reduction)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,n,d,m,r", [
+    ("dense", 20000, 50, 200, 2500),
+    ("dense", 6000, 130, 77, 3001),
+    ("dense", 3000, 600, 150, 1000),     # two 512-column tiles, ragged
+    ("dense", 500, 3, 5, 7),             # one partial 32-bucket chunk
+    ("csr", 100000, 500, 300, 25000),
+    ("dense32", 8000, 96, 129, 1024)])
+def test_sketch_gcs_bf16(api, kind, n, d, m, r):
+    _say(f"sketch_gcs bf16 {kind} n={n} d={d} m={m} r={r}")
+    if kind == "csr":
+        a = synth.csr_uniform(n, d, 1e-3, seed=1)
+    elif kind == "dense32":
+        a = synth.dense_gaussian(n, d, seed=1, dtype=np.float32)
+    else:
+        a = synth.dense_gaussian(n, d, seed=1)
+    c = api.sketch_gcs(to_device(a), m, r, seed=21, prec="bf16").cpu().numpy()
+    # kernel arithmetic: against the exact product of the rounded operands
+    e_arith = rel_fro(c, osk.sketch_gcs_bf16_reference(a, m, r, 21))
+    # format loss: against the FP64 sketch
+    e_fmt = rel_fro(c, osk.sketch_gcs(a, m, r, 21))
+    _say(f"  vs quantised reference {e_arith:.3e}, vs FP64 {e_fmt:.3e}")
+    assert e_arith <= 1e-4
+    assert e_fmt <= 1e-2
+
+
+def test_sketch_gcs_bf16_deterministic(api):
+    a = to_device(synth.csr_uniform(50000, 200, 5e-3, seed=3))
+    c1 = api.sketch_gcs(a, 150, 8000, seed=5, prec="bf16")
+    c2 = api.sketch_gcs(a, 150, 8000, seed=5, prec="bf16")
+    assert torch.equal(c1, c2)
+
+
+@pytest.mark.parametrize("kind,cond", [("dense", 1e6), ("csr", 1e2)])
+def test_lsq_solve_bf16_sketch(api, kind, cond):
+    # LSQR and the refinement run in FP64 whatever the sketch precision: the
+    # solution meets the same tolerances as with the FP64 sketch
+    n, d = 20000, 32
+    if kind == "csr":
+        a = synth.csr_uniform(n, d, 0.2, seed=2)
+        xt = np.random.default_rng(0).standard_normal(d)
+        b = a @ xt + 1e-3 * np.random.default_rng(1).standard_normal(n)
+    else:
+        a, b, _ = synth.lsq_problem(n, d, cond, seed=2)
+    x, info = api.lsq_solve(to_device(a), torch.from_numpy(b).cuda(), m=4 * d, r=d * d,
+                            seed=3, prec="bf16")
+    _say(f"lsq bf16 {kind} cond={cond}: {info}")
+    rs, _ = olsq.lsq_quality(a, b, olsq.lstsq(a, b))
+    rn, ne = olsq.lsq_quality(a, b, x.cpu().numpy())
+    assert (rn - rs) / rs <= 1e-10
+    assert ne <= 1e-10
+    assert info["status"] == "PSK_OK"
+
+
+# ---------------------------------------------------------------------------
 # Gram
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind,n,d", [("dense", 20000, 50), ("dense", 3001, 130),
