@@ -14,9 +14,11 @@ Gaussian with m = 2,000 rows):
 
 Inputs are synthetic and seeded (the paper's matrices are random with
 unstated distributions) and are resident in HBM before timing starts.
-Prints ONE JSON line.  ``value`` is GB/s of A through the whole step
-(bytes of A = values + column indices + row pointers, per step, divided by
-the step time).  The dominant kernel (the Gaussian GEMM) is timed with HIP
+Both the FP64 plain path and the path with the BF16 Gaussian GEMM are timed
+(``--prec both``, the default); the BF16 path is the headline and the FP64
+path is reported beside it.  Prints ONE JSON line.  ``value`` is GB/s of A
+through the whole step (bytes of A = values + column indices + row
+pointers, per step, divided by the step time).  The dominant kernel (the Gaussian GEMM) is timed with HIP
 events on its own stream inside the library and reported as a roofline
 fraction; the CPU oracle is timed on a bounded sample on the host.
 """
@@ -41,6 +43,31 @@ WORKLOADS = {
 }
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
+
+# HBM bytes per launch of the Gaussian GEMM from hardware counters
+# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors measured on a copy
+# kernel of known size), valid only for the kernel source they were taken
+# on: the figure is dropped (null) as soon as the source hash differs.
+PMC_TRAFFIC = {
+    ("csr-1e6x500", "bf16"): {
+        "source": "paper_2203_02798_amd/csrc/k_gauss_gemm_bf16.hip",
+        "sha256_prefix": "090bc4cedb4a449b",
+        "fetch_kib": 250149.2, "write_kib": 125122.6,
+        "fetch_scale": 2.000, "write_scale": 1.000,
+        "profile": "profiles/gauss_gemm_bf16_csr-1e6x500_pmc.md",
+    },
+}
+
+
+def pmc_traffic(workload, prec):
+    import hashlib
+    t = PMC_TRAFFIC.get((workload, prec))
+    if t is None:
+        return None
+    with open(os.path.join(HERE, t["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha256_prefix"]:
+            return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
 
 
 def log(msg):
@@ -126,9 +153,15 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="csr-1e6x500", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="f64", choices=["f64", "bf16"])
+    ap.add_argument("--prec", default="both", choices=["f64", "bf16", "both"],
+                    help="Gaussian GEMM precision; 'both' times the FP64 plain path "
+                         "and the BF16 path and reports BF16 as the headline")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark, run 4 elementwise copies of MIB "
+                         "MiB (FP64) whose HBM bytes are known, to scale hardware "
+                         "FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -137,6 +170,17 @@ def main():
 
     import torch
     from paper_2203_02798_amd import api
+
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": nb, "bytes_written": nb,
+                                               "launches": 4}}), flush=True)
+        return
 
     log(f"generating workload {args.workload}")
     kind, a, b, r, m = make_inputs(args.workload)
@@ -153,74 +197,103 @@ def main():
 
     seed = args.seed
 
-    def step():
-        C = api.sketch_gcs(A, m, r, seed, prec=args.prec)
-        Gm = api.gram(A)
-        R, Ri = api.sketch_qr(C)
-        th = api.rownorms_sq(A, Ri)
-        x, info = api.lsq_solve(A, bd, Rinv=Ri, max_iter=200, refine=1, check_every=8)
-        return C, Gm, th, x, info
+    def run_path(prec):
+        def step():
+            C = api.sketch_gcs(A, m, r, seed, prec=prec)
+            Gm = api.gram(A)
+            R, Ri = api.sketch_qr(C)
+            th = api.rownorms_sq(A, Ri)
+            x, info = api.lsq_solve(A, bd, Rinv=Ri, max_iter=200, refine=1, check_every=8)
+            return C, Gm, th, x, info
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        out = step()
-    torch.cuda.synchronize()
-    log(f"timing {args.steps} steps")
-    lat = []
-    stream = torch.cuda.current_stream(dev)
-    with api.kernel_timing() as kt:
-        torch.cuda.synchronize()
-        t_start = time.perf_counter()
-        for _ in range(args.steps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
+        log(f"[{prec}] warmup {args.warmup}")
+        for _ in range(args.warmup):
             out = step()
-            e1.record(stream)
-            e1.synchronize()
-            lat.append(e0.elapsed_time(e1))
         torch.cuda.synchronize()
-        t_total = time.perf_counter() - t_start
-        stats = kt.stats()
-    info = out[4]
-    ms_step = 1e3 * t_total / args.steps
-    lat = np.array(lat)
-    per = {k: v[0] / args.steps for k, v in stats.items()}
-    gg_ms, gg_n = stats.get("gauss_gemm", (0.0, 0))
-    gg_avg = gg_ms / max(gg_n, 1)
+        log(f"[{prec}] timing {args.steps} steps")
+        lat = []
+        stream = torch.cuda.current_stream(dev)
+        with api.kernel_timing() as kt:
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            for _ in range(args.steps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                out = step()
+                e1.record(stream)
+                e1.synchronize()
+                lat.append(e0.elapsed_time(e1))
+            torch.cuda.synchronize()
+            t_total = time.perf_counter() - t_start
+            stats = kt.stats()
+        info = out[4]
+        lat = np.array(lat)
+        per = {k: v[0] / args.steps for k, v in stats.items()}
+        gg_ms, gg_n = stats.get("gauss_gemm", (0.0, 0))
+        sketch_ms = sum(per.get(k, 0.0) for k in ("cs_bin", "cs_scatter", "sa_limbs",
+                                                   "gauss_gemm", "gemm_reduce"))
+        # residual of the returned solution, for the FP64-vs-BF16 comparison
+        x = out[3].cpu().numpy()
+        res = float(np.linalg.norm(b - a @ x))
+        return {
+            "value": nbytes * args.steps / t_total / 1e9,
+            "ms_per_step": 1e3 * t_total / args.steps,
+            "solves_per_s": args.steps / t_total,
+            "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)),
+            "sketch_gcs_gbs": nbytes / (sketch_ms * 1e-3) / 1e9 if sketch_ms > 0 else None,
+            "stage_ms": {k: round(v, 4) for k, v in sorted(per.items())},
+            "lsq": {"iters": info["iters"], "status": info["status"], "resid": res},
+            "gg_avg_ms": gg_ms / max(gg_n, 1),
+        }
+
+    paths = [args.prec] if args.prec != "both" else ["f64", "bf16"]
+    res = {p: run_path(p) for p in paths}
+    head = "bf16" if "bf16" in res else paths[0]
+    hr = res[head]
     flops = (2.0 * r - 1.0) * m * d
-    peak = PEAK_FP64_TFLOPS if args.prec == "f64" else PEAK_BF16_TFLOPS
+    peak = PEAK_FP64_TFLOPS if head == "f64" else PEAK_BF16_TFLOPS
+    gg_avg = hr["gg_avg_ms"]
     achieved = flops / (gg_avg * 1e-3) / 1e12 if gg_avg > 0 else 0.0
-    sketch_ms = sum(per.get(k, 0.0) for k in ("cs_bin", "cs_scatter", "gauss_gemm",
-                                               "gemm_reduce"))
     rec = {
         "metric": "GB/s of A sketched (G·S·A) + LSQ solves/s, p50/p99 latency vs FP64 plain path",
-        "value": nbytes * args.steps / t_total / 1e9,
+        "value": hr["value"],
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": hr["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "f64" else "bf16",
+        "dtype": head,
+        "dtype_detail": ("Gaussian GEMM bf16 operands with fp32 accumulation; hash, "
+                         "S*A, Gram, QR, row norms and LSQR in f64") if head == "bf16"
+                        else "f64 throughout",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d,
                    "nnz": int(a.nnz) if kind == "csr" else n * d,
                    "density": WORKLOADS[args.workload][3], "r": r, "m": m,
                    "a_bytes": nbytes, "parallelism": "single-gpu"},
-        "solves_per_s": args.steps / t_total,
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "sketch_gcs_gbs": nbytes / (sketch_ms * 1e-3) / 1e9 if sketch_ms > 0 else None,
-        "stage_ms": {k: round(v, 4) for k, v in sorted(per.items())},
-        "lsq": {"iters": info["iters"], "status": info["status"]},
+        "solves_per_s": hr["solves_per_s"],
+        "p50_ms": hr["p50_ms"],
+        "p99_ms": hr["p99_ms"],
+        "sketch_gcs_gbs": hr["sketch_gcs_gbs"],
+        "stage_ms": hr["stage_ms"],
+        "lsq": hr["lsq"],
         "roofline": {"bound": "mfma", "kernel": "gauss_gemm", "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "launch_ms": gg_avg,
+                     "traffic": pmc_traffic(args.workload, head), "traffic_unit": "bytes per launch",
+                     "launch_ms": gg_avg,
                      "flops_per_launch": flops},
     }
+    if head != "f64" and "f64" in res:
+        f = res["f64"]
+        rec["fp64_path"] = {k: f[k] for k in ("value", "ms_per_step", "solves_per_s",
+                                             "p50_ms", "p99_ms", "sketch_gcs_gbs",
+                                             "stage_ms", "lsq")}
+        rec["speedup_vs_fp64_path"] = f["ms_per_step"] / hr["ms_per_step"]
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         tot, cores, sample, parts = cpu_baseline(kind, a, b, r, m, seed)

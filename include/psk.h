@@ -32,8 +32,14 @@
  *   has been enqueued (argument checks happen first) unless the status is
  *   PSK_EDEVICE.  psk_last_error() gives a message for the calling thread.
  * - Results are deterministic: identical inputs give bit-identical outputs,
- *   independent of other work on the device (no floating-point atomics; all
- *   reduction orders are fixed by the shapes).
+ *   independent of other work on the device.  No floating-point atomic
+ *   touches global memory; reduction orders across workgroups and K splits
+ *   are fixed by the shapes.  Inside one wavefront, CSR kernels add into a
+ *   private LDS row (ds_add): the instruction order is fixed, and when
+ *   several lanes of one instruction hit the same address (duplicate column
+ *   indices, or short rows handled one per lane) the LDS unit applies them
+ *   in its fixed lane order, which is repeatable on this hardware but not
+ *   an ISA guarantee.
  * - Random quantities are pure functions of (seed, index) through
  *   Philox4x32-10 (Salmon et al., SC'11):
  *     hash of row i:   x = Philox(ctr=(i lo32, i hi32, 0, 0), key=(seed lo32, seed hi32)),

@@ -10,7 +10,6 @@ import tempfile
 import numpy as np
 import pytest
 
-from oracle import philox as oph
 from oracle import sketch as osk
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))

@@ -183,3 +183,47 @@ def test_bf16_limbs_refine():
     e1 = np.abs(x - l[0]).max() / np.abs(x).max()
     e2 = np.abs(x - l[0] - l[1]).max() / np.abs(x).max()
     assert e1 < 2 ** -8 and e2 < 2 ** -15
+
+
+def test_bf16_of_doubles_is_nearest_even():
+    # FP64 inputs that are not FP32 values: the result must be the nearest
+    # bfloat16 neighbour (ties to the even significand), checked against the
+    # two neighbours enumerated from the bfloat16 bit patterns.
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(5000) * 10.0 ** rng.integers(-20, 20, 5000)
+    # exact ties between neighbours, and values one FP64 ulp off a tie
+    base = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    ulp = np.ldexp(1.0, np.frexp(np.abs(base))[1] - 8)
+    ties = base + 0.5 * ulp
+    x = np.concatenate([x, ties, np.nextafter(ties, np.inf), np.nextafter(ties, -np.inf)])
+    y = osk.to_bf16(x)
+    bits = torch.from_numpy(np.abs(x).astype(np.float32)).to(torch.bfloat16).view(torch.int16)
+    bits = bits.numpy().astype(np.int64)
+    cands = []
+    for db in (-1, 0, 1):
+        c = torch.from_numpy((bits + db).astype(np.int16)).view(torch.bfloat16)
+        cands.append(c.to(torch.float64).numpy())
+    cands = np.stack(cands) * np.sign(x)[None, :]
+    dist = np.abs(cands - x[None, :])
+    best = dist.min(axis=0)
+    assert np.all(np.abs(y - x) == best)
+    # among equidistant candidates the chosen one has an even last bit
+    yb = torch.from_numpy(np.abs(y).astype(np.float32)).to(torch.bfloat16).view(torch.int16)
+    tie = (dist == best[None, :]).sum(axis=0) > 1
+    assert np.all((yb.numpy()[tie] & 1) == 0)
+
+
+def test_bf16_reference_within_rounding_bound():
+    # |bf16(z) - z| <= 2^-8 |z| and |hi + lo - sa| <= 2^-16 |sa| (RNE with 8
+    # significant bits), so the quantised product differs from the FP64 one
+    # by at most (2^-8 + 2^-16 + 2^-24) (|Z| |SA|) / sqrt(m) per entry.
+    a = synth.dense_gaussian(3000, 20, seed=4)
+    m, r, seed = 40, 500, 6
+    cq = osk.sketch_gcs_bf16_reference(a, m, r, seed)
+    c = osk.sketch_gcs(a, m, r, seed)
+    mag = np.abs(osk.gaussian_normals(m, 0, r, seed)) @ np.abs(osk.sketch_cs(a, r, seed))
+    bound = mag * (2.0 ** -8 + 2.0 ** -16 + 2.0 ** -24 + 1e-13) / np.sqrt(m)
+    assert np.all(np.abs(cq - c) <= bound)
+    rel = np.linalg.norm(cq - c) / np.linalg.norm(c)
+    assert 1e-4 < rel < 1e-2
