@@ -13,16 +13,15 @@
 // the first pass keeps the Cholesky factorization defined for condition
 // numbers up to about 1/u, and two unshifted passes restore orthogonality.
 //
-// The d x d Cholesky is blocked (64 columns): a one-workgroup kernel factors
-// the diagonal block in LDS and inverts it, then two GEMMs form the block
-// row of R and update the trailing matrix.  R^{-1} is assembled by block
-// columns: X[0:j, j] = -X[0:j, 0:j] R[0:j, j] X[j, j].
+// The d x d Cholesky and the inverse of its factor are blocked by 64 columns
+// with one launch per block step (k_chol_step, below): the panel, the
+// trailing update, one block column of R^{-1} and the factorization of the
+// next diagonal block all happen in the same launch, so a pass costs
+// ceil(d/64) + 1 launches besides its two GEMMs with C.
 #include "internal.hpp"
 
 namespace psk {
 namespace {
-
-constexpr int kNB = 64;
 
 __global__ void k_fill(double *__restrict__ p, int64_t count, double v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,81 +41,299 @@ __global__ __launch_bounds__(256) void k_shift_diag(double *__restrict__ W, int6
   for (int64_t i = threadIdx.x; i < d; i += 256) W[i * d + i] += coef * tr;
 }
 
-// Upper Cholesky U^T U = W[j0:j0+nb, j0:j0+nb] and its inverse by one
-// wavefront: lane j keeps column j of the block in registers; each step
-// publishes one row through a 64-entry LDS buffer that every lane reads with
-// broadcast loads (no barriers beyond the wavefront).  Rows stay unscaled
-// during elimination (step k subtracts U[k][i] U[k][j] / U[k][k]) and are
-// scaled by 1/sqrt(U[k][k]) at the end.  A block narrower than 64 is padded
-// with the identity.  The inverse is back substitution on each column:
-// x_i = (e_j[i] - sum_{k>i} U[i][k] x_k) / U[i][i].
+// ---------------------------------------------------------------------------
+// Blocked Cholesky W = R^T R with X = R^{-1}, 64-column blocks, one kernel
+// launch per block step.  Step j (k_chol_step) runs one 256-thread workgroup
+// per 64 x 64 tile of work:
+//   panel    R[j, J]  = X_jj^T W[j, J]                       (J > j)
+//   trailing W[I, J] -= P_I^T P_J,  P_K = X_jj^T W[j, K]     (j < I <= J)
+//   inverse  X[I, j]  = -(X[I, I:j] R[I:j, j]) X_jj          (I < j)
+// and the workgroup that owns the next diagonal tile (j+1, j+1), whose update
+// is the last one it receives, factors it in the same launch (wavefront 0:
+// Cholesky and triangular inverse of the 64 x 64 block), so the next step
+// finds R_{j+1,j+1} and X_{j+1,j+1} ready.  Block 0 is factored by
+// k_chol_first.  W is read in its upper block triangle and destroyed.
+// ---------------------------------------------------------------------------
+constexpr int kLd = 68;      // LDS row stride of 64-wide tiles (doubles)
+constexpr int kUt = 66;      // LDS row stride of the transposed factor
+constexpr int kTh = 256;
+
+struct CholSmem {
+  double As[16 * kLd];
+  double Bs[16 * kLd];
+  double PI[64 * kLd];       // also the diagonal tile to factor
+  double PJ[64 * kLd];
+  double Ut[64 * kUt];       // Ut[l][k] = U[k][l]
+  double rowbuf[2][64];
+  double rinv[64];
+};
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
-__global__ __launch_bounds__(64) void k_potrf_block(const double *__restrict__ W,
-                                                    int64_t d, int64_t j0, int nb,
+// Wavefront 0 only.  T: the 64 x 64 tile in LDS (row-major, stride kLd), of
+// which the leading nb x nb block is used (the rest is taken as identity).
+// Right-looking Cholesky with lane l holding column l: step k reads the
+// pivot from lane k, scales row k (lane l's entry U[k][l]), publishes it
+// through LDS and applies the rank-1 update to its column.  Then lane l
+// solves U x = e_l column-wise (x_i = b_i / U_ii, b_k -= U[k][i] x_i for
+// k < i), reading column i of U contiguously from Ut.
+__device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int64_t j0,
+                            double *__restrict__ R, double *__restrict__ X,
+                            int *__restrict__ flag) {
+  const int l = threadIdx.x;
+  double c[64];
+#pragma clang loop unroll(full)
+  for (int i = 0; i < 64; ++i) {
+    const double v = S.PI[i * kLd + l];  // always inside the tile: no branch
+    c[i] = (i < nb && l < nb) ? v : (i == l ? 1.0 : 0.0);
+  }
+  bool bad = false;
+#pragma clang loop unroll(full)
+  for (int k = 0; k < 64; ++k) {
+    double piv = readlane_f64(c[k], k);
+    bad |= !(piv > 0.0);
+    piv = piv > 0.0 ? piv : 1.0;
+    const double rs = 1.0 / sqrt(piv);
+    const double u = (l >= k) ? c[k] * rs : 0.0;
+    double *rb = S.rowbuf[k & 1];
+    rb[l] = u;
+    S.Ut[l * kUt + k] = u;
+    S.rinv[k] = rs;  // the same value from every lane
+    wave_sync_lds();
+#pragma clang loop unroll(full)
+    for (int i = k + 1; i < 64; ++i) c[i] -= rb[i] * u;
+    // keep the scheduler from hoisting later steps' loads over this one
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  wave_sync_lds();
+  // R block (lower part of the block is zero: Ut[l][k] = 0 for l < k)
+#pragma clang loop unroll(full)
+  for (int k = 0; k < 64; ++k)
+    if (k < nb && l < nb) R[(j0 + k) * d + j0 + l] = S.Ut[l * kUt + k];
+  // X = U^{-1}, column l per lane
+  double b[64];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < 64; ++k) b[k] = (k == l) ? 1.0 : 0.0;
+#pragma clang loop unroll(full)
+  for (int i = 63; i >= 0; --i) {
+    const double xi = b[i] * S.rinv[i];
+    b[i] = xi;
+    const double *ucol = S.Ut + i * kUt;  // U[0..i-1][i]
+#pragma clang loop unroll(full)
+    for (int k = 0; k < i; ++k) b[k] -= ucol[k] * xi;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma clang loop unroll(full)
+  for (int k = 0; k < 64; ++k)
+    if (k < nb && l < nb) X[(j0 + k) * d + j0 + l] = b[k];
+  if (bad) atomicOr(flag, 1);
+}
+
+// acc (this thread's 4 x 4 of a 64 x 64 tile: rows 4*ty.., columns 4*tx..)
+// += op(A) op(B) over K, staged through LDS 16 k at a time with the next
+// chunk prefetched into registers.  fa(i, k) = op(A)[i][k], fb(k, j) =
+// op(B)[k][j]; both return 0 outside the operand.  KCONTIG_A tells which
+// index of A is contiguous in memory (coalesced staging).
+template <bool KCONTIG_A, class FA, class FB>
+__device__ __forceinline__ void tile_mm(double acc[4][4], FA fa, FB fb, int K, CholSmem &S) {
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  double pa[4], pb[4];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + kTh * e;  // 0..1023
+      int i, kk;
+      if (KCONTIG_A) { kk = idx & 15; i = idx >> 4; } else { i = idx & 63; kk = idx >> 6; }
+      pa[e] = (k0 + kk < K) ? fa(i, k0 + kk) : 0.0;
+      const int jj = idx & 63, kb = idx >> 6;
+      pb[e] = (k0 + kb < K) ? fb(k0 + kb, jj) : 0.0;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + kTh * e;
+      int i, kk;
+      if (KCONTIG_A) { kk = idx & 15; i = idx >> 4; } else { i = idx & 63; kk = idx >> 6; }
+      S.As[kk * kLd + i] = pa[e];
+      S.Bs[(idx >> 6) * kLd + (idx & 63)] = pb[e];
+    }
+    __syncthreads();
+    if (k0 + 16 < K) fetch(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const double4 a = *reinterpret_cast<const double4 *>(S.As + kk * kLd + 4 * ty);
+      const double4 bq = *reinterpret_cast<const double4 *>(S.Bs + kk * kLd + 4 * tx);
+      const double av[4] = {a.x, a.y, a.z, a.w};
+      const double bv[4] = {bq.x, bq.y, bq.z, bq.w};
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = fma(av[r], bv[q], acc[r][q]);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void zero_acc(double acc[4][4]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[r][q] = 0.0;
+}
+
+// acc -> LDS tile (row-major, stride kLd)
+__device__ __forceinline__ void acc_to_lds(const double acc[4][4], double *T) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    *reinterpret_cast<double4 *>(T + (4 * ty + r) * kLd + 4 * tx) =
+        double4{acc[r][0], acc[r][1], acc[r][2], acc[r][3]};
+}
+
+// P = X_jj^T W[j, K] (64 x 64) into the LDS tile P.
+__device__ __forceinline__ void panel_tile(const double *__restrict__ W, const double *__restrict__ X,
+                           int64_t d, int64_t j0, int nbj, int64_t c0, double *P,
+                           CholSmem &S) {
+  double acc[4][4];
+  zero_acc(acc);
+  // op(A)[i][k] = X[j0+k][j0+i] (i, k < nbj): contiguous in i
+  auto fa = [&](int i, int k) {
+    return (i < nbj && k < nbj) ? X[(j0 + k) * d + j0 + i] : 0.0;
+  };
+  auto fb = [&](int k, int jj) {
+    return (k < nbj && c0 + jj < d) ? W[(j0 + k) * d + c0 + jj] : 0.0;
+  };
+  tile_mm<false>(acc, fa, fb, nbj, S);
+  acc_to_lds(acc, P);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kTh) void k_chol_first(const double *__restrict__ W, int64_t d,
                                                     double *__restrict__ R,
                                                     double *__restrict__ X,
                                                     int *__restrict__ flag) {
-  __shared__ double rowbuf[kNB];
-  const int j = threadIdx.x;
-  double c[kNB];
-#pragma unroll
-  for (int i = 0; i < kNB; ++i)
-    c[i] = (i < nb && j < nb) ? W[(j0 + i) * d + j0 + j] : (i == j ? 1.0 : 0.0);
-  bool bad = false;
-  double mypiv = 1.0;  // this lane's pivot U[j][j] once step j is reached
-#pragma clang loop unroll(full)
-  for (int k = 0; k < kNB; ++k) {
-    rowbuf[j] = c[k];  // row k of the (unscaled) factor
-    wave_sync_lds();
-    double piv = rowbuf[k];
-    mypiv = (k == j) ? piv : mypiv;
-    bad |= !(piv > 0.0);
-    piv = piv > 0.0 ? piv : 1.0;
-    const double f = c[k] / piv;  // U[k][j] / U[k][k]
-#pragma clang loop unroll(full)
-    for (int i = k + 1; i < kNB; ++i) c[i] -= rowbuf[i] * f;
-    wave_sync_lds();
+  __shared__ CholSmem S;
+  const int nb = (int)(d < 64 ? d : 64);
+  for (int e = threadIdx.x; e < 64 * 64; e += kTh) {
+    const int i = e >> 6, jj = e & 63;
+    S.PI[i * kLd + jj] = (i < nb && jj < nb) ? W[(int64_t)i * d + jj] : 0.0;
   }
-  // scale row k by 1/sqrt(U[k][k]) (the diagonal entries sit in lane k)
-  rowbuf[j] = sqrt(mypiv > 0.0 ? mypiv : 1.0);
-  wave_sync_lds();
-#pragma unroll
-  for (int k = 0; k < kNB; ++k) {
-    const double v = (k <= j) ? c[k] / rowbuf[k] : 0.0;
-    if (k < nb && j < nb) R[(j0 + k) * d + j0 + j] = v;
-  }
-  if (bad && j == 0) atomicOr(flag, 1);
+  __syncthreads();
+  if (threadIdx.x < 64) factor_diag(S, nb, d, 0, R, X, flag);
 }
 
-// Inverse of the upper-triangular diagonal block R[j0:j0+nb, j0:j0+nb] into
-// the same block of X: lane j solves U x = e_j by back substitution,
-// x_i = (e_j[i] - sum_{k>i} U[i][k] x_k) / U[i][i], reading U from LDS
-// (broadcast loads).  Padding beyond nb is the identity.
-__global__ __launch_bounds__(64) void k_trinv_block(const double *__restrict__ R, int64_t d,
-                                                    int64_t j0, int nb,
-                                                    double *__restrict__ X) {
-  __shared__ double Ul[kNB][kNB + 1];
-  const int j = threadIdx.x;
+__global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64_t d,
+                                                   int nblk, int j,
+                                                   double *__restrict__ R,
+                                                   double *__restrict__ X,
+                                                   int *__restrict__ flag) {
+  __shared__ CholSmem S;
+  const int p = nblk - j - 1;
+  const int ntrail = p * (p + 1) / 2;
+  int t = blockIdx.x;
+  const int64_t j0 = (int64_t)j * 64;
+  const int nbj = (int)((d - j0) < 64 ? (d - j0) : 64);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  if (t < ntrail) {
+    // trailing tile (I, J), enumerated row by row of the upper block triangle
+    int I = j + 1, rem = t;
+    while (rem >= nblk - I) { rem -= nblk - I; ++I; }
+    const int J = I + rem;
+    const int64_t r0 = (int64_t)I * 64, c0 = (int64_t)J * 64;
+    panel_tile(W, X, d, j0, nbj, r0, S.PI, S);
+    if (J != I) panel_tile(W, X, d, j0, nbj, c0, S.PJ, S);
+    const double *PJ = (J != I) ? S.PJ : S.PI;
+    double acc[4][4];
+    zero_acc(acc);
+#pragma unroll 4
+    for (int k = 0; k < 64; ++k) {
+      const double4 a = *reinterpret_cast<const double4 *>(S.PI + k * kLd + 4 * ty);
+      const double4 bq = *reinterpret_cast<const double4 *>(PJ + k * kLd + 4 * tx);
+      const double av[4] = {a.x, a.y, a.z, a.w};
+      const double bv[4] = {bq.x, bq.y, bq.z, bq.w};
 #pragma unroll
-  for (int i = 0; i < kNB; ++i)
-    Ul[i][j] = (i < nb && j < nb) ? R[(j0 + i) * d + j0 + j] : (i == j ? 1.0 : 0.0);
-  wave_sync_lds();
-  double x[kNB];
-#pragma clang loop unroll(full)
-  for (int i = kNB - 1; i >= 0; --i) {
-    double s = (i == j) ? 1.0 : 0.0;
-#pragma clang loop unroll(full)
-    for (int k = i + 1; k < kNB; ++k) s -= Ul[i][k] * x[k];
-    x[i] = s / Ul[i][i];
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[r][q] = fma(av[r], bv[q], acc[r][q]);
+    }
+    if (I == j + 1 && J == j + 1) {
+      // the next diagonal tile: update in LDS and factor it here
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t gi = r0 + 4 * ty + r, gj = c0 + 4 * tx + q;
+          const double w = (gi < d && gj < d) ? W[gi * d + gj] : 0.0;
+          S.PI[(4 * ty + r) * kLd + 4 * tx + q] = w - acc[r][q];
+        }
+      __syncthreads();
+      const int nb1 = (int)((d - r0) < 64 ? (d - r0) : 64);
+      if (threadIdx.x < 64) factor_diag(S, nb1, d, r0, R, X, flag);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t gi = r0 + 4 * ty + r, gj = c0 + 4 * tx + q;
+          if (gi < d && gj < d) W[gi * d + gj] -= acc[r][q];
+        }
+    }
+    return;
   }
-  if (j < nb) {
+  t -= ntrail;
+  if (t < j) {
+    // inverse column tile X[I, j] = -(X[I, I:j] R[I:j, j]) X_jj
+    const int I = t;
+    const int64_t r0 = (int64_t)I * 64;
+    const int K = (int)(j0 - r0);
+    double acc[4][4];
+    zero_acc(acc);
+    auto fa = [&](int i, int k) { return X[(r0 + i) * d + r0 + k]; };          // in range
+    auto fb = [&](int k, int jj) { return jj < nbj ? R[(r0 + k) * d + j0 + jj] : 0.0; };
+    tile_mm<true>(acc, fa, fb, K, S);
+    acc_to_lds(acc, S.PI);
+    __syncthreads();
+    zero_acc(acc);
+    auto ga = [&](int i, int k) { return S.PI[i * kLd + k]; };
+    auto gb = [&](int k, int jj) {
+      return (k < nbj && jj < nbj) ? X[(j0 + k) * d + j0 + jj] : 0.0;
+    };
+    tile_mm<true>(acc, ga, gb, nbj, S);
 #pragma unroll
-    for (int i = 0; i < kNB; ++i)
-      if (i < nb) X[(j0 + i) * d + j0 + j] = (i <= j) ? x[i] : 0.0;
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gi = r0 + 4 * ty + r, gj = j0 + 4 * tx + q;
+        if (gj < d) X[gi * d + gj] = -acc[r][q];
+      }
+    return;
+  }
+  t -= j;
+  if (t < p) {
+    // panel tile R[j, J] = X_jj^T W[j, J]
+    const int64_t c0 = (int64_t)(j + 1 + t) * 64;
+    panel_tile(W, X, d, j0, nbj, c0, S.PI, S);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t gi = j0 + 4 * ty + r, gj = c0 + 4 * tx + q;
+        if (4 * ty + r < nbj && gj < d) R[gi * d + gj] = S.PI[(4 * ty + r) * kLd + 4 * tx + q];
+      }
   }
 }
 
@@ -124,42 +341,18 @@ void fill(double *p, int64_t count, double v, hipStream_t st) {
   k_fill<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(p, count, v);
 }
 
-// Upper Cholesky of W (destroyed) into R, and X = R^{-1}.  T is d x d scratch.
-int chol_inv(double *W, int64_t d, double *R, double *X, double *T, int *flag,
-             Arena &ws, hipStream_t st) {
-  const bool run = !ws.dry();
-  if (run) {
-    fill(R, d * d, 0.0, st);
-    fill(X, d * d, 0.0, st);
-  }
-  const size_t mk = ws.mark();
-  for (int64_t j0 = 0; j0 < d; j0 += kNB) {
-    const int nb = (int)((d - j0) < kNB ? (d - j0) : kNB);
-    if (run) {
-      k_potrf_block<<<1, 64, 0, st>>>(W, d, j0, nb, R, X, flag);
-      k_trinv_block<<<1, 64, 0, st>>>(R, d, j0, nb, X);
-    }
-    const int64_t rest = d - j0 - nb;
-    if (rest > 0) {
-      int rc = dgemm(true, false, nb, rest, nb, 1.0, X + j0 * d + j0, d,
-                     W + j0 * d + j0 + nb, d, 0.0, R + j0 * d + j0 + nb, d, ws, st);
-      ws.release(mk);
-      if (rc) return rc;
-      rc = dgemm(true, false, rest, rest, nb, -1.0, R + j0 * d + j0 + nb, d,
-                 R + j0 * d + j0 + nb, d, 1.0, W + (j0 + nb) * d + j0 + nb, d, ws, st);
-      ws.release(mk);
-      if (rc) return rc;
-    }
-  }
-  for (int64_t j0 = kNB; j0 < d; j0 += kNB) {
-    const int nb = (int)((d - j0) < kNB ? (d - j0) : kNB);
-    int rc = dgemm(false, false, j0, nb, j0, 1.0, X, d, R + j0, d, 0.0, T, d, ws, st);
-    ws.release(mk);
-    if (rc) return rc;
-    rc = dgemm(false, false, j0, nb, nb, -1.0, T, d, X + j0 * d + j0, d, 0.0, X + j0, d,
-               ws, st);
-    ws.release(mk);
-    if (rc) return rc;
+// Upper Cholesky of W (destroyed) into R, and X = R^{-1}.
+int chol_inv(double *W, int64_t d, double *R, double *X, int *flag, Arena &ws,
+             hipStream_t st) {
+  if (ws.dry()) return 0;
+  fill(R, d * d, 0.0, st);
+  fill(X, d * d, 0.0, st);
+  const int nblk = (int)ceil_div(d, 64);
+  k_chol_first<<<1, kTh, 0, st>>>(W, d, R, X, flag);
+  for (int j = 0; j < nblk; ++j) {
+    const int p = nblk - j - 1;
+    const int tiles = p * (p + 1) / 2 + j + p;
+    if (tiles > 0) k_chol_step<<<tiles, kTh, 0, st>>>(W, d, nblk, j, R, X, flag);
   }
   return 0;
 }
@@ -193,21 +386,21 @@ int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rin
   const double u = 1.1102230246251565e-16;
   const double coef = 11.0 * ((double)m * d + (double)d * (d + 1)) * u;
   if (run) k_shift_diag<<<1, 256, 0, st>>>(W, d, coef);
-  if ((rc = chol_inv(W, d, R1, X1, T, flag, ws, st))) return rc;
+  if ((rc = chol_inv(W, d, R1, X1, flag, ws, st))) return rc;
   ws.release(mk);
   if ((rc = dgemm(false, false, m, d, d, 1.0, C, d, X1, d, 0.0, Qa, d, ws, st))) return rc;
   ws.release(mk);
   // pass 2
   if ((rc = dgemm(true, false, d, d, m, 1.0, Qa, d, Qa, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
-  if ((rc = chol_inv(W, d, R2, X2, T, flag, ws, st))) return rc;
+  if ((rc = chol_inv(W, d, R2, X2, flag, ws, st))) return rc;
   ws.release(mk);
   if ((rc = dgemm(false, false, m, d, d, 1.0, Qa, d, X2, d, 0.0, Qb, d, ws, st))) return rc;
   ws.release(mk);
   // pass 3
   if ((rc = dgemm(true, false, d, d, m, 1.0, Qb, d, Qb, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
-  if ((rc = chol_inv(W, d, R3, X3, T, flag, ws, st))) return rc;
+  if ((rc = chol_inv(W, d, R3, X3, flag, ws, st))) return rc;
   ws.release(mk);
   // R = R3 R2 R1, R^{-1} = X1 X2 X3
   if ((rc = dgemm(false, false, d, d, d, 1.0, R2, d, R1, d, 0.0, T, d, ws, st))) return rc;

@@ -297,7 +297,9 @@ def test_rownorms_alpha_beta(api):
 # ---------------------------------------------------------------------------
 # QR of the sketch, leverage scores, least squares
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("m,d,cond", [(200, 50, 1e2), (1030, 257, 1e6), (96, 96, 1e3)])
+@pytest.mark.parametrize("m,d,cond", [(200, 50, 1e2), (1030, 257, 1e6), (96, 96, 1e3),
+                                     (40, 1, 1.0), (64, 64, 10.0), (2000, 500, 1e8),
+                                     (3000, 700, 1e4)])
 def test_sketch_qr(api, m, d, cond):
     _say(f"sketch_qr m={m} d={d} cond={cond}")
     c, _, _ = synth.lsq_problem(m, d, cond, seed=1, noise=0.0)
