@@ -224,8 +224,10 @@ __device__ __forceinline__ void panel_tile(const double *__restrict__ W, const d
 __global__ __launch_bounds__(kTh) void k_chol_first(const double *__restrict__ W, int64_t d,
                                                     double *__restrict__ R,
                                                     double *__restrict__ X,
-                                                    int *__restrict__ flag) {
+                                                    int *__restrict__ flag,
+                                                    const int *__restrict__ sel) {
   __shared__ CholSmem S;
+  if (sel && *sel != 0) return;  // the series path was selected
   const int nb = (int)(d < 64 ? d : 64);
   for (int e = threadIdx.x; e < 64 * 64; e += kTh) {
     const int i = e >> 6, jj = e & 63;
@@ -239,8 +241,10 @@ __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64
                                                    int nblk, int j,
                                                    double *__restrict__ R,
                                                    double *__restrict__ X,
-                                                   int *__restrict__ flag) {
+                                                   int *__restrict__ flag,
+                                                   const int *__restrict__ sel) {
   __shared__ CholSmem S;
+  if (sel && *sel != 0) return;  // the series path was selected
   const int p = nblk - j - 1;
   const int ntrail = p * (p + 1) / 2;
   int t = blockIdx.x;
@@ -337,24 +341,172 @@ __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64
   }
 }
 
+// ---------------------------------------------------------------------------
+// Cholesky factor and inverse of a near-identity W = I + E by matrix products
+// only (used for the second and third Cholesky-QR passes, whose Gram matrix
+// is the identity up to a small E when the previous pass was accurate).
+// With R = I + U (U upper triangular), R^T R = W reads U + U^T = E - U^T U,
+// so U = Phi(E - U^T U) where Phi keeps the strict upper triangle and half
+// the diagonal.  The fixed point iteration U_0 = Phi(E), U_{t+1} =
+// Phi(E - U_t^T U_t) gains a factor ~||E|| per step; X = R^{-1} is the
+// Neumann series I - U + U^2 - ..., evaluated as X_{t+1} = I - U X_t.  For
+// ||E||_F <= kSeriesTol = 1e-4 two steps of each leave errors below 1e-16.
+// The choice between this path and the blocked Cholesky is made on the
+// device (k_decide writes *sel), so no host synchronisation is needed: the
+// kernels of the path not taken return at once.
+// ---------------------------------------------------------------------------
+constexpr double kSeriesTol = 1e-4;
+constexpr int kParts = 64;
+
+// part[b] = sum over a fixed slice of (W - I)^2, fixed reduction order
+__global__ __launch_bounds__(256) void k_fro_partials(const double *__restrict__ W, int64_t d,
+                                                      double *__restrict__ part) {
+  __shared__ double red[4];
+  const int64_t n = d * d;
+  const int64_t chunk = ceil_div(n, kParts);
+  const int64_t b0 = (int64_t)blockIdx.x * chunk;
+  const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  double s = 0.0;
+  for (int64_t e = b0 + threadIdx.x; e < b1; e += 256) {
+    const int64_t i = e / d, jj = e - i * d;
+    const double v = W[e] - (i == jj ? 1.0 : 0.0);
+    s = fma(v, v, s);
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// *sel = 1 if ||W - I||_F <= tol (series path), else 0 (Cholesky path)
+__global__ void k_decide(const double *__restrict__ part, double tol, int *__restrict__ sel) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int b = 0; b < kParts; ++b) s += part[b];
+  *sel = (s <= tol * tol) ? 1 : 0;
+}
+
+// U = Phi(W - I) (the whole matrix: zero below the diagonal)
+__global__ __launch_bounds__(256) void k_series_u0(const double *__restrict__ W, int64_t d,
+                                                   double *__restrict__ U,
+                                                   const int *__restrict__ sel) {
+  if (*sel != 1) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= d * d) return;
+  const int64_t i = e / d, jj = e - i * d;
+  U[e] = jj > i ? W[e] : (jj == i ? 0.5 * (W[e] - 1.0) : 0.0);
+}
+
+// R = I + U, X = I - U (whole matrices)
+__global__ __launch_bounds__(256) void k_series_rx(const double *__restrict__ U, int64_t d,
+                                                   double *__restrict__ R,
+                                                   double *__restrict__ X,
+                                                   const int *__restrict__ sel) {
+  if (*sel != 1) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= d * d) return;
+  const int64_t i = e / d, jj = e - i * d;
+  const double id = (i == jj) ? 1.0 : 0.0;
+  R[e] = id + U[e];
+  X[e] = id - U[e];
+}
+
+// One upper 64 x 64 tile (I <= J) of
+//   MODE 0: out = Phi(W - I - U^T U)      (A = U)
+//   MODE 1: out = I - U Xin               (A = U, B = Xin)
+// with U, Xin upper triangular (the K range is limited to their nonzeros).
+// Entries below the diagonal of a diagonal tile are written as zero; tiles
+// below the diagonal are not touched.
+template <int MODE>
+__global__ __launch_bounds__(kTh) void k_series_mm(const double *__restrict__ A,
+                                                   const double *__restrict__ B,
+                                                   const double *__restrict__ W, int64_t d,
+                                                   int nblk, double *__restrict__ out,
+                                                   const int *__restrict__ sel) {
+  __shared__ CholSmem S;
+  if (*sel != 1) return;
+  int I = 0, rem = blockIdx.x;
+  while (rem >= nblk - I) { rem -= nblk - I; ++I; }
+  const int J = I + rem;
+  const int64_t r0 = (int64_t)I * 64, c0 = (int64_t)J * 64;
+  double acc[4][4];
+  zero_acc(acc);
+  if (MODE == 0) {
+    // (U^T U)[i][j] = sum_k U[k][i] U[k][j], k <= min(i, j)
+    const int64_t kend = (r0 + 64) < d ? r0 + 64 : d;
+    auto fa = [&](int i, int k) { return r0 + i < d ? A[(int64_t)k * d + r0 + i] : 0.0; };
+    auto fb = [&](int k, int jj) { return c0 + jj < d ? A[(int64_t)k * d + c0 + jj] : 0.0; };
+    tile_mm<false>(acc, fa, fb, (int)kend, S);
+  } else {
+    // (U X)[i][j] = sum_k U[i][k] X[k][j], i <= k <= j
+    const int64_t kend = (c0 + 64) < d ? c0 + 64 : d;
+    auto fa = [&](int i, int k) {
+      return r0 + i < d ? A[(r0 + i) * d + r0 + k] : 0.0;
+    };
+    auto fb = [&](int k, int jj) {
+      return c0 + jj < d ? B[(r0 + k) * d + c0 + jj] : 0.0;
+    };
+    tile_mm<true>(acc, fa, fb, (int)(kend - r0), S);
+  }
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t gi = r0 + 4 * ty + r, gj = c0 + 4 * tx + q;
+      if (gi >= d || gj >= d) continue;
+      double v;
+      if (MODE == 0) {
+        const double m = W[gi * d + gj] - (gi == gj ? 1.0 : 0.0) - acc[r][q];
+        v = gj > gi ? m : (gj == gi ? 0.5 * m : 0.0);
+      } else {
+        v = gj >= gi ? (gi == gj ? 1.0 : 0.0) - acc[r][q] : 0.0;
+      }
+      out[gi * d + gj] = v;
+    }
+}
+
 void fill(double *p, int64_t count, double v, hipStream_t st) {
   k_fill<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(p, count, v);
 }
 
-// Upper Cholesky of W (destroyed) into R, and X = R^{-1}.
-int chol_inv(double *W, int64_t d, double *R, double *X, int *flag, Arena &ws,
-             hipStream_t st) {
-  if (ws.dry()) return 0;
-  fill(R, d * d, 0.0, st);
-  fill(X, d * d, 0.0, st);
+// Upper Cholesky of W (destroyed) into R, and X = R^{-1}; R and X must be
+// zero on entry.  With sel, the launches do nothing unless *sel == 0.
+void chol_inv(double *W, int64_t d, double *R, double *X, int *flag, const int *sel,
+              hipStream_t st) {
   const int nblk = (int)ceil_div(d, 64);
-  k_chol_first<<<1, kTh, 0, st>>>(W, d, R, X, flag);
+  k_chol_first<<<1, kTh, 0, st>>>(W, d, R, X, flag, sel);
   for (int j = 0; j < nblk; ++j) {
     const int p = nblk - j - 1;
     const int tiles = p * (p + 1) / 2 + j + p;
-    if (tiles > 0) k_chol_step<<<tiles, kTh, 0, st>>>(W, d, nblk, j, R, X, flag);
+    if (tiles > 0) k_chol_step<<<tiles, kTh, 0, st>>>(W, d, nblk, j, R, X, flag, sel);
   }
-  return 0;
+}
+
+// R, X of W = I + E by the series when ||E||_F <= kSeriesTol, else by the
+// blocked Cholesky; the choice is made on the device.  Ua, Ub: d x d
+// scratch; part: kParts doubles; sel: one int.
+void near_identity_chol(double *W, int64_t d, double *R, double *X, double *Ua,
+                        double *Ub, double *part, int *sel, int *flag, hipStream_t st) {
+  const int nblk = (int)ceil_div(d, 64);
+  const unsigned ew = (unsigned)ceil_div(d * d, 256);
+  const unsigned tiles = (unsigned)(nblk * (nblk + 1) / 2);
+  fill(R, d * d, 0.0, st);
+  fill(X, d * d, 0.0, st);
+  fill(Ub, d * d, 0.0, st);
+  k_fro_partials<<<kParts, 256, 0, st>>>(W, d, part);
+  k_decide<<<1, 64, 0, st>>>(part, kSeriesTol, sel);
+  // series path
+  k_series_u0<<<ew, 256, 0, st>>>(W, d, Ua, sel);
+  k_series_mm<0><<<tiles, kTh, 0, st>>>(Ua, nullptr, W, d, nblk, Ub, sel);
+  k_series_mm<0><<<tiles, kTh, 0, st>>>(Ub, nullptr, W, d, nblk, Ua, sel);
+  k_series_rx<<<ew, 256, 0, st>>>(Ua, d, R, Ub, sel);          // R = I + U, Ub = I - U
+  k_series_mm<1><<<tiles, kTh, 0, st>>>(Ua, Ub, nullptr, d, nblk, X, sel);   // I - U (I - U)
+  k_series_mm<1><<<tiles, kTh, 0, st>>>(Ua, X, nullptr, d, nblk, Ub, sel);   // I - U X
+  // the last product goes to X: copy through the same kernel shape
+  k_series_mm<1><<<tiles, kTh, 0, st>>>(Ua, Ub, nullptr, d, nblk, X, sel);
+  // Cholesky path
+  chol_inv(W, d, R, X, flag, sel, st);
 }
 
 }  // namespace
@@ -372,36 +524,41 @@ int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rin
   double *X2 = ws.take<double>((size_t)d * d);
   double *X3 = ws.take<double>((size_t)d * d);
   double *T = ws.take<double>((size_t)d * d);
+  double *Ua = ws.take<double>((size_t)d * d);
+  double *Ub = ws.take<double>((size_t)d * d);
+  double *part = ws.take<double>(kParts);
   int *flag = ws.take<int>(4);
   const bool run = !ws.dry();
   if (run && !ws.ok()) return fail(PSK_ENOMEM, "workspace too small for sketch_qr");
   const size_t mk = ws.mark();
   int rc;
   KTimer timer("sketch_qr", st);
+  // flag[0]: a Cholesky pivot failed; flag[1], flag[2]: path of passes 2, 3
   if (run) k_fill<<<1, 64, 0, st>>>(reinterpret_cast<double *>(flag), 2, 0.0);
   if (flag_out) *flag_out = flag;
-  // pass 1 (shifted): W = C^T C + s I
+  // pass 1 (shifted): W = C^T C + s I, blocked Cholesky
   if ((rc = dgemm(true, false, d, d, m, 1.0, C, d, C, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
   const double u = 1.1102230246251565e-16;
   const double coef = 11.0 * ((double)m * d + (double)d * (d + 1)) * u;
-  if (run) k_shift_diag<<<1, 256, 0, st>>>(W, d, coef);
-  if ((rc = chol_inv(W, d, R1, X1, flag, ws, st))) return rc;
-  ws.release(mk);
+  if (run) {
+    k_shift_diag<<<1, 256, 0, st>>>(W, d, coef);
+    fill(R1, d * d, 0.0, st);
+    fill(X1, d * d, 0.0, st);
+    chol_inv(W, d, R1, X1, flag, nullptr, st);
+  }
   if ((rc = dgemm(false, false, m, d, d, 1.0, C, d, X1, d, 0.0, Qa, d, ws, st))) return rc;
   ws.release(mk);
-  // pass 2
+  // pass 2: W = Qa^T Qa
   if ((rc = dgemm(true, false, d, d, m, 1.0, Qa, d, Qa, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
-  if ((rc = chol_inv(W, d, R2, X2, flag, ws, st))) return rc;
-  ws.release(mk);
+  if (run) near_identity_chol(W, d, R2, X2, Ua, Ub, part, flag + 1, flag, st);
   if ((rc = dgemm(false, false, m, d, d, 1.0, Qa, d, X2, d, 0.0, Qb, d, ws, st))) return rc;
   ws.release(mk);
-  // pass 3
+  // pass 3: W = Qb^T Qb
   if ((rc = dgemm(true, false, d, d, m, 1.0, Qb, d, Qb, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
-  if ((rc = chol_inv(W, d, R3, X3, flag, ws, st))) return rc;
-  ws.release(mk);
+  if (run) near_identity_chol(W, d, R3, X3, Ua, Ub, part, flag + 2, flag, st);
   // R = R3 R2 R1, R^{-1} = X1 X2 X3
   if ((rc = dgemm(false, false, d, d, d, 1.0, R2, d, R1, d, 0.0, T, d, ws, st))) return rc;
   ws.release(mk);
