@@ -353,7 +353,8 @@ __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64
 // ||E||_F <= kSeriesTol = 1e-4 two steps of each leave errors below 1e-16.
 // The choice between this path and the blocked Cholesky is made on the
 // device (k_decide writes *sel), so no host synchronisation is needed: the
-// kernels of the path not taken return at once.
+// series results are copied in only when selected, and the Cholesky
+// kernels return at once when not.
 // ---------------------------------------------------------------------------
 constexpr double kSeriesTol = 1e-4;
 constexpr int kParts = 64;
@@ -388,21 +389,28 @@ __global__ void k_decide(const double *__restrict__ part, double tol, int *__res
 
 // U = Phi(W - I) (the whole matrix: zero below the diagonal)
 __global__ __launch_bounds__(256) void k_series_u0(const double *__restrict__ W, int64_t d,
-                                                   double *__restrict__ U,
-                                                   const int *__restrict__ sel) {
-  if (*sel != 1) return;
+                                                   double *__restrict__ U) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= d * d) return;
   const int64_t i = e / d, jj = e - i * d;
   U[e] = jj > i ? W[e] : (jj == i ? 0.5 * (W[e] - 1.0) : 0.0);
 }
 
+// U = Phi(W - I - T), T = U_prev^T U_prev
+__global__ __launch_bounds__(256) void k_series_phi(const double *__restrict__ W,
+                                                    const double *__restrict__ T, int64_t d,
+                                                    double *__restrict__ U) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= d * d) return;
+  const int64_t i = e / d, jj = e - i * d;
+  const double m = W[e] - (i == jj ? 1.0 : 0.0) - T[e];
+  U[e] = jj > i ? m : (jj == i ? 0.5 * m : 0.0);
+}
+
 // R = I + U, X = I - U (whole matrices)
 __global__ __launch_bounds__(256) void k_series_rx(const double *__restrict__ U, int64_t d,
                                                    double *__restrict__ R,
-                                                   double *__restrict__ X,
-                                                   const int *__restrict__ sel) {
-  if (*sel != 1) return;
+                                                   double *__restrict__ X) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= d * d) return;
   const int64_t i = e / d, jj = e - i * d;
@@ -411,59 +419,26 @@ __global__ __launch_bounds__(256) void k_series_rx(const double *__restrict__ U,
   X[e] = id - U[e];
 }
 
-// One upper 64 x 64 tile (I <= J) of
-//   MODE 0: out = Phi(W - I - U^T U)      (A = U)
-//   MODE 1: out = I - U Xin               (A = U, B = Xin)
-// with U, Xin upper triangular (the K range is limited to their nonzeros).
-// Entries below the diagonal of a diagonal tile are written as zero; tiles
-// below the diagonal are not touched.
-template <int MODE>
-__global__ __launch_bounds__(kTh) void k_series_mm(const double *__restrict__ A,
-                                                   const double *__restrict__ B,
-                                                   const double *__restrict__ W, int64_t d,
-                                                   int nblk, double *__restrict__ out,
-                                                   const int *__restrict__ sel) {
-  __shared__ CholSmem S;
-  if (*sel != 1) return;
-  int I = 0, rem = blockIdx.x;
-  while (rem >= nblk - I) { rem -= nblk - I; ++I; }
-  const int J = I + rem;
-  const int64_t r0 = (int64_t)I * 64, c0 = (int64_t)J * 64;
-  double acc[4][4];
-  zero_acc(acc);
-  if (MODE == 0) {
-    // (U^T U)[i][j] = sum_k U[k][i] U[k][j], k <= min(i, j)
-    const int64_t kend = (r0 + 64) < d ? r0 + 64 : d;
-    auto fa = [&](int i, int k) { return r0 + i < d ? A[(int64_t)k * d + r0 + i] : 0.0; };
-    auto fb = [&](int k, int jj) { return c0 + jj < d ? A[(int64_t)k * d + c0 + jj] : 0.0; };
-    tile_mm<false>(acc, fa, fb, (int)kend, S);
-  } else {
-    // (U X)[i][j] = sum_k U[i][k] X[k][j], i <= k <= j
-    const int64_t kend = (c0 + 64) < d ? c0 + 64 : d;
-    auto fa = [&](int i, int k) {
-      return r0 + i < d ? A[(r0 + i) * d + r0 + k] : 0.0;
-    };
-    auto fb = [&](int k, int jj) {
-      return c0 + jj < d ? B[(r0 + k) * d + c0 + jj] : 0.0;
-    };
-    tile_mm<true>(acc, fa, fb, (int)(kend - r0), S);
-  }
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t gi = r0 + 4 * ty + r, gj = c0 + 4 * tx + q;
-      if (gi >= d || gj >= d) continue;
-      double v;
-      if (MODE == 0) {
-        const double m = W[gi * d + gj] - (gi == gj ? 1.0 : 0.0) - acc[r][q];
-        v = gj > gi ? m : (gj == gi ? 0.5 * m : 0.0);
-      } else {
-        v = gj >= gi ? (gi == gj ? 1.0 : 0.0) - acc[r][q] : 0.0;
-      }
-      out[gi * d + gj] = v;
-    }
+// X = I - T on and above the diagonal, 0 below (T = U X_prev, upper)
+__global__ __launch_bounds__(256) void k_series_x(const double *__restrict__ T, int64_t d,
+                                                  double *__restrict__ X) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= d * d) return;
+  const int64_t i = e / d, jj = e - i * d;
+  X[e] = jj >= i ? (i == jj ? 1.0 : 0.0) - T[e] : 0.0;
+}
+
+// *sel == 1: R, X = the series results; else zero them for the Cholesky path
+__global__ __launch_bounds__(256) void k_series_select(const double *__restrict__ Rs,
+                                                       const double *__restrict__ Xs,
+                                                       int64_t d, const int *__restrict__ sel,
+                                                       double *__restrict__ R,
+                                                       double *__restrict__ X) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= d * d) return;
+  const bool s = *sel == 1;
+  R[e] = s ? Rs[e] : 0.0;
+  X[e] = s ? Xs[e] : 0.0;
 }
 
 void fill(double *p, int64_t count, double v, hipStream_t st) {
@@ -483,30 +458,43 @@ void chol_inv(double *W, int64_t d, double *R, double *X, int *flag, const int *
   }
 }
 
-// R, X of W = I + E by the series when ||E||_F <= kSeriesTol, else by the
-// blocked Cholesky; the choice is made on the device.  Ua, Ub: d x d
-// scratch; part: kParts doubles; sel: one int.
-void near_identity_chol(double *W, int64_t d, double *R, double *X, double *Ua,
-                        double *Ub, double *part, int *sel, int *flag, hipStream_t st) {
-  const int nblk = (int)ceil_div(d, 64);
+// R, X of W = I + E: the series is always evaluated (four d x d products)
+// and taken when ||E||_F <= kSeriesTol; otherwise the blocked Cholesky runs
+// (its launches return at once when the series was taken).  The choice is
+// made on the device.  B0..B3: d x d scratch; part: kParts doubles; sel: one
+// int.
+int near_identity_chol(double *W, int64_t d, double *R, double *X, double *B0, double *B1,
+                       double *B2, double *B3, double *part, int *sel, int *flag,
+                       Arena &ws, hipStream_t st) {
+  const bool run = !ws.dry();
   const unsigned ew = (unsigned)ceil_div(d * d, 256);
-  const unsigned tiles = (unsigned)(nblk * (nblk + 1) / 2);
-  fill(R, d * d, 0.0, st);
-  fill(X, d * d, 0.0, st);
-  fill(Ub, d * d, 0.0, st);
-  k_fro_partials<<<kParts, 256, 0, st>>>(W, d, part);
-  k_decide<<<1, 64, 0, st>>>(part, kSeriesTol, sel);
-  // series path
-  k_series_u0<<<ew, 256, 0, st>>>(W, d, Ua, sel);
-  k_series_mm<0><<<tiles, kTh, 0, st>>>(Ua, nullptr, W, d, nblk, Ub, sel);
-  k_series_mm<0><<<tiles, kTh, 0, st>>>(Ub, nullptr, W, d, nblk, Ua, sel);
-  k_series_rx<<<ew, 256, 0, st>>>(Ua, d, R, Ub, sel);          // R = I + U, Ub = I - U
-  k_series_mm<1><<<tiles, kTh, 0, st>>>(Ua, Ub, nullptr, d, nblk, X, sel);   // I - U (I - U)
-  k_series_mm<1><<<tiles, kTh, 0, st>>>(Ua, X, nullptr, d, nblk, Ub, sel);   // I - U X
-  // the last product goes to X: copy through the same kernel shape
-  k_series_mm<1><<<tiles, kTh, 0, st>>>(Ua, Ub, nullptr, d, nblk, X, sel);
-  // Cholesky path
-  chol_inv(W, d, R, X, flag, sel, st);
+  const size_t mk = ws.mark();
+  int rc;
+  if (run) {
+    k_fro_partials<<<kParts, 256, 0, st>>>(W, d, part);
+    k_decide<<<1, 64, 0, st>>>(part, kSeriesTol, sel);
+    k_series_u0<<<ew, 256, 0, st>>>(W, d, B0);
+  }
+  // U_{t+1} = Phi(E - U_t^T U_t), two steps: B0 -> B1 -> B0
+  double *u = B0, *v = B1;
+  for (int t = 0; t < 2; ++t) {
+    if ((rc = dgemm(true, false, d, d, d, 1.0, u, d, u, d, 0.0, B2, d, ws, st))) return rc;
+    ws.release(mk);
+    if (run) k_series_phi<<<ew, 256, 0, st>>>(W, B2, d, v);
+    double *tmp = u; u = v; v = tmp;
+  }
+  // R_s = I + U (B3), X_1 = I - U (v); X_{t+1} = I - U X_t, two steps
+  if (run) k_series_rx<<<ew, 256, 0, st>>>(u, d, B3, v);
+  for (int t = 0; t < 2; ++t) {
+    if ((rc = dgemm(false, false, d, d, d, 1.0, u, d, v, d, 0.0, B2, d, ws, st))) return rc;
+    ws.release(mk);
+    if (run) k_series_x<<<ew, 256, 0, st>>>(B2, d, v);
+  }
+  if (run) {
+    k_series_select<<<ew, 256, 0, st>>>(B3, v, d, sel, R, X);
+    chol_inv(W, d, R, X, flag, sel, st);
+  }
+  return 0;
 }
 
 }  // namespace
@@ -524,8 +512,9 @@ int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rin
   double *X2 = ws.take<double>((size_t)d * d);
   double *X3 = ws.take<double>((size_t)d * d);
   double *T = ws.take<double>((size_t)d * d);
-  double *Ua = ws.take<double>((size_t)d * d);
-  double *Ub = ws.take<double>((size_t)d * d);
+  double *B0 = ws.take<double>((size_t)d * d);
+  double *B1 = ws.take<double>((size_t)d * d);
+  double *B2 = ws.take<double>((size_t)d * d);
   double *part = ws.take<double>(kParts);
   int *flag = ws.take<int>(4);
   const bool run = !ws.dry();
@@ -552,13 +541,17 @@ int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rin
   // pass 2: W = Qa^T Qa
   if ((rc = dgemm(true, false, d, d, m, 1.0, Qa, d, Qa, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
-  if (run) near_identity_chol(W, d, R2, X2, Ua, Ub, part, flag + 1, flag, st);
+  if ((rc = near_identity_chol(W, d, R2, X2, B0, B1, B2, T, part, flag + 1, flag, ws, st)))
+    return rc;
+  ws.release(mk);
   if ((rc = dgemm(false, false, m, d, d, 1.0, Qa, d, X2, d, 0.0, Qb, d, ws, st))) return rc;
   ws.release(mk);
   // pass 3: W = Qb^T Qb
   if ((rc = dgemm(true, false, d, d, m, 1.0, Qb, d, Qb, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
-  if (run) near_identity_chol(W, d, R3, X3, Ua, Ub, part, flag + 2, flag, st);
+  if ((rc = near_identity_chol(W, d, R3, X3, B0, B1, B2, T, part, flag + 2, flag, ws, st)))
+    return rc;
+  ws.release(mk);
   // R = R3 R2 R1, R^{-1} = X1 X2 X3
   if ((rc = dgemm(false, false, d, d, d, 1.0, R2, d, R1, d, 0.0, T, d, ws, st))) return rc;
   ws.release(mk);
