@@ -68,7 +68,8 @@ typedef enum {
   PSK_EDEVICE = -4,      /* a HIP runtime call failed                         */
   PSK_ENOCONV = -5,      /* lsq_solve reached max_iter before its tolerance   */
   PSK_ERANK = -6,        /* sketch numerically rank deficient (R_jj tiny)     */
-  PSK_EUNSUPPORTED = -7  /* shape outside the limits documented per call      */
+  PSK_EUNSUPPORTED = -7, /* shape outside the limits documented per call      */
+  PSK_PENDING = 1        /* psk_server_poll: the request has not finished yet */
 } psk_status;
 
 /* ---- matrix descriptor ------------------------------------------------- */
@@ -226,6 +227,82 @@ typedef struct psk_lsq_info {
 int lsq_solve(const psk_mat *A, const double *b, double *x,
               const psk_lsq_opts *opts, psk_lsq_info *info,
               void *ws, size_t ws_bytes, void *stream);
+
+/* ---- request server (serving form) ---------------------------------------
+ * Continuous batching of least-squares and leverage-score requests of
+ * uneven n and d on one GPU.  `slots` host worker threads, each with its own
+ * HIP stream (default priority), take requests in arrival order; a request
+ * is admitted when a slot is free and its whole workspace fits in the
+ * caller's device pool, which the server carves with a first-fit allocator,
+ * so the workspace footprint of the requests in flight never exceeds
+ * pool_bytes.  Admission is strictly first-in first-out.  Requests on
+ * different slots run concurrently on the device; each request's result is
+ * the same bit for bit as when it runs alone (its kernels read only its own
+ * inputs and workspace).
+ *
+ * Requests:
+ *   PSK_REQ_LSQ       x = argmin ||A x - b|| exactly as lsq_solve with
+ *                     `opts` (out: x, d doubles);
+ *   PSK_REQ_LEVERAGE  sketched leverage scores theta_i = ||e_i^T A R^{-1}||^2
+ *                     with R from sketch_qr(sketch_gcs(A, opts.m, opts.r,
+ *                     opts.seed, opts.prec)) (Algorithm
+ *                     ls_approximate_drineas with QR; out: theta, n doubles).
+ * A, b and out are device pointers owned by the caller and must stay valid
+ * and unmodified until the request has completed (psk_server_wait or a
+ * psk_server_poll that returns PSK_OK).  Times are seconds of a monotonic
+ * host clock.  The server object is thread-safe. */
+typedef struct psk_server psk_server;
+
+typedef struct psk_server_opts {
+  void *pool;          /* device memory for request workspaces, 256-byte  *
+                        * aligned, owned by the caller, untouched by the   *
+                        * caller while the server exists                   */
+  size_t pool_bytes;
+  int32_t slots;       /* requests on the device at once, 1 .. 64          */
+} psk_server_opts;
+
+enum { PSK_REQ_LSQ = 0, PSK_REQ_LEVERAGE = 1 };
+
+typedef struct psk_request {
+  int32_t op;          /* PSK_REQ_*                                         */
+  psk_mat A;
+  const double *b;     /* LSQ: n doubles (device)                           */
+  double *out;         /* LSQ: x (d); LEVERAGE: theta (n) (device)           */
+  psk_lsq_opts opts;   /* LSQ: as lsq_solve; LEVERAGE: m, r, seed, prec     */
+} psk_request;
+
+typedef struct psk_result {
+  int32_t status;      /* PSK_OK or the status lsq_solve would return       */
+  int32_t iters;       /* LSQ: LSQR iterations                              */
+  double resid;        /* LSQ: as psk_lsq_info                              */
+  double ne_resid;
+  double t_submit;     /* submit, admission and completion times (s)        */
+  double t_start;
+  double t_end;
+} psk_result;
+
+typedef struct psk_server_stats_t {
+  int64_t submitted, completed, queued;
+  int32_t inflight, inflight_peak;   /* requests on the device (now, max)  */
+  size_t pool_bytes, pool_used, pool_peak;
+} psk_server_stats_t;
+
+/* Create a server on the current HIP device.
+ * Errors: PSK_EINVAL (slots, pool), PSK_EDEVICE. */
+int psk_server_create(const psk_server_opts *opts, psk_server **server);
+/* Queue a request (returns at once) and give it a ticket.
+ * Errors: as lsq_solve's argument checks; PSK_ENOMEM if the request's
+ * workspace is larger than the whole pool. */
+int psk_server_submit(psk_server *server, const psk_request *req, int64_t *ticket);
+/* Block until the request has finished; fills `result` and forgets the
+ * ticket.  The request's own failure is reported in result->status. */
+int psk_server_wait(psk_server *server, int64_t ticket, psk_result *result);
+/* PSK_OK with `result` filled (ticket forgotten) if finished, PSK_PENDING if
+ * not. */
+int psk_server_poll(psk_server *server, int64_t ticket, psk_result *result);
+int psk_server_stats(psk_server *server, psk_server_stats_t *stats);
+/* Finish every queued request, stop the workers, destroy the streams. */
+int psk_server_destroy(psk_server *server);
 
 /* ---- kernel timing (diagnostics) ----------------------------------------
  * When enabled, the library brackets its main kernels (and a few multi-kernel

@@ -16,7 +16,10 @@ PSK_OK = 0
 STATUS_NAMES = {
     0: "PSK_OK", -1: "PSK_EINVAL", -2: "PSK_EDTYPE", -3: "PSK_ENOMEM",
     -4: "PSK_EDEVICE", -5: "PSK_ENOCONV", -6: "PSK_ERANK", -7: "PSK_EUNSUPPORTED",
+    1: "PSK_PENDING",
 }
+PSK_PENDING = 1
+PSK_REQ_LSQ, PSK_REQ_LEVERAGE = 0, 1
 PSK_DENSE, PSK_CSR = 0, 1
 PSK_F64, PSK_F32 = 0, 1
 PSK_PREC_F64, PSK_PREC_BF16 = 0, 1
@@ -26,7 +29,9 @@ PSK_PREC_F64, PSK_PREC_BF16 = 0, 1
 EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "gram", "rownorms_sq", "sketch_qr",
             "lsq_solve", "psk_timing_enable", "psk_timing_reset",
-            "psk_timing_collect", "psk_timing_names"]
+            "psk_timing_collect", "psk_timing_names", "psk_server_create",
+            "psk_server_submit", "psk_server_wait", "psk_server_poll",
+            "psk_server_stats", "psk_server_destroy"]
 
 
 class PskMat(ctypes.Structure):
@@ -67,6 +72,49 @@ class PskLsqInfo(ctypes.Structure):
     ]
 
 
+class PskServerOpts(ctypes.Structure):
+    _fields_ = [
+        ("pool", ctypes.c_void_p),
+        ("pool_bytes", ctypes.c_size_t),
+        ("slots", ctypes.c_int32),
+    ]
+
+
+class PskRequest(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_int32),
+        ("A", PskMat),
+        ("b", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+        ("opts", PskLsqOpts),
+    ]
+
+
+class PskResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("iters", ctypes.c_int32),
+        ("resid", ctypes.c_double),
+        ("ne_resid", ctypes.c_double),
+        ("t_submit", ctypes.c_double),
+        ("t_start", ctypes.c_double),
+        ("t_end", ctypes.c_double),
+    ]
+
+
+class PskServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("queued", ctypes.c_int64),
+        ("inflight", ctypes.c_int32),
+        ("inflight_peak", ctypes.c_int32),
+        ("pool_bytes", ctypes.c_size_t),
+        ("pool_used", ctypes.c_size_t),
+        ("pool_peak", ctypes.c_size_t),
+    ]
+
+
 class PskError(RuntimeError):
     def __init__(self, status, where, message):
         self.status = status
@@ -99,6 +147,14 @@ _SIGS = {
     "psk_timing_collect": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "psk_timing_names": ([], ctypes.c_char_p),
+    "psk_server_create": ([ctypes.POINTER(PskServerOpts), ctypes.POINTER(ctypes.c_void_p)],
+                          ctypes.c_int),
+    "psk_server_submit": ([_vp, ctypes.POINTER(PskRequest), ctypes.POINTER(ctypes.c_int64)],
+                          ctypes.c_int),
+    "psk_server_wait": ([_vp, _i64, ctypes.POINTER(PskResult)], ctypes.c_int),
+    "psk_server_poll": ([_vp, _i64, ctypes.POINTER(PskResult)], ctypes.c_int),
+    "psk_server_stats": ([_vp, ctypes.POINTER(PskServerStats)], ctypes.c_int),
+    "psk_server_destroy": ([_vp], ctypes.c_int),
 }
 
 

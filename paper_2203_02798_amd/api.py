@@ -15,7 +15,7 @@ from . import _lib as L
 
 __all__ = [
     "CsrMatrix", "cs_hash", "sketch_cs", "sketch_gcs", "gram", "rownorms_sq",
-    "sketch_qr", "lsq_solve", "workspace_size", "version", "PskError",
+    "sketch_qr", "lsq_solve", "workspace_size", "version", "PskError", "Server",
 ]
 
 PskError = L.PskError
@@ -227,6 +227,100 @@ def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,
         L.check(st, "lsq_solve")
     return x, dict(iters=info.iters, status=L.STATUS_NAMES.get(info.status, info.status),
                    resid=info.resid, ne_resid=info.ne_resid)
+
+
+class Server:
+    """Continuous-batching request server (psk_server_* in include/psk.h).
+
+    ``pool_bytes`` of device memory are allocated here (torch) and handed to
+    the library, which carves request workspaces out of it; ``slots``
+    requests run on the device at once, each on its own HIP stream.  The
+    tensors of a request are kept referenced until its result is collected
+    (``wait`` / ``poll``)."""
+
+    def __init__(self, pool_bytes, slots=4, device="cuda"):
+        self.device = torch.device(device)
+        self._pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        o = L.PskServerOpts(pool=self._pool.data_ptr(), pool_bytes=int(pool_bytes),
+                            slots=int(slots))
+        h = ctypes.c_void_p()
+        L.check(L.lib().psk_server_create(ctypes.byref(o), ctypes.byref(h)),
+                "psk_server_create")
+        self._h = h
+        self._keep = {}
+
+    def _submit(self, op, A, b, out, opts):
+        # inputs written on the current stream must be complete before a
+        # worker stream reads them
+        torch.cuda.current_stream(self.device).synchronize()
+        q = L.PskRequest(op=op, A=_mat(A), b=b.data_ptr() if b is not None else None,
+                         out=out.data_ptr(), opts=opts)
+        t = ctypes.c_int64()
+        L.check(L.lib().psk_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)),
+                "psk_server_submit")
+        self._keep[t.value] = (A, b, out)
+        return t.value
+
+    def submit_lsq(self, A, b, m, r, seed=0, prec="f64", max_iter=300, refine=1,
+                   check_every=8, atol=1e-14, btol=1e-14):
+        """Queue x = argmin ||A x - b||; returns (ticket, x) with x filled on
+        completion."""
+        pm = _mat(A)
+        x = torch.empty(pm.d, dtype=torch.float64, device=self.device)
+        o = L.PskLsqOpts(Rinv=None, m=m, r=r, seed=seed, prec=_PREC[prec],
+                         max_iter=max_iter, refine=refine, check_every=check_every,
+                         atol=atol, btol=btol)
+        return self._submit(L.PSK_REQ_LSQ, A, b.contiguous(), x, o), x
+
+    def submit_leverage(self, A, m, r, seed=0, prec="f64"):
+        """Queue sketched leverage scores; returns (ticket, theta)."""
+        pm = _mat(A)
+        th = torch.empty(pm.n, dtype=torch.float64, device=self.device)
+        o = L.PskLsqOpts(Rinv=None, m=m, r=r, seed=seed, prec=_PREC[prec], max_iter=1,
+                         refine=0, check_every=1, atol=0.0, btol=0.0)
+        return self._submit(L.PSK_REQ_LEVERAGE, A, None, th, o), th
+
+    @staticmethod
+    def _result(res):
+        return dict(status=L.STATUS_NAMES.get(res.status, res.status), iters=res.iters,
+                    resid=res.resid, ne_resid=res.ne_resid, t_submit=res.t_submit,
+                    t_start=res.t_start, t_end=res.t_end)
+
+    def wait(self, ticket):
+        res = L.PskResult()
+        L.check(L.lib().psk_server_wait(self._h, ticket, ctypes.byref(res)),
+                "psk_server_wait")
+        self._keep.pop(ticket, None)
+        return self._result(res)
+
+    def poll(self, ticket):
+        """The result dict if finished, else None."""
+        res = L.PskResult()
+        st = L.lib().psk_server_poll(self._h, ticket, ctypes.byref(res))
+        if st == L.PSK_PENDING:
+            return None
+        L.check(st, "psk_server_poll")
+        self._keep.pop(ticket, None)
+        return self._result(res)
+
+    def stats(self):
+        s = L.PskServerStats()
+        L.check(L.lib().psk_server_stats(self._h, ctypes.byref(s)), "psk_server_stats")
+        return {k: getattr(s, k) for k, _ in L.PskServerStats._fields_}
+
+    def close(self):
+        if self._h is not None:
+            L.check(L.lib().psk_server_destroy(self._h), "psk_server_destroy")
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
 
 
 class kernel_timing:

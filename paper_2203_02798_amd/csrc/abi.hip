@@ -74,8 +74,6 @@ int fail(int status, const std::string &msg) {
   return status;
 }
 
-namespace {
-
 int check_mat(const psk_mat *A) {
   if (!A) return fail(PSK_EINVAL, "A is NULL");
   if (A->format != PSK_DENSE && A->format != PSK_CSR)
@@ -102,9 +100,10 @@ int check_r(int64_t r) {
   return 0;
 }
 
-hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
-// plan + run helpers shared by the entry points and psk_workspace_size
+// plan + run helpers shared by the entry points, psk_workspace_size and the
+// request server
 int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws,
                  hipStream_t st) {
   uint32_t *perm = nullptr, *bptr = nullptr;
@@ -122,7 +121,6 @@ int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int pre
   return gauss_gemm(m, r, A.d, seed, prec, SA, A.dtype, (double *)C, ws, st);
 }
 
-}  // namespace
 }  // namespace psk
 
 using namespace psk;

@@ -76,6 +76,16 @@ int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
 int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
              const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st);
 
+// Argument checks shared by the entry points (abi.hip): 0 or a status.
+int check_mat(const psk_mat *A);
+int check_r(int64_t r);
+
+// S*A and G*S*A end to end (binning, scatter, GEMM), abi.hip.
+int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws,
+                 hipStream_t st);
+int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec,
+                  void *C, Arena &ws, hipStream_t st);
+
 // ---- Gaussian GEMM (k_gauss_gemm.hip) --------------------------------------
 // C (m x d, FP64) = G (m x r) * SA (r x d, dtype sa_dtype), G generated.
 int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,

@@ -435,7 +435,8 @@ __global__ void k_zero(double *p, int64_t count) {
   if (i < count) p[i] = 0.0;
 }
 
-// res_i = b_i - A_i x (one wavefront per row)
+// res_i = b_i - A_i x.  Dense: one wavefront per row.  CSR: one lane per
+// row, and rows longer than kShortRow are taken by the whole wavefront.
 template <typename T, bool CSR>
 __global__ __launch_bounds__(256) void k_resid(const T *__restrict__ vals,
                                                const int64_t *__restrict__ indptr,
@@ -444,16 +445,39 @@ __global__ __launch_bounds__(256) void k_resid(const T *__restrict__ vals,
                                                const double *__restrict__ x,
                                                const double *__restrict__ b,
                                                double *__restrict__ res) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
+  if (CSR) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool have = i < n;
+    int64_t p0 = 0, p1 = 0;
+    if (have) {
+      p0 = indptr[i];
+      p1 = indptr[i + 1];
+    }
+    const bool longrow = have && (p1 - p0) > kShortRow;
+    if (have && !longrow) {
+      double dot = 0.0;
+      for (int64_t p = p0; p < p1; ++p) dot += (double)vals[p] * x[indices[p]];
+      res[i] = b[i] - dot;
+    }
+    uint64_t pending = __ballot(longrow);
+    while (pending) {
+      const int src = __ffsll((unsigned long long)pending) - 1;
+      pending &= pending - 1;
+      const int64_t q0 = __shfl(p0, src, 64);
+      const int64_t q1 = __shfl(p1, src, 64);
+      const int64_t row = __shfl(i, src, 64);
+      double dot = 0.0;
+      for (int64_t p = q0 + lane; p < q1; p += 64) dot += (double)vals[p] * x[indices[p]];
+      dot = wave_sum(dot);
+      if (lane == 0) res[row] = b[row] - dot;
+    }
+    return;
+  }
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (i >= n) return;
   double dot = 0.0;
-  if (CSR) {
-    for (int64_t p = indptr[i] + lane; p < indptr[i + 1]; p += 64)
-      dot += (double)vals[p] * x[indices[p]];
-  } else {
-    for (int64_t c = lane; c < d; c += 64) dot += (double)vals[i * ld + c] * x[c];
-  }
+  for (int64_t c = lane; c < d; c += 64) dot += (double)vals[i * ld + c] * x[c];
   dot = wave_sum(dot);
   if (lane == 0) res[i] = b[i] - dot;
 }
@@ -575,7 +599,8 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   for (int pass = 0; pass <= o.refine; ++pass) {
     const double *rhs = b;
     if (pass > 0) {
-      const unsigned rb = (unsigned)ceil_div(n * 64, 256);
+      // CSR: a lane per row; dense: a wavefront per row
+      const unsigned rb = (unsigned)ceil_div(A.format == PSK_CSR ? n : n * 64, 256);
       if (A.format == PSK_CSR) {
         if (A.dtype == PSK_F64)
           k_resid<double, true><<<rb, 256, 0, st>>>((const double *)A.values, A.indptr,

@@ -1,0 +1,351 @@
+// Request server of libpsk: continuous batching of least-squares and
+// leverage-score requests on one GPU.
+//
+// Paper mapping (arXiv 2203.02798): each request is one run of Algorithm
+// least_squares_precondition (lsq_solve) or of the sketched leverage scores
+// of Algorithm ls_approximate_drineas (sketch_gcs, sketch_qr, rownorms_sq on
+// A R^{-1}); the server only schedules them.
+//
+// Design: `slots` worker threads, each with its own HIP stream, take
+// requests in arrival order.  A request is admitted when a slot is free and
+// its whole workspace (sized by the same dry run as psk_workspace_size) fits
+// in the caller's device pool; the pool is carved by a first-fit allocator
+// with coalescing, so the device-memory footprint of the requests in flight
+// never exceeds the pool.  Admission is strictly first-in first-out (a large
+// request at the head waits for memory rather than being overtaken).
+// Requests on different slots overlap on the device; each request's kernels
+// read only its own inputs and workspace, so its result does not depend on
+// what else runs.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace psk {
+namespace {
+
+constexpr size_t kAlign = 256;
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, cap) with coalescing of free ranges.
+class PoolAlloc {
+ public:
+  explicit PoolAlloc(size_t cap) : cap_(cap) {
+    if (cap_ > 0) free_[0] = cap_;
+  }
+  // offset of a block of `bytes`, or SIZE_MAX if none fits
+  size_t alloc(size_t bytes) {
+    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+    if (bytes == 0) bytes = kAlign;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        const size_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > bytes) free_[off + bytes] = len - bytes;
+        used_ += bytes;
+        if (used_ > peak_) peak_ = used_;
+        sizes_[off] = bytes;
+        return off;
+      }
+    }
+    return SIZE_MAX;
+  }
+  void release(size_t off) {
+    auto s = sizes_.find(off);
+    if (s == sizes_.end()) return;
+    size_t start = off, len = s->second;
+    sizes_.erase(s);
+    used_ -= len;
+    auto next = free_.find(start + len);  // merge with the following free range
+    if (next != free_.end()) {
+      len += next->second;
+      free_.erase(next);
+    }
+    auto it = free_.lower_bound(start);  // and with the preceding one
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == start) {
+        start = prev->first;
+        len += prev->second;
+        free_.erase(prev);
+      }
+    }
+    free_[start] = len;
+  }
+  size_t peak() const { return peak_; }
+  size_t used() const { return used_; }
+
+ private:
+  size_t cap_, used_ = 0, peak_ = 0;
+  std::map<size_t, size_t> free_;   // offset -> length
+  std::map<size_t, size_t> sizes_;  // allocated offset -> length
+};
+
+struct Job {
+  psk_request req;
+  int64_t ticket = 0;
+  size_t ws_bytes = 0;
+  size_t ws_off = SIZE_MAX;
+  double t_submit = 0, t_start = 0, t_end = 0;
+  int status = PSK_OK;
+  psk_lsq_info info{};
+  bool done = false;
+};
+
+// Workspace plan of a leverage request: C (m x d), R, R^{-1} (d x d) and the
+// largest of the sketch, factorization and row-norm workspaces.
+int leverage_run(const psk_request &q, Arena &ws, hipStream_t st) {
+  const psk_mat &A = q.A;
+  const int64_t m = q.opts.m, d = A.d;
+  double *C = ws.take<double>((size_t)m * d);
+  double *R = ws.take<double>((size_t)d * d);
+  double *Ri = ws.take<double>((size_t)d * d);
+  const size_t mk = ws.mark();
+  int rc;
+  if ((rc = do_sketch_gcs(A, m, q.opts.r, q.opts.seed, q.opts.prec, C, ws, st))) return rc;
+  ws.release(mk);
+  if ((rc = sketch_qr_impl(C, m, d, R, Ri, ws, st))) return rc;
+  ws.release(mk);
+  rc = A.format == PSK_DENSE ? rownorms_dense(1.0, A, Ri, d, 0.0, q.out, ws, st)
+                             : rownorms_csr(1.0, A, Ri, d, 0.0, q.out, ws, st);
+  ws.release(mk);
+  return rc;
+}
+
+int plan_request(const psk_request &q, size_t *bytes) {
+  Arena plan;
+  int rc;
+  if (q.op == PSK_REQ_LSQ) {
+    rc = lsq_impl(q.A, nullptr, nullptr, q.opts, nullptr, plan, nullptr);
+  } else {
+    rc = leverage_run(q, plan, nullptr);
+  }
+  if (rc) return rc;
+  *bytes = plan.peak + kAlign;
+  return 0;
+}
+
+}  // namespace
+
+struct Server {
+  int device = 0;
+  unsigned char *pool = nullptr;
+  size_t pool_bytes = 0;
+  PoolAlloc alloc{0};
+  std::vector<hipStream_t> streams;
+  std::vector<std::thread> workers;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Job *> queue;
+  std::map<int64_t, Job *> jobs;
+  int64_t next_ticket = 1;
+  int inflight = 0, inflight_peak = 0;
+  int64_t submitted = 0, completed = 0;
+  bool stop = false;
+
+  void worker(int slot) {
+    (void)hipSetDevice(device);
+    hipStream_t st = streams[slot];
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+      Job *job = nullptr;
+      cv_work.wait(lk, [&] {
+        if (stop && queue.empty()) return true;
+        if (queue.empty()) return false;
+        const size_t off = alloc.alloc(queue.front()->ws_bytes);
+        if (off == SIZE_MAX) return false;
+        queue.front()->ws_off = off;
+        return true;
+      });
+      if (queue.empty()) return;  // stopping and nothing left
+      job = queue.front();
+      queue.pop_front();
+      ++inflight;
+      if (inflight > inflight_peak) inflight_peak = inflight;
+      job->t_start = now_s();
+      lk.unlock();
+      cv_work.notify_all();  // the next request may fit as well
+      Arena ws = Arena::over(pool + job->ws_off, job->ws_bytes);
+      int rc;
+      if (job->req.op == PSK_REQ_LSQ) {
+        rc = lsq_impl(job->req.A, job->req.b, job->req.out, job->req.opts, &job->info, ws, st);
+      } else {
+        rc = leverage_run(job->req, ws, st);
+      }
+      const hipError_t e = hipStreamSynchronize(st);
+      if (!rc && e != hipSuccess) rc = fail(PSK_EDEVICE, hipGetErrorString(e));
+      lk.lock();
+      job->status = rc;
+      job->t_end = now_s();
+      job->done = true;
+      alloc.release(job->ws_off);
+      --inflight;
+      ++completed;
+      cv_done.notify_all();
+      cv_work.notify_all();
+    }
+  }
+};
+
+}  // namespace psk
+
+using namespace psk;
+
+extern "C" {
+
+int psk_server_create(const psk_server_opts *o, psk_server **out) {
+  if (!o || !out) return fail(PSK_EINVAL, "NULL argument");
+  if (o->slots < 1 || o->slots > 64) return fail(PSK_EINVAL, "slots must be in [1, 64]");
+  if (!o->pool || o->pool_bytes < kAlign)
+    return fail(PSK_EINVAL, "a device pool of at least 256 bytes is needed");
+  if (((uintptr_t)o->pool % kAlign) != 0)
+    return fail(PSK_EINVAL, "the pool must be 256-byte aligned");
+  Server *s = new Server();
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(PSK_EDEVICE, "hipGetDevice failed");
+  }
+  s->pool = (unsigned char *)o->pool;
+  s->pool_bytes = o->pool_bytes;
+  s->alloc = PoolAlloc(o->pool_bytes);
+  for (int i = 0; i < o->slots; ++i) {
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (auto x : s->streams) (void)hipStreamDestroy(x);
+      delete s;
+      return fail(PSK_EDEVICE, "hipStreamCreateWithFlags failed");
+    }
+    s->streams.push_back(st);
+  }
+  for (int i = 0; i < o->slots; ++i) s->workers.emplace_back([s, i] { s->worker(i); });
+  *out = reinterpret_cast<psk_server *>(s);
+  return PSK_OK;
+}
+
+int psk_server_submit(psk_server *srv, const psk_request *q, int64_t *ticket) {
+  if (!srv || !q || !ticket) return fail(PSK_EINVAL, "NULL argument");
+  Server *s = reinterpret_cast<Server *>(srv);
+  int rc = check_mat(&q->A);
+  if (rc) return rc;
+  if (q->op != PSK_REQ_LSQ && q->op != PSK_REQ_LEVERAGE)
+    return fail(PSK_EINVAL, "op must be PSK_REQ_LSQ or PSK_REQ_LEVERAGE");
+  if (!q->out) return fail(PSK_EINVAL, "out is NULL");
+  const psk_lsq_opts &o = q->opts;
+  if (q->op == PSK_REQ_LSQ) {
+    if (!q->b) return fail(PSK_EINVAL, "b is NULL");
+    if (!o.Rinv) {
+      if (o.m < q->A.d) return fail(PSK_EINVAL, "opts.m must be >= d");
+      if ((rc = check_r(o.r))) return rc;
+      if (o.r < o.m) return fail(PSK_EINVAL, "opts.r must be >= opts.m");
+    }
+    if (o.max_iter < 1 || o.check_every < 1 || o.refine < 0)
+      return fail(PSK_EINVAL, "max_iter >= 1, check_every >= 1, refine >= 0 needed");
+  } else {
+    if (o.m < q->A.d) return fail(PSK_EINVAL, "opts.m must be >= d");
+    if ((rc = check_r(o.r))) return rc;
+    if (o.r < o.m) return fail(PSK_EINVAL, "opts.r must be >= opts.m");
+  }
+  if (o.prec != PSK_PREC_F64 && o.prec != PSK_PREC_BF16)
+    return fail(PSK_EDTYPE, "opts.prec must be PSK_PREC_F64 or PSK_PREC_BF16");
+  size_t bytes = 0;
+  if ((rc = plan_request(*q, &bytes))) return rc;
+  if (bytes > s->pool_bytes)
+    return fail(PSK_ENOMEM, "request workspace exceeds the whole server pool");
+  Job *job = new Job();
+  job->req = *q;
+  job->ws_bytes = bytes;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      delete job;
+      return fail(PSK_EINVAL, "server is shutting down");
+    }
+    job->ticket = s->next_ticket++;
+    job->t_submit = now_s();
+    s->jobs[job->ticket] = job;
+    s->queue.push_back(job);
+    ++s->submitted;
+  }
+  s->cv_work.notify_all();
+  *ticket = job->ticket;
+  return PSK_OK;
+}
+
+static void fill_result(const Job *j, psk_result *res) {
+  res->status = j->status;
+  res->iters = j->info.iters;
+  res->resid = j->info.resid;
+  res->ne_resid = j->info.ne_resid;
+  res->t_submit = j->t_submit;
+  res->t_start = j->t_start;
+  res->t_end = j->t_end;
+}
+
+int psk_server_wait(psk_server *srv, int64_t ticket, psk_result *res) {
+  if (!srv || !res) return fail(PSK_EINVAL, "NULL argument");
+  Server *s = reinterpret_cast<Server *>(srv);
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return fail(PSK_EINVAL, "unknown ticket");
+  Job *j = it->second;
+  s->cv_done.wait(lk, [&] { return j->done; });
+  fill_result(j, res);
+  s->jobs.erase(it);
+  delete j;
+  return PSK_OK;
+}
+
+int psk_server_poll(psk_server *srv, int64_t ticket, psk_result *res) {
+  if (!srv || !res) return fail(PSK_EINVAL, "NULL argument");
+  Server *s = reinterpret_cast<Server *>(srv);
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(ticket);
+  if (it == s->jobs.end()) return fail(PSK_EINVAL, "unknown ticket");
+  Job *j = it->second;
+  if (!j->done) return PSK_PENDING;
+  fill_result(j, res);
+  s->jobs.erase(it);
+  delete j;
+  return PSK_OK;
+}
+
+int psk_server_stats(psk_server *srv, psk_server_stats_t *out) {
+  if (!srv || !out) return fail(PSK_EINVAL, "NULL argument");
+  Server *s = reinterpret_cast<Server *>(srv);
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->queued = (int64_t)s->queue.size();
+  out->inflight = s->inflight;
+  out->inflight_peak = s->inflight_peak;
+  out->pool_bytes = s->pool_bytes;
+  out->pool_used = s->alloc.used();
+  out->pool_peak = s->alloc.peak();
+  return PSK_OK;
+}
+
+int psk_server_destroy(psk_server *srv) {
+  if (!srv) return fail(PSK_EINVAL, "NULL argument");
+  Server *s = reinterpret_cast<Server *>(srv);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (auto &t : s->workers) t.join();
+  for (auto st : s->streams) (void)hipStreamDestroy(st);
+  for (auto &kv : s->jobs) delete kv.second;
+  delete s;
+  return PSK_OK;
+}
+
+}  // extern "C"

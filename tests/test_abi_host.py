@@ -124,3 +124,18 @@ def test_python_binding_reports_missing_library(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "_LIB", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         L.lib()
+
+
+def test_server_argument_checks_before_any_device_call(lib):
+    import ctypes as C
+    h = C.c_void_p()
+    assert lib.psk_server_create(None, C.byref(h)) == -1
+    o = L.PskServerOpts(pool=None, pool_bytes=1 << 20, slots=2)
+    assert lib.psk_server_create(C.byref(o), C.byref(h)) == -1      # no pool
+    o = L.PskServerOpts(pool=256, pool_bytes=1 << 20, slots=0)
+    assert lib.psk_server_create(C.byref(o), C.byref(h)) == -1      # slots
+    o = L.PskServerOpts(pool=257, pool_bytes=1 << 20, slots=2)
+    assert lib.psk_server_create(C.byref(o), C.byref(h)) == -1      # alignment
+    t = C.c_int64()
+    assert lib.psk_server_submit(None, None, C.byref(t)) == -1
+    assert lib.psk_server_destroy(None) == -1
