@@ -93,6 +93,105 @@ def make_inputs(name):
     return kind, a, b, r, m
 
 
+def serving_trace_gpu(torch, num, seed, n_lo, n_hi, device):
+    """Synthetic least-squares requests drawn on the device: n log-uniform in
+    [n_lo, n_hi], d uniform over {32, 64, 128, 256}, condition number
+    log-uniform in [1, 1e8]; A = X diag(s) V^T with X ~ N(0,1)/sqrt(n), V the
+    Q factor of a Gaussian, s geometric from 1 to 1/cond; b = A x + 1e-3 e."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(num):
+        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        d = int(rng.choice([32, 64, 128, 256]))
+        cond = float(np.exp(rng.uniform(0.0, np.log(1e8))))
+        g = torch.Generator(device=device)
+        g.manual_seed(seed * 100003 + k)
+        x = torch.randn(n, d, generator=g, device=device, dtype=torch.float64) / n ** 0.5
+        v, _ = torch.linalg.qr(torch.randn(d, d, generator=g, device=device,
+                                           dtype=torch.float64))
+        sv = torch.logspace(0.0, -np.log10(cond), d, device=device, dtype=torch.float64)
+        a = ((x * sv) @ v.T).contiguous()
+        xt = torch.randn(d, generator=g, device=device, dtype=torch.float64)
+        b = a @ xt + 1e-3 * torch.randn(n, generator=g, device=device, dtype=torch.float64)
+        reqs.append(dict(a=a, b=b, n=n, d=d, cond=cond, m=4 * d, r=min(d * d, n), seed=k))
+    torch.cuda.synchronize(device)
+    return reqs
+
+
+def serving_bench(api, torch, device, num=64, slots=8, pool_gb=16.0):
+    """Closed-loop runs (all requests queued at t = 0) of the request server
+    for the FP64 and BF16 sketch at two sketch sizes (m = 4d and 8d; r =
+    min(d^2, n) >= m), and an open-loop run (Poisson arrivals at 0.8x the best
+    FP64 rate) with the best BF16 configuration."""
+    reqs = serving_trace_gpu(torch, num, 0, 1e4, 2e5, device)
+    pool = int(pool_gb * (1 << 30))
+
+    def run(prec, mf, esc=0.0, arrivals=None):
+        with api.Server(pool, slots=slots, device=device) as srv:
+            t0 = time.perf_counter()
+            pend = []
+            for k, q in enumerate(reqs):
+                if arrivals is not None:
+                    wait = arrivals[k] - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                m = mf * q["d"]
+                r = max(min(q["d"] * q["d"], q["n"]), m)
+                pend.append(srv.submit_lsq(q["a"], q["b"], m=m, r=r, seed=q["seed"],
+                                           prec=prec, escalate_cond=esc))
+            res = [srv.wait(t) for t, _ in pend]
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        lat = np.array([1e3 * (r_["t_end"] - r_["t_submit"]) for r_ in res])
+        out = {"prec": prec, "m": f"{mf}d", "solves_per_s": num / wall,
+               "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "wall_s": wall,
+               "failed": sum(1 for r_ in res if r_["status"] != "PSK_OK"),
+               "inflight_peak": st["inflight_peak"], "pool_peak_bytes": st["pool_peak"],
+               "lsqr_iters_mean": float(np.mean([r_["iters"] for r_ in res]))}
+        if prec == "bf16":
+            out["escalate_cond"] = esc if esc else 1e4
+            out["escalated_to_f64"] = int(sum(1 for r_ in res if r_["prec_used"] == "f64"))
+        return out, [x for _, x in pend]
+
+    runs = {}
+    sols = {}
+    for prec, mf, esc in (("f64", 4, 0.0), ("f64", 8, 0.0), ("bf16", 4, 0.0),
+                          ("bf16", 8, 0.0), ("bf16", 8, 1e3), ("bf16", 16, 0.0)):
+        key = f"{prec}_m{mf}d" + ("_esc1e3" if esc else "")
+        log(f"serving: {num} requests, closed loop, {key}")
+        runs[key], sols[key] = run(prec, mf, esc)
+    ok = lambda k: runs[k]["failed"] == 0
+    best64 = max((k for k in runs if k.startswith("f64") and ok(k)),
+                 key=lambda k: runs[k]["solves_per_s"])
+    best16 = max((k for k in runs if k.startswith("bf16") and ok(k)),
+                 key=lambda k: runs[k]["solves_per_s"])
+    # residual of each solution, best BF16 vs best FP64 configuration
+    rel = []
+    for q, xa, xb in zip(reqs, sols[best64], sols[best16]):
+        ra = torch.linalg.vector_norm(q["b"] - q["a"] @ xa).item()
+        rb = torch.linalg.vector_norm(q["b"] - q["a"] @ xb).item()
+        rel.append(abs(rb - ra) / ra)
+    rate = 0.8 * runs[best64]["solves_per_s"]
+    arr = np.cumsum(np.random.default_rng(1).exponential(1.0 / rate, size=num))
+    prec, mf = runs[best16]["prec"], int(runs[best16]["m"][:-1])
+    esc = 1e3 if best16.endswith("esc1e3") else 0.0
+    log(f"serving: open loop, Poisson arrivals at {rate:.1f}/s, {best16}")
+    ol, _ = run(prec, mf, esc, arrivals=arr)
+    olf, _ = run("f64", int(runs[best64]["m"][:-1]), 0.0, arrivals=arr)
+    return {
+        "trace": (f"{num} synthetic LSQ requests, n log-uniform [1e4, 2e5], d in "
+                  "{32,64,128,256}, cond log-uniform [1, 1e8], r = max(min(d^2, n), m), "
+                  "A resident in HBM before submission"),
+        "slots": slots, "pool_bytes": pool,
+        "closed_loop": runs,
+        "best_fp64": best64, "best_bf16": best16,
+        "bf16_vs_fp64_solves": runs[best16]["solves_per_s"] / runs[best64]["solves_per_s"],
+        "resid_rel_diff_max": float(max(rel)),
+        "open_loop": {"arrival_rate": rate, best16: ol, best64: olf},
+    }
+
+
 def cpu_baseline(kind, a, b, r, m, seed, budget_s=12.0):
     """The oracle on the host: every stage in full except the Gaussian GEMM,
     whose bucket batches (Algorithm countgauss_multiply) are timed on a
@@ -158,6 +257,8 @@ def main():
                          "and the BF16 path and reports BF16 as the headline")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the request-server measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 4 elementwise copies of MIB "
                          "MiB (FP64) whose HBM bytes are known, to scale hardware "
@@ -294,6 +395,8 @@ def main():
                                              "p50_ms", "p99_ms", "sketch_gcs_gbs",
                                              "stage_ms", "lsq")}
         rec["speedup_vs_fp64_path"] = f["ms_per_step"] / hr["ms_per_step"]
+    if not args.no_serving:
+        rec["serving"] = serving_bench(api, torch, dev)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         tot, cores, sample, parts = cpu_baseline(kind, a, b, r, m, seed)

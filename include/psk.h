@@ -206,6 +206,12 @@ typedef struct psk_lsq_opts {
   int32_t check_every;/* iterations between convergence checks (>=1) */
   double atol;        /* stop when ||(AN)^T r|| <= atol*||AN||*||r|| */
   double btol;        /* or when ||r|| <= btol*||b||                  */
+  double escalate_cond; /* prec == PSK_PREC_BF16: when the factor's  *
+                       * diagonal ratio max|R_ii| / min|R_ii| (a    *
+                       * lower estimate of cond(A)) exceeds this,    *
+                       * the sketch is rebuilt in FP64 from the same *
+                       * S*A before LSQR starts; 0 selects 1e4,      *
+                       * a negative value never escalates            */
 } psk_lsq_opts;
 
 typedef struct psk_lsq_info {
@@ -213,6 +219,9 @@ typedef struct psk_lsq_info {
   int32_t status;     /* PSK_OK or PSK_ENOCONV                        */
   double resid;       /* ||b - A x|| estimate from the recurrences   */
   double ne_resid;    /* ||(AN)^T r|| / (||AN||_F ||r||) estimate    */
+  int32_t prec_used;  /* PSK_PREC_* of the sketch the preconditioner *
+                       * came from (-1 with a caller's Rinv)          */
+  int32_t reserved;
 } psk_lsq_info;
 
 /* x = argmin ||A x - b|| by sketch-and-precondition (Algorithm
@@ -279,6 +288,8 @@ typedef struct psk_result {
   double t_submit;     /* submit, admission and completion times (s)        */
   double t_start;
   double t_end;
+  int32_t prec_used;   /* LSQ: as psk_lsq_info; LEVERAGE: opts.prec         */
+  int32_t reserved;
 } psk_result;
 
 typedef struct psk_server_stats_t {

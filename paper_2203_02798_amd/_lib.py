@@ -60,6 +60,7 @@ class PskLsqOpts(ctypes.Structure):
         ("check_every", ctypes.c_int32),
         ("atol", ctypes.c_double),
         ("btol", ctypes.c_double),
+        ("escalate_cond", ctypes.c_double),
     ]
 
 
@@ -69,6 +70,8 @@ class PskLsqInfo(ctypes.Structure):
         ("status", ctypes.c_int32),
         ("resid", ctypes.c_double),
         ("ne_resid", ctypes.c_double),
+        ("prec_used", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -99,6 +102,8 @@ class PskResult(ctypes.Structure):
         ("t_submit", ctypes.c_double),
         ("t_start", ctypes.c_double),
         ("t_end", ctypes.c_double),
+        ("prec_used", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

@@ -201,8 +201,12 @@ def sketch_qr(C):
     return R, Ri
 
 
+_PREC_NAME = {L.PSK_PREC_F64: "f64", L.PSK_PREC_BF16: "bf16", -1: None}
+
+
 def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,
-              check_every=8, atol=1e-14, btol=1e-14, Rinv=None, raise_on_noconv=False):
+              check_every=8, atol=1e-14, btol=1e-14, Rinv=None, raise_on_noconv=False,
+              escalate_cond=0.0):
     """x = argmin ||A x - b|| by sketch-and-precondition LSQR.  With ``Rinv``
     (d x d FP64 device tensor, e.g. from sketch_qr) the preconditioner is
     reused and m, r, seed, prec are ignored.  Returns (x float64[d], info)."""
@@ -216,7 +220,8 @@ def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,
             raise ValueError("Rinv must be a float64 d x d tensor")
     o = L.PskLsqOpts(Rinv=Rinv.data_ptr() if Rinv is not None else None, m=m, r=r,
                      seed=seed, prec=_PREC[prec], max_iter=max_iter, refine=refine,
-                     check_every=check_every, atol=atol, btol=btol)
+                     check_every=check_every, atol=atol, btol=btol,
+                     escalate_cond=escalate_cond)
     info = L.PskLsqInfo()
     nbytes = workspace_size(L.PSK_OP_LSQ, A, m=0 if Rinv is not None else m, r=r,
                             prec=prec)
@@ -226,7 +231,8 @@ def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,
     if st != L.PSK_OK and (st != -5 or raise_on_noconv):
         L.check(st, "lsq_solve")
     return x, dict(iters=info.iters, status=L.STATUS_NAMES.get(info.status, info.status),
-                   resid=info.resid, ne_resid=info.ne_resid)
+                   resid=info.resid, ne_resid=info.ne_resid,
+                   prec_used=_PREC_NAME.get(info.prec_used, info.prec_used))
 
 
 class Server:
@@ -263,14 +269,14 @@ class Server:
         return t.value
 
     def submit_lsq(self, A, b, m, r, seed=0, prec="f64", max_iter=300, refine=1,
-                   check_every=8, atol=1e-14, btol=1e-14):
+                   check_every=8, atol=1e-14, btol=1e-14, escalate_cond=0.0):
         """Queue x = argmin ||A x - b||; returns (ticket, x) with x filled on
         completion."""
         pm = _mat(A)
         x = torch.empty(pm.d, dtype=torch.float64, device=self.device)
         o = L.PskLsqOpts(Rinv=None, m=m, r=r, seed=seed, prec=_PREC[prec],
                          max_iter=max_iter, refine=refine, check_every=check_every,
-                         atol=atol, btol=btol)
+                         atol=atol, btol=btol, escalate_cond=escalate_cond)
         return self._submit(L.PSK_REQ_LSQ, A, b.contiguous(), x, o), x
 
     def submit_leverage(self, A, m, r, seed=0, prec="f64"):
@@ -285,7 +291,8 @@ class Server:
     def _result(res):
         return dict(status=L.STATUS_NAMES.get(res.status, res.status), iters=res.iters,
                     resid=res.resid, ne_resid=res.ne_resid, t_submit=res.t_submit,
-                    t_start=res.t_start, t_end=res.t_end)
+                    t_start=res.t_start, t_end=res.t_end,
+                    prec_used=_PREC_NAME.get(res.prec_used, res.prec_used))
 
     def wait(self, ticket):
         res = L.PskResult()

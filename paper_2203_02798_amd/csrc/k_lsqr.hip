@@ -435,6 +435,32 @@ __global__ void k_zero(double *p, int64_t count) {
   if (i < count) p[i] = 0.0;
 }
 
+// out[0] = max_i |R_ii|, out[1] = min_i |R_ii| (one workgroup, fixed order)
+__global__ __launch_bounds__(256) void k_diag_ratio(const double *__restrict__ R, int64_t d,
+                                                    double *__restrict__ out) {
+  __shared__ double mx[256], mn[256];
+  double a = 0.0, b = INFINITY;
+  for (int64_t i = threadIdx.x; i < d; i += 256) {
+    const double v = fabs(R[i * d + i]);
+    a = fmax(a, v);
+    b = fmin(b, v);
+  }
+  mx[threadIdx.x] = a;
+  mn[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + s]);
+      mn[threadIdx.x] = fmin(mn[threadIdx.x], mn[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = mx[0];
+    out[1] = mn[0];
+  }
+}
+
 // res_i = b_i - A_i x.  Dense: one wavefront per row.  CSR: one lane per
 // row, and rows longer than kShortRow are taken by the whole wavefront.
 template <typename T, bool CSR>
@@ -568,27 +594,57 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   B.vhat = ws.take<double>((size_t)d);
   double *res = ws.take<double>((size_t)n);  // residual of the refinement passes
   B.st = ws.take<LsqrState>(1);
+  double *ratio = ws.take<double>(2);       // max |R_ii|, min |R_ii|
   const size_t mk = ws.mark();
   int rc = 0;
   int *flag = nullptr;
+  int prec_used = o.prec;
+  const double cond_limit = o.escalate_cond == 0.0 ? 1e4 : o.escalate_cond;
+  const bool may_escalate = own && o.prec == PSK_PREC_BF16 && cond_limit > 0.0;
+  void *SA = nullptr;
   if (own) {
-    // sketch and factor (their scratch is released afterwards)
-    void *SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
+    // sketch and factor (their scratch is released afterwards); S*A stays
+    // until the precision decision so that an FP64 rebuild can reuse it
+    SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
     uint32_t *perm = nullptr, *bptr = nullptr;
     if ((rc = cs_bin(n, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr))) return rc;
     if ((rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return rc;
+    const size_t mk2 = ws.mark();
     if ((rc = gauss_gemm(m, o.r, d, o.seed, o.prec, SA, A.dtype, C, ws, st))) return rc;
+    ws.release(mk2);
     if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;
+    ws.release(mk2);
+    if (may_escalate && ws.dry()) {
+      // plan the FP64 rebuild as well
+      if ((rc = gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, A.dtype, C, ws, st))) return rc;
+      ws.release(mk2);
+    }
   }
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for lsq_solve");
-  ws.release(mk);
   if (own) {
     int hflag = 0;
+    double hr[2] = {1.0, 1.0};
+    k_diag_ratio<<<1, 256, 0, st>>>(R, d, ratio);
     PSK_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    PSK_HIP_TRY(hipMemcpyAsync(hr, ratio, sizeof(hr), hipMemcpyDeviceToHost, st));
     PSK_HIP_TRY(hipStreamSynchronize(st));
+    // A reduced-precision sketch only preconditions well while its relative
+    // error (about 1e-5 for the BF16 GEMM) times cond(A) stays small; the
+    // diagonal ratio of R is a cheap lower estimate of cond(A).
+    if (may_escalate && (hflag || !(hr[0] <= cond_limit * hr[1]))) {
+      const size_t mk2 = ws.mark();
+      if ((rc = gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, A.dtype, C, ws, st))) return rc;
+      ws.release(mk2);
+      if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;
+      ws.release(mk2);
+      PSK_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+      PSK_HIP_TRY(hipStreamSynchronize(st));
+      prec_used = PSK_PREC_F64;
+    }
     if (hflag) return fail(PSK_ERANK, "sketch is numerically rank deficient");
   }
+  ws.release(mk);
 
   const unsigned db = (unsigned)ceil_div(d, 256);
   const unsigned nb16 = (unsigned)ceil_div(d, kColsPerBlk);
@@ -647,6 +703,8 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     info->status = converged ? PSK_OK : PSK_ENOCONV;
     info->resid = hs.rnorm;
     info->ne_resid = hs.test2;
+    info->prec_used = own ? prec_used : -1;
+    info->reserved = 0;
   }
   if (!converged) return fail(PSK_ENOCONV, "LSQR reached max_iter before its tolerance");
   return 0;

@@ -288,6 +288,8 @@ static void fill_result(const Job *j, psk_result *res) {
   res->t_submit = j->t_submit;
   res->t_start = j->t_start;
   res->t_end = j->t_end;
+  res->prec_used = j->req.op == PSK_REQ_LSQ ? j->info.prec_used : j->req.opts.prec;
+  res->reserved = 0;
 }
 
 int psk_server_wait(psk_server *srv, int64_t ticket, psk_result *res) {

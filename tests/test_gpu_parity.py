@@ -196,10 +196,12 @@ def test_sketch_gcs_bf16_deterministic(api):
     assert torch.equal(c1, c2)
 
 
-@pytest.mark.parametrize("kind,cond", [("dense", 1e6), ("csr", 1e2)])
-def test_lsq_solve_bf16_sketch(api, kind, cond):
+@pytest.mark.parametrize("kind,cond,want", [("dense", 10.0, "bf16"), ("dense", 1e8, "f64"),
+                                            ("csr", 1e2, "bf16")])
+def test_lsq_solve_bf16_sketch(api, kind, cond, want):
     # LSQR and the refinement run in FP64 whatever the sketch precision: the
-    # solution meets the same tolerances as with the FP64 sketch
+    # solution meets the same tolerances as with the FP64 sketch.  An
+    # ill-conditioned A makes the BF16 sketch escalate to FP64.
     n, d = 20000, 32
     if kind == "csr":
         a = synth.csr_uniform(n, d, 0.2, seed=2)
@@ -210,6 +212,7 @@ def test_lsq_solve_bf16_sketch(api, kind, cond):
     x, info = api.lsq_solve(to_device(a), torch.from_numpy(b).cuda(), m=4 * d, r=d * d,
                             seed=3, prec="bf16")
     _say(f"lsq bf16 {kind} cond={cond}: {info}")
+    assert info["prec_used"] == want
     rs, _ = olsq.lsq_quality(a, b, olsq.lstsq(a, b))
     rn, ne = olsq.lsq_quality(a, b, x.cpu().numpy())
     assert (rn - rs) / rs <= 1e-10
