@@ -224,3 +224,57 @@ def sketch_gcs_bf16_reference(a, m, r, seed, nlimbs=2, batch=4096):
         zq = to_bf16(gaussian_normals(m, b0, b1, seed))
         c += zq @ saq[b0:b1]
     return c / np.sqrt(m)
+
+
+# ----------------------------------------------------------------------------
+# FP8 e4m3 with power-of-two block scales (reading of the per-128 scales)
+# ----------------------------------------------------------------------------
+E4M3_MAX = 448.0
+
+
+def e8m0_exponent(amax):
+    """Exponent e of the power-of-two scale 2^e of a block whose largest
+    magnitude is amax: the smallest integer with 448 * 2^e >= amax, i.e.
+    ceil(log2(amax / 448)), taken exactly from the binary exponent of amax
+    (amax = f 2^x, f in [1/2, 1); 448 = 0.875 2^9).  0 for an all-zero block."""
+    amax = np.asarray(amax, dtype=np.float64)
+    f, x = np.frexp(amax)
+    e = np.where(f <= 0.875, x - 9, x - 8)
+    return np.where(amax > 0, e, 0).astype(np.int64)
+
+
+def quantize_e4m3_blocks(x, block=128, axis=0):
+    """Blocks of `block` consecutive entries along `axis` (starting at index
+    0; the last may be shorter) share one scale 2^e with e = e8m0_exponent of
+    the block's largest magnitude; each entry becomes 2^e * e4m3(x / 2^e)
+    (RNE, |x / 2^e| <= 448 by construction).  Returns (dequantised x, e)
+    with e of shape (blocks, other axis)."""
+    x = np.asarray(x, dtype=np.float64)
+    xt = np.moveaxis(x, axis, 0)
+    n = xt.shape[0]
+    nb = (n + block - 1) // block
+    out = np.empty_like(xt)
+    exps = np.empty((nb,) + xt.shape[1:], dtype=np.int64)
+    for b in range(nb):
+        sl = xt[b * block:(b + 1) * block]
+        e = e8m0_exponent(np.max(np.abs(sl), axis=0))
+        s = np.ldexp(1.0, e)
+        out[b * block:(b + 1) * block] = to_e4m3(sl / s) * s
+        exps[b] = e
+    return np.moveaxis(out, 0, axis), exps
+
+
+def sketch_gcs_fp8_reference(a, m, r, seed, block=128, batch=4096):
+    """Quantisation-aware reference of the FP8 Gaussian GEMM: S*A quantised
+    per column in blocks of `block` buckets, the unscaled normals quantised
+    per row in the same bucket blocks, their exact (FP64) product scaled by
+    1/sqrt(m)."""
+    assert batch % block == 0
+    sa = sketch_cs(a, r, seed)
+    saq, _ = quantize_e4m3_blocks(sa, block, axis=0)
+    c = np.zeros((m, sa.shape[1]))
+    for b0 in range(0, r, batch):
+        b1 = min(r, b0 + batch)
+        zq, _ = quantize_e4m3_blocks(gaussian_normals(m, b0, b1, seed), block, axis=1)
+        c += zq @ saq[b0:b1]
+    return c / np.sqrt(m)

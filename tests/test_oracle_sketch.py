@@ -227,3 +227,59 @@ def test_bf16_reference_within_rounding_bound():
     assert np.all(np.abs(cq - c) <= bound)
     rel = np.linalg.norm(cq - c) / np.linalg.norm(c)
     assert 1e-4 < rel < 1e-2
+
+
+def test_e8m0_exponent_is_smallest_covering_power():
+    rng = np.random.default_rng(11)
+    amax = np.concatenate([np.abs(rng.standard_normal(2000)) * 10.0 ** rng.integers(-8, 8, 2000),
+                           448.0 * 2.0 ** np.arange(-12, 12),          # exact boundaries
+                           np.nextafter(448.0 * 2.0 ** np.arange(-12, 12), np.inf),
+                           np.nextafter(448.0 * 2.0 ** np.arange(-12, 12), 0.0)])
+    e = osk.e8m0_exponent(amax)
+    # brute force: smallest integer e with 448 * 2^e >= amax
+    for v, ev in zip(amax, e):
+        assert np.ldexp(448.0, int(ev)) >= v
+        assert np.ldexp(448.0, int(ev) - 1) < v
+    assert osk.e8m0_exponent(0.0) == 0
+
+
+def test_block_quantisation_bounds():
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((300, 7)) * 10.0 ** rng.integers(-3, 3, (300, 7))
+    q, e = osk.quantize_e4m3_blocks(x, 128, axis=0)
+    assert e.shape == (3, 7)
+    for b in range(3):
+        blk, qb = x[128 * b:128 * (b + 1)], q[128 * b:128 * (b + 1)]
+        s = np.ldexp(1.0, e[b])
+        amax = np.abs(blk).max(axis=0)
+        # the block maximum lands in (224, 448] after scaling
+        assert np.all(amax / s <= 448.0) and np.all(amax / s > 224.0)
+        # RNE with 3 fraction bits: relative error <= 2^-4 for normal values,
+        # absolute <= 2^-10 s in the subnormal range
+        err = np.abs(qb - blk)
+        assert np.all(err <= np.maximum(2.0 ** -4 * np.abs(blk), 2.0 ** -10 * s) * (1 + 1e-15))
+    # along the other axis as well
+    q2, e2 = osk.quantize_e4m3_blocks(x.T, 128, axis=1)
+    np.testing.assert_array_equal(q2, q.T)
+    np.testing.assert_array_equal(e2, e)
+
+
+def test_fp8_reference_within_rounding_bound():
+    a = synth.dense_gaussian(3000, 20, seed=4)
+    m, r, seed = 40, 500, 6
+    cq = osk.sketch_gcs_fp8_reference(a, m, r, seed)
+    c = osk.sketch_gcs(a, m, r, seed)
+    z = osk.gaussian_normals(m, 0, r, seed)
+    sa = osk.sketch_cs(a, r, seed)
+    zq, ez = osk.quantize_e4m3_blocks(z, 128, axis=1)
+    saq, es = osk.quantize_e4m3_blocks(sa, 128, axis=0)
+    # elementwise rounding bounds of the two operands (see above)
+    sz = np.repeat(np.ldexp(1.0, ez).T, 128, axis=1)[:, :r]
+    ss = np.repeat(np.ldexp(1.0, es), 128, axis=0)[:r]
+    dz = np.maximum(2.0 ** -4 * np.abs(z), 2.0 ** -10 * sz)
+    ds = np.maximum(2.0 ** -4 * np.abs(sa), 2.0 ** -10 * ss)
+    assert np.all(np.abs(zq - z) <= dz * (1 + 1e-15))
+    bound = (dz @ np.abs(sa) + np.abs(z) @ ds + dz @ ds) / np.sqrt(m)
+    assert np.all(np.abs(cq - c) <= bound * (1 + 1e-12) + 1e-13 * np.abs(c).max())
+    rel = np.linalg.norm(cq - c) / np.linalg.norm(c)
+    assert 5e-3 < rel < 1e-1
