@@ -99,12 +99,19 @@ typedef struct psk_mat {
 /* ---- precision of the Gaussian GEMM of sketch_gcs / lsq_solve ---------- */
 enum {
   PSK_PREC_F64 = 0,   /* G and S*A in FP64, FP64 MFMA, FP64 accumulation      */
-  PSK_PREC_BF16 = 1   /* G rounded to bfloat16, S*A split into two bfloat16   *
+  PSK_PREC_BF16 = 1,  /* G rounded to bfloat16, S*A split into two bfloat16   *
                        * limbs (hi + lo), BF16 MFMA with FP32 accumulation,   *
                        * FP64 reduction of the K-split partial products.      *
                        * The normals are evaluated in FP32 (a few ulps from   *
                        * the FP64 ones) before the RNE rounding; entries of   *
                        * S*A must lie in the bfloat16 range.                  */
+  PSK_PREC_FP8 = 2    /* G and S*A quantised to OCP FP8 e4m3 (RNE) with one   *
+                       * power-of-two (E8M0) scale per block of 128 buckets:  *
+                       * per row of G, per column of S*A, exponent            *
+                       * ceil(log2(amax/448)); scaled FP8 MFMA with FP32      *
+                       * accumulation, FP64 reduction of the K-split partial  *
+                       * products.  Normals evaluated in FP32 as for BF16.    *
+                       * Entries of S*A must stay below 448 * 2^127.          */
 };
 
 /* ---- operations for psk_workspace_size --------------------------------- */
@@ -156,7 +163,7 @@ int sketch_cs(const psk_mat *A, int64_t r, uint64_t seed, void *SA,
 /* C = G*(S*A) (Algorithm countgauss_multiply; csrcgs / rmcgs), G the m x r
  * Gaussian matrix with entries of variance 1/m.
  *   m    : rows of G; m == 0 returns S*A as sketch_cs does.
- *   prec : PSK_PREC_F64 or PSK_PREC_BF16 (ignored when m == 0).
+ *   prec : PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8 (ignored when m == 0).
  *   C    : m x d row-major FP64 (m > 0), or r x d in the dtype of A (m == 0).
  * G is generated inside the GEMM and never stored.
  * Errors: as sketch_cs, plus PSK_EDTYPE for an unknown prec. */
@@ -206,12 +213,13 @@ typedef struct psk_lsq_opts {
   int32_t check_every;/* iterations between convergence checks (>=1) */
   double atol;        /* stop when ||(AN)^T r|| <= atol*||AN||*||r|| */
   double btol;        /* or when ||r|| <= btol*||b||                  */
-  double escalate_cond; /* prec == PSK_PREC_BF16: when the factor's  *
+  double escalate_cond; /* prec BF16 / FP8: when the factor's        *
                        * diagonal ratio max|R_ii| / min|R_ii| (a    *
                        * lower estimate of cond(A)) exceeds this,    *
                        * the sketch is rebuilt in FP64 from the same *
-                       * S*A before LSQR starts; 0 selects 1e4,      *
-                       * a negative value never escalates            */
+                       * S*A before LSQR starts; 0 selects 1e4 for   *
+                       * BF16 and 10 for FP8, a negative value never *
+                       * escalates                                   */
 } psk_lsq_opts;
 
 typedef struct psk_lsq_info {

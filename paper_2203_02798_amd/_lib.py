@@ -22,7 +22,7 @@ PSK_PENDING = 1
 PSK_REQ_LSQ, PSK_REQ_LEVERAGE = 0, 1
 PSK_DENSE, PSK_CSR = 0, 1
 PSK_F64, PSK_F32 = 0, 1
-PSK_PREC_F64, PSK_PREC_BF16 = 0, 1
+PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 (PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
  PSK_OP_LSQ) = range(6)
 

@@ -19,7 +19,7 @@ __all__ = [
 ]
 
 PskError = L.PskError
-_PREC = {"f64": L.PSK_PREC_F64, "bf16": L.PSK_PREC_BF16}
+_PREC = {"f64": L.PSK_PREC_F64, "bf16": L.PSK_PREC_BF16, "fp8": L.PSK_PREC_FP8}
 
 
 @dataclass
@@ -201,7 +201,7 @@ def sketch_qr(C):
     return R, Ri
 
 
-_PREC_NAME = {L.PSK_PREC_F64: "f64", L.PSK_PREC_BF16: "bf16", -1: None}
+_PREC_NAME = {L.PSK_PREC_F64: "f64", L.PSK_PREC_BF16: "bf16", L.PSK_PREC_FP8: "fp8", -1: None}
 
 
 def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,

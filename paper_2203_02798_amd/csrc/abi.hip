@@ -248,8 +248,8 @@ int sketch_gcs(const psk_mat *A, int64_t m, int64_t r, uint64_t seed, int prec,
   if (rc) return rc;
   if ((rc = check_r(r))) return rc;
   if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "m must be in [0, 2^31)");
-  if (m > 0 && prec != PSK_PREC_F64 && prec != PSK_PREC_BF16)
-    return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64 or PSK_PREC_BF16");
+  if (m > 0 && prec != PSK_PREC_F64 && prec != PSK_PREC_BF16 && prec != PSK_PREC_FP8)
+    return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
   if (!C) return fail(PSK_EINVAL, "C is NULL");
   Arena plan;
   if ((rc = do_sketch_gcs(*A, m, r, seed, prec, nullptr, plan, nullptr))) return rc;
@@ -320,8 +320,9 @@ int lsq_solve(const psk_mat *A, const double *b, double *x, const psk_lsq_opts *
   }
   if (o.max_iter < 1 || o.check_every < 1 || o.refine < 0)
     return fail(PSK_EINVAL, "lsq_solve needs max_iter >= 1, check_every >= 1, refine >= 0");
-  if (!o.Rinv && o.prec != PSK_PREC_F64 && o.prec != PSK_PREC_BF16)
-    return fail(PSK_EDTYPE, "opts->prec must be PSK_PREC_F64 or PSK_PREC_BF16");
+  if (!o.Rinv && o.prec != PSK_PREC_F64 && o.prec != PSK_PREC_BF16 &&
+      o.prec != PSK_PREC_FP8)
+    return fail(PSK_EDTYPE, "opts->prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
   Arena plan;
   if ((rc = lsq_impl(*A, nullptr, nullptr, o, nullptr, plan, nullptr))) return rc;
   if (!wsp || ws_bytes < plan.peak)

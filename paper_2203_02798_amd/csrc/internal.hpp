@@ -95,6 +95,9 @@ int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
 // The same product with bfloat16 operands (k_gauss_gemm_bf16.hip).
 int gauss_gemm_bf16(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
                     int sa_dtype, double *C, Arena &ws, hipStream_t st);
+// ... and with FP8 e4m3 operands, per-128-bucket E8M0 scales (k_gauss_gemm_fp8.hip).
+int gauss_gemm_fp8(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
+                   int sa_dtype, double *C, Arena &ws, hipStream_t st);
 
 // ---- FP64 dense kernels (k_dense.hip) --------------------------------------
 // C (d x d, out_dtype) = alpha * A^T A + beta * C for dense A.

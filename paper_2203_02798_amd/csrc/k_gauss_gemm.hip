@@ -205,6 +205,7 @@ int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
                const void *SA, int sa_dtype, double *C, Arena &ws,
                hipStream_t st) {
   if (prec == PSK_PREC_BF16) return gauss_gemm_bf16(m, r, d, seed, SA, sa_dtype, C, ws, st);
+  if (prec == PSK_PREC_FP8) return gauss_gemm_fp8(m, r, d, seed, SA, sa_dtype, C, ws, st);
   if (prec != PSK_PREC_F64) return fail(PSK_EDTYPE, "unknown Gaussian GEMM precision");
   const int tiles_m = (int)ceil_div(m, kBM);
   const int tiles_n = (int)ceil_div(d, kBN);

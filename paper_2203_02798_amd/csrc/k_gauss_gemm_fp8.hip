@@ -1,0 +1,327 @@
+// C = G * (S*A) with FP8 e4m3 operands and power-of-two block scales on the
+// gfx950 matrix cores (v_mfma_scale_f32_16x16x128_f8f6f4, FP32 accumulation).
+//
+// Paper mapping (arXiv 2203.02798): Algorithm countgauss_multiply's batched
+// C += G_i * B with both operands quantised to OCP e4m3: every block of 128
+// buckets of a row of G, and of a column of S*A, shares one scale 2^e with
+// e = ceil(log2(amax / 448)) (E8M0), so the block's largest magnitude maps
+// into (224, 448].  The matrix instruction applies the two scales itself
+// (its scale operands are E8M0 exponents, one per row of G and per column
+// of S*A for each 32 values of K; the four of a 128-bucket chunk are equal
+// here).  K-split partial products are summed in FP64 by a second kernel,
+// which applies 1/sqrt(m).
+//
+// Operand layout.  For one 128-bucket chunk, lane l of the instruction
+// (row or column l % 16, lane group g = l / 16) supplies 32 bytes; byte j of
+// group g is taken here to be bucket 32 g + j for both G and S*A, so each
+// product pairs a normal with the S*A entry of the same bucket.  Quantised
+// S*A is stored as [chunk][g][half][column][16 bytes] (written by
+// k_sa_fp8), so the 16 lanes of a group read 256 contiguous bytes per load;
+// its scale bytes as [chunk][512-column tile][column % 16][column / 16 % 32]
+// so that each lane reads the 32 scales of its 32 column blocks as 8 dwords
+// and selects the byte with the instruction's opsel.
+//
+// Tiling as in the BF16 kernel: 512 threads, 128 rows x 512 columns per
+// workgroup, 16 rows x 512 columns (32 blocks) per wavefront, the chunk of
+// quantised S*A and its scales copied into double-buffered LDS by buffer
+// loads one chunk ahead while the next chunk of G is drawn in registers.
+#include "internal.hpp"
+
+namespace psk {
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kBM = 16 * kWaves;  // 128
+constexpr int kBN = 512;
+constexpr int kNB = kBN / 16;     // 32 blocks per wavefront
+constexpr int kBK = 128;          // buckets per chunk = one scale block
+constexpr int kPartBytes = kBN * 16;           // one (g, half) slab: 8 KiB
+constexpr int kDataBytes = 8 * kPartBytes;     // 64 KiB per chunk tile
+constexpr int kScaleBytes = kBN;               // 512 scale bytes per chunk tile
+constexpr int kBufBytes = kDataBytes + kScaleBytes;
+
+// exponent e of the block scale: smallest integer with 448 * 2^e >= amax
+// (amax = f 2^x, f in [1/2, 1); 448 = 0.875 2^9), 0 for amax == 0
+__device__ __forceinline__ int scale_exp_f32(float amax) {
+  int x;
+  const float f = frexpf(amax, &x);
+  const int e = (f <= 0.875f) ? x - 9 : x - 8;
+  return amax > 0.0f ? e : 0;
+}
+__device__ __forceinline__ int scale_exp_f64(double amax) {
+  int x;
+  const double f = frexp(amax, &x);
+  const int e = (f <= 0.875) ? x - 9 : x - 8;
+  return amax > 0.0 ? e : 0;
+}
+
+// FP32 of a double by round-to-odd (then a later RNE to e4m3 is a single
+// correct rounding)
+__device__ __forceinline__ float f32_odd(double v) {
+  float f = (float)v;
+  if ((double)f != v && v == v) {
+    uint32_t b = __float_as_uint(f);
+    if (fabs((double)f) > fabs(v)) b -= 1;
+    b |= 1u;
+    f = __uint_as_float(b);
+  }
+  return f;
+}
+
+// two e4m3 bytes (RNE) packed in the low 16 bits
+__device__ __forceinline__ uint32_t e4m3x2(float a, float b) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xFFFFu;
+}
+
+// Quantise S*A (r x d, dtype T) per column in 128-bucket blocks.  One thread
+// per (chunk, padded column).
+template <typename T>
+__global__ __launch_bounds__(256) void k_sa_fp8(const T *__restrict__ SA, int64_t r, int64_t d,
+                                                int64_t npad, int64_t nkc,
+                                                unsigned char *__restrict__ q,
+                                                unsigned char *__restrict__ sc) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nkc * npad) return;
+  const int64_t n = t % npad;
+  const int64_t kc = t / npad;
+  const int64_t k0 = kc * kBK;
+  double amax = 0.0;
+  if (n < d)
+    for (int i = 0; i < kBK; ++i)
+      if (k0 + i < r) amax = fmax(amax, fabs((double)SA[(k0 + i) * d + n]));
+  int e = scale_exp_f64(amax);
+  e = e < -127 ? -127 : (e > 127 ? 127 : e);
+  const double inv = ldexp(1.0, -e);
+  for (int gh = 0; gh < 8; ++gh) {  // (g, half): buckets 16 gh .. 16 gh + 15
+    uint32_t w[4];
+    for (int p = 0; p < 4; ++p) {
+      float f[4];
+      for (int u = 0; u < 4; ++u) {
+        const int64_t k = k0 + 16 * gh + 4 * p + u;
+        const double v = (n < d && k < r) ? (double)SA[k * d + n] : 0.0;
+        f[u] = f32_odd(v * inv);
+      }
+      w[p] = e4m3x2(f[0], f[1]) | (e4m3x2(f[2], f[3]) << 16);
+    }
+    reinterpret_cast<uint4 *>(q)[(kc * 8 + gh) * npad + n] = uint4{w[0], w[1], w[2], w[3]};
+  }
+  // scale byte at [kc][tile][n % 16][(n / 16) % 32]
+  const int64_t tile = n / kBN, nn = n % kBN;
+  sc[(kc * (npad / kBN) + tile) * kBN + (nn % 16) * kNB + nn / 16] = (unsigned char)(e + 127);
+}
+
+__global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
+    int64_t m, int64_t d, int64_t npad, uint64_t seed, const unsigned char *__restrict__ q,
+    const unsigned char *__restrict__ sc, int tiles_m, int tiles_n, int64_t kchunks,
+    int64_t cper, float *__restrict__ out /* [splits][m][d] */) {
+  __shared__ __align__(16) unsigned char smem[2 * kBufBytes];
+
+  const int64_t nblk = (int64_t)gridDim.x;
+  int64_t lin = blockIdx.x;
+  if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
+  const int mt = (int)(lin % tiles_m);
+  const int64_t rest = lin / tiles_m;
+  const int nt = (int)(rest % tiles_n);
+  const int ks = (int)(rest / tiles_n);
+  const int64_t m0 = (int64_t)mt * kBM;
+  const int64_t n0 = (int64_t)nt * kBN;
+  const int64_t cb = (int64_t)ks * cper;
+  int64_t ce = cb + cper;
+  if (ce > kchunks) ce = kchunks;
+  const int64_t nch = ce > cb ? ce - cb : 0;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int g = lane >> 4;
+  const int li = lane & 15;
+
+  v4f acc[kNB];
+#pragma unroll
+  for (int b = 0; b < kNB; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  // descriptors over this split's chunks: data and scales
+  const int64_t chunk_data = 8 * npad * 16;  // bytes per chunk (all columns)
+  const int64_t chunk_sc = npad;             // scale bytes per chunk
+  const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(q + cb * chunk_data), (short)0, (int)(nch * chunk_data), 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(sc + cb * chunk_sc), (short)0, (int)(nch * chunk_sc), 0x00020000);
+  auto copy_chunk = [&](int64_t crel, int buf) {
+    unsigned char *base = smem + buf * kBufBytes;
+    // 64 KiB of data: 64 pieces of 1 KiB, wave w takes pieces w, w+8, ...
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int piece = wave + kWaves * p;  // 0..63
+      const int gh = piece >> 3;            // (g, half) slab
+      const int off = (piece & 7) * 1024;
+      const int gsrc = (int)(crel * chunk_data + ((int64_t)gh * npad + n0) * 16) + off +
+                       lane * 16;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rq, (lds_ptr_t)(base + gh * kPartBytes + off),
+                                               16, gsrc, 0, 0, 0);
+    }
+    // 512 scale bytes: wave 0, two loads of 64 lanes x 4 bytes
+    if (wave == 0) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int gsrc = (int)(crel * chunk_sc + (int64_t)nt * kBN) + p * 256 + lane * 4;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+            rs, (lds_ptr_t)(base + kDataBytes + p * 256), 4, gsrc, 0, 0, 0);
+      }
+    }
+  };
+
+  const uint32_t row_a = (uint32_t)(m0 + wave * 16 + li);
+  // this lane's 32 normals of chunk c (buckets 128 c + 32 g + j), quantised
+  // with the row's block scale; returns the fragment and sets the E8M0 byte
+  auto make_a = [&](int64_t c_abs, int &sbyte) {
+    float z[32];
+    const uint64_t qb = (uint64_t)c_abs * 32u + 8u * (uint64_t)g;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) gauss4_f32(qb + t, row_a, seed, z + 4 * t);
+    float amax = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) amax = fmaxf(amax, fabsf(z[j]));
+    amax = fmaxf(amax, __shfl_xor(amax, 16, 64));
+    amax = fmaxf(amax, __shfl_xor(amax, 32, 64));
+    const int e = scale_exp_f32(amax);
+    sbyte = e + 127;
+    v8i a;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) {
+      const float s0 = ldexpf(z[4 * w + 0], -e), s1 = ldexpf(z[4 * w + 1], -e);
+      const float s2 = ldexpf(z[4 * w + 2], -e), s3 = ldexpf(z[4 * w + 3], -e);
+      a[w] = (int)(e4m3x2(s0, s1) | (e4m3x2(s2, s3) << 16));
+    }
+    return a;
+  };
+
+  v8i a_cur;
+  int sa_cur = 127;
+  if (nch > 0) {
+    copy_chunk(0, 0);
+    a_cur = make_a(cb, sa_cur);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+  for (int64_t c = 0; c < nch; ++c) {
+    const int buf = (int)(c & 1);
+    copy_chunk(c + 1, buf ^ 1);  // past the split: range check reads zeros
+    int sa_next;
+    const v8i a_next = make_a(cb + c + 1, sa_next);
+    const unsigned char *bb = smem + buf * kBufBytes;
+    const unsigned char *lo = bb + (2 * g) * kPartBytes + li * 16;      // bytes 0..15
+    const unsigned char *hi = bb + (2 * g + 1) * kPartBytes + li * 16;  // bytes 16..31
+    const uint4 *scp = reinterpret_cast<const uint4 *>(bb + kDataBytes + li * kNB);
+    const uint4 s03 = scp[0], s47 = scp[1];
+    const uint32_t sw[8] = {s03.x, s03.y, s03.z, s03.w, s47.x, s47.y, s47.z, s47.w};
+#pragma unroll
+    for (int nb = 0; nb < kNB; ++nb) {
+      const uint4 b0 = *reinterpret_cast<const uint4 *>(lo + nb * 256);
+      const uint4 b1 = *reinterpret_cast<const uint4 *>(hi + nb * 256);
+      const v8i bf = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
+                      (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+      const int sbw = (int)sw[nb >> 2];
+      switch (nb & 3) {
+        case 0:
+          acc[nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a_cur, bf, acc[nb], 0, 0,
+                                                                     0, sa_cur, 0, sbw);
+          break;
+        case 1:
+          acc[nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a_cur, bf, acc[nb], 0, 0,
+                                                                     0, sa_cur, 1, sbw);
+          break;
+        case 2:
+          acc[nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a_cur, bf, acc[nb], 0, 0,
+                                                                     0, sa_cur, 2, sbw);
+          break;
+        default:
+          acc[nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a_cur, bf, acc[nb], 0, 0,
+                                                                     0, sa_cur, 3, sbw);
+          break;
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    a_cur = a_next;
+    sa_cur = sa_next;
+  }
+
+  // accumulator element e of block nb: row 4 g + e, column li
+  float *o = out + (int64_t)ks * m * d;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t row = m0 + wave * 16 + 4 * g + e;
+    if (row >= m) continue;
+#pragma unroll
+    for (int nb = 0; nb < kNB; ++nb) {
+      const int64_t col = n0 + nb * 16 + li;
+      if (col < d) o[row * d + col] = acc[nb][e];
+    }
+  }
+}
+
+// C[i] = scale * sum_s part[s][i] (FP32 partials summed in FP64, fixed order)
+__global__ __launch_bounds__(256) void k_reduce_fp8(const float *__restrict__ part, int64_t len,
+                                                    int splits, double scale,
+                                                    double *__restrict__ C) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= len) return;
+  double acc = (double)part[i];
+  for (int s = 1; s < splits; ++s) acc += (double)part[(int64_t)s * len + i];
+  C[i] = acc * scale;
+}
+
+}  // namespace
+
+int gauss_gemm_fp8(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
+                   int sa_dtype, double *C, Arena &ws, hipStream_t st) {
+  const int tiles_m = (int)ceil_div(m, kBM);
+  const int tiles_n = (int)ceil_div(d, kBN);
+  const int64_t npad = (int64_t)tiles_n * kBN;
+  const int64_t kchunks = ceil_div(r, kBK);
+  const int64_t tiles = (int64_t)tiles_m * tiles_n;
+  int64_t splits = ceil_div(512, tiles);
+  const int64_t max_splits = kchunks / 8 > 0 ? kchunks / 8 : 1;
+  if (splits > max_splits) splits = max_splits;
+  if (splits < 1) splits = 1;
+  const int64_t cper = ceil_div(kchunks, splits);
+  splits = ceil_div(kchunks, cper);
+  if ((cper + 1) * 8 * npad * 16 + 65536 >= ((int64_t)1 << 31))
+    return fail(PSK_EUNSUPPORTED, "FP8 Gaussian GEMM: K slice too large for one descriptor");
+  unsigned char *q = ws.take<unsigned char>((size_t)(kchunks * 8 * npad * 16));
+  unsigned char *sc = ws.take<unsigned char>((size_t)(kchunks * npad));
+  float *part = ws.take<float>((size_t)splits * m * d);
+  if (ws.dry()) return 0;
+  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the FP8 Gaussian GEMM");
+  {
+    KTimer t("sa_quant", st);
+    const int64_t threads = kchunks * npad;
+    if (sa_dtype == PSK_F64)
+      k_sa_fp8<double><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
+          (const double *)SA, r, d, npad, kchunks, q, sc);
+    else
+      k_sa_fp8<float><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
+          (const float *)SA, r, d, npad, kchunks, q, sc);
+  }
+  {
+    KTimer t("gauss_gemm", st);
+    k_gauss_gemm_fp8<<<(unsigned)(tiles * splits), kThreads, 0, st>>>(
+        m, d, npad, seed, q, sc, tiles_m, tiles_n, kchunks, cper, part);
+  }
+  {
+    KTimer t("gemm_reduce", st);
+    const int64_t len = m * d;
+    k_reduce_fp8<<<(unsigned)ceil_div(len, 256), 256, 0, st>>>(part, len, (int)splits,
+                                                                 1.0 / sqrt((double)m), C);
+  }
+  PSK_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace psk

@@ -599,8 +599,12 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   int rc = 0;
   int *flag = nullptr;
   int prec_used = o.prec;
-  const double cond_limit = o.escalate_cond == 0.0 ? 1e4 : o.escalate_cond;
-  const bool may_escalate = own && o.prec == PSK_PREC_BF16 && cond_limit > 0.0;
+  // default limits: the BF16 sketch carries ~1e-5 relative error, the FP8
+  // one ~5e-2
+  const double cond_limit =
+      o.escalate_cond != 0.0 ? o.escalate_cond : (o.prec == PSK_PREC_FP8 ? 10.0 : 1e4);
+  const bool may_escalate =
+      own && (o.prec == PSK_PREC_BF16 || o.prec == PSK_PREC_FP8) && cond_limit > 0.0;
   void *SA = nullptr;
   if (own) {
     // sketch and factor (their scratch is released afterwards); S*A stays

@@ -254,8 +254,8 @@ int psk_server_submit(psk_server *srv, const psk_request *q, int64_t *ticket) {
     if ((rc = check_r(o.r))) return rc;
     if (o.r < o.m) return fail(PSK_EINVAL, "opts.r must be >= opts.m");
   }
-  if (o.prec != PSK_PREC_F64 && o.prec != PSK_PREC_BF16)
-    return fail(PSK_EDTYPE, "opts.prec must be PSK_PREC_F64 or PSK_PREC_BF16");
+  if (o.prec != PSK_PREC_F64 && o.prec != PSK_PREC_BF16 && o.prec != PSK_PREC_FP8)
+    return fail(PSK_EDTYPE, "opts.prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
   size_t bytes = 0;
   if ((rc = plan_request(*q, &bytes))) return rc;
   if (bytes > s->pool_bytes)

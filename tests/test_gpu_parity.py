@@ -189,6 +189,53 @@ def test_sketch_gcs_bf16(api, kind, n, d, m, r):
     assert e_fmt <= 1e-2
 
 
+# FP8 e4m3 with per-128-bucket power-of-two scales.  Kernel arithmetic is
+# checked against the quantisation-aware product at 5e-4 normwise: the
+# device draws the normals in FP32, so about 2 in 1e6 of them round to the
+# neighbouring e4m3 value of the FP64 oracle's (relative quantum 2^-3), each
+# moving C by about 0.1 / sqrt(m r) of its norm.
+@pytest.mark.parametrize("kind,n,d,m,r", [
+    ("dense", 20000, 50, 200, 2500),
+    ("dense", 6000, 130, 77, 3001),
+    ("dense", 3000, 600, 150, 1000),     # two 512-column tiles, ragged
+    ("dense", 500, 3, 5, 7),             # one partial 128-bucket chunk
+    ("csr", 100000, 500, 300, 25000),
+    ("dense32", 8000, 96, 129, 1024)])
+def test_sketch_gcs_fp8(api, kind, n, d, m, r):
+    _say(f"sketch_gcs fp8 {kind} n={n} d={d} m={m} r={r}")
+    if kind == "csr":
+        a = synth.csr_uniform(n, d, 1e-3, seed=1)
+    elif kind == "dense32":
+        a = synth.dense_gaussian(n, d, seed=1, dtype=np.float32)
+    else:
+        a = synth.dense_gaussian(n, d, seed=1)
+    c = api.sketch_gcs(to_device(a), m, r, seed=21, prec="fp8").cpu().numpy()
+    e_arith = rel_fro(c, osk.sketch_gcs_fp8_reference(a, m, r, 21))
+    e_fmt = rel_fro(c, osk.sketch_gcs(a, m, r, 21))
+    _say(f"  vs quantised reference {e_arith:.3e}, vs FP64 {e_fmt:.3e}")
+    assert e_arith <= 5e-4
+    assert e_fmt <= 1e-1
+
+
+def test_sketch_gcs_fp8_deterministic(api):
+    a = to_device(synth.csr_uniform(50000, 200, 5e-3, seed=3))
+    c1 = api.sketch_gcs(a, 150, 8000, seed=5, prec="fp8")
+    c2 = api.sketch_gcs(a, 150, 8000, seed=5, prec="fp8")
+    assert torch.equal(c1, c2)
+
+
+@pytest.mark.parametrize("cond,want", [(1.0, "fp8"), (1e3, "f64")])
+def test_lsq_solve_fp8_sketch(api, cond, want):
+    a, b, _ = synth.lsq_problem(20000, 32, cond, seed=2)
+    x, info = api.lsq_solve(to_device(a), torch.from_numpy(b).cuda(), m=8 * 32, r=32 * 32,
+                            seed=3, prec="fp8")
+    _say(f"lsq fp8 cond={cond}: {info}")
+    assert info["prec_used"] == want and info["status"] == "PSK_OK"
+    rs, _ = olsq.lsq_quality(a, b, olsq.lstsq(a, b))
+    rn, ne = olsq.lsq_quality(a, b, x.cpu().numpy())
+    assert (rn - rs) / rs <= 1e-10 and ne <= 1e-10
+
+
 def test_sketch_gcs_bf16_deterministic(api):
     a = to_device(synth.csr_uniform(50000, 200, 5e-3, seed=3))
     c1 = api.sketch_gcs(a, 150, 8000, seed=5, prec="bf16")
