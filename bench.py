@@ -43,6 +43,7 @@ WORKLOADS = {
 }
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP8_TFLOPS = 5000.0
 
 # HBM bytes per launch of the Gaussian GEMM from hardware counters
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors measured on a copy
@@ -252,9 +253,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="csr-1e6x500", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="both", choices=["f64", "bf16", "both"],
-                    help="Gaussian GEMM precision; 'both' times the FP64 plain path "
-                         "and the BF16 path and reports BF16 as the headline")
+    ap.add_argument("--prec", default="all", choices=["f64", "bf16", "fp8", "all"],
+                    help="Gaussian GEMM precision; 'all' times the FP64 plain path, "
+                         "the BF16 path and the FP8 path and reports BF16 as the "
+                         "headline")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
@@ -333,7 +335,7 @@ def main():
         per = {k: v[0] / args.steps for k, v in stats.items()}
         gg_ms, gg_n = stats.get("gauss_gemm", (0.0, 0))
         sketch_ms = sum(per.get(k, 0.0) for k in ("cs_bin", "cs_scatter", "sa_limbs",
-                                                   "gauss_gemm", "gemm_reduce"))
+                                                   "sa_quant", "gauss_gemm", "gemm_reduce"))
         # residual of the returned solution, for the FP64-vs-BF16 comparison
         x = out[3].cpu().numpy()
         res = float(np.linalg.norm(b - a @ x))
@@ -349,12 +351,13 @@ def main():
             "gg_avg_ms": gg_ms / max(gg_n, 1),
         }
 
-    paths = [args.prec] if args.prec != "both" else ["f64", "bf16"]
+    paths = [args.prec] if args.prec != "all" else ["f64", "bf16", "fp8"]
     res = {p: run_path(p) for p in paths}
     head = "bf16" if "bf16" in res else paths[0]
     hr = res[head]
     flops = (2.0 * r - 1.0) * m * d
-    peak = PEAK_FP64_TFLOPS if head == "f64" else PEAK_BF16_TFLOPS
+    peak = {"f64": PEAK_FP64_TFLOPS, "bf16": PEAK_BF16_TFLOPS,
+            "fp8": PEAK_FP8_TFLOPS}[head]
     gg_avg = hr["gg_avg_ms"]
     achieved = flops / (gg_avg * 1e-3) / 1e12 if gg_avg > 0 else 0.0
     rec = {
@@ -369,9 +372,11 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": head,
-        "dtype_detail": ("Gaussian GEMM bf16 operands with fp32 accumulation; hash, "
-                         "S*A, Gram, QR, row norms and LSQR in f64") if head == "bf16"
-                        else "f64 throughout",
+        "dtype_detail": {"bf16": "Gaussian GEMM bf16 operands with fp32 accumulation; "
+                                 "hash, S*A, Gram, QR, row norms and LSQR in f64",
+                         "fp8": "Gaussian GEMM fp8 e4m3 operands (per-128 E8M0 scales) "
+                                "with fp32 accumulation; the rest in f64",
+                         "f64": "f64 throughout"}[head],
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d,
                    "nnz": int(a.nnz) if kind == "csr" else n * d,
@@ -389,12 +394,20 @@ def main():
                      "launch_ms": gg_avg,
                      "flops_per_launch": flops},
     }
+    keys = ("value", "ms_per_step", "solves_per_s", "p50_ms", "p99_ms", "sketch_gcs_gbs",
+            "stage_ms", "lsq")
     if head != "f64" and "f64" in res:
         f = res["f64"]
-        rec["fp64_path"] = {k: f[k] for k in ("value", "ms_per_step", "solves_per_s",
-                                             "p50_ms", "p99_ms", "sketch_gcs_gbs",
-                                             "stage_ms", "lsq")}
+        rec["fp64_path"] = {k: f[k] for k in keys}
         rec["speedup_vs_fp64_path"] = f["ms_per_step"] / hr["ms_per_step"]
+    if head != "fp8" and "fp8" in res:
+        f = res["fp8"]
+        rec["fp8_path"] = {k: f[k] for k in keys}
+        gg = f["gg_avg_ms"]
+        rec["fp8_path"]["gauss_gemm_roofline"] = {
+            "achieved": flops / (gg * 1e-3) / 1e12 if gg > 0 else 0.0,
+            "peak": PEAK_FP8_TFLOPS, "unit": "TFLOP/s",
+            "frac": (flops / (gg * 1e-3) / 1e12) / PEAK_FP8_TFLOPS if gg > 0 else 0.0}
     if not args.no_serving:
         rec["serving"] = serving_bench(api, torch, dev)
     if not args.no_cpu_baseline:

@@ -1,0 +1,137 @@
+"""Parity at full size: the sparse bench workload (CSR 1e6 x 500, density
+1e-3, FP64, r = 250,000, m = 2,000) in the launch configuration bench.py
+times, and the Zipf workload (CSR 1e7 x 1000 FP32, density 1e-4, r = 1e6,
+m = 4,000, FP8 sketch).  Outputs the oracle cannot produce whole are checked
+on samples it computes one by one (the first rows of G times sampled
+columns of S*A), or through properties that hold at any size (the hash of
+every row, the Gram matrix, row norms with the device's own R^{-1}, the
+optimality of the least-squares solutions)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from helpers import gamma, rel_fro, to_device
+from oracle import gram as og
+from oracle import sketch as osk
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2203_02798_amd import api as a
+    return a
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _sampled_block(a, m, r, seed, rows, cols, prec):
+    """Oracle C[:rows, cols] for the given precision's definition."""
+    z = osk.gaussian_normals(rows, 0, r, seed)
+    sa = osk.sketch_cs(a[:, cols], r, seed)
+    if prec == "f64":
+        return z @ sa / np.sqrt(m)
+    if prec == "bf16":
+        hi, lo = osk.bf16_limbs(sa, 2)
+        return osk.to_bf16(z) @ (hi + lo) / np.sqrt(m)
+    zq, _ = osk.quantize_e4m3_blocks(z, 128, axis=1)
+    saq, _ = osk.quantize_e4m3_blocks(sa, 128, axis=0)
+    return zq @ saq / np.sqrt(m)
+
+
+def test_fullsize_sparse_bench_workload(api):
+    n, d, dens, r, m, seed = 1_000_000, 500, 1e-3, 250_000, 2000, 0
+    _say("generating CSR 1e6 x 500")
+    a = synth.csr_uniform(n, d, dens, seed=seed)
+    A = to_device(a)
+    # hash and sign of every row, bit for bit
+    _say("hash of all rows")
+    h, s = api.cs_hash(n, r, seed)
+    ho, so = osk.cs_hash(n, r, seed)
+    np.testing.assert_array_equal(h.cpu().numpy().astype(np.int64), ho)
+    np.testing.assert_array_equal(s.cpu().numpy(), so)
+    # sketches: first 8 rows of C on 16 sampled columns
+    cols = np.sort(np.random.default_rng(1).choice(d, 16, replace=False))
+    tol = {"f64": 1e-12, "bf16": 1e-4, "fp8": 5e-4}
+    fmt = {"bf16": 1e-2, "fp8": 1e-1}
+    ref64 = _sampled_block(a, m, r, seed, 8, cols, "f64")
+    C64 = None
+    for prec in ("f64", "bf16", "fp8"):
+        _say(f"sketch_gcs {prec}")
+        C = api.sketch_gcs(A, m, r, seed, prec=prec)
+        blk = C[:8].cpu().numpy()[:, cols]
+        ref = ref64 if prec == "f64" else _sampled_block(a, m, r, seed, 8, cols, prec)
+        e = rel_fro(blk, ref)
+        _say(f"  sampled block vs its definition {e:.3e}")
+        assert e <= tol[prec]
+        if prec != "f64":
+            assert rel_fro(blk, ref64) <= fmt[prec]
+        else:
+            C64 = C
+    # Gram matrix, whole
+    _say("gram")
+    G = api.gram(A).cpu().numpy()
+    Go = og.gram(1.0, a)
+    assert rel_fro(G, Go) <= 1e-13 and np.array_equal(G, G.T)
+    # leverage scores with the device's own R^{-1}: sampled rows against the
+    # oracle's row norms with the same B, within 3 gamma_N z_i
+    _, Ri = api.sketch_qr(C64)
+    th = api.rownorms_sq(A, Ri).cpu().numpy()
+    B = Ri.cpu().numpy()
+    rows = np.random.default_rng(2).choice(n, 20000, replace=False)
+    sub = a[rows]
+    want = og.rownorms_sq(1.0, sub, B)
+    zb = og.rownorm_bound_terms(sub, B)
+    N = max(B.shape[1], int(np.diff(sub.indptr).max()) ** 2) + d + 2
+    u = 2.0 ** -53
+    assert np.all(np.abs(th[rows] - want) <= 3 * gamma(N, u) * zb + 4 * u * np.abs(want)
+                  + 1e-300)
+    # least squares: optimality of the FP64 and BF16 sketch solutions
+    rng = np.random.default_rng(1)
+    b = a @ rng.standard_normal(d) + 1e-3 * rng.standard_normal(n)
+    bd = torch.from_numpy(b).cuda()
+    fro = sp.linalg.norm(a)
+    res = {}
+    for prec in ("f64", "bf16"):
+        _say(f"lsq_solve {prec}")
+        x, info = api.lsq_solve(A, bd, m=m, r=r, seed=seed, prec=prec)
+        assert info["status"] == "PSK_OK"
+        rv = b - a @ x.cpu().numpy()
+        res[prec] = np.linalg.norm(rv)
+        assert np.linalg.norm(a.T @ rv) / (fro * res[prec]) <= 1e-10
+    assert abs(res["bf16"] - res["f64"]) / res["f64"] <= 1e-10
+
+
+def test_fullsize_zipf_fp8_workload(api):
+    n, d, dens, r, m, seed = 10_000_000, 1000, 1e-4, 1_000_000, 4000, 0
+    _say("generating Zipf CSR 1e7 x 1000 FP32")
+    a = synth.csr_zipf(n, d, dens, seed=seed, dtype=np.float32)
+    A = to_device(a)
+    _say(f"  nnz {a.nnz}, non-empty rows {(np.diff(a.indptr) > 0).sum()}")
+    _say("hash of all rows")
+    h, s = api.cs_hash(n, r, seed)
+    ho, so = osk.cs_hash(n, r, seed)
+    np.testing.assert_array_equal(h.cpu().numpy().astype(np.int64), ho)
+    np.testing.assert_array_equal(s.cpu().numpy(), so)
+    cols = np.sort(np.random.default_rng(3).choice(d, 12, replace=False))
+    ref64 = _sampled_block(a, m, r, seed, 8, cols, "f64")
+    for prec, tol in (("fp8", 5e-4), ("f64", 1e-12)):
+        _say(f"sketch_gcs {prec}")
+        C = api.sketch_gcs(A, m, r, seed, prec=prec)
+        blk = C[:8].cpu().numpy()[:, cols]
+        ref = ref64 if prec == "f64" else _sampled_block(a, m, r, seed, 8, cols, prec)
+        # S*A is accumulated in FP32 for FP32 input; the f64 GEMM sees it
+        e = rel_fro(blk, ref)
+        _say(f"  sampled block vs its definition {e:.3e}")
+        if prec == "f64":
+            assert e <= 1e-6   # FP32 accumulation of S*A (input FP32)
+        else:
+            assert e <= tol
+            assert rel_fro(blk, ref64) <= 1e-1
+        del C
+        torch.cuda.empty_cache()
