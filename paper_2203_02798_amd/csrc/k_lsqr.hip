@@ -10,16 +10,18 @@
 // One LSQR iteration reads A once: for every row, u_i <- A_i vhat - alpha u_i
 // and A_i^T u_i is accumulated immediately (the normalisation by beta is a
 // scalar applied afterwards), so the two products A v and A^T u of the
-// bidiagonalisation share one pass over A.  An iteration is five kernels:
-//   pass   (1024 workgroups) per-workgroup partial A^T u and ||u||^2;
-//   reduce (d/64 x 16)       first level of the partial sums;
-//   vnew   (d/8)             t = A^T u / beta, vnew = R^{-T} t - beta v;
-//   update (1 workgroup)     scalar recurrences, v, w, y, stopping test;
-//   vhat   (d/8)             vhat = R^{-1} v for the next pass.
+// bidiagonalisation share one pass over A.  An iteration is four kernels:
+//   pass    (1024 workgroups) per-workgroup partial A^T u and ||u||^2;
+//   reduce  (d/64 x 16)       first level of the partial sums;
+//   vnew    (d/8)             t = A^T u / beta, vnew = R^{-T} t - beta v;
+//   update  (d/8)             vhat = R^{-1} vnew / alpha for the next pass,
+//                             and (workgroup 0) the scalar recurrences, v, w,
+//                             y and the stopping test.
 // All state stays on the device; a `done` flag set by the stopping test turns
 // the remaining enqueued iterations into no-ops, so the host synchronises
 // only every `check_every` iterations.  Every sum has a fixed order (CSR rows
-// scatter A_i^T u_i into per-wavefront LDS rows in row order).
+// scatter A_i^T u_i into per-wavefront LDS rows in a fixed instruction
+// order).
 #include <math.h>
 
 #include "internal.hpp"
@@ -36,6 +38,7 @@ struct LsqrState {
 constexpr int kPassBlocks = 1024;
 constexpr int kRedGroups = 16;  // kPassBlocks / kRedGroups = 64 partials per group
 constexpr int kShortRow = 16;   // CSR rows up to this length take one lane each
+constexpr int kRowsPerLane = 4; // CSR rows a lane works on at once in a pass
 
 __device__ __forceinline__ void block_rows(int64_t n, int64_t &r0, int64_t &r1) {
   const int64_t per = ceil_div(n, (int64_t)gridDim.x);
@@ -65,49 +68,97 @@ __global__ __launch_bounds__(256) void k_pass_csr(
   int64_t rb0, rb1;
   block_rows(n, rb0, rb1);
   double b2 = 0.0;
-  for (int64_t base = rb0 + wave * 64; base < rb1; base += 256) {
-    const int64_t i = base + lane;
-    const bool have = i < rb1;
-    int64_t p0 = 0, p1 = 0;
-    if (have) {
-      p0 = indptr[i];
-      p1 = indptr[i + 1];
+  // Each lane takes kRowsPerLane rows at once (rows base + 64 r + lane) and
+  // issues their loads together, so the dependent chains indptr -> entries
+  // -> vhat of the rows overlap instead of running one after the other.
+  for (int64_t base = rb0 + wave * 64 * kRowsPerLane; base < rb1;
+       base += 256 * kRowsPerLane) {
+    int64_t p0[kRowsPerLane], p1[kRowsPerLane];
+    bool shortr[kRowsPerLane];
+    uint64_t longmask[kRowsPerLane];
+#pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r) {
+      const int64_t i = base + 64 * r + lane;
+      p0[r] = 0;
+      p1[r] = 0;
+      if (i < rb1) {
+        p0[r] = indptr[i];
+        p1[r] = indptr[i + 1];
+      }
+      const bool lr = (p1[r] - p0[r]) > kShortRow;
+      shortr[r] = !lr;
+      longmask[r] = __ballot(lr);
     }
-    const bool longrow = have && (p1 - p0) > kShortRow;
-    if (have && !longrow) {
-      double ui;
-      if (INIT) {
-        ui = rhs[i];
-      } else {
-        double dot = 0.0;
-        for (int64_t p = p0; p < p1; ++p) dot += (double)vals[p] * vhat[indices[p]];
-        ui = dot - au * u[i];
+    int maxlen = 0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r)
+      if (shortr[r]) maxlen = max(maxlen, (int)(p1[r] - p0[r]));
+    double ui[kRowsPerLane];
+    if (INIT) {
+#pragma unroll
+      for (int r = 0; r < kRowsPerLane; ++r) {
+        const int64_t i = base + 64 * r + lane;
+        ui[r] = (shortr[r] && i < rb1) ? rhs[i] : 0.0;
       }
-      u[i] = ui;
-      b2 += ui * ui;
-      for (int64_t p = p0; p < p1; ++p) atomicAdd(&tw[indices[p]], (double)vals[p] * ui);
+    } else {
+      double dot[kRowsPerLane], uo[kRowsPerLane];
+#pragma unroll
+      for (int r = 0; r < kRowsPerLane; ++r) {
+        const int64_t i = base + 64 * r + lane;
+        dot[r] = 0.0;
+        uo[r] = (shortr[r] && i < rb1) ? u[i] : 0.0;
+      }
+      for (int e = 0; e < maxlen; ++e) {
+#pragma unroll
+        for (int r = 0; r < kRowsPerLane; ++r) {
+          const int64_t p = p0[r] + e;
+          if (shortr[r] && p < p1[r]) dot[r] += (double)vals[p] * vhat[indices[p]];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRowsPerLane; ++r) ui[r] = dot[r] - au * uo[r];
     }
-    uint64_t pending = __ballot(longrow);
-    while (pending) {
-      const int src = __ffsll((unsigned long long)pending) - 1;
-      pending &= pending - 1;
-      const int64_t q0 = __shfl(p0, src, 64);
-      const int64_t q1 = __shfl(p1, src, 64);
-      const int64_t row = __shfl(i, src, 64);
-      double ui;
-      if (INIT) {
-        ui = rhs[row];
-      } else {
-        double dot = 0.0;
-        for (int64_t p = q0 + lane; p < q1; p += 64) dot += (double)vals[p] * vhat[indices[p]];
-        ui = wave_sum(dot) - au * u[row];
+#pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r) {
+      const int64_t i = base + 64 * r + lane;
+      if (shortr[r] && i < rb1) {
+        u[i] = ui[r];
+        b2 += ui[r] * ui[r];
       }
-      if (lane == 0) {
-        u[row] = ui;
-        b2 += ui * ui;
+    }
+    // A^T u into this wavefront's LDS row, rows in the order r, then lanes
+    for (int e = 0; e < maxlen; ++e) {
+#pragma unroll
+      for (int r = 0; r < kRowsPerLane; ++r) {
+        const int64_t p = p0[r] + e;
+        if (shortr[r] && p < p1[r]) atomicAdd(&tw[indices[p]], (double)vals[p] * ui[r]);
       }
-      for (int64_t p = q0 + lane; p < q1; p += 64)
-        atomicAdd(&tw[indices[p]], (double)vals[p] * ui);
+    }
+    // rows longer than kShortRow: the whole wavefront, one row at a time
+#pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r) {
+      uint64_t pending = longmask[r];
+      while (pending) {
+        const int src = __ffsll((unsigned long long)pending) - 1;
+        pending &= pending - 1;
+        const int64_t q0 = __shfl(p0[r], src, 64);
+        const int64_t q1 = __shfl(p1[r], src, 64);
+        const int64_t row = base + 64 * r + src;
+        double uv;
+        if (INIT) {
+          uv = rhs[row];
+        } else {
+          double dt = 0.0;
+          for (int64_t p = q0 + lane; p < q1; p += 64) dt += (double)vals[p] * vhat[indices[p]];
+          uv = wave_sum(dt) - au * u[row];
+        }
+        if (lane == 0) {
+          u[row] = uv;
+          b2 += uv * uv;
+        }
+        for (int64_t p = q0 + lane; p < q1; p += 64)
+          atomicAdd(&tw[indices[p]], (double)vals[p] * uv);
+      }
     }
   }
   b2 = wave_sum(b2);
@@ -305,15 +356,12 @@ __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
   if (blockIdx.x == 0 && tid == 0) st->beta_new = beta;
 }
 
-// scalar recurrences, v/w/y updates and the stopping test (one workgroup)
-__global__ __launch_bounds__(256) void k_update(LsqrState *__restrict__ st, int64_t d,
-                                                double *__restrict__ v,
-                                                const double *__restrict__ vnew,
-                                                double *__restrict__ w,
-                                                double *__restrict__ y,
-                                                const double *__restrict__ part_a2, int nb,
-                                                double atol, double btol, int init) {
-  if (!init && st->done) return;
+// scalar recurrences, v/w/y updates and the stopping test (run by one
+// whole workgroup of 256 threads)
+__device__ void lsqr_update(LsqrState *__restrict__ st, int64_t d, double *__restrict__ v,
+                            const double *__restrict__ vnew, double *__restrict__ w,
+                            double *__restrict__ y, const double *__restrict__ part_a2, int nb,
+                            double atol, double btol, int init) {
   __shared__ double sh[8];
   __shared__ double red[4];
   if (threadIdx.x == 0) {
@@ -508,6 +556,61 @@ __global__ __launch_bounds__(256) void k_resid(const T *__restrict__ vals,
   if (lane == 0) res[i] = b[i] - dot;
 }
 
+// The second half of an iteration in one launch: every workgroup computes
+// alpha = ||vnew|| from the same partial squares in the same order and its
+// rows of vhat = R^{-1} (vnew / alpha); workgroup 0 also runs the scalar
+// recurrences, the v, w, y updates and the stopping test.  Workgroup 0 only
+// writes the state, v, w and y, which no other workgroup of this launch
+// reads; a stop it signals turns the following launches into no-ops.
+__global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ Rinv,
+                                                     int64_t d,
+                                                     const double *__restrict__ vnew,
+                                                     const double *__restrict__ part_a2, int nb,
+                                                     LsqrState *__restrict__ st,
+                                                     double *__restrict__ v,
+                                                     double *__restrict__ w,
+                                                     double *__restrict__ y,
+                                                     double *__restrict__ vhat, double atol,
+                                                     double btol, int init) {
+  if (!init && st->done) return;
+  __shared__ double red[kColsPerBlk][kPhases + 1];
+  __shared__ double ainv_s;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double a2 = 0.0;
+    for (int b = 0; b < nb; ++b) a2 += part_a2[b];
+    const double alpha = sqrt(a2);
+    ainv_s = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  }
+  __syncthreads();
+  const double ainv = ainv_s;
+  const int c = tid >> 5;  // row within the block
+  const int g = tid & 31;  // column phase
+  const int64_t i = (int64_t)blockIdx.x * kColsPerBlk + c;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  if (i < d) {
+    int64_t jj = i + ((g - (i & 31)) & 31);
+    const double *row = Rinv + i * d;
+    for (; jj + 3 * kPhases < d; jj += 4 * kPhases) {
+      a0 += row[jj] * vnew[jj];
+      a1 += row[jj + kPhases] * vnew[jj + kPhases];
+      a2 += row[jj + 2 * kPhases] * vnew[jj + 2 * kPhases];
+      a3 += row[jj + 3 * kPhases] * vnew[jj + 3 * kPhases];
+    }
+    for (; jj < d; jj += kPhases) a0 += row[jj] * vnew[jj];
+  }
+  red[c][g] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (tid < kColsPerBlk) {
+    const int64_t ii = (int64_t)blockIdx.x * kColsPerBlk + tid;
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kPhases; ++q) t += red[tid][q];
+    if (ii < d) vhat[ii] = t * ainv;
+  }
+  if (blockIdx.x == 0) lsqr_update(st, d, v, vnew, w, y, part_a2, nb, atol, btol, init);
+}
+
 struct LsqBufs {
   double *u, *part_t, *part2, *part_b2, *vnew, *part_a2, *v, *w, *y, *vhat;
   LsqrState *st;
@@ -566,9 +669,8 @@ void one_step(const psk_mat &A, bool init, const LsqBufs &B, const double *Rinv,
                                                                          B.part2, init ? 1 : 0);
   k_vnew<<<nb16, 256, (size_t)d * sizeof(double), s>>>(B.part2, B.part_b2, Rinv, d, B.v, B.st,
                                                        B.vnew, B.part_a2, init ? 1 : 0);
-  k_update<<<1, 256, 0, s>>>(B.st, d, B.v, B.vnew, B.w, B.y, B.part_a2, (int)nb16, o.atol,
-                             o.btol, init ? 1 : 0);
-  k_trmv<<<nb16, 256, 0, s>>>(Rinv, d, B.v, B.vhat, B.st, init ? 0 : 1, 0);
+  k_trmv_update<<<nb16, 256, 0, s>>>(Rinv, d, B.vnew, B.part_a2, (int)nb16, B.st, B.v, B.w,
+                                     B.y, B.vhat, o.atol, o.btol, init ? 1 : 0);
 }
 
 }  // namespace
