@@ -15,13 +15,16 @@
 // load, and the 16 columns of one quad are 256 contiguous bytes (no LDS bank
 // conflicts).  Columns are padded to a multiple of 512 with zeros.
 //
-// Tiling: 512 threads = 8 wavefronts; workgroup tile 128 rows x 512 columns;
-// each wavefront owns 16 rows x 512 columns = 32 blocks (128 FP32
-// accumulators per lane), so every Gaussian value is drawn once per 512
-// columns.  A chunk is 32 buckets: lane (row l%16, quad q = l/16) draws two
-// Philox blocks for buckets k0+8q .. k0+8q+7 (FP32 Box-Muller), rounds them
-// to bfloat16 and forms its A fragment.  The limb chunk (2 x 32 KiB) is
-// copied into double-buffered LDS by buffer loads one chunk ahead.
+// Tiling: 512 threads = 8 wavefronts; workgroup tile 128 rows x 512 columns,
+// so every Gaussian value is drawn once per 512 columns.  A chunk is 32
+// buckets: the workgroup draws the chunk's 128 x 32 block of G (FP32
+// Box-Muller, rounded to bfloat16) into LDS once, and the limb chunk of S*A
+// (2 x 32 KiB) is copied into double-buffered LDS by buffer loads one chunk
+// ahead.  Each wavefront owns 64 rows x 128 columns (4 x 8 blocks of 16 x
+// 16, 128 FP32 accumulators per lane): it reads 4 A fragments and 16 B
+// fragments per chunk and issues 64 matrix instructions, so every B
+// fragment read from LDS feeds four of them (LDS bandwidth, not the matrix
+// cores, bounded the one-row-block layout).
 #include "internal.hpp"
 
 namespace psk {
@@ -35,11 +38,14 @@ constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kBM = 16 * kWaves;  // 128
 constexpr int kBN = 512;
-constexpr int kNB = kBN / 16;      // 32 blocks per wavefront
 constexpr int kBK = 32;
 constexpr int kQuadBytes = kBN * 8 * 2;         // 8 KiB: one quad of one chunk-tile
 constexpr int kLimbBytes = 4 * kQuadBytes;      // 32 KiB per limb per chunk
 constexpr int kChunkBytes = 2 * kLimbBytes;     // 64 KiB (hi + lo)
+constexpr int kRB = 4;          // 16-row blocks per wavefront (64 rows)
+constexpr int kCB = 8;          // 16-column blocks per wavefront (128 columns)
+constexpr int kGRow = 80;       // LDS row stride of the Gaussian tile (64 B + pad)
+constexpr int kGBytes = kBM * kGRow;  // 10 KiB per Gaussian tile
 
 __device__ __forceinline__ uint16_t bf16_bits(float x) {
   return __builtin_bit_cast(uint16_t, (__bf16)x);  // v_cvt_pk_bf16_f32, RNE
@@ -107,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_bf16(
     int64_t m, int64_t d, int64_t npad, uint64_t seed, const uint16_t *__restrict__ hi,
     const uint16_t *__restrict__ lo, int tiles_m, int tiles_n, int64_t kchunks,
     int64_t cper, float *__restrict__ out /* [splits][m][d] */) {
-  __shared__ __align__(16) unsigned char smem[2 * kChunkBytes];
+  __shared__ __align__(16) unsigned char smem[2 * kChunkBytes + 2 * kGBytes];
 
   const int64_t nblk = (int64_t)gridDim.x;
   int64_t lin = blockIdx.x;
@@ -128,10 +134,14 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_bf16(
   const int lane = tid & 63;
   const int q = lane >> 4;
   const int li = lane & 15;
+  const int wr = wave >> 2;  // rows 64 wr .. 64 wr + 63 of the tile
+  const int wc = wave & 3;   // columns 128 wc .. 128 wc + 127 of the tile
 
-  v4f acc[kNB];
+  v4f acc[kRB][kCB];
 #pragma unroll
-  for (int b = 0; b < kNB; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+    for (int cb2 = 0; cb2 < kCB; ++cb2) acc[rb][cb2] = v4f{0.f, 0.f, 0.f, 0.f};
 
   // buffer descriptors over this split's chunks of each limb
   const int64_t chunk_stride = 4 * npad * 8;  // bf16 elements per chunk
@@ -158,56 +168,72 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_bf16(
     }
   };
 
-  const uint32_t row_a = (uint32_t)(m0 + wave * 16 + li);
-  auto make_a = [&](int64_t c_abs) {
-    // buckets 32 c + 8 q + (0..7): Philox blocks 8c + 2q and 8c + 2q + 1
+  // The Gaussian block of a chunk (128 rows x 32 buckets) is drawn once per
+  // workgroup: thread t takes row t / 4 and buckets 8 (t % 4) .. +7 (two
+  // Philox blocks), rounds them to bfloat16 and stores 16 bytes in the LDS
+  // G tile (row stride kGRow bytes, padded against bank conflicts), from
+  // which the wavefronts read their A fragments.
+  const int grow = tid >> 2, goct = tid & 3;
+  const uint32_t row_g = (uint32_t)(m0 + grow);
+  auto gen_g = [&](int64_t c_abs, int gbuf) {
     float z[8];
-    const uint64_t qb = (uint64_t)c_abs * 8u + 2u * (uint64_t)q;
-    gauss4_f32(qb, row_a, seed, z);
-    gauss4_f32(qb + 1, row_a, seed, z + 4);
+    const uint64_t qb = (uint64_t)c_abs * 8u + 2u * (uint64_t)goct;
+    gauss4_f32(qb, row_g, seed, z);
+    gauss4_f32(qb + 1, row_g, seed, z + 4);
     v8bf a;
 #pragma unroll
     for (int e = 0; e < 8; ++e) a[e] = (__bf16)z[e];
-    return a;
+    *reinterpret_cast<v8bf *>(smem + 2 * kChunkBytes + gbuf * kGBytes + grow * kGRow +
+                              goct * 16) = a;
   };
 
-  v8bf a_cur;
   if (nch > 0) {
     copy_chunk(0, 0);
-    a_cur = make_a(cb);
+    gen_g(cb, 0);
     __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();
   for (int64_t c = 0; c < nch; ++c) {
     const int buf = (int)(c & 1);
     copy_chunk(c + 1, buf ^ 1);  // past the split: range check reads zeros
-    const v8bf a_next = make_a(cb + c + 1);
-    const unsigned char *bh = smem + buf * kChunkBytes + q * kQuadBytes + li * 16;
+    gen_g(cb + c + 1, buf ^ 1);  // past the split: an unused tile
+    // A fragments: lane (row li of row block rb, quad q) = 8 bf16 of G
+    const unsigned char *gt = smem + 2 * kChunkBytes + buf * kGBytes;
+    v8bf af[kRB];
+#pragma unroll
+    for (int rb = 0; rb < kRB; ++rb)
+      af[rb] = *reinterpret_cast<const v8bf *>(gt + (wr * 64 + rb * 16 + li) * kGRow + q * 16);
+    const unsigned char *bh = smem + buf * kChunkBytes + q * kQuadBytes + li * 16 +
+                              wc * kCB * 256;
     const unsigned char *bl = bh + kLimbBytes;
 #pragma unroll
-    for (int nb = 0; nb < kNB; ++nb) {
-      const v8bf h = *reinterpret_cast<const v8bf *>(bh + nb * 256);
-      const v8bf l = *reinterpret_cast<const v8bf *>(bl + nb * 256);
-      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur, h, acc[nb], 0, 0, 0);
-      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_cur, l, acc[nb], 0, 0, 0);
+    for (int cb2 = 0; cb2 < kCB; ++cb2) {
+      const v8bf h = *reinterpret_cast<const v8bf *>(bh + cb2 * 256);
+      const v8bf l = *reinterpret_cast<const v8bf *>(bl + cb2 * 256);
+#pragma unroll
+      for (int rb = 0; rb < kRB; ++rb) {
+        acc[rb][cb2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rb], h, acc[rb][cb2], 0, 0, 0);
+        acc[rb][cb2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[rb], l, acc[rb][cb2], 0, 0, 0);
+      }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    a_cur = a_next;
   }
 
-  // accumulator element e of block nb: row 4*q + e, column li
+  // accumulator element e of block (rb, cb2): row 4 q + e, column li
   float *o = out + (int64_t)ks * m * d;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t row = m0 + wave * 16 + 4 * q + e;
-    if (row >= m) continue;
+  for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
-    for (int nb = 0; nb < kNB; ++nb) {
-      const int64_t col = n0 + nb * 16 + li;
-      if (col < d) o[row * d + col] = acc[nb][e];
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = m0 + wr * 64 + rb * 16 + 4 * q + e;
+      if (row >= m) continue;
+#pragma unroll
+      for (int cb2 = 0; cb2 < kCB; ++cb2) {
+        const int64_t col = n0 + (wc * kCB + cb2) * 16 + li;
+        if (col < d) o[row * d + col] = acc[rb][cb2][e];
+      }
     }
-  }
 }
 
 // C[i] = scale * sum_s part[s][i] (FP32 partials summed in FP64, fixed order)
