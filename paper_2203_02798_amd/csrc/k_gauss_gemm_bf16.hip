@@ -44,6 +44,9 @@ constexpr int kLimbBytes = 4 * kQuadBytes;      // 32 KiB per limb per chunk
 constexpr int kChunkBytes = 2 * kLimbBytes;     // 64 KiB (hi + lo)
 constexpr int kRB = 4;          // 16-row blocks per wavefront (64 rows)
 constexpr int kCB = 8;          // 16-column blocks per wavefront (128 columns)
+constexpr int kWR = kBM / 16 / kRB;   // wavefront rows of the tile
+constexpr int kWC = kWaves / kWR;     // wavefront columns of the tile
+static_assert(kWC * kCB * 16 == kBN, "wavefront tiles cover the block");
 constexpr int kGRow = 80;       // LDS row stride of the Gaussian tile (64 B + pad)
 constexpr int kGBytes = kBM * kGRow;  // 10 KiB per Gaussian tile
 
@@ -134,8 +137,8 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_bf16(
   const int lane = tid & 63;
   const int q = lane >> 4;
   const int li = lane & 15;
-  const int wr = wave >> 2;  // rows 64 wr .. 64 wr + 63 of the tile
-  const int wc = wave & 3;   // columns 128 wc .. 128 wc + 127 of the tile
+  const int wr = wave / kWC;  // rows 16 kRB wr .. of the tile
+  const int wc = wave % kWC;  // columns 16 kCB wc .. of the tile
 
   v4f acc[kRB][kCB];
 #pragma unroll
@@ -202,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_bf16(
     v8bf af[kRB];
 #pragma unroll
     for (int rb = 0; rb < kRB; ++rb)
-      af[rb] = *reinterpret_cast<const v8bf *>(gt + (wr * 64 + rb * 16 + li) * kGRow + q * 16);
+      af[rb] = *reinterpret_cast<const v8bf *>(gt + ((wr * kRB + rb) * 16 + li) * kGRow + q * 16);
     const unsigned char *bh = smem + buf * kChunkBytes + q * kQuadBytes + li * 16 +
                               wc * kCB * 256;
     const unsigned char *bl = bh + kLimbBytes;
@@ -226,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_bf16(
   for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t row = m0 + wr * 64 + rb * 16 + 4 * q + e;
+      const int64_t row = m0 + (wr * kRB + rb) * 16 + 4 * q + e;
       if (row >= m) continue;
 #pragma unroll
       for (int cb2 = 0; cb2 < kCB; ++cb2) {
