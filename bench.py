@@ -14,9 +14,9 @@ Gaussian with m = 2,000 rows):
 
 Inputs are synthetic and seeded (the paper's matrices are random with
 unstated distributions) and are resident in HBM before timing starts.
-Both the FP64 plain path and the path with the BF16 Gaussian GEMM are timed
-(``--prec both``, the default); the BF16 path is the headline and the FP64
-path is reported beside it.  Prints ONE JSON line.  ``value`` is GB/s of A
+The FP64 plain path and the paths with the BF16 and FP8 Gaussian GEMMs are
+all timed (``--prec all``, the default); the BF16 path is the headline and
+the other two are reported beside it.  Prints ONE JSON line.  ``value`` is GB/s of A
 through the whole step (bytes of A = values + column indices + row
 pointers, per step, divided by the step time).  The dominant kernel (the Gaussian GEMM) is timed with HIP
 events on its own stream inside the library and reported as a roofline

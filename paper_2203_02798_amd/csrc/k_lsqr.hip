@@ -39,6 +39,7 @@ constexpr int kPassBlocks = 1024;
 constexpr int kRedGroups = 16;  // kPassBlocks / kRedGroups = 64 partials per group
 constexpr int kShortRow = 16;   // CSR rows up to this length take one lane each
 constexpr int kRowsPerLane = 4; // CSR rows a lane works on at once in a pass
+constexpr int kRegEntries = 4;  // entries per short CSR row held in registers
 
 __device__ __forceinline__ void block_rows(int64_t n, int64_t &r0, int64_t &r1) {
   const int64_t per = ceil_div(n, (int64_t)gridDim.x);
@@ -47,9 +48,15 @@ __device__ __forceinline__ void block_rows(int64_t n, int64_t &r0, int64_t &r1) 
   if (r1 > n) r1 = n;
 }
 
-// partial A^T u and ||u||^2 of this workgroup's rows, u_i updated in place
+// partial A^T u and ||u||^2 of this workgroup's rows, u_i updated in place.
+// vhat is staged in LDS, so the gathers vhat[col] are LDS reads; the first
+// kRegEntries entries of every short row are loaded at once and kept in
+// registers for both products (A vhat and A^T u), so a row costs two
+// dependent global loads (row pointers, then entries) whatever its length up
+// to kRegEntries.  Additions keep the order: entries in sequence within a
+// row; rows r, then lanes, into a wavefront's LDS accumulator row.
 template <typename T, bool INIT>
-__global__ __launch_bounds__(256) void k_pass_csr(
+__global__ __launch_bounds__(256, 4) void k_pass_csr(
     const T *__restrict__ vals, const int64_t *__restrict__ indptr,
     const int32_t *__restrict__ indices, int64_t n, int64_t d,
     const double *__restrict__ vhat, const double *__restrict__ rhs,
@@ -57,9 +64,12 @@ __global__ __launch_bounds__(256) void k_pass_csr(
     double *__restrict__ part_t, double *__restrict__ part_b2) {
   if (!INIT && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *tl = reinterpret_cast<double *>(smem_raw);
+  double *tl = reinterpret_cast<double *>(smem_raw);  // 4 x d accumulators
+  double *vh = tl + 4 * d;                             // vhat, d
   __shared__ double b2s[4];
   for (int64_t c = threadIdx.x; c < 4 * d; c += 256) tl[c] = 0.0;
+  if (!INIT)
+    for (int64_t c = threadIdx.x; c < d; c += 256) vh[c] = vhat[c];
   __syncthreads();
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -68,51 +78,66 @@ __global__ __launch_bounds__(256) void k_pass_csr(
   int64_t rb0, rb1;
   block_rows(n, rb0, rb1);
   double b2 = 0.0;
-  // Each lane takes kRowsPerLane rows at once (rows base + 64 r + lane) and
-  // issues their loads together, so the dependent chains indptr -> entries
-  // -> vhat of the rows overlap instead of running one after the other.
   for (int64_t base = rb0 + wave * 64 * kRowsPerLane; base < rb1;
        base += 256 * kRowsPerLane) {
-    int64_t p0[kRowsPerLane], p1[kRowsPerLane];
-    bool shortr[kRowsPerLane];
+    int64_t p0[kRowsPerLane];
+    int len[kRowsPerLane];  // entries of a short row, 0 for long or absent rows
     uint64_t longmask[kRowsPerLane];
 #pragma unroll
     for (int r = 0; r < kRowsPerLane; ++r) {
       const int64_t i = base + 64 * r + lane;
-      p0[r] = 0;
-      p1[r] = 0;
+      int64_t q0 = 0, q1 = 0;
       if (i < rb1) {
-        p0[r] = indptr[i];
-        p1[r] = indptr[i + 1];
+        q0 = indptr[i];
+        q1 = indptr[i + 1];
       }
-      const bool lr = (p1[r] - p0[r]) > kShortRow;
-      shortr[r] = !lr;
+      const bool lr = (q1 - q0) > kShortRow;
+      p0[r] = q0;
+      len[r] = lr ? 0 : (int)(q1 - q0);
       longmask[r] = __ballot(lr);
     }
     int maxlen = 0;
 #pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r) maxlen = max(maxlen, len[r]);
+    // the first kRegEntries entries of every short row, all loads issued together
+    int ci[kRowsPerLane][kRegEntries];
+    double xv[kRowsPerLane][kRegEntries];
+#pragma unroll
     for (int r = 0; r < kRowsPerLane; ++r)
-      if (shortr[r]) maxlen = max(maxlen, (int)(p1[r] - p0[r]));
+#pragma unroll
+      for (int e = 0; e < kRegEntries; ++e) {
+        ci[r][e] = 0;
+        xv[r][e] = 0.0;
+        if (e < len[r]) {
+          ci[r][e] = indices[p0[r] + e];
+          xv[r][e] = (double)vals[p0[r] + e];
+        }
+      }
     double ui[kRowsPerLane];
     if (INIT) {
 #pragma unroll
       for (int r = 0; r < kRowsPerLane; ++r) {
         const int64_t i = base + 64 * r + lane;
-        ui[r] = (shortr[r] && i < rb1) ? rhs[i] : 0.0;
+        ui[r] = (i < rb1 && !((longmask[r] >> lane) & 1)) ? rhs[i] : 0.0;
       }
     } else {
       double dot[kRowsPerLane], uo[kRowsPerLane];
 #pragma unroll
       for (int r = 0; r < kRowsPerLane; ++r) {
         const int64_t i = base + 64 * r + lane;
+        uo[r] = (i < rb1 && !((longmask[r] >> lane) & 1)) ? u[i] : 0.0;
         dot[r] = 0.0;
-        uo[r] = (shortr[r] && i < rb1) ? u[i] : 0.0;
       }
-      for (int e = 0; e < maxlen; ++e) {
+#pragma unroll
+      for (int e = 0; e < kRegEntries; ++e)
+#pragma unroll
+        for (int r = 0; r < kRowsPerLane; ++r)
+          if (e < len[r]) dot[r] += xv[r][e] * vh[ci[r][e]];
+      for (int e = kRegEntries; e < maxlen; ++e) {
 #pragma unroll
         for (int r = 0; r < kRowsPerLane; ++r) {
           const int64_t p = p0[r] + e;
-          if (shortr[r] && p < p1[r]) dot[r] += (double)vals[p] * vhat[indices[p]];
+          if (e < len[r]) dot[r] += (double)vals[p] * vh[indices[p]];
         }
       }
 #pragma unroll
@@ -121,17 +146,22 @@ __global__ __launch_bounds__(256) void k_pass_csr(
 #pragma unroll
     for (int r = 0; r < kRowsPerLane; ++r) {
       const int64_t i = base + 64 * r + lane;
-      if (shortr[r] && i < rb1) {
+      if (i < rb1 && !((longmask[r] >> lane) & 1)) {
         u[i] = ui[r];
         b2 += ui[r] * ui[r];
       }
     }
-    // A^T u into this wavefront's LDS row, rows in the order r, then lanes
-    for (int e = 0; e < maxlen; ++e) {
+    // A^T u into this wavefront's LDS row, entries e, then rows r, then lanes
+#pragma unroll
+    for (int e = 0; e < kRegEntries; ++e)
+#pragma unroll
+      for (int r = 0; r < kRowsPerLane; ++r)
+        if (e < len[r]) atomicAdd(&tw[ci[r][e]], xv[r][e] * ui[r]);
+    for (int e = kRegEntries; e < maxlen; ++e) {
 #pragma unroll
       for (int r = 0; r < kRowsPerLane; ++r) {
         const int64_t p = p0[r] + e;
-        if (shortr[r] && p < p1[r]) atomicAdd(&tw[indices[p]], (double)vals[p] * ui[r]);
+        if (e < len[r]) atomicAdd(&tw[indices[p]], (double)vals[p] * ui[r]);
       }
     }
     // rows longer than kShortRow: the whole wavefront, one row at a time
@@ -141,15 +171,15 @@ __global__ __launch_bounds__(256) void k_pass_csr(
       while (pending) {
         const int src = __ffsll((unsigned long long)pending) - 1;
         pending &= pending - 1;
-        const int64_t q0 = __shfl(p0[r], src, 64);
-        const int64_t q1 = __shfl(p1[r], src, 64);
         const int64_t row = base + 64 * r + src;
+        const int64_t q0 = indptr[row];
+        const int64_t q1 = indptr[row + 1];
         double uv;
         if (INIT) {
           uv = rhs[row];
         } else {
           double dt = 0.0;
-          for (int64_t p = q0 + lane; p < q1; p += 64) dt += (double)vals[p] * vhat[indices[p]];
+          for (int64_t p = q0 + lane; p < q1; p += 64) dt += (double)vals[p] * vh[indices[p]];
           uv = wave_sum(dt) - au * u[row];
         }
         if (lane == 0) {
@@ -328,6 +358,7 @@ __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   if (j < d) {
     int64_t i = g;
+#pragma unroll 2
     for (; i + 3 * kPhases <= j; i += 4 * kPhases) {
       a0 += Rinv[i * d + j] * tvs[i];
       a1 += Rinv[(i + kPhases) * d + j] * tvs[i + kPhases];
@@ -356,18 +387,32 @@ __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
   if (blockIdx.x == 0 && tid == 0) st->beta_new = beta;
 }
 
+// ||vnew||^2 from the per-workgroup partial squares (nb <= 128), in one
+// fixed order: wavefront 0, lane l adds partials l and l + 64, then the
+// butterfly; lane 0's total is the result everywhere, so every workgroup that
+// calls this gets the same bits.  Returns the value to all threads.
+__device__ double sum_parts_fixed(const double *__restrict__ part, int nb) {
+  __shared__ double tot;
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double v = l < nb ? part[l] : 0.0;
+    if (l + 64 < nb) v += part[l + 64];
+    v = wave_sum(v);
+    if (l == 0) tot = v;
+  }
+  __syncthreads();
+  return tot;
+}
+
 // scalar recurrences, v/w/y updates and the stopping test (run by one
 // whole workgroup of 256 threads)
 __device__ void lsqr_update(LsqrState *__restrict__ st, int64_t d, double *__restrict__ v,
                             const double *__restrict__ vnew, double *__restrict__ w,
-                            double *__restrict__ y, const double *__restrict__ part_a2, int nb,
-                            double atol, double btol, int init) {
+                            double *__restrict__ y, double alpha, double atol, double btol,
+                            int init) {
   __shared__ double sh[8];
   __shared__ double red[4];
   if (threadIdx.x == 0) {
-    double a2 = 0.0;
-    for (int b = 0; b < nb; ++b) a2 += part_a2[b];
-    const double alpha = sqrt(a2);
     const double beta = st->beta_new;
     double phi = 0.0, rho = 1.0, theta = 0.0;
     int done = 0;
@@ -557,10 +602,10 @@ __global__ __launch_bounds__(256) void k_resid(const T *__restrict__ vals,
 }
 
 // The second half of an iteration in one launch: every workgroup computes
-// alpha = ||vnew|| from the same partial squares in the same order and its
-// rows of vhat = R^{-1} (vnew / alpha); workgroup 0 also runs the scalar
-// recurrences, the v, w, y updates and the stopping test.  Workgroup 0 only
-// writes the state, v, w and y, which no other workgroup of this launch
+// alpha = ||vnew|| from the partial squares (the same bits in every
+// workgroup) and rows of vhat = R^{-1} (vnew / alpha), 8 rows per workgroup;
+// the one extra workgroup (index nb) runs the scalar recurrences, the v, w, y
+// updates and the stopping test, which no other workgroup of this launch
 // reads; a stop it signals turns the following launches into no-ops.
 __global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ Rinv,
                                                      int64_t d,
@@ -574,16 +619,13 @@ __global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ 
                                                      double btol, int init) {
   if (!init && st->done) return;
   __shared__ double red[kColsPerBlk][kPhases + 1];
-  __shared__ double ainv_s;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    double a2 = 0.0;
-    for (int b = 0; b < nb; ++b) a2 += part_a2[b];
-    const double alpha = sqrt(a2);
-    ainv_s = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  const double alpha = sqrt(sum_parts_fixed(part_a2, nb));
+  if ((int)blockIdx.x == nb) {
+    lsqr_update(st, d, v, vnew, w, y, alpha, atol, btol, init);
+    return;
   }
-  __syncthreads();
-  const double ainv = ainv_s;
+  const double ainv = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  const int tid = threadIdx.x;
   const int c = tid >> 5;  // row within the block
   const int g = tid & 31;  // column phase
   const int64_t i = (int64_t)blockIdx.x * kColsPerBlk + c;
@@ -591,6 +633,7 @@ __global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ 
   if (i < d) {
     int64_t jj = i + ((g - (i & 31)) & 31);
     const double *row = Rinv + i * d;
+#pragma unroll 2
     for (; jj + 3 * kPhases < d; jj += 4 * kPhases) {
       a0 += row[jj] * vnew[jj];
       a1 += row[jj + kPhases] * vnew[jj + kPhases];
@@ -608,7 +651,6 @@ __global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ 
     for (int q = 0; q < kPhases; ++q) t += red[tid][q];
     if (ii < d) vhat[ii] = t * ainv;
   }
-  if (blockIdx.x == 0) lsqr_update(st, d, v, vnew, w, y, part_a2, nb, atol, btol, init);
 }
 
 struct LsqBufs {
@@ -636,7 +678,7 @@ template <typename T>
 void launch_pass(const psk_mat &A, bool init, const LsqBufs &B, const double *rhs,
                  hipStream_t s) {
   if (A.format == PSK_CSR) {
-    const size_t lds = (size_t)4 * A.d * sizeof(double);
+    const size_t lds = (size_t)5 * A.d * sizeof(double);
     const T *vals = (const T *)A.values;
     if (init)
       k_pass_csr<T, true><<<kPassBlocks, 256, lds, s>>>(vals, A.indptr, A.indices, A.n, A.d,
@@ -669,7 +711,7 @@ void one_step(const psk_mat &A, bool init, const LsqBufs &B, const double *Rinv,
                                                                          B.part2, init ? 1 : 0);
   k_vnew<<<nb16, 256, (size_t)d * sizeof(double), s>>>(B.part2, B.part_b2, Rinv, d, B.v, B.st,
                                                        B.vnew, B.part_a2, init ? 1 : 0);
-  k_trmv_update<<<nb16, 256, 0, s>>>(Rinv, d, B.vnew, B.part_a2, (int)nb16, B.st, B.v, B.w,
+  k_trmv_update<<<nb16 + 1, 256, 0, s>>>(Rinv, d, B.vnew, B.part_a2, (int)nb16, B.st, B.v, B.w,
                                      B.y, B.vhat, o.atol, o.btol, init ? 1 : 0);
 }
 
