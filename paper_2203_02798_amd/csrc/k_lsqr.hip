@@ -67,34 +67,50 @@ __global__ __launch_bounds__(256, 4) void k_pass_csr(
   double *tl = reinterpret_cast<double *>(smem_raw);  // 4 x d accumulators
   double *vh = tl + 4 * d;                             // vhat, d
   __shared__ double b2s[4];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  int64_t rb0, rb1;
+  block_rows(n, rb0, rb1);
+  // row pointers and u (rhs on the first pass) of a batch of rows, fetched
+  // ahead: the first batch's loads are in flight while the LDS is prepared,
+  // the next batch's are issued at the end of the one before
+  int64_t fq0[kRowsPerLane], fq1[kRowsPerLane];
+  double fu[kRowsPerLane];
+  auto fetch = [&](int64_t b) {
+#pragma unroll
+    for (int r = 0; r < kRowsPerLane; ++r) {
+      const int64_t i = b + 64 * r + lane;
+      fq0[r] = 0;
+      fq1[r] = 0;
+      fu[r] = 0.0;
+      if (i < rb1) {
+        fq0[r] = indptr[i];
+        fq1[r] = indptr[i + 1];
+        fu[r] = INIT ? rhs[i] : u[i];
+      }
+    }
+  };
+  int64_t base = rb0 + wave * 64 * kRowsPerLane;
+  fetch(base);
   for (int64_t c = threadIdx.x; c < 4 * d; c += 256) tl[c] = 0.0;
   if (!INIT)
     for (int64_t c = threadIdx.x; c < d; c += 256) vh[c] = vhat[c];
   __syncthreads();
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
   double *tw = tl + (int64_t)wave * d;
   const double au = INIT ? 0.0 : st->alpha * st->ufac;
-  int64_t rb0, rb1;
-  block_rows(n, rb0, rb1);
   double b2 = 0.0;
-  for (int64_t base = rb0 + wave * 64 * kRowsPerLane; base < rb1;
-       base += 256 * kRowsPerLane) {
+  for (; base < rb1; base += 256 * kRowsPerLane) {
     int64_t p0[kRowsPerLane];
     int len[kRowsPerLane];  // entries of a short row, 0 for long or absent rows
     uint64_t longmask[kRowsPerLane];
+    double ux[kRowsPerLane];  // u_i (rhs_i on the first pass) of short rows, else 0
 #pragma unroll
     for (int r = 0; r < kRowsPerLane; ++r) {
-      const int64_t i = base + 64 * r + lane;
-      int64_t q0 = 0, q1 = 0;
-      if (i < rb1) {
-        q0 = indptr[i];
-        q1 = indptr[i + 1];
-      }
-      const bool lr = (q1 - q0) > kShortRow;
-      p0[r] = q0;
-      len[r] = lr ? 0 : (int)(q1 - q0);
+      const bool lr = (fq1[r] - fq0[r]) > kShortRow;
+      p0[r] = fq0[r];
+      len[r] = lr ? 0 : (int)(fq1[r] - fq0[r]);
       longmask[r] = __ballot(lr);
+      ux[r] = lr ? 0.0 : fu[r];
     }
     int maxlen = 0;
 #pragma unroll
@@ -116,18 +132,11 @@ __global__ __launch_bounds__(256, 4) void k_pass_csr(
     double ui[kRowsPerLane];
     if (INIT) {
 #pragma unroll
-      for (int r = 0; r < kRowsPerLane; ++r) {
-        const int64_t i = base + 64 * r + lane;
-        ui[r] = (i < rb1 && !((longmask[r] >> lane) & 1)) ? rhs[i] : 0.0;
-      }
+      for (int r = 0; r < kRowsPerLane; ++r) ui[r] = ux[r];
     } else {
-      double dot[kRowsPerLane], uo[kRowsPerLane];
+      double dot[kRowsPerLane];
 #pragma unroll
-      for (int r = 0; r < kRowsPerLane; ++r) {
-        const int64_t i = base + 64 * r + lane;
-        uo[r] = (i < rb1 && !((longmask[r] >> lane) & 1)) ? u[i] : 0.0;
-        dot[r] = 0.0;
-      }
+      for (int r = 0; r < kRowsPerLane; ++r) dot[r] = 0.0;
 #pragma unroll
       for (int e = 0; e < kRegEntries; ++e)
 #pragma unroll
@@ -141,7 +150,7 @@ __global__ __launch_bounds__(256, 4) void k_pass_csr(
         }
       }
 #pragma unroll
-      for (int r = 0; r < kRowsPerLane; ++r) ui[r] = dot[r] - au * uo[r];
+      for (int r = 0; r < kRowsPerLane; ++r) ui[r] = dot[r] - au * ux[r];
     }
 #pragma unroll
     for (int r = 0; r < kRowsPerLane; ++r) {
@@ -190,6 +199,7 @@ __global__ __launch_bounds__(256, 4) void k_pass_csr(
           atomicAdd(&tw[indices[p]], (double)vals[p] * uv);
       }
     }
+    if (base + 256 * kRowsPerLane < rb1) fetch(base + 256 * kRowsPerLane);
   }
   b2 = wave_sum(b2);
   if (lane == 0) b2s[wave] = b2;
@@ -320,6 +330,32 @@ __global__ __launch_bounds__(256) void k_reduce1(const double *__restrict__ part
 // phases (four independent accumulators each), combined in a fixed order.
 constexpr int kColsPerBlk = 8;
 constexpr int kPhases = 32;
+constexpr int kMaxK = 1024 / kPhases;  // terms per thread in a phase (d <= 1024)
+
+// sum_{k<K} rv[k] * tv[first + kPhases k] with four accumulators: the full
+// quads of k go round-robin to a0..a3, the remaining k to a0, and the result
+// is (a0 + a1) + (a2 + a3).  rv holds the matrix entries, loaded ahead.
+__device__ __forceinline__ double phased_dot(const double (&rv)[kMaxK],
+                                             const double *__restrict__ tv, int64_t first,
+                                             int K) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int full = K & ~3;
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) {
+    if (k < K) {
+      const double t = tv[first + (int64_t)kPhases * k];
+      if (k < full) {
+        if ((k & 3) == 0) a0 += rv[k] * t;
+        else if ((k & 3) == 1) a1 += rv[k] * t;
+        else if ((k & 3) == 2) a2 += rv[k] * t;
+        else a3 += rv[k] * t;
+      } else {
+        a0 += rv[k] * t;
+      }
+    }
+  }
+  return (a0 + a1) + (a2 + a3);
+}
 
 __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
                                               const double *__restrict__ part_b2,
@@ -334,40 +370,58 @@ __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
   __shared__ double red[kPhases][kColsPerBlk + 1];
   __shared__ double bred[4];
   const int tid = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * kColsPerBlk;
+  int64_t ilim = j0 + kColsPerBlk;
+  if (ilim > d) ilim = d;
+  const int g = tid >> 3;
+  const int c = tid & 7;
+  const int64_t j = j0 + c;
+  // terms i = g + kPhases k <= j of column j
+  const int K = (j < d && j >= g) ? (int)((j - g) / kPhases) + 1 : 0;
+  // every global load of the workgroup is issued before the first wait:
+  // the R^{-1} entries, the partial squares and the partial sums of A^T u
+  double rv[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k)
+    rv[k] = k < K ? Rinv[(int64_t)(g + kPhases * k) * d + j] : 0.0;
+  double pb[kPassBlocks / 256];
+#pragma unroll
+  for (int q = 0; q < kPassBlocks / 256; ++q) pb[q] = part_b2[tid + 256 * q];
+  double tp[2][kRedGroups];
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl) {
+    const int64_t i = tid + 256 * sl;
+#pragma unroll
+    for (int gg = 0; gg < kRedGroups; ++gg)
+      tp[sl][gg] = i < ilim ? part2[(int64_t)gg * d + i] : 0.0;
+  }
   // beta from the kPassBlocks partial squares (same fixed order in every block)
   double s = 0.0;
-  for (int b = tid; b < kPassBlocks; b += 256) s += part_b2[b];
+#pragma unroll
+  for (int q = 0; q < kPassBlocks / 256; ++q) s += pb[q];
   s = wave_sum(s);
   if ((tid & 63) == 0) bred[tid >> 6] = s;
   __syncthreads();
   const double beta = sqrt(((bred[0] + bred[1]) + bred[2]) + bred[3]);
   const double binv = beta > 0.0 ? 1.0 / beta : 0.0;
-  const int64_t j0 = (int64_t)blockIdx.x * kColsPerBlk;
-  int64_t ilim = j0 + kColsPerBlk;
-  if (ilim > d) ilim = d;
-  for (int64_t i = tid; i < ilim; i += 256) {
+#pragma unroll
+  for (int sl = 0; sl < 2; ++sl) {
+    const int64_t i = tid + 256 * sl;
+    if (i < ilim) {
+      double t = 0.0;
+#pragma unroll
+      for (int gg = 0; gg < kRedGroups; ++gg) t += tp[sl][gg];
+      tvs[i] = t * binv;
+    }
+  }
+  for (int64_t i = tid + 512; i < ilim; i += 256) {
     double t = 0.0;
 #pragma unroll
-    for (int g = 0; g < kRedGroups; ++g) t += part2[(int64_t)g * d + i];
+    for (int gg = 0; gg < kRedGroups; ++gg) t += part2[(int64_t)gg * d + i];
     tvs[i] = t * binv;
   }
   __syncthreads();
-  const int g = tid >> 3;
-  const int c = tid & 7;
-  const int64_t j = j0 + c;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (j < d) {
-    int64_t i = g;
-#pragma unroll 2
-    for (; i + 3 * kPhases <= j; i += 4 * kPhases) {
-      a0 += Rinv[i * d + j] * tvs[i];
-      a1 += Rinv[(i + kPhases) * d + j] * tvs[i + kPhases];
-      a2 += Rinv[(i + 2 * kPhases) * d + j] * tvs[i + 2 * kPhases];
-      a3 += Rinv[(i + 3 * kPhases) * d + j] * tvs[i + 3 * kPhases];
-    }
-    for (; i <= j; i += kPhases) a0 += Rinv[i * d + j] * tvs[i];
-  }
-  red[g][c] = (a0 + a1) + (a2 + a3);
+  red[g][c] = phased_dot(rv, tvs, g, K);
   __syncthreads();
   if (tid < kColsPerBlk) {
     double sj = 0.0;
@@ -385,23 +439,6 @@ __global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
     if (tid == 0) part_a2[blockIdx.x] = a2s;
   }
   if (blockIdx.x == 0 && tid == 0) st->beta_new = beta;
-}
-
-// ||vnew||^2 from the per-workgroup partial squares (nb <= 128), in one
-// fixed order: wavefront 0, lane l adds partials l and l + 64, then the
-// butterfly; lane 0's total is the result everywhere, so every workgroup that
-// calls this gets the same bits.  Returns the value to all threads.
-__device__ double sum_parts_fixed(const double *__restrict__ part, int nb) {
-  __shared__ double tot;
-  if (threadIdx.x < 64) {
-    const int l = threadIdx.x;
-    double v = l < nb ? part[l] : 0.0;
-    if (l + 64 < nb) v += part[l + 64];
-    v = wave_sum(v);
-    if (l == 0) tot = v;
-  }
-  __syncthreads();
-  return tot;
 }
 
 // scalar recurrences, v/w/y updates and the stopping test (run by one
@@ -602,10 +639,12 @@ __global__ __launch_bounds__(256) void k_resid(const T *__restrict__ vals,
 }
 
 // The second half of an iteration in one launch: every workgroup computes
-// alpha = ||vnew|| from the partial squares (the same bits in every
-// workgroup) and rows of vhat = R^{-1} (vnew / alpha), 8 rows per workgroup;
-// the one extra workgroup (index nb) runs the scalar recurrences, the v, w, y
-// updates and the stopping test, which no other workgroup of this launch
+// alpha = ||vnew|| from the partial squares and rows of
+// vhat = R^{-1} (vnew / alpha), 8 rows per workgroup.  alpha is summed by
+// wavefront 0 in one fixed order (lane l adds partials l and l + 64, then
+// the butterfly, lane 0's total), so every workgroup gets the same bits.
+// The one extra workgroup (index nb) runs the scalar recurrences, the v, w,
+// y updates and the stopping test, which no other workgroup of this launch
 // reads; a stop it signals turns the following launches into no-ops.
 __global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ Rinv,
                                                      int64_t d,
@@ -618,31 +657,40 @@ __global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ 
                                                      double *__restrict__ vhat, double atol,
                                                      double btol, int init) {
   if (!init && st->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *vn = reinterpret_cast<double *>(smem_raw);  // vnew, d doubles
   __shared__ double red[kColsPerBlk][kPhases + 1];
-  const double alpha = sqrt(sum_parts_fixed(part_a2, nb));
-  if ((int)blockIdx.x == nb) {
+  __shared__ double alpha_s;
+  const int tid = threadIdx.x;
+  const bool upd = (int)blockIdx.x == nb;
+  const int c = tid >> 5;  // row within the block
+  const int g = tid & 31;  // column phase
+  const int64_t i = (int64_t)blockIdx.x * kColsPerBlk + c;
+  const int64_t jj0 = i + ((g - (i & 31)) & 31);  // first j >= i with j = g mod 32
+  const int K = (!upd && i < d && jj0 < d) ? (int)ceil_div(d - jj0, kPhases) : 0;
+  // loads first: this thread's R^{-1} entries, vnew, the partial squares
+  double rv[kMaxK];
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) rv[k] = k < K ? Rinv[i * d + jj0 + kPhases * k] : 0.0;
+  double pa = 0.0;
+  if (tid < 64) {
+    pa = tid < nb ? part_a2[tid] : 0.0;
+    if (tid + 64 < nb) pa += part_a2[tid + 64];
+  }
+  if (!upd)
+    for (int64_t q = tid; q < d; q += 256) vn[q] = vnew[q];
+  if (tid < 64) {
+    pa = wave_sum(pa);
+    if (tid == 0) alpha_s = sqrt(pa);
+  }
+  __syncthreads();
+  const double alpha = alpha_s;
+  if (upd) {
     lsqr_update(st, d, v, vnew, w, y, alpha, atol, btol, init);
     return;
   }
   const double ainv = alpha > 0.0 ? 1.0 / alpha : 0.0;
-  const int tid = threadIdx.x;
-  const int c = tid >> 5;  // row within the block
-  const int g = tid & 31;  // column phase
-  const int64_t i = (int64_t)blockIdx.x * kColsPerBlk + c;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  if (i < d) {
-    int64_t jj = i + ((g - (i & 31)) & 31);
-    const double *row = Rinv + i * d;
-#pragma unroll 2
-    for (; jj + 3 * kPhases < d; jj += 4 * kPhases) {
-      a0 += row[jj] * vnew[jj];
-      a1 += row[jj + kPhases] * vnew[jj + kPhases];
-      a2 += row[jj + 2 * kPhases] * vnew[jj + 2 * kPhases];
-      a3 += row[jj + 3 * kPhases] * vnew[jj + 3 * kPhases];
-    }
-    for (; jj < d; jj += kPhases) a0 += row[jj] * vnew[jj];
-  }
-  red[c][g] = (a0 + a1) + (a2 + a3);
+  red[c][g] = phased_dot(rv, vn, jj0, K);
   __syncthreads();
   if (tid < kColsPerBlk) {
     const int64_t ii = (int64_t)blockIdx.x * kColsPerBlk + tid;
@@ -711,7 +759,8 @@ void one_step(const psk_mat &A, bool init, const LsqBufs &B, const double *Rinv,
                                                                          B.part2, init ? 1 : 0);
   k_vnew<<<nb16, 256, (size_t)d * sizeof(double), s>>>(B.part2, B.part_b2, Rinv, d, B.v, B.st,
                                                        B.vnew, B.part_a2, init ? 1 : 0);
-  k_trmv_update<<<nb16 + 1, 256, 0, s>>>(Rinv, d, B.vnew, B.part_a2, (int)nb16, B.st, B.v, B.w,
+  k_trmv_update<<<nb16 + 1, 256, (size_t)d * sizeof(double), s>>>(Rinv, d, B.vnew, B.part_a2,
+                                                                (int)nb16, B.st, B.v, B.w,
                                      B.y, B.vhat, o.atol, o.btol, init ? 1 : 0);
 }
 
