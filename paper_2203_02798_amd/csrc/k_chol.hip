@@ -63,7 +63,7 @@ struct CholSmem {
   double Bs[16 * kLd];
   double PI[64 * kLd];       // also the diagonal tile to factor
   double PJ[64 * kLd];
-  double Ut[64 * kUt];       // Ut[l][k] = U[k][l]
+  double Ut[64 * kUt];       // block inverses of the diagonal factor
   double rowbuf[2][64];
   double rinv[64];
 };
@@ -80,62 +80,170 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Wavefront 0 only.  T: the 64 x 64 tile in LDS (row-major, stride kLd), of
-// which the leading nb x nb block is used (the rest is taken as identity).
-// Right-looking Cholesky with lane l holding column l: step k reads the
-// pivot from lane k, scales row k (lane l's entry U[k][l]), publishes it
-// through LDS and applies the rank-1 update to its column.  Then lane l
-// solves U x = e_l column-wise (x_i = b_i / U_ii, b_k -= U[k][i] x_i for
-// k < i), reading column i of U contiguously from Ut.
-__device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int64_t j0,
-                            double *__restrict__ R, double *__restrict__ X,
-                            int *__restrict__ flag) {
-  const int l = threadIdx.x;
-  double c[64];
-#pragma clang loop unroll(full)
-  for (int i = 0; i < 64; ++i) {
-    const double v = S.PI[i * kLd + l];  // always inside the tile: no branch
-    c[i] = (i < nb && l < nb) ? v : (i == l ? 1.0 : 0.0);
-  }
+// 1/sqrt(x) to about one ulp: the hardware estimate, then one third-order
+// and one Newton correction, each from the residual e = 1 - x y^2 taken with
+// an FMA.
+__device__ __forceinline__ double rsqrt_acc(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double e = fma(-(x * y), y, 1.0);
+  y = fma(y * e, fma(e, 0.375, 0.5), y);
+  e = fma(-(x * y), y, 1.0);
+  return fma(y * e, 0.5, y);
+}
+
+constexpr int kVb = 16 * 17;  // one 16 x 16 block inverse in LDS (row stride 17)
+
+// Wavefront 0: Cholesky of the 16 x 16 block at (o, o) of the LDS tile T
+// (its upper triangle is read), right-looking with lane l % 16 holding
+// column l % 16: step k takes the pivot from lane k, scales row k, publishes
+// it through LDS and applies the rank-1 update to its column.  U overwrites
+// the block's upper triangle, 1/U_ii goes to rinv[o + i] and the block's
+// inverse V = U^{-1} (lane l solving U x = e_l from the last row up) to Vb.
+// Lanes 16..63 repeat lanes 0..15 and store nothing.  Returns true when a
+// pivot was not positive (it is then replaced by 1).
+__device__ __forceinline__ bool factor16(double *__restrict__ T, int o,
+                                         double *__restrict__ rowbuf,
+                                         double *__restrict__ rinv, double *__restrict__ Vb) {
+  const int l = threadIdx.x & 15;
+  const bool st = threadIdx.x < 16;
+  double c[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) c[i] = T[(o + i) * kLd + o + l];
   bool bad = false;
-#pragma clang loop unroll(full)
-  for (int k = 0; k < 64; ++k) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
     double piv = readlane_f64(c[k], k);
     bad |= !(piv > 0.0);
     piv = piv > 0.0 ? piv : 1.0;
-    const double rs = 1.0 / sqrt(piv);
+    const double rs = rsqrt_acc(piv);
     const double u = (l >= k) ? c[k] * rs : 0.0;
-    double *rb = S.rowbuf[k & 1];
-    rb[l] = u;
-    S.Ut[l * kUt + k] = u;
-    S.rinv[k] = rs;  // the same value from every lane
+    double *rb = rowbuf + (k & 1) * 16;
+    if (st) {
+      rb[l] = u;
+      if (l >= k) T[(o + k) * kLd + o + l] = u;
+      if (l == k) rinv[o + k] = rs;
+    }
     wave_sync_lds();
-#pragma clang loop unroll(full)
-    for (int i = k + 1; i < 64; ++i) c[i] -= rb[i] * u;
-    // keep the scheduler from hoisting later steps' loads over this one
+#pragma unroll
+    for (int i = k + 1; i < 16; ++i) c[i] -= rb[i] * u;
     __builtin_amdgcn_sched_barrier(0);
   }
-  wave_sync_lds();
-  // R block (lower part of the block is zero: Ut[l][k] = 0 for l < k)
-#pragma clang loop unroll(full)
-  for (int k = 0; k < 64; ++k)
-    if (k < nb && l < nb) R[(j0 + k) * d + j0 + l] = S.Ut[l * kUt + k];
-  // X = U^{-1}, column l per lane
-  double b[64];
-#pragma clang loop unroll(full)
-  for (int k = 0; k < 64; ++k) b[k] = (k == l) ? 1.0 : 0.0;
-#pragma clang loop unroll(full)
-  for (int i = 63; i >= 0; --i) {
-    const double xi = b[i] * S.rinv[i];
-    b[i] = xi;
-    const double *ucol = S.Ut + i * kUt;  // U[0..i-1][i]
-#pragma clang loop unroll(full)
-    for (int k = 0; k < i; ++k) b[k] -= ucol[k] * xi;
+  double bv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) bv[i] = (i == l) ? 1.0 : 0.0;
+#pragma unroll
+  for (int i = 15; i >= 0; --i) {
+    const double xi = bv[i] * rinv[o + i];
+    bv[i] = xi;
+#pragma unroll
+    for (int m = 0; m < i; ++m) bv[m] -= T[(o + m) * kLd + o + i] * xi;
     __builtin_amdgcn_sched_barrier(0);
   }
-#pragma clang loop unroll(full)
-  for (int k = 0; k < 64; ++k)
-    if (k < nb && l < nb) X[(j0 + k) * d + j0 + l] = b[k];
+  if (st) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Vb[i * 17 + l] = bv[i];
+  }
+  return bad;
+}
+
+// All 256 threads.  T = S.PI: the 64 x 64 tile (row-major, stride kLd), of
+// which the leading nb x nb block is used (the rest is taken as identity).
+// Blocked right-looking Cholesky over four 16-column blocks: block kb is
+// factored by wavefront 0 (factor16), then the panel right of it is solved
+// (U[kb, J] = V_kb^T T[kb, J]) and the trailing block updated
+// (T[I, J] -= U[kb, I]^T U[kb, J]) by the whole workgroup.  The inverse
+// X = U^{-1} is built block column by block column:
+// X[I, J] = -(sum_{K = I..J-1} X[I, K] U[K, J]) V_J.  Writes the nb x nb
+// blocks of R (= U, zero below the diagonal) and X at (j0, j0).
+__device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int64_t j0,
+                                            double *__restrict__ R, double *__restrict__ X,
+                                            int *__restrict__ flag) {
+  double *T = S.PI;
+  double *XT = S.PJ;
+  double *V = S.Ut;   // four block inverses, kVb doubles each
+  double *P = S.As;   // up to three 16 x 16 partial products (stride 17)
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += kTh) {
+    const int i = e >> 6, j = e & 63;
+    if (i >= nb || j >= nb) T[i * kLd + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  bool bad = false;
+#pragma unroll 1
+  for (int kb = 0; kb < 4; ++kb) {
+    const int o = 16 * kb;
+    if (tid < 64) bad |= factor16(T, o, S.rowbuf[0], S.rinv, V + kb * kVb);
+    __syncthreads();
+    const int rest = 48 - o;  // columns right of the block
+    if (rest == 0) break;
+    {
+      // panel rows o..o+15, columns o+16..63: U[o+r][j] = sum_{m<=r} V[m][r] T[o+m][j]
+      const double *Vk = V + kb * kVb;
+      const int r = tid & 15, jg = tid >> 4;
+      double pv[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int j = o + 16 + jg + 16 * q;
+        double acc = 0.0;
+        if (j < 64) {
+          for (int m = 0; m <= r; ++m) acc += Vk[m * 17 + r] * T[(o + m) * kLd + j];
+        }
+        pv[q] = acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const int j = o + 16 + jg + 16 * q;
+        if (j < 64) T[(o + r) * kLd + j] = pv[q];
+      }
+      __syncthreads();
+    }
+    // trailing block rows / columns o+16..63
+    for (int e = tid; e < rest * rest; e += kTh) {
+      const int i = o + 16 + e / rest, j = o + 16 + e % rest;
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) acc += T[(o + m) * kLd + i] * T[(o + m) * kLd + j];
+      T[i * kLd + j] -= acc;
+    }
+    __syncthreads();
+  }
+  // X: diagonal blocks from the block inverses, zero below them
+  for (int e = tid; e < 64 * 64; e += kTh) {
+    const int i = e >> 6, j = e & 63;
+    const int bi = i >> 4, bj = j >> 4;
+    XT[i * kLd + j] = (bi == bj) ? V[bi * kVb + (i & 15) * 17 + (j & 15)]
+                                 : 0.0;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int J = 1; J < 4; ++J) {
+    // P[I] = sum_{K=I}^{J-1} X[I, K] U[K, J] for I < J (J * 256 entries)
+    for (int e = tid; e < J * 256; e += kTh) {
+      const int I = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      double acc = 0.0;
+      for (int kk = 16 * I; kk < 16 * J; ++kk)
+        acc += XT[(16 * I + r) * kLd + kk] * T[kk * kLd + 16 * J + c];
+      P[I * kVb + r * 17 + c] = acc;
+    }
+    __syncthreads();
+    // X[I, J] = -P[I] V_J (V_J upper triangular)
+    const double *VJ = V + J * kVb;
+    for (int e = tid; e < J * 256; e += kTh) {
+      const int I = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      double acc = 0.0;
+      for (int m = 0; m <= c; ++m) acc += P[I * kVb + r * 17 + m] * VJ[m * 17 + c];
+      XT[(16 * I + r) * kLd + 16 * J + c] = -acc;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 64 * 64; e += kTh) {
+    const int i = e >> 6, j = e & 63;
+    if (i < nb && j < nb) {
+      R[(j0 + i) * d + j0 + j] = (i <= j) ? T[i * kLd + j] : 0.0;
+      X[(j0 + i) * d + j0 + j] = XT[i * kLd + j];
+    }
+  }
   if (bad) atomicOr(flag, 1);
 }
 
@@ -234,7 +342,7 @@ __global__ __launch_bounds__(kTh) void k_chol_first(const double *__restrict__ W
     S.PI[i * kLd + jj] = (i < nb && jj < nb) ? W[(int64_t)i * d + jj] : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x < 64) factor_diag(S, nb, d, 0, R, X, flag);
+  factor_diag(S, nb, d, 0, R, X, flag);
 }
 
 __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64_t d,
@@ -286,7 +394,7 @@ __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64
         }
       __syncthreads();
       const int nb1 = (int)((d - r0) < 64 ? (d - r0) : 64);
-      if (threadIdx.x < 64) factor_diag(S, nb1, d, r0, R, X, flag);
+      factor_diag(S, nb1, d, r0, R, X, flag);
     } else {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
