@@ -212,6 +212,70 @@ __device__ __forceinline__ void gauss4_f32(uint64_t q, uint32_t a, uint64_t seed
 }
 
 // ---------------------------------------------------------------------------
+// CountSketch bucket sum of CSR rows into an LDS row (one wavefront)
+// ---------------------------------------------------------------------------
+// acc[col] += sign * A[row, col] for the rows of bin-list entries j0 .. j1-1
+// (perm[j] = row | sign << 31), rows applied in list order, a row's entries
+// in any order (they touch distinct columns), so the sums have one fixed
+// order.  The row pointers and the first kBucketEnt entries of up to 64 rows
+// are loaded at once, one row per lane, and the rows are then applied one
+// after another from registers; rows with more entries are spread over the
+// wavefront.
+constexpr int kBucketEnt = 4;
+
+template <typename T>
+__device__ __forceinline__ void bucket_rows_add(const T *__restrict__ vals,
+                                                const int64_t *__restrict__ indptr,
+                                                const int32_t *__restrict__ indices,
+                                                const uint32_t *__restrict__ perm, uint32_t j0,
+                                                uint32_t j1, T *acc) {
+  const int lane = (int)(threadIdx.x & 63u);
+  for (uint32_t base = j0; base < j1; base += 64) {
+    const uint32_t j = base + (uint32_t)lane;
+    int64_t p0 = 0, p1 = 0;
+    int ng = 0;
+    if (j < j1) {
+      const uint32_t pv = perm[j];
+      const int64_t row = (int64_t)(pv & 0x7fffffffu);
+      ng = (int)(pv >> 31);
+      p0 = indptr[row];
+      p1 = indptr[row + 1];
+    }
+    const int64_t len = p1 - p0;
+    const bool lng = len > kBucketEnt;
+    int ci[kBucketEnt];
+    T xv[kBucketEnt];
+#pragma unroll
+    for (int e = 0; e < kBucketEnt; ++e) {
+      ci[e] = 0;
+      xv[e] = T(0);
+      if (!lng && e < len) {
+        ci[e] = indices[p0 + e];
+        const T v = vals[p0 + e];
+        xv[e] = ng ? -v : v;
+      }
+    }
+    const uint64_t longmask = __ballot(lng);
+    const int cnt = (j1 - base) < 64u ? (int)(j1 - base) : 64;
+    for (int i = 0; i < cnt; ++i) {
+      if ((longmask >> i) & 1u) {
+        const int64_t q0 = __shfl(p0, i, 64);
+        const int64_t q1 = __shfl(p1, i, 64);
+        const int ngi = __shfl(ng, i, 64);
+        for (int64_t p = q0 + lane; p < q1; p += 64) {
+          const T v = vals[p];
+          atomicAdd(&acc[indices[p]], ngi ? -v : v);
+        }
+      } else if (lane == i) {
+#pragma unroll
+        for (int e = 0; e < kBucketEnt; ++e)
+          if (e < len) atomicAdd(&acc[ci[e]], xv[e]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Small helpers
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) {

@@ -75,6 +75,9 @@ int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
 // S*A into SA (r x d row-major, dtype of A).
 int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
              const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st);
+// Wavefronts per bucket cs_apply uses for n rows in r buckets (1 = one
+// wavefront sums a whole bucket).
+int cs_splits(int64_t n, int64_t r);
 
 // Argument checks shared by the entry points (abi.hip): 0 or a status.
 int check_mat(const psk_mat *A);
@@ -95,6 +98,13 @@ int gauss_gemm(int64_t m, int64_t r, int64_t d, uint64_t seed, int prec,
 // The same product with bfloat16 operands (k_gauss_gemm_bf16.hip).
 int gauss_gemm_bf16(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
                     int sa_dtype, double *C, Arena &ws, hipStream_t st);
+// For CSR A the BF16 product can start from the binned rows (perm, bptr of
+// cs_bin) and form the limbs of S*A directly, without the r x d array; the
+// result is the same bits.  bf16_csr_fusable tells when this path applies.
+bool bf16_csr_fusable(const psk_mat &A, int64_t r);
+int gauss_gemm_bf16_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
+                        const uint32_t *bptr, uint64_t seed, double *C, Arena &ws,
+                        hipStream_t st);
 // ... and with FP8 e4m3 operands, per-128-bucket E8M0 scales (k_gauss_gemm_fp8.hip).
 int gauss_gemm_fp8(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
                    int sa_dtype, double *C, Arena &ws, hipStream_t st);

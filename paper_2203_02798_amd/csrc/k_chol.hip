@@ -47,12 +47,18 @@ __global__ __launch_bounds__(256) void k_shift_diag(double *__restrict__ W, int6
 // per 64 x 64 tile of work:
 //   panel    R[j, J]  = X_jj^T W[j, J]                       (J > j)
 //   trailing W[I, J] -= P_I^T P_J,  P_K = X_jj^T W[j, K]     (j < I <= J)
-//   inverse  X[I, j]  = -(X[I, I:j] R[I:j, j]) X_jj          (I < j)
+//   partial  P_j[I][K] = X[I, K] R[K, j]                     (I <= K <= j-2)
+//   finish   X[I, c]  = -(sum_K P_c[I][K] + X[I, c-1] R[c-1, c]) X_cc
+//                                                   (c = j - 1, I < c)
 // and the workgroup that owns the next diagonal tile (j+1, j+1), whose update
-// is the last one it receives, factors it in the same launch (wavefront 0:
-// Cholesky and triangular inverse of the 64 x 64 block), so the next step
-// finds R_{j+1,j+1} and X_{j+1,j+1} ready.  Block 0 is factored by
-// k_chol_first.  W is read in its upper block triangle and destroyed.
+// is the last one it receives, factors it in the same launch (Cholesky and
+// triangular inverse of the 64 x 64 block), so the next step finds R_{j+1,j+1}
+// and X_{j+1,j+1} ready.  The off-diagonal blocks of X = R^{-1}, whose sums
+// run over up to d - 64 terms, are split into 64-term partial products so
+// that no workgroup carries a long sum; a block column is summed (in K
+// order) and finished one launch after its partials, and one extra launch
+// finishes the last column.  Block 0 is factored by k_chol_first.  W is read
+// in its upper block triangle and destroyed.
 // ---------------------------------------------------------------------------
 constexpr int kLd = 68;      // LDS row stride of 64-wide tiles (doubles)
 constexpr int kUt = 66;      // LDS row stride of the transposed factor
@@ -186,7 +192,9 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
         const int j = o + 16 + jg + 16 * q;
         double acc = 0.0;
         if (j < 64) {
-          for (int m = 0; m <= r; ++m) acc += Vk[m * 17 + r] * T[(o + m) * kLd + j];
+#pragma unroll
+          for (int m = 0; m < 16; ++m)
+            if (m <= r) acc += Vk[m * 17 + r] * T[(o + m) * kLd + j];
         }
         pv[q] = acc;
       }
@@ -222,8 +230,11 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
     for (int e = tid; e < J * 256; e += kTh) {
       const int I = e >> 8, r = (e >> 4) & 15, c = e & 15;
       double acc = 0.0;
-      for (int kk = 16 * I; kk < 16 * J; ++kk)
-        acc += XT[(16 * I + r) * kLd + kk] * T[kk * kLd + 16 * J + c];
+      for (int K = I; K < J; ++K) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m)
+          acc += XT[(16 * I + r) * kLd + 16 * K + m] * T[(16 * K + m) * kLd + 16 * J + c];
+      }
       P[I * kVb + r * 17 + c] = acc;
     }
     __syncthreads();
@@ -232,7 +243,9 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
     for (int e = tid; e < J * 256; e += kTh) {
       const int I = e >> 8, r = (e >> 4) & 15, c = e & 15;
       double acc = 0.0;
-      for (int m = 0; m <= c; ++m) acc += P[I * kVb + r * 17 + m] * VJ[m * 17 + c];
+#pragma unroll
+      for (int m = 0; m < 16; ++m)
+        if (m <= c) acc += P[I * kVb + r * 17 + m] * VJ[m * 17 + c];
       XT[(16 * I + r) * kLd + 16 * J + c] = -acc;
     }
     __syncthreads();
@@ -350,11 +363,15 @@ __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64
                                                    double *__restrict__ R,
                                                    double *__restrict__ X,
                                                    int *__restrict__ flag,
-                                                   const int *__restrict__ sel) {
+                                                   const int *__restrict__ sel,
+                                                   double *__restrict__ xpart) {
   __shared__ CholSmem S;
   if (sel && *sel != 0) return;  // the series path was selected
-  const int p = nblk - j - 1;
+  const int p = j < nblk ? nblk - j - 1 : 0;
   const int ntrail = p * (p + 1) / 2;
+  const int npart = (j >= 2 && j < nblk) ? (j - 1) * j / 2 : 0;
+  const int cfin = j - 1;  // the X block column finished in this launch
+  const int nfin = cfin >= 1 ? cfin : 0;
   int t = blockIdx.x;
   const int64_t j0 = (int64_t)j * 64;
   const int nbj = (int)((d - j0) < 64 ? (d - j0) : 64);
@@ -407,34 +424,73 @@ __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64
     return;
   }
   t -= ntrail;
-  if (t < j) {
-    // inverse column tile X[I, j] = -(X[I, I:j] R[I:j, j]) X_jj
-    const int I = t;
-    const int64_t r0 = (int64_t)I * 64;
-    const int K = (int)(j0 - r0);
+  const int64_t half = (int64_t)(nblk - 2) * (nblk - 1) / 2 * 4096;  // tiles per parity
+  if (t < npart) {
+    // partial product P_j[I][K] = X[I, K] R[K, j] for I <= K <= j - 2
+    int K = 0;
+    while ((K + 1) * (K + 2) / 2 <= t) ++K;
+    const int I = t - K * (K + 1) / 2;
+    const int64_t r0 = (int64_t)I * 64, k0 = (int64_t)K * 64;
     double acc[4][4];
     zero_acc(acc);
-    auto fa = [&](int i, int k) { return X[(r0 + i) * d + r0 + k]; };          // in range
-    auto fb = [&](int k, int jj) { return jj < nbj ? R[(r0 + k) * d + j0 + jj] : 0.0; };
-    tile_mm<true>(acc, fa, fb, K, S);
+    auto fa = [&](int i, int k) { return X[(r0 + i) * d + k0 + k]; };  // in range
+    auto fb = [&](int k, int jj) { return jj < nbj ? R[(k0 + k) * d + j0 + jj] : 0.0; };
+    tile_mm<true>(acc, fa, fb, 64, S);
+    double *P = xpart + (j & 1) * half + (int64_t)t * 4096;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) P[(4 * ty + r) * 64 + 4 * tx + q] = acc[r][q];
+    return;
+  }
+  t -= npart;
+  if (t < nfin) {
+    // X[I, c] = -(sum_{K=I}^{c-2} P_c[I][K] + X[I, c-1] R[c-1, c]) X_cc, c = cfin
+    const int I = t, c = cfin;
+    const int64_t r0 = (int64_t)I * 64, cm0 = (int64_t)(c - 1) * 64, c0 = (int64_t)c * 64;
+    const int nbc = (int)((d - c0) < 64 ? (d - c0) : 64);
+    double acc[4][4];
+    zero_acc(acc);
+    auto fa = [&](int i, int k) { return X[(r0 + i) * d + cm0 + k]; };  // in range
+    auto fb = [&](int k, int jj) { return jj < nbc ? R[(cm0 + k) * d + c0 + jj] : 0.0; };
+    tile_mm<true>(acc, fa, fb, 64, S);
+    const double *Pc = xpart + (c & 1) * half;
+    double sum[4][4];
+    zero_acc(sum);
+#pragma unroll 4
+    for (int K = I; K <= c - 2; ++K) {
+      const double *pk = Pc + (int64_t)(K * (K + 1) / 2 + I) * 4096 + 4 * tx;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double4 v = *reinterpret_cast<const double4 *>(pk + (4 * ty + r) * 64);
+        sum[r][0] += v.x;
+        sum[r][1] += v.y;
+        sum[r][2] += v.z;
+        sum[r][3] += v.w;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[r][q] = sum[r][q] + acc[r][q];
     acc_to_lds(acc, S.PI);
     __syncthreads();
     zero_acc(acc);
     auto ga = [&](int i, int k) { return S.PI[i * kLd + k]; };
     auto gb = [&](int k, int jj) {
-      return (k < nbj && jj < nbj) ? X[(j0 + k) * d + j0 + jj] : 0.0;
+      return (k < nbc && jj < nbc) ? X[(c0 + k) * d + c0 + jj] : 0.0;
     };
-    tile_mm<true>(acc, ga, gb, nbj, S);
+    tile_mm<true>(acc, ga, gb, nbc, S);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t gi = r0 + 4 * ty + r, gj = j0 + 4 * tx + q;
+        const int64_t gi = r0 + 4 * ty + r, gj = c0 + 4 * tx + q;
         if (gj < d) X[gi * d + gj] = -acc[r][q];
       }
     return;
   }
-  t -= j;
+  t -= nfin;
   if (t < p) {
     // panel tile R[j, J] = X_jj^T W[j, J]
     const int64_t c0 = (int64_t)(j + 1 + t) * 64;
@@ -555,14 +611,20 @@ void fill(double *p, int64_t count, double v, hipStream_t st) {
 
 // Upper Cholesky of W (destroyed) into R, and X = R^{-1}; R and X must be
 // zero on entry.  With sel, the launches do nothing unless *sel == 0.
+// xpart: scratch of at least d * d doubles for the partial products of the
+// off-diagonal blocks of X (two block columns' worth, by parity).
 void chol_inv(double *W, int64_t d, double *R, double *X, int *flag, const int *sel,
-              hipStream_t st) {
+              double *xpart, hipStream_t st) {
   const int nblk = (int)ceil_div(d, 64);
   k_chol_first<<<1, kTh, 0, st>>>(W, d, R, X, flag, sel);
-  for (int j = 0; j < nblk; ++j) {
-    const int p = nblk - j - 1;
-    const int tiles = p * (p + 1) / 2 + j + p;
-    if (tiles > 0) k_chol_step<<<tiles, kTh, 0, st>>>(W, d, nblk, j, R, X, flag, sel);
+  // launch j = nblk only finishes the last block column of X
+  for (int j = 0; j <= nblk; ++j) {
+    const int p = j < nblk ? nblk - j - 1 : 0;
+    const int npart = (j >= 2 && j < nblk) ? (j - 1) * j / 2 : 0;
+    const int nfin = j - 1 >= 1 ? j - 1 : 0;
+    const int tiles = p * (p + 1) / 2 + npart + nfin + p;
+    if (tiles > 0)
+      k_chol_step<<<tiles, kTh, 0, st>>>(W, d, nblk, j, R, X, flag, sel, xpart);
   }
 }
 
@@ -600,7 +662,7 @@ int near_identity_chol(double *W, int64_t d, double *R, double *X, double *B0, d
   }
   if (run) {
     k_series_select<<<ew, 256, 0, st>>>(B3, v, d, sel, R, X);
-    chol_inv(W, d, R, X, flag, sel, st);
+    chol_inv(W, d, R, X, flag, sel, B2, st);  // B2 is free again here
   }
   return 0;
 }
@@ -642,7 +704,7 @@ int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rin
     k_shift_diag<<<1, 256, 0, st>>>(W, d, coef);
     fill(R1, d * d, 0.0, st);
     fill(X1, d * d, 0.0, st);
-    chol_inv(W, d, R1, X1, flag, nullptr, st);
+    chol_inv(W, d, R1, X1, flag, nullptr, B0, st);  // B0 is not in use yet
   }
   if ((rc = dgemm(false, false, m, d, d, 1.0, C, d, X1, d, 0.0, Qa, d, ws, st))) return rc;
   ws.release(mk);

@@ -8,7 +8,9 @@
 // matrix instructions per block.  K-split partial products are stored in
 // FP32 and summed in FP64 by a second kernel, which applies 1/sqrt(m).
 //
-// Layout of the limbs (written by k_sa_limbs): for 32-bucket chunk kc and
+// Layout of the limbs (written by k_sa_limbs from a materialised S*A, or for
+// CSR A by k_scatter_csr_limbs straight from the binned rows): for 32-bucket
+// chunk kc and
 // k-quad q (buckets 32kc + 8q .. +7) the 8 values of column n are 16
 // contiguous bytes at Lq[kc][q][n][0..7]; a B fragment of the 16x16x32
 // instruction (lane l: column l%16, buckets 8(l/16)..+7) is then one 16-byte
@@ -110,6 +112,54 @@ __global__ __launch_bounds__(256) void k_sa_limbs(const T *__restrict__ SA, int6
   pl.w = l8[6] | ((uint32_t)l8[7] << 16);
   reinterpret_cast<uint4 *>(hi)[t] = ph;
   reinterpret_cast<uint4 *>(lo)[t] = pl;
+}
+
+// S*A of CSR A straight into the limb layout, without the r x d array: a
+// workgroup of 8 wavefronts owns the quad of buckets 8 * blockIdx.x + e
+// (e = 0..7); wavefront e sums its bucket's rows into an LDS row of npad
+// accumulators exactly as the CountSketch scatter does (rows one after
+// another in bin order, a row's entries spread over the lanes), then every
+// thread turns the 8 sums of one column into its hi and lo limbs (the same
+// values k_sa_limbs makes from the materialised S*A).
+template <typename T>
+__global__ __launch_bounds__(512) void k_scatter_csr_limbs(
+    const T *__restrict__ vals, const int64_t *__restrict__ indptr,
+    const int32_t *__restrict__ indices, int64_t npad, int64_t r,
+    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
+    uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *accs = reinterpret_cast<T *>(smem_raw);  // 8 x npad
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t quad = blockIdx.x;
+  const int64_t b = quad * 8 + wave;
+  T *acc = accs + (int64_t)wave * npad;
+  for (int64_t c = lane; c < npad; c += 64) acc[c] = T(0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (b < r) bucket_rows_add(vals, indptr, indices, perm, bptr[b], bptr[b + 1], acc);
+  __syncthreads();
+  for (int64_t n = threadIdx.x; n < npad; n += 512) {
+    uint16_t h8[8], l8[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const double v = (double)accs[(int64_t)e * npad + n];
+      const uint16_t h = bf16_of_f64(v);
+      h8[e] = h;
+      l8[e] = bf16_of_f64(v - bf16_to_f64(h));  // exact difference
+    }
+    uint4 ph, pl;
+    ph.x = h8[0] | ((uint32_t)h8[1] << 16);
+    ph.y = h8[2] | ((uint32_t)h8[3] << 16);
+    ph.z = h8[4] | ((uint32_t)h8[5] << 16);
+    ph.w = h8[6] | ((uint32_t)h8[7] << 16);
+    pl.x = l8[0] | ((uint32_t)l8[1] << 16);
+    pl.y = l8[2] | ((uint32_t)l8[3] << 16);
+    pl.z = l8[4] | ((uint32_t)l8[5] << 16);
+    pl.w = l8[6] | ((uint32_t)l8[7] << 16);
+    reinterpret_cast<uint4 *>(hi)[quad * npad + n] = ph;
+    reinterpret_cast<uint4 *>(lo)[quad * npad + n] = pl;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_gauss_gemm_bf16(
@@ -253,50 +303,105 @@ __global__ __launch_bounds__(256) void k_reduce_splits_f32(const float *__restri
 
 }  // namespace
 
-int gauss_gemm_bf16(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
-                    int sa_dtype, double *C, Arena &ws, hipStream_t st) {
-  const int tiles_m = (int)ceil_div(m, kBM);
-  const int tiles_n = (int)ceil_div(d, kBN);
-  const int64_t npad = (int64_t)tiles_n * kBN;
-  const int64_t kchunks = ceil_div(r, kBK);
-  const int64_t tiles = (int64_t)tiles_m * tiles_n;
-  int64_t splits = ceil_div(512, tiles);
-  const int64_t max_splits = kchunks / 32 > 0 ? kchunks / 32 : 1;
+namespace {
+
+// Tiling, K split and workspace of one BF16 product (limbs, FP32 partials).
+struct Bf16Plan {
+  int tiles_m, tiles_n;
+  int64_t npad, kchunks, tiles, splits, cper;
+  uint16_t *hi, *lo;
+  float *part;
+};
+
+int bf16_plan(int64_t m, int64_t r, int64_t d, Arena &ws, Bf16Plan &P) {
+  P.tiles_m = (int)ceil_div(m, kBM);
+  P.tiles_n = (int)ceil_div(d, kBN);
+  P.npad = (int64_t)P.tiles_n * kBN;
+  P.kchunks = ceil_div(r, kBK);
+  P.tiles = (int64_t)P.tiles_m * P.tiles_n;
+  int64_t splits = ceil_div(512, P.tiles);
+  const int64_t max_splits = P.kchunks / 32 > 0 ? P.kchunks / 32 : 1;
   if (splits > max_splits) splits = max_splits;
   if (splits < 1) splits = 1;
-  const int64_t cper = ceil_div(kchunks, splits);
-  splits = ceil_div(kchunks, cper);
-  const int64_t limb_elems = kchunks * 4 * npad * 8;
-  if ((cper + 1) * 4 * npad * 8 * 2 + 65536 >= ((int64_t)1 << 31))
+  P.cper = ceil_div(P.kchunks, splits);
+  P.splits = ceil_div(P.kchunks, P.cper);
+  const int64_t limb_elems = P.kchunks * 4 * P.npad * 8;
+  if ((P.cper + 1) * 4 * P.npad * 8 * 2 + 65536 >= ((int64_t)1 << 31))
     return fail(PSK_EUNSUPPORTED, "BF16 Gaussian GEMM: K slice too large for one descriptor");
-  uint16_t *hi = ws.take<uint16_t>((size_t)limb_elems);
-  uint16_t *lo = ws.take<uint16_t>((size_t)limb_elems);
-  float *part = ws.take<float>((size_t)splits * m * d);
-  if (ws.dry()) return 0;
-  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the BF16 Gaussian GEMM");
-  {
-    KTimer t("sa_limbs", st);
-    const int64_t threads = kchunks * 4 * npad;
-    if (sa_dtype == PSK_F64)
-      k_sa_limbs<double><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
-          (const double *)SA, r, d, npad, kchunks, hi, lo);
-    else
-      k_sa_limbs<float><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
-          (const float *)SA, r, d, npad, kchunks, hi, lo);
-  }
+  P.hi = ws.take<uint16_t>((size_t)limb_elems);
+  P.lo = ws.take<uint16_t>((size_t)limb_elems);
+  P.part = ws.take<float>((size_t)P.splits * m * d);
+  if (!ws.dry() && !ws.ok())
+    return fail(PSK_ENOMEM, "workspace too small for the BF16 Gaussian GEMM");
+  return 0;
+}
+
+// the product of prepared limbs and the FP64 sum of the K-split partials
+int bf16_run(const Bf16Plan &P, int64_t m, int64_t d, uint64_t seed, double *C,
+             hipStream_t st) {
   {
     KTimer t("gauss_gemm", st);
-    k_gauss_gemm_bf16<<<(unsigned)(tiles * splits), kThreads, 0, st>>>(
-        m, d, npad, seed, hi, lo, tiles_m, tiles_n, kchunks, cper, part);
+    k_gauss_gemm_bf16<<<(unsigned)(P.tiles * P.splits), kThreads, 0, st>>>(
+        m, d, P.npad, seed, P.hi, P.lo, P.tiles_m, P.tiles_n, P.kchunks, P.cper, P.part);
   }
   {
     KTimer t("gemm_reduce", st);
     const int64_t len = m * d;
     k_reduce_splits_f32<<<(unsigned)ceil_div(len, 256), 256, 0, st>>>(
-        part, len, (int)splits, 1.0 / sqrt((double)m), C);
+        P.part, len, (int)P.splits, 1.0 / sqrt((double)m), C);
   }
   PSK_HIP_TRY(hipGetLastError());
   return 0;
+}
+
+size_t csr_limbs_lds(const psk_mat &A, int64_t d) {
+  return (size_t)8 * ceil_div(d, kBN) * kBN * elem_size(A.dtype);
+}
+
+}  // namespace
+
+int gauss_gemm_bf16(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
+                    int sa_dtype, double *C, Arena &ws, hipStream_t st) {
+  Bf16Plan P;
+  int rc = bf16_plan(m, r, d, ws, P);
+  if (rc || ws.dry()) return rc;
+  {
+    KTimer t("sa_limbs", st);
+    const int64_t threads = P.kchunks * 4 * P.npad;
+    if (sa_dtype == PSK_F64)
+      k_sa_limbs<double><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
+          (const double *)SA, r, d, P.npad, P.kchunks, P.hi, P.lo);
+    else
+      k_sa_limbs<float><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
+          (const float *)SA, r, d, P.npad, P.kchunks, P.hi, P.lo);
+  }
+  return bf16_run(P, m, d, seed, C, st);
+}
+
+bool bf16_csr_fusable(const psk_mat &A, int64_t r) {
+  return A.format == PSK_CSR && cs_splits(A.n, r) == 1 && csr_limbs_lds(A, A.d) <= 65536;
+}
+
+int gauss_gemm_bf16_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
+                        const uint32_t *bptr, uint64_t seed, double *C, Arena &ws,
+                        hipStream_t st) {
+  if (!bf16_csr_fusable(A, r))
+    return fail(PSK_EUNSUPPORTED, "fused CSR limbs need one split per bucket, d <= 1024");
+  Bf16Plan P;
+  int rc = bf16_plan(m, r, A.d, ws, P);
+  if (rc || ws.dry()) return rc;
+  {
+    KTimer t("cs_scatter_limbs", st);
+    const unsigned quads = (unsigned)(P.kchunks * 4);
+    const size_t lds = csr_limbs_lds(A, A.d);
+    if (A.dtype == PSK_F64)
+      k_scatter_csr_limbs<double><<<quads, 512, lds, st>>>(
+          (const double *)A.values, A.indptr, A.indices, P.npad, r, perm, bptr, P.hi, P.lo);
+    else
+      k_scatter_csr_limbs<float><<<quads, 512, lds, st>>>(
+          (const float *)A.values, A.indptr, A.indices, P.npad, r, perm, bptr, P.hi, P.lo);
+  }
+  return bf16_run(P, m, A.d, seed, C, st);
 }
 
 }  // namespace psk

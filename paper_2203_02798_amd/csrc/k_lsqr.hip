@@ -798,22 +798,39 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
       o.escalate_cond != 0.0 ? o.escalate_cond : (o.prec == PSK_PREC_FP8 ? 10.0 : 1e4);
   const bool may_escalate =
       own && (o.prec == PSK_PREC_BF16 || o.prec == PSK_PREC_FP8) && cond_limit > 0.0;
+  // CSR A with the BF16 GEMM: the limbs come straight from the binned rows
+  // and S*A is only formed if the solve escalates to FP64
+  const bool fused = own && o.prec == PSK_PREC_BF16 && bf16_csr_fusable(A, o.r);
   void *SA = nullptr;
+  uint32_t *perm = nullptr, *bptr = nullptr;
+  // the FP64 sketch (after a reduced-precision one), S*A formed here if needed
+  auto rebuild_f64 = [&]() -> int {
+    int e;
+    if (fused) {
+      SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
+      if ((e = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return e;
+    }
+    return gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, A.dtype, C, ws, st);
+  };
   if (own) {
-    // sketch and factor (their scratch is released afterwards); S*A stays
-    // until the precision decision so that an FP64 rebuild can reuse it
-    SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
-    uint32_t *perm = nullptr, *bptr = nullptr;
+    // sketch and factor (their scratch is released afterwards); S*A (or the
+    // binned rows it is formed from) stays until the precision decision so
+    // that an FP64 rebuild can reuse it
+    if (!fused) SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
     if ((rc = cs_bin(n, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr))) return rc;
-    if ((rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return rc;
+    if (!fused && (rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return rc;
     const size_t mk2 = ws.mark();
-    if ((rc = gauss_gemm(m, o.r, d, o.seed, o.prec, SA, A.dtype, C, ws, st))) return rc;
+    if (fused)
+      rc = gauss_gemm_bf16_csr(m, o.r, A, perm, bptr, o.seed, C, ws, st);
+    else
+      rc = gauss_gemm(m, o.r, d, o.seed, o.prec, SA, A.dtype, C, ws, st);
+    if (rc) return rc;
     ws.release(mk2);
     if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;
     ws.release(mk2);
     if (may_escalate && ws.dry()) {
       // plan the FP64 rebuild as well
-      if ((rc = gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, A.dtype, C, ws, st))) return rc;
+      if ((rc = rebuild_f64())) return rc;
       ws.release(mk2);
     }
   }
@@ -831,7 +848,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     // diagonal ratio of R is a cheap lower estimate of cond(A).
     if (may_escalate && (hflag || !(hr[0] <= cond_limit * hr[1]))) {
       const size_t mk2 = ws.mark();
-      if ((rc = gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, A.dtype, C, ws, st))) return rc;
+      if ((rc = rebuild_f64())) return rc;
       ws.release(mk2);
       if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;
       ws.release(mk2);

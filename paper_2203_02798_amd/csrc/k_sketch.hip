@@ -332,8 +332,8 @@ __global__ __launch_bounds__(256) void k_scatter_dense(
 
 // ---------------------------------------------------------------------------
 // S*A, CSR A: one wavefront per (bucket, split) with a private LDS row of d
-// accumulators; rows of the bucket are applied one after another, a row's
-// entries spread over the lanes.
+// accumulators; rows of the bucket are applied one after another
+// (bucket_rows_add).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_scatter_csr(
@@ -355,18 +355,7 @@ __global__ __launch_bounds__(256) void k_scatter_csr(
   for (int64_t c = lane; c < d; c += 64) acc[c] = T(0);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  for (uint32_t j = j0; j < j1; ++j) {
-    const uint32_t pv = perm[j];
-    const int64_t row = (int64_t)(pv & 0x7fffffffu);
-    const bool ng = (pv >> 31) != 0;
-    const int64_t p0 = indptr[row];
-    const int64_t p1 = indptr[row + 1];
-    for (int64_t p = p0 + lane; p < p1; p += 64) {
-      const int32_t col = indices[p];
-      const T v = vals[p];
-      atomicAdd(&acc[col], ng ? -v : v);
-    }
-  }
+  bucket_rows_add(vals, indptr, indices, perm, j0, j1, acc);
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
   T *orow = out + ((int64_t)s * r + b) * d;
@@ -419,6 +408,8 @@ void launch_dense(const psk_mat &A, int64_t r, const uint32_t *perm,
 // ---------------------------------------------------------------------------
 // host entry points
 // ---------------------------------------------------------------------------
+int cs_splits(int64_t n, int64_t r) { return choose_splits(n, r); }
+
 int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
                    int32_t *h, int8_t *sign, hipStream_t st) {
   if (count == 0) return 0;

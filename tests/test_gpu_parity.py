@@ -244,14 +244,18 @@ def test_sketch_gcs_bf16_deterministic(api):
 
 
 @pytest.mark.parametrize("kind,cond,want", [("dense", 10.0, "bf16"), ("dense", 1e8, "f64"),
-                                            ("csr", 1e2, "bf16")])
+                                            ("csr", 1e2, "bf16"), ("csr", 1e8, "f64")])
 def test_lsq_solve_bf16_sketch(api, kind, cond, want):
     # LSQR and the refinement run in FP64 whatever the sketch precision: the
     # solution meets the same tolerances as with the FP64 sketch.  An
-    # ill-conditioned A makes the BF16 sketch escalate to FP64.
+    # ill-conditioned A makes the BF16 sketch escalate to FP64 (for CSR A the
+    # BF16 limbs come from the binned rows, and S*A is formed only then).
     n, d = 20000, 32
     if kind == "csr":
         a = synth.csr_uniform(n, d, 0.2, seed=2)
+        if cond > 1e2:
+            # column scales spanning cond
+            a = (a @ sp.diags(np.logspace(0.0, -np.log10(cond), d))).tocsr()
         xt = np.random.default_rng(0).standard_normal(d)
         b = a @ xt + 1e-3 * np.random.default_rng(1).standard_normal(n)
     else:
