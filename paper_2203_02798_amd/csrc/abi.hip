@@ -115,12 +115,15 @@ int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws
 int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec,
                   void *C, Arena &ws, hipStream_t st) {
   if (m == 0) return do_sketch_cs(A, r, seed, C, ws, st);
-  if (prec == PSK_PREC_BF16 && bf16_csr_fusable(A, r)) {
-    // the limbs of S*A straight from the binned rows
+  const bool fb = prec == PSK_PREC_BF16 && bf16_csr_fusable(A, r);
+  const bool f8 = prec == PSK_PREC_FP8 && fp8_csr_fusable(A, r);
+  if (fb || f8) {
+    // the BF16 limbs / FP8 bytes of S*A straight from the binned rows
     uint32_t *perm = nullptr, *bptr = nullptr;
     int rc = cs_bin(A.n, (uint32_t)r, seed, ws, st, &perm, &bptr);
     if (rc) return rc;
-    return gauss_gemm_bf16_csr(m, r, A, perm, bptr, seed, (double *)C, ws, st);
+    if (fb) return gauss_gemm_bf16_csr(m, r, A, perm, bptr, seed, (double *)C, ws, st);
+    return gauss_gemm_fp8_csr(m, r, A, perm, bptr, seed, (double *)C, ws, st);
   }
   void *SA = ws.take<unsigned char>((size_t)r * A.d * elem_size(A.dtype));
   int rc = do_sketch_cs(A, r, seed, SA, ws, st);

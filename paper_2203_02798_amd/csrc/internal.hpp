@@ -108,6 +108,11 @@ int gauss_gemm_bf16_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *
 // ... and with FP8 e4m3 operands, per-128-bucket E8M0 scales (k_gauss_gemm_fp8.hip).
 int gauss_gemm_fp8(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
                    int sa_dtype, double *C, Arena &ws, hipStream_t st);
+// The FP8 product of CSR A from the binned rows (same bits, no r x d array).
+bool fp8_csr_fusable(const psk_mat &A, int64_t r);
+int gauss_gemm_fp8_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
+                       const uint32_t *bptr, uint64_t seed, double *C, Arena &ws,
+                       hipStream_t st);
 
 // ---- FP64 dense kernels (k_dense.hip) --------------------------------------
 // C (d x d, out_dtype) = alpha * A^T A + beta * C for dense A.

@@ -16,7 +16,7 @@
 // group g is taken here to be bucket 32 g + j for both G and S*A, so each
 // product pairs a normal with the S*A entry of the same bucket.  Quantised
 // S*A is stored as [chunk][g][half][column][16 bytes] (written by
-// k_sa_fp8), so the 16 lanes of a group read 256 contiguous bytes per load;
+// k_sa_fp8, or for CSR A by k_scatter_csr_fp8 from the binned rows), so the 16 lanes of a group read 256 contiguous bytes per load;
 // its scale bytes as [chunk][512-column tile][column % 16][column / 16 % 32]
 // so that each lane reads the 32 scales of its 32 column blocks as 8 dwords
 // and selects the byte with the instruction's opsel.
@@ -113,6 +113,185 @@ __global__ __launch_bounds__(256) void k_sa_fp8(const T *__restrict__ SA, int64_
   // scale byte at [kc][tile][n % 16][(n / 16) % 32]
   const int64_t tile = n / kBN, nn = n % kBN;
   sc[(kc * (npad / kBN) + tile) * kBN + (nn % 16) * kNB + nn / 16] = (unsigned char)(e + 127);
+}
+
+// S*A of CSR A straight into the quantised layout, without the r x d array.
+// Workgroup (kc, y) owns the 128 buckets of chunk kc and the 64-column
+// slices s = kSlices y .. kSlices y + kSlices - 1, taken one after another
+// through one LDS tile of 128 x 64 accumulators (dtype of A).  Wavefront w
+// (of 8) owns buckets 16 w .. 16 w + 15, one run of the bin list: the row
+// pointers and first kBucketEnt entries of its first 64 rows are loaded
+// once, one row per lane (a lane finds its row's bucket among the 17 bucket
+// pointers, held one per lane), and kept in registers for all slices; later
+// batches of a longer run are reloaded per slice.  Per slice the rows are
+// applied bucket-parallel, each bucket's rows in list order (apply_batch),
+// keeping the entries of the slice's columns, so every sum has the order of
+// the CountSketch scatter.  Then thread (w, l)
+// takes column 64 s + l, buckets 16 w .. 16 w + 15 (one e4m3 group): the
+// column's amax over the chunk gives the scale exponent, and the values are
+// rounded to e4m3 as k_sa_fp8 does.
+constexpr int kSlices = 8;
+
+template <typename T>
+struct RowBatch {
+  int64_t p0, p1;
+  int ng, lb;
+  int rank;   // position of the row among its bucket's rows in the batch, -1 past the run
+  int nrank;  // 1 + the largest rank in the batch
+  uint64_t longmask;
+  int ci[kBucketEnt];
+  T xv[kBucketEnt];
+};
+
+template <typename T>
+__device__ __forceinline__ void load_batch(RowBatch<T> &B, uint32_t base, uint32_t j1,
+                                           uint32_t bpl, const T *__restrict__ vals,
+                                           const int64_t *__restrict__ indptr,
+                                           const int32_t *__restrict__ indices,
+                                           const uint32_t *__restrict__ perm) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const uint32_t j = base + (uint32_t)lane;
+  B.p0 = 0;
+  B.p1 = 0;
+  B.ng = 0;
+  if (j < j1) {
+    const uint32_t pv = perm[j];
+    const int64_t row = (int64_t)(pv & 0x7fffffffu);
+    B.ng = (int)(pv >> 31);
+    B.p0 = indptr[row];
+    B.p1 = indptr[row + 1];
+  }
+  // bucket of list entry j: the last b in 0..15 with bp[b] <= j
+  B.lb = 0;
+#pragma unroll
+  for (int step = 8; step >= 1; step >>= 1) {
+    const uint32_t v = (uint32_t)__shfl((int)bpl, B.lb + step, 64);
+    if (v <= j) B.lb += step;
+  }
+  const int64_t len = B.p1 - B.p0;
+  const bool lng = len > kBucketEnt;
+#pragma unroll
+  for (int e = 0; e < kBucketEnt; ++e) {
+    B.ci[e] = -1;
+    B.xv[e] = T(0);
+    if (!lng && e < len) {
+      B.ci[e] = indices[B.p0 + e];
+      const T v = vals[B.p0 + e];
+      B.xv[e] = B.ng ? -v : v;
+    }
+  }
+  B.longmask = __ballot(lng);
+  // rank counted from the bucket's first row in this batch
+  uint32_t start = (uint32_t)__shfl((int)bpl, B.lb, 64);
+  if (start < base) start = base;
+  B.rank = j < j1 ? (int)(j - start) : -1;
+  int mr = B.rank;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mr = max(mr, __shfl_xor(mr, off, 64));
+  B.nrank = mr + 1;
+}
+
+// Round t applies the t-th row (in list order) of every bucket of the
+// batch: rows of different buckets write different LDS rows, and a bucket's
+// rows keep their order, so each sum is formed in list order.
+template <typename T>
+__device__ __forceinline__ void apply_batch(const RowBatch<T> &B, int64_t c0,
+                                            const T *__restrict__ vals,
+                                            const int32_t *__restrict__ indices, T *myacc) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int64_t len = B.p1 - B.p0;
+  const bool lng = (B.longmask >> lane) & 1u;
+  for (int t = 0; t < B.nrank; ++t) {
+    if (B.rank == t && !lng) {
+#pragma unroll
+      for (int e = 0; e < kBucketEnt; ++e) {
+        const int64_t cl = (int64_t)B.ci[e] - c0;
+        if (e < len && cl >= 0 && cl < 64) atomicAdd(&myacc[B.lb * 64 + cl], B.xv[e]);
+      }
+    }
+    uint64_t lm = __ballot(B.rank == t && lng);
+    while (lm) {
+      const int i = __ffsll((unsigned long long)lm) - 1;
+      lm &= lm - 1;
+      const int64_t q0 = __shfl(B.p0, i, 64);
+      const int64_t q1 = __shfl(B.p1, i, 64);
+      const int ngi = __shfl(B.ng, i, 64);
+      const int lbi = __shfl(B.lb, i, 64);
+      for (int64_t p = q0 + lane; p < q1; p += 64) {
+        const int64_t cl = (int64_t)indices[p] - c0;
+        if (cl >= 0 && cl < 64) {
+          const T v = vals[p];
+          atomicAdd(&myacc[lbi * 64 + cl], ngi ? -v : v);
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(512) void k_scatter_csr_fp8(
+    const T *__restrict__ vals, const int64_t *__restrict__ indptr,
+    const int32_t *__restrict__ indices, int64_t npad, int64_t r,
+    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
+    unsigned char *__restrict__ q, unsigned char *__restrict__ sc) {
+  __shared__ __align__(16) T acc[kBK * 64];
+  __shared__ double amax_s[2][8][64];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t kc = blockIdx.x;
+  const int64_t k0 = kc * kBK;
+  const int b0 = 16 * wave;  // first bucket of this wavefront (in the chunk)
+  // bucket pointers b0 .. b0 + 16, one per lane
+  const int64_t kb = k0 + b0 + (lane <= 16 ? lane : 16);
+  const uint32_t bpl = bptr[kb < r ? kb : r];
+  const uint32_t j0 = (uint32_t)__shfl((int)bpl, 0, 64);
+  const uint32_t j1 = (uint32_t)__shfl((int)bpl, 16, 64);
+  RowBatch<T> first;
+  load_batch(first, j0, j1, bpl, vals, indptr, indices, perm);
+  T *myacc = acc + b0 * 64;
+  const int nsl = (int)(npad / 64);
+  const int s0 = (int)blockIdx.y * kSlices;
+  const int s1 = (s0 + kSlices) < nsl ? (s0 + kSlices) : nsl;
+  for (int sl = s0; sl < s1; ++sl) {
+    const int64_t c0 = (int64_t)sl * 64;
+    for (int i = lane; i < 16 * 64; i += 64) myacc[i] = T(0);
+    if (j0 < j1) apply_batch(first, c0, vals, indices, myacc);
+    for (uint32_t base = j0 + 64; base < j1; base += 64) {
+      RowBatch<T> more;
+      load_batch(more, base, j1, bpl, vals, indptr, indices, perm);
+      apply_batch(more, c0, vals, indices, myacc);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    double am = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) am = fmax(am, fabs((double)myacc[i * 64 + lane]));
+    double(*ams)[64] = amax_s[sl & 1];
+    ams[wave][lane] = am;
+    __syncthreads();
+    double amax = ams[0][lane];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) amax = fmax(amax, ams[w][lane]);
+    int e = scale_exp_f64(amax);
+    e = e < -127 ? -127 : (e > 127 ? 127 : e);
+    const double inv = ldexp(1.0, -e);
+    const int64_t n = c0 + lane;
+    // this wavefront's 16 buckets are e4m3 group gh = wave
+    uint32_t w4[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      float f[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f[u] = f32_odd((double)myacc[(4 * p + u) * 64 + lane] * inv);
+      w4[p] = e4m3x2(f[0], f[1]) | (e4m3x2(f[2], f[3]) << 16);
+    }
+    reinterpret_cast<uint4 *>(q)[(kc * 8 + wave) * npad + n] =
+        uint4{w4[0], w4[1], w4[2], w4[3]};
+    if (wave == 0) {
+      const int64_t tile = n / kBN, nn = n % kBN;
+      sc[(kc * (npad / kBN) + tile) * kBN + (nn % 16) * kNB + nn / 16] =
+          (unsigned char)(e + 127);
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
@@ -279,49 +458,98 @@ __global__ __launch_bounds__(256) void k_reduce_fp8(const float *__restrict__ pa
 
 }  // namespace
 
-int gauss_gemm_fp8(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
-                   int sa_dtype, double *C, Arena &ws, hipStream_t st) {
-  const int tiles_m = (int)ceil_div(m, kBM);
-  const int tiles_n = (int)ceil_div(d, kBN);
-  const int64_t npad = (int64_t)tiles_n * kBN;
-  const int64_t kchunks = ceil_div(r, kBK);
-  const int64_t tiles = (int64_t)tiles_m * tiles_n;
-  int64_t splits = ceil_div(512, tiles);
-  const int64_t max_splits = kchunks / 8 > 0 ? kchunks / 8 : 1;
+namespace {
+
+// Tiling, K split and workspace of one FP8 product (bytes, scales, partials).
+struct Fp8Plan {
+  int tiles_m, tiles_n;
+  int64_t npad, kchunks, tiles, splits, cper;
+  unsigned char *q, *sc;
+  float *part;
+};
+
+int fp8_plan(int64_t m, int64_t r, int64_t d, Arena &ws, Fp8Plan &P) {
+  P.tiles_m = (int)ceil_div(m, kBM);
+  P.tiles_n = (int)ceil_div(d, kBN);
+  P.npad = (int64_t)P.tiles_n * kBN;
+  P.kchunks = ceil_div(r, kBK);
+  P.tiles = (int64_t)P.tiles_m * P.tiles_n;
+  int64_t splits = ceil_div(512, P.tiles);
+  const int64_t max_splits = P.kchunks / 8 > 0 ? P.kchunks / 8 : 1;
   if (splits > max_splits) splits = max_splits;
   if (splits < 1) splits = 1;
-  const int64_t cper = ceil_div(kchunks, splits);
-  splits = ceil_div(kchunks, cper);
-  if ((cper + 1) * 8 * npad * 16 + 65536 >= ((int64_t)1 << 31))
+  P.cper = ceil_div(P.kchunks, splits);
+  P.splits = ceil_div(P.kchunks, P.cper);
+  if ((P.cper + 1) * 8 * P.npad * 16 + 65536 >= ((int64_t)1 << 31))
     return fail(PSK_EUNSUPPORTED, "FP8 Gaussian GEMM: K slice too large for one descriptor");
-  unsigned char *q = ws.take<unsigned char>((size_t)(kchunks * 8 * npad * 16));
-  unsigned char *sc = ws.take<unsigned char>((size_t)(kchunks * npad));
-  float *part = ws.take<float>((size_t)splits * m * d);
-  if (ws.dry()) return 0;
-  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the FP8 Gaussian GEMM");
-  {
-    KTimer t("sa_quant", st);
-    const int64_t threads = kchunks * npad;
-    if (sa_dtype == PSK_F64)
-      k_sa_fp8<double><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
-          (const double *)SA, r, d, npad, kchunks, q, sc);
-    else
-      k_sa_fp8<float><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
-          (const float *)SA, r, d, npad, kchunks, q, sc);
-  }
+  P.q = ws.take<unsigned char>((size_t)(P.kchunks * 8 * P.npad * 16));
+  P.sc = ws.take<unsigned char>((size_t)(P.kchunks * P.npad));
+  P.part = ws.take<float>((size_t)P.splits * m * d);
+  if (!ws.dry() && !ws.ok())
+    return fail(PSK_ENOMEM, "workspace too small for the FP8 Gaussian GEMM");
+  return 0;
+}
+
+int fp8_run(const Fp8Plan &P, int64_t m, int64_t d, uint64_t seed, double *C,
+            hipStream_t st) {
   {
     KTimer t("gauss_gemm", st);
-    k_gauss_gemm_fp8<<<(unsigned)(tiles * splits), kThreads, 0, st>>>(
-        m, d, npad, seed, q, sc, tiles_m, tiles_n, kchunks, cper, part);
+    k_gauss_gemm_fp8<<<(unsigned)(P.tiles * P.splits), kThreads, 0, st>>>(
+        m, d, P.npad, seed, P.q, P.sc, P.tiles_m, P.tiles_n, P.kchunks, P.cper, P.part);
   }
   {
     KTimer t("gemm_reduce", st);
     const int64_t len = m * d;
-    k_reduce_fp8<<<(unsigned)ceil_div(len, 256), 256, 0, st>>>(part, len, (int)splits,
+    k_reduce_fp8<<<(unsigned)ceil_div(len, 256), 256, 0, st>>>(P.part, len, (int)P.splits,
                                                                  1.0 / sqrt((double)m), C);
   }
   PSK_HIP_TRY(hipGetLastError());
   return 0;
+}
+
+}  // namespace
+
+int gauss_gemm_fp8(int64_t m, int64_t r, int64_t d, uint64_t seed, const void *SA,
+                   int sa_dtype, double *C, Arena &ws, hipStream_t st) {
+  Fp8Plan P;
+  int rc = fp8_plan(m, r, d, ws, P);
+  if (rc || ws.dry()) return rc;
+  {
+    KTimer t("sa_quant", st);
+    const int64_t threads = P.kchunks * P.npad;
+    if (sa_dtype == PSK_F64)
+      k_sa_fp8<double><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
+          (const double *)SA, r, d, P.npad, P.kchunks, P.q, P.sc);
+    else
+      k_sa_fp8<float><<<(unsigned)ceil_div(threads, 256), 256, 0, st>>>(
+          (const float *)SA, r, d, P.npad, P.kchunks, P.q, P.sc);
+  }
+  return fp8_run(P, m, d, seed, C, st);
+}
+
+bool fp8_csr_fusable(const psk_mat &A, int64_t r) {
+  return A.format == PSK_CSR && cs_splits(A.n, r) == 1;
+}
+
+int gauss_gemm_fp8_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
+                       const uint32_t *bptr, uint64_t seed, double *C, Arena &ws,
+                       hipStream_t st) {
+  if (!fp8_csr_fusable(A, r))
+    return fail(PSK_EUNSUPPORTED, "fused CSR quantisation needs one split per bucket");
+  Fp8Plan P;
+  int rc = fp8_plan(m, r, A.d, ws, P);
+  if (rc || ws.dry()) return rc;
+  {
+    KTimer t("cs_scatter_quant", st);
+    const dim3 grid((unsigned)P.kchunks, (unsigned)ceil_div(P.npad / 64, kSlices));
+    if (A.dtype == PSK_F64)
+      k_scatter_csr_fp8<double><<<grid, 512, 0, st>>>(
+          (const double *)A.values, A.indptr, A.indices, P.npad, r, perm, bptr, P.q, P.sc);
+    else
+      k_scatter_csr_fp8<float><<<grid, 512, 0, st>>>(
+          (const float *)A.values, A.indptr, A.indices, P.npad, r, perm, bptr, P.q, P.sc);
+  }
+  return fp8_run(P, m, A.d, seed, C, st);
 }
 
 }  // namespace psk

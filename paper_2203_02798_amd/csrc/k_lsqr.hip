@@ -798,9 +798,10 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
       o.escalate_cond != 0.0 ? o.escalate_cond : (o.prec == PSK_PREC_FP8 ? 10.0 : 1e4);
   const bool may_escalate =
       own && (o.prec == PSK_PREC_BF16 || o.prec == PSK_PREC_FP8) && cond_limit > 0.0;
-  // CSR A with the BF16 GEMM: the limbs come straight from the binned rows
-  // and S*A is only formed if the solve escalates to FP64
-  const bool fused = own && o.prec == PSK_PREC_BF16 && bf16_csr_fusable(A, o.r);
+  // CSR A with the BF16 or FP8 GEMM: its operand comes straight from the
+  // binned rows and S*A is only formed if the solve escalates to FP64
+  const bool fused = own && ((o.prec == PSK_PREC_BF16 && bf16_csr_fusable(A, o.r)) ||
+                             (o.prec == PSK_PREC_FP8 && fp8_csr_fusable(A, o.r)));
   void *SA = nullptr;
   uint32_t *perm = nullptr, *bptr = nullptr;
   // the FP64 sketch (after a reduced-precision one), S*A formed here if needed
@@ -820,8 +821,10 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     if ((rc = cs_bin(n, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr))) return rc;
     if (!fused && (rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return rc;
     const size_t mk2 = ws.mark();
-    if (fused)
+    if (fused && o.prec == PSK_PREC_BF16)
       rc = gauss_gemm_bf16_csr(m, o.r, A, perm, bptr, o.seed, C, ws, st);
+    else if (fused)
+      rc = gauss_gemm_fp8_csr(m, o.r, A, perm, bptr, o.seed, C, ws, st);
     else
       rc = gauss_gemm(m, o.r, d, o.seed, o.prec, SA, A.dtype, C, ws, st);
     if (rc) return rc;

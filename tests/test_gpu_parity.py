@@ -224,12 +224,23 @@ def test_sketch_gcs_fp8_deterministic(api):
     assert torch.equal(c1, c2)
 
 
-@pytest.mark.parametrize("cond,want", [(1.0, "fp8"), (1e3, "f64")])
-def test_lsq_solve_fp8_sketch(api, cond, want):
-    a, b, _ = synth.lsq_problem(20000, 32, cond, seed=2)
+@pytest.mark.parametrize("kind,cond,want", [("dense", 1.0, "fp8"), ("dense", 1e3, "f64"),
+                                            ("csr", 1.0, "fp8"), ("csr", 1e3, "f64")])
+def test_lsq_solve_fp8_sketch(api, kind, cond, want):
+    # CSR A: the FP8 bytes come from the binned rows; S*A is formed only when
+    # the solve escalates
+    if kind == "csr":
+        n, d = 20000, 32
+        a = synth.csr_uniform(n, d, 0.2, seed=2)
+        if cond > 1.0:
+            a = (a @ sp.diags(np.logspace(0.0, -np.log10(cond), d))).tocsr()
+        xt = np.random.default_rng(0).standard_normal(d)
+        b = a @ xt + 1e-3 * np.random.default_rng(1).standard_normal(n)
+    else:
+        a, b, _ = synth.lsq_problem(20000, 32, cond, seed=2)
     x, info = api.lsq_solve(to_device(a), torch.from_numpy(b).cuda(), m=8 * 32, r=32 * 32,
                             seed=3, prec="fp8")
-    _say(f"lsq fp8 cond={cond}: {info}")
+    _say(f"lsq fp8 {kind} cond={cond}: {info}")
     assert info["prec_used"] == want and info["status"] == "PSK_OK"
     rs, _ = olsq.lsq_quality(a, b, olsq.lstsq(a, b))
     rn, ne = olsq.lsq_quality(a, b, x.cpu().numpy())
