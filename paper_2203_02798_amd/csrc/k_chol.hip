@@ -11,13 +11,19 @@
 // preconditioner).  Cholesky-QR keeps the work in GEMMs on the matrix cores
 // (W = C^T C, Q = C R^{-1}); the shift s = 11 (m d + d (d+1)) u ||C||_F^2 on
 // the first pass keeps the Cholesky factorization defined for condition
-// numbers up to about 1/u, and two unshifted passes restore orthogonality.
+// numbers up to about 1/u, and up to two unshifted passes restore
+// orthogonality.  The second pass stops the factorisation when its Gram
+// matrix is within 1e-4 of the identity: then the first pass's Q was
+// already orthonormal to that level, the second pass leaves it orthonormal
+// to rounding level (Cholesky-QR loses orthogonality like cond(Q)^2 u), and
+// a third pass would change R only by rounding.  Otherwise (ill-conditioned
+// C) the third pass runs as in sCQR3.
 //
 // The d x d Cholesky and the inverse of its factor are blocked by 64 columns
 // with one launch per block step (k_chol_step, below): the panel, the
-// trailing update, one block column of R^{-1} and the factorization of the
-// next diagonal block all happen in the same launch, so a pass costs
-// ceil(d/64) + 1 launches besides its two GEMMs with C.
+// trailing update, the partial products of R^{-1} and the factorization of
+// the next diagonal block all happen in the same launch, so a pass costs
+// ceil(d/64) + 2 launches besides its two GEMMs with C.
 #include "internal.hpp"
 
 namespace psk {
@@ -345,10 +351,8 @@ __device__ __forceinline__ void panel_tile(const double *__restrict__ W, const d
 __global__ __launch_bounds__(kTh) void k_chol_first(const double *__restrict__ W, int64_t d,
                                                     double *__restrict__ R,
                                                     double *__restrict__ X,
-                                                    int *__restrict__ flag,
-                                                    const int *__restrict__ sel) {
+                                                    int *__restrict__ flag) {
   __shared__ CholSmem S;
-  if (sel && *sel != 0) return;  // the series path was selected
   const int nb = (int)(d < 64 ? d : 64);
   for (int e = threadIdx.x; e < 64 * 64; e += kTh) {
     const int i = e >> 6, jj = e & 63;
@@ -363,10 +367,8 @@ __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64
                                                    double *__restrict__ R,
                                                    double *__restrict__ X,
                                                    int *__restrict__ flag,
-                                                   const int *__restrict__ sel,
                                                    double *__restrict__ xpart) {
   __shared__ CholSmem S;
-  if (sel && *sel != 0) return;  // the series path was selected
   const int p = j < nblk ? nblk - j - 1 : 0;
   const int ntrail = p * (p + 1) / 2;
   const int npart = (j >= 2 && j < nblk) ? (j - 1) * j / 2 : 0;
@@ -514,11 +516,11 @@ __global__ __launch_bounds__(kTh) void k_chol_step(double *__restrict__ W, int64
 // the diagonal.  The fixed point iteration U_0 = Phi(E), U_{t+1} =
 // Phi(E - U_t^T U_t) gains a factor ~||E|| per step; X = R^{-1} is the
 // Neumann series I - U + U^2 - ..., evaluated as X_{t+1} = I - U X_t.  For
-// ||E||_F <= kSeriesTol = 1e-4 two steps of each leave errors below 1e-16.
-// The choice between this path and the blocked Cholesky is made on the
-// device (k_decide writes *sel), so no host synchronisation is needed: the
-// series results are copied in only when selected, and the Cholesky
-// kernels return at once when not.
+// ||E||_F <= kSeriesTol = 1e-4 two steps of each leave errors below 1e-16;
+// smaller ||E|| needs fewer (series_depth).  ||E||_F is read back to the
+// host (one stream synchronisation per pass), which picks the series or
+// the blocked Cholesky and, after a second pass that took the series, ends
+// the factorisation there.
 // ---------------------------------------------------------------------------
 constexpr double kSeriesTol = 1e-4;
 constexpr int kParts = 64;
@@ -541,14 +543,6 @@ __global__ __launch_bounds__(256) void k_fro_partials(const double *__restrict__
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// *sel = 1 if ||W - I||_F <= tol (series path), else 0 (Cholesky path)
-__global__ void k_decide(const double *__restrict__ part, double tol, int *__restrict__ sel) {
-  if (threadIdx.x != 0) return;
-  double s = 0.0;
-  for (int b = 0; b < kParts; ++b) s += part[b];
-  *sel = (s <= tol * tol) ? 1 : 0;
 }
 
 // U = Phi(W - I) (the whole matrix: zero below the diagonal)
@@ -592,31 +586,18 @@ __global__ __launch_bounds__(256) void k_series_x(const double *__restrict__ T, 
   X[e] = jj >= i ? (i == jj ? 1.0 : 0.0) - T[e] : 0.0;
 }
 
-// *sel == 1: R, X = the series results; else zero them for the Cholesky path
-__global__ __launch_bounds__(256) void k_series_select(const double *__restrict__ Rs,
-                                                       const double *__restrict__ Xs,
-                                                       int64_t d, const int *__restrict__ sel,
-                                                       double *__restrict__ R,
-                                                       double *__restrict__ X) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= d * d) return;
-  const bool s = *sel == 1;
-  R[e] = s ? Rs[e] : 0.0;
-  X[e] = s ? Xs[e] : 0.0;
-}
-
 void fill(double *p, int64_t count, double v, hipStream_t st) {
   k_fill<<<(unsigned)ceil_div(count, 256), 256, 0, st>>>(p, count, v);
 }
 
 // Upper Cholesky of W (destroyed) into R, and X = R^{-1}; R and X must be
-// zero on entry.  With sel, the launches do nothing unless *sel == 0.
+// zero on entry.
 // xpart: scratch of at least d * d doubles for the partial products of the
 // off-diagonal blocks of X (two block columns' worth, by parity).
-void chol_inv(double *W, int64_t d, double *R, double *X, int *flag, const int *sel,
-              double *xpart, hipStream_t st) {
+void chol_inv(double *W, int64_t d, double *R, double *X, int *flag, double *xpart,
+              hipStream_t st) {
   const int nblk = (int)ceil_div(d, 64);
-  k_chol_first<<<1, kTh, 0, st>>>(W, d, R, X, flag, sel);
+  k_chol_first<<<1, kTh, 0, st>>>(W, d, R, X, flag);
   // launch j = nblk only finishes the last block column of X
   for (int j = 0; j <= nblk; ++j) {
     const int p = j < nblk ? nblk - j - 1 : 0;
@@ -624,46 +605,76 @@ void chol_inv(double *W, int64_t d, double *R, double *X, int *flag, const int *
     const int nfin = j - 1 >= 1 ? j - 1 : 0;
     const int tiles = p * (p + 1) / 2 + npart + nfin + p;
     if (tiles > 0)
-      k_chol_step<<<tiles, kTh, 0, st>>>(W, d, nblk, j, R, X, flag, sel, xpart);
+      k_chol_step<<<tiles, kTh, 0, st>>>(W, d, nblk, j, R, X, flag, xpart);
   }
 }
 
-// R, X of W = I + E: the series is always evaluated (four d x d products)
-// and taken when ||E||_F <= kSeriesTol; otherwise the blocked Cholesky runs
-// (its launches return at once when the series was taken).  The choice is
-// made on the device.  B0..B3: d x d scratch; part: kParts doubles; sel: one
-// int.
-int near_identity_chol(double *W, int64_t d, double *R, double *X, double *B0, double *B1,
-                       double *B2, double *B3, double *part, int *sel, int *flag,
-                       Arena &ws, hipStream_t st) {
+// ||W - I||_F^2, summed on the host in a fixed order from kParts device
+// partials (synchronises the stream).
+int fro_dist_identity_sq(const double *W, int64_t d, double *part, hipStream_t st,
+                         double *out) {
+  k_fro_partials<<<kParts, 256, 0, st>>>(W, d, part);
+  double h[kParts];
+  PSK_HIP_TRY(hipMemcpyAsync(h, part, sizeof(h), hipMemcpyDeviceToHost, st));
+  PSK_HIP_TRY(hipStreamSynchronize(st));
+  double sum = 0.0;
+  for (int b = 0; b < kParts; ++b) sum += h[b];
+  *out = sum;
+  return 0;
+}
+
+// Products of the series for ||E||_F = eps: after t fixed-point steps U is
+// off by about 2^t eps^(t+2), and I - U + ... + (-U)^(t+1) by eps^(t+2).
+int series_depth(double eps) {
+  if (eps <= 1e-8) return 0;
+  if (eps <= 3e-6) return 1;
+  return 2;
+}
+
+// R = I + U, X = R^{-1} of W = I + E with ||E||_F <= kSeriesTol: U_0 =
+// Phi(E), U_{t+1} = Phi(E - U_t^T U_t), X_1 = I - U, X_{t+1} = I - U X_t,
+// `depth` steps of each.  B0, B1, B2: d x d scratch.
+int series_chol(const double *W, int64_t d, int depth, double *R, double *X, double *B0,
+                double *B1, double *B2, Arena &ws, hipStream_t st) {
   const bool run = !ws.dry();
   const unsigned ew = (unsigned)ceil_div(d * d, 256);
   const size_t mk = ws.mark();
   int rc;
-  if (run) {
-    k_fro_partials<<<kParts, 256, 0, st>>>(W, d, part);
-    k_decide<<<1, 64, 0, st>>>(part, kSeriesTol, sel);
-    k_series_u0<<<ew, 256, 0, st>>>(W, d, B0);
-  }
-  // U_{t+1} = Phi(E - U_t^T U_t), two steps: B0 -> B1 -> B0
+  if (run) k_series_u0<<<ew, 256, 0, st>>>(W, d, B0);
   double *u = B0, *v = B1;
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < depth; ++t) {
     if ((rc = dgemm(true, false, d, d, d, 1.0, u, d, u, d, 0.0, B2, d, ws, st))) return rc;
     ws.release(mk);
     if (run) k_series_phi<<<ew, 256, 0, st>>>(W, B2, d, v);
     double *tmp = u; u = v; v = tmp;
   }
-  // R_s = I + U (B3), X_1 = I - U (v); X_{t+1} = I - U X_t, two steps
-  if (run) k_series_rx<<<ew, 256, 0, st>>>(u, d, B3, v);
-  for (int t = 0; t < 2; ++t) {
-    if ((rc = dgemm(false, false, d, d, d, 1.0, u, d, v, d, 0.0, B2, d, ws, st))) return rc;
+  if (run) k_series_rx<<<ew, 256, 0, st>>>(u, d, R, X);
+  for (int t = 0; t < depth; ++t) {
+    if ((rc = dgemm(false, false, d, d, d, 1.0, u, d, X, d, 0.0, B2, d, ws, st))) return rc;
     ws.release(mk);
-    if (run) k_series_x<<<ew, 256, 0, st>>>(B2, d, v);
+    if (run) k_series_x<<<ew, 256, 0, st>>>(B2, d, X);
   }
-  if (run) {
-    k_series_select<<<ew, 256, 0, st>>>(B3, v, d, sel, R, X);
-    chol_inv(W, d, R, X, flag, sel, B2, st);  // B2 is free again here
+  return 0;
+}
+
+// R, X of the Gram matrix W = Q^T Q of a pass after the first: the series
+// when ||W - I||_F <= kSeriesTol, else the blocked Cholesky.  In a planning
+// run (no data) both are planned.  *series tells which ran.
+int later_pass_chol(double *W, int64_t d, double *R, double *X, double *B0, double *B1,
+                    double *B2, double *part, int *flag, bool *series, Arena &ws,
+                    hipStream_t st) {
+  int rc;
+  if (ws.dry()) {
+    *series = false;
+    return series_chol(W, d, 2, R, X, B0, B1, B2, ws, st);
   }
+  double e2;
+  if ((rc = fro_dist_identity_sq(W, d, part, st, &e2))) return rc;
+  *series = e2 <= kSeriesTol * kSeriesTol;
+  if (*series) return series_chol(W, d, series_depth(sqrt(e2)), R, X, B0, B1, B2, ws, st);
+  fill(R, d * d, 0.0, st);
+  fill(X, d * d, 0.0, st);
+  chol_inv(W, d, R, X, flag, B2, st);
   return 0;
 }
 
@@ -692,7 +703,7 @@ int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rin
   const size_t mk = ws.mark();
   int rc;
   KTimer timer("sketch_qr", st);
-  // flag[0]: a Cholesky pivot failed; flag[1], flag[2]: path of passes 2, 3
+  // flag[0]: a Cholesky pivot failed
   if (run) k_fill<<<1, 64, 0, st>>>(reinterpret_cast<double *>(flag), 2, 0.0);
   if (flag_out) *flag_out = flag;
   // pass 1 (shifted): W = C^T C + s I, blocked Cholesky
@@ -704,22 +715,34 @@ int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rin
     k_shift_diag<<<1, 256, 0, st>>>(W, d, coef);
     fill(R1, d * d, 0.0, st);
     fill(X1, d * d, 0.0, st);
-    chol_inv(W, d, R1, X1, flag, nullptr, B0, st);  // B0 is not in use yet
+    chol_inv(W, d, R1, X1, flag, B0, st);  // B0 is not in use yet
   }
   if ((rc = dgemm(false, false, m, d, d, 1.0, C, d, X1, d, 0.0, Qa, d, ws, st))) return rc;
   ws.release(mk);
   // pass 2: W = Qa^T Qa
   if ((rc = dgemm(true, false, d, d, m, 1.0, Qa, d, Qa, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
-  if ((rc = near_identity_chol(W, d, R2, X2, B0, B1, B2, T, part, flag + 1, flag, ws, st)))
+  bool series2 = false, series3 = false;
+  if ((rc = later_pass_chol(W, d, R2, X2, B0, B1, B2, part, flag, &series2, ws, st)))
     return rc;
   ws.release(mk);
+  // When pass 2 took the series (Qa was orthonormal to within 1e-4), its
+  // result is orthonormal to rounding level and a third pass would change R
+  // only at that level: R = R2 R1, R^{-1} = X1 X2.
+  if (series2) {
+    if ((rc = dgemm(false, false, d, d, d, 1.0, R2, d, R1, d, 0.0, R, d, ws, st))) return rc;
+    ws.release(mk);
+    if ((rc = dgemm(false, false, d, d, d, 1.0, X1, d, X2, d, 0.0, Rinv, d, ws, st))) return rc;
+    ws.release(mk);
+    if (run) PSK_HIP_TRY(hipGetLastError());
+    return 0;
+  }
   if ((rc = dgemm(false, false, m, d, d, 1.0, Qa, d, X2, d, 0.0, Qb, d, ws, st))) return rc;
   ws.release(mk);
   // pass 3: W = Qb^T Qb
   if ((rc = dgemm(true, false, d, d, m, 1.0, Qb, d, Qb, d, 0.0, W, d, ws, st))) return rc;
   ws.release(mk);
-  if ((rc = near_identity_chol(W, d, R3, X3, B0, B1, B2, T, part, flag + 2, flag, ws, st)))
+  if ((rc = later_pass_chol(W, d, R3, X3, B0, B1, B2, part, flag, &series3, ws, st)))
     return rc;
   ws.release(mk);
   // R = R3 R2 R1, R^{-1} = X1 X2 X3
