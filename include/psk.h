@@ -237,9 +237,10 @@ typedef struct psk_lsq_info {
  * operator A*R^{-1} (Paige & Saunders 1982) in FP64, x = R^{-1} y, then
  * `refine` passes that solve for the residual and add the correction.
  *   b : n FP64 (device);  x : d FP64 (device, output).
- * The call enqueues LSQR iterations in groups of check_every and
- * synchronises `stream` after each group to read the convergence flag, so
- * it returns with the stream idle.
+ * The call enqueues LSQR iterations in groups of check_every; each group's
+ * convergence flag is copied to pinned host memory (a few pinned bytes per
+ * concurrent solve, kept for the life of the process) and read while the
+ * next group runs.  The call returns with the stream idle.
  * Errors: PSK_EINVAL, PSK_ENOMEM, PSK_ENOCONV (x still written), PSK_ERANK. */
 int lsq_solve(const psk_mat *A, const double *b, double *x,
               const psk_lsq_opts *opts, psk_lsq_info *info,

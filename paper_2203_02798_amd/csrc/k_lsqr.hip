@@ -10,19 +10,25 @@
 // One LSQR iteration reads A once: for every row, u_i <- A_i vhat - alpha u_i
 // and A_i^T u_i is accumulated immediately (the normalisation by beta is a
 // scalar applied afterwards), so the two products A v and A^T u of the
-// bidiagonalisation share one pass over A.  An iteration is four kernels:
-//   pass    (1024 workgroups) per-workgroup partial A^T u and ||u||^2;
-//   reduce  (d/64 x 16)       first level of the partial sums;
-//   vnew    (d/8)             t = A^T u / beta, vnew = R^{-T} t - beta v;
-//   update  (d/8)             vhat = R^{-1} vnew / alpha for the next pass,
-//                             and (workgroup 0) the scalar recurrences, v, w,
-//                             y and the stopping test.
+// bidiagonalisation share one pass over A.  An iteration is three kernels:
+//   pass    (512 workgroups)  per-workgroup partial A^T u and ||u||^2;
+//   vnew    (d/16)            beta, t = A^T u / beta for 16 rows each, and
+//                             those rows' share of R^{-T} t;
+//   update  (d/8 + 1)         vnew = R^{-T} t - beta v and alpha = ||vnew||
+//                             (every workgroup sums the shares in the same
+//                             order), vhat = R^{-1} vnew / alpha for the next
+//                             pass, and (the extra workgroup) the scalar
+//                             recurrences, v, w, y and the stopping test.
 // All state stays on the device; a `done` flag set by the stopping test turns
-// the remaining enqueued iterations into no-ops, so the host synchronises
-// only every `check_every` iterations.  Every sum has a fixed order (CSR rows
+// the remaining enqueued iterations into no-ops, so the host reads the state
+// only every `check_every` iterations, and reads each group's copy while the
+// next group runs.  Every sum has a fixed order (CSR rows
 // scatter A_i^T u_i into per-wavefront LDS rows in a fixed instruction
 // order).
 #include <math.h>
+
+#include <mutex>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -35,8 +41,52 @@ struct LsqrState {
   int done, iters, pad0, pad1;
 };
 
-constexpr int kPassBlocks = 1024;
-constexpr int kRedGroups = 16;  // kPassBlocks / kRedGroups = 64 partials per group
+// Pinned host copies of the LSQR state with their events: the host reads a
+// group's convergence flag while the next group runs.  Kept for the life of
+// the process and reused (one pair per running solve, per device).
+struct StateSlot {
+  int dev = -1;
+  LsqrState *h = nullptr;  // two snapshots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+std::mutex g_slot_mu;
+std::vector<StateSlot> g_free_slots;
+
+int take_slot(StateSlot *out) {
+  int dev = 0;
+  PSK_HIP_TRY(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    for (size_t i = 0; i < g_free_slots.size(); ++i)
+      if (g_free_slots[i].dev == dev) {
+        *out = g_free_slots[i];
+        g_free_slots.erase(g_free_slots.begin() + (long)i);
+        return 0;
+      }
+  }
+  StateSlot sl;
+  sl.dev = dev;
+  PSK_HIP_TRY(hipHostMalloc((void **)&sl.h, 2 * sizeof(LsqrState), hipHostMallocDefault));
+  for (int k = 0; k < 2; ++k)
+    PSK_HIP_TRY(hipEventCreateWithFlags(&sl.ev[k], hipEventDisableTiming));
+  *out = sl;
+  return 0;
+}
+
+// returns the slot to the pool once no copy into it is pending
+struct SlotGuard {
+  StateSlot sl;
+  bool held = false;
+  ~SlotGuard() {
+    if (!held) return;
+    for (int k = 0; k < 2; ++k) (void)hipEventSynchronize(sl.ev[k]);
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    g_free_slots.push_back(sl);
+  }
+};
+
+constexpr int kPassBlocks = 512;  // partial A^T u vectors per pass
+constexpr int kCsrWaves = 8;      // wavefronts of a CSR pass workgroup
 constexpr int kShortRow = 16;   // CSR rows up to this length take one lane each
 constexpr int kRowsPerLane = 4; // CSR rows a lane works on at once in a pass
 constexpr int kRegEntries = 4;  // entries per short CSR row held in registers
@@ -56,7 +106,7 @@ __device__ __forceinline__ void block_rows(int64_t n, int64_t &r0, int64_t &r1) 
 // to kRegEntries.  Additions keep the order: entries in sequence within a
 // row; rows r, then lanes, into a wavefront's LDS accumulator row.
 template <typename T, bool INIT>
-__global__ __launch_bounds__(256, 4) void k_pass_csr(
+__global__ __launch_bounds__(64 * kCsrWaves, 4) void k_pass_csr(
     const T *__restrict__ vals, const int64_t *__restrict__ indptr,
     const int32_t *__restrict__ indices, int64_t n, int64_t d,
     const double *__restrict__ vhat, const double *__restrict__ rhs,
@@ -64,9 +114,9 @@ __global__ __launch_bounds__(256, 4) void k_pass_csr(
     double *__restrict__ part_t, double *__restrict__ part_b2) {
   if (!INIT && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *tl = reinterpret_cast<double *>(smem_raw);  // 4 x d accumulators
-  double *vh = tl + 4 * d;                             // vhat, d
-  __shared__ double b2s[4];
+  double *tl = reinterpret_cast<double *>(smem_raw);  // kCsrWaves x d accumulators
+  double *vh = tl + kCsrWaves * d;                     // vhat, d
+  __shared__ double b2s[kCsrWaves];
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   int64_t rb0, rb1;
@@ -92,14 +142,14 @@ __global__ __launch_bounds__(256, 4) void k_pass_csr(
   };
   int64_t base = rb0 + wave * 64 * kRowsPerLane;
   fetch(base);
-  for (int64_t c = threadIdx.x; c < 4 * d; c += 256) tl[c] = 0.0;
+  for (int64_t c = threadIdx.x; c < kCsrWaves * d; c += 64 * kCsrWaves) tl[c] = 0.0;
   if (!INIT)
-    for (int64_t c = threadIdx.x; c < d; c += 256) vh[c] = vhat[c];
+    for (int64_t c = threadIdx.x; c < d; c += 64 * kCsrWaves) vh[c] = vhat[c];
   __syncthreads();
   double *tw = tl + (int64_t)wave * d;
   const double au = INIT ? 0.0 : st->alpha * st->ufac;
   double b2 = 0.0;
-  for (; base < rb1; base += 256 * kRowsPerLane) {
+  for (; base < rb1; base += 64 * kCsrWaves * kRowsPerLane) {
     int64_t p0[kRowsPerLane];
     int len[kRowsPerLane];  // entries of a short row, 0 for long or absent rows
     uint64_t longmask[kRowsPerLane];
@@ -199,15 +249,24 @@ __global__ __launch_bounds__(256, 4) void k_pass_csr(
           atomicAdd(&tw[indices[p]], (double)vals[p] * uv);
       }
     }
-    if (base + 256 * kRowsPerLane < rb1) fetch(base + 256 * kRowsPerLane);
+    if (base + 64 * kCsrWaves * kRowsPerLane < rb1)
+      fetch(base + 64 * kCsrWaves * kRowsPerLane);
   }
   b2 = wave_sum(b2);
   if (lane == 0) b2s[wave] = b2;
   __syncthreads();
-  for (int64_t c = threadIdx.x; c < d; c += 256)
-    part_t[(int64_t)blockIdx.x * d + c] =
-        ((tl[c] + tl[d + c]) + tl[2 * d + c]) + tl[3 * d + c];
-  if (threadIdx.x == 0) part_b2[blockIdx.x] = ((b2s[0] + b2s[1]) + b2s[2]) + b2s[3];
+  for (int64_t c = threadIdx.x; c < d; c += 64 * kCsrWaves) {
+    double t = tl[c];
+#pragma unroll
+    for (int w = 1; w < kCsrWaves; ++w) t += tl[(int64_t)w * d + c];
+    part_t[(int64_t)blockIdx.x * d + c] = t;
+  }
+  if (threadIdx.x == 0) {
+    double t = b2s[0];
+#pragma unroll
+    for (int w = 1; w < kCsrWaves; ++w) t += b2s[w];
+    part_b2[blockIdx.x] = t;
+  }
 }
 
 // dense rows: wavefront per row, lane owns columns lane + 64k (k < KC)
@@ -303,31 +362,8 @@ __global__ __launch_bounds__(256) void k_pass_dense(
   if (threadIdx.x == 0) part_b2[blockIdx.x] = ((b2s[0] + b2s[1]) + b2s[2]) + b2s[3];
 }
 
-// part2[g][c] = sum of the 64 pass partials of group g, column c
-__global__ __launch_bounds__(256) void k_reduce1(const double *__restrict__ part_t, int64_t d,
-                                                 const LsqrState *__restrict__ st,
-                                                 double *__restrict__ part2, int init) {
-  if (!init && st->done) return;
-  __shared__ double red[4][64];
-  const int sub = threadIdx.x >> 6;
-  const int c = threadIdx.x & 63;
-  const int64_t col = (int64_t)blockIdx.x * 64 + c;
-  const int g = blockIdx.y;
-  constexpr int per = kPassBlocks / kRedGroups;
-  double s = 0.0;
-  if (col < d) {
-#pragma unroll 4
-    for (int q = 0; q < per / 4; ++q) s += part_t[(int64_t)(g * per + sub + 4 * q) * d + col];
-  }
-  red[sub][c] = s;
-  __syncthreads();
-  if (sub == 0 && col < d)
-    part2[(int64_t)g * d + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-}
-
-// beta = ||u||, t = (A^T u) / beta, vnew_j = sum_{i<=j} Rinv[i][j] t_i - beta v_j.
-// A workgroup owns 8 columns; its 256 threads split the i range into 32
-// phases (four independent accumulators each), combined in a fixed order.
+// Triangular products with R^{-1}: a workgroup owns 8 rows (or columns);
+// its 256 threads split the other index into 32 phases.
 constexpr int kColsPerBlk = 8;
 constexpr int kPhases = 32;
 constexpr int kMaxK = 1024 / kPhases;  // terms per thread in a phase (d <= 1024)
@@ -357,86 +393,80 @@ __device__ __forceinline__ double phased_dot(const double (&rv)[kMaxK],
   return (a0 + a1) + (a2 + a3);
 }
 
-__global__ __launch_bounds__(256) void k_vnew(const double *__restrict__ part2,
-                                              const double *__restrict__ part_b2,
-                                              const double *__restrict__ Rinv, int64_t d,
-                                              const double *__restrict__ v,
-                                              LsqrState *__restrict__ st,
-                                              double *__restrict__ vnew,
-                                              double *__restrict__ part_a2, int init) {
+// beta = ||u||, t = (A^T u) / beta and the contributions of rows
+// i0 .. i0 + kVRows - 1 of R^{-1} to vnew_j = sum_{i<=j} Rinv[i][j] t_i
+// (the -beta v term is added where the partials are summed, k_update).
+// Workgroup b owns those rows: it sums their t_i from the kPassBlocks pass
+// partials (thread (g, c): column i0 + c, partials g, g + kVGroups, ...;
+// the groups then in order) and writes vpart[b][j] for j >= i0.
+constexpr int kVRows = 16;
+constexpr int kVThreads = 512;
+constexpr int kVGroups = kVThreads / kVRows;  // 32
+constexpr int kVSlots = 1024 / kVThreads;     // columns j per thread (d <= 1024)
+
+__global__ __launch_bounds__(kVThreads) void k_vnew_rows(
+    const double *__restrict__ part_t, const double *__restrict__ part_b2,
+    const double *__restrict__ Rinv, int64_t d, LsqrState *__restrict__ st,
+    double *__restrict__ vpart, int init) {
   if (!init && st->done) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *tvs = reinterpret_cast<double *>(smem_raw);  // d doubles
-  __shared__ double red[kPhases][kColsPerBlk + 1];
-  __shared__ double bred[4];
+  __shared__ double red[kVGroups][kVRows + 1];
+  __shared__ double tv[kVRows];
+  __shared__ double bred[kVThreads / 64];
   const int tid = threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * kColsPerBlk;
-  int64_t ilim = j0 + kColsPerBlk;
-  if (ilim > d) ilim = d;
-  const int g = tid >> 3;
-  const int c = tid & 7;
-  const int64_t j = j0 + c;
-  // terms i = g + kPhases k <= j of column j
-  const int K = (j < d && j >= g) ? (int)((j - g) / kPhases) + 1 : 0;
-  // every global load of the workgroup is issued before the first wait:
-  // the R^{-1} entries, the partial squares and the partial sums of A^T u
-  double rv[kMaxK];
+  const int c = tid % kVRows, g = tid / kVRows;
+  const int64_t i0 = (int64_t)blockIdx.x * kVRows;
+  const int64_t i = i0 + c;
+  // loads first, all unconditional (indices clamped into range, values
+  // masked afterwards): the pass partials, one partial square and the
+  // R^{-1} entries of this thread's columns j in the workgroup's rows
+  const int64_t ic = i < d ? i : d - 1;
+  double pt[kPassBlocks / kVGroups];
 #pragma unroll
-  for (int k = 0; k < kMaxK; ++k)
-    rv[k] = k < K ? Rinv[(int64_t)(g + kPhases * k) * d + j] : 0.0;
-  double pb[kPassBlocks / 256];
+  for (int q = 0; q < kPassBlocks / kVGroups; ++q)
+    pt[q] = part_t[(int64_t)(g + kVGroups * q) * d + ic];
+  double s = part_b2[tid < kPassBlocks ? tid : 0];
+  double rr[kVSlots][kVRows];
 #pragma unroll
-  for (int q = 0; q < kPassBlocks / 256; ++q) pb[q] = part_b2[tid + 256 * q];
-  double tp[2][kRedGroups];
+  for (int sl = 0; sl < kVSlots; ++sl) {
+    const int64_t j = i0 + tid + kVThreads * sl;
+    const int64_t jc = j < d ? j : d - 1;
 #pragma unroll
-  for (int sl = 0; sl < 2; ++sl) {
-    const int64_t i = tid + 256 * sl;
-#pragma unroll
-    for (int gg = 0; gg < kRedGroups; ++gg)
-      tp[sl][gg] = i < ilim ? part2[(int64_t)gg * d + i] : 0.0;
+    for (int r = 0; r < kVRows; ++r) {
+      const int64_t row = (i0 + r) <= jc ? i0 + r : jc;
+      rr[sl][r] = Rinv[row * d + jc];
+    }
   }
-  // beta from the kPassBlocks partial squares (same fixed order in every block)
-  double s = 0.0;
-#pragma unroll
-  for (int q = 0; q < kPassBlocks / 256; ++q) s += pb[q];
+  if (tid >= kPassBlocks) s = 0.0;
+  // beta from the kPassBlocks partial squares (same order in every workgroup)
   s = wave_sum(s);
   if ((tid & 63) == 0) bred[tid >> 6] = s;
+  double ts = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPassBlocks / kVGroups; ++q) ts += pt[q];
+  red[g][c] = i < d ? ts : 0.0;
   __syncthreads();
-  const double beta = sqrt(((bred[0] + bred[1]) + bred[2]) + bred[3]);
+  double b2 = bred[0];
+#pragma unroll
+  for (int w = 1; w < kVThreads / 64; ++w) b2 += bred[w];
+  const double beta = sqrt(b2);
   const double binv = beta > 0.0 ? 1.0 / beta : 0.0;
-#pragma unroll
-  for (int sl = 0; sl < 2; ++sl) {
-    const int64_t i = tid + 256 * sl;
-    if (i < ilim) {
-      double t = 0.0;
-#pragma unroll
-      for (int gg = 0; gg < kRedGroups; ++gg) t += tp[sl][gg];
-      tvs[i] = t * binv;
-    }
-  }
-  for (int64_t i = tid + 512; i < ilim; i += 256) {
+  if (tid < kVRows) {
     double t = 0.0;
 #pragma unroll
-    for (int gg = 0; gg < kRedGroups; ++gg) t += part2[(int64_t)gg * d + i];
-    tvs[i] = t * binv;
+    for (int q = 0; q < kVGroups; ++q) t += red[q][tid];
+    tv[tid] = t * binv;
   }
   __syncthreads();
-  red[g][c] = phased_dot(rv, tvs, g, K);
-  __syncthreads();
-  if (tid < kColsPerBlk) {
-    double sj = 0.0;
 #pragma unroll
-    for (int q = 0; q < kPhases; ++q) sj += red[q][tid];
-    const int64_t jj = j0 + tid;
-    double val = 0.0;
-    if (jj < d) {
-      val = init ? sj : sj - beta * v[jj];
-      vnew[jj] = val;
+  for (int sl = 0; sl < kVSlots; ++sl) {
+    const int64_t j = i0 + tid + kVThreads * sl;
+    if (j < d) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < kVRows; ++r)
+        if (i0 + r <= j) acc += rr[sl][r] * tv[r];
+      vpart[(int64_t)blockIdx.x * d + j] = acc;
     }
-    double a2s = val * val;
-#pragma unroll
-    for (int off = 4; off > 0; off >>= 1) a2s += __shfl_xor(a2s, off, 64);
-    if (tid == 0) part_a2[blockIdx.x] = a2s;
   }
   if (blockIdx.x == 0 && tid == 0) st->beta_new = beta;
 }
@@ -639,28 +669,29 @@ __global__ __launch_bounds__(256) void k_resid(const T *__restrict__ vals,
 }
 
 // The second half of an iteration in one launch: every workgroup computes
-// alpha = ||vnew|| from the partial squares and rows of
-// vhat = R^{-1} (vnew / alpha), 8 rows per workgroup.  alpha is summed by
-// wavefront 0 in one fixed order (lane l adds partials l and l + 64, then
-// the butterfly, lane 0's total), so every workgroup gets the same bits.
-// The one extra workgroup (index nb) runs the scalar recurrences, the v, w,
-// y updates and the stopping test, which no other workgroup of this launch
+// v of the previous iteration is read from v_in and the new one written to
+// v_out (the two alternate), since every workgroup reads v while the extra
+// one writes it.
+// vnew_j = sum_{b <= j / kVRows} vpart[b][j] - beta v_j (partials in order),
+// alpha = ||vnew|| (one fixed order, so every workgroup has the same bits)
+// and rows of vhat = R^{-1} (vnew / alpha), 8 rows per workgroup.  The one
+// extra workgroup (index nb) runs the scalar recurrences, the v, w, y
+// updates and the stopping test, which no other workgroup of this launch
 // reads; a stop it signals turns the following launches into no-ops.
-__global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ Rinv,
-                                                     int64_t d,
-                                                     const double *__restrict__ vnew,
-                                                     const double *__restrict__ part_a2, int nb,
-                                                     LsqrState *__restrict__ st,
-                                                     double *__restrict__ v,
-                                                     double *__restrict__ w,
-                                                     double *__restrict__ y,
-                                                     double *__restrict__ vhat, double atol,
-                                                     double btol, int init) {
+template <int NBV>  // bound on the number of vnew partials (ceil(d / kVRows))
+__global__ __launch_bounds__(256) void k_update(const double *__restrict__ Rinv, int64_t d,
+                                                const double *__restrict__ vpart, int nb,
+                                                LsqrState *__restrict__ st,
+                                                const double *__restrict__ v_in,
+                                                double *__restrict__ v_out,
+                                                double *__restrict__ w, double *__restrict__ y,
+                                                double *__restrict__ vhat, double atol,
+                                                double btol, int init) {
   if (!init && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *vn = reinterpret_cast<double *>(smem_raw);  // vnew, d doubles
   __shared__ double red[kColsPerBlk][kPhases + 1];
-  __shared__ double alpha_s;
+  __shared__ double a2red[4];
   const int tid = threadIdx.x;
   const bool upd = (int)blockIdx.x == nb;
   const int c = tid >> 5;  // row within the block
@@ -668,25 +699,35 @@ __global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ 
   const int64_t i = (int64_t)blockIdx.x * kColsPerBlk + c;
   const int64_t jj0 = i + ((g - (i & 31)) & 31);  // first j >= i with j = g mod 32
   const int K = (!upd && i < d && jj0 < d) ? (int)ceil_div(d - jj0, kPhases) : 0;
-  // loads first: this thread's R^{-1} entries, vnew, the partial squares
+  // loads first: this thread's R^{-1} entries
   double rv[kMaxK];
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) rv[k] = k < K ? Rinv[i * d + jj0 + kPhases * k] : 0.0;
-  double pa = 0.0;
-  if (tid < 64) {
-    pa = tid < nb ? part_a2[tid] : 0.0;
-    if (tid + 64 < nb) pa += part_a2[tid + 64];
+  const double beta = st->beta_new;
+  double a2 = 0.0;
+  for (int64_t j = tid; j < d; j += 256) {
+    // the shares of workgroups b <= j / kVRows, loaded unconditionally
+    // (row index clamped) and summed in order
+    const int nbj = (int)(j / kVRows) + 1;
+    double pv[NBV];
+#pragma unroll
+    for (int b = 0; b < NBV; ++b)
+      pv[b] = vpart[(int64_t)(b < nbj ? b : nbj - 1) * d + j];
+    const double vj = init ? 0.0 : v_in[j];
+    double sv = 0.0;
+#pragma unroll
+    for (int b = 0; b < NBV; ++b)
+      if (b < nbj) sv += pv[b];
+    const double val = init ? sv : sv - beta * vj;
+    vn[j] = val;
+    a2 += val * val;
   }
-  if (!upd)
-    for (int64_t q = tid; q < d; q += 256) vn[q] = vnew[q];
-  if (tid < 64) {
-    pa = wave_sum(pa);
-    if (tid == 0) alpha_s = sqrt(pa);
-  }
+  a2 = wave_sum(a2);
+  if ((tid & 63) == 0) a2red[tid >> 6] = a2;
   __syncthreads();
-  const double alpha = alpha_s;
+  const double alpha = sqrt(((a2red[0] + a2red[1]) + a2red[2]) + a2red[3]);
   if (upd) {
-    lsqr_update(st, d, v, vnew, w, y, alpha, atol, btol, init);
+    lsqr_update(st, d, v_out, vn, w, y, alpha, atol, btol, init);
     return;
   }
   const double ainv = alpha > 0.0 ? 1.0 / alpha : 0.0;
@@ -702,7 +743,7 @@ __global__ __launch_bounds__(256) void k_trmv_update(const double *__restrict__ 
 }
 
 struct LsqBufs {
-  double *u, *part_t, *part2, *part_b2, *vnew, *part_a2, *v, *w, *y, *vhat;
+  double *u, *part_t, *part_b2, *vpart, *v[2], *w, *y, *vhat;
   LsqrState *st;
 };
 
@@ -726,14 +767,14 @@ template <typename T>
 void launch_pass(const psk_mat &A, bool init, const LsqBufs &B, const double *rhs,
                  hipStream_t s) {
   if (A.format == PSK_CSR) {
-    const size_t lds = (size_t)5 * A.d * sizeof(double);
+    const size_t lds = (size_t)(kCsrWaves + 1) * A.d * sizeof(double);
     const T *vals = (const T *)A.values;
     if (init)
-      k_pass_csr<T, true><<<kPassBlocks, 256, lds, s>>>(vals, A.indptr, A.indices, A.n, A.d,
+      k_pass_csr<T, true><<<kPassBlocks, 64 * kCsrWaves, lds, s>>>(vals, A.indptr, A.indices, A.n, A.d,
                                                         B.vhat, rhs, B.u, B.st, B.part_t,
                                                         B.part_b2);
     else
-      k_pass_csr<T, false><<<kPassBlocks, 256, lds, s>>>(vals, A.indptr, A.indices, A.n, A.d,
+      k_pass_csr<T, false><<<kPassBlocks, 64 * kCsrWaves, lds, s>>>(vals, A.indptr, A.indices, A.n, A.d,
                                                          B.vhat, rhs, B.u, B.st, B.part_t,
                                                          B.part_b2);
   } else {
@@ -744,7 +785,8 @@ void launch_pass(const psk_mat &A, bool init, const LsqBufs &B, const double *rh
   }
 }
 
-void one_step(const psk_mat &A, bool init, const LsqBufs &B, const double *Rinv,
+// step k of a solve reads v[k & 1] and writes v[(k + 1) & 1]
+void one_step(const psk_mat &A, bool init, int k, const LsqBufs &B, const double *Rinv,
               const double *rhs, const psk_lsq_opts &o, hipStream_t s) {
   const int64_t d = A.d;
   const unsigned nb16 = (unsigned)ceil_div(d, kColsPerBlk);
@@ -755,13 +797,18 @@ void one_step(const psk_mat &A, bool init, const LsqBufs &B, const double *Rinv,
     else
       launch_pass<float>(A, init, B, rhs, s);
   }
-  k_reduce1<<<dim3((unsigned)ceil_div(d, 64), kRedGroups), 256, 0, s>>>(B.part_t, d, B.st,
-                                                                         B.part2, init ? 1 : 0);
-  k_vnew<<<nb16, 256, (size_t)d * sizeof(double), s>>>(B.part2, B.part_b2, Rinv, d, B.v, B.st,
-                                                       B.vnew, B.part_a2, init ? 1 : 0);
-  k_trmv_update<<<nb16 + 1, 256, (size_t)d * sizeof(double), s>>>(Rinv, d, B.vnew, B.part_a2,
-                                                                (int)nb16, B.st, B.v, B.w,
-                                     B.y, B.vhat, o.atol, o.btol, init ? 1 : 0);
+  const unsigned nbv = (unsigned)ceil_div(d, kVRows);
+  k_vnew_rows<<<nbv, kVThreads, 0, s>>>(B.part_t, B.part_b2, Rinv, d, B.st, B.vpart,
+                                        init ? 1 : 0);
+  const size_t lds = (size_t)d * sizeof(double);
+  if (nbv <= 512 / kVRows)
+    k_update<512 / kVRows><<<nb16 + 1, 256, lds, s>>>(
+        Rinv, d, B.vpart, (int)nb16, B.st, B.v[k & 1], B.v[(k + 1) & 1], B.w, B.y, B.vhat,
+        o.atol, o.btol, init ? 1 : 0);
+  else
+    k_update<1024 / kVRows><<<nb16 + 1, 256, lds, s>>>(
+        Rinv, d, B.vpart, (int)nb16, B.st, B.v[k & 1], B.v[(k + 1) & 1], B.w, B.y, B.vhat,
+        o.atol, o.btol, init ? 1 : 0);
 }
 
 }  // namespace
@@ -777,11 +824,10 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   LsqBufs B;
   B.u = ws.take<double>((size_t)n);
   B.part_t = ws.take<double>((size_t)kPassBlocks * d);
-  B.part2 = ws.take<double>((size_t)kRedGroups * d);
   B.part_b2 = ws.take<double>(kPassBlocks);
-  B.vnew = ws.take<double>((size_t)d);
-  B.part_a2 = ws.take<double>((size_t)ceil_div(d, kColsPerBlk));
-  B.v = ws.take<double>((size_t)d);
+  B.vpart = ws.take<double>((size_t)ceil_div(d, kVRows) * d);
+  B.v[0] = ws.take<double>((size_t)d);
+  B.v[1] = ws.take<double>((size_t)d);
   B.w = ws.take<double>((size_t)d);
   B.y = ws.take<double>((size_t)d);
   B.vhat = ws.take<double>((size_t)d);
@@ -865,6 +911,9 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
 
   const unsigned db = (unsigned)ceil_div(d, 256);
   const unsigned nb16 = (unsigned)ceil_div(d, kColsPerBlk);
+  SlotGuard slot;
+  if ((rc = take_slot(&slot.sl))) return rc;
+  slot.held = true;
   k_zero<<<db, 256, 0, st>>>(x, d);
   int total_iters = 0;
   bool converged = true;
@@ -892,21 +941,38 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
       rhs = res;
     }
     k_state_reset<<<1, 64, 0, st>>>(B.st);
-    k_zero<<<db, 256, 0, st>>>(B.v, d);
-    one_step(A, true, B, Rinv, rhs, o, st);
-    int it = 0;
+    k_zero<<<db, 256, 0, st>>>(B.v[0], d);
+    one_step(A, true, 0, B, Rinv, rhs, o, st);
+    int kstep = 1;
+    // groups of check_every iterations; after each, the state is copied to
+    // pinned memory and the host reads the previous group's copy while this
+    // one runs.  A group enqueued after convergence costs only no-op
+    // launches (the device-side done flag).
+    int it = 0, ngroup = 0, inflight = -1;
     bool done = false;
     while (it < o.max_iter) {
       int batch = o.check_every;
       if (batch > o.max_iter - it) batch = o.max_iter - it;
-      for (int q = 0; q < batch; ++q) one_step(A, false, B, Rinv, rhs, o, st);
+      for (int q = 0; q < batch; ++q) one_step(A, false, kstep++, B, Rinv, rhs, o, st);
       it += batch;
-      PSK_HIP_TRY(hipMemcpyAsync(&hs, B.st, sizeof(hs), hipMemcpyDeviceToHost, st));
-      PSK_HIP_TRY(hipStreamSynchronize(st));
-      if (hs.done) {
-        done = true;
-        break;
+      const int cur = ngroup++ & 1;
+      PSK_HIP_TRY(hipMemcpyAsync(&slot.sl.h[cur], B.st, sizeof(LsqrState),
+                                 hipMemcpyDeviceToHost, st));
+      PSK_HIP_TRY(hipEventRecord(slot.sl.ev[cur], st));
+      if (inflight >= 0) {
+        PSK_HIP_TRY(hipEventSynchronize(slot.sl.ev[inflight]));
+        if (slot.sl.h[inflight].done) {
+          hs = slot.sl.h[inflight];
+          done = true;
+          break;
+        }
       }
+      inflight = cur;
+    }
+    if (!done && inflight >= 0) {
+      PSK_HIP_TRY(hipEventSynchronize(slot.sl.ev[inflight]));
+      hs = slot.sl.h[inflight];
+      done = hs.done != 0;
     }
     if (!done) converged = false;
     total_iters += hs.iters;
