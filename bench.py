@@ -52,8 +52,8 @@ PEAK_FP8_TFLOPS = 5000.0
 PMC_TRAFFIC = {
     ("csr-1e6x500", "bf16"): {
         "source": "paper_2203_02798_amd/csrc/k_gauss_gemm_bf16.hip",
-        "sha256_prefix": "090bc4cedb4a449b",
-        "fetch_kib": 250149.2, "write_kib": 125122.6,
+        "sha256_prefix": "04bb607fce6e8e8f",
+        "fetch_kib": 250140.9, "write_kib": 125141.9,
         "fetch_scale": 2.000, "write_scale": 1.000,
         "profile": "profiles/gauss_gemm_bf16_csr-1e6x500_pmc.md",
     },
