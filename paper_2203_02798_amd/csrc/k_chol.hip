@@ -108,19 +108,24 @@ constexpr int kVb = 16 * 17;  // one 16 x 16 block inverse in LDS (row stride 17
 // Wavefront 0: Cholesky of the 16 x 16 block at (o, o) of the LDS tile T
 // (its upper triangle is read), right-looking with lane l % 16 holding
 // column l % 16: step k takes the pivot from lane k, scales row k, publishes
-// it through LDS and applies the rank-1 update to its column.  U overwrites
-// the block's upper triangle, 1/U_ii goes to rinv[o + i] and the block's
-// inverse V = U^{-1} (lane l solving U x = e_l from the last row up) to Vb.
-// Lanes 16..63 repeat lanes 0..15 and store nothing.  Returns true when a
-// pivot was not positive (it is then replaced by 1).
+// it through LDS and applies the rank-1 update to its column.  The same row
+// operations (scale row k by 1/U_kk, subtract U_ki times row k from row i)
+// applied to the identity leave L^{-1} = U^{-T} in z, lane l holding its
+// column l, i.e. row l of V = U^{-1}.  U overwrites the block's upper
+// triangle and V goes to Vb (row-major, stride 17).  Lanes 16..63 repeat
+// lanes 0..15 and store nothing.  Returns true when a pivot was not
+// positive (it is then replaced by 1).
 __device__ __forceinline__ bool factor16(double *__restrict__ T, int o,
                                          double *__restrict__ rowbuf,
-                                         double *__restrict__ rinv, double *__restrict__ Vb) {
+                                         double *__restrict__ Vb) {
   const int l = threadIdx.x & 15;
   const bool st = threadIdx.x < 16;
-  double c[16];
+  double c[16], z[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) c[i] = T[(o + i) * kLd + o + l];
+  for (int i = 0; i < 16; ++i) {
+    c[i] = T[(o + i) * kLd + o + l];
+    z[i] = (i == l) ? 1.0 : 0.0;
+  }
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
@@ -129,31 +134,26 @@ __device__ __forceinline__ bool factor16(double *__restrict__ T, int o,
     piv = piv > 0.0 ? piv : 1.0;
     const double rs = rsqrt_acc(piv);
     const double u = (l >= k) ? c[k] * rs : 0.0;
+    z[k] *= rs;
     double *rb = rowbuf + (k & 1) * 16;
     if (st) {
       rb[l] = u;
       if (l >= k) T[(o + k) * kLd + o + l] = u;
-      if (l == k) rinv[o + k] = rs;
     }
     wave_sync_lds();
+    double rbv[16];
 #pragma unroll
-    for (int i = k + 1; i < 16; ++i) c[i] -= rb[i] * u;
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  double bv[16];
+    for (int i = k + 1; i < 16; ++i) rbv[i] = rb[i];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) bv[i] = (i == l) ? 1.0 : 0.0;
-#pragma unroll
-  for (int i = 15; i >= 0; --i) {
-    const double xi = bv[i] * rinv[o + i];
-    bv[i] = xi;
-#pragma unroll
-    for (int m = 0; m < i; ++m) bv[m] -= T[(o + m) * kLd + o + i] * xi;
+    for (int i = k + 1; i < 16; ++i) {
+      c[i] -= rbv[i] * u;
+      z[i] -= rbv[i] * z[k];
+    }
     __builtin_amdgcn_sched_barrier(0);
   }
   if (st) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) Vb[i * 17 + l] = bv[i];
+    for (int i = 0; i < 16; ++i) Vb[l * 17 + i] = z[i];
   }
   return bad;
 }
@@ -161,12 +161,43 @@ __device__ __forceinline__ bool factor16(double *__restrict__ T, int o,
 // All 256 threads.  T = S.PI: the 64 x 64 tile (row-major, stride kLd), of
 // which the leading nb x nb block is used (the rest is taken as identity).
 // Blocked right-looking Cholesky over four 16-column blocks: block kb is
-// factored by wavefront 0 (factor16), then the panel right of it is solved
-// (U[kb, J] = V_kb^T T[kb, J]) and the trailing block updated
-// (T[I, J] -= U[kb, I]^T U[kb, J]) by the whole workgroup.  The inverse
-// X = U^{-1} is built block column by block column:
-// X[I, J] = -(sum_{K = I..J-1} X[I, K] U[K, J]) V_J.  Writes the nb x nb
-// blocks of R (= U, zero below the diagonal) and X at (j0, j0).
+// factored by wavefront 0 (factor16, which also gives the block's inverse),
+// then the panel right of it is solved (U[kb, J] = V_kb^T T[kb, J]) and the
+// trailing block updated (T[I, J] -= U[kb, I]^T U[kb, J]) by the whole
+// workgroup, each thread owning a small register tile of outputs with its
+// operands loaded ahead.  The inverse X = U^{-1} is built block column by
+// block column: X[I, J] = -(sum_{K = I..J-1} X[I, K] U[K, J]) V_J.  Writes
+// the nb x nb blocks of R (= U, zero below the diagonal) and X at (j0, j0).
+template <int TR>
+__device__ __forceinline__ void trailing_update(double *__restrict__ T, int o) {
+  // rows / columns o + 16 + t + 16 a (a < TR) of thread (ti, tj)
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  const int b0 = o + 16;
+  double acc[TR][TR];
+#pragma unroll
+  for (int a = 0; a < TR; ++a)
+#pragma unroll
+    for (int b = 0; b < TR; ++b) acc[a][b] = 0.0;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const double *row = T + (o + m) * kLd;
+    double ri[TR], cj[TR];
+#pragma unroll
+    for (int a = 0; a < TR; ++a) {
+      ri[a] = row[b0 + ti + 16 * a];
+      cj[a] = row[b0 + tj + 16 * a];
+    }
+#pragma unroll
+    for (int a = 0; a < TR; ++a)
+#pragma unroll
+      for (int b = 0; b < TR; ++b) acc[a][b] = fma(ri[a], cj[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < TR; ++a)
+#pragma unroll
+    for (int b = 0; b < TR; ++b) T[(b0 + ti + 16 * a) * kLd + b0 + tj + 16 * b] -= acc[a][b];
+}
+
 __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int64_t j0,
                                             double *__restrict__ R, double *__restrict__ X,
                                             int *__restrict__ flag) {
@@ -184,7 +215,7 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
 #pragma unroll 1
   for (int kb = 0; kb < 4; ++kb) {
     const int o = 16 * kb;
-    if (tid < 64) bad |= factor16(T, o, S.rowbuf[0], S.rinv, V + kb * kVb);
+    if (tid < 64) bad |= factor16(T, o, S.rowbuf[0], V + kb * kVb);
     __syncthreads();
     const int rest = 48 - o;  // columns right of the block
     if (rest == 0) break;
@@ -192,17 +223,24 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
       // panel rows o..o+15, columns o+16..63: U[o+r][j] = sum_{m<=r} V[m][r] T[o+m][j]
       const double *Vk = V + kb * kVb;
       const int r = tid & 15, jg = tid >> 4;
+      double vc[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) vc[m] = (m <= r) ? Vk[m * 17 + r] : 0.0;
       double pv[3];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         const int j = o + 16 + jg + 16 * q;
-        double acc = 0.0;
-        if (j < 64) {
+        const int jc = j < 64 ? j : 63;
+        double tc[16];
 #pragma unroll
-          for (int m = 0; m < 16; ++m)
-            if (m <= r) acc += Vk[m * 17 + r] * T[(o + m) * kLd + j];
+        for (int m = 0; m < 16; ++m) tc[m] = T[(o + m) * kLd + jc];
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int m = 0; m < 16; m += 2) {
+          a0 = fma(vc[m], tc[m], a0);
+          a1 = fma(vc[m + 1], tc[m + 1], a1);
         }
-        pv[q] = acc;
+        pv[q] = a0 + a1;
       }
       __syncthreads();
 #pragma unroll
@@ -213,13 +251,9 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
       __syncthreads();
     }
     // trailing block rows / columns o+16..63
-    for (int e = tid; e < rest * rest; e += kTh) {
-      const int i = o + 16 + e / rest, j = o + 16 + e % rest;
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m < 16; ++m) acc += T[(o + m) * kLd + i] * T[(o + m) * kLd + j];
-      T[i * kLd + j] -= acc;
-    }
+    if (rest == 48) trailing_update<3>(T, o);
+    else if (rest == 32) trailing_update<2>(T, o);
+    else trailing_update<1>(T, o);
     __syncthreads();
   }
   // X: diagonal blocks from the block inverses, zero below them
@@ -230,31 +264,54 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
                                  : 0.0;
   }
   __syncthreads();
+  {
+    const int r = tid >> 4, c = tid & 15;
 #pragma unroll 1
-  for (int J = 1; J < 4; ++J) {
-    // P[I] = sum_{K=I}^{J-1} X[I, K] U[K, J] for I < J (J * 256 entries)
-    for (int e = tid; e < J * 256; e += kTh) {
-      const int I = e >> 8, r = (e >> 4) & 15, c = e & 15;
-      double acc = 0.0;
-      for (int K = I; K < J; ++K) {
+    for (int J = 1; J < 4; ++J) {
+      // P[I] = sum_{K=I}^{J-1} X[I, K] U[K, J] for every I < J at once:
+      // thread (r, c) keeps one accumulator per I
+      double acc[3] = {0.0, 0.0, 0.0};
+      for (int K = 0; K < J; ++K) {
+        double tcol[16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m)
-          acc += XT[(16 * I + r) * kLd + 16 * K + m] * T[(16 * K + m) * kLd + 16 * J + c];
+        for (int m = 0; m < 16; ++m) tcol[m] = T[(16 * K + m) * kLd + 16 * J + c];
+#pragma unroll
+        for (int I = 0; I < 3; ++I) {
+          if (I <= K) {
+            double xr[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) xr[m] = XT[(16 * I + r) * kLd + 16 * K + m];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) acc[I] = fma(xr[m], tcol[m], acc[I]);
+          }
+        }
       }
-      P[I * kVb + r * 17 + c] = acc;
-    }
-    __syncthreads();
-    // X[I, J] = -P[I] V_J (V_J upper triangular)
-    const double *VJ = V + J * kVb;
-    for (int e = tid; e < J * 256; e += kTh) {
-      const int I = e >> 8, r = (e >> 4) & 15, c = e & 15;
-      double acc = 0.0;
 #pragma unroll
-      for (int m = 0; m < 16; ++m)
-        if (m <= c) acc += P[I * kVb + r * 17 + m] * VJ[m * 17 + c];
-      XT[(16 * I + r) * kLd + 16 * J + c] = -acc;
+      for (int I = 0; I < 3; ++I)
+        if (I < J) P[I * kVb + r * 17 + c] = acc[I];
+      __syncthreads();
+      // X[I, J] = -P[I] V_J (V_J upper triangular)
+      const double *VJ = V + J * kVb;
+      double vcol[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) vcol[m] = (m <= c) ? VJ[m * 17 + c] : 0.0;
+#pragma unroll
+      for (int I = 0; I < 3; ++I) {
+        if (I < J) {
+          double pr[16];
+#pragma unroll
+          for (int m = 0; m < 16; ++m) pr[m] = P[I * kVb + r * 17 + m];
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+          for (int m = 0; m < 16; m += 2) {
+            a0 = fma(pr[m], vcol[m], a0);
+            a1 = fma(pr[m + 1], vcol[m + 1], a1);
+          }
+          XT[(16 * I + r) * kLd + 16 * J + c] = -(a0 + a1);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   for (int e = tid; e < 64 * 64; e += kTh) {
     const int i = e >> 6, j = e & 63;
