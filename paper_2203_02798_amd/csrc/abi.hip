@@ -115,6 +115,13 @@ int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws
 int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec,
                   void *C, Arena &ws, hipStream_t st) {
   if (m == 0) return do_sketch_cs(A, r, seed, C, ws, st);
+  if (gauss_sparse_pick(A, r, m, prec)) {
+    // S*A is sparse: the product over its nonzeros
+    uint32_t *perm = nullptr, *bptr = nullptr;
+    int rc = cs_bin(A.n, (uint32_t)r, seed, ws, st, &perm, &bptr);
+    if (rc) return rc;
+    return gauss_gemm_sparse(m, r, A, perm, bptr, seed, prec, (double *)C, ws, st);
+  }
   const bool fb = prec == PSK_PREC_BF16 && bf16_csr_fusable(A, r);
   const bool f8 = prec == PSK_PREC_FP8 && fp8_csr_fusable(A, r);
   if (fb || f8) {

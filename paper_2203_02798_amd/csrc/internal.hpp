@@ -78,6 +78,10 @@ int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
 // Wavefronts per bucket cs_apply uses for n rows in r buckets (1 = one
 // wavefront sums a whole bucket).
 int cs_splits(int64_t n, int64_t r);
+// In-place exclusive scan of L uint32 values (k_sketch.hip); sums: scratch of
+// scan_plan.
+int scan_plan(int64_t L, Arena &ws, uint32_t **sums);
+void scan_run(uint32_t *data, int64_t L, uint32_t *sums, hipStream_t st);
 
 // Argument checks shared by the entry points (abi.hip): 0 or a status.
 int check_mat(const psk_mat *A);
@@ -113,6 +117,17 @@ bool fp8_csr_fusable(const psk_mat &A, int64_t r);
 int gauss_gemm_fp8_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
                        const uint32_t *bptr, uint64_t seed, double *C, Arena &ws,
                        hipStream_t st);
+
+// The Gaussian product of CSR A over the nonzeros of S*A (k_gauss_sparse.hip),
+// from the binned rows, in any of the three precisions; gauss_sparse_ok tells
+// when it applies (S*A at most 1/32 dense, d <= 1023), gauss_sparse_pick when
+// it is the kernel to use (FP8 keeps the fused dense FP8 GEMM unless S*A is
+// below 1/1024 dense: its contraction costs less than the sparse FP64 updates).
+bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m);
+bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec);
+int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
+                      const uint32_t *bptr, uint64_t seed, int prec, double *C, Arena &ws,
+                      hipStream_t st);
 
 // ---- FP64 dense kernels (k_dense.hip) --------------------------------------
 // C (d x d, out_dtype) = alpha * A^T A + beta * C for dense A.

@@ -1,0 +1,608 @@
+// C = G * (S*A) for CSR A over the nonzeros of S*A only.
+//
+// Paper mapping (arXiv 2203.02798): Algorithm countgauss_multiply's product
+// C = G (S A), evaluated as C = sum_b G[:, b] (S A)[b, :], the sum running
+// over the nonzero entries of S*A (the (G S) A form of the sparse sketches).
+// A CountSketch of a sparse matrix has few nonzeros per bucket row (about
+// nnz(A) / r), so this costs 2 m nnz(S A) flops instead of the dense
+// product's 2 m r d, besides drawing the m x r Gaussian once.  The result is
+// the same product in the same precision as the dense kernels:
+//   FP64  G and S*A in FP64;
+//   BF16  G rounded to bfloat16, S*A as its two bfloat16 limbs hi + lo;
+//   FP8   both in OCP e4m3 with one E8M0 scale per 128-bucket block (per row
+//         of G, per column of S*A).
+// Products of the rounded operands are exact in FP64 and are accumulated in
+// FP64 (the dense reduced-precision kernels accumulate in FP32).
+//
+// Steps (all on the binned rows of cs_bin):
+//   k_row_nnz + scan   offsets: bucket b's entries occupy slots
+//                      eoff[bptr[b]] .. eoff[bptr[b+1]] (its rows' lengths);
+//   k_sa_entries       a workgroup of 8 wavefronts sums 8 buckets' rows into
+//                      LDS rows (the CountSketch scatter's order, so the
+//                      same bits as S*A) and writes each bucket's nonzeros
+//                      (bucket, column, value) into its slots, the unused
+//                      slots as holes (column -1);
+//   k_entries_fp8      (FP8) the per-column, per-128-bucket scale and the
+//                      e4m3 rounding of the values;
+//   k_gauss_sparse     workgroup (32-row tile of C, a range of 128-bucket
+//                      blocks): per block it draws G for its rows
+//                      into LDS, then every entry (b, j, s) adds G[a, b] s to
+//                      C[a, j] of the tile held in LDS, entries in slot
+//                      order; the tile goes out as one K-split partial;
+//   k_sparse_reduce    C = (1/sqrt m) sum of the partials in split order.
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace psk {
+namespace {
+
+constexpr int kBlk = 128;  // buckets per FP8 scale block
+constexpr int kSw = 8;     // wavefronts (buckets) per k_sa_entries workgroup
+
+// rn[j] = number of entries of the row at bin position j; rn[n] = 0
+__global__ __launch_bounds__(256) void k_row_nnz(const int64_t *__restrict__ indptr,
+                                                 const uint32_t *__restrict__ perm, int64_t n,
+                                                 uint32_t *__restrict__ rn) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j > n) return;
+  uint32_t v = 0;
+  if (j < n) {
+    const int64_t row = (int64_t)(perm[j] & 0x7fffffffu);
+    v = (uint32_t)(indptr[row + 1] - indptr[row]);
+  }
+  rn[j] = v;
+}
+
+// be[k] = first entry slot of bucket block k of blk buckets (be[nblk] = total)
+__global__ __launch_bounds__(256) void k_block_entries(const uint32_t *__restrict__ bptr,
+                                                       const uint32_t *__restrict__ eoff,
+                                                       int64_t r, int64_t blk, int64_t nblk,
+                                                       uint32_t *__restrict__ be) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k > nblk) return;
+  const int64_t b = k * blk < r ? k * blk : r;
+  be[k] = eoff[bptr[b]];
+}
+
+// bfloat16 (RNE) of a double in one rounding (round-to-odd to FP32 first)
+__device__ __forceinline__ double bf16_round(double v) {
+  if (v != v) return v;
+  float f = (float)v;
+  if ((double)f != v) {
+    uint32_t b = __float_as_uint(f);
+    if (fabs((double)f) > fabs(v)) b -= 1;
+    b |= 1u;
+    f = __uint_as_float(b);
+  }
+  return (double)(float)(__bf16)f;
+}
+
+// exponent e of the E8M0 block scale: smallest integer with 448 * 2^e >= amax
+// (amax = f 2^x, f in [1/2, 1); 448 = 0.875 2^9), 0 for amax == 0, clamped
+__device__ __forceinline__ int e8m0_exp(double amax) {
+  int x;
+  const double f = frexp(amax, &x);
+  int e = (f <= 0.875) ? x - 9 : x - 8;
+  if (!(amax > 0.0)) e = 0;
+  return e < -127 ? -127 : (e > 127 ? 127 : e);
+}
+
+// e4m3 (OCP, RNE) of v 2^-e, returned as its value times 2^e; v 2^-e goes
+// to FP32 by round-to-odd first, so the e4m3 rounding is a single one
+__device__ __forceinline__ double e4m3_round(double v, int e) {
+  const double x = ldexp(v, -e);
+  float f = (float)x;
+  if ((double)f != x && x == x) {
+    uint32_t b = __float_as_uint(f);
+    if (fabs((double)f) > fabs(x)) b -= 1;
+    b |= 1u;
+    f = __uint_as_float(b);
+  }
+  const int byte = __builtin_amdgcn_cvt_pk_fp8_f32(f, 0.0f, 0, false) & 0xff;
+  return ldexp((double)__builtin_amdgcn_cvt_f32_fp8(byte, 0), e);
+}
+
+// e4m3_round of an FP32 value: v 2^-e is exact in FP32 (|v 2^-e| <= 448,
+// and the values of G lie far inside FP32's normal range), so one
+// hardware rounding gives the same byte
+__device__ __forceinline__ float e4m3_round_f32(float v, int e) {
+  const float x = ldexpf(v, -e);
+  const int byte = __builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xff;
+  return ldexpf(__builtin_amdgcn_cvt_f32_fp8(byte, 0), e);
+}
+
+// S*A entries of buckets 8 blockIdx.x .. +7 (wavefront w: bucket 8 blk + w).
+// BF16: the value written is hi + lo (the two limbs); otherwise S*A itself.
+template <typename T, bool LIMBS>
+__global__ __launch_bounds__(64 * kSw) void k_sa_entries(
+    const T *__restrict__ vals, const int64_t *__restrict__ indptr,
+    const int32_t *__restrict__ indices, int64_t d, int64_t dpad, int64_t r,
+    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
+    const uint32_t *__restrict__ eoff, uint32_t *__restrict__ eb,
+    int32_t *__restrict__ ec, double *__restrict__ ev) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * kSw + wave;
+  if (b >= r) return;
+  T *acc = reinterpret_cast<T *>(smem_raw) + (int64_t)wave * dpad;
+  for (int64_t c = lane; c < dpad; c += 64) acc[c] = T(0);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t j0 = bptr[b], j1 = bptr[b + 1];
+  if (j0 == j1) return;
+  bucket_rows_add(vals, indptr, indices, perm, j0, j1, acc);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t e0 = eoff[j0], cap = eoff[j1] - e0;
+  uint32_t cnt = 0;
+  for (int64_t c0 = 0; c0 < d; c0 += 64) {
+    const int64_t c = c0 + lane;
+    const double v = c < d ? (double)acc[c] : 0.0;
+    const bool nz = v != 0.0;
+    const uint64_t mask = __ballot(nz);
+    if (nz) {
+      const uint32_t pos =
+          e0 + cnt + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+      double w = v;
+      if (LIMBS) {
+        const double hi = bf16_round(v);
+        w = hi + bf16_round(v - hi);  // exact: 16 significant bits at most
+      }
+      eb[pos] = (uint32_t)b;
+      ec[pos] = (int32_t)c;
+      ev[pos] = w;
+    }
+    cnt += (uint32_t)__popcll(mask);
+  }
+  for (uint32_t p = cnt + lane; p < cap; p += 64) {
+    eb[e0 + p] = (uint32_t)b;
+    ec[e0 + p] = -1;
+    ev[e0 + p] = 0.0;
+  }
+}
+
+// FP8: entry values of 128-bucket block blockIdx.x rounded to e4m3 with the
+// scale of their column in that block (amax over the block's entries of the
+// column, taken exactly with integer max on the bit patterns).
+__global__ __launch_bounds__(256) void k_entries_fp8(const uint32_t *__restrict__ bptr,
+                                                     const uint32_t *__restrict__ eoff,
+                                                     int64_t r, int64_t d,
+                                                     const int32_t *__restrict__ ec,
+                                                     double *__restrict__ ev) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned long long *amax = reinterpret_cast<unsigned long long *>(smem_raw);  // d
+  const int64_t b0 = (int64_t)blockIdx.x * kBlk;
+  const int64_t b1 = b0 + kBlk < r ? b0 + kBlk : r;
+  const uint32_t e0 = eoff[bptr[b0]], e1 = eoff[bptr[b1]];
+  for (int64_t c = threadIdx.x; c < d; c += 256) amax[c] = 0ull;
+  __syncthreads();
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int32_t c = ec[e];
+    if (c >= 0)
+      atomicMax(&amax[c], (unsigned long long)__double_as_longlong(fabs(ev[e])));
+  }
+  __syncthreads();
+  for (uint32_t e = e0 + threadIdx.x; e < e1; e += 256) {
+    const int32_t c = ec[e];
+    if (c >= 0) {
+      const int ex = e8m0_exp(__longlong_as_double((long long)amax[c]));
+      ev[e] = e4m3_round(ev[e], ex);
+    }
+  }
+}
+
+// Packed sorted entry: column (bits 0-9), bucket offset in its G block
+// (10-18), entries of the column left in the block counting this one
+// (19-28), first entry of the column in the block (29); kHole for none.
+constexpr uint32_t kHole = 0xffffffffu;
+constexpr int kCscCols = 1024;  // columns of S*A the block sort takes at most
+
+// Entries of G block blockIdx.x (32 W buckets, slots be[k] .. be[k+1]) in
+// (column, bucket) order: the valid ones first, packed, then the holes.
+// Each bucket holds a column at most once, so an entry's place among its
+// column's entries is the number of the column's buckets before its own:
+// a bitmap of buckets per column, its popcounts and a scan over the
+// columns give every entry its slot, with no dependence on timing.
+template <int W>
+__global__ __launch_bounds__(512) void k_block_csc(const uint32_t *__restrict__ be,
+                                                   const uint32_t *__restrict__ eb,
+                                                   const int32_t *__restrict__ ec,
+                                                   const double *__restrict__ ev, int64_t d,
+                                                   uint32_t *__restrict__ sp,
+                                                   double *__restrict__ sv) {
+  __shared__ uint32_t bits[kCscCols * W];   // [column][word]: buckets present
+  __shared__ uint16_t wpre[kCscCols * W];   // buckets present in the words before
+  __shared__ uint32_t ccnt[kCscCols];       // entries per column
+  __shared__ uint32_t cst[kCscCols];        // exclusive scan of ccnt
+  const int tid = threadIdx.x;
+  const int64_t k = blockIdx.x;
+  const uint32_t lo = be[k], hi = be[k + 1];
+  const uint32_t b0 = (uint32_t)(k * (32 * W));
+  for (int64_t i = tid; i < d * W; i += 512) bits[i] = 0u;
+  __syncthreads();
+  for (uint32_t e = lo + tid; e < hi; e += 512) {
+    const int32_t c = ec[e];
+    if (c >= 0) {
+      const uint32_t bo = eb[e] - b0;
+      atomicOr(&bits[c * W + (bo >> 5)], 1u << (bo & 31));
+    }
+  }
+  __syncthreads();
+  for (int64_t c = tid; c < d; c += 512) {
+    uint32_t run = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      wpre[c * W + w] = (uint16_t)run;
+      run += (uint32_t)__popc(bits[c * W + w]);
+    }
+    ccnt[c] = run;
+  }
+  __syncthreads();
+  if (tid < 64) {  // one wavefront scans the column counts
+    const int64_t per = ceil_div(d, (int64_t)64);
+    const int64_t c0 = tid * per, c1 = c0 + per < d ? c0 + per : d;
+    uint32_t s = 0;
+    for (int64_t c = c0; c < c1; ++c) s += ccnt[c];
+    uint32_t x = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t y = __shfl_up(x, off, 64);
+      if (tid >= off) x += y;
+    }
+    uint32_t ex = x - s;
+    for (int64_t c = c0; c < c1; ++c) {
+      cst[c] = ex;
+      ex += ccnt[c];
+    }
+  }
+  __syncthreads();
+  for (uint32_t e = lo + tid; e < hi; e += 512) {
+    const int32_t c = ec[e];
+    if (c >= 0) {
+      const uint32_t bo = eb[e] - b0, w = bo >> 5;
+      const uint32_t rank =
+          wpre[c * W + w] + (uint32_t)__popc(bits[c * W + w] & ((1u << (bo & 31)) - 1u));
+      const uint32_t pos = lo + cst[c] + rank;
+      sp[pos] = (uint32_t)c | (bo << 10) | ((ccnt[c] - rank) << 19) | ((rank == 0u) << 29);
+      sv[pos] = ev[e];
+    }
+  }
+  const uint32_t nv = cst[d - 1] + ccnt[d - 1];
+  for (uint32_t p = lo + nv + tid; p < hi; p += 512) {
+    sp[p] = kHole;
+    sv[p] = 0.0;
+  }
+}
+
+// G precision of the sparse product
+enum { kG64 = 0, kGbf16 = 1, kGfp8 = 2 };
+
+constexpr int kSThreads = 1024;
+constexpr int kStage = 2 * kSThreads;  // entries of a block staged in LDS at once
+
+// Workgroup (row tile mt, K split ks), 1024 threads: rows a0 .. a0 + MT of
+// C (MT = 16 1024 / DP) and the G blocks of BLK buckets ks bper .. ks bper +
+// bper - 1 (BLK = 512 with G in FP32, four FP8 scale blocks; 256 with G in
+// FP64).  Thread (h, j) = (tid / DP, tid % DP) holds C[a0 + 16 h + i, j],
+// i < 16, in FP64 registers.  Per block: every thread draws its share of
+// the block of G into LDS (bucket-major, so one bucket's MT values are
+// contiguous); the block's entries, sorted by (column, bucket), are staged
+// in LDS with, per column, the range of its entries; thread (h, j) then
+// adds G[a, b] s for the entries (b, j, s) of its column in bucket order.
+// So each element of C is summed by one thread, over buckets in ascending
+// order, with no atomics.  Entries are fetched two blocks ahead, the block
+// bounds three; a block of more than kStage entries is staged in turns.
+template <int GP, int DP, int BLK>
+__global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
+    int64_t m, int64_t d, int64_t r, uint64_t seed, const uint32_t *__restrict__ be,
+    const uint32_t *__restrict__ sp, const double *__restrict__ sv, int tiles_m, int64_t bper,
+    double *__restrict__ part /* [splits][m][d] */) {
+  typedef typename std::conditional<GP == kG64, double, float>::type GT;
+  constexpr int RG = kSThreads / DP;                // row groups
+  constexpr int MT = 16 * RG;                       // tile rows
+  constexpr int GS = MT + 16 / (int)sizeof(GT);     // LDS stride of a bucket of G
+  constexpr int kQ = BLK / 4;                       // Philox blocks per row of G
+  constexpr int NIT = MT * kQ / kSThreads;          // G items per thread
+  static_assert(NIT >= 1 && MT * kQ % kSThreads == 0, "whole G items per thread");
+  static_assert(GP != kGfp8 || BLK == 4 * kBlk, "FP8 G blocks hold four scale blocks");
+  __shared__ __align__(16) GT Gb[BLK * GS];
+  __shared__ uint32_t stp[kStage];
+  __shared__ double stv[kStage];
+  __shared__ uint2 crng[DP];  // per column: tag, first staged slot | count << 16
+  const int tid = threadIdx.x;
+  const int mt = (int)(blockIdx.x % tiles_m);
+  const int64_t ks = blockIdx.x / tiles_m;
+  const int64_t a0 = (int64_t)mt * MT;
+  const int64_t nblk = ceil_div(r, BLK);
+  const int64_t k0 = ks * bper;
+  const int64_t k1 = k0 + bper < nblk ? k0 + bper : nblk;
+  const int j = tid % DP, h = tid / DP;
+  for (int i = tid; i < DP; i += kSThreads) crng[i] = make_uint2(kHole, 0u);
+  double acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+  uint32_t tag = 0;  // one per staged turn, never kHole
+  // G item u of this thread: row ga_u, Philox block q_u of the block.  FP8
+  // takes the amax of a row over a 128-bucket scale block, 32 Philox blocks:
+  // a wavefront holds 64 / LQ rows of one scale block, LQ lanes per row, NIT
+  // items per lane; otherwise consecutive lanes take consecutive rows.
+  constexpr int LQ = 32 / NIT;
+  auto item = [&](int u, int &a, int &q) {
+    if (GP == kGfp8) {
+      const int w = tid >> 6, lane = tid & 63;
+      a = (w >> 2) * (64 / LQ) + lane / LQ;
+      q = (w & 3) * 32 + lane % LQ + LQ * u;
+    } else {
+      const int it = tid + kSThreads * u;
+      a = it % MT;
+      q = it / MT;
+    }
+  };
+  // block bounds, loaded per lane (through vz, a zero the compiler cannot
+  // see) so that they join the entries in the in-order vector load counter
+  struct Bnd {
+    uint32_t lo, hi;
+  };
+  struct ESet {
+    uint32_t p[kStage / kSThreads];
+    double v[kStage / kSThreads];
+    uint32_t lo, hi;
+  };
+  int vz;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vz));
+  auto bounds = [&](int64_t k, Bnd &B) {
+    B.lo = be[(k < k1 ? k : k1) + vz];
+    B.hi = be[(k + 1 < k1 ? k + 1 : k1) + vz];
+  };
+  auto load = [&](uint32_t base, uint32_t hi, uint32_t *pp, double *vv) {
+#pragma unroll
+    for (int s2 = 0; s2 < kStage / kSThreads; ++s2) {
+      const uint32_t e = base + (uint32_t)(tid + kSThreads * s2);
+      const uint32_t ei = e < hi ? e : (hi ? hi - 1 : 0u);  // clamped; masked when staged
+      pp[s2] = sp[ei];
+      vv[s2] = sv[ei];
+    }
+  };
+  auto fetch = [&](const Bnd &B, ESet &R) {
+    load(B.lo, B.hi, R.p, R.v);
+    R.lo = B.lo;
+    R.hi = B.hi;
+  };
+  // stage one turn (nch entries) and its column ranges; barrier before and after
+  auto stage = [&](const uint32_t *pp, const double *vv, uint32_t nch) {
+#pragma unroll
+    for (int s2 = 0; s2 < kStage / kSThreads; ++s2) {
+      const int idx = tid + kSThreads * s2;
+      const uint32_t pv = (uint32_t)idx < nch ? pp[s2] : kHole;
+      stp[idx] = pv;
+      stv[idx] = vv[s2];
+      if (pv != kHole && (((pv >> 29) & 1u) || idx == 0)) {
+        const uint32_t left = (pv >> 19) & 1023u;
+        const uint32_t room = nch - (uint32_t)idx;
+        crng[pv & 1023u] = make_uint2(tag, (uint32_t)idx | ((left < room ? left : room) << 16));
+      }
+    }
+  };
+  auto consume = [&]() {
+    const uint2 cr = crng[j];
+    if (cr.x == tag) {
+      const int s0 = (int)(cr.y & 0xffffu), s1 = s0 + (int)(cr.y >> 16);
+      for (int i = s0; i < s1; ++i) {
+        const uint32_t pv = stp[i];
+        const double v = stv[i];
+        const GT *gp = Gb + ((pv >> 10) & 511u) * GS + 16 * h;
+        GT gv[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) gv[t] = gp[t];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = fma((double)gv[t], v, acc[t]);
+      }
+    }
+    ++tag;
+  };
+  auto step = [&](int64_t kb, ESet &X, Bnd &BX, Bnd &BY) __attribute__((always_inline)) {
+    const int64_t b0 = kb * BLK;
+    GT g[NIT][4];
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      int a, q;
+      item(u, a, q);
+      const int64_t ga = a0 + a, bq = b0 + 4 * q;
+      if (GP == kG64) {
+        double z[4] = {0.0, 0.0, 0.0, 0.0};
+        if (ga < m && bq < r) gauss4_f64((uint64_t)(bq >> 2), (uint32_t)ga, seed, z);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) g[u][t] = (GT)z[t];
+      } else {
+        float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (ga < m && bq < r) gauss4_f32((uint64_t)(bq >> 2), (uint32_t)ga, seed, z);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (bq + t >= r) z[t] = 0.0f;  // G ends at bucket r
+        if (GP == kGbf16) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) g[u][t] = (GT)(float)(__bf16)z[t];
+        } else {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) g[u][t] = (GT)z[t];
+        }
+      }
+    }
+    if (GP == kGfp8) {
+      // amax of each row over its scale block: NIT items here, LQ lanes
+      float am = 0.0f;
+#pragma unroll
+      for (int u = 0; u < NIT; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) am = fmaxf(am, fabsf((float)g[u][t]));
+#pragma unroll
+      for (int off = LQ / 2; off > 0; off >>= 1) am = fmaxf(am, __shfl_xor(am, off, 64));
+      const int ex = e8m0_exp((double)am);
+#pragma unroll
+      for (int u = 0; u < NIT; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) g[u][t] = (GT)e4m3_round_f32((float)g[u][t], ex);
+    }
+    __syncthreads();  // the previous block is done with Gb, the stage and crng
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      int a, q;
+      item(u, a, q);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) Gb[(4 * q + t) * GS + a] = g[u][t];
+    }
+    const uint32_t lo = X.lo, hi = X.hi;
+    stage(X.p, X.v, hi - lo < (uint32_t)kStage ? hi - lo : (uint32_t)kStage);
+    __syncthreads();
+    bounds(kb + 3, BY);  // block kb + 3 is fetched in the next step
+    fetch(BX, X);        // block kb + 2, bounds loaded in the previous step
+    consume();
+    // more than kStage entries: the further turns, loaded here
+    for (uint32_t base = lo + kStage; base < hi; base += kStage) {
+      uint32_t pp[kStage / kSThreads];
+      double vv[kStage / kSThreads];
+      load(base, hi, pp, vv);
+      __syncthreads();
+      stage(pp, vv, hi - base < (uint32_t)kStage ? hi - base : (uint32_t)kStage);
+      __syncthreads();
+      consume();
+    }
+  };
+  Bnd BA, BB;
+  ESet RA, RB;
+  bounds(k0, BA);
+  fetch(BA, RA);
+  bounds(k0 + 1, BB);
+  fetch(BB, RB);
+  bounds(k0 + 2, BA);
+  // both steps unconditional (a conditional one would copy set B at the
+  // loop's end): a step at k1 has empty bounds and adds nothing
+  for (int64_t kb = k0; kb < k1; kb += 2) {
+    step(kb, RA, BA, BB);
+    step(kb + 1, RB, BB, BA);
+  }
+  if (j < d) {
+    double *o = part + (ks * m + a0 + 16 * h) * d + j;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (a0 + 16 * h + i < m) o[(int64_t)i * d] = acc[i];
+  }
+}
+
+// C[i] = scale * sum_s part[s][i], splits in order
+__global__ __launch_bounds__(256) void k_sparse_reduce(const double *__restrict__ part,
+                                                       int64_t len, int splits, double scale,
+                                                       double *__restrict__ C) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= len) return;
+  double s = part[i];
+  for (int q = 1; q < splits; ++q) s += part[(int64_t)q * len + i];
+  C[i] = s * scale;
+}
+
+}  // namespace
+
+bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m) {
+  if (A.format != PSK_CSR || m <= 0) return false;
+  // the bucket rows of the entry kernel: 8 x d accumulators in 64 KiB of LDS
+  if ((size_t)kSw * ((A.d + 3) & ~(int64_t)3) * elem_size(A.dtype) > 65536) return false;
+  if (A.d > 1023) return false;
+  if (A.nnz >= ((int64_t)1 << 31) || A.n >= ((int64_t)1 << 31)) return false;
+  if (cs_splits(A.n, r) != 1) return false;
+  // S*A sparse enough: at most one nonzero in 32 of its r x d entries
+  return A.nnz * 32 <= r * A.d;
+}
+
+bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec) {
+  if (!gauss_sparse_ok(A, r, m)) return false;
+  // FP8: the dense MFMA contraction runs about 1000 times the rate of the
+  // sparse product's FP64 updates, so it wins until S*A is below 1/1024 dense
+  if (prec == PSK_PREC_FP8 && fp8_csr_fusable(A, r)) return A.nnz * 1024 <= r * A.d;
+  return true;
+}
+
+int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
+                      const uint32_t *bptr, uint64_t seed, int prec, double *C, Arena &ws,
+                      hipStream_t st) {
+  if (!gauss_sparse_ok(A, r, m))
+    return fail(PSK_EUNSUPPORTED, "sparse Gaussian product: CSR, d <= 1023, S*A sparse");
+  const int64_t n = A.n, d = A.d;
+  const int mtr = d <= 512 ? 32 : 16;
+  const int tiles_m = (int)ceil_div(m, mtr);
+  const int64_t blk = prec == PSK_PREC_F64 ? 256 : 4 * kBlk;  // buckets per G block
+  const int64_t nblk = ceil_div(r, blk);
+  // one 1024-thread workgroup per CU: about 256 of them in all
+  int64_t splits = 256 / tiles_m;
+  if (splits > nblk / 4) splits = nblk / 4;
+  if (splits < 1) splits = 1;
+  const int64_t bper = ceil_div(nblk, splits);
+  splits = ceil_div(nblk, bper);
+  uint32_t *eoff = ws.take<uint32_t>((size_t)n + 1);
+  uint32_t *be = ws.take<uint32_t>((size_t)nblk + 1);
+  uint32_t *sums = nullptr;
+  scan_plan(n + 1, ws, &sums);
+  uint32_t *eb = ws.take<uint32_t>((size_t)A.nnz + 1);
+  int32_t *ec = ws.take<int32_t>((size_t)A.nnz + 1);
+  double *ev = ws.take<double>((size_t)A.nnz + 1);
+  uint32_t *sp = ws.take<uint32_t>((size_t)A.nnz + 1);
+  double *sv = ws.take<double>((size_t)A.nnz + 1);
+  double *part = ws.take<double>((size_t)splits * m * d);
+  if (ws.dry()) return 0;
+  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the sparse Gaussian product");
+  {
+    KTimer t("sa_entries", st);
+    k_row_nnz<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(A.indptr, perm, n, eoff);
+    scan_run(eoff, n + 1, sums, st);
+    const int64_t dpad = (d + 3) & ~(int64_t)3;
+    const size_t lds = (size_t)kSw * dpad * elem_size(A.dtype);
+    const unsigned nb = (unsigned)ceil_div(r, kSw);
+    const bool limbs = prec == PSK_PREC_BF16;
+#define PSK_SAE(TT, LB)                                                                      \
+  k_sa_entries<TT, LB><<<nb, 64 * kSw, lds, st>>>((const TT *)A.values, A.indptr, A.indices, \
+                                                   d, dpad, r, perm, bptr, eoff, eb, ec, ev)
+    if (A.dtype == PSK_F64) {
+      if (limbs) PSK_SAE(double, true); else PSK_SAE(double, false);
+    } else {
+      if (limbs) PSK_SAE(float, true); else PSK_SAE(float, false);
+    }
+#undef PSK_SAE
+    if (prec == PSK_PREC_FP8)
+      k_entries_fp8<<<(unsigned)ceil_div(r, kBlk), 256, (size_t)d * 8, st>>>(bptr, eoff, r, d,
+                                                                          ec, ev);
+    k_block_entries<<<(unsigned)ceil_div(nblk + 1, 256), 256, 0, st>>>(bptr, eoff, r, blk, nblk,
+                                                                     be);
+    if (blk == 256)
+      k_block_csc<8><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, sp, sv);
+    else
+      k_block_csc<16><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, sp, sv);
+  }
+  {
+    KTimer t("gauss_gemm", st);
+    const unsigned grid = (unsigned)(tiles_m * splits);
+#define PSK_GSP(GP, DP, BLK)                                                                 \
+  k_gauss_sparse<GP, DP, BLK><<<grid, kSThreads, 0, st>>>(m, d, r, seed, be, sp, sv, tiles_m, \
+                                                         bper, part)
+#define PSK_GSP_MT(GP, BLK)                   \
+  do {                                        \
+    if (d <= 512) PSK_GSP(GP, 512, BLK);      \
+    else PSK_GSP(GP, 1024, BLK);              \
+  } while (0)
+    if (prec == PSK_PREC_F64) PSK_GSP_MT(kG64, 256);
+    else if (prec == PSK_PREC_BF16) PSK_GSP_MT(kGbf16, 512);
+    else PSK_GSP_MT(kGfp8, 512);
+#undef PSK_GSP_MT
+#undef PSK_GSP
+  }
+  {
+    KTimer t("gemm_reduce", st);
+    const int64_t len = m * d;
+    k_sparse_reduce<<<(unsigned)ceil_div(len, 256), 256, 0, st>>>(part, len, (int)splits,
+                                                                  1.0 / sqrt((double)m), C);
+  }
+  PSK_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+}  // namespace psk

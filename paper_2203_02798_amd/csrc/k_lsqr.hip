@@ -844,15 +844,23 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
       o.escalate_cond != 0.0 ? o.escalate_cond : (o.prec == PSK_PREC_FP8 ? 10.0 : 1e4);
   const bool may_escalate =
       own && (o.prec == PSK_PREC_BF16 || o.prec == PSK_PREC_FP8) && cond_limit > 0.0;
-  // CSR A with the BF16 or FP8 GEMM: its operand comes straight from the
-  // binned rows and S*A is only formed if the solve escalates to FP64
-  const bool fused = own && ((o.prec == PSK_PREC_BF16 && bf16_csr_fusable(A, o.r)) ||
-                             (o.prec == PSK_PREC_FP8 && fp8_csr_fusable(A, o.r)));
+  // CSR A whose S*A is sparse: the product over the nonzeros of S*A from
+  // the binned rows (the FP64 rebuild too, whatever the first precision).
+  // Otherwise, CSR A with the BF16 or FP8 GEMM: its operand comes straight
+  // from the binned rows and S*A is only formed if the solve escalates to
+  // FP64.
+  const bool sparse_ok = own && gauss_sparse_ok(A, o.r, m);
+  const bool sparse = sparse_ok && gauss_sparse_pick(A, o.r, m, o.prec);
+  const bool fused = own && !sparse &&
+                     ((o.prec == PSK_PREC_BF16 && bf16_csr_fusable(A, o.r)) ||
+                      (o.prec == PSK_PREC_FP8 && fp8_csr_fusable(A, o.r)));
   void *SA = nullptr;
   uint32_t *perm = nullptr, *bptr = nullptr;
   // the FP64 sketch (after a reduced-precision one), S*A formed here if needed
   auto rebuild_f64 = [&]() -> int {
     int e;
+    if (sparse_ok)
+      return gauss_gemm_sparse(m, o.r, A, perm, bptr, o.seed, PSK_PREC_F64, C, ws, st);
     if (fused) {
       SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
       if ((e = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return e;
@@ -863,11 +871,14 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     // sketch and factor (their scratch is released afterwards); S*A (or the
     // binned rows it is formed from) stays until the precision decision so
     // that an FP64 rebuild can reuse it
-    if (!fused) SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
+    if (!fused && !sparse) SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
     if ((rc = cs_bin(n, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr))) return rc;
-    if (!fused && (rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return rc;
+    if (!fused && !sparse && (rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st)))
+      return rc;
     const size_t mk2 = ws.mark();
-    if (fused && o.prec == PSK_PREC_BF16)
+    if (sparse)
+      rc = gauss_gemm_sparse(m, o.r, A, perm, bptr, o.seed, o.prec, C, ws, st);
+    else if (fused && o.prec == PSK_PREC_BF16)
       rc = gauss_gemm_bf16_csr(m, o.r, A, perm, bptr, o.seed, C, ws, st);
     else if (fused)
       rc = gauss_gemm_fp8_csr(m, o.r, A, perm, bptr, o.seed, C, ws, st);

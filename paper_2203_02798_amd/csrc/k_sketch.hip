@@ -193,12 +193,12 @@ __global__ __launch_bounds__(256) void k_scan_add(uint32_t *__restrict__ data, i
   if (i < L) data[i] += sums[i / kScanTile];
 }
 
-int scan_plan(int64_t L, Arena &ws, uint32_t **sums) {
+int scan_plan_impl(int64_t L, Arena &ws, uint32_t **sums) {
   *sums = ws.take<uint32_t>((size_t)ceil_div(L, kScanTile) + 1);
   return 0;
 }
 
-void scan_run(uint32_t *data, int64_t L, uint32_t *sums, hipStream_t st) {
+void scan_run_impl(uint32_t *data, int64_t L, uint32_t *sums, hipStream_t st) {
   const int64_t nb = ceil_div(L, kScanTile);
   k_scan_tiles<<<(unsigned)nb, kScanThreads, 0, st>>>(data, L, sums);
   k_scan_sums<<<1, kScanThreads, 0, st>>>(sums, nb);
@@ -409,6 +409,10 @@ void launch_dense(const psk_mat &A, int64_t r, const uint32_t *perm,
 // host entry points
 // ---------------------------------------------------------------------------
 int cs_splits(int64_t n, int64_t r) { return choose_splits(n, r); }
+int scan_plan(int64_t L, Arena &ws, uint32_t **sums) { return scan_plan_impl(L, ws, sums); }
+void scan_run(uint32_t *data, int64_t L, uint32_t *sums, hipStream_t st) {
+  scan_run_impl(data, L, sums, st);
+}
 
 int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
                    int32_t *h, int8_t *sign, hipStream_t st) {
@@ -430,7 +434,7 @@ int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
   uint32_t *v1 = passes ? ws.take<uint32_t>(n) : nullptr;
   uint32_t *hist = passes ? ws.take<uint32_t>(L) : nullptr;
   uint32_t *sums = nullptr;
-  if (passes) scan_plan(L, ws, &sums);
+  if (passes) scan_plan_impl(L, ws, &sums);
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for a radix sort");
   uint32_t *kin = keys, *vin = vals, *kout = k1, *vout = v1;
@@ -440,7 +444,7 @@ int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
     const uint32_t mask = (1u << nb) - 1u;
     k_radix_hist<<<(unsigned)ntiles, kSortThreads, 0, st>>>(kin, n, shift, mask, hist,
                                                             ntiles);
-    scan_run(hist, L, sums, st);
+    scan_run_impl(hist, L, sums, st);
     k_radix_scatter<<<(unsigned)ntiles, kSortThreads, 0, st>>>(kin, vin, n, shift, nb,
                                                                hist, ntiles, kout, vout);
     uint32_t *t;

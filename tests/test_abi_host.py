@@ -64,8 +64,13 @@ def test_workspace_planning(lib):
     assert st == 0 and b1 >= 20000 * 4 * 2
     st, b2 = _ws(L.PSK_OP_SKETCH_GCS, _dense(20000, 50), m=200, r=2500)
     assert st == 0 and b2 > b1 + 2500 * 50 * 8
+    # sparse S*A (500,000 nonzeros in 250,000 x 500): the product runs over its
+    # nonzeros, which are staged (slot, column, value) instead of the r x d array
     st, b3 = _ws(L.PSK_OP_SKETCH_GCS, _csr(1_000_000, 500, 500_000), m=2000, r=250_000)
-    assert st == 0 and b3 > 250_000 * 500 * 8  # S*A is staged in the workspace
+    assert st == 0 and 500_000 * 16 <= b3 < 250_000 * 500 * 8
+    # a denser CSR matrix takes the GEMM, with S*A staged in the workspace
+    st, b3d = _ws(L.PSK_OP_SKETCH_GCS, _csr(100_000, 64, 3_000_000), m=256, r=8192)
+    assert st == 0 and b3d > 8192 * 64 * 8
     st, b4 = _ws(L.PSK_OP_GRAM, _dense(1000, 64))
     assert st == 0 and b4 > 0
     st, b5 = _ws(L.PSK_OP_ROWNORMS, _csr(1000, 64, 100), k=64)

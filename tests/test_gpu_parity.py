@@ -121,19 +121,27 @@ def test_sketch_cs_csr_empty_rows_and_empty_matrix(api):
 # ---------------------------------------------------------------------------
 # G*S*A (FP64)
 # ---------------------------------------------------------------------------
+def _gcs_input(kind, n, d):
+    """'csr' (density 1e-3) or 'csr:<density>', 'dense32', 'dense'."""
+    if kind.startswith("csr"):
+        dens = float(kind.split(":")[1]) if ":" in kind else 1e-3
+        return synth.csr_uniform(n, d, dens, seed=1)
+    if kind == "dense32":
+        return synth.dense_gaussian(n, d, seed=1, dtype=np.float32)
+    return synth.dense_gaussian(n, d, seed=1)
+
+
 @pytest.mark.parametrize("kind,n,d,m,r", [
     ("dense", 20000, 50, 200, 2500),      # the small dense FP64 workload
     ("dense", 6000, 130, 77, 3001),
     ("csr", 100000, 500, 300, 25000),
+    # S*A sparse, d > 512 (16-row tiles), G blocks of about 6000 entries
+    # (staged in several turns), ragged m
+    ("csr", 50000, 1000, 77, 4096),
     ("dense32", 8000, 96, 129, 1024)])
 def test_sketch_gcs_f64(api, kind, n, d, m, r):
     _say(f"sketch_gcs {kind} n={n} d={d} m={m} r={r}")
-    if kind == "csr":
-        a = synth.csr_uniform(n, d, 1e-3, seed=1)
-    elif kind == "dense32":
-        a = synth.dense_gaussian(n, d, seed=1, dtype=np.float32)
-    else:
-        a = synth.dense_gaussian(n, d, seed=1)
+    a = _gcs_input(kind, n, d)
     c = api.sketch_gcs(to_device(a), m, r, seed=21).cpu().numpy()
     ref = osk.sketch_gcs(a, m, r, 21)
     err = rel_fro(c, ref)
@@ -170,15 +178,11 @@ def test_sketch_gcs_deterministic(api):
     ("dense", 3000, 600, 150, 1000),     # two 512-column tiles, ragged
     ("dense", 500, 3, 5, 7),             # one partial 32-bucket chunk
     ("csr", 100000, 500, 300, 25000),
+    ("csr", 50000, 1000, 77, 4096),
     ("dense32", 8000, 96, 129, 1024)])
 def test_sketch_gcs_bf16(api, kind, n, d, m, r):
     _say(f"sketch_gcs bf16 {kind} n={n} d={d} m={m} r={r}")
-    if kind == "csr":
-        a = synth.csr_uniform(n, d, 1e-3, seed=1)
-    elif kind == "dense32":
-        a = synth.dense_gaussian(n, d, seed=1, dtype=np.float32)
-    else:
-        a = synth.dense_gaussian(n, d, seed=1)
+    a = _gcs_input(kind, n, d)
     c = api.sketch_gcs(to_device(a), m, r, seed=21, prec="bf16").cpu().numpy()
     # kernel arithmetic: against the exact product of the rounded operands
     e_arith = rel_fro(c, osk.sketch_gcs_bf16_reference(a, m, r, 21))
@@ -200,15 +204,14 @@ def test_sketch_gcs_bf16(api, kind, n, d, m, r):
     ("dense", 3000, 600, 150, 1000),     # two 512-column tiles, ragged
     ("dense", 500, 3, 5, 7),             # one partial 128-bucket chunk
     ("csr", 100000, 500, 300, 25000),
+    # S*A below 1/1024 dense: the product over its nonzeros (512- and
+    # 1024-column forms)
+    ("csr", 30000, 200, 100, 32768),
+    ("csr:2e-4", 20000, 700, 77, 8192),
     ("dense32", 8000, 96, 129, 1024)])
 def test_sketch_gcs_fp8(api, kind, n, d, m, r):
     _say(f"sketch_gcs fp8 {kind} n={n} d={d} m={m} r={r}")
-    if kind == "csr":
-        a = synth.csr_uniform(n, d, 1e-3, seed=1)
-    elif kind == "dense32":
-        a = synth.dense_gaussian(n, d, seed=1, dtype=np.float32)
-    else:
-        a = synth.dense_gaussian(n, d, seed=1)
+    a = _gcs_input(kind, n, d)
     c = api.sketch_gcs(to_device(a), m, r, seed=21, prec="fp8").cpu().numpy()
     e_arith = rel_fro(c, osk.sketch_gcs_fp8_reference(a, m, r, 21))
     e_fmt = rel_fro(c, osk.sketch_gcs(a, m, r, 21))
