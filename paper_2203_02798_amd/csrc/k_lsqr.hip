@@ -21,11 +21,14 @@
 //                             recurrences, v, w, y and the stopping test.
 // All state stays on the device; a `done` flag set by the stopping test turns
 // the remaining enqueued iterations into no-ops, so the host reads the state
-// only every `check_every` iterations, and reads each group's copy while the
-// next group runs.  Every sum has a fixed order (CSR rows
+// only after groups of up to `check_every` iterations, each group's copy
+// while the next group runs, and cuts the last group short where the
+// stopping margin's observed rate predicts the stop.  Every sum has a fixed order (CSR rows
 // scatter A_i^T u_i into per-wavefront LDS rows in a fixed instruction
 // order).
 #include <math.h>
+
+#include <cmath>
 
 #include <mutex>
 #include <vector>
@@ -929,6 +932,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   int total_iters = 0;
   bool converged = true;
   LsqrState hs{};
+  double rate = 0.0;  // d log(stopping margin) / d iteration, from the last pass
   for (int pass = 0; pass <= o.refine; ++pass) {
     const double *rhs = b;
     if (pass > 0) {
@@ -955,36 +959,83 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     k_zero<<<db, 256, 0, st>>>(B.v[0], d);
     one_step(A, true, 0, B, Rinv, rhs, o, st);
     int kstep = 1;
-    // groups of check_every iterations; after each, the state is copied to
-    // pinned memory and the host reads the previous group's copy while this
-    // one runs.  A group enqueued after convergence costs only no-op
-    // launches (the device-side done flag).
-    int it = 0, ngroup = 0, inflight = -1;
+    // Groups of at most check_every iterations; after each, the state is
+    // copied to pinned memory and the host reads the previous group's copy
+    // while this one runs.  A group enqueued after convergence costs only
+    // no-op launches (the device-side done flag), so the host sizes the
+    // groups near the end: the stopping margin q (1 at the stopping test)
+    // falls about geometrically, and from its rate over the known states the
+    // last group is cut to end one iteration past the predicted stop and is
+    // read at once.  A refinement pass starts from the first pass's rate,
+    // with a short first group read at once (it usually needs few
+    // iterations).  The prediction only sizes groups: the stop itself is the
+    // device's test, and a wrong prediction costs a wait or no-op launches.
+    int it = 0, ngroup = 0;
+    int queue[2], queued = 0;  // slots of the groups enqueued and not yet read
+    int known_it = -1, prev_it = -1;
+    double known_q = 0.0, prev_q = 0.0;
     bool done = false;
-    while (it < o.max_iter) {
+    auto margin = [&](const LsqrState &s2) {
+      double q = INFINITY;
+      const double anorm = sqrt(s2.anorm2);
+      if (o.atol > 0.0) q = s2.test2 / o.atol;
+      const double den = o.btol * s2.bnorm + o.atol * anorm * sqrt(s2.ynorm2);
+      if (den > 0.0) q = fmin(q, s2.rnorm / den);
+      return q;
+    };
+    while (it < o.max_iter || queued > 0) {
+      if (prev_it >= 0 && known_it > prev_it && prev_q > 0.0 && known_q > 0.0) {
+        const double r = log(known_q / prev_q) / (known_it - prev_it);
+        if (std::isfinite(r) && r < -1e-3) rate = r;
+      }
       int batch = o.check_every;
+      bool read_now = false;
+      if (pass > 0 && ngroup == 0) {
+        batch = batch < 4 ? batch : 4;
+        read_now = true;
+      } else if (known_it >= 0 && rate < 0.0 && known_q > 0.0 && std::isfinite(known_q)) {
+        const int need =
+            known_q <= 1.0 ? 0 : (int)fmin(ceil(log(known_q) / -rate), (double)o.max_iter);
+        const int left = need - (it - known_it);  // predicted, beyond what is enqueued
+        if (left <= 0 && queued > 0) {
+          batch = 0;
+        } else if (left < batch) {
+          batch = left > 0 ? left + 1 : 1;
+          read_now = true;
+        }
+      }
       if (batch > o.max_iter - it) batch = o.max_iter - it;
-      for (int q = 0; q < batch; ++q) one_step(A, false, kstep++, B, Rinv, rhs, o, st);
-      it += batch;
-      const int cur = ngroup++ & 1;
-      PSK_HIP_TRY(hipMemcpyAsync(&slot.sl.h[cur], B.st, sizeof(LsqrState),
-                                 hipMemcpyDeviceToHost, st));
-      PSK_HIP_TRY(hipEventRecord(slot.sl.ev[cur], st));
-      if (inflight >= 0) {
-        PSK_HIP_TRY(hipEventSynchronize(slot.sl.ev[inflight]));
-        if (slot.sl.h[inflight].done) {
-          hs = slot.sl.h[inflight];
+      if (batch > 0) {
+        for (int q = 0; q < batch; ++q) one_step(A, false, kstep++, B, Rinv, rhs, o, st);
+        it += batch;
+        const int cur = ngroup++ & 1;
+        PSK_HIP_TRY(hipMemcpyAsync(&slot.sl.h[cur], B.st, sizeof(LsqrState),
+                                   hipMemcpyDeviceToHost, st));
+        PSK_HIP_TRY(hipEventRecord(slot.sl.ev[cur], st));
+        queue[queued++] = cur;
+      }
+      // read the older group while the newer one runs; everything when a
+      // group was cut short, nothing was enqueued or max_iter is reached
+      const int keep = (read_now || batch == 0 || it >= o.max_iter) ? 0 : 1;
+      while (queued > keep) {
+        const int sl = queue[0];
+        queue[0] = queue[1];
+        --queued;
+        PSK_HIP_TRY(hipEventSynchronize(slot.sl.ev[sl]));
+        hs = slot.sl.h[sl];
+        prev_it = known_it;
+        prev_q = known_q;
+        known_it = hs.iters;
+        known_q = margin(hs);
+        if (hs.done) {
           done = true;
           break;
         }
       }
-      inflight = cur;
+      if (done) break;
     }
-    if (!done && inflight >= 0) {
-      PSK_HIP_TRY(hipEventSynchronize(slot.sl.ev[inflight]));
-      hs = slot.sl.h[inflight];
-      done = hs.done != 0;
-    }
+    // the groups still enqueued after the stop are no-ops; the stream
+    // synchronisation below waits for them
     if (!done) converged = false;
     total_iters += hs.iters;
     // x += R^{-1} y
