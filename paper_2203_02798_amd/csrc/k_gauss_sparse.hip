@@ -11,8 +11,10 @@
 //   BF16  G rounded to bfloat16, S*A as its two bfloat16 limbs hi + lo;
 //   FP8   both in OCP e4m3 with one E8M0 scale per 128-bucket block (per row
 //         of G, per column of S*A).
-// Products of the rounded operands are exact in FP64 and are accumulated in
-// FP64 (the dense reduced-precision kernels accumulate in FP32).
+// FP64 accumulates in FP64.  BF16 and FP8 accumulate in FP32 within a K
+// split, as the dense reduced-precision kernels do (each product is exact
+// inside the FMA; BF16's value hi + lo is rounded to FP32 where its limbs
+// span more than 24 bits), and the split partials are summed in FP64.
 //
 // Steps (all on the binned rows of cs_bin):
 //   k_row_nnz + scan   offsets: bucket b's entries occupy slots
@@ -24,11 +26,15 @@
 //                      slots as holes (column -1);
 //   k_entries_fp8      (FP8) the per-column, per-128-bucket scale and the
 //                      e4m3 rounding of the values;
-//   k_gauss_sparse     workgroup (32-row tile of C, a range of 128-bucket
-//                      blocks): per block it draws G for its rows
-//                      into LDS, then every entry (b, j, s) adds G[a, b] s to
-//                      C[a, j] of the tile held in LDS, entries in slot
-//                      order; the tile goes out as one K-split partial;
+//   k_block_entries    the first slot of every G block (512 buckets; 256
+//                      for FP64);
+//   k_block_csc        each G block's entries sorted by (column, bucket),
+//                      packed with their column's run length;
+//   k_gauss_sparse     workgroup (32- or 16-row tile of C, a range of G
+//                      blocks): per block it draws G for its rows into LDS
+//                      and stages the block's entries; each thread adds the
+//                      entries of its column into its rows of C, held in
+//                      registers; the tile goes out as one K-split partial;
 //   k_sparse_reduce    C = (1/sqrt m) sum of the partials in split order.
 #include <type_traits>
 
@@ -290,7 +296,8 @@ constexpr int kStage = 2 * kSThreads;  // entries of a block staged in LDS at on
 // the block of G into LDS (bucket-major, so one bucket's MT values are
 // contiguous); the block's entries, sorted by (column, bucket), are staged
 // in LDS with, per column, the range of its entries; thread (h, j) then
-// adds G[a, b] s for the entries (b, j, s) of its column in bucket order.
+// adds G[a, b] s for the entries (b, j, s) of its column in bucket order
+// (FP64, or FP32 when G is drawn in FP32).
 // So each element of C is summed by one thread, over buckets in ascending
 // order, with no atomics.  Entries are fetched two blocks ahead, the block
 // bounds three; a block of more than kStage entries is staged in turns.
@@ -300,6 +307,7 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     const uint32_t *__restrict__ sp, const double *__restrict__ sv, int tiles_m, int64_t bper,
     double *__restrict__ part /* [splits][m][d] */) {
   typedef typename std::conditional<GP == kG64, double, float>::type GT;
+  typedef GT AT;  // accumulator and staged value: FP64, or FP32 with G in FP32
   constexpr int RG = kSThreads / DP;                // row groups
   constexpr int MT = 16 * RG;                       // tile rows
   constexpr int GS = MT + 16 / (int)sizeof(GT);     // LDS stride of a bucket of G
@@ -309,7 +317,7 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
   static_assert(GP != kGfp8 || BLK == 4 * kBlk, "FP8 G blocks hold four scale blocks");
   __shared__ __align__(16) GT Gb[BLK * GS];
   __shared__ uint32_t stp[kStage];
-  __shared__ double stv[kStage];
+  __shared__ AT stv[kStage];
   __shared__ uint2 crng[DP];  // per column: tag, first staged slot | count << 16
   const int tid = threadIdx.x;
   const int mt = (int)(blockIdx.x % tiles_m);
@@ -320,9 +328,9 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
   const int64_t k1 = k0 + bper < nblk ? k0 + bper : nblk;
   const int j = tid % DP, h = tid / DP;
   for (int i = tid; i < DP; i += kSThreads) crng[i] = make_uint2(kHole, 0u);
-  double acc[16];
+  AT acc[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+  for (int i = 0; i < 16; ++i) acc[i] = AT(0);
   uint32_t tag = 0;  // one per staged turn, never kHole
   // G item u of this thread: row ga_u, Philox block q_u of the block.  FP8
   // takes the amax of a row over a 128-bucket scale block, 32 Philox blocks:
@@ -377,7 +385,7 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
       const int idx = tid + kSThreads * s2;
       const uint32_t pv = (uint32_t)idx < nch ? pp[s2] : kHole;
       stp[idx] = pv;
-      stv[idx] = vv[s2];
+      stv[idx] = (AT)vv[s2];
       if (pv != kHole && (((pv >> 29) & 1u) || idx == 0)) {
         const uint32_t left = (pv >> 19) & 1023u;
         const uint32_t room = nch - (uint32_t)idx;
@@ -391,13 +399,13 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
       const int s0 = (int)(cr.y & 0xffffu), s1 = s0 + (int)(cr.y >> 16);
       for (int i = s0; i < s1; ++i) {
         const uint32_t pv = stp[i];
-        const double v = stv[i];
+        const AT v = stv[i];
         const GT *gp = Gb + ((pv >> 10) & 511u) * GS + 16 * h;
         GT gv[16];
 #pragma unroll
         for (int t = 0; t < 16; ++t) gv[t] = gp[t];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = fma((double)gv[t], v, acc[t]);
+        for (int t = 0; t < 16; ++t) acc[t] = fma(gv[t], v, acc[t]);
       }
     }
     ++tag;
@@ -487,7 +495,7 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     double *o = part + (ks * m + a0 + 16 * h) * d + j;
 #pragma unroll
     for (int i = 0; i < 16; ++i)
-      if (a0 + 16 * h + i < m) o[(int64_t)i * d] = acc[i];
+      if (a0 + 16 * h + i < m) o[(int64_t)i * d] = (double)acc[i];
   }
 }
 
