@@ -19,11 +19,12 @@
 // Steps (all on the binned rows of cs_bin):
 //   k_row_nnz + scan   offsets: bucket b's entries occupy slots
 //                      eoff[bptr[b]] .. eoff[bptr[b+1]] (its rows' lengths);
-//   k_sa_entries       a workgroup of 8 wavefronts sums 8 buckets' rows into
-//                      LDS rows (the CountSketch scatter's order, so the
-//                      same bits as S*A) and writes each bucket's nonzeros
-//                      (bucket, column, value) into its slots, the unused
-//                      slots as holes (column -1);
+//   k_sa_entries       a lane per bucket sums the bucket's rows in
+//                      registers (the CountSketch scatter's order, so the
+//                      same bits as S*A; longer buckets through a dense LDS
+//                      row per wavefront) and writes its nonzeros (bucket,
+//                      column, value) in column order into its slots, the
+//                      unused slots as holes (column -1);
 //   k_entries_fp8      (FP8) the per-column, per-128-bucket scale and the
 //                      e4m3 rounding of the values;
 //   k_block_entries    the first slot of every G block (512 buckets; 256
@@ -44,7 +45,6 @@ namespace psk {
 namespace {
 
 constexpr int kBlk = 128;  // buckets per FP8 scale block
-constexpr int kSw = 8;     // wavefronts (buckets) per k_sa_entries workgroup
 
 // rn[j] = number of entries of the row at bin position j; rn[n] = 0
 __global__ __launch_bounds__(256) void k_row_nnz(const int64_t *__restrict__ indptr,
@@ -118,30 +118,31 @@ __device__ __forceinline__ float e4m3_round_f32(float v, int e) {
   return ldexpf(__builtin_amdgcn_cvt_f32_fp8(byte, 0), e);
 }
 
-// S*A entries of buckets 8 blockIdx.x .. +7 (wavefront w: bucket 8 blk + w).
-// BF16: the value written is hi + lo (the two limbs); otherwise S*A itself.
+// The value written for an S*A entry: BF16 keeps hi + lo, its two limbs
+template <bool LIMBS>
+__device__ __forceinline__ double entry_value(double v) {
+  if (!LIMBS) return v;
+  const double hi = bf16_round(v);
+  return hi + bf16_round(v - hi);
+}
+
+// Bucket b's S*A entries through a dense LDS row of d (one wavefront): its
+// rows summed in the CountSketch scatter's order, the nonzeros written in
+// column order into the slots e0 .. e0 + cap, the rest as holes.
 template <typename T, bool LIMBS>
-__global__ __launch_bounds__(64 * kSw) void k_sa_entries(
-    const T *__restrict__ vals, const int64_t *__restrict__ indptr,
-    const int32_t *__restrict__ indices, int64_t d, int64_t dpad, int64_t r,
-    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
-    const uint32_t *__restrict__ eoff, uint32_t *__restrict__ eb,
-    int32_t *__restrict__ ec, double *__restrict__ ev) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * kSw + wave;
-  if (b >= r) return;
-  T *acc = reinterpret_cast<T *>(smem_raw) + (int64_t)wave * dpad;
+__device__ void bucket_entries_wave(const T *__restrict__ vals, const int64_t *__restrict__ indptr,
+                                    const int32_t *__restrict__ indices,
+                                    const uint32_t *__restrict__ perm, uint32_t j0, uint32_t j1,
+                                    uint32_t e0, uint32_t cap, int64_t b, int64_t d,
+                                    int64_t dpad, T *acc, uint32_t *__restrict__ eb,
+                                    int32_t *__restrict__ ec, double *__restrict__ ev) {
+  const int lane = (int)(threadIdx.x & 63u);
   for (int64_t c = lane; c < dpad; c += 64) acc[c] = T(0);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  const uint32_t j0 = bptr[b], j1 = bptr[b + 1];
-  if (j0 == j1) return;
   bucket_rows_add(vals, indptr, indices, perm, j0, j1, acc);
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  const uint32_t e0 = eoff[j0], cap = eoff[j1] - e0;
   uint32_t cnt = 0;
   for (int64_t c0 = 0; c0 < d; c0 += 64) {
     const int64_t c = c0 + lane;
@@ -149,16 +150,10 @@ __global__ __launch_bounds__(64 * kSw) void k_sa_entries(
     const bool nz = v != 0.0;
     const uint64_t mask = __ballot(nz);
     if (nz) {
-      const uint32_t pos =
-          e0 + cnt + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-      double w = v;
-      if (LIMBS) {
-        const double hi = bf16_round(v);
-        w = hi + bf16_round(v - hi);  // exact: 16 significant bits at most
-      }
+      const uint32_t pos = e0 + cnt + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
       eb[pos] = (uint32_t)b;
       ec[pos] = (int32_t)c;
-      ev[pos] = w;
+      ev[pos] = entry_value<LIMBS>(v);
     }
     cnt += (uint32_t)__popcll(mask);
   }
@@ -166,6 +161,115 @@ __global__ __launch_bounds__(64 * kSw) void k_sa_entries(
     eb[e0 + p] = (uint32_t)b;
     ec[e0 + p] = -1;
     ev[e0 + p] = 0.0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();  // acc is reused by the wavefront's next bucket
+}
+
+constexpr int kLaneEnt = 8;  // entries a bucket may have for the lane path
+
+// S*A entries of buckets 256 blockIdx.x .. +255, a lane per bucket: the
+// bucket's rows (at most kLaneEnt entries in all) are added into a list of
+// (column, value) in registers, row after row in list order, so each value
+// is summed in the CountSketch scatter's order and has the same bits as
+// S*A; the list is sorted by column and its nonzeros written in that order,
+// then the holes.  Buckets with more entries are taken afterwards, one at a
+// time, by their wavefront through a dense LDS row (bucket_entries_wave).
+// BF16: the value written is hi + lo (the two limbs); otherwise S*A itself.
+template <typename T, bool LIMBS>
+__global__ __launch_bounds__(256) void k_sa_entries(
+    const T *__restrict__ vals, const int64_t *__restrict__ indptr,
+    const int32_t *__restrict__ indices, int64_t d, int64_t dpad, int64_t r,
+    const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
+    const uint32_t *__restrict__ eoff, uint32_t *__restrict__ eb,
+    int32_t *__restrict__ ec, double *__restrict__ ev) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int lane = (int)(threadIdx.x & 63u);
+  T *acc = reinterpret_cast<T *>(smem_raw) + (int64_t)(threadIdx.x >> 6) * dpad;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  uint32_t j0 = 0, j1 = 0, e0 = 0, cap = 0;
+  if (b < r) {
+    j0 = bptr[b];
+    j1 = bptr[b + 1];
+    e0 = eoff[j0];
+    cap = eoff[j1] - e0;
+  }
+  const bool lng = cap > (uint32_t)kLaneEnt;
+  if (cap > 0 && !lng) {
+    int col[kLaneEnt];
+    T val[kLaneEnt];
+#pragma unroll
+    for (int k = 0; k < kLaneEnt; ++k) {
+      col[k] = INT32_MAX;
+      val[k] = T(0);
+    }
+    int n = 0;
+    for (uint32_t j = j0; j < j1; ++j) {
+      const uint32_t pv = perm[j];
+      const int64_t row = (int64_t)(pv & 0x7fffffffu);
+      const bool ng = (pv >> 31) != 0u;
+      const int64_t p1 = indptr[row + 1];
+      for (int64_t p = indptr[row]; p < p1; ++p) {
+        const int32_t c = indices[p];
+        const T v0 = vals[p];
+        const T v = ng ? -v0 : v0;
+        bool hit = false;
+#pragma unroll
+        for (int k = 0; k < kLaneEnt; ++k)
+          if (col[k] == c) {
+            val[k] += v;
+            hit = true;
+          }
+        if (!hit) {
+#pragma unroll
+          for (int k = 0; k < kLaneEnt; ++k)
+            if (k == n) {
+              col[k] = c;
+              val[k] = v;
+            }
+          ++n;
+        }
+      }
+    }
+    // sort by column (odd-even transposition; unused slots hold INT32_MAX)
+#pragma unroll
+    for (int ph = 0; ph < kLaneEnt; ++ph)
+#pragma unroll
+      for (int k = ph & 1; k + 1 < kLaneEnt; k += 2)
+        if (col[k] > col[k + 1]) {
+          const int tc = col[k];
+          col[k] = col[k + 1];
+          col[k + 1] = tc;
+          const T tv = val[k];
+          val[k] = val[k + 1];
+          val[k + 1] = tv;
+        }
+    uint32_t pos = 0;
+#pragma unroll
+    for (int k = 0; k < kLaneEnt; ++k) {
+      const double v = (double)val[k];
+      if (k < n && v != 0.0) {
+        eb[e0 + pos] = (uint32_t)b;
+        ec[e0 + pos] = col[k];
+        ev[e0 + pos] = entry_value<LIMBS>(v);
+        ++pos;
+      }
+    }
+    for (; pos < cap; ++pos) {
+      eb[e0 + pos] = (uint32_t)b;
+      ec[e0 + pos] = -1;
+      ev[e0 + pos] = 0.0;
+    }
+  }
+  uint64_t lm = __ballot(lng);
+  while (lm) {
+    const int i = __ffsll((unsigned long long)lm) - 1;
+    lm &= lm - 1;
+    const uint32_t bj0 = __shfl(j0, i, 64), bj1 = __shfl(j1, i, 64);
+    const uint32_t be0 = __shfl(e0, i, 64), bcap = __shfl(cap, i, 64);
+    const int64_t bb = b - lane + i;
+    bucket_entries_wave<T, LIMBS>(vals, indptr, indices, perm, bj0, bj1, be0, bcap, bb, d, dpad,
+                                  acc, eb, ec, ev);
   }
 }
 
@@ -514,8 +618,8 @@ __global__ __launch_bounds__(256) void k_sparse_reduce(const double *__restrict_
 
 bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m) {
   if (A.format != PSK_CSR || m <= 0) return false;
-  // the bucket rows of the entry kernel: 8 x d accumulators in 64 KiB of LDS
-  if ((size_t)kSw * ((A.d + 3) & ~(int64_t)3) * elem_size(A.dtype) > 65536) return false;
+  // the dense bucket rows of the entry kernel: 4 x d accumulators in 64 KiB of LDS
+  if ((size_t)4 * ((A.d + 3) & ~(int64_t)3) * elem_size(A.dtype) > 65536) return false;
   if (A.d > 1023) return false;
   if (A.nnz >= ((int64_t)1 << 31) || A.n >= ((int64_t)1 << 31)) return false;
   if (cs_splits(A.n, r) != 1) return false;
@@ -564,12 +668,12 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
     k_row_nnz<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(A.indptr, perm, n, eoff);
     scan_run(eoff, n + 1, sums, st);
     const int64_t dpad = (d + 3) & ~(int64_t)3;
-    const size_t lds = (size_t)kSw * dpad * elem_size(A.dtype);
-    const unsigned nb = (unsigned)ceil_div(r, kSw);
+    const size_t lds = (size_t)4 * dpad * elem_size(A.dtype);
+    const unsigned nb = (unsigned)ceil_div(r, 256);
     const bool limbs = prec == PSK_PREC_BF16;
-#define PSK_SAE(TT, LB)                                                                      \
-  k_sa_entries<TT, LB><<<nb, 64 * kSw, lds, st>>>((const TT *)A.values, A.indptr, A.indices, \
-                                                   d, dpad, r, perm, bptr, eoff, eb, ec, ev)
+#define PSK_SAE(TT, LB)                                                                   \
+  k_sa_entries<TT, LB><<<nb, 256, lds, st>>>((const TT *)A.values, A.indptr, A.indices, d, \
+                                              dpad, r, perm, bptr, eoff, eb, ec, ev)
     if (A.dtype == PSK_F64) {
       if (limbs) PSK_SAE(double, true); else PSK_SAE(double, false);
     } else {
