@@ -18,9 +18,11 @@ The FP64 plain path and the paths with the BF16 and FP8 Gaussian GEMMs are
 all timed (``--prec all``, the default); the BF16 path is the headline and
 the other two are reported beside it.  Prints ONE JSON line.  ``value`` is GB/s of A
 through the whole step (bytes of A = values + column indices + row
-pointers, per step, divided by the step time).  The dominant kernel (the Gaussian GEMM) is timed with HIP
-events on its own stream inside the library and reported as a roofline
-fraction; the CPU oracle is timed on a bounded sample on the host.
+pointers, per step, divided by the step time).  The dominant kernel (the
+Gaussian product; for this sparse workload k_gauss_sparse, bound by the
+VALU work of drawing G) is timed with HIP events on its own stream inside
+the library and reported as a roofline fraction; the CPU oracle is timed on
+a bounded sample on the host.
 """
 from __future__ import annotations
 
@@ -44,18 +46,27 @@ WORKLOADS = {
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP8_TFLOPS = 5000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-operation
+# per lane per clock (the FP32 FMA rate without packed math, 78.6 TFLOP/s / 2)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU lane-operations per Gaussian sample of the sparse product's G (BF16):
+# a Philox4x32-10 block and its Box-Muller pair of pairs give 4 samples for
+# 20 64-bit multiplies, 20 three-input XORs and 71 further operations
+# (uniforms, 2 log, 2 sqrt, sin/cos polynomials, products), log and sqrt at
+# half rate (+4), and 8 for the rounding to bfloat16: 123 per 4 samples
+VALU_OPS_PER_SAMPLE_BF16 = 123 / 4
 
-# HBM bytes per launch of the Gaussian GEMM from hardware counters
+# HBM bytes per launch of the dominant kernel from hardware counters
 # (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors measured on a copy
 # kernel of known size), valid only for the kernel source they were taken
 # on: the figure is dropped (null) as soon as the source hash differs.
 PMC_TRAFFIC = {
     ("csr-1e6x500", "bf16"): {
-        "source": "paper_2203_02798_amd/csrc/k_gauss_gemm_bf16.hip",
-        "sha256_prefix": "04bb607fce6e8e8f",
-        "fetch_kib": 250140.9, "write_kib": 125141.9,
+        "source": "paper_2203_02798_amd/csrc/k_gauss_sparse.hip",
+        "sha256_prefix": "7b71628d0843992d",
+        "fetch_kib": 23556.6, "write_kib": 31250.0,
         "fetch_scale": 2.000, "write_scale": 1.000,
-        "profile": "profiles/gauss_gemm_bf16_csr-1e6x500_pmc.md",
+        "profile": "profiles/gauss_sparse_bf16_csr-1e6x500_pmc.md",
     },
 }
 
@@ -349,6 +360,7 @@ def main():
             "stage_ms": {k: round(v, 4) for k, v in sorted(per.items())},
             "lsq": {"iters": info["iters"], "status": info["status"], "resid": res},
             "gg_avg_ms": gg_ms / max(gg_n, 1),
+            "sparse_product": "sa_entries" in stats,
         }
 
     paths = [args.prec] if args.prec != "all" else ["f64", "bf16", "fp8"]
@@ -356,10 +368,35 @@ def main():
     head = "bf16" if "bf16" in res else paths[0]
     hr = res[head]
     flops = (2.0 * r - 1.0) * m * d
-    peak = {"f64": PEAK_FP64_TFLOPS, "bf16": PEAK_BF16_TFLOPS,
-            "fp8": PEAK_FP8_TFLOPS}[head]
     gg_avg = hr["gg_avg_ms"]
-    achieved = flops / (gg_avg * 1e-3) / 1e12 if gg_avg > 0 else 0.0
+    if hr["sparse_product"] and head == "bf16":
+        # k_gauss_sparse: bound by the VALU work of drawing G (m r samples)
+        # plus one FMA per (row of G, nonzero of S*A)
+        if kind == "csr":
+            h, _ = api.cs_hash(n, r, seed, device=dev)
+            rows = np.repeat(np.arange(n), np.diff(a.indptr))
+            keys = h.cpu().numpy().astype(np.int64)[rows] * d + a.indices
+            nnz_sa = int(np.unique(keys).size)
+        else:
+            nnz_sa = r * d
+        ops = m * r * VALU_OPS_PER_SAMPLE_BF16 + m * nnz_sa
+        achieved = ops / (gg_avg * 1e-3) / 1e12 if gg_avg > 0 else 0.0
+        roof = {"bound": "alu", "kernel": "k_gauss_sparse", "achieved": achieved,
+                "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-ops/s",
+                "frac": achieved / PEAK_VALU_TOPS,
+                "traffic": pmc_traffic(args.workload, head),
+                "traffic_unit": "bytes per launch", "launch_ms": gg_avg,
+                "ops_per_launch": ops, "samples_per_launch": m * r,
+                "valu_ops_per_sample": VALU_OPS_PER_SAMPLE_BF16,
+                "nnz_sa": nnz_sa, "fma_per_launch": m * nnz_sa}
+    else:
+        peak = {"f64": PEAK_FP64_TFLOPS, "bf16": PEAK_BF16_TFLOPS,
+                "fp8": PEAK_FP8_TFLOPS}[head]
+        achieved = flops / (gg_avg * 1e-3) / 1e12 if gg_avg > 0 else 0.0
+        roof = {"bound": "mfma", "kernel": "gauss_gemm", "achieved": achieved,
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "traffic_unit": "bytes per launch",
+                "launch_ms": gg_avg, "flops_per_launch": flops}
     rec = {
         "metric": "GB/s of A sketched (G·S·A) + LSQ solves/s, p50/p99 latency vs FP64 plain path",
         "value": hr["value"],
@@ -372,8 +409,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": head,
-        "dtype_detail": {"bf16": "Gaussian GEMM bf16 operands with fp32 accumulation; "
-                                 "hash, S*A, Gram, QR, row norms and LSQR in f64",
+        "dtype_detail": {"bf16": "Gaussian product with bf16 G and S*A as two bf16 limbs, "
+                                 "fp32 accumulation; hash, S*A, Gram, QR, row norms and "
+                                 "LSQR in f64",
                          "fp8": "Gaussian GEMM fp8 e4m3 operands (per-128 E8M0 scales) "
                                 "with fp32 accumulation; the rest in f64",
                          "f64": "f64 throughout"}[head],
@@ -388,11 +426,7 @@ def main():
         "sketch_gcs_gbs": hr["sketch_gcs_gbs"],
         "stage_ms": hr["stage_ms"],
         "lsq": hr["lsq"],
-        "roofline": {"bound": "mfma", "kernel": "gauss_gemm", "achieved": achieved,
-                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": pmc_traffic(args.workload, head), "traffic_unit": "bytes per launch",
-                     "launch_ms": gg_avg,
-                     "flops_per_launch": flops},
+        "roofline": roof,
     }
     keys = ("value", "ms_per_step", "solves_per_s", "p50_ms", "p99_ms", "sketch_gcs_gbs",
             "stage_ms", "lsq")
