@@ -12,6 +12,9 @@ Paper passages followed (arXiv 2203.02798):
   batch forms B = S_i*A, draws a fresh Gaussian block G_i and accumulates
   C += G_i*B.  ``csrcgs``/``rmcgs`` (section "Software") scale G by 1/sqrt(m)
   and return S*A when m = 0.
+* Algorithm ``gaussian_sketch`` (section "Gaussian sketching"; ``csrjlt``):
+  C = G*A for an m x n Gaussian G, each row k of A scaled by its own fresh
+  column of normals and added into C.
 
 Readings where the paper leaves the choice open (it uses per-thread STL
 engines, so its streams are not reproducible across thread counts):
@@ -20,7 +23,8 @@ engines, so its streams are not reproducible across thread counts):
   key=(seed mod 2^32, seed div 2^32)); h(i) = floor((x1*2^32 + x0) * r / 2^64)
   (a 64-bit multiply-high range reduction, bias at most r/2^64);
   sigma_i = +1 if x2 is even, else -1.
-* Gaussian: for bucket column b and row a of G, q = b div 4 and
+* Gaussian: for bucket column b (for G*A: row b of A) and row a of G,
+  q = b div 4 and
   x = Philox4x32-10(counter=(q mod 2^32, q div 2^32, a, 1), key as above);
   u_k = (x_k + 1/2) * 2^-32 lies in (0, 1); Box-Muller gives
   z0, z1 = sqrt(-2 ln u0) * (cos, sin)(2 pi u1) and
@@ -151,6 +155,41 @@ def gaussian_block(m, b0, b1, seed):
     return gaussian_normals(m, b0, b1, seed) / np.sqrt(m)
 
 
+def sketch_g(a, m, seed, batch=4096):
+    """C = G*A, G the m x n Gaussian with entries of variance 1/m (Algorithm
+    ``gaussian_sketch``): column i of G, the normals drawn for row i of A,
+    is the one the combined sketch draws for bucket i, so G*A is the
+    combined sketch with S the identity.  Rows of A in batches."""
+    a = _as_f64(a)
+    n, d = a.shape
+    c = np.zeros((m, d))
+    for b0 in range(0, n, batch):
+        b1 = min(n, b0 + batch)
+        blk = a[b0:b1]
+        if sp.issparse(blk):
+            c += np.asarray((blk.T @ gaussian_block(m, b0, b1, seed).T).T)
+        else:
+            c += gaussian_block(m, b0, b1, seed) @ blk
+    return c
+
+
+def sketch_g_literal(a, m, seed):
+    """Algorithm ``gaussian_sketch`` as written, for tiny CSR inputs: for each
+    row k draw its m normals g, then for each stored entry (k, j, v) add
+    g * v to column j of C (one processor, so the block of rows of G is all
+    of it).  Duplicated entries of a row are added one after another."""
+    a = sp.csr_matrix(a, dtype=np.float64)
+    n, d = a.shape
+    c = np.zeros((m, d))
+    for k in range(n):
+        g = gaussian_normals(m, k, k + 1, seed)[:, 0] / np.sqrt(m)
+        for h in range(a.indptr[k], a.indptr[k + 1]):
+            j = a.indices[h]
+            for i in range(m):
+                c[i, j] += g[i] * a.data[h]
+    return c
+
+
 def sketch_gcs(a, m, r, seed, batch=4096):
     """C = G*(S*A) (Algorithm ``countgauss_multiply``): S*A formed once, then
     C accumulated over bucket batches with a fresh block of G each.
@@ -210,20 +249,34 @@ def bf16_limbs(x, nlimbs=2):
     return limbs
 
 
+def gauss_product_bf16_reference(b, m, seed, nlimbs=2, batch=4096):
+    """G*B with G's unscaled normals rounded to bfloat16 and B (r x d, the
+    operand: S*A or A) as its bfloat16 limbs, the product exact in FP64,
+    then scaled by 1/sqrt(m)."""
+    b = np.asarray(b, dtype=np.float64)
+    r = b.shape[0]
+    bq = np.sum(bf16_limbs(b, nlimbs), axis=0)
+    c = np.zeros((m, b.shape[1]))
+    for b0 in range(0, r, batch):
+        b1 = min(r, b0 + batch)
+        zq = to_bf16(gaussian_normals(m, b0, b1, seed))
+        c += zq @ bq[b0:b1]
+    return c / np.sqrt(m)
+
+
 def sketch_gcs_bf16_reference(a, m, r, seed, nlimbs=2, batch=4096):
     """Quantisation-aware reference of the BF16 Gaussian GEMM: the exact (FP64)
     product of the BF16-rounded unscaled normals with the BF16 limb
     decomposition of S*A, then scaled by 1/sqrt(m).  Comparing the device
     result with this isolates the kernel's arithmetic from the format loss."""
-    sa = sketch_cs(a, r, seed)
-    limbs = bf16_limbs(sa, nlimbs)
-    saq = np.sum(limbs, axis=0)
-    c = np.zeros((m, sa.shape[1]))
-    for b0 in range(0, r, batch):
-        b1 = min(r, b0 + batch)
-        zq = to_bf16(gaussian_normals(m, b0, b1, seed))
-        c += zq @ saq[b0:b1]
-    return c / np.sqrt(m)
+    return gauss_product_bf16_reference(sketch_cs(a, r, seed), m, seed, nlimbs, batch)
+
+
+def sketch_g_bf16_reference(a, m, seed, nlimbs=2, batch=4096):
+    """The same for G*A (the operand is A itself)."""
+    a = _as_f64(a)
+    return gauss_product_bf16_reference(a.toarray() if sp.issparse(a) else a, m, seed,
+                                        nlimbs, batch)
 
 
 # ----------------------------------------------------------------------------
@@ -264,17 +317,32 @@ def quantize_e4m3_blocks(x, block=128, axis=0):
     return np.moveaxis(out, 0, axis), exps
 
 
+def gauss_product_fp8_reference(b, m, seed, block=128, batch=4096):
+    """G*B with B (r x d: S*A or A) quantised per column in blocks of `block`
+    rows, the unscaled normals quantised per row of G in the same blocks of
+    columns, their exact (FP64) product scaled by 1/sqrt(m)."""
+    assert batch % block == 0
+    b = np.asarray(b, dtype=np.float64)
+    r = b.shape[0]
+    bq, _ = quantize_e4m3_blocks(b, block, axis=0)
+    c = np.zeros((m, b.shape[1]))
+    for b0 in range(0, r, batch):
+        b1 = min(r, b0 + batch)
+        zq, _ = quantize_e4m3_blocks(gaussian_normals(m, b0, b1, seed), block, axis=1)
+        c += zq @ bq[b0:b1]
+    return c / np.sqrt(m)
+
+
 def sketch_gcs_fp8_reference(a, m, r, seed, block=128, batch=4096):
     """Quantisation-aware reference of the FP8 Gaussian GEMM: S*A quantised
     per column in blocks of `block` buckets, the unscaled normals quantised
     per row in the same bucket blocks, their exact (FP64) product scaled by
     1/sqrt(m)."""
-    assert batch % block == 0
-    sa = sketch_cs(a, r, seed)
-    saq, _ = quantize_e4m3_blocks(sa, block, axis=0)
-    c = np.zeros((m, sa.shape[1]))
-    for b0 in range(0, r, batch):
-        b1 = min(r, b0 + batch)
-        zq, _ = quantize_e4m3_blocks(gaussian_normals(m, b0, b1, seed), block, axis=1)
-        c += zq @ saq[b0:b1]
-    return c / np.sqrt(m)
+    return gauss_product_fp8_reference(sketch_cs(a, r, seed), m, seed, block, batch)
+
+
+def sketch_g_fp8_reference(a, m, seed, block=128, batch=4096):
+    """The same for G*A (blocks of `block` rows of A)."""
+    a = _as_f64(a)
+    return gauss_product_fp8_reference(a.toarray() if sp.issparse(a) else a, m, seed,
+                                       block, batch)

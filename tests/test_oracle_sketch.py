@@ -283,3 +283,68 @@ def test_fp8_reference_within_rounding_bound():
     assert np.all(np.abs(cq - c) <= bound * (1 + 1e-12) + 1e-13 * np.abs(c).max())
     rel = np.linalg.norm(cq - c) / np.linalg.norm(c)
     assert 5e-3 < rel < 1e-1
+
+
+# ---------------------------------------------------------------------------
+# G*A (Algorithm gaussian_sketch, csrjlt)
+# ---------------------------------------------------------------------------
+def _csr_with_duplicates():
+    """Tiny CSR with empty rows, unsorted columns and a duplicated entry."""
+    indptr = np.array([0, 2, 2, 5, 6, 6, 8])
+    indices = np.array([3, 0, 1, 4, 1, 2, 4, 0])
+    data = np.array([1.5, -2.0, 0.5, 3.0, -1.0, 2.5, 1.0, -0.75])
+    return sp.csr_matrix((data, indices, indptr), shape=(6, 5))
+
+
+def test_sketch_g_matches_algorithm_loops():
+    """The batched matrix form equals Algorithm gaussian_sketch's loops (a
+    fresh column of normals per row of A, entries added one by one)."""
+    a = _csr_with_duplicates()
+    c = osk.sketch_g(a, 7, seed=3)
+    np.testing.assert_allclose(c, osk.sketch_g_literal(a, 7, seed=3), rtol=1e-14, atol=1e-15)
+    b = synth.csr_uniform(200, 9, 0.3, seed=2)
+    np.testing.assert_allclose(osk.sketch_g(b, 5, seed=8, batch=17),
+                               osk.sketch_g_literal(b, 5, seed=8), rtol=1e-12, atol=1e-13)
+    # dense input, different batch size: same matrix
+    np.testing.assert_allclose(osk.sketch_g(b.toarray(), 5, seed=8, batch=64),
+                               osk.sketch_g(b, 5, seed=8), rtol=1e-12, atol=1e-13)
+
+
+def test_sketch_g_is_the_combined_sketch_with_identity():
+    """G*(S*A) through sketch_g on the r-row matrix S*A is the combined sketch:
+    both draw column b of G for bucket (row) b."""
+    a = synth.dense_gaussian(400, 6, seed=1)
+    r, m = 90, 11
+    np.testing.assert_allclose(osk.sketch_g(osk.sketch_cs(a, r, 4), m, 4),
+                               osk.sketch_gcs(a, m, r, 4), rtol=1e-12, atol=1e-12)
+
+
+def test_sketch_g_embedding_in_expectation():
+    """E[C^T C] = A^T A for C = G*A, G with variance 1/m (Monte Carlo)."""
+    a = synth.dense_gaussian(30, 3, seed=6)
+    m, T = 8, 800
+    acc = np.zeros((3, 3))
+    for s in range(T):
+        c = osk.sketch_g(a, m, seed=s)
+        acc += c.T @ c
+    ata = a.T @ a
+    # the entries' standard error is about sqrt(2/(m T)) of the diagonal scale
+    assert np.abs(acc / T - ata).max() <= 6 * np.sqrt(2.0 / (m * T)) * np.abs(np.diag(ata)).max()
+
+
+def test_sketch_g_quantised_references_within_bounds():
+    a = synth.csr_uniform(900, 10, 0.2, seed=3)
+    ad = a.toarray()
+    m, seed = 16, 5
+    c = osk.sketch_g(a, m, seed)
+    z = osk.gaussian_normals(m, 0, 900, seed)
+    mag = np.abs(z) @ np.abs(ad) / np.sqrt(m)
+    cb = osk.sketch_g_bf16_reference(a, m, seed)
+    assert np.all(np.abs(cb - c) <= mag * (2.0 ** -8 + 2.0 ** -16 + 2.0 ** -24 + 1e-13))
+    c8 = osk.sketch_g_fp8_reference(a, m, seed)
+    zq, ez = osk.quantize_e4m3_blocks(z, 128, axis=1)
+    aq, ea = osk.quantize_e4m3_blocks(ad, 128, axis=0)
+    np.testing.assert_allclose(c8, zq @ aq / np.sqrt(m), rtol=1e-12, atol=1e-14)
+    # 900 = 7 * 128 + 4: the last block holds rows 896 .. 899, and its scale
+    # is taken over those rows only
+    np.testing.assert_array_equal(ea[-1], osk.e8m0_exponent(np.abs(ad[896:]).max(axis=0)))
