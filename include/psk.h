@@ -121,7 +121,8 @@ enum {
   PSK_OP_GRAM = 2,
   PSK_OP_ROWNORMS = 3,
   PSK_OP_QR = 4,
-  PSK_OP_LSQ = 5
+  PSK_OP_LSQ = 5,
+  PSK_OP_SKETCH_G = 6
 };
 
 /* Library version string (static storage). */
@@ -134,9 +135,10 @@ const char *psk_last_error(void);
 /* Minimum workspace, in bytes, for one call of `op`.
  *   A    : the matrix the call will get (for PSK_OP_QR only A->n = m rows and
  *          A->d = d columns of the sketch are read);
- *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ);
+ *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ; SKETCH_G
+ *          reads m only);
  *   k    : columns of B (ROWNORMS);
- *   prec : PSK_PREC_* (SKETCH_GCS, LSQ).
+ *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ).
  * For PSK_OP_LSQ, m == 0 sizes a call that passes its own opts->Rinv.
  * Arguments an op does not use are ignored. */
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r,
@@ -169,6 +171,25 @@ int sketch_cs(const psk_mat *A, int64_t r, uint64_t seed, void *SA,
  * Errors: as sketch_cs, plus PSK_EDTYPE for an unknown prec. */
 int sketch_gcs(const psk_mat *A, int64_t m, int64_t r, uint64_t seed,
                int prec, void *C, void *ws, size_t ws_bytes, void *stream);
+
+/* C = G*A (section "Gaussian sketching", Algorithm gaussian_sketch; csrjlt),
+ * G the m x n Gaussian matrix with entries of variance 1/m.  Column i of G
+ * is the column sketch_gcs draws for bucket i (same seed), so sketch_g(A)
+ * is sketch_gcs with S the n x n identity.
+ *   m    : rows of G (1 <= m < 2^31).
+ *   prec : PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8: the operand formats
+ *          of sketch_gcs with A in the place of S*A (FP8 scale blocks: 128
+ *          rows of A per column, 128 columns of G per row).
+ *   C    : m x d row-major FP64 (device, written entirely; csrjlt returns
+ *          the column-major layout, every result of this library is
+ *          row-major).
+ * Dense A: the Gaussian GEMM with A as its operand (its rows are copied to
+ * a contiguous workspace first when ld > d).  CSR A: the product over the
+ * stored entries of A (duplicates summed), 2 nnz(A) m flops, G drawn once.
+ * Errors: PSK_EINVAL (shapes, m out of range, NULL pointers), PSK_EDTYPE
+ * (prec), PSK_EUNSUPPORTED (CSR with d > 1023 or nnz >= 2^31), PSK_ENOMEM. */
+int sketch_g(const psk_mat *A, int64_t m, uint64_t seed, int prec, double *C,
+             void *ws, size_t ws_bytes, void *stream);
 
 /* C <- alpha*A^T*A + beta*C (Algorithm gram; csrrk).  C is d x d row-major in
  * the dtype of A, both triangles written.  beta == 0 ignores C's previous

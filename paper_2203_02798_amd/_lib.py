@@ -24,10 +24,10 @@ PSK_DENSE, PSK_CSR = 0, 1
 PSK_F64, PSK_F32 = 0, 1
 PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 (PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
- PSK_OP_LSQ) = range(6)
+ PSK_OP_LSQ, PSK_OP_SKETCH_G) = range(7)
 
 EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
-            "sketch_cs", "sketch_gcs", "gram", "rownorms_sq", "sketch_qr",
+            "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq", "sketch_qr",
             "lsq_solve", "psk_timing_enable", "psk_timing_reset",
             "psk_timing_collect", "psk_timing_names", "psk_server_create",
             "psk_server_submit", "psk_server_wait", "psk_server_poll",
@@ -141,6 +141,8 @@ _SIGS = {
     "sketch_cs": ([_PM, _i64, _u64, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "sketch_gcs": ([_PM, _i64, _i64, _u64, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp],
                    ctypes.c_int),
+    "sketch_g": ([_PM, _i64, _u64, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp],
+                 ctypes.c_int),
     "gram": ([_dbl, _PM, _dbl, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "rownorms_sq": ([_dbl, _PM, _vp, _i64, _dbl, _vp, _vp, ctypes.c_size_t, _vp],
                     ctypes.c_int),

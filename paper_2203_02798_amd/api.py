@@ -14,7 +14,7 @@ import torch
 from . import _lib as L
 
 __all__ = [
-    "CsrMatrix", "cs_hash", "sketch_cs", "sketch_gcs", "gram", "rownorms_sq",
+    "CsrMatrix", "cs_hash", "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq",
     "sketch_qr", "lsq_solve", "workspace_size", "version", "PskError", "Server",
 ]
 
@@ -151,6 +151,19 @@ def sketch_gcs(A, m, r, seed, prec="f64", out=None):
     ws = _ws(nbytes, dev)
     L.check(L.lib().sketch_gcs(ctypes.byref(pm), m, r, seed, _PREC[prec], out.data_ptr(),
                                ws.data_ptr(), ws.numel(), _stream(dev)), "sketch_gcs")
+    return out
+
+
+def sketch_g(A, m, seed, prec="f64", out=None):
+    """G*A (m x d, float64), G the m x n Gaussian of variance 1/m."""
+    pm = _mat(A)
+    dev = _device(A)
+    if out is None:
+        out = torch.empty((m, pm.d), dtype=torch.float64, device=dev)
+    nbytes = workspace_size(L.PSK_OP_SKETCH_G, A, m=m, prec=prec)
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().sketch_g(ctypes.byref(pm), m, seed, _PREC[prec], out.data_ptr(),
+                             ws.data_ptr(), ws.numel(), _stream(dev)), "sketch_g")
     return out
 
 

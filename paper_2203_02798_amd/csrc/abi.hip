@@ -138,6 +138,31 @@ int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int pre
   return gauss_gemm(m, r, A.d, seed, prec, SA, A.dtype, (double *)C, ws, st);
 }
 
+int do_sketch_g(const psk_mat &A, int64_t m, uint64_t seed, int prec, double *C, Arena &ws,
+                hipStream_t st) {
+  if (A.format == PSK_CSR) {
+    if (!gauss_sparse_fits(A))
+      return fail(PSK_EUNSUPPORTED, "sketch_g of CSR A needs d <= 1023 and nnz < 2^31");
+    uint32_t *perm = nullptr, *bptr = nullptr;
+    int rc = identity_bins(A.n, ws, &perm, &bptr, st);
+    if (rc) return rc;
+    return gauss_gemm_sparse(m, A.n, A, perm, bptr, seed, prec, C, ws, st);
+  }
+  const void *op = A.values;
+  if (A.ld != A.d) {
+    // the GEMM reads its operand with row stride d
+    const size_t es = elem_size(A.dtype);
+    void *cp = ws.take<unsigned char>((size_t)A.n * A.d * es);
+    if (!ws.dry()) {
+      if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for sketch_g");
+      PSK_HIP_TRY(hipMemcpy2DAsync(cp, (size_t)A.d * es, A.values, (size_t)A.ld * es,
+                                   (size_t)A.d * es, (size_t)A.n, hipMemcpyDeviceToDevice, st));
+    }
+    op = cp;
+  }
+  return gauss_gemm(m, A.n, A.d, seed, prec, op, A.dtype, C, ws, st);
+}
+
 }  // namespace psk
 
 using namespace psk;
@@ -229,6 +254,10 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
       rc = lsq_impl(*A, nullptr, nullptr, o, nullptr, ws, nullptr);
       break;
     }
+    case PSK_OP_SKETCH_G:
+      if (m < 1 || m >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "m must be in [1, 2^31)");
+      rc = do_sketch_g(*A, m, 0, prec, nullptr, ws, nullptr);
+      break;
     default:
       return fail(PSK_EINVAL, "unknown op");
   }
@@ -274,6 +303,22 @@ int sketch_gcs(const psk_mat *A, int64_t m, int64_t r, uint64_t seed, int prec,
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_GCS)");
   Arena ws = Arena::over(wsp, ws_bytes);
   return do_sketch_gcs(*A, m, r, seed, prec, C, ws, as_stream(stream));
+}
+
+int sketch_g(const psk_mat *A, int64_t m, uint64_t seed, int prec, double *C, void *wsp,
+             size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if (m < 1 || m >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "m must be in [1, 2^31)");
+  if (prec != PSK_PREC_F64 && prec != PSK_PREC_BF16 && prec != PSK_PREC_FP8)
+    return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
+  if (!C) return fail(PSK_EINVAL, "C is NULL");
+  Arena plan;
+  if ((rc = do_sketch_g(*A, m, seed, prec, nullptr, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_G)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return do_sketch_g(*A, m, seed, prec, C, ws, as_stream(stream));
 }
 
 int gram(double alpha, const psk_mat *A, double beta, void *C, void *wsp,

@@ -92,6 +92,10 @@ int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws
                  hipStream_t st);
 int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec,
                   void *C, Arena &ws, hipStream_t st);
+// C = G*A (sketch_g): the Gaussian GEMM with A as operand (dense), or the
+// sparse product over A's entries with one row per bucket (CSR)
+int do_sketch_g(const psk_mat &A, int64_t m, uint64_t seed, int prec, double *C, Arena &ws,
+                hipStream_t st);
 
 // ---- Gaussian GEMM (k_gauss_gemm.hip) --------------------------------------
 // C (m x d, FP64) = G (m x r) * SA (r x d, dtype sa_dtype), G generated.
@@ -125,6 +129,11 @@ int gauss_gemm_fp8_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *p
 // below 1/1024 dense: its contraction costs less than the sparse FP64 updates).
 bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m);
 bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec);
+// the product's own limits (CSR, d <= 1023, sizes); gauss_gemm_sparse checks
+// only these, the callers choose when it is worth taking
+bool gauss_sparse_fits(const psk_mat &A);
+// one row per bucket, in row order, sign +1: the bins of S = identity
+int identity_bins(int64_t n, Arena &ws, uint32_t **perm, uint32_t **bptr, hipStream_t st);
 int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
                       const uint32_t *bptr, uint64_t seed, int prec, double *C, Arena &ws,
                       hipStream_t st);

@@ -603,6 +603,14 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
   }
 }
 
+// perm[j] = j (sign +1), bptr[b] = b: bucket b holds row b alone
+__global__ __launch_bounds__(256) void k_identity_bins(int64_t n, uint32_t *__restrict__ perm,
+                                                       uint32_t *__restrict__ bptr) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j < n) perm[j] = (uint32_t)j;
+  if (j <= n) bptr[j] = (uint32_t)j;
+}
+
 // C[i] = scale * sum_s part[s][i], splits in order
 __global__ __launch_bounds__(256) void k_sparse_reduce(const double *__restrict__ part,
                                                        int64_t len, int splits, double scale,
@@ -616,15 +624,31 @@ __global__ __launch_bounds__(256) void k_sparse_reduce(const double *__restrict_
 
 }  // namespace
 
-bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m) {
-  if (A.format != PSK_CSR || m <= 0) return false;
+bool gauss_sparse_fits(const psk_mat &A) {
+  if (A.format != PSK_CSR) return false;
   // the dense bucket rows of the entry kernel: 4 x d accumulators in 64 KiB of LDS
   if ((size_t)4 * ((A.d + 3) & ~(int64_t)3) * elem_size(A.dtype) > 65536) return false;
   if (A.d > 1023) return false;
-  if (A.nnz >= ((int64_t)1 << 31) || A.n >= ((int64_t)1 << 31)) return false;
+  return A.nnz < ((int64_t)1 << 31) && A.n < ((int64_t)1 << 31);
+}
+
+bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m) {
+  if (m <= 0 || !gauss_sparse_fits(A)) return false;
+  // S*A from the binned rows has the bits of S*A from cs_apply when no
+  // bucket's rows are split
   if (cs_splits(A.n, r) != 1) return false;
   // S*A sparse enough: at most one nonzero in 32 of its r x d entries
   return A.nnz * 32 <= r * A.d;
+}
+
+int identity_bins(int64_t n, Arena &ws, uint32_t **perm, uint32_t **bptr, hipStream_t st) {
+  *perm = ws.take<uint32_t>((size_t)n + 1);
+  *bptr = ws.take<uint32_t>((size_t)n + 1);
+  if (ws.dry()) return 0;
+  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the bins of G*A");
+  k_identity_bins<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(n, *perm, *bptr);
+  PSK_HIP_TRY(hipGetLastError());
+  return 0;
 }
 
 bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec) {
@@ -638,8 +662,8 @@ bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec) {
 int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
                       const uint32_t *bptr, uint64_t seed, int prec, double *C, Arena &ws,
                       hipStream_t st) {
-  if (!gauss_sparse_ok(A, r, m))
-    return fail(PSK_EUNSUPPORTED, "sparse Gaussian product: CSR, d <= 1023, S*A sparse");
+  if (m <= 0 || !gauss_sparse_fits(A))
+    return fail(PSK_EUNSUPPORTED, "sparse Gaussian product: CSR, d <= 1023, nnz < 2^31");
   const int64_t n = A.n, d = A.d;
   const int mtr = d <= 512 ? 32 : 16;
   const int tiles_m = (int)ceil_div(m, mtr);

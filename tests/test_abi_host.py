@@ -86,6 +86,18 @@ def test_workspace_planning(lib):
     assert st == -1
     st, _ = _ws(L.PSK_OP_SKETCH_CS, _dense(5000, 32), r=0)
     assert st == -1
+    # G*A: dense A is the GEMM operand in place (a contiguous copy when
+    # ld > d); CSR A stages its entries and one bin per row
+    st, g1 = _ws(L.PSK_OP_SKETCH_G, _dense(20000, 50), m=200)
+    assert st == 0 and g1 < 20000 * 50 * 8
+    st, g2 = _ws(L.PSK_OP_SKETCH_G, _dense(20000, 50, ld=64), m=200)
+    assert st == 0 and g2 >= g1 + 20000 * 50 * 8
+    st, g3 = _ws(L.PSK_OP_SKETCH_G, _csr(1_000_000, 500, 500_000), m=1000)
+    assert st == 0 and g3 >= 500_000 * 28 + 2 * 1_000_000 * 4
+    st, _ = _ws(L.PSK_OP_SKETCH_G, _csr(1000, 2000, 100), m=10)
+    assert st == -7  # CSR with d > 1023
+    st, _ = _ws(L.PSK_OP_SKETCH_G, _dense(100, 5), m=0)
+    assert st == -1
 
 
 def test_rejects_bad_arguments_without_device_work(lib):
@@ -104,6 +116,10 @@ def test_rejects_bad_arguments_without_device_work(lib):
     assert lib.sketch_cs(ctypes.byref(good), 4, 0, sa, ws, 16, stream) == -3
     assert lib.sketch_gcs(ctypes.byref(good), -1, 4, 0, 0, sa, ws, 1 << 20, stream) == -1
     assert lib.sketch_gcs(ctypes.byref(good), 3, 4, 0, 9, sa, ws, 1 << 20, stream) == -2
+    assert lib.sketch_g(ctypes.byref(good), 0, 0, 0, sa, ws, 1 << 20, stream) == -1
+    assert lib.sketch_g(ctypes.byref(good), 3, 0, 5, sa, ws, 1 << 20, stream) == -2
+    assert lib.sketch_g(ctypes.byref(good), 3, 0, 0, None, ws, 1 << 20, stream) == -1
+    assert lib.sketch_g(ctypes.byref(good), 3, 0, 0, sa, ws, 16, stream) == -3
     assert lib.cs_hash(0, 10, 0, 0, None, None, stream) == -1
     assert lib.cs_hash(-1, 10, 5, 0, None, None, stream) == -1
     assert lib.sketch_qr(sa, 3, 5, sa, sa, ws, 1 << 20, stream) == -1

@@ -227,6 +227,63 @@ def test_sketch_gcs_fp8_deterministic(api):
     assert torch.equal(c1, c2)
 
 
+# ---------------------------------------------------------------------------
+# G*A (Gaussian-only sketch, csrjlt)
+# ---------------------------------------------------------------------------
+def _g_input(kind, n, d):
+    """'dense', 'dense32', 'dense_ld' (row stride > d), 'csr[:density]',
+    'csr32' (FP32 values)."""
+    if kind == "dense_ld":
+        full = synth.dense_gaussian(n, d + 11, seed=2)
+        return full[:, :d], torch.from_numpy(full).cuda()[:, :d]
+    if kind == "csr32":
+        a = synth.csr_uniform(n, d, 2e-3, seed=2, dtype=np.float32)
+        return a, to_device(a)
+    a = _gcs_input(kind, n, d)
+    return a, to_device(a)
+
+
+@pytest.mark.parametrize("kind,n,d,m", [
+    ("dense", 20000, 50, 200),
+    ("dense_ld", 5000, 37, 77),
+    ("dense32", 8000, 96, 129),
+    ("csr", 100000, 500, 300),
+    ("csr:2e-2", 20000, 700, 77),        # d > 512; rows of ~14 entries
+    ("csr32", 50000, 200, 100)])
+def test_sketch_g_f64(api, kind, n, d, m):
+    _say(f"sketch_g f64 {kind} n={n} d={d} m={m}")
+    a, ad = _g_input(kind, n, d)
+    c = api.sketch_g(ad, m, seed=13).cpu().numpy()
+    err = rel_fro(c, osk.sketch_g(a, m, 13))
+    _say(f"  rel err {err:.3e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("prec,tol_arith,tol_fmt", [("bf16", 1e-4, 1e-2), ("fp8", 5e-4, 1e-1)])
+@pytest.mark.parametrize("kind,n,d,m", [
+    ("dense", 20000, 50, 200),
+    ("csr", 40000, 300, 150),
+    ("csr:2e-2", 20000, 700, 77)])
+def test_sketch_g_reduced(api, prec, tol_arith, tol_fmt, kind, n, d, m):
+    _say(f"sketch_g {prec} {kind} n={n} d={d} m={m}")
+    a, ad = _g_input(kind, n, d)
+    c = api.sketch_g(ad, m, seed=13, prec=prec).cpu().numpy()
+    ref = (osk.sketch_g_bf16_reference if prec == "bf16" else osk.sketch_g_fp8_reference)
+    e_arith = rel_fro(c, ref(a, m, 13))
+    e_fmt = rel_fro(c, osk.sketch_g(a, m, 13))
+    _say(f"  vs quantised reference {e_arith:.3e}, vs FP64 {e_fmt:.3e}")
+    assert e_arith <= tol_arith
+    assert e_fmt <= tol_fmt
+
+
+def test_sketch_g_deterministic(api):
+    a = to_device(synth.csr_uniform(50000, 200, 5e-3, seed=3))
+    for prec in ("f64", "bf16", "fp8"):
+        c1 = api.sketch_g(a, 150, seed=5, prec=prec)
+        c2 = api.sketch_g(a, 150, seed=5, prec=prec)
+        assert torch.equal(c1, c2), prec
+
+
 @pytest.mark.parametrize("kind,cond,want", [("dense", 1.0, "fp8"), ("dense", 1e3, "f64"),
                                             ("csr", 1.0, "fp8"), ("csr", 1e3, "f64")])
 def test_lsq_solve_fp8_sketch(api, kind, cond, want):
