@@ -294,10 +294,12 @@ __global__ __launch_bounds__(512) void k_scatter_csr_fp8(
   }
 }
 
+template <bool TAIL>
 __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
-    int64_t m, int64_t d, int64_t npad, uint64_t seed, const unsigned char *__restrict__ q,
-    const unsigned char *__restrict__ sc, int tiles_m, int tiles_n, int64_t kchunks,
-    int64_t cper, float *__restrict__ out /* [splits][m][d] */) {
+    int64_t m, int64_t d, int64_t r, int64_t npad, uint64_t seed,
+    const unsigned char *__restrict__ q, const unsigned char *__restrict__ sc, int tiles_m,
+    int tiles_n, int64_t c0, int64_t kend, int64_t cper, int ks0,
+    float *__restrict__ out /* [splits][m][d] */) {
   __shared__ __align__(16) unsigned char smem[2 * kBufBytes];
 
   const int64_t nblk = (int64_t)gridDim.x;
@@ -309,9 +311,9 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
   const int ks = (int)(rest / tiles_n);
   const int64_t m0 = (int64_t)mt * kBM;
   const int64_t n0 = (int64_t)nt * kBN;
-  const int64_t cb = (int64_t)ks * cper;
+  const int64_t cb = c0 + (int64_t)ks * cper;
   int64_t ce = cb + cper;
-  if (ce > kchunks) ce = kchunks;
+  if (ce > kend) ce = kend;
   const int64_t nch = ce > cb ? ce - cb : 0;
 
   const int tid = threadIdx.x;
@@ -357,12 +359,21 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
 
   const uint32_t row_a = (uint32_t)(m0 + wave * 16 + li);
   // this lane's 32 normals of chunk c (buckets 128 c + 32 g + j), quantised
-  // with the row's block scale; returns the fragment and sets the E8M0 byte
+  // with the row's block scale; returns the fragment and sets the E8M0 byte.
+  // TAIL (the launch of the chunk that holds bucket r): G ends at bucket r,
+  // so the values from there on are zero and the block scale is taken over
+  // the buckets that exist.
   auto make_a = [&](int64_t c_abs, int &sbyte) {
     float z[32];
     const uint64_t qb = (uint64_t)c_abs * 32u + 8u * (uint64_t)g;
 #pragma unroll
     for (int t = 0; t < 8; ++t) gauss4_f32(qb + t, row_a, seed, z + 4 * t);
+    if (TAIL) {
+      const int64_t valid = r - (int64_t)(4 * qb);
+#pragma unroll
+      for (int j = 0; j < 32; ++j)
+        if (j >= valid) z[j] = 0.0f;
+    }
     float amax = 0.0f;
 #pragma unroll
     for (int j = 0; j < 32; ++j) amax = fmaxf(amax, fabsf(z[j]));
@@ -432,7 +443,7 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
   }
 
   // accumulator element e of block nb: row 4 g + e, column li
-  float *o = out + (int64_t)ks * m * d;
+  float *o = out + (int64_t)(ks0 + ks) * m * d;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int64_t row = m0 + wave * 16 + 4 * g + e;
@@ -461,25 +472,31 @@ __global__ __launch_bounds__(256) void k_reduce_fp8(const float *__restrict__ pa
 namespace {
 
 // Tiling, K split and workspace of one FP8 product (bytes, scales, partials).
+// K is cut into kfull whole 128-bucket chunks, split splits_main ways, and,
+// when 128 does not divide r, the tail chunk as one more split of its own
+// (the one launch that masks G past bucket r).
 struct Fp8Plan {
   int tiles_m, tiles_n;
-  int64_t npad, kchunks, tiles, splits, cper;
+  int64_t r, npad, kchunks, kfull, tiles, splits, splits_main, cper;
   unsigned char *q, *sc;
   float *part;
 };
 
 int fp8_plan(int64_t m, int64_t r, int64_t d, Arena &ws, Fp8Plan &P) {
+  P.r = r;
   P.tiles_m = (int)ceil_div(m, kBM);
   P.tiles_n = (int)ceil_div(d, kBN);
   P.npad = (int64_t)P.tiles_n * kBN;
   P.kchunks = ceil_div(r, kBK);
+  P.kfull = r / kBK;
   P.tiles = (int64_t)P.tiles_m * P.tiles_n;
   int64_t splits = ceil_div(512, P.tiles);
-  const int64_t max_splits = P.kchunks / 8 > 0 ? P.kchunks / 8 : 1;
+  const int64_t max_splits = P.kfull / 8 > 0 ? P.kfull / 8 : 1;
   if (splits > max_splits) splits = max_splits;
   if (splits < 1) splits = 1;
-  P.cper = ceil_div(P.kchunks, splits);
-  P.splits = ceil_div(P.kchunks, P.cper);
+  P.cper = P.kfull > 0 ? ceil_div(P.kfull, splits) : 1;
+  P.splits_main = P.kfull > 0 ? ceil_div(P.kfull, P.cper) : 0;
+  P.splits = P.splits_main + (P.kfull < P.kchunks ? 1 : 0);
   if ((P.cper + 1) * 8 * P.npad * 16 + 65536 >= ((int64_t)1 << 31))
     return fail(PSK_EUNSUPPORTED, "FP8 Gaussian GEMM: K slice too large for one descriptor");
   P.q = ws.take<unsigned char>((size_t)(P.kchunks * 8 * P.npad * 16));
@@ -494,8 +511,14 @@ int fp8_run(const Fp8Plan &P, int64_t m, int64_t d, uint64_t seed, double *C,
             hipStream_t st) {
   {
     KTimer t("gauss_gemm", st);
-    k_gauss_gemm_fp8<<<(unsigned)(P.tiles * P.splits), kThreads, 0, st>>>(
-        m, d, P.npad, seed, P.q, P.sc, P.tiles_m, P.tiles_n, P.kchunks, P.cper, P.part);
+    if (P.splits_main > 0)
+      k_gauss_gemm_fp8<false><<<(unsigned)(P.tiles * P.splits_main), kThreads, 0, st>>>(
+          m, d, P.r, P.npad, seed, P.q, P.sc, P.tiles_m, P.tiles_n, 0, P.kfull, P.cper, 0,
+          P.part);
+    if (P.kfull < P.kchunks)
+      k_gauss_gemm_fp8<true><<<(unsigned)P.tiles, kThreads, 0, st>>>(
+          m, d, P.r, P.npad, seed, P.q, P.sc, P.tiles_m, P.tiles_n, P.kfull, P.kchunks, 1,
+          (int)P.splits_main, P.part);
   }
   {
     KTimer t("gemm_reduce", st);
