@@ -204,6 +204,32 @@ def serving_bench(api, torch, device, num=64, slots=8, pool_gb=16.0):
     }
 
 
+def gaussian_only_bench(api, torch, A, m, n, d, nnz, seed, steps, warmup):
+    """G*A (sketch_g, the Gaussian-only sketch of CSR A, BF16 G) on the same
+    matrix: m n normals and one FMA per (row of G, nonzero of A), the same
+    kernel as the combined sketch with one bucket per row."""
+    for _ in range(warmup):
+        api.sketch_g(A, m, seed, prec="bf16")
+    torch.cuda.synchronize()
+    with api.kernel_timing() as kt:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            api.sketch_g(A, m, seed, prec="bf16")
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        stats = kt.stats()
+    gg_ms, gg_n = stats.get("gauss_gemm", (0.0, 0))
+    launch = gg_ms / max(gg_n, 1)
+    ops = m * n * VALU_OPS_PER_SAMPLE_BF16 + m * nnz
+    ach = ops / (launch * 1e-3) / 1e12 if launch > 0 else 0.0
+    return {"call": "sketch_g", "prec": "bf16", "m": m, "ms_per_call": 1e3 * wall,
+            "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(stats.items())},
+            "roofline": {"bound": "alu", "kernel": "k_gauss_sparse", "achieved": ach,
+                         "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-ops/s",
+                         "frac": ach / PEAK_VALU_TOPS, "launch_ms": launch,
+                         "samples_per_launch": m * n, "fma_per_launch": m * nnz}}
+
+
 def cpu_baseline(kind, a, b, r, m, seed, budget_s=12.0):
     """The oracle on the host: every stage in full except the Gaussian GEMM,
     whose bucket batches (Algorithm countgauss_multiply) are timed on a
@@ -442,6 +468,9 @@ def main():
             "achieved": flops / (gg * 1e-3) / 1e12 if gg > 0 else 0.0,
             "peak": PEAK_FP8_TFLOPS, "unit": "TFLOP/s",
             "frac": (flops / (gg * 1e-3) / 1e12) / PEAK_FP8_TFLOPS if gg > 0 else 0.0}
+    if head == "bf16" and kind == "csr":
+        rec["gaussian_only"] = gaussian_only_bench(api, torch, A, m, n, d, int(a.nnz), seed,
+                                                   args.steps, args.warmup)
     if not args.no_serving:
         rec["serving"] = serving_bench(api, torch, dev)
     if not args.no_cpu_baseline:
