@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64 * kCsrWaves, 4) void k_pass_csr(
     const double *__restrict__ vhat, const double *__restrict__ rhs,
     double *__restrict__ u, const LsqrState *__restrict__ st,
     double *__restrict__ part_t, double *__restrict__ part_b2) {
-  if (!INIT && st->done) return;
+  const int stop = INIT ? 0 : st->done;  // tested after the first barrier
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *tl = reinterpret_cast<double *>(smem_raw);  // kCsrWaves x d accumulators
   double *vh = tl + kCsrWaves * d;                     // vhat, d
@@ -149,6 +149,7 @@ __global__ __launch_bounds__(64 * kCsrWaves, 4) void k_pass_csr(
   if (!INIT)
     for (int64_t c = threadIdx.x; c < d; c += 64 * kCsrWaves) vh[c] = vhat[c];
   __syncthreads();
+  if (stop) return;  // uniform per workgroup; nothing global written yet
   double *tw = tl + (int64_t)wave * d;
   const double au = INIT ? 0.0 : st->alpha * st->ufac;
   double b2 = 0.0;
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kVThreads) void k_vnew_rows(
     const double *__restrict__ part_t, const double *__restrict__ part_b2,
     const double *__restrict__ Rinv, int64_t d, LsqrState *__restrict__ st,
     double *__restrict__ vpart, int init) {
-  if (!init && st->done) return;
+  const int stop = init ? 0 : st->done;  // tested after the first barrier
   __shared__ double red[kVGroups][kVRows + 1];
   __shared__ double tv[kVRows];
   __shared__ double bred[kVThreads / 64];
@@ -448,6 +449,7 @@ __global__ __launch_bounds__(kVThreads) void k_vnew_rows(
   for (int q = 0; q < kPassBlocks / kVGroups; ++q) ts += pt[q];
   red[g][c] = i < d ? ts : 0.0;
   __syncthreads();
+  if (stop) return;  // uniform per workgroup; nothing written yet
   double b2 = bred[0];
 #pragma unroll
   for (int w = 1; w < kVThreads / 64; ++w) b2 += bred[w];
@@ -475,15 +477,21 @@ __global__ __launch_bounds__(kVThreads) void k_vnew_rows(
 }
 
 // scalar recurrences, v/w/y updates and the stopping test (run by one
-// whole workgroup of 256 threads)
-__device__ void lsqr_update(LsqrState *__restrict__ st, int64_t d, double *__restrict__ v,
-                            const double *__restrict__ vnew, double *__restrict__ w,
-                            double *__restrict__ y, double alpha, double atol, double btol,
-                            int init) {
+// whole workgroup of 256 threads).  ss is the workgroup's LDS copy of the
+// state, loaded at the kernel's start; wp, yp the thread's first kUpdPre
+// entries of w and y (j = tid + 256 q), likewise loaded early, so that
+// nothing here waits on memory but the few entries of d > 256 kUpdPre.
+constexpr int kUpdPre = 4;
+
+__device__ void lsqr_update(LsqrState *__restrict__ st, const LsqrState &ss, int64_t d,
+                            double *__restrict__ v, const double *__restrict__ vnew,
+                            double *__restrict__ w, double *__restrict__ y,
+                            const double (&wp)[kUpdPre], const double (&yp)[kUpdPre],
+                            double alpha, double atol, double btol, int init) {
   __shared__ double sh[8];
   __shared__ double red[4];
   if (threadIdx.x == 0) {
-    const double beta = st->beta_new;
+    const double beta = ss.beta_new;
     double phi = 0.0, rho = 1.0, theta = 0.0;
     int done = 0;
     if (init) {
@@ -494,24 +502,26 @@ __device__ void lsqr_update(LsqrState *__restrict__ st, int64_t d, double *__res
       st->iters = 0;
       if (beta == 0.0 || alpha == 0.0) done = 1;
     } else {
-      st->anorm2 += st->alpha * st->alpha + beta * beta;
-      const double rhobar = st->rhobar;
+      const double anorm2 = ss.anorm2 + ss.alpha * ss.alpha + beta * beta;
+      st->anorm2 = anorm2;
+      const double rhobar = ss.rhobar;
       rho = sqrt(rhobar * rhobar + beta * beta);
       const double c = rhobar / rho;
       const double s = beta / rho;
       theta = s * alpha;
       st->rhobar = -c * alpha;
-      phi = c * st->phibar;
-      st->phibar = s * st->phibar;
-      st->iters += 1;
-      const double anorm = sqrt(st->anorm2);
-      const double rnorm = st->phibar;
+      phi = c * ss.phibar;
+      const double phibar = s * ss.phibar;
+      st->phibar = phibar;
+      st->iters = ss.iters + 1;
+      const double anorm = sqrt(anorm2);
+      const double rnorm = phibar;
       const double arnorm = rnorm * alpha * fabs(c);
       st->rnorm = rnorm;
       st->arnorm = arnorm;
       st->test2 = (anorm > 0.0 && rnorm > 0.0) ? arnorm / (anorm * rnorm) : 0.0;
       if (arnorm <= atol * anorm * rnorm) done = 1;
-      if (rnorm <= btol * st->bnorm + atol * anorm * sqrt(st->ynorm2)) done = 1;
+      if (rnorm <= btol * ss.bnorm + atol * anorm * sqrt(ss.ynorm2)) done = 1;
       if (alpha == 0.0 || beta == 0.0) done = 1;
     }
     st->alpha = alpha;
@@ -524,20 +534,25 @@ __device__ void lsqr_update(LsqrState *__restrict__ st, int64_t d, double *__res
   __syncthreads();
   const double ainv = sh[0], fx = sh[1], fw = sh[2];
   double y2 = 0.0;
-  for (int64_t j = threadIdx.x; j < d; j += 256) {
+  auto step = [&](int64_t j, double wj, double yj0) {
     const double vj = vnew[j] * ainv;
     if (init) {
       w[j] = vj;
       y[j] = 0.0;
     } else {
-      const double wj = w[j];
-      const double yj = y[j] + fx * wj;
+      const double yj = yj0 + fx * wj;
       y[j] = yj;
       y2 += yj * yj;
       w[j] = vj - fw * wj;
     }
     v[j] = vj;
+  };
+#pragma unroll
+  for (int q = 0; q < kUpdPre; ++q) {
+    const int64_t j = threadIdx.x + 256 * q;
+    if (j < d) step(j, wp[q], yp[q]);
   }
+  for (int64_t j = threadIdx.x + 256 * kUpdPre; j < d; j += 256) step(j, w[j], y[j]);
   y2 = wave_sum(y2);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = y2;
   __syncthreads();
@@ -690,13 +705,37 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ Rinv,
                                                 double *__restrict__ w, double *__restrict__ y,
                                                 double *__restrict__ vhat, double atol,
                                                 double btol, int init) {
-  if (!init && st->done) return;
+  // the stop flag is read now and tested after the first barrier, so that
+  // this launch's loads are already in flight (nothing is written before)
+  const int stop = init ? 0 : st->done;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *vn = reinterpret_cast<double *>(smem_raw);  // vnew, d doubles
   __shared__ double red[kColsPerBlk][kPhases + 1];
   __shared__ double a2red[4];
+  __shared__ LsqrState ss;  // the update workgroup's copy of the state
   const int tid = threadIdx.x;
   const bool upd = (int)blockIdx.x == nb;
+  // the update workgroup loads the state and its w, y entries up front
+  static_assert(sizeof(LsqrState) % 8 == 0 && sizeof(LsqrState) / 8 <= 256, "state words");
+  double wp[kUpdPre], yp[kUpdPre];
+#pragma unroll
+  for (int q = 0; q < kUpdPre; ++q) {
+    wp[q] = 0.0;
+    yp[q] = 0.0;
+  }
+  if (upd) {
+    if (tid < (int)(sizeof(LsqrState) / 8))
+      reinterpret_cast<double *>(&ss)[tid] = reinterpret_cast<const double *>(st)[tid];
+    if (!init) {
+#pragma unroll
+      for (int q = 0; q < kUpdPre; ++q) {
+        const int64_t j = tid + 256 * q;
+        const int64_t jc = j < d ? j : d - 1;
+        wp[q] = w[jc];
+        yp[q] = y[jc];
+      }
+    }
+  }
   const int c = tid >> 5;  // row within the block
   const int g = tid & 31;  // column phase
   const int64_t i = (int64_t)blockIdx.x * kColsPerBlk + c;
@@ -728,9 +767,10 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ Rinv,
   a2 = wave_sum(a2);
   if ((tid & 63) == 0) a2red[tid >> 6] = a2;
   __syncthreads();
+  if (stop) return;  // uniform: every workgroup read the same flag
   const double alpha = sqrt(((a2red[0] + a2red[1]) + a2red[2]) + a2red[3]);
   if (upd) {
-    lsqr_update(st, d, v_out, vn, w, y, alpha, atol, btol, init);
+    lsqr_update(st, ss, d, v_out, vn, w, y, wp, yp, alpha, atol, btol, init);
     return;
   }
   const double ainv = alpha > 0.0 ? 1.0 / alpha : 0.0;
