@@ -1,9 +1,13 @@
 """Least squares min ||A x - b||, plain FP64.
 
-Paper passage followed (arXiv 2203.02798): Algorithm
+Paper passages followed (arXiv 2203.02798): Algorithm
 ``least_squares_precondition`` (sketch-and-precondition): B = G S A, factor B,
 N = the inverse factor, solve min_y ||A N y - b|| with a preconditioned
-iterative method, return x = N y.
+iterative method, return x = N y.  Algorithm ``least_squares_approx``
+(sketch-and-solve): [A~ b~] = G S [A b], x = the least-squares solution of
+A~ x = b~ (the SVD route, here LAPACK's least-squares solver).  Algorithm
+``least_squares_gram`` computes the same x* as ``lstsq`` (from the Gram
+matrix), so ``lstsq`` is its oracle.
 
 Readings: the factor is the R of a QR of the sketch (N = R^{-1}); the
 iterative method, which the paper leaves open, is LSQR (Paige & Saunders,
@@ -29,6 +33,15 @@ def lstsq(a, b):
     x, *_ = np.linalg.lstsq(np.asarray(a, dtype=np.float64),
                             np.asarray(b, dtype=np.float64), rcond=None)
     return x
+
+
+def lsq_sketch_solve(a, b, m, r, seed):
+    """Sketch-and-solve (Algorithm ``least_squares_approx``): the sketch of A
+    and the sketch of b with the same S and G (the same seed), then the
+    least-squares solution of the small m x d problem."""
+    c = sketch_gcs(a, m, r, seed)
+    cb = sketch_gcs(np.asarray(b, dtype=np.float64)[:, None], m, r, seed)[:, 0]
+    return lstsq(c, cb)
 
 
 def _precond_op(a, rr):

@@ -119,3 +119,32 @@ def test_lsq_matches_lapack(cond):
     assert ne < 1e-10
     # a preconditioned LSQR converges in few iterations regardless of cond
     assert info["iters"][0] < 80
+
+
+# ---------------------------------------------------------------------------
+# sketch-and-solve (Algorithm least_squares_approx)
+# ---------------------------------------------------------------------------
+def test_sketch_solve_recovers_consistent_solution():
+    """b in range(A): the sketched system is consistent too, so the sketched
+    least-squares solution is the exact one."""
+    a, b, xt = synth.lsq_problem(3000, 8, cond=1e3, seed=5, noise=0.0)
+    x = olsq.lsq_sketch_solve(a, b, m=40, r=200, seed=3)
+    assert np.linalg.norm(x - xt) / np.linalg.norm(xt) < 1e3 * 1e-12
+
+
+def test_sketch_solve_residual_near_optimal():
+    """||A x~ - b|| >= ||A x* - b|| always (x* minimises it), and for a
+    Gaussian embedding the squared ratio averages about 1 + d / (m - d - 1)
+    (Monte Carlo over seeds, loose bounds)."""
+    a, b, _ = synth.lsq_problem(4000, 6, cond=10.0, seed=6, noise=1.0)
+    xs = olsq.lstsq(a, b)
+    rs = np.linalg.norm(a @ xs - b)
+    m, r = 30, 600
+    ratios = []
+    for s in range(60):
+        x = olsq.lsq_sketch_solve(a, b, m, r, seed=s)
+        ratios.append((np.linalg.norm(a @ x - b) / rs) ** 2)
+    ratios = np.array(ratios)
+    assert np.all(ratios >= 1.0 - 1e-12)
+    expect = 1.0 + 6 / (m - 6 - 1)
+    assert 1.0 + 0.5 * (expect - 1.0) < ratios.mean() < 1.0 + 2.0 * (expect - 1.0)
