@@ -122,7 +122,10 @@ enum {
   PSK_OP_ROWNORMS = 3,
   PSK_OP_QR = 4,
   PSK_OP_LSQ = 5,
-  PSK_OP_SKETCH_G = 6
+  PSK_OP_SKETCH_G = 6,
+  PSK_OP_LEVERAGE_GRAM = 7,
+  PSK_OP_LSQ_GRAM = 8,
+  PSK_OP_LSQ_SKETCH = 9
 };
 
 /* Library version string (static storage). */
@@ -135,10 +138,10 @@ const char *psk_last_error(void);
 /* Minimum workspace, in bytes, for one call of `op`.
  *   A    : the matrix the call will get (for PSK_OP_QR only A->n = m rows and
  *          A->d = d columns of the sketch are read);
- *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ; SKETCH_G
- *          reads m only);
+ *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ,
+ *          LSQ_SKETCH; SKETCH_G reads m only);
  *   k    : columns of B (ROWNORMS);
- *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ).
+ *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ, LSQ_SKETCH).
  * For PSK_OP_LSQ, m == 0 sizes a call that passes its own opts->Rinv.
  * Arguments an op does not use are ignored. */
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r,
@@ -266,6 +269,45 @@ typedef struct psk_lsq_info {
 int lsq_solve(const psk_mat *A, const double *b, double *x,
               const psk_lsq_opts *opts, psk_lsq_info *info,
               void *ws, size_t ws_bytes, void *stream);
+
+/* ---- direct solvers and exact leverage scores ---------------------------
+ * Section 4's Gram-based and sketch-and-solve algorithms.  A triangular
+ * factor stands in for the paper's SVD (A R^{-1} spans the column space of
+ * A V Sigma^{-1} with orthonormal columns, so leverage scores and
+ * least-squares solutions are the same); full column rank is assumed and a
+ * Cholesky pivot that is not positive returns PSK_ERANK (the outputs are
+ * still written).  These calls synchronise the stream once, to read that
+ * pivot flag.  d <= 4096. */
+
+/* theta_i = ||e_i^T A B^{-1/2}||^2, B = A^T A (Algorithm ls_direct): the
+ * exact leverage scores of A, from the FP64 Gram matrix, its Cholesky factor
+ * R and rownorms_sq(A, R^{-1}).  B squares the condition number: the scores
+ * carry an error of about cond(A)^2 u.
+ *   theta : n FP64 (device, written).
+ * Errors: PSK_EINVAL, PSK_EUNSUPPORTED (d > 4096), PSK_ENOMEM, PSK_ERANK. */
+int leverage_gram(const psk_mat *A, double *theta, void *ws, size_t ws_bytes, void *stream);
+
+/* x = argmin ||A x - b|| = B^{-1} A^T b, B = A^T A (Algorithm
+ * least_squares_gram): Cholesky B = R^T R, c = A^T b (row-block partials in
+ * a fixed order), x = R^{-1} R^{-T} c.  Accurate to about cond(A)^2 u.
+ *   b : n FP64 (device);  x : d FP64 (device, written).
+ * Errors: PSK_EINVAL, PSK_EUNSUPPORTED (d > 4096), PSK_ENOMEM, PSK_ERANK. */
+int lsq_gram(const psk_mat *A, const double *b, double *x, void *ws, size_t ws_bytes,
+             void *stream);
+
+/* x = argmin ||G S A x - G S b|| (Algorithm least_squares_approx,
+ * sketch-and-solve): the sketches of A and of b with the same seed (so the
+ * same S and G), R from sketch_qr of A~ = G S A, and the corrected
+ * semi-normal equations x = R^{-1} R^{-T} A~^T b~ plus one correction from
+ * the residual b~ - A~ x.  The solution of the sketched problem, so an
+ * approximation of the least-squares solution (its residual is within a
+ * factor of about 1 + d / (m - d) of the optimum in expectation).
+ *   m, r, seed, prec : as for sketch_gcs (d <= m <= 2^31 - 1, r >= 1).
+ *   b : n FP64 (device);  x : d FP64 (device, written).
+ * Errors: PSK_EINVAL (shapes, m < d), PSK_EDTYPE (prec), PSK_EUNSUPPORTED,
+ * PSK_ENOMEM, PSK_ERANK. */
+int lsq_sketch_solve(const psk_mat *A, const double *b, double *x, int64_t m, int64_t r,
+                     uint64_t seed, int prec, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- request server (serving form) ---------------------------------------
  * Continuous batching of least-squares and leverage-score requests of

@@ -15,6 +15,7 @@ from . import _lib as L
 
 __all__ = [
     "CsrMatrix", "cs_hash", "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq",
+    "leverage_gram", "lsq_gram", "lsq_sketch_solve",
     "sketch_qr", "lsq_solve", "workspace_size", "version", "PskError", "Server",
 ]
 
@@ -164,6 +165,43 @@ def sketch_g(A, m, seed, prec="f64", out=None):
     ws = _ws(nbytes, dev)
     L.check(L.lib().sketch_g(ctypes.byref(pm), m, seed, _PREC[prec], out.data_ptr(),
                              ws.data_ptr(), ws.numel(), _stream(dev)), "sketch_g")
+    return out
+
+
+def leverage_gram(A, out=None):
+    """Exact leverage scores of A (n float64) from its Gram matrix."""
+    pm = _mat(A)
+    dev = _device(A)
+    if out is None:
+        out = torch.empty(pm.n, dtype=torch.float64, device=dev)
+    ws = _ws(workspace_size(L.PSK_OP_LEVERAGE_GRAM, A), dev)
+    L.check(L.lib().leverage_gram(ctypes.byref(pm), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                  _stream(dev)), "leverage_gram")
+    return out
+
+
+def lsq_gram(A, b, out=None):
+    """argmin ||A x - b|| (d float64) by the normal equations, B = A^T A."""
+    pm = _mat(A)
+    dev = _device(A)
+    if out is None:
+        out = torch.empty(pm.d, dtype=torch.float64, device=dev)
+    ws = _ws(workspace_size(L.PSK_OP_LSQ_GRAM, A), dev)
+    L.check(L.lib().lsq_gram(ctypes.byref(pm), b.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                             ws.numel(), _stream(dev)), "lsq_gram")
+    return out
+
+
+def lsq_sketch_solve(A, b, m, r, seed, prec="f64", out=None):
+    """argmin ||G S (A x - b)|| (d float64): sketch-and-solve."""
+    pm = _mat(A)
+    dev = _device(A)
+    if out is None:
+        out = torch.empty(pm.d, dtype=torch.float64, device=dev)
+    ws = _ws(workspace_size(L.PSK_OP_LSQ_SKETCH, A, m=m, r=r, prec=prec), dev)
+    L.check(L.lib().lsq_sketch_solve(ctypes.byref(pm), b.data_ptr(), out.data_ptr(), m, r, seed,
+                                     _PREC[prec], ws.data_ptr(), ws.numel(), _stream(dev)),
+            "lsq_sketch_solve")
     return out
 
 

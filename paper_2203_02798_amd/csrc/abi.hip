@@ -258,6 +258,18 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
       if (m < 1 || m >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "m must be in [1, 2^31)");
       rc = do_sketch_g(*A, m, 0, prec, nullptr, ws, nullptr);
       break;
+    case PSK_OP_LEVERAGE_GRAM:
+      rc = leverage_gram_impl(*A, nullptr, ws, nullptr);
+      break;
+    case PSK_OP_LSQ_GRAM:
+      rc = lsq_gram_impl(*A, nullptr, nullptr, ws, nullptr);
+      break;
+    case PSK_OP_LSQ_SKETCH:
+      if ((rc = check_r(r))) return rc;
+      if (m < A->d || m >= ((int64_t)1 << 31))
+        return fail(PSK_EINVAL, "lsq_sketch_solve needs d <= m < 2^31");
+      rc = lsq_sketch_solve_impl(*A, nullptr, nullptr, m, r, 0, prec, ws, nullptr);
+      break;
     default:
       return fail(PSK_EINVAL, "unknown op");
   }
@@ -319,6 +331,50 @@ int sketch_g(const psk_mat *A, int64_t m, uint64_t seed, int prec, double *C, vo
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_G)");
   Arena ws = Arena::over(wsp, ws_bytes);
   return do_sketch_g(*A, m, seed, prec, C, ws, as_stream(stream));
+}
+
+int leverage_gram(const psk_mat *A, double *theta, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if (!theta) return fail(PSK_EINVAL, "theta is NULL");
+  Arena plan;
+  if ((rc = leverage_gram_impl(*A, nullptr, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LEVERAGE_GRAM)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return leverage_gram_impl(*A, theta, ws, as_stream(stream));
+}
+
+int lsq_gram(const psk_mat *A, const double *b, double *x, void *wsp, size_t ws_bytes,
+             void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if (!b || !x) return fail(PSK_EINVAL, "b and x must be non-NULL");
+  Arena plan;
+  if ((rc = lsq_gram_impl(*A, nullptr, nullptr, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LSQ_GRAM)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return lsq_gram_impl(*A, b, x, ws, as_stream(stream));
+}
+
+int lsq_sketch_solve(const psk_mat *A, const double *b, double *x, int64_t m, int64_t r,
+                     uint64_t seed, int prec, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if ((rc = check_r(r))) return rc;
+  if (m < A->d || m >= ((int64_t)1 << 31))
+    return fail(PSK_EINVAL, "lsq_sketch_solve needs d <= m < 2^31");
+  if (prec != PSK_PREC_F64 && prec != PSK_PREC_BF16 && prec != PSK_PREC_FP8)
+    return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
+  if (!b || !x) return fail(PSK_EINVAL, "b and x must be non-NULL");
+  Arena plan;
+  if ((rc = lsq_sketch_solve_impl(*A, nullptr, nullptr, m, r, seed, prec, plan, nullptr)))
+    return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LSQ_SKETCH)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return lsq_sketch_solve_impl(*A, b, x, m, r, seed, prec, ws, as_stream(stream));
 }
 
 int gram(double alpha, const psk_mat *A, double beta, void *C, void *wsp,

@@ -141,7 +141,7 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
 // ---- FP64 dense kernels (k_dense.hip) --------------------------------------
 // C (d x d, out_dtype) = alpha * A^T A + beta * C for dense A.
 int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
-               hipStream_t st);
+               hipStream_t st, bool out_f64 = false);
 // x = alpha * rownorm^2(A B) + beta * x, dense A, B d x k FP64.
 int rownorms_dense(double alpha, const psk_mat &A, const double *B, int64_t k,
                    double beta, double *x, Arena &ws, hipStream_t st);
@@ -151,8 +151,9 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
           double beta, double *C, int64_t ldc, Arena &ws, hipStream_t st);
 
 // ---- CSR kernels (k_csr.hip) -----------------------------------------------
+// out_f64: C is FP64 whatever the dtype of A (else the dtype of A)
 int gram_csr(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
-             hipStream_t st);
+             hipStream_t st, bool out_f64 = false);
 int rownorms_csr(double alpha, const psk_mat &A, const double *B, int64_t k,
                  double beta, double *x, Arena &ws, hipStream_t st);
 
@@ -162,6 +163,18 @@ int rownorms_csr(double alpha, const psk_mat &A, const double *B, int64_t k,
 int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R,
                    double *Rinv, Arena &ws, hipStream_t st,
                    int **flag_out = nullptr);
+// Upper Cholesky factor R of the SPD d x d matrix W (destroyed), W = R^T R,
+// and X = R^{-1} (both written entirely, zero below the diagonal); *flag (a
+// device int, 8-byte aligned, two ints cleared here) is set non-zero when a
+// pivot was not positive.  d <= 4096.
+int chol_factor(double *W, int64_t d, double *R, double *X, int *flag, Arena &ws,
+                hipStream_t st);
+
+// ---- direct solvers and exact leverage scores (k_direct.hip) ---------------
+int leverage_gram_impl(const psk_mat &A, double *theta, Arena &ws, hipStream_t st);
+int lsq_gram_impl(const psk_mat &A, const double *b, double *x, Arena &ws, hipStream_t st);
+int lsq_sketch_solve_impl(const psk_mat &A, const double *b, double *x, int64_t m, int64_t r,
+                          uint64_t seed, int prec, Arena &ws, hipStream_t st);
 
 // ---- LSQR (k_lsqr.hip) -----------------------------------------------------
 int lsq_impl(const psk_mat &A, const double *b, double *x,

@@ -737,6 +737,20 @@ int later_pass_chol(double *W, int64_t d, double *R, double *X, double *B0, doub
 
 }  // namespace
 
+int chol_factor(double *W, int64_t d, double *R, double *X, int *flag, Arena &ws,
+                hipStream_t st) {
+  if (d > 4096) return fail(PSK_EUNSUPPORTED, "the Cholesky factorization supports d <= 4096");
+  double *xpart = ws.take<double>((size_t)d * d);
+  if (ws.dry()) return 0;
+  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the Cholesky factorization");
+  k_fill<<<1, 64, 0, st>>>(reinterpret_cast<double *>(flag), 2, 0.0);
+  fill(R, d * d, 0.0, st);
+  fill(X, d * d, 0.0, st);
+  chol_inv(W, d, R, X, flag, xpart, st);
+  PSK_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
                    Arena &ws, hipStream_t st, int **flag_out) {
   if (d > 4096) return fail(PSK_EUNSUPPORTED, "sketch_qr supports d <= 4096");

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_rownorm_csr(
 }  // namespace
 
 int gram_csr(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
-             hipStream_t st) {
+             hipStream_t st, bool out_f64) {
   const int64_t d = A.d, n = A.n, nnz = A.nnz;
   if (d > 8192) return fail(PSK_EUNSUPPORTED, "CSR gram supports d <= 8192");
   if (nnz >= ((int64_t)1 << 32)) return fail(PSK_EUNSUPPORTED, "CSR gram needs nnz < 2^32");
@@ -151,6 +151,10 @@ int gram_csr(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
   if (A.dtype == PSK_F64)
     k_gram_csc<double, double><<<blocks, 64 * wpb, lds, st>>>(
         (const double *)A.values, A.indptr, A.indices, rowidx, cperm, cptr, d, dpad, alpha,
+        beta, (double *)C);
+  else if (out_f64)
+    k_gram_csc<float, double><<<blocks, 64 * wpb, lds, st>>>(
+        (const float *)A.values, A.indptr, A.indices, rowidx, cperm, cptr, d, dpad, alpha,
         beta, (double *)C);
   else
     k_gram_csc<float, float><<<blocks, 64 * wpb, lds, st>>>(

@@ -354,13 +354,13 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
 }
 
 int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
-               hipStream_t st) {
+               hipStream_t st, bool out_f64) {
   KTimer timer("gram", st);
   const bool f32 = A.dtype == PSK_F32;
   if (f32)
     return gemm_partial_launch<float, float, true, false, 2, 2, 2, 2, true>(
         A.d, A.d, A.n, (const float *)A.values, A.ld, (const float *)A.values, A.ld,
-        alpha, beta, C, A.d, true, ws, st);
+        alpha, beta, C, A.d, !out_f64, ws, st);
   return gemm_partial_launch<double, double, true, false, 2, 2, 2, 2, true>(
       A.d, A.d, A.n, (const double *)A.values, A.ld, (const double *)A.values, A.ld,
       alpha, beta, C, A.d, false, ws, st);

@@ -98,6 +98,17 @@ def test_workspace_planning(lib):
     assert st == -7  # CSR with d > 1023
     st, _ = _ws(L.PSK_OP_SKETCH_G, _dense(100, 5), m=0)
     assert st == -1
+    # direct solvers: the FP64 Gram matrix, its factor and inverse (d x d each)
+    st, l1 = _ws(L.PSK_OP_LEVERAGE_GRAM, _csr(100_000, 200, 10_000))
+    assert st == 0 and l1 >= 3 * 200 * 200 * 8
+    st, l2 = _ws(L.PSK_OP_LSQ_GRAM, _dense(5000, 64))
+    assert st == 0 and l2 >= 3 * 64 * 64 * 8
+    st, l3 = _ws(L.PSK_OP_LSQ_SKETCH, _dense(5000, 64), m=256, r=1024)
+    assert st == 0 and l3 >= 256 * 64 * 8
+    st, _ = _ws(L.PSK_OP_LSQ_SKETCH, _dense(5000, 64), m=32, r=1024)  # m < d
+    assert st == -1
+    st, _ = _ws(L.PSK_OP_LEVERAGE_GRAM, _dense(50000, 5000))
+    assert st == -7  # d > 4096
 
 
 def test_rejects_bad_arguments_without_device_work(lib):
@@ -120,6 +131,13 @@ def test_rejects_bad_arguments_without_device_work(lib):
     assert lib.sketch_g(ctypes.byref(good), 3, 0, 5, sa, ws, 1 << 20, stream) == -2
     assert lib.sketch_g(ctypes.byref(good), 3, 0, 0, None, ws, 1 << 20, stream) == -1
     assert lib.sketch_g(ctypes.byref(good), 3, 0, 0, sa, ws, 16, stream) == -3
+    assert lib.leverage_gram(ctypes.byref(good), None, ws, 1 << 20, stream) == -1
+    assert lib.leverage_gram(ctypes.byref(good), sa, ws, 16, stream) == -3
+    assert lib.lsq_gram(ctypes.byref(good), None, sa, ws, 1 << 20, stream) == -1
+    assert lib.lsq_sketch_solve(ctypes.byref(good), sa, sa, 4, 8, 0, 0, ws, 1 << 20,
+                                stream) == -1  # m < d
+    assert lib.lsq_sketch_solve(ctypes.byref(good), sa, sa, 8, 16, 0, 3, ws, 1 << 20,
+                                stream) == -2  # prec
     assert lib.cs_hash(0, 10, 0, 0, None, None, stream) == -1
     assert lib.cs_hash(-1, 10, 5, 0, None, None, stream) == -1
     assert lib.sketch_qr(sa, 3, 5, sa, sa, ws, 1 << 20, stream) == -1

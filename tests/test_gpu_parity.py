@@ -276,6 +276,35 @@ def test_sketch_g_reduced(api, prec, tol_arith, tol_fmt, kind, n, d, m):
     assert e_fmt <= tol_fmt
 
 
+@pytest.mark.parametrize("prec", ["f64", "bf16", "fp8"])
+def test_sparse_products_degenerate_inputs(api, prec):
+    """The products over the nonzeros (sketch_gcs of sparse S*A, sketch_g of
+    CSR A) on empty and near-empty matrices and one-row G: an empty matrix
+    gives exactly zero; one or three entries, m = 1 and n = 1 match the
+    oracle (FP8/BF16 against their quantised references)."""
+    tol = {"f64": 1e-13, "bf16": 1e-4, "fp8": 5e-4}[prec]
+    ref_g = {"f64": lambda a, m, s: osk.sketch_g(a, m, s),
+             "bf16": osk.sketch_g_bf16_reference, "fp8": osk.sketch_g_fp8_reference}[prec]
+    ref_gcs = {"f64": lambda a, m, r, s: osk.sketch_gcs(a, m, r, s),
+               "bf16": osk.sketch_gcs_bf16_reference,
+               "fp8": osk.sketch_gcs_fp8_reference}[prec]
+    z = synth.csr_from_parts(3000, 40, [], [], [])
+    assert np.all(api.sketch_g(to_device(z), 7, seed=2, prec=prec).cpu().numpy() == 0)
+    assert np.all(api.sketch_gcs(to_device(z), 7, 4096, seed=2, prec=prec).cpu().numpy() == 0)
+    cases = [
+        (synth.csr_from_parts(3000, 40, [1234], [17], [2.5]), 9, 4096),
+        (synth.csr_from_parts(3000, 40, [0, 1234, 2999], [0, 17, 39], [1.0, -3.0, 0.5]), 1, 8192),
+        (synth.csr_from_parts(1, 40, [0, 0], [3, 30], [1.5, -2.0]), 5, 1)]
+    for a, m, r in cases:
+        _say(f"degenerate {prec}: nnz={a.nnz} n={a.shape[0]} m={m} r={r}")
+        c = api.sketch_g(to_device(a), m, seed=2, prec=prec).cpu().numpy()
+        ref = ref_g(a, m, 2)
+        assert rel_fro(c, ref) <= tol, ("sketch_g", rel_fro(c, ref))
+        c = api.sketch_gcs(to_device(a), m, r, seed=2, prec=prec).cpu().numpy()
+        ref = ref_gcs(a, m, r, 2)
+        assert rel_fro(c, ref) <= tol, ("sketch_gcs", rel_fro(c, ref))
+
+
 def test_sketch_g_deterministic(api):
     a = to_device(synth.csr_uniform(50000, 200, 5e-3, seed=3))
     for prec in ("f64", "bf16", "fp8"):
@@ -494,3 +523,96 @@ def test_lsq_solve_matches_lapack(api, kind, cond):
     assert (rn - rs) / rs <= 1e-10
     assert ne <= 1e-10
     assert info["status"] == "PSK_OK"
+
+
+# ---------------------------------------------------------------------------
+# Direct solvers and exact leverage scores (Gram route; sketch-and-solve)
+# ---------------------------------------------------------------------------
+def _direct_input(kind, cond):
+    if kind == "csr":
+        return synth.csr_uniform(100000, 64, 0.02, seed=4)
+    if kind == "csr32":
+        return synth.csr_uniform(50000, 48, 0.05, seed=4, dtype=np.float32)
+    if kind == "dense32":
+        return synth.dense_gaussian(20000, 40, seed=4, dtype=np.float32)
+    a, _, _ = synth.lsq_problem(20000, 40, cond, seed=4)
+    return a
+
+
+@pytest.mark.parametrize("kind,cond", [("dense", 1.0), ("dense", 1e3), ("csr", 1.0),
+                                       ("csr32", 1.0), ("dense32", 1.0)])
+def test_leverage_gram_exact(api, kind, cond):
+    a = _direct_input(kind, cond)
+    d = a.shape[1]
+    th = api.leverage_gram(to_device(a)).cpu().numpy()
+    ex = olev.leverage_exact(a)
+    err = np.abs(th - ex).max()
+    _say(f"leverage_gram {kind} cond={cond}: max |dtheta| {err:.3e}, sum {th.sum():.12f}")
+    # B = A^T A carries cond^2: the scores are exact to about cond^2 u
+    tol = 1e-12 * max(cond, 1.0) ** 2
+    assert err <= tol
+    assert abs(th.sum() - d) <= d * tol
+
+
+def test_leverage_gram_reports_rank_deficiency(api):
+    a = synth.dense_gaussian(3000, 12, seed=1)
+    a[:, 5] = 0.0  # a zero column: a zero pivot
+    with pytest.raises(RuntimeError, match="rank|ERANK"):
+        api.leverage_gram(to_device(a))
+        torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("kind,cond", [("dense", 1.0), ("dense", 1e3), ("csr", 1.0),
+                                       ("dense32", 1.0)])
+def test_lsq_gram_matches_lapack(api, kind, cond):
+    a = _direct_input(kind, cond)
+    n = a.shape[0]
+    rng = np.random.default_rng(7)
+    b = a @ rng.standard_normal(a.shape[1]) + 1e-3 * rng.standard_normal(n)
+    b = np.asarray(b, dtype=np.float64)
+    x = api.lsq_gram(to_device(a), torch.from_numpy(b).cuda()).cpu().numpy()
+    xs = olsq.lstsq(a, b)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    _say(f"lsq_gram {kind} cond={cond}: rel err {err:.3e}")
+    assert err <= 1e-12 * max(cond, 1.0) ** 2
+
+
+@pytest.mark.parametrize("kind,n,d,m,r", [
+    ("dense", 20000, 32, 128, 1024),
+    ("csr", 100000, 64, 256, 8192),           # S*A dense enough for the GEMM
+    ("csr:2e-3", 200000, 64, 256, 32768)])    # the product over S*A's nonzeros
+@pytest.mark.parametrize("prec", ["f64", "bf16", "fp8"])
+def test_lsq_sketch_solve(api, kind, n, d, m, r, prec):
+    if kind == "dense":
+        a, b, _ = synth.lsq_problem(n, d, 10.0, seed=8)
+    else:
+        dens = float(kind.split(":")[1]) if ":" in kind else 0.02
+        a = synth.csr_uniform(n, d, dens, seed=8)
+        rng = np.random.default_rng(2)
+        b = a @ rng.standard_normal(d) + 1e-2 * rng.standard_normal(n)
+    b = np.asarray(b, dtype=np.float64)
+    x = api.lsq_sketch_solve(to_device(a), torch.from_numpy(b).cuda(), m, r, seed=11,
+                             prec=prec).cpu().numpy()
+    if prec == "f64":
+        ref = olsq.lsq_sketch_solve(a, b, m, r, 11)
+        tol = 1e-10
+    else:
+        q = (osk.sketch_gcs_bf16_reference if prec == "bf16" else osk.sketch_gcs_fp8_reference)
+        c = q(a, m, r, 11)
+        cb = q(b[:, None], m, r, 11)[:, 0]
+        ref = olsq.lstsq(c, cb)
+        # the sketch's kernel arithmetic (~2e-5 BF16, ~5e-4 FP8 normwise)
+        # times cond(A~) ~ 10
+        tol = 5e-4 if prec == "bf16" else 5e-3
+    err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    # the residual of the sketched solution against the optimum (1 + d/m-ish)
+    xs = olsq.lstsq(a, b)
+    ratio = np.linalg.norm(a @ x - b) / np.linalg.norm(a @ xs - b)
+    _say(f"lsq_sketch_solve {prec} {kind}: vs reference {err:.3e}, residual ratio {ratio:.4f}")
+    assert err <= tol
+    assert ratio >= 1.0 - 1e-12
+    if prec != "fp8":
+        # FP8's ~5% operand rounding moves the sketched solution by more than
+        # the optimal residual of these near-consistent problems; its bar is
+        # the quantised reference above
+        assert ratio <= 1.0 + 4.0 * d / m
