@@ -230,6 +230,35 @@ def gaussian_only_bench(api, torch, A, m, n, d, nnz, seed, steps, warmup):
                          "samples_per_launch": m * n, "fma_per_launch": m * nnz}}
 
 
+def direct_bench(api, torch, A, a, b, bd, m, r, seed, steps, warmup, lsqr_resid):
+    """The direct solvers on the same matrix: exact leverage scores and least
+    squares from the Gram matrix, and sketch-and-solve with the bench's
+    sketch (BF16 G), each timed alone, with the quality of its result."""
+    calls = {
+        "leverage_gram": lambda: api.leverage_gram(A),
+        "lsq_gram": lambda: api.lsq_gram(A, bd),
+        "lsq_sketch_solve_bf16": lambda: api.lsq_sketch_solve(A, bd, m, r, seed, prec="bf16"),
+    }
+    out = {}
+    for name, f in calls.items():
+        for _ in range(warmup):
+            f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = f()
+        torch.cuda.synchronize()
+        out[name] = {"ms_per_call": 1e3 * (time.perf_counter() - t0) / steps}
+        v = res.cpu().numpy()
+        if name == "leverage_gram":
+            out[name]["sum_minus_d"] = float(v.sum() - a.shape[1])
+        else:
+            rn = float(np.linalg.norm(b - a @ v))
+            out[name]["resid"] = rn
+            out[name]["resid_vs_lsqr"] = rn / lsqr_resid
+    return out
+
+
 def cpu_baseline(kind, a, b, r, m, seed, budget_s=12.0):
     """The oracle on the host: every stage in full except the Gaussian GEMM,
     whose bucket batches (Algorithm countgauss_multiply) are timed on a
@@ -298,6 +327,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-server measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the Gaussian-only sketch and direct-solver measurements "
+                         "(hardware-counter runs: one workload per kernel)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 4 elementwise copies of MIB "
                          "MiB (FP64) whose HBM bytes are known, to scale hardware "
@@ -468,9 +500,11 @@ def main():
             "achieved": flops / (gg * 1e-3) / 1e12 if gg > 0 else 0.0,
             "peak": PEAK_FP8_TFLOPS, "unit": "TFLOP/s",
             "frac": (flops / (gg * 1e-3) / 1e12) / PEAK_FP8_TFLOPS if gg > 0 else 0.0}
-    if head == "bf16" and kind == "csr":
+    if head == "bf16" and kind == "csr" and not args.no_extras:
         rec["gaussian_only"] = gaussian_only_bench(api, torch, A, m, n, d, int(a.nnz), seed,
                                                    args.steps, args.warmup)
+        rec["direct"] = direct_bench(api, torch, A, a, b, bd, m, r, seed, args.steps,
+                                     args.warmup, hr["lsq"]["resid"])
     if not args.no_serving:
         rec["serving"] = serving_bench(api, torch, dev)
     if not args.no_cpu_baseline:

@@ -391,6 +391,13 @@ enum { kG64 = 0, kGbf16 = 1, kGfp8 = 2 };
 
 constexpr int kSThreads = 1024;
 constexpr int kStage = 2 * kSThreads;  // entries of a block staged in LDS at once
+// A column with more than kHeavy entries in a staged turn (a dense column
+// of A, or b appended to A) is summed by all threads together; a turn holds
+// at most kStage / (kHeavy + 1) < kHeavyMax such columns, so the list never
+// overflows and which columns take that path depends on the data alone.
+constexpr int kHeavy = 32;
+constexpr int kHeavyMax = 64;
+static_assert(kStage / (kHeavy + 1) < kHeavyMax, "heavy list capacity");
 
 // Workgroup (row tile mt, K split ks), 1024 threads: rows a0 .. a0 + MT of
 // C (MT = 16 1024 / DP) and the G blocks of BLK buckets ks bper .. ks bper +
@@ -423,6 +430,12 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
   __shared__ uint32_t stp[kStage];
   __shared__ AT stv[kStage];
   __shared__ uint2 crng[DP];  // per column: tag, first staged slot | count << 16
+  // heavy columns of the turn: column, first slot | count << 16; the count
+  // alternates with the turn's parity so that it is cleared a turn ahead
+  __shared__ uint2 hlist[kHeavyMax];
+  __shared__ uint32_t hcnt[2];
+  constexpr int NSTR = kSThreads / MT;  // entry streams of a heavy column
+  __shared__ AT hred[NSTR * MT];
   const int tid = threadIdx.x;
   const int mt = (int)(blockIdx.x % tiles_m);
   const int64_t ks = blockIdx.x / tiles_m;
@@ -432,6 +445,7 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
   const int64_t k1 = k0 + bper < nblk ? k0 + bper : nblk;
   const int j = tid % DP, h = tid / DP;
   for (int i = tid; i < DP; i += kSThreads) crng[i] = make_uint2(kHole, 0u);
+  if (tid < 2) hcnt[tid] = 0u;
   AT acc[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = AT(0);
@@ -483,7 +497,8 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     R.hi = B.hi;
   };
   // stage one turn (nch entries) and its column ranges; barrier before and after
-  auto stage = [&](const uint32_t *pp, const double *vv, uint32_t nch) {
+  auto stage = [&](const uint32_t *pp, const double *vv, uint32_t nch)
+                   __attribute__((always_inline)) {
 #pragma unroll
     for (int s2 = 0; s2 < kStage / kSThreads; ++s2) {
       const int idx = tid + kSThreads * s2;
@@ -493,11 +508,21 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
       if (pv != kHole && (((pv >> 29) & 1u) || idx == 0)) {
         const uint32_t left = (pv >> 19) & 1023u;
         const uint32_t room = nch - (uint32_t)idx;
-        crng[pv & 1023u] = make_uint2(tag, (uint32_t)idx | ((left < room ? left : room) << 16));
+        const uint32_t cnt = left < room ? left : room;
+        const uint32_t rng = (uint32_t)idx | (cnt << 16);
+        if (cnt > (uint32_t)kHeavy) {
+          // all threads sum it in consume; its owner skips it (no tag is
+          // kHole, this turn's or a later one's)
+          const uint32_t k = atomicAdd(&hcnt[tag & 1u], 1u);
+          hlist[k] = make_uint2(pv & 1023u, rng);
+          crng[pv & 1023u] = make_uint2(kHole, 0u);
+        } else {
+          crng[pv & 1023u] = make_uint2(tag, rng);
+        }
       }
     }
   };
-  auto consume = [&]() {
+  auto consume = [&]() __attribute__((always_inline)) {
     const uint2 cr = crng[j];
     if (cr.x == tag) {
       const int s0 = (int)(cr.y & 0xffffu), s1 = s0 + (int)(cr.y >> 16);
@@ -511,6 +536,35 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
 #pragma unroll
         for (int t = 0; t < 16; ++t) acc[t] = fma(gv[t], v, acc[t]);
       }
+    }
+    // heavy columns: thread (stream st, row a) takes the column's entries
+    // st, st + NSTR, ... for row a; the streams' sums are added to the
+    // owners' accumulators in stream order
+    const uint32_t nh = hcnt[tag & 1u];
+    if (tid == 0) hcnt[(tag & 1u) ^ 1u] = 0u;  // the next turn's count
+    const int ha = tid % MT, hs = tid / MT;
+#pragma unroll 1
+    for (uint32_t q = 0; __builtin_expect(q < nh, 0); ++q) {
+      const uint2 hv = hlist[q];
+      const int s0 = (int)(hv.y & 0xffffu), s1 = s0 + (int)(hv.y >> 16);
+      AT part = AT(0);
+#pragma unroll 1
+      for (int i = s0 + hs; i < s1; i += NSTR) {
+        const uint32_t pv = stp[i];
+        part = fma((AT)Gb[((pv >> 10) & 511u) * GS + ha], stv[i], part);
+      }
+      hred[hs * MT + ha] = part;
+      __syncthreads();
+      if ((uint32_t)j == hv.x) {
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          AT sum = AT(0);
+#pragma unroll 4
+          for (int q2 = 0; q2 < NSTR; ++q2) sum += hred[q2 * MT + 16 * h + t];
+          acc[t] += sum;
+        }
+      }
+      __syncthreads();
     }
     ++tag;
   };

@@ -305,6 +305,28 @@ def test_sparse_products_degenerate_inputs(api, prec):
         assert rel_fro(c, ref) <= tol, ("sketch_gcs", rel_fro(c, ref))
 
 
+@pytest.mark.parametrize("prec", ["f64", "bf16", "fp8"])
+def test_sparse_products_dense_column(api, prec):
+    """A CSR matrix with one full column (an intercept, or b appended to A):
+    in the products over the nonzeros that column fills whole G blocks and
+    is summed by all threads of the workgroup together."""
+    n, d, r, m = 100000, 500, 8192, 160
+    a = synth.csr_uniform(n, d, 1e-4, seed=6).tolil()
+    a[:, 7] = 1.0 + 0.001 * np.arange(n)[:, None]
+    a = a.tocsr()
+    tol = {"f64": 1e-12, "bf16": 1e-4, "fp8": 5e-4}[prec]
+    ref_g = {"f64": lambda: osk.sketch_g(a, m, 3), "bf16": lambda: osk.sketch_g_bf16_reference(a, m, 3),
+             "fp8": lambda: osk.sketch_g_fp8_reference(a, m, 3)}[prec]
+    ref_gcs = {"f64": lambda: osk.sketch_gcs(a, m, r, 3),
+               "bf16": lambda: osk.sketch_gcs_bf16_reference(a, m, r, 3),
+               "fp8": lambda: osk.sketch_gcs_fp8_reference(a, m, r, 3)}[prec]
+    ad = to_device(a)
+    e1 = rel_fro(api.sketch_g(ad, m, seed=3, prec=prec).cpu().numpy(), ref_g())
+    e2 = rel_fro(api.sketch_gcs(ad, m, r, seed=3, prec=prec).cpu().numpy(), ref_gcs())
+    _say(f"dense column {prec}: sketch_g {e1:.3e}, sketch_gcs {e2:.3e}")
+    assert e1 <= tol and e2 <= tol
+
+
 def test_sketch_g_deterministic(api):
     a = to_device(synth.csr_uniform(50000, 200, 5e-3, seed=3))
     for prec in ("f64", "bf16", "fp8"):
