@@ -8,11 +8,19 @@ Paper passages followed (arXiv 2203.02798):
   the factor is the R of a QR of the sketch, which spans the same
   orthogonaliser: A R^{-1} and A V Sigma^{-1} differ by an orthogonal d x d
   matrix, so the row norms agree.
+* Algorithm ``ls_approximate_drineas`` with its Johnson-Lindenstrauss step:
+  X = R^{-1} Pi for a d x t Gaussian Pi scaled to variance 1/t, and
+  theta~_i = ||e_i^T A X||^2, which preserves each row norm of A R^{-1} up to
+  a factor 1 +- eps when t = O(log n / eps^2).  The sketch is S A alone in
+  the algorithm (m = 0 here) or G S A (m > 0).
 * Algorithm ``ls_direct``: exact leverage scores theta_i = ||e_i^T U||^2 for an
   orthonormal basis U of range(A) (computed here from a thin QR of A).
 
-Reading: full column rank is assumed (the paper's "truncate if needed" is not
-applied); R is normalised to a non-negative diagonal.
+Readings: full column rank is assumed (the paper's "truncate if needed" is
+not applied); R is normalised to a non-negative diagonal.  Pi is drawn by the
+generator of G (``oracle.sketch``) on stream 2: Pi[b, j] = Z[j, b] / sqrt(t)
+with Z the normals of a t-row Gaussian whose columns are indexed by
+b = 0 .. d-1, so Pi^T is that t x d Gaussian.
 """
 from __future__ import annotations
 
@@ -21,7 +29,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .gram import rownorms_sq
-from .sketch import sketch_gcs
+from .sketch import gaussian_normals, sketch_gcs
 
 
 def qr_r(c):
@@ -45,6 +53,26 @@ def leverage_sketched(a, m, r, seed):
     c = sketch_gcs(a, m, r, seed)
     rr = qr_r(c)
     return rownorms_sq(1.0, a, tri_inv(rr)), rr
+
+
+def jl_matrix(d, t, seed):
+    """Pi (d x t): the scaled Gaussian of the JL step, entries of variance 1/t."""
+    return gaussian_normals(t, 0, d, seed, stream=2).T / np.sqrt(t)
+
+
+def leverage_from_sketch(a, c, t, seed):
+    """theta~_i = ||e_i^T A X||^2 with X = R^{-1} (t = 0) or X = R^{-1} Pi
+    (t > 0), R from QR(c) for the sketch c of A."""
+    x = tri_inv(qr_r(c))
+    if t > 0:
+        x = x @ jl_matrix(x.shape[0], t, seed)
+    return rownorms_sq(1.0, a, x)
+
+
+def leverage_sketched_jl(a, m, r, t, seed):
+    """Algorithm ``ls_approximate_drineas`` with the JL step: sketch
+    (S A for m = 0, else G S A), factor, X = R^{-1} Pi, row norms of A X."""
+    return leverage_from_sketch(a, sketch_gcs(a, m, r, seed), t, seed)
 
 
 def leverage_sketched_svd(a, m, r, seed):

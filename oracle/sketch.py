@@ -30,6 +30,8 @@ engines, so its streams are not reproducible across thread counts):
   z0, z1 = sqrt(-2 ln u0) * (cos, sin)(2 pi u1) and
   z2, z3 = sqrt(-2 ln u2) * (cos, sin)(2 pi u3);  G[a, b] = z_{b mod 4} / sqrt(m)
   (variance 1/m, i.e. N(0, 1/sqrt(m)) in the paper's (mean, std) notation).
+  Counter word 3 names the stream: 0 for the hash, 1 for G, 2 for the JL
+  matrix of the leverage-score estimate (see ``oracle.leverage``).
 """
 from __future__ import annotations
 
@@ -125,8 +127,9 @@ def bucket_occupancy(n, r, seed):
 # ----------------------------------------------------------------------------
 # Gaussian matrix (generated in column blocks, never whole)
 # ----------------------------------------------------------------------------
-def gaussian_normals(m, b0, b1, seed):
-    """Unscaled standard normals Z[a, b] for rows a < m, buckets b0 <= b < b1."""
+def gaussian_normals(m, b0, b1, seed, stream=1):
+    """Unscaled standard normals Z[a, b] for rows a < m, buckets b0 <= b < b1
+    (counter word 3 = stream)."""
     if b1 <= b0 or m == 0:
         return np.zeros((m, max(b1 - b0, 0)))
     q0, q1 = b0 // 4, (b1 + 3) // 4
@@ -136,7 +139,7 @@ def gaussian_normals(m, b0, b1, seed):
     ctr[:, :, 0] = (q & np.uint64(0xFFFFFFFF))[None, :]
     ctr[:, :, 1] = (q >> np.uint64(32))[None, :]
     ctr[:, :, 2] = a[:, None]
-    ctr[:, :, 3] = 1
+    ctr[:, :, 3] = stream
     x = philox4x32(ctr, seed_key(seed)).astype(np.float64)
     u = (x + 0.5) * TWO_M32
     rho0 = np.sqrt(-2.0 * np.log(u[..., 0]))

@@ -84,6 +84,75 @@ def test_sketched_leverage_invariants(sparse):
                                rtol=1e-9, atol=1e-15)
 
 
+def test_countsketch_only_leverage_invariants():
+    """Algorithm ls_approximate_drineas sketches with S alone (m = 0): the
+    bracket by the singular values of S U holds for that sketch too."""
+    n, d, r = 3000, 5, 400
+    a = synth.dense_gaussian(n, d, seed=2)
+    th = olev.leverage_exact(a)
+    tt, _ = olev.leverage_sketched(a, 0, r, seed=6)
+    sv = olev.sketch_distortion(a, 0, r, seed=6)
+    assert np.all(tt >= th / sv.max() ** 2 * (1 - 1e-9))
+    assert np.all(tt <= th / sv.min() ** 2 * (1 + 1e-9))
+    assert abs(tt.sum() - (sv ** -2).sum()) < 1e-9 * tt.sum()
+
+
+def test_jl_matrix_distribution_and_stream():
+    """Pi (d x t) has independent entries of mean 0 and variance 1/t, so
+    E[Pi Pi^T] = I, and its normals are not those of G at the same counters
+    (stream 2 against stream 1)."""
+    d, t = 64, 4096
+    pi = olev.jl_matrix(d, t, seed=3)
+    assert pi.shape == (d, t)
+    z = pi * np.sqrt(t)
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1) < 5 * np.sqrt(2 / z.size)
+    g = osk.gaussian_normals(t, 0, d, 3)  # stream 1, same (row, column) counters
+    assert abs((z * g.T).mean()) < 5 / np.sqrt(z.size)
+    pp = pi @ pi.T
+    assert np.abs(np.diag(pp) - 1).max() < 6 * np.sqrt(2 / t)
+    assert np.abs(pp - np.diag(np.diag(pp))).max() < 6 / np.sqrt(t)
+    # the first columns of Pi do not depend on t beyond the 1/sqrt(t) scale
+    np.testing.assert_allclose(olev.jl_matrix(d, 100, seed=3)[:, :40] * 10,
+                               z[:, :40], rtol=1e-15, atol=0)
+
+
+def test_jl_leverage_t0_is_the_unreduced_estimate():
+    a = synth.csr_uniform(800, 7, 0.4, seed=3)
+    tt, _ = olev.leverage_sketched(a, 30, 200, seed=8)
+    np.testing.assert_array_equal(olev.leverage_sketched_jl(a, 30, 200, 0, seed=8), tt)
+
+
+def test_jl_leverage_unbiased_over_pi():
+    """For a fixed sketch, theta~_i / theta_i (JL step) is chi^2_t / t: mean 1,
+    variance 2/t.  The mean over K draws of Pi stays within 6 standard
+    deviations of 1 on every row."""
+    n, d, t, K = 200, 6, 8, 400
+    a = synth.dense_gaussian(n, d, seed=4)
+    c = osk.sketch_gcs(a, 24, 120, seed=1)
+    t0 = olev.leverage_from_sketch(a, c, 0, seed=1)
+    acc = np.zeros(n)
+    for s in range(K):
+        acc += olev.leverage_from_sketch(a, c, t, seed=1000 + s)
+    ratio = acc / K / t0
+    assert np.abs(ratio - 1).max() < 6 * np.sqrt(2 / t / K)
+    # and one draw alone is spread as chi^2_t / t
+    one = olev.leverage_from_sketch(a, c, t, seed=7) / t0
+    assert 0.5 < one.var() / (2 / t) < 2.0
+
+
+@pytest.mark.parametrize("m", [0, 60])
+def test_jl_leverage_within_jl_bound(m):
+    """With t = 3000 every row norm of A R^{-1} is kept to within
+    1 +- 6 sqrt(2/t) (about 0.155): the JL property the step relies on."""
+    n, d, r, t = 3000, 10, 500, 3000
+    a = synth.dense_gaussian(n, d, seed=11)
+    t0 = olev.leverage_sketched_jl(a, m, r, 0, seed=4)
+    tj = olev.leverage_sketched_jl(a, m, r, t, seed=4)
+    assert np.abs(tj / t0 - 1).max() < 6 * np.sqrt(2 / t)
+    assert abs(tj.sum() / t0.sum() - 1) < 6 * np.sqrt(2 / t / d)
+
+
 def test_distortion_within_marchenko_pastur_edges():
     n, d, m, r = 20000, 8, 400, 4000
     a = synth.dense_gaussian(n, d, seed=9)
