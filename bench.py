@@ -230,6 +230,55 @@ def gaussian_only_bench(api, torch, A, m, n, d, nnz, seed, steps, warmup):
                          "samples_per_launch": m * n, "fma_per_launch": m * nnz}}
 
 
+def leverage_jl_bench(api, torch, steps, warmup, n=4_000_000, d=256, r=65536, m=1024,
+                      t=64, seed=0):
+    """leverage_sketch on the dense tall-skinny FP32 configuration (4,000,000 x
+    256, singular values geometric from 1 to 1e-6, 5% of rows scaled by 100),
+    with and without the JL step.  A = Z diag(s) V^T with Z Gaussian and V
+    orthogonal, generated on the device.  The sketch is FP64 (at cond 1e6 a
+    BF16 S A loses the small singular directions).  Reported: time per call,
+    the row-norm product's time (n d^2 against n d t multiply-adds), and the
+    spread of theta(t) / theta(0), which the JL bound keeps near
+    1 +- sqrt(2/t) per row."""
+    g = torch.Generator(device="cuda:0").manual_seed(seed)
+    v, _ = torch.linalg.qr(torch.randn(d, d, generator=g, device="cuda:0",
+                                       dtype=torch.float64))
+    s = torch.logspace(0, -6, d, dtype=torch.float64, device="cuda:0")
+    w = (s[:, None] * v.T).to(torch.float32)
+    A = torch.randn(n, d, generator=g, device="cuda:0", dtype=torch.float32) @ w
+    hot = torch.randperm(n, generator=g, device="cuda:0")[: n // 20]
+    A[hot] *= 100.0
+    torch.cuda.synchronize()
+    out = {"workload": f"dense FP32 {n} x {d}, r = {r}, m = {m}, sketch f64", "t": t}
+    th = {}
+    for tt in (0, t):
+        for _ in range(warmup):
+            api.leverage_sketch(A, m, r, seed, t=tt)
+        torch.cuda.synchronize()
+        with api.kernel_timing() as kt:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                res = api.leverage_sketch(A, m, r, seed, t=tt)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / steps
+            stats = kt.stats()
+        rn_ms = stats.get("rownorm", (0.0, 0))[0] / steps
+        k = tt if tt > 0 else d
+        out[f"t{tt}"] = {"ms_per_call": 1e3 * wall, "rownorm_ms": rn_ms,
+                         "rownorm_tflops": 2.0 * n * d * k / (rn_ms * 1e-3) / 1e12
+                         if rn_ms > 0 else None,
+                         "stage_ms": {kk: round(vv[0] / steps, 4)
+                                      for kk, vv in sorted(stats.items())}}
+        th[tt] = res
+    ratio = (th[t] / th[0]).cpu().numpy()
+    out["jl_ratio"] = {"min": float(ratio.min()), "max": float(ratio.max()),
+                       "std": float(ratio.std()), "jl_std": float(np.sqrt(2.0 / t))}
+    out["sum_theta_t0"] = float(th[0].sum())
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def direct_bench(api, torch, A, a, b, bd, m, r, seed, steps, warmup, lsqr_resid):
     """The direct solvers on the same matrix: exact leverage scores and least
     squares from the Gram matrix, and sketch-and-solve with the bench's
@@ -328,7 +377,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-server measurement")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the Gaussian-only sketch and direct-solver measurements "
+                    help="skip the Gaussian-only sketch, direct-solver and JL leverage measurements "
                          "(hardware-counter runs: one workload per kernel)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 4 elementwise copies of MIB "
@@ -505,6 +554,8 @@ def main():
                                                    args.steps, args.warmup)
         rec["direct"] = direct_bench(api, torch, A, a, b, bd, m, r, seed, args.steps,
                                      args.warmup, hr["lsq"]["resid"])
+        log("leverage scores with the JL step, dense FP32 4,000,000 x 256")
+        rec["leverage_jl"] = leverage_jl_bench(api, torch, args.steps, args.warmup)
     if not args.no_serving:
         rec["serving"] = serving_bench(api, torch, dev)
     if not args.no_cpu_baseline:

@@ -17,6 +17,10 @@
  *                                                             Alg. ls_approximate_drineas
  *                                                             and least_squares_precondition)
  *   lsq_solve    min ||A x - b|| by sketch-and-precondition  (Alg. least_squares_precondition)
+ *   leverage_sketch  approximate leverage scores, optionally    (Alg. ls_approximate_drineas)
+ *                    through a JL matrix Pi
+ *   leverage_gram, lsq_gram, lsq_sketch_solve, sketch_g: section 4's direct
+ *                    solvers and exact leverage scores, and Gaussian sketching
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -46,7 +50,9 @@
  *                      h(i) = floor((x1*2^32 + x0) * r / 2^64), sigma_i = x2 even ? +1 : -1;
  *     Gaussian G[a,b]: x = Philox(ctr=(q lo32, q hi32, a, 1), key as above), q = b div 4,
  *                      u_k = (x_k + 1/2) 2^-32, Box-Muller on (u0,u1) and (u2,u3) gives
- *                      z0..z3, G[a,b] = z_{b mod 4} / sqrt(m).
+ *                      z0..z3, G[a,b] = z_{b mod 4} / sqrt(m);
+ *     JL matrix Pi[b,j] (leverage_sketch): the same with counter word 3 = 2 and
+ *                      a = j, Pi[b,j] = z_{b mod 4} / sqrt(t).
  * - Limits: n < 2^31 rows, r < 2^31 buckets, CSR nnz < 2^62.
  */
 #ifndef PSK_H
@@ -125,7 +131,8 @@ enum {
   PSK_OP_SKETCH_G = 6,
   PSK_OP_LEVERAGE_GRAM = 7,
   PSK_OP_LSQ_GRAM = 8,
-  PSK_OP_LSQ_SKETCH = 9
+  PSK_OP_LSQ_SKETCH = 9,
+  PSK_OP_LEVERAGE_SKETCH = 10
 };
 
 /* Library version string (static storage). */
@@ -139,9 +146,9 @@ const char *psk_last_error(void);
  *   A    : the matrix the call will get (for PSK_OP_QR only A->n = m rows and
  *          A->d = d columns of the sketch are read);
  *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ,
- *          LSQ_SKETCH; SKETCH_G reads m only);
- *   k    : columns of B (ROWNORMS);
- *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ, LSQ_SKETCH).
+ *          LSQ_SKETCH, LEVERAGE_SKETCH; SKETCH_G reads m only);
+ *   k    : columns of B (ROWNORMS), columns t of Pi (LEVERAGE_SKETCH);
+ *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ, LSQ_SKETCH, LEVERAGE_SKETCH).
  * For PSK_OP_LSQ, m == 0 sizes a call that passes its own opts->Rinv.
  * Arguments an op does not use are ignored. */
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r,
@@ -269,6 +276,31 @@ typedef struct psk_lsq_info {
 int lsq_solve(const psk_mat *A, const double *b, double *x,
               const psk_lsq_opts *opts, psk_lsq_info *info,
               void *ws, size_t ws_bytes, void *stream);
+
+/* theta_i ~ leverage score of row i (Algorithm ls_approximate_drineas):
+ *   1. the sketch: S A (m == 0, the algorithm as stated; r >= d) or G S A
+ *      (m > 0; d <= m < 2^31), as sketch_cs / sketch_gcs with this seed and,
+ *      for m > 0, prec;
+ *   2. R and R^{-1} of the sketch (sketch_qr; the triangular factor stands in
+ *      for the paper's SVD: A R^{-1} and A V Sigma^{-1} differ by an
+ *      orthogonal factor, so their row norms agree);
+ *   3. t > 0: X = R^{-1} Pi with Pi the d x t Gaussian of variance 1/t drawn
+ *      as stated in the header comment (row norms kept to within 1 +- eps
+ *      for t = O(log n / eps^2); the dense row-norm product costs n d t
+ *      multiply-adds instead of n d^2); t == 0: X = R^{-1};
+ *   4. theta_i = ||e_i^T A X||^2 (rownorms_sq).
+ * An FP32 S A (m == 0) is widened to FP64 before the factorization.
+ *   theta : n FP64 (device, written).
+ * The call synchronises the stream once, to read the factorization's pivot
+ * flag.  Workspace: psk_workspace_size(PSK_OP_LEVERAGE_SKETCH, A, m, r, t,
+ * prec); it holds the sketch and two copies of it for the QR passes.
+ * Errors: PSK_EINVAL (shapes, m, r out of range, t < 0 or d * t >= 2^31,
+ * NULL theta), PSK_EDTYPE
+ * (prec, when m > 0), PSK_EUNSUPPORTED (d > 4096; as sketch_cs), PSK_ENOMEM,
+ * PSK_ERANK (a Cholesky pivot of the factorization was not positive; theta
+ * is still written). */
+int leverage_sketch(const psk_mat *A, int64_t m, int64_t r, int64_t t, uint64_t seed, int prec,
+                    double *theta, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- direct solvers and exact leverage scores ---------------------------
  * Section 4's Gram-based and sketch-and-solve algorithms.  A triangular

@@ -168,6 +168,20 @@ def sketch_g(A, m, seed, prec="f64", out=None):
     return out
 
 
+def leverage_sketch(A, m, r, seed, t=0, prec="f64", out=None):
+    """Approximate leverage scores of A (n float64): R from the sketch
+    (G S A, or S A when m == 0), theta_i = ||e_i^T A R^{-1} Pi||^2 with Pi the
+    d x t JL matrix (t == 0: no JL step)."""
+    pm = _mat(A)
+    dev = _device(A)
+    if out is None:
+        out = torch.empty(pm.n, dtype=torch.float64, device=dev)
+    ws = _ws(workspace_size(L.PSK_OP_LEVERAGE_SKETCH, A, m=m, r=r, k=t, prec=prec), dev)
+    L.check(L.lib().leverage_sketch(ctypes.byref(pm), m, r, t, seed, _PREC[prec], out.data_ptr(),
+                                    ws.data_ptr(), ws.numel(), _stream(dev)), "leverage_sketch")
+    return out
+
+
 def leverage_gram(A, out=None):
     """Exact leverage scores of A (n float64) from its Gram matrix."""
     pm = _mat(A)

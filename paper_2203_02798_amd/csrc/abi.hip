@@ -207,6 +207,22 @@ const char *psk_timing_names(void) {
 
 const char *psk_last_error(void) { return g_last_error.c_str(); }
 
+// Shapes of leverage_sketch: the sketch has m >= d rows (G S A) or, with
+// m == 0, r >= d rows (S A); t >= 0 columns of Pi, d * t < 2^31.
+static int check_leverage_sketch(const psk_mat &A, int64_t m, int64_t r, int64_t t,
+                                 int prec) {
+  int rc = check_r(r);
+  if (rc) return rc;
+  if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "m must be in [0, 2^31)");
+  if (m == 0 && r < A.d) return fail(PSK_EINVAL, "leverage_sketch with m == 0 needs r >= d");
+  if (m > 0 && m < A.d) return fail(PSK_EINVAL, "leverage_sketch needs m >= d (or m == 0)");
+  if (t < 0 || A.d * t >= ((int64_t)1 << 31))
+    return fail(PSK_EINVAL, "t must be >= 0 with d * t < 2^31");
+  if (m > 0 && prec != PSK_PREC_F64 && prec != PSK_PREC_BF16 && prec != PSK_PREC_FP8)
+    return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
+  return 0;
+}
+
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k,
                        int prec, size_t *bytes) {
   if (!bytes) return fail(PSK_EINVAL, "bytes is NULL");
@@ -269,6 +285,10 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
       if (m < A->d || m >= ((int64_t)1 << 31))
         return fail(PSK_EINVAL, "lsq_sketch_solve needs d <= m < 2^31");
       rc = lsq_sketch_solve_impl(*A, nullptr, nullptr, m, r, 0, prec, ws, nullptr);
+      break;
+    case PSK_OP_LEVERAGE_SKETCH:
+      if ((rc = check_leverage_sketch(*A, m, r, k, prec))) return rc;
+      rc = leverage_sketch_impl(*A, m, r, k, 0, prec, nullptr, true, ws, nullptr);
       break;
     default:
       return fail(PSK_EINVAL, "unknown op");
@@ -375,6 +395,21 @@ int lsq_sketch_solve(const psk_mat *A, const double *b, double *x, int64_t m, in
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LSQ_SKETCH)");
   Arena ws = Arena::over(wsp, ws_bytes);
   return lsq_sketch_solve_impl(*A, b, x, m, r, seed, prec, ws, as_stream(stream));
+}
+
+int leverage_sketch(const psk_mat *A, int64_t m, int64_t r, int64_t t, uint64_t seed, int prec,
+                    double *theta, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if ((rc = check_leverage_sketch(*A, m, r, t, prec))) return rc;
+  if (!theta) return fail(PSK_EINVAL, "theta is NULL");
+  Arena plan;
+  if ((rc = leverage_sketch_impl(*A, m, r, t, seed, prec, nullptr, true, plan, nullptr)))
+    return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LEVERAGE_SKETCH)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return leverage_sketch_impl(*A, m, r, t, seed, prec, theta, true, ws, as_stream(stream));
 }
 
 int gram(double alpha, const psk_mat *A, double beta, void *C, void *wsp,

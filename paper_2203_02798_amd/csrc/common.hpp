@@ -137,10 +137,12 @@ __host__ __device__ __forceinline__ void bm_sincospi(double z, double &sn, doubl
 }
 
 // Four unscaled standard normals z0..z3 for buckets 4q .. 4q+3 of Gaussian
-// row a (Box-Muller on two pairs of uniforms in (0,1)), FP64.
+// row a (Box-Muller on two pairs of uniforms in (0,1)), FP64.  Counter word 3
+// is the stream: 1 for G, 2 for the JL matrix of the leverage estimate (the
+// hash uses 0).
 __host__ __device__ __forceinline__ void gauss4_f64(uint64_t q, uint32_t a, uint64_t seed,
-                                           double z[4]) {
-  const u32x4 x = philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), a, 1u,
+                                           double z[4], uint32_t stream = 1u) {
+  const u32x4 x = philox4x32_10((uint32_t)q, (uint32_t)(q >> 32), a, stream,
                                 (uint32_t)seed, (uint32_t)(seed >> 32));
   const double s = 2.3283064365386963e-10;  // 2^-32
   const double u0 = ((double)x.x0 + 0.5) * s;

@@ -176,6 +176,13 @@ int lsq_gram_impl(const psk_mat &A, const double *b, double *x, Arena &ws, hipSt
 int lsq_sketch_solve_impl(const psk_mat &A, const double *b, double *x, int64_t m, int64_t r,
                           uint64_t seed, int prec, Arena &ws, hipStream_t st);
 
+// ---- leverage scores from a sketch (k_leverage.hip) -------------------------
+// theta_i = ||e_i^T A X||^2, X = R^{-1} (t == 0) or R^{-1} Pi (d x t), R from
+// sketch_qr of G S A (m > 0) or S A (m == 0).  check_rank: synchronise the
+// stream and return PSK_ERANK when a Cholesky pivot was not positive.
+int leverage_sketch_impl(const psk_mat &A, int64_t m, int64_t r, int64_t t, uint64_t seed,
+                         int prec, double *theta, bool check_rank, Arena &ws, hipStream_t st);
+
 // ---- LSQR (k_lsqr.hip) -----------------------------------------------------
 int lsq_impl(const psk_mat &A, const double *b, double *x,
              const psk_lsq_opts &o, psk_lsq_info *info, Arena &ws,

@@ -101,24 +101,11 @@ struct Job {
   bool done = false;
 };
 
-// Workspace plan of a leverage request: C (m x d), R, R^{-1} (d x d) and the
-// largest of the sketch, factorization and row-norm workspaces.
+// A leverage request: leverage_sketch without the JL step and without the
+// rank check (which would synchronise the slot's stream mid-request).
 int leverage_run(const psk_request &q, Arena &ws, hipStream_t st) {
-  const psk_mat &A = q.A;
-  const int64_t m = q.opts.m, d = A.d;
-  double *C = ws.take<double>((size_t)m * d);
-  double *R = ws.take<double>((size_t)d * d);
-  double *Ri = ws.take<double>((size_t)d * d);
-  const size_t mk = ws.mark();
-  int rc;
-  if ((rc = do_sketch_gcs(A, m, q.opts.r, q.opts.seed, q.opts.prec, C, ws, st))) return rc;
-  ws.release(mk);
-  if ((rc = sketch_qr_impl(C, m, d, R, Ri, ws, st))) return rc;
-  ws.release(mk);
-  rc = A.format == PSK_DENSE ? rownorms_dense(1.0, A, Ri, d, 0.0, q.out, ws, st)
-                             : rownorms_csr(1.0, A, Ri, d, 0.0, q.out, ws, st);
-  ws.release(mk);
-  return rc;
+  return leverage_sketch_impl(q.A, q.opts.m, q.opts.r, 0, q.opts.seed, q.opts.prec, q.out,
+                              false, ws, st);
 }
 
 int plan_request(const psk_request &q, size_t *bytes) {

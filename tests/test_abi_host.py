@@ -109,6 +109,24 @@ def test_workspace_planning(lib):
     assert st == -1
     st, _ = _ws(L.PSK_OP_LEVERAGE_GRAM, _dense(50000, 5000))
     assert st == -7  # d > 4096
+    # sketched leverage: the sketch (m x d, or r x d for S A alone), two
+    # copies for the QR passes; the JL step adds Pi and R^{-1} Pi (d x t each)
+    st, s1 = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=200, r=2500, k=0)
+    assert st == 0 and s1 >= 3 * 200 * 50 * 8
+    st, s2 = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=200, r=2500, k=16)
+    assert st == 0 and s2 >= s1
+    st, s3 = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=0, r=2500, k=0)
+    assert st == 0 and s3 >= 3 * 2500 * 50 * 8
+    st, _ = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=0, r=40)  # r < d
+    assert st == -1
+    st, _ = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=30, r=2500)  # m < d
+    assert st == -1
+    st, _ = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=64, r=2500, k=-1)
+    assert st == -1
+    st, _ = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=64, r=2500, prec=4)
+    assert st == -2
+    st, _ = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=0, r=2500, prec=4)
+    assert st == 0  # prec is not read without the Gaussian stage
 
 
 def test_rejects_bad_arguments_without_device_work(lib):
@@ -138,6 +156,16 @@ def test_rejects_bad_arguments_without_device_work(lib):
                                 stream) == -1  # m < d
     assert lib.lsq_sketch_solve(ctypes.byref(good), sa, sa, 8, 16, 0, 3, ws, 1 << 20,
                                 stream) == -2  # prec
+    assert lib.leverage_sketch(ctypes.byref(good), 8, 16, 0, 0, 0, None, ws, 1 << 20,
+                               stream) == -1  # theta
+    assert lib.leverage_sketch(ctypes.byref(good), 4, 16, 0, 0, 0, sa, ws, 1 << 20,
+                               stream) == -1  # m < d
+    assert lib.leverage_sketch(ctypes.byref(good), 0, 4, 0, 0, 0, sa, ws, 1 << 20,
+                               stream) == -1  # m == 0 and r < d
+    assert lib.leverage_sketch(ctypes.byref(good), 8, 16, 0, 0, 7, sa, ws, 1 << 20,
+                               stream) == -2  # prec
+    assert lib.leverage_sketch(ctypes.byref(good), 8, 16, 4, 0, 0, sa, ws, 16,
+                               stream) == -3  # workspace
     assert lib.cs_hash(0, 10, 0, 0, None, None, stream) == -1
     assert lib.cs_hash(-1, 10, 5, 0, None, None, stream) == -1
     assert lib.sketch_qr(sa, 3, 5, sa, sa, ws, 1 << 20, stream) == -1

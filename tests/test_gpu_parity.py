@@ -506,6 +506,69 @@ def test_leverage_pipeline(api, kind):
     assert abs(th.sum() - d) < 0.5 * d
 
 
+# Algorithm ls_approximate_drineas in one call, with and without the JL step.
+# FP64 bar: R from the device's QR differs from LAPACK's by cond(C) u times a
+# modest factor, so theta agrees to 1e-9 relative; FP32 A is summed into S A
+# in FP32 (u = 6e-8, buckets of ~n/r rows), which moves theta by ~1e-6.
+@pytest.mark.parametrize("kind,n,d,m,r,t", [
+    ("dense", 20000, 50, 200, 2500, 0),
+    ("dense", 20000, 50, 200, 2500, 16),
+    ("dense", 20000, 50, 200, 2500, 100),    # t > 64 (wide row-norm tiles), t > d
+    ("dense", 6000, 130, 0, 3001, 37),       # S A alone (m == 0), ragged t
+    ("csr:0.02", 100000, 64, 256, 8192, 32),
+    ("csr:0.02", 100000, 64, 0, 8192, 0),
+    ("csr", 100000, 500, 640, 25000, 48),    # the sparse Gaussian product
+    ("dense32", 8000, 96, 129, 1024, 24),
+    ("dense32", 8000, 20, 0, 1024, 5),       # FP32 S A widened to FP64
+    ("dense", 500, 1, 3, 7, 1)])             # d = 1, t = 1
+def test_leverage_sketch_f64(api, kind, n, d, m, r, t):
+    _say(f"leverage_sketch {kind} n={n} d={d} m={m} r={r} t={t}")
+    a = _gcs_input(kind, n, d)
+    th = api.leverage_sketch(to_device(a), m, r, seed=13, t=t).cpu().numpy()
+    ref = olev.leverage_sketched_jl(a, m, r, t, 13)
+    z = ref == 0
+    assert np.array_equal(th[z], ref[z])  # empty rows: exactly 0
+    err = np.abs(th[~z] / ref[~z] - 1).max()
+    _say(f"  max rel err {err:.3e}, sum {th.sum():.6f}")
+    assert err <= (2e-5 if kind == "dense32" else 1e-9)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("kind,n,d,m,r,t", [
+    ("dense", 20000, 50, 200, 2500, 16),
+    ("csr:2e-3", 200000, 64, 256, 32768, 32)])
+def test_leverage_sketch_reduced(api, prec, kind, n, d, m, r, t):
+    """Against the oracle's scores from the quantised-operand sketch: the
+    sketch's kernel arithmetic (normwise ~1e-6 BF16, <= 5e-4 FP8) times a
+    small multiple of cond(C)."""
+    _say(f"leverage_sketch {prec} {kind} n={n} d={d} m={m} r={r} t={t}")
+    a = _gcs_input(kind, n, d)
+    th = api.leverage_sketch(to_device(a), m, r, seed=13, t=t, prec=prec).cpu().numpy()
+    q = osk.sketch_gcs_bf16_reference if prec == "bf16" else osk.sketch_gcs_fp8_reference
+    ref = olev.leverage_from_sketch(a, q(a, m, r, 13), t, 13)
+    z = ref == 0
+    assert np.array_equal(th[z], ref[z])
+    err = np.abs(th[~z] / ref[~z] - 1).max()
+    _say(f"  max rel err vs quantised reference {err:.3e}")
+    assert err <= (1e-3 if prec == "bf16" else 1e-2)
+
+
+def test_leverage_sketch_matches_composed_calls(api):
+    """t = 0 is sketch_gcs, sketch_qr and rownorms_sq in sequence, bit for bit."""
+    a = to_device(synth.csr_uniform(100000, 64, 0.05, seed=5))
+    th = api.leverage_sketch(a, 256, 8192, seed=9, t=0, prec="bf16")
+    _, ri = api.sketch_qr(api.sketch_gcs(a, 256, 8192, seed=9, prec="bf16"))
+    assert torch.equal(th, api.rownorms_sq(a, ri))
+
+
+def test_leverage_sketch_reports_rank_deficiency(api):
+    a = synth.dense_gaussian(3000, 12, seed=1)
+    a[:, 7] = 0.0
+    with pytest.raises(RuntimeError, match="rank|ERANK"):
+        api.leverage_sketch(to_device(a), 0, 400, seed=2, t=4)
+        torch.cuda.synchronize()
+
+
 def test_lsq_solve_with_precomputed_preconditioner(api):
     a, b, _ = synth.lsq_problem(20000, 40, 1e5, seed=4)
     ad = to_device(a)
