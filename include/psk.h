@@ -19,6 +19,8 @@
  *   lsq_solve    min ||A x - b|| by sketch-and-precondition  (Alg. least_squares_precondition)
  *   leverage_sketch  approximate leverage scores, optionally    (Alg. ls_approximate_drineas)
  *                    through a JL matrix Pi
+ *   css_select   k columns by a pivoted QR of the sketch     (Alg. cgrrqr)
+ *   leverage_css leverage scores of the selected columns     (Alg. ls_hrn_exact)
  *   leverage_gram, lsq_gram, lsq_sketch_solve, sketch_g: section 4's direct
  *                    solvers and exact leverage scores, and Gaussian sketching
  *
@@ -132,7 +134,9 @@ enum {
   PSK_OP_LEVERAGE_GRAM = 7,
   PSK_OP_LSQ_GRAM = 8,
   PSK_OP_LSQ_SKETCH = 9,
-  PSK_OP_LEVERAGE_SKETCH = 10
+  PSK_OP_LEVERAGE_SKETCH = 10,
+  PSK_OP_CSS = 11,
+  PSK_OP_LEVERAGE_CSS = 12
 };
 
 /* Library version string (static storage). */
@@ -146,9 +150,12 @@ const char *psk_last_error(void);
  *   A    : the matrix the call will get (for PSK_OP_QR only A->n = m rows and
  *          A->d = d columns of the sketch are read);
  *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ,
- *          LSQ_SKETCH, LEVERAGE_SKETCH; SKETCH_G reads m only);
- *   k    : columns of B (ROWNORMS), columns t of Pi (LEVERAGE_SKETCH);
- *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ, LSQ_SKETCH, LEVERAGE_SKETCH).
+ *          LSQ_SKETCH, LEVERAGE_SKETCH, CSS, LEVERAGE_CSS; SKETCH_G reads m
+ *          only);
+ *   k    : columns of B (ROWNORMS), columns t of Pi (LEVERAGE_SKETCH),
+ *          columns selected (CSS, LEVERAGE_CSS);
+ *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ, LSQ_SKETCH, LEVERAGE_SKETCH,
+ *          CSS, LEVERAGE_CSS).
  * For PSK_OP_LSQ, m == 0 sizes a call that passes its own opts->Rinv.
  * Arguments an op does not use are ignored. */
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r,
@@ -301,6 +308,36 @@ int lsq_solve(const psk_mat *A, const double *b, double *x,
  * is still written). */
 int leverage_sketch(const psk_mat *A, int64_t m, int64_t r, int64_t t, uint64_t seed, int prec,
                     double *theta, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- column subset selection (section 4.1) -------------------------------
+ * The sketch B is G S A (m > 0, d <= m < 2^31) or S A (m == 0, r >= d), as
+ * sketch_gcs with this seed and prec (an FP32 S A is widened to FP64), and
+ * 1 <= k <= d <= 4096.  The pivoted QR is the column-pivoted Householder QR
+ * of Businger and Golub (as LAPACK geqp3): step j takes the remaining column
+ * of B whose rows j .. end have the largest norm (lowest index on equal
+ * norms; norms recomputed exactly at each step), and a Householder reflector
+ * zeroes that column below row j in every remaining column.  One kernel
+ * launch per step; B is copied to a column-major workspace first. */
+
+/* cols[0..k) = the first k pivots of the pivoted QR of B, in order (Algorithm
+ * cgrrqr: the "top-k" columns of A).
+ *   cols : k int32 (device, written).
+ * Errors: PSK_EINVAL (shapes, k out of range, NULL cols), PSK_EDTYPE (prec,
+ * when m > 0), PSK_EUNSUPPORTED (d > 4096; as sketch_cs), PSK_ENOMEM. */
+int css_select(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,
+               int32_t *cols, void *ws, size_t ws_bytes, void *stream);
+
+/* theta_i = leverage score of row i of A[:, K], K = css_select(A, m, r, k,
+ * seed, prec) (Algorithm ls_hrn_exact; exact for A when k = rank(A) = d):
+ * the K x K block of the FP64 Gram matrix A^T A, its Cholesky factor R_K, and
+ * theta_i = ||e_i^T A B||^2 with B (d x k) holding R_K^{-1} at the rows K.
+ *   theta : n FP64 (device, written);  cols : k int32 (device, written) or
+ *   NULL.
+ * The call synchronises the stream once, to read the pivot flag.
+ * Errors: as css_select, plus PSK_ERANK (A[:, K] numerically rank deficient;
+ * theta still written). */
+int leverage_css(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,
+                 double *theta, int32_t *cols, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- direct solvers and exact leverage scores ---------------------------
  * Section 4's Gram-based and sketch-and-solve algorithms.  A triangular

@@ -58,6 +58,34 @@ def qrcp_pivots(b, k=None):
     return piv, rdiag
 
 
+def qrcp_replay(b, piv):
+    """The pivoted QR of b forced to take the columns piv in order: for each
+    step, (squared residual norm of the column taken, largest squared
+    residual norm among the remaining columns).  A pivot sequence is a valid
+    outcome of the selection when the two agree at every step up to rounding."""
+    w = np.array(b, dtype=np.float64, copy=True)
+    m, d = w.shape
+    live = np.ones(d, dtype=bool)
+    took = np.empty(len(piv))
+    best = np.empty(len(piv))
+    for j, p in enumerate(piv):
+        norms2 = np.sum(w[j:, :] ** 2, axis=0)
+        took[j] = norms2[p]
+        best[j] = norms2[live].max()
+        live[p] = False
+        nx = np.sqrt(norms2[p])
+        if nx == 0.0:
+            continue
+        x = w[j:, p].copy()
+        alpha = x[0]
+        beta = -nx if alpha >= 0 else nx
+        x[0] = alpha - beta
+        vtv = 2.0 * beta * (beta - alpha)
+        cols = np.flatnonzero(live)
+        w[j:, cols] -= np.outer(x, 2.0 * (x @ w[j:, cols]) / vtv)
+    return took, best
+
+
 def qrcp_pivots_by_projection(b, k=None):
     """The same selection by its definition, for tiny inputs: at each step
     the column of b farthest from the span of the columns already chosen

@@ -25,11 +25,12 @@ PSK_F64, PSK_F32 = 0, 1
 PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 (PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
  PSK_OP_LSQ, PSK_OP_SKETCH_G, PSK_OP_LEVERAGE_GRAM, PSK_OP_LSQ_GRAM,
- PSK_OP_LSQ_SKETCH, PSK_OP_LEVERAGE_SKETCH) = range(11)
+ PSK_OP_LSQ_SKETCH, PSK_OP_LEVERAGE_SKETCH, PSK_OP_CSS, PSK_OP_LEVERAGE_CSS) = range(13)
 
 EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq", "sketch_qr",
-            "lsq_solve", "leverage_sketch", "leverage_gram", "lsq_gram", "lsq_sketch_solve",
+            "lsq_solve", "leverage_sketch", "css_select", "leverage_css", "leverage_gram",
+            "lsq_gram", "lsq_sketch_solve",
             "psk_timing_enable", "psk_timing_reset",
             "psk_timing_collect", "psk_timing_names", "psk_server_create",
             "psk_server_submit", "psk_server_wait", "psk_server_poll",
@@ -153,6 +154,10 @@ _SIGS = {
                    _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "leverage_sketch": ([_PM, _i64, _i64, _i64, _u64, ctypes.c_int, _vp, _vp, ctypes.c_size_t,
                          _vp], ctypes.c_int),
+    "css_select": ([_PM, _i64, _i64, _i64, _u64, ctypes.c_int, _vp, _vp, ctypes.c_size_t, _vp],
+                   ctypes.c_int),
+    "leverage_css": ([_PM, _i64, _i64, _i64, _u64, ctypes.c_int, _vp, _vp, _vp, ctypes.c_size_t,
+                      _vp], ctypes.c_int),
     "leverage_gram": ([_PM, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "lsq_gram": ([_PM, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "lsq_sketch_solve": ([_PM, _vp, _vp, _i64, _i64, _u64, ctypes.c_int, _vp, ctypes.c_size_t,

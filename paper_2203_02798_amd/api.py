@@ -182,6 +182,32 @@ def leverage_sketch(A, m, r, seed, t=0, prec="f64", out=None):
     return out
 
 
+def css_select(A, m, r, k, seed, prec="f64"):
+    """The k columns (int32 device tensor, in pivot order) that the pivoted QR
+    of the sketch (G S A, or S A when m == 0) picks first."""
+    pm = _mat(A)
+    dev = _device(A)
+    cols = torch.empty(k, dtype=torch.int32, device=dev)
+    ws = _ws(workspace_size(L.PSK_OP_CSS, A, m=m, r=r, k=k, prec=prec), dev)
+    L.check(L.lib().css_select(ctypes.byref(pm), m, r, k, seed, _PREC[prec], cols.data_ptr(),
+                               ws.data_ptr(), ws.numel(), _stream(dev)), "css_select")
+    return cols
+
+
+def leverage_css(A, m, r, k, seed, prec="f64"):
+    """(theta, cols): exact leverage scores of A[:, cols] (n float64) for the
+    k columns css_select picks."""
+    pm = _mat(A)
+    dev = _device(A)
+    theta = torch.empty(pm.n, dtype=torch.float64, device=dev)
+    cols = torch.empty(k, dtype=torch.int32, device=dev)
+    ws = _ws(workspace_size(L.PSK_OP_LEVERAGE_CSS, A, m=m, r=r, k=k, prec=prec), dev)
+    L.check(L.lib().leverage_css(ctypes.byref(pm), m, r, k, seed, _PREC[prec], theta.data_ptr(),
+                                 cols.data_ptr(), ws.data_ptr(), ws.numel(), _stream(dev)),
+            "leverage_css")
+    return theta, cols
+
+
 def leverage_gram(A, out=None):
     """Exact leverage scores of A (n float64) from its Gram matrix."""
     pm = _mat(A)

@@ -223,6 +223,15 @@ static int check_leverage_sketch(const psk_mat &A, int64_t m, int64_t r, int64_t
   return 0;
 }
 
+// Shapes of the column subset selection: the sketch as for leverage_sketch,
+// 1 <= k <= d <= 4096.
+static int check_css(const psk_mat &A, int64_t m, int64_t r, int64_t k, int prec) {
+  int rc = check_leverage_sketch(A, m, r, 0, prec);
+  if (rc) return rc;
+  if (k < 1 || k > A.d) return fail(PSK_EINVAL, "k must be in [1, d]");
+  return 0;
+}
+
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k,
                        int prec, size_t *bytes) {
   if (!bytes) return fail(PSK_EINVAL, "bytes is NULL");
@@ -289,6 +298,14 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
     case PSK_OP_LEVERAGE_SKETCH:
       if ((rc = check_leverage_sketch(*A, m, r, k, prec))) return rc;
       rc = leverage_sketch_impl(*A, m, r, k, 0, prec, nullptr, true, ws, nullptr);
+      break;
+    case PSK_OP_CSS:
+      if ((rc = check_css(*A, m, r, k, prec))) return rc;
+      rc = css_select_impl(*A, m, r, k, 0, prec, nullptr, ws, nullptr);
+      break;
+    case PSK_OP_LEVERAGE_CSS:
+      if ((rc = check_css(*A, m, r, k, prec))) return rc;
+      rc = leverage_css_impl(*A, m, r, k, 0, prec, nullptr, nullptr, ws, nullptr);
       break;
     default:
       return fail(PSK_EINVAL, "unknown op");
@@ -410,6 +427,36 @@ int leverage_sketch(const psk_mat *A, int64_t m, int64_t r, int64_t t, uint64_t 
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LEVERAGE_SKETCH)");
   Arena ws = Arena::over(wsp, ws_bytes);
   return leverage_sketch_impl(*A, m, r, t, seed, prec, theta, true, ws, as_stream(stream));
+}
+
+int css_select(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,
+               int32_t *cols, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if ((rc = check_css(*A, m, r, k, prec))) return rc;
+  if (!cols) return fail(PSK_EINVAL, "cols is NULL");
+  Arena plan;
+  if ((rc = css_select_impl(*A, m, r, k, seed, prec, nullptr, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_CSS)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return css_select_impl(*A, m, r, k, seed, prec, cols, ws, as_stream(stream));
+}
+
+int leverage_css(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,
+                 double *theta, int32_t *cols, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if ((rc = check_css(*A, m, r, k, prec))) return rc;
+  if (!theta) return fail(PSK_EINVAL, "theta is NULL");
+  Arena plan;
+  // planned without the caller's cols, so the bound covers both forms
+  if ((rc = leverage_css_impl(*A, m, r, k, seed, prec, nullptr, nullptr, plan, nullptr)))
+    return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LEVERAGE_CSS)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return leverage_css_impl(*A, m, r, k, seed, prec, theta, cols, ws, as_stream(stream));
 }
 
 int gram(double alpha, const psk_mat *A, double beta, void *C, void *wsp,

@@ -182,6 +182,19 @@ int lsq_sketch_solve_impl(const psk_mat &A, const double *b, double *x, int64_t 
 // stream and return PSK_ERANK when a Cholesky pivot was not positive.
 int leverage_sketch_impl(const psk_mat &A, int64_t m, int64_t r, int64_t t, uint64_t seed,
                          int prec, double *theta, bool check_rank, Arena &ws, hipStream_t st);
+// The sketch as an FP64 operand of the factorizations: G S A (m > 0, m x d)
+// or S A (m == 0, r x d; an FP32 S A is widened).
+int sketch_f64(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec, double *C,
+               Arena &ws, hipStream_t st);
+
+// ---- column subset selection (k_css.hip) ------------------------------------
+// cols[0..k): the first k pivots of the column-pivoted QR of the sketch.
+int css_select_impl(const psk_mat &A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,
+                    int32_t *cols, Arena &ws, hipStream_t st);
+// theta: exact leverage scores of A[:, cols] for those k columns (cols may be
+// NULL: kept in the workspace).
+int leverage_css_impl(const psk_mat &A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,
+                      double *theta, int32_t *cols, Arena &ws, hipStream_t st);
 
 // ---- LSQR (k_lsqr.hip) -----------------------------------------------------
 int lsq_impl(const psk_mat &A, const double *b, double *x,

@@ -46,6 +46,23 @@ __global__ __launch_bounds__(256) void k_widen_f32(const float *__restrict__ src
 
 }  // namespace
 
+int sketch_f64(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec, double *C,
+               Arena &ws, hipStream_t st) {
+  if (m > 0 || A.dtype == PSK_F64) return do_sketch_gcs(A, m, r, seed, prec, C, ws, st);
+  // S A in FP32 (the dtype of A), widened for the FP64 factorizations
+  const size_t mk = ws.mark();
+  float *sa = ws.take<float>((size_t)r * A.d);
+  int rc = do_sketch_cs(A, r, seed, sa, ws, st);
+  if (rc) return rc;
+  if (!ws.dry()) {
+    const int64_t cnt = r * A.d;
+    const unsigned blocks = (unsigned)(ceil_div(cnt, 256) < 8192 ? ceil_div(cnt, 256) : 8192);
+    k_widen_f32<<<blocks, 256, 0, st>>>(sa, cnt, C);
+  }
+  ws.release(mk);
+  return 0;
+}
+
 int leverage_sketch_impl(const psk_mat &A, int64_t m, int64_t r, int64_t t, uint64_t seed,
                          int prec, double *theta, bool check_rank, Arena &ws, hipStream_t st) {
   const int64_t d = A.d;
@@ -60,18 +77,7 @@ int leverage_sketch_impl(const psk_mat &A, int64_t m, int64_t r, int64_t t, uint
   if (run && !ws.ok()) return fail(PSK_ENOMEM, "workspace too small for leverage_sketch");
   const size_t mk = ws.mark();
   int rc;
-  if (m > 0 || A.dtype == PSK_F64) {
-    if ((rc = do_sketch_gcs(A, m, r, seed, prec, C, ws, st))) return rc;
-  } else {
-    // S A in FP32 (the dtype of A), widened for the FP64 factorization
-    float *sa = ws.take<float>((size_t)r * d);
-    if ((rc = do_sketch_cs(A, r, seed, sa, ws, st))) return rc;
-    if (run) {
-      const int64_t cnt = r * d;
-      const unsigned blocks = (unsigned)(ceil_div(cnt, 256) < 8192 ? ceil_div(cnt, 256) : 8192);
-      k_widen_f32<<<blocks, 256, 0, st>>>(sa, cnt, C);
-    }
-  }
+  if ((rc = sketch_f64(A, m, r, seed, prec, C, ws, st))) return rc;
   ws.release(mk);
   int *flag = nullptr;
   if ((rc = sketch_qr_impl(C, rows, d, R, Ri, ws, st, &flag))) return rc;

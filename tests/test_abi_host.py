@@ -127,6 +127,17 @@ def test_workspace_planning(lib):
     assert st == -2
     st, _ = _ws(L.PSK_OP_LEVERAGE_SKETCH, _dense(20000, 50), m=0, r=2500, prec=4)
     assert st == 0  # prec is not read without the Gaussian stage
+    # column subset selection: the sketch and its column-major copy; the
+    # leverage scores add the d x d Gram matrix
+    st, c1 = _ws(L.PSK_OP_CSS, _dense(20000, 50), m=100, r=2500, k=10)
+    assert st == 0 and c1 >= 2 * 100 * 50 * 8
+    st, c2 = _ws(L.PSK_OP_LEVERAGE_CSS, _dense(20000, 50), m=100, r=2500, k=10)
+    assert st == 0 and c2 >= c1 + 50 * 50 * 8
+    for k in (0, 51):
+        st, _ = _ws(L.PSK_OP_CSS, _dense(20000, 50), m=100, r=2500, k=k)
+        assert st == -1
+    st, _ = _ws(L.PSK_OP_CSS, _csr(1000, 5000, 100), m=6000, r=8000, k=3)
+    assert st == -7  # d > 4096
 
 
 def test_rejects_bad_arguments_without_device_work(lib):
@@ -166,6 +177,15 @@ def test_rejects_bad_arguments_without_device_work(lib):
                                stream) == -2  # prec
     assert lib.leverage_sketch(ctypes.byref(good), 8, 16, 4, 0, 0, sa, ws, 16,
                                stream) == -3  # workspace
+    assert lib.css_select(ctypes.byref(good), 8, 16, 3, 0, 0, None, ws, 1 << 20,
+                          stream) == -1  # cols
+    assert lib.css_select(ctypes.byref(good), 8, 16, 6, 0, 0, sa, ws, 1 << 20,
+                          stream) == -1  # k > d
+    assert lib.css_select(ctypes.byref(good), 8, 16, 3, 0, 0, sa, ws, 16, stream) == -3
+    assert lib.leverage_css(ctypes.byref(good), 8, 16, 3, 0, 0, None, None, ws, 1 << 20,
+                            stream) == -1  # theta
+    assert lib.leverage_css(ctypes.byref(good), 8, 16, 3, 0, 9, sa, None, ws, 1 << 20,
+                            stream) == -2  # prec
     assert lib.cs_hash(0, 10, 0, 0, None, None, stream) == -1
     assert lib.cs_hash(-1, 10, 5, 0, None, None, stream) == -1
     assert lib.sketch_qr(sa, 3, 5, sa, sa, ws, 1 << 20, stream) == -1

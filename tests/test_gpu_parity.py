@@ -8,6 +8,7 @@ import scipy.sparse as sp
 import synth
 from helpers import U32, U64, gamma, rel_fro, sketch_abs_bound, to_device
 from oracle import gram as og
+from oracle import css as ocss
 from oracle import leverage as olev
 from oracle import lsq as olsq
 from oracle import sketch as osk
@@ -566,6 +567,98 @@ def test_leverage_sketch_reports_rank_deficiency(api):
     a[:, 7] = 0.0
     with pytest.raises(RuntimeError, match="rank|ERANK"):
         api.leverage_sketch(to_device(a), 0, 400, seed=2, t=4)
+        torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# Column subset selection (Algorithm cgrrqr) and Algorithm ls_hrn_exact
+# ---------------------------------------------------------------------------
+def _css_input(kind, n, d, spread):
+    """_gcs_input with its columns scaled by a permuted geometric sequence
+    from 1 to 1/spread (spread 1: unscaled), so that the pivots have margins."""
+    a = _gcs_input(kind, n, d)
+    if spread == 1:
+        return a
+    sc = np.logspace(0, -np.log10(spread), d)[np.random.default_rng(3).permutation(d)]
+    if sp.issparse(a):
+        return (a @ sp.diags(sc)).tocsr().astype(a.dtype)
+    return (a * sc).astype(a.dtype)
+
+
+def _check_pivots(dev, b, k, tol):
+    """dev equals the oracle's pivots, or (near ties) is a valid outcome: at
+    every step the column taken has the largest residual norm up to tol."""
+    ref, _ = ocss.qrcp_pivots(b, k)
+    assert len(set(dev.tolist())) == k and dev.min() >= 0 and dev.max() < b.shape[1]
+    if np.array_equal(dev, ref):
+        return 0
+    took, best = ocss.qrcp_replay(b, dev)
+    assert np.all(took >= best * (1 - tol)), (dev, ref)
+    return int(np.argmax(dev != ref))
+
+
+@pytest.mark.parametrize("kind,n,d,m,r,k,spread", [
+    ("dense", 20000, 50, 200, 2500, 50, 100.0),    # all d pivots
+    ("dense", 20000, 50, 100, 2500, 20, 1.0),      # unscaled: near ties allowed
+    ("dense", 6000, 130, 0, 3001, 40, 1e3),        # S A alone (m == 0)
+    ("csr:0.02", 100000, 64, 256, 8192, 20, 10.0),
+    ("csr", 100000, 500, 1000, 25000, 100, 1e3),   # m = 2d (the algorithm's choice)
+    ("dense32", 8000, 96, 200, 1024, 96, 1e2),
+    ("dense", 500, 1, 3, 7, 1, 1.0)])              # d = 1
+def test_css_select(api, kind, n, d, m, r, k, spread):
+    _say(f"css_select {kind} n={n} d={d} m={m} r={r} k={k} spread={spread}")
+    a = _css_input(kind, n, d, spread)
+    dev = api.css_select(to_device(a), m, r, k, seed=17).cpu().numpy().astype(np.int64)
+    b = osk.sketch_gcs(a, m, r, 17)
+    # FP32 A: S A is summed in FP32, the sketch differs at ~1e-7
+    first = _check_pivots(dev, b, k, 1e-4 if kind == "dense32" else 1e-10)
+    _say(f"  pivots equal to the oracle's up to step {first or k}")
+    if spread > 1 and kind != "dense32":
+        assert first == 0
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_css_select_reduced(api, prec):
+    a = _css_input("dense", 20000, 50, 1e2)
+    dev = api.css_select(to_device(a), 200, 2500, 30, seed=17, prec=prec).cpu().numpy()
+    q = osk.sketch_gcs_bf16_reference if prec == "bf16" else osk.sketch_gcs_fp8_reference
+    _check_pivots(dev.astype(np.int64), q(a, 200, 2500, 17), 30, 1e-3)
+
+
+def test_css_select_zero_columns_last(api):
+    a = synth.dense_gaussian(5000, 12, seed=3)
+    a[:, [2, 9]] = 0.0
+    dev = api.css_select(to_device(a), 48, 600, 12, seed=1).cpu().numpy()
+    np.testing.assert_array_equal(dev[10:], [2, 9])
+
+
+@pytest.mark.parametrize("kind,n,d,m,r,k", [
+    ("dense", 20000, 50, 100, 2500, 50),     # k = d: the exact scores of A
+    ("dense", 20000, 50, 100, 2500, 12),
+    ("csr:0.02", 100000, 64, 128, 8192, 30),
+    ("csr", 100000, 500, 1000, 25000, 100),
+    ("dense32", 8000, 96, 200, 1024, 40)])
+def test_leverage_css(api, kind, n, d, m, r, k):
+    _say(f"leverage_css {kind} n={n} d={d} m={m} r={r} k={k}")
+    a = _css_input(kind, n, d, 100.0)
+    th, cols = api.leverage_css(to_device(a), m, r, k, seed=5)
+    ref, rcols = ocss.leverage_css(a, m, r, k, 5)
+    np.testing.assert_array_equal(cols.cpu().numpy(), rcols)
+    th = th.cpu().numpy()
+    # the Gram route: cond(A[:, K])^2 u, cond <= ~1e2 here (column spread)
+    err = np.abs(th - ref).max()
+    _say(f"  max |dtheta| {err:.3e}, sum {th.sum():.10f}")
+    assert err <= 1e-8
+    assert abs(th.sum() - k) <= 1e-8 * k
+    if k == d:
+        assert np.abs(th - olev.leverage_exact(a)).max() <= 1e-8
+
+
+def test_leverage_css_reports_rank_deficiency(api):
+    a = synth.dense_gaussian(3000, 10, seed=2)
+    a[:, 4] = 0.0
+    with pytest.raises(RuntimeError, match="rank|ERANK"):
+        api.leverage_css(to_device(a), 40, 500, 10, seed=1)
         torch.cuda.synchronize()
 
 

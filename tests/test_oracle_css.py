@@ -37,6 +37,18 @@ def test_qrcp_matches_selection_by_projection():
                                   ocss.qrcp_pivots_by_projection(b, 5))
 
 
+def test_qrcp_replay_accepts_its_own_pivots_and_flags_others():
+    b = _scaled(60, 15, 7)
+    piv, rdiag = ocss.qrcp_pivots(b)
+    took, best = ocss.qrcp_replay(b, piv)
+    np.testing.assert_allclose(took, best, rtol=1e-13)
+    np.testing.assert_allclose(np.sqrt(took), rdiag, rtol=1e-13)
+    bad = piv.copy()
+    bad[[2, 3]] = bad[[3, 2]]
+    took, best = ocss.qrcp_replay(b, bad)
+    assert took[2] < best[2] * (1 - 1e-6)
+
+
 def test_qrcp_reveals_rank_and_orders_the_diagonal():
     rng = np.random.default_rng(4)
     base = rng.standard_normal((50, 5))
