@@ -279,6 +279,35 @@ def leverage_jl_bench(api, torch, steps, warmup, n=4_000_000, d=256, r=65536, m=
     return out
 
 
+def css_bench(api, torch, A, d, r, seed, steps, warmup):
+    """Column subset selection on the bench matrix with the algorithm's own
+    sketch sizes (m = 2d Gaussian rows; r = d^2 buckets is the bench's r):
+    the first k pivots for k = d/5 and k = d, and Algorithm ls_hrn_exact's
+    leverage scores of the d/5 selected columns, BF16 Gaussian product."""
+    m = 2 * d
+    kk = max(d // 5, 1)
+    calls = {
+        f"css_select_k{kk}": lambda: api.css_select(A, m, r, kk, seed, prec="bf16"),
+        f"css_select_k{d}": lambda: api.css_select(A, m, r, d, seed, prec="bf16"),
+        f"leverage_css_k{kk}": lambda: api.leverage_css(A, m, r, kk, seed, prec="bf16"),
+    }
+    out = {"m": m, "r": r, "prec": "bf16"}
+    for name, f in calls.items():
+        for _ in range(warmup):
+            f()
+        torch.cuda.synchronize()
+        with api.kernel_timing() as kt:
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                f()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / steps
+            stats = kt.stats()
+        out[name] = {"ms_per_call": 1e3 * wall,
+                     "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(stats.items())}}
+    return out
+
+
 def direct_bench(api, torch, A, a, b, bd, m, r, seed, steps, warmup, lsqr_resid):
     """The direct solvers on the same matrix: exact leverage scores and least
     squares from the Gram matrix, and sketch-and-solve with the bench's
@@ -377,7 +406,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-server measurement")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the Gaussian-only sketch, direct-solver and JL leverage measurements "
+                    help="skip the Gaussian-only sketch, direct-solver, column-selection and JL "
+                         "leverage measurements "
                          "(hardware-counter runs: one workload per kernel)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark, run 4 elementwise copies of MIB "
@@ -554,6 +584,7 @@ def main():
                                                    args.steps, args.warmup)
         rec["direct"] = direct_bench(api, torch, A, a, b, bd, m, r, seed, args.steps,
                                      args.warmup, hr["lsq"]["resid"])
+        rec["css"] = css_bench(api, torch, A, d, r, seed, args.steps, args.warmup)
         log("leverage scores with the JL step, dense FP32 4,000,000 x 256")
         rec["leverage_jl"] = leverage_jl_bench(api, torch, args.steps, args.warmup)
     if not args.no_serving:

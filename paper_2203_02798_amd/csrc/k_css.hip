@@ -64,6 +64,19 @@ __global__ __launch_bounds__(256) void k_col_norms(const double *__restrict__ Bt
   if (lane == 0) norms[c] = s;
 }
 
+// Rows per lane that k_qrcp_step keeps in registers (the rows below the
+// pivot row of up to 64 * kQrReg rows); longer columns stream through memory
+// twice.  Both forms add the same terms in the same order.
+constexpr int kQrReg = 16;
+
+// (v, i) pair reduction: the larger value, the lower index on equal values.
+__device__ __forceinline__ void argmax_merge(double &v, int &i, double v2, int i2) {
+  if (v2 > v || (v2 == v && i2 < i)) {
+    v = v2;
+    i = i2;
+  }
+}
+
 // One pivot step j.  nin: squared norms of rows j.. of the live columns, -1
 // for chosen ones; nout receives the same for step j + 1.
 __global__ __launch_bounds__(256) void k_qrcp_step(double *__restrict__ Bt, int64_t rows,
@@ -71,9 +84,9 @@ __global__ __launch_bounds__(256) void k_qrcp_step(double *__restrict__ Bt, int6
                                                    const double *__restrict__ nin,
                                                    double *__restrict__ nout,
                                                    int32_t *__restrict__ cols) {
-  __shared__ double sv[256];
-  __shared__ int si[256];
-  const int tid = threadIdx.x;
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // argmax over the live columns, lowest index on equal norms; a NaN norm
   // (non-finite input) counts as -0.5, below every other live column but
   // above the chosen ones (-1), so p is always a live column (j < d)
@@ -87,25 +100,22 @@ __global__ __launch_bounds__(256) void k_qrcp_step(double *__restrict__ Bt, int6
       bi = c;
     }
   }
-  sv[tid] = best;
-  si[tid] = bi;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) {
-      const double v2 = sv[tid + h];
-      const int i2 = si[tid + h];
-      if (v2 > sv[tid] || (v2 == sv[tid] && i2 < si[tid])) {
-        sv[tid] = v2;
-        si[tid] = i2;
-      }
-    }
-    __syncthreads();
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+    argmax_merge(best, bi, __shfl_xor(best, off, 64), __shfl_xor(bi, off, 64));
+  if (lane == 0) {
+    sv[wave] = best;
+    si[wave] = bi;
   }
-  const int p = si[0];
-  const double n2 = sv[0];
+  __syncthreads();
+  best = sv[0];
+  bi = si[0];
+#pragma unroll
+  for (int w = 1; w < 4; ++w) argmax_merge(best, bi, sv[w], si[w]);
+  const int p = bi;
+  const double n2 = best;
   // no barrier below this point
-  const int lane = tid & 63;
-  const int64_t c = (int64_t)blockIdx.x * 4 + (tid >> 6);
+  const int64_t c = (int64_t)blockIdx.x * 4 + wave;
   if (c >= d) return;
   const double nc = nin[c];
   if (nc < 0.0) {
@@ -121,29 +131,63 @@ __global__ __launch_bounds__(256) void k_qrcp_step(double *__restrict__ Bt, int6
   }
   double *col = Bt + c * rows;
   const double *x = Bt + (int64_t)p * rows;
-  double s = 0.0, v0 = 0.0;
-  if (n2 > 0.0) {
+  // reflector H = I - 2 v v^T / (v^T v), v = x - beta e_j on rows j..
+  double v0 = 0.0, vtv = 1.0;
+  const bool reflect = n2 > 0.0;
+  if (reflect) {
     const double alpha = x[j];
     const double nx = sqrt(n2);
     const double beta = alpha >= 0.0 ? -nx : nx;
     v0 = alpha - beta;
-    const double vtv = 2.0 * beta * (beta - alpha);
-    double part = 0.0;
-    for (int64_t i = j + 1 + lane; i < rows; i += 64) part = fma(x[i], col[i], part);
-    const double w = fma(v0, col[j], wave_sum(part));
-    s = 2.0 * w / vtv;
+    vtv = 2.0 * beta * (beta - alpha);
   }
-  double part2 = 0.0;
-  for (int64_t i = j + 1 + lane; i < rows; i += 64) {
-    const double y = fma(-s, x[i], col[i]);
-    col[i] = y;
-    part2 = fma(y, y, part2);
+  const double cj = col[j];
+  const int64_t i0 = j + 1 + lane;
+  double nn;
+  if (rows - (j + 1) <= 64 * kQrReg) {
+    double xr[kQrReg], cr[kQrReg];
+#pragma unroll
+    for (int t = 0; t < kQrReg; ++t) {
+      const int64_t i = i0 + 64 * t;
+      xr[t] = i < rows ? x[i] : 0.0;
+      cr[t] = i < rows ? col[i] : 0.0;
+    }
+    double s = 0.0;
+    if (reflect) {
+      double part = 0.0;
+#pragma unroll
+      for (int t = 0; t < kQrReg; ++t) part = fma(xr[t], cr[t], part);
+      s = 2.0 * fma(v0, cj, wave_sum(part)) / vtv;
+    }
+    double part2 = 0.0;
+#pragma unroll
+    for (int t = 0; t < kQrReg; ++t) {
+      const int64_t i = i0 + 64 * t;
+      const double y = fma(-s, xr[t], cr[t]);
+      if (i < rows) col[i] = y;
+      part2 = fma(y, y, part2);
+    }
+    nn = wave_sum(part2);
+    if (lane == 0) col[j] = fma(-s, v0, cj);
+  } else {
+    double s = 0.0;
+    if (reflect) {
+      double part = 0.0;
+#pragma unroll 4
+      for (int64_t i = i0; i < rows; i += 64) part = fma(x[i], col[i], part);
+      s = 2.0 * fma(v0, cj, wave_sum(part)) / vtv;
+    }
+    double part2 = 0.0;
+#pragma unroll 4
+    for (int64_t i = i0; i < rows; i += 64) {
+      const double y = fma(-s, x[i], col[i]);
+      col[i] = y;
+      part2 = fma(y, y, part2);
+    }
+    nn = wave_sum(part2);
+    if (lane == 0) col[j] = fma(-s, v0, cj);
   }
-  const double nn = wave_sum(part2);
-  if (lane == 0) {
-    col[j] = fma(-s, v0, col[j]);
-    nout[c] = nn;
-  }
+  if (lane == 0) nout[c] = nn;
 }
 
 // W[a, b] = G[cols[a], cols[b]] (k x k block of the d x d Gram matrix).
