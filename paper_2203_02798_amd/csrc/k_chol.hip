@@ -773,7 +773,7 @@ int sketch_qr_impl(const double *C, int64_t m, int64_t d, double *R, double *Rin
   if (run && !ws.ok()) return fail(PSK_ENOMEM, "workspace too small for sketch_qr");
   const size_t mk = ws.mark();
   int rc;
-  KTimer timer("sketch_qr", st);
+  KTimer timer("sketch_qr", st, run);
   // flag[0]: a Cholesky pivot failed
   if (run) k_fill<<<1, 64, 0, st>>>(reinterpret_cast<double *>(flag), 2, 0.0);
   if (flag_out) *flag_out = flag;

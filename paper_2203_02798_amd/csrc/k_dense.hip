@@ -310,23 +310,23 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
   const int64_t n = Am.n, d = Am.d;
   const TA *A = (const TA *)Am.values;
   if (k <= 64) {
-    constexpr int BM = 64, BN = 64;
+    constexpr int BM = 32, BN = 64;
     const int tm = (int)ceil_div(n, BM), tn = (int)ceil_div(k, BN);
     double *part = ws.take<double>((size_t)tn * n);
     if (ws.dry()) return 0;
     if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for row norms");
-    k_dgemm<TA, double, false, false, 4, 1, 1, 4, EPI_ROWNORM, false>
+    k_dgemm<TA, double, false, false, 2, 2, 1, 2, EPI_ROWNORM, false>
         <<<(unsigned)((int64_t)tm * tn), 256, 0, st>>>(n, k, d, A, Am.ld, B, k, tm, tn, d,
                                                        part, n, 1.0, 0.0);
     k_rownorm_reduce<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(part, n, tn, alpha,
                                                                   beta, x);
   } else {
-    constexpr int BM = 64, BN = 256;
+    constexpr int BM = 32, BN = 256;
     const int tm = (int)ceil_div(n, BM), tn = (int)ceil_div(k, BN);
     double *part = ws.take<double>((size_t)tn * n);
     if (ws.dry()) return 0;
     if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for row norms");
-    k_dgemm<TA, double, false, false, 4, 1, 1, 16, EPI_ROWNORM, false>
+    k_dgemm<TA, double, false, false, 2, 2, 1, 8, EPI_ROWNORM, false>
         <<<(unsigned)((int64_t)tm * tn), 256, 0, st>>>(n, k, d, A, Am.ld, B, k, tm, tn, d,
                                                        part, n, 1.0, 0.0);
     k_rownorm_reduce<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(part, n, tn, alpha,
@@ -355,7 +355,7 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
 
 int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
                hipStream_t st, bool out_f64) {
-  KTimer timer("gram", st);
+  KTimer timer("gram", st, !ws.dry());
   const bool f32 = A.dtype == PSK_F32;
   if (f32)
     return gemm_partial_launch<float, float, true, false, 2, 2, 2, 2, true>(
@@ -368,7 +368,7 @@ int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
 
 int rownorms_dense(double alpha, const psk_mat &A, const double *B, int64_t k,
                    double beta, double *x, Arena &ws, hipStream_t st) {
-  KTimer timer("rownorm", st);
+  KTimer timer("rownorm", st, !ws.dry());
   if (A.dtype == PSK_F32) return rownorm_launch<float>(A, B, k, alpha, beta, x, ws, st);
   return rownorm_launch<double>(A, B, k, alpha, beta, x, ws, st);
 }

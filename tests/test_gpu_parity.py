@@ -446,7 +446,10 @@ def _rownorm_check(xh, a, b, alpha=1.0, beta=0.0, x0=None):
 
 @pytest.mark.parametrize("kind,n,d,k", [("dense", 20000, 50, 50), ("dense", 5000, 130, 257),
                                         ("dense32", 7000, 256, 256), ("csr", 100000, 500, 500),
-                                        ("csrzipf", 20000, 300, 64)])
+                                        ("csrzipf", 20000, 300, 64),
+                                        # ragged row tiles and k around the 64-column form
+                                        ("dense", 9001, 70, 33), ("dense32", 3001, 256, 64),
+                                        ("dense", 4097, 33, 65)])
 def test_rownorms_sq(api, kind, n, d, k):
     _say(f"rownorms {kind} n={n} d={d} k={k}")
     if kind == "csr":
