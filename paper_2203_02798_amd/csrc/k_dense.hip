@@ -304,12 +304,186 @@ int gemm_partial_launch(int64_t M, int64_t N, int64_t K, const TA *A, int64_t ld
   return 0;
 }
 
+// Fused row norms with a column tile of B resident in LDS.  B[:, n0 : n0 +
+// BNC] (rows padded to a multiple of 16 with zeros, row stride BNC + 4) is
+// staged once per workgroup; the 8 wavefronts then stream 32-row tiles of A
+// straight from memory into the MFMA operand registers (no LDS round trip
+// and no barrier in the main loop) and keep 2 x BNC/16 accumulator blocks.
+// Inside a 16-wide K chunk, lane (li, kq) feeds column k0 + 4 kq + s of A at
+// step s, and B row k0 + 4 kq + s: the same permutation of the chunk on both
+// operands, so one lane reads four consecutive elements of its row.
+// part[nt * n + row] = the row's squared norm over the tile's BNC columns.
+// Workgroups form row groups of tn (one per column tile) that sit on one XCD
+// (linear ids equal mod 8) and walk the same rows, so A is fetched into that
+// XCD's L2 about once for all tn tiles.
+constexpr int kBresThreads = 512;
+
+template <typename TA, int BNC, bool VEC>
+__global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
+    const TA *__restrict__ A, int64_t ld, int64_t n, int64_t d, const double *__restrict__ B,
+    int64_t k, int tn, double *__restrict__ part) {
+  static_assert(!VEC || sizeof(TA) == 4, "vector loads are for FP32 A");
+  extern __shared__ double Bs[];
+  constexpr int LDB = BNC + 4;
+  constexpr int NB = BNC / 16;
+  constexpr int MB = 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int64_t lin = blockIdx.x, nblk = gridDim.x;
+  const int64_t slot = lin >> 3;
+  const int nt = (int)(slot % tn);
+  const int64_t ngroups = nblk / tn;
+  const int64_t group = (slot / tn) * 8 + (lin & 7);
+  const int64_t n0 = (int64_t)nt * BNC;
+  const int64_t kch = (d + 15) / 16;
+  const int64_t drows = kch * 16;
+  for (int64_t e = tid; e < drows * BNC; e += kBresThreads) {
+    const int64_t kk = e / BNC;
+    const int jj = (int)(e - kk * BNC);
+    const int64_t col = n0 + jj;
+    Bs[kk * LDB + jj] = (kk < d && col < k) ? B[kk * k + col] : 0.0;
+  }
+  __syncthreads();
+  const int64_t ntiles = (n + 31) / 32;
+  for (int64_t t = group * 8 + wave; t < ntiles; t += ngroups * 8) {
+    const int64_t r0 = t * 32;
+    const TA *arow[MB];
+    bool rin[MB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int64_t row = r0 + mb * 16 + li;
+      rin[mb] = row < n;
+      arow[mb] = A + (rin[mb] ? row : 0) * ld;
+    }
+    auto load = [&](int64_t c, double (&a)[MB][4]) __attribute__((always_inline)) {
+      const int64_t kb = c * 16 + 4 * kq;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        if constexpr (VEC) {
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (rin[mb] && kb < d) v = *reinterpret_cast<const float4 *>(arow[mb] + kb);
+          a[mb][0] = v.x;
+          a[mb][1] = v.y;
+          a[mb][2] = v.z;
+          a[mb][3] = v.w;
+        } else {
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            a[mb][s] = (rin[mb] && kb + s < d) ? (double)arow[mb][kb + s] : 0.0;
+        }
+      }
+    };
+    v4d acc[MB][NB];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
+    double a0[MB][4], a1[MB][4];
+    load(0, a0);
+    for (int64_t c = 0; c < kch; c += 2) {
+      if (c + 1 < kch) load(c + 1, a1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double *brow = Bs + (c * 16 + 4 * kq + s) * LDB + li;
+        double bv[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bv[nb] = brow[nb * 16];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[mb][s], bv[nb], acc[mb][nb],
+                                                               0, 0, 0);
+      }
+      if (c + 1 >= kch) break;
+      if (c + 2 < kch) load(c + 2, a0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double *brow = Bs + ((c + 1) * 16 + 4 * kq + s) * LDB + li;
+        double bv[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bv[nb] = brow[nb * 16];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[mb][s], bv[nb], acc[mb][nb],
+                                                               0, 0, 0);
+      }
+    }
+    // lane (li, kq) holds rows kq + 4 e, column li of each 16 x 16 block
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        double s2 = 0.0;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) s2 += acc[mb][nb][e] * acc[mb][nb][e];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) s2 += __shfl_xor(s2, off, 64);
+        const int64_t row = r0 + mb * 16 + kq + 4 * e;
+        if (li == 0 && row < n) part[(int64_t)nt * n + row] = s2;
+      }
+  }
+}
+
+// Column width of the LDS-resident form for d (0: the tile does not fit).
+int bres_width(int64_t d, int64_t k) {
+  const int64_t drows = ceil_div(d, (int64_t)16) * 16;
+  if (k > 32 && drows * (64 + 4) * 8 <= 163840) return 64;
+  if (drows * (32 + 4) * 8 <= 163840) return 32;
+  return 0;
+}
+
+template <typename TA, int BNC, bool VEC>
+int bres_launch(const psk_mat &Am, const double *B, int64_t k, double *part, int tn,
+                hipStream_t st) {
+  const int64_t n = Am.n, d = Am.d;
+  const size_t lds = (size_t)ceil_div(d, (int64_t)16) * 16 * (BNC + 4) * sizeof(double);
+  PSK_HIP_TRY(hipFuncSetAttribute((const void *)k_rownorm_bres<TA, BNC, VEC>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  // one workgroup per CU (the LDS tile), row groups of tn workgroups per XCD
+  const int64_t tiles = ceil_div(n, (int64_t)32);
+  int64_t groups = 256 / tn;
+  if (groups < 8) groups = 8;
+  groups = (groups / 8) * 8;
+  const int64_t need = ceil_div(tiles, (int64_t)8);  // 8 wavefronts per workgroup
+  while (groups > 8 && groups / 2 >= need) groups /= 2;
+  const unsigned nblk = (unsigned)(groups * tn);
+  k_rownorm_bres<TA, BNC, VEC><<<nblk, kBresThreads, lds, st>>>(
+      (const TA *)Am.values, Am.ld, n, d, B, k, tn, part);
+  return 0;
+}
+
 template <typename TA>
 int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
                    double beta, double *x, Arena &ws, hipStream_t st) {
   const int64_t n = Am.n, d = Am.d;
   const TA *A = (const TA *)Am.values;
-  if (k <= 64) {
+  const int bw = bres_width(d, k);
+  if (bw > 0) {
+    const int tn = (int)ceil_div(k, (int64_t)bw);
+    double *part = ws.take<double>((size_t)tn * n);
+    if (ws.dry()) return 0;
+    if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for row norms");
+    // FP32 rows read four elements at a time when every such group is aligned
+    const bool vec = Am.ld % 4 == 0 && d % 4 == 0 && ((uintptr_t)Am.values & 15) == 0;
+    int rc;
+    if constexpr (sizeof(TA) == 4) {
+      if (bw == 64)
+        rc = vec ? bres_launch<TA, 64, true>(Am, B, k, part, tn, st)
+                 : bres_launch<TA, 64, false>(Am, B, k, part, tn, st);
+      else
+        rc = vec ? bres_launch<TA, 32, true>(Am, B, k, part, tn, st)
+                 : bres_launch<TA, 32, false>(Am, B, k, part, tn, st);
+    } else {
+      (void)vec;
+      rc = bw == 64 ? bres_launch<TA, 64, false>(Am, B, k, part, tn, st)
+                    : bres_launch<TA, 32, false>(Am, B, k, part, tn, st);
+    }
+    if (rc) return rc;
+    k_rownorm_reduce<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(part, n, tn, alpha, beta, x);
+  } else if (k <= 64) {
     constexpr int BM = 32, BN = 64;
     const int tm = (int)ceil_div(n, BM), tn = (int)ceil_div(k, BN);
     double *part = ws.take<double>((size_t)tn * n);

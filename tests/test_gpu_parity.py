@@ -449,7 +449,12 @@ def _rownorm_check(xh, a, b, alpha=1.0, beta=0.0, x0=None):
                                         ("csrzipf", 20000, 300, 64),
                                         # ragged row tiles and k around the 64-column form
                                         ("dense", 9001, 70, 33), ("dense32", 3001, 256, 64),
-                                        ("dense", 4097, 33, 65)])
+                                        ("dense", 4097, 33, 65),
+                                        # the LDS-resident column tile: 32-wide (k <= 32,
+                                        # or d above 288), FP32 rows not in groups of 4;
+                                        # and d beyond the LDS tile (the staged GEMM)
+                                        ("dense", 5000, 40, 16), ("dense32", 3000, 400, 100),
+                                        ("dense32", 2500, 254, 70), ("dense", 2000, 600, 70)])
 def test_rownorms_sq(api, kind, n, d, k):
     _say(f"rownorms {kind} n={n} d={d} k={k}")
     if kind == "csr":
