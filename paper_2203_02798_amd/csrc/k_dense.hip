@@ -305,18 +305,23 @@ int gemm_partial_launch(int64_t M, int64_t N, int64_t K, const TA *A, int64_t ld
 }
 
 // Fused row norms with a column tile of B resident in LDS.  B[:, n0 : n0 +
-// BNC] (rows padded to a multiple of 16 with zeros, row stride BNC + 4) is
-// staged once per workgroup; the 8 wavefronts then stream 32-row tiles of A
-// straight from memory into the MFMA operand registers (no LDS round trip
-// and no barrier in the main loop) and keep 2 x BNC/16 accumulator blocks.
-// Inside a 16-wide K chunk, lane (li, kq) feeds column k0 + 4 kq + s of A at
-// step s, and B row k0 + 4 kq + s: the same permutation of the chunk on both
-// operands, so one lane reads four consecutive elements of its row.
+// BNC] (rows padded to a multiple of the chunk with zeros, row stride BNC + 4) is
+// staged once per workgroup; the 8 wavefronts then stream row tiles of A
+// (kBresMB blocks of 16 rows) straight from memory into the MFMA operand
+// registers (no LDS round trip and no barrier in the main loop) and keep
+// kBresMB x BNC/16 accumulator blocks.
+// Inside a K chunk of 4 kBresKW columns, lane (li, kq) feeds column
+// k0 + kBresKW kq + s of A at step s, and B row k0 + kBresKW kq + s: the same
+// permutation of the chunk on both operands, so one lane reads kBresKW
+// consecutive elements of its row.
 // part[nt * n + row] = the row's squared norm over the tile's BNC columns.
 // Workgroups form row groups of tn (one per column tile) that sit on one XCD
 // (linear ids equal mod 8) and walk the same rows, so A is fetched into that
 // XCD's L2 about once for all tn tiles.
 constexpr int kBresThreads = 512;
+constexpr int kBresMB = 2;  // 16-row blocks per wavefront tile
+constexpr int kBresRows = 16 * kBresMB;
+constexpr int kBresKW = 8;
 
 template <typename TA, int BNC, bool VEC>
 __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
@@ -326,7 +331,9 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
   extern __shared__ double Bs[];
   constexpr int LDB = BNC + 4;
   constexpr int NB = BNC / 16;
-  constexpr int MB = 2;
+  constexpr int MB = kBresMB;
+  constexpr int KW = kBresKW;  // consecutive elements of a row per lane per chunk
+  constexpr int CK = 4 * KW;   // K chunk width
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, kq = lane >> 4;
   const int64_t lin = blockIdx.x, nblk = gridDim.x;
@@ -335,8 +342,8 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
   const int64_t ngroups = nblk / tn;
   const int64_t group = (slot / tn) * 8 + (lin & 7);
   const int64_t n0 = (int64_t)nt * BNC;
-  const int64_t kch = (d + 15) / 16;
-  const int64_t drows = kch * 16;
+  const int64_t kch = (d + CK - 1) / CK;
+  const int64_t drows = kch * CK;
   for (int64_t e = tid; e < drows * BNC; e += kBresThreads) {
     const int64_t kk = e / BNC;
     const int jj = (int)(e - kk * BNC);
@@ -344,9 +351,9 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
     Bs[kk * LDB + jj] = (kk < d && col < k) ? B[kk * k + col] : 0.0;
   }
   __syncthreads();
-  const int64_t ntiles = (n + 31) / 32;
+  const int64_t ntiles = (n + kBresRows - 1) / kBresRows;
   for (int64_t t = group * 8 + wave; t < ntiles; t += ngroups * 8) {
-    const int64_t r0 = t * 32;
+    const int64_t r0 = t * kBresRows;
     const TA *arow[MB];
     bool rin[MB];
 #pragma unroll
@@ -355,61 +362,56 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
       rin[mb] = row < n;
       arow[mb] = A + (rin[mb] ? row : 0) * ld;
     }
-    auto load = [&](int64_t c, double (&a)[MB][4]) __attribute__((always_inline)) {
-      const int64_t kb = c * 16 + 4 * kq;
-#pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        if constexpr (VEC) {
-          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (rin[mb] && kb < d) v = *reinterpret_cast<const float4 *>(arow[mb] + kb);
-          a[mb][0] = v.x;
-          a[mb][1] = v.y;
-          a[mb][2] = v.z;
-          a[mb][3] = v.w;
-        } else {
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-            a[mb][s] = (rin[mb] && kb + s < d) ? (double)arow[mb][kb + s] : 0.0;
-        }
-      }
-    };
     v4d acc[MB][NB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
-    double a0[MB][4], a1[MB][4];
+    auto load = [&](int64_t c, double (&a)[MB][KW]) __attribute__((always_inline)) {
+      const int64_t kb = c * CK + KW * kq;
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb) {
+        if constexpr (VEC) {
+#pragma unroll
+          for (int q = 0; q < KW / 4; ++q) {
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (rin[mb] && kb + 4 * q < d)
+              v = *reinterpret_cast<const float4 *>(arow[mb] + kb + 4 * q);
+            a[mb][4 * q + 0] = v.x;
+            a[mb][4 * q + 1] = v.y;
+            a[mb][4 * q + 2] = v.z;
+            a[mb][4 * q + 3] = v.w;
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < KW; ++s)
+            a[mb][s] = (rin[mb] && kb + s < d) ? (double)arow[mb][kb + s] : 0.0;
+        }
+      }
+    };
+    auto step = [&](int64_t c, const double (&a)[MB][KW]) __attribute__((always_inline)) {
+#pragma unroll
+      for (int s = 0; s < KW; ++s) {
+        const double *brow = Bs + (c * CK + KW * kq + s) * LDB + li;
+        double bv[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bv[nb] = brow[nb * 16];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][s], bv[nb], acc[mb][nb],
+                                                               0, 0, 0);
+      }
+    };
+    double a0[MB][KW], a1[MB][KW];
     load(0, a0);
     for (int64_t c = 0; c < kch; c += 2) {
       if (c + 1 < kch) load(c + 1, a1);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const double *brow = Bs + (c * 16 + 4 * kq + s) * LDB + li;
-        double bv[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) bv[nb] = brow[nb * 16];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[mb][s], bv[nb], acc[mb][nb],
-                                                               0, 0, 0);
-      }
+      step(c, a0);
       if (c + 1 >= kch) break;
       if (c + 2 < kch) load(c + 2, a0);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const double *brow = Bs + ((c + 1) * 16 + 4 * kq + s) * LDB + li;
-        double bv[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) bv[nb] = brow[nb * 16];
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[mb][s], bv[nb], acc[mb][nb],
-                                                               0, 0, 0);
-      }
+      step(c + 1, a1);
     }
     // lane (li, kq) holds rows kq + 4 e, column li of each 16 x 16 block
 #pragma unroll
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
 
 // Column width of the LDS-resident form for d (0: the tile does not fit).
 int bres_width(int64_t d, int64_t k) {
-  const int64_t drows = ceil_div(d, (int64_t)16) * 16;
+  const int64_t drows = ceil_div(d, (int64_t)(4 * kBresKW)) * (4 * kBresKW);
   if (k > 32 && drows * (64 + 4) * 8 <= 163840) return 64;
   if (drows * (32 + 4) * 8 <= 163840) return 32;
   return 0;
@@ -439,11 +441,12 @@ template <typename TA, int BNC, bool VEC>
 int bres_launch(const psk_mat &Am, const double *B, int64_t k, double *part, int tn,
                 hipStream_t st) {
   const int64_t n = Am.n, d = Am.d;
-  const size_t lds = (size_t)ceil_div(d, (int64_t)16) * 16 * (BNC + 4) * sizeof(double);
+  const size_t lds =
+      (size_t)ceil_div(d, (int64_t)(4 * kBresKW)) * (4 * kBresKW) * (BNC + 4) * sizeof(double);
   PSK_HIP_TRY(hipFuncSetAttribute((const void *)k_rownorm_bres<TA, BNC, VEC>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   // one workgroup per CU (the LDS tile), row groups of tn workgroups per XCD
-  const int64_t tiles = ceil_div(n, (int64_t)32);
+  const int64_t tiles = ceil_div(n, (int64_t)kBresRows);
   int64_t groups = 256 / tn;
   if (groups < 8) groups = 8;
   groups = (groups / 8) * 8;
