@@ -91,6 +91,23 @@ def test_fullsize_sparse_bench_workload(api):
     u = 2.0 ** -53
     assert np.all(np.abs(th[rows] - want) <= 3 * gamma(N, u) * zb + 4 * u * np.abs(want)
                   + 1e-300)
+    # leverage_sketch in one call: bit-identical to the composed calls above
+    # (t = 0), and the JL step keeps every score within 1 +- 6 sqrt(2/t)
+    _say("leverage_sketch t = 0 and t = 2000")
+    th1 = api.leverage_sketch(A, m, r, seed, t=0).cpu().numpy()
+    assert np.array_equal(th1, th)
+    thj = api.leverage_sketch(A, m, r, seed, t=2000).cpu().numpy()
+    nz = th > 0
+    assert np.array_equal(thj[~nz], th[~nz])
+    assert np.abs(thj[nz] / th[nz] - 1).max() <= 6 * np.sqrt(2 / 2000)
+    # column subset selection with the algorithm's sizes (m = 2d): k distinct
+    # columns, and the selected columns' scores sum to k
+    _say("css_select / leverage_css, m = 2d")
+    cols = api.css_select(A, 2 * d, r, 100, seed).cpu().numpy()
+    assert len(set(cols.tolist())) == 100 and cols.min() >= 0 and cols.max() < d
+    thc, cols2 = api.leverage_css(A, 2 * d, r, 100, seed)
+    assert np.array_equal(cols2.cpu().numpy(), cols)
+    assert abs(thc.sum().item() - 100) <= 1e-8 * 100
     # least squares: optimality of the FP64 and BF16 sketch solutions
     rng = np.random.default_rng(1)
     b = a @ rng.standard_normal(d) + 1e-3 * rng.standard_normal(n)
