@@ -106,7 +106,9 @@ typedef struct psk_mat {
 
 /* ---- precision of the Gaussian GEMM of sketch_gcs / lsq_solve ---------- */
 enum {
-  PSK_PREC_F64 = 0,   /* G and S*A in FP64, FP64 MFMA, FP64 accumulation      */
+  PSK_PREC_F64 = 0,   /* G and S*A in FP64, FP64 MFMA, FP64 accumulation      *
+                       * (S*A of FP32 A is summed in FP32, as sketch_cs      *
+                       * documents, then widened exactly)                    */
   PSK_PREC_BF16 = 1,  /* G rounded to bfloat16, S*A split into two bfloat16   *
                        * limbs (hi + lo), BF16 MFMA with FP32 accumulation,   *
                        * FP64 reduction of the K-split partial products.      *
