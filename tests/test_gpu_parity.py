@@ -542,6 +542,26 @@ def test_leverage_sketch_f64(api, kind, n, d, m, r, t):
     assert err <= (2e-5 if kind == "dense32" else 1e-9)
 
 
+@pytest.mark.parametrize("dtype,t", [(np.float64, 0), (np.float64, 32), (np.float32, 0)])
+def test_leverage_sketch_coherent(api, dtype, t):
+    """The dense coherent structure (singular values geometric from 1 to 1e-6,
+    5% of rows scaled by 100) at n = 100,000, d = 64.  FP64: the scores agree
+    to ~cond(C) u.  FP32: S A is summed in FP32 (buckets of ~24 rows); at
+    cond 1e6 that moves the scores by up to ~0.4% (the oracle, summing the same
+    bucket in FP32 in row order, shows 4.3e-3 max and 3.9e-4 median)."""
+    n, d, m, r = 100000, 64, 256, 4096
+    a = synth.dense_coherent(n, d, seed=3, smin=1e-6, dtype=dtype)
+    th = api.leverage_sketch(to_device(a), m, r, seed=1, t=t).cpu().numpy()
+    ref = olev.leverage_sketched_jl(a, m, r, t, 1)
+    err = np.abs(th / ref - 1)
+    _say(f"leverage_sketch coherent {np.dtype(dtype).name} t={t}: max {err.max():.3e} "
+         f"median {np.median(err):.3e}")
+    if dtype == np.float64:
+        assert err.max() <= 1e-7
+    else:
+        assert err.max() <= 2e-2 and np.median(err) <= 2e-3
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("kind,n,d,m,r,t", [
     ("dense", 20000, 50, 200, 2500, 16),
