@@ -46,9 +46,11 @@ WORKLOADS = {
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP8_TFLOPS = 5000.0
-# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-operation
-# per lane per clock (the FP32 FMA rate without packed math, 78.6 TFLOP/s / 2)
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU peak in lane-operations: the FP32 vector rate, 157.3 TFLOP/s at 256 CUs
+# and 2.4 GHz, is 128 FP32 FMA lanes per CU per clock (a wave64 v_fma_f32 in
+# two cycles per SIMD; psk_probe_valu_f32 reaches ~82% of it without packed
+# instructions), one lane-operation per FMA: 157.3 / 2 = 78.65 T/s
+PEAK_VALU_TOPS = 157.3 / 2
 # VALU lane-operations per Gaussian sample of the sparse product's G (BF16):
 # a Philox4x32-10 block and its Box-Muller pair of pairs give 4 samples for
 # 20 64-bit multiplies, 20 three-input XORs and 71 further operations
@@ -534,6 +536,17 @@ def main():
                 "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": None, "traffic_unit": "bytes per launch",
                 "launch_ms": gg_avg, "flops_per_launch": flops}
+    # the rates this device sustains (ceiling probes), beside the datasheet's
+    ceil = None
+    if not args.no_extras:
+        log("ceiling probes: copy, FP64 MFMA, VALU")
+        ceil = api.measure_ceilings(dev)
+        if roof["bound"] == "alu":
+            roof["measured_peak"] = ceil["valu_Tops"]
+        elif head == "f64":
+            roof["measured_peak"] = ceil["fp64_mfma_TFs"]
+        if "measured_peak" in roof:
+            roof["frac_measured"] = roof["achieved"] / roof["measured_peak"]
     rec = {
         "metric": "GB/s of A sketched (G·S·A) + LSQ solves/s, p50/p99 latency vs FP64 plain path",
         "value": hr["value"],
@@ -565,6 +578,12 @@ def main():
         "lsq": hr["lsq"],
         "roofline": roof,
     }
+    if ceil is not None:
+        rec["ceilings"] = {**ceil, "datasheet": {"hbm_GBs": 8000.0,
+                                                 "fp64_mfma_TFs": PEAK_FP64_TFLOPS,
+                                                 "valu_Tops": PEAK_VALU_TOPS},
+                           "probes": "psk_probe_copy (1 GiB read + 1 GiB written), "
+                                     "psk_probe_mfma_f64, psk_probe_valu_f32; best of 3"}
     keys = ("value", "ms_per_step", "solves_per_s", "p50_ms", "p99_ms", "sketch_gcs_gbs",
             "stage_ms", "lsq")
     if head != "f64" and "f64" in res:
@@ -587,6 +606,12 @@ def main():
         rec["css"] = css_bench(api, torch, A, d, r, seed, args.steps, args.warmup)
         log("leverage scores with the JL step, dense FP32 4,000,000 x 256")
         rec["leverage_jl"] = leverage_jl_bench(api, torch, args.steps, args.warmup)
+        if ceil is not None:
+            for tt in ("t0", f"t{rec['leverage_jl']['t']}"):
+                tf = rec["leverage_jl"][tt]["rownorm_tflops"]
+                if tf:
+                    rec["leverage_jl"][tt]["rownorm_frac"] = tf / PEAK_FP64_TFLOPS
+                    rec["leverage_jl"][tt]["rownorm_frac_measured"] = tf / ceil["fp64_mfma_TFs"]
     if not args.no_serving:
         rec["serving"] = serving_bench(api, torch, dev)
     if not args.no_cpu_baseline:

@@ -380,6 +380,31 @@ int lsq_gram(const psk_mat *A, const double *b, double *x, void *ws, size_t ws_b
 int lsq_sketch_solve(const psk_mat *A, const double *b, double *x, int64_t m, int64_t r,
                      uint64_t seed, int prec, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- ceiling probes ------------------------------------------------------
+ * Measurement kernels, not part of the method: they give the rates this
+ * device sustains for the resources the path's kernels are bound by, so a
+ * kernel's roofline fraction can be stated against the measured ceiling as
+ * well as the datasheet peak.  Each call enqueues one kernel on `stream`;
+ * the caller times it (e.g. with events on that stream). */
+#define PSK_PROBE_BLOCKS 4096 /* workgroups (of 256 threads) of the arithmetic probes */
+
+/* dst <- src, a grid-stride copy of 16-byte words (HBM: `bytes` read and
+ * `bytes` written).  bytes > 0, a multiple of 16; src, dst 16-byte aligned
+ * device pointers, not overlapping.  Errors: PSK_EINVAL. */
+int psk_probe_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/* iters x 8 v_mfma_f64_16x16x4f64 per wavefront on 8 independent register
+ * accumulators: PSK_PROBE_BLOCKS * 4 * iters * 8 * 2048 FP64 flops.
+ *   out : PSK_PROBE_BLOCKS * 256 doubles (device), one value per thread.
+ * Errors: PSK_EINVAL (iters < 1, NULL out). */
+int psk_probe_mfma_f64(int64_t iters, double *out, void *stream);
+
+/* iters x 8 independent v_fma_f32 per lane: PSK_PROBE_BLOCKS * 256 * iters
+ * * 8 VALU lane-operations.
+ *   out : PSK_PROBE_BLOCKS * 256 floats (device), one value per thread.
+ * Errors: PSK_EINVAL (iters < 1, NULL out). */
+int psk_probe_valu_f32(int64_t iters, float *out, void *stream);
+
 /* ---- request server (serving form) ---------------------------------------
  * Continuous batching of least-squares and leverage-score requests of
  * uneven n and d on one GPU.  `slots` host worker threads, each with its own

@@ -22,6 +22,7 @@ PSK_PENDING = 1
 PSK_REQ_LSQ, PSK_REQ_LEVERAGE = 0, 1
 PSK_DENSE, PSK_CSR = 0, 1
 PSK_F64, PSK_F32 = 0, 1
+PSK_PROBE_BLOCKS = 4096
 PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 (PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
  PSK_OP_LSQ, PSK_OP_SKETCH_G, PSK_OP_LEVERAGE_GRAM, PSK_OP_LSQ_GRAM,
@@ -31,6 +32,7 @@ EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq", "sketch_qr",
             "lsq_solve", "leverage_sketch", "css_select", "leverage_css", "leverage_gram",
             "lsq_gram", "lsq_sketch_solve",
+            "psk_probe_copy", "psk_probe_mfma_f64", "psk_probe_valu_f32",
             "psk_timing_enable", "psk_timing_reset",
             "psk_timing_collect", "psk_timing_names", "psk_server_create",
             "psk_server_submit", "psk_server_wait", "psk_server_poll",
@@ -162,6 +164,9 @@ _SIGS = {
     "lsq_gram": ([_PM, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "lsq_sketch_solve": ([_PM, _vp, _vp, _i64, _i64, _u64, ctypes.c_int, _vp, ctypes.c_size_t,
                           _vp], ctypes.c_int),
+    "psk_probe_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "psk_probe_mfma_f64": ([_i64, _vp, _vp], ctypes.c_int),
+    "psk_probe_valu_f32": ([_i64, _vp, _vp], ctypes.c_int),
     "psk_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "psk_timing_reset": ([], ctypes.c_int),
     "psk_timing_collect": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),

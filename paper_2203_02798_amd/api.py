@@ -421,6 +421,45 @@ class Server:
         return False
 
 
+def measure_ceilings(device="cuda:0", copy_bytes=1 << 30, reps=3):
+    """Rates this device sustains (the ceiling probes, each timed with events
+    on the launch stream, best of ``reps``): HBM GB/s of a plain copy (bytes
+    read + written), FP64 matrix TFLOP/s, VALU tera lane-operations/s."""
+    dev = torch.device(device)
+    st = _stream(dev)
+    stream = torch.cuda.current_stream(dev)
+    src = torch.ones(copy_bytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    outd = torch.empty(L.PSK_PROBE_BLOCKS * 256, dtype=torch.float64, device=dev)
+    outf = torch.empty(L.PSK_PROBE_BLOCKS * 256, dtype=torch.float32, device=dev)
+
+    def best(launch):
+        launch()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            launch()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return min(ts)
+
+    t = best(lambda: L.check(L.lib().psk_probe_copy(src.data_ptr(), dst.data_ptr(), copy_bytes,
+                                                    st), "psk_probe_copy"))
+    hbm = 2.0 * copy_bytes / t / 1e9
+    it_m = 1000
+    t = best(lambda: L.check(L.lib().psk_probe_mfma_f64(it_m, outd.data_ptr(), st),
+                             "psk_probe_mfma_f64"))
+    mfma = L.PSK_PROBE_BLOCKS * 4 * it_m * 8 * 2048.0 / t / 1e12
+    it_v = 20000
+    t = best(lambda: L.check(L.lib().psk_probe_valu_f32(it_v, outf.data_ptr(), st),
+                             "psk_probe_valu_f32"))
+    valu = L.PSK_PROBE_BLOCKS * 256 * it_v * 8.0 / t / 1e12
+    return {"hbm_copy_GBs": hbm, "fp64_mfma_TFs": mfma, "valu_Tops": valu}
+
+
 class kernel_timing:
     """Context manager that enables the library's event brackets around its
     main kernels; ``stats()`` returns {name: (total_ms, launches)}."""

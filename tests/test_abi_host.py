@@ -186,6 +186,11 @@ def test_rejects_bad_arguments_without_device_work(lib):
                             stream) == -1  # theta
     assert lib.leverage_css(ctypes.byref(good), 8, 16, 3, 0, 9, sa, None, ws, 1 << 20,
                             stream) == -2  # prec
+    assert lib.psk_probe_copy(sa, ws, 24, stream) == -1       # not a multiple of 16
+    assert lib.psk_probe_copy(None, ws, 32, stream) == -1
+    assert lib.psk_probe_copy(ctypes.c_void_p(0x4008), ws, 32, stream) == -1  # alignment
+    assert lib.psk_probe_mfma_f64(0, sa, stream) == -1
+    assert lib.psk_probe_valu_f32(10, None, stream) == -1
     assert lib.cs_hash(0, 10, 0, 0, None, None, stream) == -1
     assert lib.cs_hash(-1, 10, 5, 0, None, None, stream) == -1
     assert lib.sketch_qr(sa, 3, 5, sa, sa, ws, 1 << 20, stream) == -1
