@@ -581,9 +581,12 @@ def main():
     if ceil is not None:
         rec["ceilings"] = {**ceil, "datasheet": {"hbm_GBs": 8000.0,
                                                  "fp64_mfma_TFs": PEAK_FP64_TFLOPS,
+                                                 "bf16_mfma_TFs": PEAK_BF16_TFLOPS,
+                                                 "fp8_mfma_TFs": PEAK_FP8_TFLOPS,
                                                  "valu_Tops": PEAK_VALU_TOPS},
                            "probes": "psk_probe_copy (1 GiB read + 1 GiB written), "
-                                     "psk_probe_mfma_f64, psk_probe_valu_f32; best of 3"}
+                                     "psk_probe_mfma_f64, psk_probe_mfma_lowp (bf16, fp8), "
+                                     "psk_probe_valu_f32; best of 3"}
     keys = ("value", "ms_per_step", "solves_per_s", "p50_ms", "p99_ms", "sketch_gcs_gbs",
             "stage_ms", "lsq")
     if head != "f64" and "f64" in res:
@@ -598,6 +601,10 @@ def main():
             "achieved": flops / (gg * 1e-3) / 1e12 if gg > 0 else 0.0,
             "peak": PEAK_FP8_TFLOPS, "unit": "TFLOP/s",
             "frac": (flops / (gg * 1e-3) / 1e12) / PEAK_FP8_TFLOPS if gg > 0 else 0.0}
+        if ceil is not None and gg > 0:
+            g8 = rec["fp8_path"]["gauss_gemm_roofline"]
+            g8["measured_peak"] = ceil["fp8_mfma_TFs"]
+            g8["frac_measured"] = g8["achieved"] / ceil["fp8_mfma_TFs"]
     if head == "bf16" and kind == "csr" and not args.no_extras:
         rec["gaussian_only"] = gaussian_only_bench(api, torch, A, m, n, d, int(a.nnz), seed,
                                                    args.steps, args.warmup)

@@ -399,6 +399,14 @@ int psk_probe_copy(const void *src, void *dst, size_t bytes, void *stream);
  * Errors: PSK_EINVAL (iters < 1, NULL out). */
 int psk_probe_mfma_f64(int64_t iters, double *out, void *stream);
 
+/* fmt PSK_PREC_BF16: iters x 8 v_mfma_f32_16x16x32_bf16 per wavefront
+ * (PSK_PROBE_BLOCKS * 4 * iters * 8 * 16384 flops); PSK_PREC_FP8: iters x 8
+ * v_mfma_scale_f32_16x16x128_f8f6f4 on e4m3 operands with unit scales
+ * (PSK_PROBE_BLOCKS * 4 * iters * 8 * 65536 flops); FP32 accumulation.
+ *   out : PSK_PROBE_BLOCKS * 256 floats (device).
+ * Errors: PSK_EINVAL (iters < 1, NULL out), PSK_EDTYPE (fmt). */
+int psk_probe_mfma_lowp(int fmt, int64_t iters, float *out, void *stream);
+
 /* iters x 8 independent v_fma_f32 per lane: PSK_PROBE_BLOCKS * 256 * iters
  * * 8 VALU lane-operations.
  *   out : PSK_PROBE_BLOCKS * 256 floats (device), one value per thread.

@@ -32,7 +32,8 @@ EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq", "sketch_qr",
             "lsq_solve", "leverage_sketch", "css_select", "leverage_css", "leverage_gram",
             "lsq_gram", "lsq_sketch_solve",
-            "psk_probe_copy", "psk_probe_mfma_f64", "psk_probe_valu_f32",
+            "psk_probe_copy", "psk_probe_mfma_f64", "psk_probe_mfma_lowp",
+            "psk_probe_valu_f32",
             "psk_timing_enable", "psk_timing_reset",
             "psk_timing_collect", "psk_timing_names", "psk_server_create",
             "psk_server_submit", "psk_server_wait", "psk_server_poll",
@@ -166,6 +167,7 @@ _SIGS = {
                           _vp], ctypes.c_int),
     "psk_probe_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "psk_probe_mfma_f64": ([_i64, _vp, _vp], ctypes.c_int),
+    "psk_probe_mfma_lowp": ([ctypes.c_int, _i64, _vp, _vp], ctypes.c_int),
     "psk_probe_valu_f32": ([_i64, _vp, _vp], ctypes.c_int),
     "psk_timing_enable": ([ctypes.c_int], ctypes.c_int),
     "psk_timing_reset": ([], ctypes.c_int),

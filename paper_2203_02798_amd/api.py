@@ -424,7 +424,8 @@ class Server:
 def measure_ceilings(device="cuda:0", copy_bytes=1 << 30, reps=3):
     """Rates this device sustains (the ceiling probes, each timed with events
     on the launch stream, best of ``reps``): HBM GB/s of a plain copy (bytes
-    read + written), FP64 matrix TFLOP/s, VALU tera lane-operations/s."""
+    read + written), FP64 / BF16 / FP8 matrix TFLOP/s, VALU tera
+    lane-operations/s."""
     dev = torch.device(device)
     st = _stream(dev)
     stream = torch.cuda.current_stream(dev)
@@ -453,11 +454,20 @@ def measure_ceilings(device="cuda:0", copy_bytes=1 << 30, reps=3):
     t = best(lambda: L.check(L.lib().psk_probe_mfma_f64(it_m, outd.data_ptr(), st),
                              "psk_probe_mfma_f64"))
     mfma = L.PSK_PROBE_BLOCKS * 4 * it_m * 8 * 2048.0 / t / 1e12
+    it_b = 100
+    t = best(lambda: L.check(L.lib().psk_probe_mfma_lowp(L.PSK_PREC_BF16, it_b, outf.data_ptr(),
+                                                         st), "psk_probe_mfma_lowp"))
+    bf16 = L.PSK_PROBE_BLOCKS * 4 * it_b * 8 * 16384.0 / t / 1e12
+    it_8 = 50
+    t = best(lambda: L.check(L.lib().psk_probe_mfma_lowp(L.PSK_PREC_FP8, it_8, outf.data_ptr(),
+                                                         st), "psk_probe_mfma_lowp"))
+    fp8 = L.PSK_PROBE_BLOCKS * 4 * it_8 * 8 * 65536.0 / t / 1e12
     it_v = 20000
     t = best(lambda: L.check(L.lib().psk_probe_valu_f32(it_v, outf.data_ptr(), st),
                              "psk_probe_valu_f32"))
     valu = L.PSK_PROBE_BLOCKS * 256 * it_v * 8.0 / t / 1e12
-    return {"hbm_copy_GBs": hbm, "fp64_mfma_TFs": mfma, "valu_Tops": valu}
+    return {"hbm_copy_GBs": hbm, "fp64_mfma_TFs": mfma, "bf16_mfma_TFs": bf16,
+            "fp8_mfma_TFs": fp8, "valu_Tops": valu}
 
 
 class kernel_timing:

@@ -191,6 +191,8 @@ def test_rejects_bad_arguments_without_device_work(lib):
     assert lib.psk_probe_copy(ctypes.c_void_p(0x4008), ws, 32, stream) == -1  # alignment
     assert lib.psk_probe_mfma_f64(0, sa, stream) == -1
     assert lib.psk_probe_valu_f32(10, None, stream) == -1
+    assert lib.psk_probe_mfma_lowp(0, 10, sa, stream) == -2   # PSK_PREC_F64 is not a probe
+    assert lib.psk_probe_mfma_lowp(1, 0, sa, stream) == -1
     assert lib.cs_hash(0, 10, 0, 0, None, None, stream) == -1
     assert lib.cs_hash(-1, 10, 5, 0, None, None, stream) == -1
     assert lib.sketch_qr(sa, 3, 5, sa, sa, ws, 1 << 20, stream) == -1
