@@ -125,8 +125,9 @@ int gauss_gemm_fp8_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *p
 // The Gaussian product of CSR A over the nonzeros of S*A (k_gauss_sparse.hip),
 // from the binned rows, in any of the three precisions; gauss_sparse_ok tells
 // when it applies (S*A at most 1/32 dense, d <= 1023), gauss_sparse_pick when
-// it is the kernel to use (FP8 keeps the fused dense FP8 GEMM unless S*A is
-// below 1/1024 dense: its contraction costs less than the sparse FP64 updates).
+// it is the kernel to use (FP8 keeps the fused dense FP8 GEMM unless A has
+// fewer than r d / 512 nonzeros: above that its MFMA contraction costs less
+// than the sparse product's per-nonzero updates).
 bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m);
 bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec);
 // the product's own limits (CSR, d <= 1023, sizes); gauss_gemm_sparse checks

@@ -707,9 +707,12 @@ int identity_bins(int64_t n, Arena &ws, uint32_t **perm, uint32_t **bptr, hipStr
 
 bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec) {
   if (!gauss_sparse_ok(A, r, m)) return false;
-  // FP8: the dense MFMA contraction runs about 1000 times the rate of the
-  // sparse product's FP64 updates, so it wins until S*A is below 1/1024 dense
-  if (prec == PSK_PREC_FP8 && fp8_csr_fusable(A, r)) return A.nnz * 1024 <= r * A.d;
+  // FP8: both forms draw the same m r normals; the dense form adds the FP8
+  // MFMA contraction over all r d entries and the scatter of S*A, the sparse
+  // form m FP32 updates per nonzero.  Measured crossover near 1/500 of r d
+  // (CSR 1e7 x 1000 at 1e-3 of r d: sparse 8.1 ms, dense 11.2 ms; CSR
+  // 1e6 x 500 at 4e-3: sparse 1.09 ms, dense 1.00 ms).
+  if (prec == PSK_PREC_FP8 && fp8_csr_fusable(A, r)) return A.nnz * 512 <= r * A.d;
   return true;
 }
 

@@ -205,8 +205,8 @@ def test_sketch_gcs_bf16(api, kind, n, d, m, r):
     ("dense", 3000, 600, 150, 1000),     # two 512-column tiles, ragged
     ("dense", 500, 3, 5, 7),             # one partial 128-bucket chunk
     ("csr", 100000, 500, 300, 25000),
-    # S*A below 1/1024 dense: the product over its nonzeros (512- and
-    # 1024-column forms)
+    # A with fewer than r d / 512 nonzeros: the product over the nonzeros
+    # of S*A (512- and 1024-column forms)
     ("csr", 30000, 200, 100, 32768),
     ("csr:2e-4", 20000, 700, 77, 8192),
     ("dense32", 8000, 96, 129, 1024)])
