@@ -272,6 +272,16 @@ def leverage_jl_bench(api, torch, steps, warmup, n=4_000_000, d=256, r=65536, m=
                          "stage_ms": {kk: round(vv[0] / steps, 4)
                                       for kk, vv in sorted(stats.items())}}
         th[tt] = res
+    # the sketch alone in the configuration's own precision (BF16 G)
+    for _ in range(warmup):
+        api.sketch_gcs(A, m, r, seed, prec="bf16")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        api.sketch_gcs(A, m, r, seed, prec="bf16")
+    torch.cuda.synchronize()
+    sk = (time.perf_counter() - t0) / steps
+    out["sketch_gcs_bf16"] = {"ms_per_call": 1e3 * sk, "gbs": n * d * 4 / sk / 1e9}
     ratio = (th[t] / th[0]).cpu().numpy()
     out["jl_ratio"] = {"min": float(ratio.min()), "max": float(ratio.max()),
                        "std": float(ratio.std()), "jl_std": float(np.sqrt(2.0 / t))}
@@ -308,6 +318,30 @@ def css_bench(api, torch, A, d, r, seed, steps, warmup):
         out[name] = {"ms_per_call": 1e3 * wall,
                      "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(stats.items())}}
     return out
+
+
+def zipf_fp8_bench(api, torch, steps, warmup, n=10_000_000, d=1000, dens=1e-4, r=1_000_000,
+                   m=4000, seed=0):
+    """G*S*A with the FP8 Gaussian product on the Zipf-row CSR configuration
+    (10,000,000 x 1,000 FP32, density 1e-4, Zipf(1.5) row lengths, r = 1e6,
+    m = 4,000), A resident in HBM."""
+    import synth
+    a = synth.csr_zipf(n, d, dens, seed=seed, dtype=np.float32)
+    A = api.CsrMatrix.from_scipy(a, device="cuda:0")
+    for _ in range(warmup):
+        api.sketch_gcs(A, m, r, seed, prec="fp8")
+    torch.cuda.synchronize()
+    with api.kernel_timing() as kt:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            api.sketch_gcs(A, m, r, seed, prec="fp8")
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        stats = kt.stats()
+    nbytes = a_bytes(a, "csr")
+    return {"workload": f"CSR {n} x {d} FP32, Zipf rows, nnz {a.nnz}, r = {r}, m = {m}",
+            "ms_per_call": 1e3 * wall, "gbs": nbytes / wall / 1e9, "a_bytes": nbytes,
+            "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(stats.items())}}
 
 
 def direct_bench(api, torch, A, a, b, bd, m, r, seed, steps, warmup, lsqr_resid):
@@ -408,7 +442,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the request-server measurement")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the Gaussian-only sketch, direct-solver, column-selection and JL "
+                    help="skip the Gaussian-only sketch, direct-solver, column-selection, Zipf FP8, JL "
                          "leverage measurements "
                          "(hardware-counter runs: one workload per kernel)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -611,6 +645,8 @@ def main():
         rec["direct"] = direct_bench(api, torch, A, a, b, bd, m, r, seed, args.steps,
                                      args.warmup, hr["lsq"]["resid"])
         rec["css"] = css_bench(api, torch, A, d, r, seed, args.steps, args.warmup)
+        log("FP8 sketch of the Zipf CSR 10,000,000 x 1,000")
+        rec["zipf_fp8"] = zipf_fp8_bench(api, torch, args.steps, args.warmup)
         log("leverage scores with the JL step, dense FP32 4,000,000 x 256")
         rec["leverage_jl"] = leverage_jl_bench(api, torch, args.steps, args.warmup)
         if ceil is not None:
