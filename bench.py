@@ -65,7 +65,7 @@ VALU_OPS_PER_SAMPLE_BF16 = 123 / 4
 PMC_TRAFFIC = {
     ("csr-1e6x500", "bf16"): {
         "source": "paper_2203_02798_amd/csrc/k_gauss_sparse.hip",
-        "sha256_prefix": "99f35ebb80159cb0",
+        "sha256_prefix": "813cd88f73adeb9b",
         "fetch_kib": 23572.2, "write_kib": 31250.0,
         "fetch_scale": 2.000, "write_scale": 1.000,
         "profile": "profiles/gauss_sparse_bf16_csr-1e6x500_pmc.md",
