@@ -520,9 +520,14 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
           double *C, int64_t ldc, Arena &ws, hipStream_t st) {
   if (M <= 0 || N <= 0) return 0;
   if (K <= 0) return fail(PSK_EINVAL, "internal GEMM with K <= 0");
+  // up to 1024 x 1024 outputs (the d x d products of the factorizations),
+  // 32 x 32 tiles give the chip four times the workgroups of 64 x 64 ones
 #define PSK_DG(TRA, TRB)                                                            \
-  return gemm_partial_launch<double, double, TRA, TRB, 2, 2, 2, 2, false>(         \
-      M, N, K, A, lda, B, ldb, alpha, beta, C, ldc, false, ws, st)
+  return (M * N <= 1024 * 1024)                                                     \
+      ? gemm_partial_launch<double, double, TRA, TRB, 2, 2, 1, 1, false>(            \
+            M, N, K, A, lda, B, ldb, alpha, beta, C, ldc, false, ws, st)             \
+      : gemm_partial_launch<double, double, TRA, TRB, 2, 2, 2, 2, false>(            \
+            M, N, K, A, lda, B, ldb, alpha, beta, C, ldc, false, ws, st)
   if (ta && tb) PSK_DG(true, true);
   if (ta) PSK_DG(true, false);
   if (tb) PSK_DG(false, true);
