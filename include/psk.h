@@ -504,6 +504,12 @@ int psk_server_destroy(psk_server *server);
  * storage, valid until the next timing call).  Not thread-safe against
  * concurrent psk calls that record events. */
 int psk_timing_enable(int on);
+/* Record only the brackets named in `names` (comma separated, e.g.
+ * "gauss_gemm"); NULL or "" records all of them again.  Each bracket costs
+ * two event creations and records on the host, so timing a whole pipeline
+ * slows its host side; a filter keeps the overhead to the kernels that are
+ * being measured. */
+int psk_timing_only(const char *names);
 int psk_timing_reset(void);
 int psk_timing_collect(const char *name, double *total_ms, int64_t *launches);
 const char *psk_timing_names(void);

@@ -34,7 +34,7 @@ EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "lsq_gram", "lsq_sketch_solve",
             "psk_probe_copy", "psk_probe_mfma_f64", "psk_probe_mfma_lowp",
             "psk_probe_valu_f32",
-            "psk_timing_enable", "psk_timing_reset",
+            "psk_timing_enable", "psk_timing_only", "psk_timing_reset",
             "psk_timing_collect", "psk_timing_names", "psk_server_create",
             "psk_server_submit", "psk_server_wait", "psk_server_poll",
             "psk_server_stats", "psk_server_destroy"]
@@ -170,6 +170,7 @@ _SIGS = {
     "psk_probe_mfma_lowp": ([ctypes.c_int, _i64, _vp, _vp], ctypes.c_int),
     "psk_probe_valu_f32": ([_i64, _vp, _vp], ctypes.c_int),
     "psk_timing_enable": ([ctypes.c_int], ctypes.c_int),
+    "psk_timing_only": ([ctypes.c_char_p], ctypes.c_int),
     "psk_timing_reset": ([], ctypes.c_int),
     "psk_timing_collect": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),

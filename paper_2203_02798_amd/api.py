@@ -472,15 +472,21 @@ def measure_ceilings(device="cuda:0", copy_bytes=1 << 30, reps=3):
 
 class kernel_timing:
     """Context manager that enables the library's event brackets around its
-    main kernels; ``stats()`` returns {name: (total_ms, launches)}."""
+    main kernels (only those named in ``only``, if given); ``stats()``
+    returns {name: (total_ms, launches)}."""
+
+    def __init__(self, only=None):
+        self.only = ",".join(only).encode() if only else None
 
     def __enter__(self):
         L.lib().psk_timing_reset()
+        L.lib().psk_timing_only(self.only)
         L.lib().psk_timing_enable(1)
         return self
 
     def __exit__(self, *exc):
         L.lib().psk_timing_enable(0)
+        L.lib().psk_timing_only(None)
         return False
 
     @staticmethod

@@ -29,6 +29,7 @@ std::mutex g_tmu;
 bool g_timing = false;
 std::vector<Pending> g_pending;
 std::map<std::string, Agg> g_agg;
+std::string g_only;  // ",name,name," to record only those brackets; empty: all
 std::string g_names;
 
 void drain_locked() {
@@ -50,6 +51,8 @@ bool timing_enabled() { return g_timing; }
 
 int timing_begin(const char *name, hipStream_t st) {
   std::lock_guard<std::mutex> lk(g_tmu);
+  if (!g_only.empty() && g_only.find("," + std::string(name) + ",") == std::string::npos)
+    return -1;
   Pending p;
   p.name = name;
   if (hipEventCreate(&p.a) != hipSuccess) return -1;
@@ -174,6 +177,12 @@ const char *psk_version(void) { return "psk 0.1.0 (gfx950)"; }
 int psk_timing_enable(int on) {
   std::lock_guard<std::mutex> lk(g_tmu);
   g_timing = on != 0;
+  return PSK_OK;
+}
+
+int psk_timing_only(const char *names) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_only = (names && *names) ? "," + std::string(names) + "," : std::string();
   return PSK_OK;
 }
 
