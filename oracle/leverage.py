@@ -15,6 +15,16 @@ Paper passages followed (arXiv 2203.02798):
   the algorithm (m = 0 here) or G S A (m > 0).
 * Algorithm ``ls_direct``: exact leverage scores theta_i = ||e_i^T U||^2 for an
   orthonormal basis U of range(A) (computed here from a thin QR of A).
+* The perturbation of a sketch, delta = ||(C^ - C) R^{-1}||_2 for a sketch C^
+  that stands in for C = G S A (a reduced-precision one, say) and R from a QR
+  of C.  It measures C^ in the metric in which C is orthonormal, the one of
+  Definition 2's embedding bound: with C^ R^{-1} = Q + F, ||F||_2 = delta,
+  the singular values of R^ R^{-1} lie in [1 - delta, 1 + delta], so the scores
+  of Algorithm ``ls_approximate_drineas`` from C^ and from C satisfy
+  (1 + delta)^-2 <= theta^_i / theta~_i <= (1 - delta)^-2 (delta < 1), and
+  the preconditioner of Algorithm ``least_squares_precondition`` built from
+  C^ keeps cond(A R^^{-1}) within a factor (1 + delta) / (1 - delta) of the
+  one built from C.
 
 Readings: full column rank is assumed (the paper's "truncate if needed" is
 not applied); R is normalised to a non-negative diagonal.  Pi is drawn by the
@@ -88,6 +98,25 @@ def leverage_exact(a):
         a = a.toarray()
     q, _ = np.linalg.qr(np.asarray(a, dtype=np.float64), mode="reduced")
     return np.einsum("ij,ij->i", q, q)
+
+
+def sketch_perturbation(c_hat, c):
+    """delta = ||(C^ - C) R^{-1}||_2 with R from QR(C) (both m x d, C of full
+    column rank): the relative perturbation of the sketch C^ against C in
+    the metric in which C is orthonormal.  Computed exactly: the triangular
+    solve F^T = R^{-T} (C^ - C)^T, then the largest singular value of F."""
+    c_hat = np.asarray(c_hat, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    r = qr_r(c)
+    f = sla.solve_triangular(r, (c_hat - c).T, trans="T", lower=False).T
+    return float(np.linalg.norm(f, 2))
+
+
+def leverage_ratio_bound(delta):
+    """Largest |theta^_i / theta~_i - 1| a sketch perturbation delta < 1 allows:
+    (1 - delta)^-2 - 1 (the upper edge; the lower one, 1 - (1 + delta)^-2, is
+    smaller)."""
+    return (1.0 - delta) ** -2 - 1.0
 
 
 def sketch_distortion(a, m, r, seed):
