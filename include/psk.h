@@ -107,8 +107,8 @@ typedef struct psk_mat {
 /* ---- precision of the Gaussian GEMM of sketch_gcs / lsq_solve ---------- */
 enum {
   PSK_PREC_F64 = 0,   /* G and S*A in FP64, FP64 MFMA, FP64 accumulation      *
-                       * (S*A of FP32 A is summed in FP32, as sketch_cs      *
-                       * documents, then widened exactly)                    */
+                       * (S*A of FP32 A is summed in FP64 from the exactly   *
+                       * widened entries and used unrounded)                 */
   PSK_PREC_BF16 = 1,  /* G rounded to bfloat16, S*A split into two bfloat16   *
                        * limbs (hi + lo), BF16 MFMA with FP32 accumulation,   *
                        * FP64 reduction of the K-split partial products.      *
@@ -175,9 +175,11 @@ int cs_hash(int64_t row0, int64_t count, int64_t r, uint64_t seed,
  *   SA : r x d row-major, leading dimension d, dtype of A (device, written
  *        entirely; rows of empty buckets are zero).
  * Row i of A is added to row h(i) of SA with sign sigma_i; the rows of one
- * bucket are summed in increasing row order in the dtype of A.
+ * bucket are summed in increasing row order in FP64 (FP32 entries widened
+ * exactly) and the sum is rounded once to the dtype of A.  Every Gaussian
+ * product of this library reads those FP64 sums before any rounding.
  * Errors: PSK_EINVAL (shapes, r < 1, NULL pointers), PSK_EUNSUPPORTED (CSR
- * with d > 8192 for FP64 / 16384 for FP32), PSK_ENOMEM. */
+ * with d > 20480), PSK_ENOMEM. */
 int sketch_cs(const psk_mat *A, int64_t r, uint64_t seed, void *SA,
               void *ws, size_t ws_bytes, void *stream);
 

@@ -108,11 +108,11 @@ static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 // plan + run helpers shared by the entry points, psk_workspace_size and the
 // request server
 int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws,
-                 hipStream_t st) {
+                 hipStream_t st, bool out_f64) {
   uint32_t *perm = nullptr, *bptr = nullptr;
   int rc = cs_bin(A.n, (uint32_t)r, seed, ws, st, &perm, &bptr);
   if (rc) return rc;
-  return cs_apply(A, (uint32_t)r, perm, bptr, SA, ws, st);
+  return cs_apply(A, (uint32_t)r, perm, bptr, SA, ws, st, out_f64);
 }
 
 int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec,
@@ -135,10 +135,11 @@ int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int pre
     if (fb) return gauss_gemm_bf16_csr(m, r, A, perm, bptr, seed, (double *)C, ws, st);
     return gauss_gemm_fp8_csr(m, r, A, perm, bptr, seed, (double *)C, ws, st);
   }
-  void *SA = ws.take<unsigned char>((size_t)r * A.d * elem_size(A.dtype));
-  int rc = do_sketch_cs(A, r, seed, SA, ws, st);
+  // S*A as its FP64 sums (FP32 A too), the operand of every Gaussian GEMM
+  void *SA = ws.take<double>((size_t)r * A.d);
+  int rc = do_sketch_cs(A, r, seed, SA, ws, st, true);
   if (rc) return rc;
-  return gauss_gemm(m, r, A.d, seed, prec, SA, A.dtype, (double *)C, ws, st);
+  return gauss_gemm(m, r, A.d, seed, prec, SA, PSK_F64, (double *)C, ws, st);
 }
 
 int do_sketch_g(const psk_mat &A, int64_t m, uint64_t seed, int prec, double *C, Arena &ws,

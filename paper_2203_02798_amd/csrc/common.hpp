@@ -222,15 +222,16 @@ __device__ __forceinline__ void gauss4_f32(uint64_t q, uint32_t a, uint64_t seed
 // order.  The row pointers and the first kBucketEnt entries of up to 64 rows
 // are loaded at once, one row per lane, and the rows are then applied one
 // after another from registers; rows with more entries are spread over the
-// wavefront.
+// wavefront.  The accumulators have type AT (FP64 for every S*A of this
+// library: FP32 entries are widened exactly and summed in FP64).
 constexpr int kBucketEnt = 4;
 
-template <typename T>
+template <typename T, typename AT>
 __device__ __forceinline__ void bucket_rows_add(const T *__restrict__ vals,
                                                 const int64_t *__restrict__ indptr,
                                                 const int32_t *__restrict__ indices,
                                                 const uint32_t *__restrict__ perm, uint32_t j0,
-                                                uint32_t j1, T *acc) {
+                                                uint32_t j1, AT *acc) {
   const int lane = (int)(threadIdx.x & 63u);
   for (uint32_t base = j0; base < j1; base += 64) {
     const uint32_t j = base + (uint32_t)lane;
@@ -246,14 +247,14 @@ __device__ __forceinline__ void bucket_rows_add(const T *__restrict__ vals,
     const int64_t len = p1 - p0;
     const bool lng = len > kBucketEnt;
     int ci[kBucketEnt];
-    T xv[kBucketEnt];
+    AT xv[kBucketEnt];
 #pragma unroll
     for (int e = 0; e < kBucketEnt; ++e) {
       ci[e] = 0;
-      xv[e] = T(0);
+      xv[e] = AT(0);
       if (!lng && e < len) {
         ci[e] = indices[p0 + e];
-        const T v = vals[p0 + e];
+        const AT v = (AT)vals[p0 + e];
         xv[e] = ng ? -v : v;
       }
     }
@@ -265,7 +266,7 @@ __device__ __forceinline__ void bucket_rows_add(const T *__restrict__ vals,
         const int64_t q1 = __shfl(p1, i, 64);
         const int ngi = __shfl(ng, i, 64);
         for (int64_t p = q0 + lane; p < q1; p += 64) {
-          const T v = vals[p];
+          const AT v = (AT)vals[p];
           atomicAdd(&acc[indices[p]], ngi ? -v : v);
         }
       } else if (lane == i) {

@@ -72,9 +72,11 @@ int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
                hipStream_t st, uint32_t **skeys, uint32_t **svals, uint32_t *ptr);
 int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
                    int32_t *h, int8_t *sign, hipStream_t st);
-// S*A into SA (r x d row-major, dtype of A).
+// S*A into SA (r x d row-major): each bucket's rows summed in FP64 in bin
+// order, written in the dtype of A, or in FP64 with out_f64.
 int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
-             const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st);
+             const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st,
+             bool out_f64 = false);
 // Wavefronts per bucket cs_apply uses for n rows in r buckets (1 = one
 // wavefront sums a whole bucket).
 int cs_splits(int64_t n, int64_t r);
@@ -88,8 +90,9 @@ int check_mat(const psk_mat *A);
 int check_r(int64_t r);
 
 // S*A and G*S*A end to end (binning, scatter, GEMM), abi.hip.
+// S*A in the dtype of A (FP64 sums rounded once), or as the FP64 sums
 int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws,
-                 hipStream_t st);
+                 hipStream_t st, bool out_f64 = false);
 int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec,
                   void *C, Arena &ws, hipStream_t st);
 // C = G*A (sketch_g): the Gaussian GEMM with A as operand (dense), or the

@@ -15,6 +15,8 @@
 // advances 16 at a time through LDS tiles kept k-major (As[k][i], Bs[k][j]),
 // with the next chunk prefetched into registers while the current one is
 // multiplied.  FP32 inputs are widened to FP64 when staged.
+#include <type_traits>
+
 #include "internal.hpp"
 
 namespace psk {
@@ -304,33 +306,90 @@ int gemm_partial_launch(int64_t M, int64_t N, int64_t K, const TA *A, int64_t ld
   return 0;
 }
 
-// Fused row norms with a column tile of B resident in LDS.  B[:, n0 : n0 +
-// BNC] (rows padded to a multiple of the chunk with zeros, row stride BNC + 4) is
-// staged once per workgroup; the 8 wavefronts then stream row tiles of A
-// (kBresMB blocks of 16 rows) straight from memory into the MFMA operand
-// registers (no LDS round trip and no barrier in the main loop) and keep
-// kBresMB x BNC/16 accumulator blocks.
+// Four consecutive elements of one row as loaded (raw, in the dtype of A)
+// and whether they are inside the matrix.  The load is branch-free: the
+// address is clamped to a valid element and the values are selected and
+// widened only when used, so the load stays in flight meanwhile (a load
+// inside a branch, or converted right away, is waited for on the spot).
+// VEC: one 16-byte FP32 load / two FP64 ones; needs d % 4 == 0 so that a
+// column group is wholly inside or outside.
+template <typename TA>
+struct Raw4 {
+  TA x[4];
+  bool ok[4];
+};
+
+template <typename TA, bool VEC>
+__device__ __forceinline__ void raw4_load(const TA *__restrict__ A, int64_t ld, int64_t d,
+                                          int64_t row, bool rok, int64_t c, Raw4<TA> &v) {
+  if constexpr (VEC) {
+    const bool ok = rok && c < d;
+    const TA *p = A + (ok ? row * ld + c : 0);
+    if constexpr (sizeof(TA) == 4) {
+      const float4 x = *reinterpret_cast<const float4 *>(p);
+      v.x[0] = x.x; v.x[1] = x.y; v.x[2] = x.z; v.x[3] = x.w;
+    } else {
+      const double2 x = *reinterpret_cast<const double2 *>(p);
+      const double2 y = *reinterpret_cast<const double2 *>(p + 2);
+      v.x[0] = x.x; v.x[1] = x.y; v.x[2] = y.x; v.x[3] = y.y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v.ok[q] = ok;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool ok = rok && c + q < d;
+      v.x[q] = A[ok ? row * ld + c + q : 0];
+      v.ok[q] = ok;
+    }
+  }
+}
+
+template <typename TA>
+__device__ __forceinline__ double raw4_get(const Raw4<TA> &v, int q) {
+  return v.ok[q] ? (double)v.x[q] : 0.0;
+}
+
+// Fused row norms with a column tile of B resident in LDS.  A workgroup
+// holds 32-column tiles of B: one (PAIR false), or two, tiles p and
+// T - 1 - p of the T = ceil(k / 32) tiles (PAIR true; one when they
+// coincide).  Its B columns (rows padded to a multiple of the K chunk with
+// zeros, row stride BNC + 4) are staged once; the 8 wavefronts then stream
+// row tiles of A (kBresMB blocks of 16 rows) straight from memory into the
+// MFMA operand registers (no LDS round trip and no barrier in the main loop)
+// and keep kBresMB x BNC/16 accumulator blocks.
+// While staging, the workgroup finds each tile's row extent: one past the
+// last row of B holding a nonzero in the tile's columns.  K chunks at or past
+// a tile's extent only add exact zeros to its products, so they are skipped:
+// for B = R^{-1} upper triangular, tile t needs its first 32 (t + 1) rows,
+// and pairing tile t with tile T - 1 - t gives every workgroup the same
+// work.  (Skipped products are a * 0 with a finite: the sums are the same
+// bits as the full product's.)
 // Inside a K chunk of 4 kBresKW columns, lane (li, kq) feeds column
 // k0 + kBresKW kq + s of A at step s, and B row k0 + kBresKW kq + s: the same
 // permutation of the chunk on both operands, so one lane reads kBresKW
 // consecutive elements of its row.
-// part[nt * n + row] = the row's squared norm over the tile's BNC columns.
-// Workgroups form row groups of tn (one per column tile) that sit on one XCD
+// part[slot * n + row] = the row's squared norm over the slot's columns.
+// Workgroups form row groups of tn (one per slot) that sit on one XCD
 // (linear ids equal mod 8) and walk the same rows, so A is fetched into that
-// XCD's L2 about once for all tn tiles.
+// XCD's L2 about once for all tn slots.
 constexpr int kBresThreads = 512;
 constexpr int kBresMB = 2;  // 16-row blocks per wavefront tile
 constexpr int kBresRows = 16 * kBresMB;
 constexpr int kBresKW = 8;
+constexpr int kBresTile = 32;  // columns of B per tile
 
-template <typename TA, int BNC, bool VEC>
+template <typename TA, bool PAIR, bool VEC>
 __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
     const TA *__restrict__ A, int64_t ld, int64_t n, int64_t d, const double *__restrict__ B,
     int64_t k, int tn, double *__restrict__ part) {
   static_assert(!VEC || sizeof(TA) == 4, "vector loads are for FP32 A");
   extern __shared__ double Bs[];
+  __shared__ int ext[2];
+  constexpr int BNC = PAIR ? 2 * kBresTile : kBresTile;
   constexpr int LDB = BNC + 4;
   constexpr int NB = BNC / 16;
+  constexpr int NBH = kBresTile / 16;  // blocks per tile
   constexpr int MB = kBresMB;
   constexpr int KW = kBresKW;  // consecutive elements of a row per lane per chunk
   constexpr int CK = 4 * KW;   // K chunk width
@@ -341,16 +400,35 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
   const int nt = (int)(slot % tn);
   const int64_t ngroups = nblk / tn;
   const int64_t group = (slot / tn) * 8 + (lin & 7);
-  const int64_t n0 = (int64_t)nt * BNC;
+  const int64_t ntile = ceil_div(k, (int64_t)kBresTile);
+  // first columns of the (one or two) tiles; -1: no second tile
+  const int64_t c0a = (int64_t)nt * kBresTile;
+  const int64_t tb = PAIR ? ntile - 1 - nt : -1;
+  const int64_t c0b = (PAIR && tb != nt) ? tb * kBresTile : -1;
   const int64_t kch = (d + CK - 1) / CK;
   const int64_t drows = kch * CK;
+  if (tid < 2) ext[tid] = 0;
+  __syncthreads();
+  int exa = 0, exb = 0;
   for (int64_t e = tid; e < drows * BNC; e += kBresThreads) {
     const int64_t kk = e / BNC;
     const int jj = (int)(e - kk * BNC);
-    const int64_t col = n0 + jj;
-    Bs[kk * LDB + jj] = (kk < d && col < k) ? B[kk * k + col] : 0.0;
+    const bool hb = jj >= kBresTile;
+    const int64_t cb = hb ? c0b : c0a;
+    const int64_t col = cb + (hb ? jj - kBresTile : jj);
+    const double v = (cb >= 0 && kk < d && col < k) ? B[kk * k + col] : 0.0;
+    Bs[kk * LDB + jj] = v;
+    if (v != 0.0) {  // NaN counts as nonzero
+      if (hb) exb = (int)kk + 1;
+      else exa = (int)kk + 1;
+    }
   }
+  if (exa) atomicMax(&ext[0], exa);
+  if (exb) atomicMax(&ext[1], exb);
   __syncthreads();
+  // K chunks each tile needs (uniform over the workgroup)
+  const int64_t kca = __builtin_amdgcn_readfirstlane((ext[0] + CK - 1) / CK);
+  const int64_t kcb = __builtin_amdgcn_readfirstlane((ext[1] + CK - 1) / CK);
   const int64_t ntiles = (n + kBresRows - 1) / kBresRows;
   for (int64_t t = group * 8 + wave; t < ntiles; t += ngroups * 8) {
     const int64_t r0 = t * kBresRows;
@@ -367,51 +445,67 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) acc[mb][nb] = v4d{0.0, 0.0, 0.0, 0.0};
-    auto load = [&](int64_t c, double (&a)[MB][KW]) __attribute__((always_inline)) {
+    // the chunk's KW elements of each of the lane's rows, loaded raw and
+    // branch-free (Raw4: clamped address, values selected and widened in
+    // step), so the next chunk's loads stay in flight during this one's
+    // matrix instructions
+    typedef Raw4<TA> RawChunk[MB][KW / 4];
+    auto load = [&](int64_t c, RawChunk &a) __attribute__((always_inline)) {
       const int64_t kb = c * CK + KW * kq;
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        if constexpr (VEC) {
+      for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-          for (int q = 0; q < KW / 4; ++q) {
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (rin[mb] && kb + 4 * q < d)
-              v = *reinterpret_cast<const float4 *>(arow[mb] + kb + 4 * q);
-            a[mb][4 * q + 0] = v.x;
-            a[mb][4 * q + 1] = v.y;
-            a[mb][4 * q + 2] = v.z;
-            a[mb][4 * q + 3] = v.w;
-          }
-        } else {
-#pragma unroll
-          for (int s = 0; s < KW; ++s)
-            a[mb][s] = (rin[mb] && kb + s < d) ? (double)arow[mb][kb + s] : 0.0;
-        }
-      }
+        for (int q = 0; q < KW / 4; ++q)
+          raw4_load<TA, VEC>(arow[mb], 0, d, 0, rin[mb], kb + 4 * q, a[mb][q]);
     };
-    auto step = [&](int64_t c, const double (&a)[MB][KW]) __attribute__((always_inline)) {
+    // one K chunk for the blocks of the tiles in HM (bit 0: first tile,
+    // bit 1: second tile)
+    auto step = [&](auto hm, int64_t c, const RawChunk &raw) __attribute__((always_inline)) {
+      constexpr int HM = decltype(hm)::value;
+      double a[MB][KW];
+#pragma unroll
+      for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int s = 0; s < KW; ++s) a[mb][s] = raw4_get(raw[mb][s / 4], s % 4);
 #pragma unroll
       for (int s = 0; s < KW; ++s) {
         const double *brow = Bs + (c * CK + KW * kq + s) * LDB + li;
         double bv[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) bv[nb] = brow[nb * 16];
+        for (int nb = 0; nb < NB; ++nb)
+          if ((HM >> (nb / NBH)) & 1) bv[nb] = brow[nb * 16];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
-            acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][s], bv[nb], acc[mb][nb],
-                                                               0, 0, 0);
+            if ((HM >> (nb / NBH)) & 1)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][s], bv[nb], acc[mb][nb],
+                                                                 0, 0, 0);
       }
     };
-    double a0[MB][KW], a1[MB][KW];
-    load(0, a0);
-    for (int64_t c = 0; c < kch; c += 2) {
-      if (c + 1 < kch) load(c + 1, a1);
-      step(c, a0);
-      if (c + 1 >= kch) break;
-      if (c + 2 < kch) load(c + 2, a0);
-      step(c + 1, a1);
+    // chunks c0 .. c1 - 1, the next chunk's A loaded while one is multiplied
+    auto run = [&](auto hm, int64_t c0, int64_t c1) __attribute__((always_inline)) {
+      if (c0 >= c1) return;
+      RawChunk a0, a1;
+      load(c0, a0);
+      for (int64_t c = c0; c < c1; c += 2) {
+        if (c + 1 < c1) load(c + 1, a1);
+        step(hm, c, a0);
+        if (c + 1 >= c1) break;
+        if (c + 2 < c1) load(c + 2, a0);
+        step(hm, c + 1, a1);
+      }
+    };
+    using HBoth = std::integral_constant<int, 3>;
+    using HA = std::integral_constant<int, 1>;
+    using HB = std::integral_constant<int, 2>;
+    if constexpr (PAIR) {
+      const int64_t kboth = kca < kcb ? kca : kcb;
+      run(HBoth{}, 0, kboth);
+      if (kca > kboth) run(HA{}, kboth, kca);
+      else if (kcb > kboth) run(HB{}, kboth, kcb);
+    } else {
+      run(HA{}, 0, kca);
     }
     // lane (li, kq) holds rows kq + 4 e, column li of each 16 x 16 block
 #pragma unroll
@@ -429,21 +523,23 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
   }
 }
 
-// Column width of the LDS-resident form for d (0: the tile does not fit).
+// LDS-resident form for d: 2 paired tiles (64 columns) when k > 32 and they
+// fit, else 1 tile of 32 columns; 0: the tile does not fit.
 int bres_width(int64_t d, int64_t k) {
   const int64_t drows = ceil_div(d, (int64_t)(4 * kBresKW)) * (4 * kBresKW);
-  if (k > 32 && drows * (64 + 4) * 8 <= 163840) return 64;
-  if (drows * (32 + 4) * 8 <= 163840) return 32;
+  if (k > kBresTile && drows * (2 * kBresTile + 4) * 8 <= 163840) return 2;
+  if (drows * (kBresTile + 4) * 8 <= 163840) return 1;
   return 0;
 }
 
-template <typename TA, int BNC, bool VEC>
+template <typename TA, bool PAIR, bool VEC>
 int bres_launch(const psk_mat &Am, const double *B, int64_t k, double *part, int tn,
                 hipStream_t st) {
   const int64_t n = Am.n, d = Am.d;
+  constexpr int BNC = PAIR ? 2 * kBresTile : kBresTile;
   const size_t lds =
       (size_t)ceil_div(d, (int64_t)(4 * kBresKW)) * (4 * kBresKW) * (BNC + 4) * sizeof(double);
-  PSK_HIP_TRY(hipFuncSetAttribute((const void *)k_rownorm_bres<TA, BNC, VEC>,
+  PSK_HIP_TRY(hipFuncSetAttribute((const void *)k_rownorm_bres<TA, PAIR, VEC>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   // one workgroup per CU (the LDS tile), row groups of tn workgroups per XCD
   const int64_t tiles = ceil_div(n, (int64_t)kBresRows);
@@ -453,7 +549,7 @@ int bres_launch(const psk_mat &Am, const double *B, int64_t k, double *part, int
   const int64_t need = ceil_div(tiles, (int64_t)8);  // 8 wavefronts per workgroup
   while (groups > 8 && groups / 2 >= need) groups /= 2;
   const unsigned nblk = (unsigned)(groups * tn);
-  k_rownorm_bres<TA, BNC, VEC><<<nblk, kBresThreads, lds, st>>>(
+  k_rownorm_bres<TA, PAIR, VEC><<<nblk, kBresThreads, lds, st>>>(
       (const TA *)Am.values, Am.ld, n, d, B, k, tn, part);
   return 0;
 }
@@ -465,7 +561,9 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
   const TA *A = (const TA *)Am.values;
   const int bw = bres_width(d, k);
   if (bw > 0) {
-    const int tn = (int)ceil_div(k, (int64_t)bw);
+    // slots: pairs of 32-column tiles (bw 2) or single tiles (bw 1)
+    const int64_t ntile = ceil_div(k, (int64_t)kBresTile);
+    const int tn = (int)(bw == 2 ? ceil_div(ntile, (int64_t)2) : ntile);
     double *part = ws.take<double>((size_t)tn * n);
     if (ws.dry()) return 0;
     if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for row norms");
@@ -473,16 +571,16 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
     const bool vec = Am.ld % 4 == 0 && d % 4 == 0 && ((uintptr_t)Am.values & 15) == 0;
     int rc;
     if constexpr (sizeof(TA) == 4) {
-      if (bw == 64)
-        rc = vec ? bres_launch<TA, 64, true>(Am, B, k, part, tn, st)
-                 : bres_launch<TA, 64, false>(Am, B, k, part, tn, st);
+      if (bw == 2)
+        rc = vec ? bres_launch<TA, true, true>(Am, B, k, part, tn, st)
+                 : bres_launch<TA, true, false>(Am, B, k, part, tn, st);
       else
-        rc = vec ? bres_launch<TA, 32, true>(Am, B, k, part, tn, st)
-                 : bres_launch<TA, 32, false>(Am, B, k, part, tn, st);
+        rc = vec ? bres_launch<TA, false, true>(Am, B, k, part, tn, st)
+                 : bres_launch<TA, false, false>(Am, B, k, part, tn, st);
     } else {
       (void)vec;
-      rc = bw == 64 ? bres_launch<TA, 64, false>(Am, B, k, part, tn, st)
-                    : bres_launch<TA, 32, false>(Am, B, k, part, tn, st);
+      rc = bw == 2 ? bres_launch<TA, true, false>(Am, B, k, part, tn, st)
+                   : bres_launch<TA, false, false>(Am, B, k, part, tn, st);
     }
     if (rc) return rc;
     k_rownorm_reduce<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(part, n, tn, alpha, beta, x);
@@ -513,6 +611,191 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
   return 0;
 }
 
+
+// ---------------------------------------------------------------------------
+// Gram matrix of a dense tall A: C = A^T A as a sum over row slabs
+// ---------------------------------------------------------------------------
+// Each wavefront owns one 64 x 64 tile (I, J), I <= J, of the upper block
+// triangle of C and one slab of consecutive rows of A, and accumulates that
+// slab's contribution in registers (4 x 4 blocks of 16 x 16 FP64
+// accumulators).  Lane (li, kq) = (lane % 16, lane / 16) reads, for row
+// k0 + kq, the four consecutive columns 64 I + 4 li .. + 3 (one vector load)
+// and the same four of the tile's J columns: component a of that load is
+// row li of the MFMA operand block a, so block a of the tile holds the
+// columns 64 I + 4 i + a, i = 0 .. 15 (and likewise for J).  Block (a, b)
+// then accumulates C[64 I + 4 i + a][64 J + 4 j + b].  On a diagonal tile
+// (I = J) block (b, a) is the transpose of block (a, b), so only a <= b are
+// multiplied (10 of 16) and the others are mirrored when the tile is
+// written: the executed products are those of the upper triangle at the
+// 16 x 16 block level, n d (d + 16) flops for d a multiple of 64.
+// Rows past the slab and columns past d read as zero.  Slab s of tile t
+// writes its 64 x 64 partial (both triangles of a diagonal tile) to
+// part[s][t]; k_gram_reduce sums the slabs in order (no atomics).
+// Work item g = (slab g / U, tile g % U), U tiles; four per workgroup, and
+// workgroups of the same XCD (linear ids equal mod 8) take consecutive
+// items, so the tiles of one slab read its rows through one L2.
+constexpr int kGramPF = 4;  // row steps whose loads are in flight
+
+template <typename TA, bool VEC>
+__global__ __launch_bounds__(256) void k_gram_syrk(const TA *__restrict__ A, int64_t ld,
+                                                   int64_t n, int64_t d, int T, int U,
+                                                   int64_t slabs, int64_t rows_per,
+                                                   double *__restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, kq = lane >> 4;
+  const int64_t nblk = gridDim.x;
+  int64_t lin = blockIdx.x;
+  if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
+  const int64_t g = lin * 4 + wave;
+  if (g >= slabs * U) return;
+  const int64_t slab = g / U;
+  const int t = (int)(g - slab * U);
+  // tile t of the upper triangle in row-major order -> (I, J)
+  int I = 0, rest = t;
+  while (rest >= T - I) {
+    rest -= T - I;
+    ++I;
+  }
+  const int J = I + rest;
+  const bool diag = I == J;
+  const int64_t k_begin = slab * rows_per;
+  int64_t k_end = k_begin + rows_per;
+  if (k_end > n) k_end = n;
+  const int64_t ci = (int64_t)I * 64 + 4 * li, cj = (int64_t)J * 64 + 4 * li;
+  v4d acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  auto run = [&](auto dg) __attribute__((always_inline)) {
+    constexpr bool DG = decltype(dg)::value;
+    Raw4<TA> xa[kGramPF], xb[kGramPF];
+    auto fetch = [&](int p, int64_t k0) __attribute__((always_inline)) {
+      const int64_t row = k0 + kq;
+      const bool rok = row < k_end;
+      raw4_load<TA, VEC>(A, ld, d, rok ? row : 0, rok, ci, xa[p]);
+      if constexpr (!DG) raw4_load<TA, VEC>(A, ld, d, rok ? row : 0, rok, cj, xb[p]);
+    };
+#pragma unroll
+    for (int p = 0; p < kGramPF; ++p) fetch(p, k_begin + 4 * p);
+    for (int64_t k0 = k_begin; k0 < k_end; k0 += 4 * kGramPF) {
+#pragma unroll
+      for (int p = 0; p < kGramPF; ++p) {
+        double av[4], bv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          av[q] = raw4_get(xa[p], q);
+          bv[q] = DG ? av[q] : raw4_get(xb[p], q);
+        }
+        fetch(p, k0 + 4 * (p + kGramPF));
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            if (!DG || a <= b)
+              acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+  };
+  if (diag) run(std::true_type{});
+  else run(std::false_type{});
+  // lane (li, kq) holds rows kq + 4 e, column li of each block: the tile's
+  // local element (4 (kq + 4 e) + a, 4 li + b)
+  double *o = part + (slab * U + t) * 4096;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (diag && a > b) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int pr = 4 * (kq + 4 * e) + a, pc = 4 * li + b;
+        o[pr * 64 + pc] = acc[a][b][e];
+        if (diag && a < b) o[pc * 64 + pr] = acc[a][b][e];
+      }
+    }
+}
+
+// First level of the slab sum: group q of kGramGroups sums its slabs in
+// order, gpart[q][p][c] for the d x d output, taken from the upper tile
+// (transposed for p > c).
+constexpr int kGramGroups = 16;
+
+__global__ __launch_bounds__(256) void k_gram_reduce1(const double *__restrict__ part,
+                                                      int64_t d, int T, int U, int64_t slabs,
+                                                      double *__restrict__ gpart) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t q = blockIdx.y;
+  if (e >= d * d) return;
+  int64_t p = e / d, c = e % d;
+  if (p / 64 > c / 64) {
+    const int64_t x = p;
+    p = c;
+    c = x;
+  }
+  const int I = (int)(p / 64), J = (int)(c / 64);
+  const int t = I * T - I * (I - 1) / 2 + (J - I);
+  const int64_t off = (int64_t)t * 4096 + (p % 64) * 64 + (c % 64);
+  const int64_t s0 = slabs * q / kGramGroups, s1 = slabs * (q + 1) / kGramGroups;
+  double acc = 0.0;
+  for (int64_t s = s0; s < s1; ++s) acc += part[s * U * 4096 + off];
+  gpart[q * d * d + e] = acc;
+}
+
+// C = alpha * sum of the groups (in order) + beta * C (beta == 0 ignores C)
+template <typename TO>
+__global__ __launch_bounds__(256) void k_gram_reduce2(const double *__restrict__ gpart,
+                                                      int64_t dd, double alpha, double beta,
+                                                      TO *__restrict__ C) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= dd) return;
+  double acc = gpart[e];
+#pragma unroll
+  for (int q = 1; q < kGramGroups; ++q) acc += gpart[q * dd + e];
+  double v = alpha * acc;
+  if (beta != 0.0) v += beta * (double)C[e];
+  C[e] = (TO)v;
+}
+
+template <typename TA>
+int gram_syrk_launch(double alpha, const psk_mat &Am, double beta, void *C, bool out_f32,
+                     Arena &ws, hipStream_t st) {
+  const int64_t n = Am.n, d = Am.d;
+  const int T = (int)ceil_div(d, (int64_t)64);
+  const int U = T * (T + 1) / 2;
+  // about two wavefronts per SIMD in one round: 2048 work items
+  int64_t slabs = 2048 / U;
+  if (slabs < 8) slabs = 8;
+  int64_t rows_per = ceil_div(ceil_div(n, slabs), (int64_t)(4 * kGramPF)) * (4 * kGramPF);
+  slabs = ceil_div(n, rows_per);
+  double *part = ws.take<double>((size_t)slabs * U * 4096);
+  double *gpart = ws.take<double>((size_t)kGramGroups * d * d);
+  if (ws.dry()) return 0;
+  if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the Gram matrix");
+  const int64_t items = slabs * U;
+  int64_t nblk = ceil_div(items, (int64_t)4);
+  nblk = ceil_div(nblk, (int64_t)8) * 8;  // whole XCD rounds for the remap
+  const uintptr_t addr = (uintptr_t)Am.values;
+  const bool vec = (Am.ld % 4 == 0) && (d % 4 == 0) && (addr % 16 == 0);
+  if (vec)
+    k_gram_syrk<TA, true><<<(unsigned)nblk, 256, 0, st>>>((const TA *)Am.values, Am.ld, n, d, T,
+                                                          U, slabs, rows_per, part);
+  else
+    k_gram_syrk<TA, false><<<(unsigned)nblk, 256, 0, st>>>((const TA *)Am.values, Am.ld, n, d,
+                                                           T, U, slabs, rows_per, part);
+  const int64_t dd = d * d;
+  dim3 g1((unsigned)ceil_div(dd, (int64_t)256), kGramGroups);
+  k_gram_reduce1<<<g1, 256, 0, st>>>(part, d, T, U, slabs, gpart);
+  if (out_f32)
+    k_gram_reduce2<float><<<(unsigned)ceil_div(dd, (int64_t)256), 256, 0, st>>>(
+        gpart, dd, alpha, beta, (float *)C);
+  else
+    k_gram_reduce2<double><<<(unsigned)ceil_div(dd, (int64_t)256), 256, 0, st>>>(
+        gpart, dd, alpha, beta, (double *)C);
+  PSK_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 }  // namespace
 
 int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
@@ -538,14 +821,8 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
 int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
                hipStream_t st, bool out_f64) {
   KTimer timer("gram", st, !ws.dry());
-  const bool f32 = A.dtype == PSK_F32;
-  if (f32)
-    return gemm_partial_launch<float, float, true, false, 2, 2, 2, 2, true>(
-        A.d, A.d, A.n, (const float *)A.values, A.ld, (const float *)A.values, A.ld,
-        alpha, beta, C, A.d, !out_f64, ws, st);
-  return gemm_partial_launch<double, double, true, false, 2, 2, 2, 2, true>(
-      A.d, A.d, A.n, (const double *)A.values, A.ld, (const double *)A.values, A.ld,
-      alpha, beta, C, A.d, false, ws, st);
+  if (A.dtype == PSK_F32) return gram_syrk_launch<float>(alpha, A, beta, C, !out_f64, ws, st);
+  return gram_syrk_launch<double>(alpha, A, beta, C, false, ws, st);
 }
 
 int rownorms_dense(double alpha, const psk_mat &A, const double *B, int64_t k,

@@ -128,13 +128,13 @@ __global__ __launch_bounds__(512) void k_scatter_csr_limbs(
     const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
     uint16_t *__restrict__ hi, uint16_t *__restrict__ lo) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *accs = reinterpret_cast<T *>(smem_raw);  // 8 x npad
+  double *accs = reinterpret_cast<double *>(smem_raw);  // 8 x npad FP64 sums
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int64_t quad = blockIdx.x;
   const int64_t b = quad * 8 + wave;
-  T *acc = accs + (int64_t)wave * npad;
-  for (int64_t c = lane; c < npad; c += 64) acc[c] = T(0);
+  double *acc = accs + (int64_t)wave * npad;
+  for (int64_t c = lane; c < npad; c += 64) acc[c] = 0.0;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   if (b < r) bucket_rows_add(vals, indptr, indices, perm, bptr[b], bptr[b + 1], acc);
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(512) void k_scatter_csr_limbs(
     uint16_t h8[8], l8[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const double v = (double)accs[(int64_t)e * npad + n];
+      const double v = accs[(int64_t)e * npad + n];
       const uint16_t h = bf16_of_f64(v);
       h8[e] = h;
       l8[e] = bf16_of_f64(v - bf16_to_f64(h));  // exact difference
@@ -354,8 +354,10 @@ int bf16_run(const Bf16Plan &P, int64_t m, int64_t d, uint64_t seed, double *C,
   return 0;
 }
 
+// FP64 bucket sums of 8 buckets over the padded columns
 size_t csr_limbs_lds(const psk_mat &A, int64_t d) {
-  return (size_t)8 * ceil_div(d, kBN) * kBN * elem_size(A.dtype);
+  (void)A;
+  return (size_t)8 * ceil_div(d, kBN) * kBN * sizeof(double);
 }
 
 }  // namespace

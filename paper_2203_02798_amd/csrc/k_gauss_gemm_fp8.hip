@@ -140,7 +140,7 @@ struct RowBatch {
   int nrank;  // 1 + the largest rank in the batch
   uint64_t longmask;
   int ci[kBucketEnt];
-  T xv[kBucketEnt];
+  double xv[kBucketEnt];  // FP64: every S*A sum is formed in FP64
 };
 
 template <typename T>
@@ -173,10 +173,10 @@ __device__ __forceinline__ void load_batch(RowBatch<T> &B, uint32_t base, uint32
 #pragma unroll
   for (int e = 0; e < kBucketEnt; ++e) {
     B.ci[e] = -1;
-    B.xv[e] = T(0);
+    B.xv[e] = 0.0;
     if (!lng && e < len) {
       B.ci[e] = indices[B.p0 + e];
-      const T v = vals[B.p0 + e];
+      const double v = (double)vals[B.p0 + e];
       B.xv[e] = B.ng ? -v : v;
     }
   }
@@ -197,7 +197,7 @@ __device__ __forceinline__ void load_batch(RowBatch<T> &B, uint32_t base, uint32
 template <typename T>
 __device__ __forceinline__ void apply_batch(const RowBatch<T> &B, int64_t c0,
                                             const T *__restrict__ vals,
-                                            const int32_t *__restrict__ indices, T *myacc) {
+                                            const int32_t *__restrict__ indices, double *myacc) {
   const int lane = (int)(threadIdx.x & 63u);
   const int64_t len = B.p1 - B.p0;
   const bool lng = (B.longmask >> lane) & 1u;
@@ -220,7 +220,7 @@ __device__ __forceinline__ void apply_batch(const RowBatch<T> &B, int64_t c0,
       for (int64_t p = q0 + lane; p < q1; p += 64) {
         const int64_t cl = (int64_t)indices[p] - c0;
         if (cl >= 0 && cl < 64) {
-          const T v = vals[p];
+          const double v = (double)vals[p];
           atomicAdd(&myacc[lbi * 64 + cl], ngi ? -v : v);
         }
       }
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(512) void k_scatter_csr_fp8(
     const int32_t *__restrict__ indices, int64_t npad, int64_t r,
     const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
     unsigned char *__restrict__ q, unsigned char *__restrict__ sc) {
-  __shared__ __align__(16) T acc[kBK * 64];
+  __shared__ __align__(16) double acc[kBK * 64];  // FP64 bucket sums
   __shared__ double amax_s[2][8][64];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t kc = blockIdx.x;
@@ -247,13 +247,13 @@ __global__ __launch_bounds__(512) void k_scatter_csr_fp8(
   const uint32_t j1 = (uint32_t)__shfl((int)bpl, 16, 64);
   RowBatch<T> first;
   load_batch(first, j0, j1, bpl, vals, indptr, indices, perm);
-  T *myacc = acc + b0 * 64;
+  double *myacc = acc + b0 * 64;
   const int nsl = (int)(npad / 64);
   const int s0 = (int)blockIdx.y * kSlices;
   const int s1 = (s0 + kSlices) < nsl ? (s0 + kSlices) : nsl;
   for (int sl = s0; sl < s1; ++sl) {
     const int64_t c0 = (int64_t)sl * 64;
-    for (int i = lane; i < 16 * 64; i += 64) myacc[i] = T(0);
+    for (int i = lane; i < 16 * 64; i += 64) myacc[i] = 0.0;
     if (j0 < j1) apply_batch(first, c0, vals, indices, myacc);
     for (uint32_t base = j0 + 64; base < j1; base += 64) {
       RowBatch<T> more;
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(512) void k_scatter_csr_fp8(
     __builtin_amdgcn_wave_barrier();
     double am = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) am = fmax(am, fabs((double)myacc[i * 64 + lane]));
+    for (int i = 0; i < 16; ++i) am = fmax(am, fabs(myacc[i * 64 + lane]));
     double(*ams)[64] = amax_s[sl & 1];
     ams[wave][lane] = am;
     __syncthreads();
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(512) void k_scatter_csr_fp8(
     for (int p = 0; p < 4; ++p) {
       float f[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) f[u] = f32_odd((double)myacc[(4 * p + u) * 64 + lane] * inv);
+      for (int u = 0; u < 4; ++u) f[u] = f32_odd(myacc[(4 * p + u) * 64 + lane] * inv);
       w4[p] = e4m3x2(f[0], f[1]) | (e4m3x2(f[2], f[3]) << 16);
     }
     reinterpret_cast<uint4 *>(q)[(kc * 8 + wave) * npad + n] =

@@ -134,10 +134,10 @@ __device__ void bucket_entries_wave(const T *__restrict__ vals, const int64_t *_
                                     const int32_t *__restrict__ indices,
                                     const uint32_t *__restrict__ perm, uint32_t j0, uint32_t j1,
                                     uint32_t e0, uint32_t cap, int64_t b, int64_t d,
-                                    int64_t dpad, T *acc, uint32_t *__restrict__ eb,
+                                    int64_t dpad, double *acc, uint32_t *__restrict__ eb,
                                     int32_t *__restrict__ ec, double *__restrict__ ev) {
   const int lane = (int)(threadIdx.x & 63u);
-  for (int64_t c = lane; c < dpad; c += 64) acc[c] = T(0);
+  for (int64_t c = lane; c < dpad; c += 64) acc[c] = 0.0;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   bucket_rows_add(vals, indptr, indices, perm, j0, j1, acc);
@@ -146,7 +146,7 @@ __device__ void bucket_entries_wave(const T *__restrict__ vals, const int64_t *_
   uint32_t cnt = 0;
   for (int64_t c0 = 0; c0 < d; c0 += 64) {
     const int64_t c = c0 + lane;
-    const double v = c < d ? (double)acc[c] : 0.0;
+    const double v = c < d ? acc[c] : 0.0;
     const bool nz = v != 0.0;
     const uint64_t mask = __ballot(nz);
     if (nz) {
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(256) void k_sa_entries(
     int32_t *__restrict__ ec, double *__restrict__ ev) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = (int)(threadIdx.x & 63u);
-  T *acc = reinterpret_cast<T *>(smem_raw) + (int64_t)(threadIdx.x >> 6) * dpad;
+  double *acc = reinterpret_cast<double *>(smem_raw) + (int64_t)(threadIdx.x >> 6) * dpad;
   const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
   uint32_t j0 = 0, j1 = 0, e0 = 0, cap = 0;
   if (b < r) {
@@ -197,11 +197,11 @@ __global__ __launch_bounds__(256) void k_sa_entries(
   const bool lng = cap > (uint32_t)kLaneEnt;
   if (cap > 0 && !lng) {
     int col[kLaneEnt];
-    T val[kLaneEnt];
+    double val[kLaneEnt];  // FP64 sums, FP32 entries widened exactly
 #pragma unroll
     for (int k = 0; k < kLaneEnt; ++k) {
       col[k] = INT32_MAX;
-      val[k] = T(0);
+      val[k] = 0.0;
     }
     int n = 0;
     for (uint32_t j = j0; j < j1; ++j) {
@@ -211,8 +211,8 @@ __global__ __launch_bounds__(256) void k_sa_entries(
       const int64_t p1 = indptr[row + 1];
       for (int64_t p = indptr[row]; p < p1; ++p) {
         const int32_t c = indices[p];
-        const T v0 = vals[p];
-        const T v = ng ? -v0 : v0;
+        const double v0 = (double)vals[p];
+        const double v = ng ? -v0 : v0;
         bool hit = false;
 #pragma unroll
         for (int k = 0; k < kLaneEnt; ++k)
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_sa_entries(
           const int tc = col[k];
           col[k] = col[k + 1];
           col[k + 1] = tc;
-          const T tv = val[k];
+          const double tv = val[k];
           val[k] = val[k + 1];
           val[k + 1] = tv;
         }
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(256) void k_sparse_reduce(const double *__restrict_
 bool gauss_sparse_fits(const psk_mat &A) {
   if (A.format != PSK_CSR) return false;
   // the dense bucket rows of the entry kernel: 4 x d accumulators in 64 KiB of LDS
-  if ((size_t)4 * ((A.d + 3) & ~(int64_t)3) * elem_size(A.dtype) > 65536) return false;
+  if ((size_t)4 * ((A.d + 3) & ~(int64_t)3) * sizeof(double) > 65536) return false;
   if (A.d > 1023) return false;
   return A.nnz < ((int64_t)1 << 31) && A.n < ((int64_t)1 << 31);
 }
@@ -749,7 +749,7 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
     k_row_nnz<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(A.indptr, perm, n, eoff);
     scan_run(eoff, n + 1, sums, st);
     const int64_t dpad = (d + 3) & ~(int64_t)3;
-    const size_t lds = (size_t)4 * dpad * elem_size(A.dtype);
+    const size_t lds = (size_t)4 * dpad * sizeof(double);
     const unsigned nb = (unsigned)ceil_div(r, 256);
     const bool limbs = prec == PSK_PREC_BF16;
 #define PSK_SAE(TT, LB)                                                                   \

@@ -37,30 +37,13 @@ __global__ __launch_bounds__(256) void k_jl_normals(int64_t d, int64_t t, uint64
   }
 }
 
-__global__ __launch_bounds__(256) void k_widen_f32(const float *__restrict__ src, int64_t count,
-                                                   double *__restrict__ dst) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
-    dst[i] = (double)src[i];
-}
-
 }  // namespace
 
 int sketch_f64(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec, double *C,
                Arena &ws, hipStream_t st) {
-  if (m > 0 || A.dtype == PSK_F64) return do_sketch_gcs(A, m, r, seed, prec, C, ws, st);
-  // S A in FP32 (the dtype of A), widened for the FP64 factorizations
-  const size_t mk = ws.mark();
-  float *sa = ws.take<float>((size_t)r * A.d);
-  int rc = do_sketch_cs(A, r, seed, sa, ws, st);
-  if (rc) return rc;
-  if (!ws.dry()) {
-    const int64_t cnt = r * A.d;
-    const unsigned blocks = (unsigned)(ceil_div(cnt, 256) < 8192 ? ceil_div(cnt, 256) : 8192);
-    k_widen_f32<<<blocks, 256, 0, st>>>(sa, cnt, C);
-  }
-  ws.release(mk);
-  return 0;
+  if (m > 0) return do_sketch_gcs(A, m, r, seed, prec, C, ws, st);
+  // S A as its FP64 sums (FP32 A is widened exactly and summed in FP64)
+  return do_sketch_cs(A, r, seed, C, ws, st, true);
 }
 
 int leverage_sketch_impl(const psk_mat &A, int64_t m, int64_t r, int64_t t, uint64_t seed,

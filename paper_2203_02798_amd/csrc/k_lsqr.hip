@@ -905,18 +905,18 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     if (sparse_ok)
       return gauss_gemm_sparse(m, o.r, A, perm, bptr, o.seed, PSK_PREC_F64, C, ws, st);
     if (fused) {
-      SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
-      if ((e = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st))) return e;
+      SA = ws.take<double>((size_t)o.r * d);
+      if ((e = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st, true))) return e;
     }
-    return gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, A.dtype, C, ws, st);
+    return gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, PSK_F64, C, ws, st);
   };
   if (own) {
     // sketch and factor (their scratch is released afterwards); S*A (or the
     // binned rows it is formed from) stays until the precision decision so
     // that an FP64 rebuild can reuse it
-    if (!fused && !sparse) SA = ws.take<unsigned char>((size_t)o.r * d * elem_size(A.dtype));
+    if (!fused && !sparse) SA = ws.take<double>((size_t)o.r * d);
     if ((rc = cs_bin(n, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr))) return rc;
-    if (!fused && !sparse && (rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st)))
+    if (!fused && !sparse && (rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st, true)))
       return rc;
     const size_t mk2 = ws.mark();
     if (sparse)
@@ -926,7 +926,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     else if (fused)
       rc = gauss_gemm_fp8_csr(m, o.r, A, perm, bptr, o.seed, C, ws, st);
     else
-      rc = gauss_gemm(m, o.r, d, o.seed, o.prec, SA, A.dtype, C, ws, st);
+      rc = gauss_gemm(m, o.r, d, o.seed, o.prec, SA, PSK_F64, C, ws, st);
     if (rc) return rc;
     ws.release(mk2);
     if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;

@@ -237,6 +237,8 @@ template <>
 struct Vec<float, 2> { typedef float2 type; };
 template <>
 struct Vec<float, 4> { typedef float4 type; };
+template <>
+struct Vec<double, 4> { typedef double4 type; };
 
 template <typename T, int VW>
 __device__ __forceinline__ void vload(const T *p, T (&x)[VW]) {
@@ -257,11 +259,26 @@ __device__ __forceinline__ void vstore(T *p, const T (&x)[VW]) {
   *reinterpret_cast<V *>(p) = v;
 }
 
-template <typename T, int VW, int CH, int U>
+// VW adjacent outputs: one vector store where the vector type exists (the
+// row of out is aligned whenever the loads of A are), else element stores
+template <typename TO, int VW>
+__device__ __forceinline__ void store_out(TO *p, const TO (&x)[VW]) {
+  if constexpr (sizeof(TO) * VW <= 16) {
+    vstore<TO, VW>(p, x);
+  } else {
+#pragma unroll
+    for (int q = 0; q < VW; q += 2) {
+      const TO y[2] = {x[q], x[q + 1]};
+      vstore<TO, 2>(p + q, y);
+    }
+  }
+}
+
+template <typename T, typename TO, int VW, int CH, int U>
 __global__ __launch_bounds__(256) void k_scatter_dense(
     const T *__restrict__ A, int64_t ld, int64_t d, int64_t r,
     const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
-    int splits, T *__restrict__ out) {
+    int splits, TO *__restrict__ out) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (wave >= r * splits) return;
   const int64_t b = wave / splits;
@@ -270,15 +287,15 @@ __global__ __launch_bounds__(256) void k_scatter_dense(
   const uint32_t len = bptr[b + 1] - lo;
   const uint32_t j0 = lo + (uint32_t)(((uint64_t)len * s) / splits);
   const uint32_t j1 = lo + (uint32_t)(((uint64_t)len * (s + 1)) / splits);
-  T *orow = out + ((int64_t)s * r + b) * d;
+  TO *orow = out + ((int64_t)s * r + b) * d;
   const int lane = threadIdx.x & 63;
   constexpr int64_t kSpan = 64 * VW * CH;
   for (int64_t c0 = 0; c0 < d; c0 += kSpan) {
-    T acc[CH][VW];
+    double acc[CH][VW];
 #pragma unroll
     for (int c = 0; c < CH; ++c)
 #pragma unroll
-      for (int q = 0; q < VW; ++q) acc[c][q] = T(0);
+      for (int q = 0; q < VW; ++q) acc[c][q] = 0.0;
     uint32_t j = j0;
     for (; j + U <= j1; j += U) {
       T x[U][CH][VW];
@@ -304,8 +321,10 @@ __global__ __launch_bounds__(256) void k_scatter_dense(
 #pragma unroll
         for (int c = 0; c < CH; ++c)
 #pragma unroll
-          for (int q = 0; q < VW; ++q)
-            acc[c][q] += neg[u] ? -x[u][c][q] : x[u][c][q];
+          for (int q = 0; q < VW; ++q) {
+            const double xv = (double)x[u][c][q];
+            acc[c][q] += neg[u] ? -xv : xv;
+          }
     }
     for (; j < j1; ++j) {
       const uint32_t pv = perm[j];
@@ -318,31 +337,36 @@ __global__ __launch_bounds__(256) void k_scatter_dense(
           T xv[VW];
           vload<T, VW>(A + row * ld + col, xv);
 #pragma unroll
-          for (int q = 0; q < VW; ++q) acc[c][q] += ng ? -xv[q] : xv[q];
+          for (int q = 0; q < VW; ++q) acc[c][q] += ng ? -(double)xv[q] : (double)xv[q];
         }
       }
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int64_t col = c0 + (int64_t)(c * 64 + lane) * VW;
-      if (col < d) vstore<T, VW>(orow + col, acc[c]);
+      if (col < d) {
+        TO ov[VW];
+#pragma unroll
+        for (int q = 0; q < VW; ++q) ov[q] = (TO)acc[c][q];
+        store_out<TO, VW>(orow + col, ov);
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
 // S*A, CSR A: one wavefront per (bucket, split) with a private LDS row of d
-// accumulators; rows of the bucket are applied one after another
+// FP64 accumulators; rows of the bucket are applied one after another
 // (bucket_rows_add).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename TO>
 __global__ __launch_bounds__(256) void k_scatter_csr(
     const T *__restrict__ vals, const int64_t *__restrict__ indptr,
     const int32_t *__restrict__ indices, int64_t d, int64_t dpad, int64_t r,
     const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
-    int splits, T *__restrict__ out) {
+    int splits, TO *__restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *acc = reinterpret_cast<T *>(smem_raw) + (threadIdx.x >> 6) * dpad;
+  double *acc = reinterpret_cast<double *>(smem_raw) + (threadIdx.x >> 6) * dpad;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (wave >= r * splits) return;
   const int lane = threadIdx.x & 63;
@@ -352,26 +376,27 @@ __global__ __launch_bounds__(256) void k_scatter_csr(
   const uint32_t len = bptr[b + 1] - lo;
   const uint32_t j0 = lo + (uint32_t)(((uint64_t)len * s) / splits);
   const uint32_t j1 = lo + (uint32_t)(((uint64_t)len * (s + 1)) / splits);
-  for (int64_t c = lane; c < d; c += 64) acc[c] = T(0);
+  for (int64_t c = lane; c < d; c += 64) acc[c] = 0.0;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   bucket_rows_add(vals, indptr, indices, perm, j0, j1, acc);
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  T *orow = out + ((int64_t)s * r + b) * d;
-  for (int64_t c = lane; c < d; c += 64) orow[c] = acc[c];
+  TO *orow = out + ((int64_t)s * r + b) * d;
+  for (int64_t c = lane; c < d; c += 64) orow[c] = (TO)acc[c];
 }
 
-// SA[b, c] = sum over splits of partial[s, b, c], splits in increasing order
-template <typename T>
-__global__ __launch_bounds__(256) void k_combine_splits(const T *__restrict__ part,
+// SA[b, c] = sum over splits of partial[s, b, c] (FP64), splits in
+// increasing order, rounded once to the output type
+template <typename TO>
+__global__ __launch_bounds__(256) void k_combine_splits(const double *__restrict__ part,
                                                         int64_t rd, int splits,
-                                                        T *__restrict__ SA) {
+                                                        TO *__restrict__ SA) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rd) return;
-  T acc = part[e];
+  double acc = part[e];
   for (int s = 1; s < splits; ++s) acc += part[(int64_t)s * rd + e];
-  SA[e] = acc;
+  SA[e] = (TO)acc;
 }
 
 int choose_splits(int64_t n, int64_t r) {
@@ -386,22 +411,43 @@ int choose_splits(int64_t n, int64_t r) {
   return s < 1 ? 1 : (int)s;
 }
 
-template <typename T, int VW>
+template <typename T, typename TO, int VW>
 void launch_dense(const psk_mat &A, int64_t r, const uint32_t *perm,
-                  const uint32_t *bptr, int splits, T *out, hipStream_t st) {
+                  const uint32_t *bptr, int splits, TO *out, hipStream_t st) {
   const int64_t waves = r * splits;
   const unsigned blocks = (unsigned)ceil_div(waves, 4);
   const int64_t span1 = 64 * VW;  // columns per lane group
   if (A.d <= span1)
-    k_scatter_dense<T, VW, 1, 8><<<blocks, 256, 0, st>>>(
+    k_scatter_dense<T, TO, VW, 1, 8><<<blocks, 256, 0, st>>>(
         (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
   else if (A.d <= 2 * span1)
-    k_scatter_dense<T, VW, 2, 4><<<blocks, 256, 0, st>>>(
+    k_scatter_dense<T, TO, VW, 2, 4><<<blocks, 256, 0, st>>>(
         (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
   else
-    k_scatter_dense<T, VW, 4, 4><<<blocks, 256, 0, st>>>(
+    k_scatter_dense<T, TO, VW, 4, 4><<<blocks, 256, 0, st>>>(
         (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
 }
+
+// VW adjacent columns per lane where the rows of A and of the output allow
+// aligned vector accesses
+template <typename T, typename TO>
+void launch_dense_vw(const psk_mat &A, int64_t r, const uint32_t *perm,
+                     const uint32_t *bptr, int splits, TO *out, hipStream_t st) {
+  const uintptr_t addr = (uintptr_t)A.values, oaddr = (uintptr_t)out;
+  constexpr int es = (int)sizeof(T), os = (int)sizeof(TO);
+  const bool v4 = es == 4 && (A.d % 4 == 0) && (A.ld % 4 == 0) && (addr % 16 == 0) &&
+                  oaddr % (os == 4 ? 16 : 16) == 0;
+  const bool v2 = (A.d % 2 == 0) && (A.ld % 2 == 0) && (addr % (2 * es) == 0) &&
+                  oaddr % (2 * os) == 0;
+  if constexpr (sizeof(T) == 4) {
+    if (v4) return launch_dense<T, TO, 4>(A, r, perm, bptr, splits, out, st);
+  }
+  if (v2) return launch_dense<T, TO, 2>(A, r, perm, bptr, splits, out, st);
+  launch_dense<T, TO, 1>(A, r, perm, bptr, splits, out, st);
+}
+
+// LDS of the CSR scatter: FP64 accumulators of wpb wavefronts
+constexpr size_t kCsrLdsMax = 163840;
 
 }  // namespace
 
@@ -479,59 +525,65 @@ int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
 }
 
 int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
-             const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st) {
+             const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st, bool out_f64) {
   const int splits = choose_splits(A.n, r);
-  const size_t es = elem_size(A.dtype);
+  const bool o64 = out_f64 || A.dtype == PSK_F64;
   void *part = nullptr;
-  if (splits > 1) part = ws.take<unsigned char>((size_t)splits * r * A.d * es);
+  if (splits > 1) part = ws.take<double>((size_t)splits * r * A.d);
+  const int64_t dpad = (A.d + 3) & ~(int64_t)3;
+  if (A.format == PSK_CSR && (size_t)dpad * 8 > kCsrLdsMax)
+    return fail(PSK_EUNSUPPORTED, "CSR S*A supports d <= 20480");
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for S*A");
-  void *out = splits > 1 ? part : SA;
   KTimer timer("cs_scatter", st);
   if (A.format == PSK_DENSE) {
-    const uintptr_t addr = (uintptr_t)A.values;
-    if (A.dtype == PSK_F64) {
-      const bool v2 = (A.d % 2 == 0) && (A.ld % 2 == 0) && (addr % 16 == 0);
-      if (v2)
-        launch_dense<double, 2>(A, r, perm, bptr, splits, (double *)out, st);
+    if (splits > 1) {
+      if (A.dtype == PSK_F64)
+        launch_dense_vw<double, double>(A, r, perm, bptr, splits, (double *)part, st);
       else
-        launch_dense<double, 1>(A, r, perm, bptr, splits, (double *)out, st);
+        launch_dense_vw<float, double>(A, r, perm, bptr, splits, (double *)part, st);
+    } else if (A.dtype == PSK_F64) {
+      launch_dense_vw<double, double>(A, r, perm, bptr, 1, (double *)SA, st);
+    } else if (o64) {
+      launch_dense_vw<float, double>(A, r, perm, bptr, 1, (double *)SA, st);
     } else {
-      const bool v4 = (A.d % 4 == 0) && (A.ld % 4 == 0) && (addr % 16 == 0);
-      const bool v2 = (A.d % 2 == 0) && (A.ld % 2 == 0) && (addr % 8 == 0);
-      if (v4)
-        launch_dense<float, 4>(A, r, perm, bptr, splits, (float *)out, st);
-      else if (v2)
-        launch_dense<float, 2>(A, r, perm, bptr, splits, (float *)out, st);
-      else
-        launch_dense<float, 1>(A, r, perm, bptr, splits, (float *)out, st);
+      launch_dense_vw<float, float>(A, r, perm, bptr, 1, (float *)SA, st);
     }
   } else {
-    const int64_t dpad = (A.d + 3) & ~(int64_t)3;
     int wpb = 4;
-    while (wpb > 1 && (size_t)wpb * dpad * es > 65536) --wpb;
-    if ((size_t)dpad * es > 65536)
-      return fail(PSK_EUNSUPPORTED, "CSR S*A supports d*elem <= 64 KiB");
-    const size_t lds = (size_t)wpb * dpad * es;
+    while (wpb > 1 && (size_t)wpb * dpad * 8 > 65536) --wpb;
+    const size_t lds = (size_t)wpb * dpad * 8;
     const int64_t waves = (int64_t)r * splits;
     const unsigned blocks = (unsigned)ceil_div(waves, wpb);
-    if (A.dtype == PSK_F64)
-      k_scatter_csr<double><<<blocks, 64 * wpb, lds, st>>>(
-          (const double *)A.values, A.indptr, A.indices, A.d, dpad, r, perm, bptr,
-          splits, (double *)out);
-    else
-      k_scatter_csr<float><<<blocks, 64 * wpb, lds, st>>>(
-          (const float *)A.values, A.indptr, A.indices, A.d, dpad, r, perm, bptr,
-          splits, (float *)out);
+#define PSK_SCSR(T, TO, OUT)                                                               \
+  do {                                                                                     \
+    if (lds > 65536)                                                                       \
+      PSK_HIP_TRY(hipFuncSetAttribute((const void *)k_scatter_csr<T, TO>,                  \
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
+    k_scatter_csr<T, TO><<<blocks, 64 * wpb, lds, st>>>((const T *)A.values, A.indptr,     \
+                                                        A.indices, A.d, dpad, r, perm, bptr, \
+                                                        splits, (TO *)(OUT));              \
+  } while (0)
+    if (splits > 1) {
+      if (A.dtype == PSK_F64) PSK_SCSR(double, double, part);
+      else PSK_SCSR(float, double, part);
+    } else if (A.dtype == PSK_F64) {
+      PSK_SCSR(double, double, SA);
+    } else if (o64) {
+      PSK_SCSR(float, double, SA);
+    } else {
+      PSK_SCSR(float, float, SA);
+    }
+#undef PSK_SCSR
   }
   if (splits > 1) {
     const int64_t rd = (int64_t)r * A.d;
-    if (A.dtype == PSK_F64)
+    if (o64)
       k_combine_splits<double><<<(unsigned)ceil_div(rd, 256), 256, 0, st>>>(
           (const double *)part, rd, splits, (double *)SA);
     else
       k_combine_splits<float><<<(unsigned)ceil_div(rd, 256), 256, 0, st>>>(
-          (const float *)part, rd, splits, (float *)SA);
+          (const double *)part, rd, splits, (float *)SA);
   }
   PSK_HIP_TRY(hipGetLastError());
   return 0;
