@@ -320,10 +320,27 @@ def quantize_e4m3_blocks(x, block=128, axis=0):
     return np.moveaxis(out, 0, axis), exps
 
 
+# The unscaled normals of this generator are bounded: u >= 2^-33 gives
+# |z| <= sqrt(-2 ln 2^-33) = sqrt(66 ln 2) < 6.77, so the power-of-two scale
+# 2^G_FP8_EXP with 448 * 2^G_FP8_EXP >= 6.77 covers every block of G; with
+# it the e4m3 rounding of G never saturates, and for every value in the
+# normal e4m3 range (|z| >= 2^-12) it equals the rounding under the block's
+# own amax scale (a power-of-two scale does not move the significand).
+G_FP8_EXP = -6
+
+
+def quantize_gaussian_e4m3(z):
+    """The FP8 operand of G: 2^G_FP8_EXP * e4m3(z / 2^G_FP8_EXP), one fixed
+    E8M0 scale for every 128-bucket block of every row."""
+    s = np.ldexp(1.0, G_FP8_EXP)
+    return to_e4m3(np.asarray(z, dtype=np.float64) / s) * s
+
+
 def gauss_product_fp8_reference(b, m, seed, block=128, batch=4096):
     """G*B with B (r x d: S*A or A) quantised per column in blocks of `block`
-    rows, the unscaled normals quantised per row of G in the same blocks of
-    columns, their exact (FP64) product scaled by 1/sqrt(m)."""
+    rows (scale from each block's amax), the unscaled normals quantised with
+    G's fixed scale (quantize_gaussian_e4m3), their exact (FP64) product
+    scaled by 1/sqrt(m)."""
     assert batch % block == 0
     b = np.asarray(b, dtype=np.float64)
     r = b.shape[0]
@@ -331,7 +348,7 @@ def gauss_product_fp8_reference(b, m, seed, block=128, batch=4096):
     c = np.zeros((m, b.shape[1]))
     for b0 in range(0, r, batch):
         b1 = min(r, b0 + batch)
-        zq, _ = quantize_e4m3_blocks(gaussian_normals(m, b0, b1, seed), block, axis=1)
+        zq = quantize_gaussian_e4m3(gaussian_normals(m, b0, b1, seed))
         c += zq @ bq[b0:b1]
     return c / np.sqrt(m)
 
@@ -339,8 +356,7 @@ def gauss_product_fp8_reference(b, m, seed, block=128, batch=4096):
 def sketch_gcs_fp8_reference(a, m, r, seed, block=128, batch=4096):
     """Quantisation-aware reference of the FP8 Gaussian GEMM: S*A quantised
     per column in blocks of `block` buckets, the unscaled normals quantised
-    per row in the same bucket blocks, their exact (FP64) product scaled by
-    1/sqrt(m)."""
+    with G's fixed scale, their exact (FP64) product scaled by 1/sqrt(m)."""
     return gauss_product_fp8_reference(sketch_cs(a, r, seed), m, seed, block, batch)
 
 

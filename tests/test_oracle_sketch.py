@@ -271,10 +271,11 @@ def test_fp8_reference_within_rounding_bound():
     c = osk.sketch_gcs(a, m, r, seed)
     z = osk.gaussian_normals(m, 0, r, seed)
     sa = osk.sketch_cs(a, r, seed)
-    zq, ez = osk.quantize_e4m3_blocks(z, 128, axis=1)
+    zq = osk.quantize_gaussian_e4m3(z)
     saq, es = osk.quantize_e4m3_blocks(sa, 128, axis=0)
-    # elementwise rounding bounds of the two operands (see above)
-    sz = np.repeat(np.ldexp(1.0, ez).T, 128, axis=1)[:, :r]
+    # elementwise rounding bounds of the two operands (see above); G's scale
+    # is the fixed 2^G_FP8_EXP
+    sz = np.full(z.shape, np.ldexp(1.0, osk.G_FP8_EXP))
     ss = np.repeat(np.ldexp(1.0, es), 128, axis=0)[:r]
     dz = np.maximum(2.0 ** -4 * np.abs(z), 2.0 ** -10 * sz)
     ds = np.maximum(2.0 ** -4 * np.abs(sa), 2.0 ** -10 * ss)
@@ -342,9 +343,32 @@ def test_sketch_g_quantised_references_within_bounds():
     cb = osk.sketch_g_bf16_reference(a, m, seed)
     assert np.all(np.abs(cb - c) <= mag * (2.0 ** -8 + 2.0 ** -16 + 2.0 ** -24 + 1e-13))
     c8 = osk.sketch_g_fp8_reference(a, m, seed)
-    zq, ez = osk.quantize_e4m3_blocks(z, 128, axis=1)
+    zq = osk.quantize_gaussian_e4m3(z)
     aq, ea = osk.quantize_e4m3_blocks(ad, 128, axis=0)
     np.testing.assert_allclose(c8, zq @ aq / np.sqrt(m), rtol=1e-12, atol=1e-14)
     # 900 = 7 * 128 + 4: the last block holds rows 896 .. 899, and its scale
     # is taken over those rows only
     np.testing.assert_array_equal(ea[-1], osk.e8m0_exponent(np.abs(ad[896:]).max(axis=0)))
+
+
+def test_gaussian_fp8_scale_covers_every_normal():
+    """G's fixed FP8 scale: the largest radius the generator can produce
+    (smallest uniform, u = 2^-33) maps below 448, so no value of G
+    saturates; on the normal e4m3 range the fixed scale rounds exactly as the
+    block-amax scale does (power-of-two scaling keeps the significand), and
+    below it the rounding error stays under half a subnormal quantum."""
+    rmax = np.sqrt(-2.0 * np.log(2.0 ** -33))
+    assert rmax * 2.0 ** -osk.G_FP8_EXP < 448.0
+    assert 448.0 * 2.0 ** (osk.G_FP8_EXP - 1) < rmax  # and 2^-7 would not cover it
+    z = osk.gaussian_normals(64, 0, 4096, 3)
+    zq = osk.quantize_gaussian_e4m3(z)
+    zb, _ = osk.quantize_e4m3_blocks(z, 128, axis=1)
+    big = np.abs(z) >= 2.0 ** (osk.G_FP8_EXP - 6)
+    np.testing.assert_array_equal(zq[big], zb[big])
+    quantum = 2.0 ** (osk.G_FP8_EXP - 9)  # e4m3 subnormal step at this scale
+    assert np.all(np.abs(zq - z)[~big] <= quantum / 2)
+    # the largest normal the generator gives (u0 = 2^-33, u1 -> 0) quantises
+    # to a finite e4m3 value within the relative rounding bound
+    zr = osk.quantize_gaussian_e4m3(np.array([rmax, -rmax]))
+    np.testing.assert_array_equal(zr, osk.to_e4m3(np.array([rmax, -rmax]) * 64.0) / 64.0)
+    assert np.all(np.abs(np.abs(zr) - rmax) <= rmax * 2.0 ** -4)
