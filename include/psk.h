@@ -112,16 +112,20 @@ enum {
   PSK_PREC_BF16 = 1,  /* G rounded to bfloat16, S*A split into two bfloat16   *
                        * limbs (hi + lo), BF16 MFMA with FP32 accumulation,   *
                        * FP64 reduction of the K-split partial products.      *
-                       * The normals are evaluated in FP32 (a few ulps from   *
-                       * the FP64 ones) before the RNE rounding; entries of   *
-                       * S*A must lie in the bfloat16 range.                  */
+                       * Each value of G is the RNE rounding of the FP64      *
+                       * normal (drawn in FP32, redrawn in FP64 where the     *
+                       * FP32 value lies within 8 ulps of a rounding          *
+                       * midpoint); entries of S*A must lie in the bfloat16   *
+                       * range.                                               */
   PSK_PREC_FP8 = 2    /* G and S*A quantised to OCP FP8 e4m3 (RNE) with one   *
                        * power-of-two (E8M0) scale per block of 128 buckets:  *
-                       * per row of G, per column of S*A, exponent            *
-                       * ceil(log2(amax/448)); scaled FP8 MFMA with FP32      *
-                       * accumulation, FP64 reduction of the K-split partial  *
-                       * products.  Normals evaluated in FP32 as for BF16.    *
-                       * Entries of S*A must stay below 448 * 2^127.          */
+                       * for S*A per column, exponent ceil(log2(amax/448));   *
+                       * for G the fixed 2^-6 (every normal of the generator  *
+                       * has |z| < 6.77 < 448 * 2^-6), each value the         *
+                       * rounding of the FP64 normal as for BF16.  Scaled     *
+                       * FP8 MFMA with FP32 accumulation, FP64 reduction of   *
+                       * the K-split partial products.  Entries of S*A must   *
+                       * stay below 448 * 2^127.                              */
 };
 
 /* ---- operations for psk_workspace_size --------------------------------- */
@@ -138,7 +142,8 @@ enum {
   PSK_OP_LSQ_SKETCH = 9,
   PSK_OP_LEVERAGE_SKETCH = 10,
   PSK_OP_CSS = 11,
-  PSK_OP_LEVERAGE_CSS = 12
+  PSK_OP_LEVERAGE_CSS = 12,
+  PSK_OP_DELTA = 13
 };
 
 /* Library version string (static storage). */
@@ -149,13 +154,14 @@ const char *psk_version(void);
 const char *psk_last_error(void);
 
 /* Minimum workspace, in bytes, for one call of `op`.
- *   A    : the matrix the call will get (for PSK_OP_QR only A->n = m rows and
- *          A->d = d columns of the sketch are read);
+ *   A    : the matrix the call will get (for PSK_OP_QR and PSK_OP_DELTA only
+ *          A->n = m rows and A->d = d columns of the sketch are read);
  *   m, r : Gaussian rows and CountSketch buckets (SKETCH_*, LSQ,
  *          LSQ_SKETCH, LEVERAGE_SKETCH, CSS, LEVERAGE_CSS; SKETCH_G reads m
  *          only);
  *   k    : columns of B (ROWNORMS), columns t of Pi (LEVERAGE_SKETCH),
- *          columns selected (CSS, LEVERAGE_CSS);
+ *          columns selected (CSS, LEVERAGE_CSS); for LSQ nonzero when the
+ *          call will set opts->want_delta;
  *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ, LSQ_SKETCH, LEVERAGE_SKETCH,
  *          CSS, LEVERAGE_CSS).
  * For PSK_OP_LSQ, m == 0 sizes a call that passes its own opts->Rinv.
@@ -240,6 +246,27 @@ int rownorms_sq(double alpha, const psk_mat *A, const double *B, int64_t k,
 int sketch_qr(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
               void *ws, size_t ws_bytes, void *stream);
 
+/* delta = ||(Chat - C) R^{-1}||_2, the perturbation of a sketch Chat (a
+ * reduced-precision one, say) against a sketch C of the same A, with R the
+ * triangular factor of C = Q R (sketch_qr).  With Chat R^{-1} = Q + F the
+ * singular values of Rhat R^{-1} lie in [1 - delta, 1 + delta], so for
+ * delta < 1 the leverage scores of Algorithm ls_approximate_drineas from Chat
+ * and from C differ by a factor in [(1 + delta)^-2, (1 - delta)^-2], and the
+ * preconditioner of Algorithm least_squares_precondition from Chat keeps
+ * cond(A Rhat^{-1}) within (1 + delta) / (1 - delta) of the one from C.
+ *   Chat, C : m x d row-major FP64 (device), m >= d, C of full column rank.
+ *   delta   : one FP64 (device, written).
+ * ||F||_2 is the square root of the largest eigenvalue of F^T F, found by
+ * twelve normalised squarings of F^T F and the Rayleigh quotient of the
+ * dominant column: never above ||F||_2, and within about (s2/s1)^8192 of it
+ * relatively (s1 >= s2 the two largest singular values of F).  The stream
+ * is synchronised once (inside sketch_qr).
+ * Workspace: psk_workspace_size(PSK_OP_DELTA, A with n = m and d).
+ * Errors: PSK_EINVAL (m < d, NULL pointers), PSK_EUNSUPPORTED (d > 4096),
+ * PSK_ENOMEM. */
+int sketch_delta(const double *Chat, const double *C, int64_t m, int64_t d, double *delta,
+                 void *ws, size_t ws_bytes, void *stream);
+
 /* Options and report of lsq_solve. */
 typedef struct psk_lsq_opts {
   const double *Rinv; /* optional d x d row-major FP64 R^{-1} of a   *
@@ -262,6 +289,12 @@ typedef struct psk_lsq_opts {
                        * S*A before LSQR starts; 0 selects 1e4 for   *
                        * BF16 and 10 for FP8, a negative value never *
                        * escalates                                   */
+  int32_t want_delta; /* prec BF16 / FP8, own sketch: also form the  *
+                       * FP64 sketch of the same S*A and report the  *
+                       * reduced sketch's delta (as sketch_delta) in *
+                       * info->delta_est; costs an FP64 Gaussian     *
+                       * product and two factorizations more         */
+  int32_t reserved;
 } psk_lsq_opts;
 
 typedef struct psk_lsq_info {
@@ -272,6 +305,11 @@ typedef struct psk_lsq_info {
   int32_t prec_used;  /* PSK_PREC_* of the sketch the preconditioner *
                        * came from (-1 with a caller's Rinv)          */
   int32_t reserved;
+  double delta_est;   /* delta = ||(Chat - C) R^{-1}||_2 of the sketch *
+                       * LSQR was preconditioned with against the FP64 *
+                       * sketch (sketch_delta): 0 when that is the     *
+                       * FP64 sketch (prec F64, or escalated), the     *
+                       * measured value with want_delta, else NaN      */
 } psk_lsq_info;
 
 /* x = argmin ||A x - b|| by sketch-and-precondition (Algorithm
@@ -468,6 +506,8 @@ typedef struct psk_result {
   double t_end;
   int32_t prec_used;   /* LSQ: as psk_lsq_info; LEVERAGE: opts.prec         */
   int32_t reserved;
+  double delta_est;    /* LSQ: as psk_lsq_info (opts.want_delta); LEVERAGE: *
+                        * NaN                                                */
 } psk_result;
 
 typedef struct psk_server_stats_t {

@@ -26,12 +26,13 @@ PSK_PROBE_BLOCKS = 4096
 PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 (PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
  PSK_OP_LSQ, PSK_OP_SKETCH_G, PSK_OP_LEVERAGE_GRAM, PSK_OP_LSQ_GRAM,
- PSK_OP_LSQ_SKETCH, PSK_OP_LEVERAGE_SKETCH, PSK_OP_CSS, PSK_OP_LEVERAGE_CSS) = range(13)
+ PSK_OP_LSQ_SKETCH, PSK_OP_LEVERAGE_SKETCH, PSK_OP_CSS, PSK_OP_LEVERAGE_CSS,
+ PSK_OP_DELTA) = range(14)
 
 EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq", "sketch_qr",
             "lsq_solve", "leverage_sketch", "css_select", "leverage_css", "leverage_gram",
-            "lsq_gram", "lsq_sketch_solve",
+            "lsq_gram", "lsq_sketch_solve", "sketch_delta",
             "psk_probe_copy", "psk_probe_mfma_f64", "psk_probe_mfma_lowp",
             "psk_probe_valu_f32",
             "psk_timing_enable", "psk_timing_only", "psk_timing_reset",
@@ -67,6 +68,8 @@ class PskLsqOpts(ctypes.Structure):
         ("atol", ctypes.c_double),
         ("btol", ctypes.c_double),
         ("escalate_cond", ctypes.c_double),
+        ("want_delta", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -78,6 +81,7 @@ class PskLsqInfo(ctypes.Structure):
         ("ne_resid", ctypes.c_double),
         ("prec_used", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("delta_est", ctypes.c_double),
     ]
 
 
@@ -110,6 +114,7 @@ class PskResult(ctypes.Structure):
         ("t_end", ctypes.c_double),
         ("prec_used", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("delta_est", ctypes.c_double),
     ]
 
 
@@ -165,6 +170,7 @@ _SIGS = {
     "lsq_gram": ([_PM, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "lsq_sketch_solve": ([_PM, _vp, _vp, _i64, _i64, _u64, ctypes.c_int, _vp, ctypes.c_size_t,
                           _vp], ctypes.c_int),
+    "sketch_delta": ([_vp, _vp, _i64, _i64, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "psk_probe_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "psk_probe_mfma_f64": ([_i64, _vp, _vp], ctypes.c_int),
     "psk_probe_mfma_lowp": ([ctypes.c_int, _i64, _vp, _vp], ctypes.c_int),

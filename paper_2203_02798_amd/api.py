@@ -295,9 +295,26 @@ def sketch_qr(C):
 _PREC_NAME = {L.PSK_PREC_F64: "f64", L.PSK_PREC_BF16: "bf16", L.PSK_PREC_FP8: "fp8", -1: None}
 
 
+def sketch_delta(Chat, C):
+    """delta = ||(Chat - C) R^{-1}||_2 (R from the QR of C), both m x d FP64
+    device tensors; returns a one-element FP64 device tensor."""
+    Chat = Chat.contiguous()
+    C = C.contiguous()
+    if Chat.shape != C.shape or C.dtype != torch.float64 or Chat.dtype != torch.float64:
+        raise ValueError("Chat and C must be float64 tensors of one shape")
+    m, d = C.shape
+    dev = C.device
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    nbytes = workspace_size(L.PSK_OP_DELTA, (m, d))
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().sketch_delta(Chat.data_ptr(), C.data_ptr(), m, d, out.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _stream(dev)), "sketch_delta")
+    return out
+
+
 def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,
               check_every=8, atol=1e-14, btol=1e-14, Rinv=None, raise_on_noconv=False,
-              escalate_cond=0.0):
+              escalate_cond=0.0, want_delta=False):
     """x = argmin ||A x - b|| by sketch-and-precondition LSQR.  With ``Rinv``
     (d x d FP64 device tensor, e.g. from sketch_qr) the preconditioner is
     reused and m, r, seed, prec are ignored.  Returns (x float64[d], info)."""
@@ -312,10 +329,10 @@ def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,
     o = L.PskLsqOpts(Rinv=Rinv.data_ptr() if Rinv is not None else None, m=m, r=r,
                      seed=seed, prec=_PREC[prec], max_iter=max_iter, refine=refine,
                      check_every=check_every, atol=atol, btol=btol,
-                     escalate_cond=escalate_cond)
+                     escalate_cond=escalate_cond, want_delta=int(bool(want_delta)))
     info = L.PskLsqInfo()
     nbytes = workspace_size(L.PSK_OP_LSQ, A, m=0 if Rinv is not None else m, r=r,
-                            prec=prec)
+                            k=int(bool(want_delta)), prec=prec)
     ws = _ws(nbytes, dev)
     st = L.lib().lsq_solve(ctypes.byref(pm), b.data_ptr(), x.data_ptr(), ctypes.byref(o),
                            ctypes.byref(info), ws.data_ptr(), ws.numel(), _stream(dev))
@@ -323,7 +340,8 @@ def lsq_solve(A, b, m=0, r=0, seed=0, prec="f64", max_iter=300, refine=1,
         L.check(st, "lsq_solve")
     return x, dict(iters=info.iters, status=L.STATUS_NAMES.get(info.status, info.status),
                    resid=info.resid, ne_resid=info.ne_resid,
-                   prec_used=_PREC_NAME.get(info.prec_used, info.prec_used))
+                   prec_used=_PREC_NAME.get(info.prec_used, info.prec_used),
+                   delta_est=info.delta_est)
 
 
 class Server:
@@ -360,14 +378,16 @@ class Server:
         return t.value
 
     def submit_lsq(self, A, b, m, r, seed=0, prec="f64", max_iter=300, refine=1,
-                   check_every=8, atol=1e-14, btol=1e-14, escalate_cond=0.0):
+                   check_every=8, atol=1e-14, btol=1e-14, escalate_cond=0.0,
+                   want_delta=False):
         """Queue x = argmin ||A x - b||; returns (ticket, x) with x filled on
         completion."""
         pm = _mat(A)
         x = torch.empty(pm.d, dtype=torch.float64, device=self.device)
         o = L.PskLsqOpts(Rinv=None, m=m, r=r, seed=seed, prec=_PREC[prec],
                          max_iter=max_iter, refine=refine, check_every=check_every,
-                         atol=atol, btol=btol, escalate_cond=escalate_cond)
+                         atol=atol, btol=btol, escalate_cond=escalate_cond,
+                         want_delta=int(bool(want_delta)))
         return self._submit(L.PSK_REQ_LSQ, A, b.contiguous(), x, o), x
 
     def submit_leverage(self, A, m, r, seed=0, prec="f64"):
@@ -383,7 +403,8 @@ class Server:
         return dict(status=L.STATUS_NAMES.get(res.status, res.status), iters=res.iters,
                     resid=res.resid, ne_resid=res.ne_resid, t_submit=res.t_submit,
                     t_start=res.t_start, t_end=res.t_end,
-                    prec_used=_PREC_NAME.get(res.prec_used, res.prec_used))
+                    prec_used=_PREC_NAME.get(res.prec_used, res.prec_used),
+                    delta_est=res.delta_est)
 
     def wait(self, ticket):
         res = L.PskResult()

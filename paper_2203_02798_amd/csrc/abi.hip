@@ -271,6 +271,10 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
     case PSK_OP_QR:
       rc = sketch_qr_impl(nullptr, A->n, A->d, nullptr, nullptr, ws, nullptr);
       break;
+    case PSK_OP_DELTA:
+      if (A->d < 1 || A->n < A->d) return fail(PSK_EINVAL, "PSK_OP_DELTA needs n = m >= d >= 1");
+      rc = sketch_delta_impl(nullptr, nullptr, A->n, A->d, nullptr, ws, nullptr);
+      break;
     case PSK_OP_LSQ: {
       psk_lsq_opts o{};
       if (m == 0) {
@@ -286,6 +290,7 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
       o.prec = prec;
       o.max_iter = 1;
       o.check_every = 1;
+      o.want_delta = k != 0 ? 1 : 0;
       rc = lsq_impl(*A, nullptr, nullptr, o, nullptr, ws, nullptr);
       break;
     }
@@ -515,6 +520,19 @@ int sketch_qr(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_QR)");
   Arena ws = Arena::over(wsp, ws_bytes);
   return sketch_qr_impl(C, m, d, R, Rinv, ws, as_stream(stream));
+}
+
+int sketch_delta(const double *Chat, const double *C, int64_t m, int64_t d, double *delta,
+                 void *wsp, size_t ws_bytes, void *stream) {
+  if (d < 1 || m < d) return fail(PSK_EINVAL, "sketch_delta needs m >= d >= 1");
+  if (!Chat || !C || !delta) return fail(PSK_EINVAL, "Chat, C and delta must be non-NULL");
+  Arena plan;
+  int rc = sketch_delta_impl(nullptr, nullptr, m, d, nullptr, plan, nullptr);
+  if (rc) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_DELTA)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return sketch_delta_impl(Chat, C, m, d, delta, ws, as_stream(stream));
 }
 
 int lsq_solve(const psk_mat *A, const double *b, double *x, const psk_lsq_opts *opts,

@@ -191,6 +191,15 @@ int leverage_sketch_impl(const psk_mat &A, int64_t m, int64_t r, int64_t t, uint
 int sketch_f64(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec, double *C,
                Arena &ws, hipStream_t st);
 
+// ---- perturbation of a sketch (k_delta.hip) ----------------------------------
+// *delta (device) = ||(Chat - C) R^{-1}||_2, R from sketch_qr of C (m x d,
+// m >= d, FP64 row-major).
+int sketch_delta_impl(const double *Chat, const double *C, int64_t m, int64_t d, double *delta,
+                      Arena &ws, hipStream_t st);
+// the same with R^{-1} of C already at hand
+int delta_from_factor(const double *Chat, const double *C, const double *Ri, int64_t m,
+                      int64_t d, double *delta, Arena &ws, hipStream_t st);
+
 // ---- column subset selection (k_css.hip) ------------------------------------
 // cols[0..k): the first k pivots of the column-pivoted QR of the sketch.
 int css_select_impl(const psk_mat &A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,

@@ -229,10 +229,10 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_bf16(
   const int grow = tid >> 2, goct = tid & 3;
   const uint32_t row_g = (uint32_t)(m0 + grow);
   auto gen_g = [&](int64_t c_abs, int gbuf) {
-    float z[8];
+    float z[8];  // bfloat16 values (each the rounding of the FP64 normal)
     const uint64_t qb = (uint64_t)c_abs * 8u + 2u * (uint64_t)goct;
-    gauss4_f32(qb, row_g, seed, z);
-    gauss4_f32(qb + 1, row_g, seed, z + 4);
+    gauss4_bf16(qb, row_g, seed, z);
+    gauss4_bf16(qb + 1, row_g, seed, z + 4);
     v8bf a;
 #pragma unroll
     for (int e = 0; e < 8; ++e) a[e] = (__bf16)z[e];

@@ -294,9 +294,39 @@ __global__ __launch_bounds__(512) void k_scatter_csr_fp8(
   }
 }
 
+// G's FP8 operand, drawn once: thread (chunk c, row a, lane group g) writes
+// the e4m3 bytes (G's fixed scale, each the rounding of the FP64 normal) of
+// buckets 128 c + 32 g .. + 31 of row a, 32 contiguous bytes at
+// gq[((c m_pad + a) 4 + g) 32], the A fragment of MFMA lane (a % 16, g);
+// rows past m and buckets past r are zero.
+__global__ __launch_bounds__(256) void k_draw_g_e4m3(int64_t m, int64_t m_pad, int64_t r,
+                                                     int64_t kchunks, uint64_t seed,
+                                                     unsigned char *__restrict__ gq) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= kchunks * m_pad * 4) return;
+  const int g = (int)(t & 3);
+  const int64_t a = (t >> 2) % m_pad;
+  const int64_t c = (t >> 2) / m_pad;
+  uint32_t w[8];
+  const uint64_t qb = (uint64_t)c * 32u + 8u * (uint64_t)g;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    uint32_t by = a < m ? gauss4_e4m3(qb + u, (uint32_t)a, seed) : 0u;
+    const int64_t valid = r - (int64_t)(4 * (qb + u));
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (k >= valid) by &= ~(0xFFu << (8 * k));
+    w[u] = by;
+  }
+  uint4 *o = reinterpret_cast<uint4 *>(gq + t * 32);
+  o[0] = uint4{w[0], w[1], w[2], w[3]};
+  o[1] = uint4{w[4], w[5], w[6], w[7]};
+}
+
 template <bool TAIL>
 __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
-    int64_t m, int64_t d, int64_t r, int64_t npad, uint64_t seed,
+    int64_t m, int64_t d, int64_t r, int64_t npad, const unsigned char *__restrict__ gq,
+    int64_t m_pad, int64_t kchunks,
     const unsigned char *__restrict__ q, const unsigned char *__restrict__ sc, int tiles_m,
     int tiles_n, int64_t c0, int64_t kend, int64_t cper, int ks0,
     float *__restrict__ out /* [splits][m][d] */) {
@@ -358,36 +388,17 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
   };
 
   const uint32_t row_a = (uint32_t)(m0 + wave * 16 + li);
-  // this lane's 32 normals of chunk c (buckets 128 c + 32 g + j), quantised
-  // with the row's block scale; returns the fragment and sets the E8M0 byte.
-  // TAIL (the launch of the chunk that holds bucket r): G ends at bucket r,
-  // so the values from there on are zero and the block scale is taken over
-  // the buckets that exist.
+  // this lane's A fragment of chunk c: the 32 e4m3 bytes of G (buckets
+  // 128 c + 32 g + j of its row) drawn by k_draw_g_e4m3, and the E8M0 byte
+  // of G's fixed scale (chunks past the last read the last, unused)
+  (void)r;
   auto make_a = [&](int64_t c_abs, int &sbyte) {
-    float z[32];
-    const uint64_t qb = (uint64_t)c_abs * 32u + 8u * (uint64_t)g;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) gauss4_f32(qb + t, row_a, seed, z + 4 * t);
-    if (TAIL) {
-      const int64_t valid = r - (int64_t)(4 * qb);
-#pragma unroll
-      for (int j = 0; j < 32; ++j)
-        if (j >= valid) z[j] = 0.0f;
-    }
-    float amax = 0.0f;
-#pragma unroll
-    for (int j = 0; j < 32; ++j) amax = fmaxf(amax, fabsf(z[j]));
-    amax = fmaxf(amax, __shfl_xor(amax, 16, 64));
-    amax = fmaxf(amax, __shfl_xor(amax, 32, 64));
-    const int e = scale_exp_f32(amax);
-    sbyte = e + 127;
-    v8i a;
-#pragma unroll
-    for (int w = 0; w < 8; ++w) {
-      const float s0 = ldexpf(z[4 * w + 0], -e), s1 = ldexpf(z[4 * w + 1], -e);
-      const float s2 = ldexpf(z[4 * w + 2], -e), s3 = ldexpf(z[4 * w + 3], -e);
-      a[w] = (int)(e4m3x2(s0, s1) | (e4m3x2(s2, s3) << 16));
-    }
+    const int64_t cc = c_abs < kchunks ? c_abs : kchunks - 1;
+    const uint4 *p = reinterpret_cast<const uint4 *>(gq + ((cc * m_pad + row_a) * 4 + g) * 32);
+    const uint4 x0 = p[0], x1 = p[1];
+    const v8i a = {(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w,
+                   (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+    sbyte = 127 + kGFp8Exp;
     return a;
   };
 
@@ -477,8 +488,8 @@ namespace {
 // (the one launch that masks G past bucket r).
 struct Fp8Plan {
   int tiles_m, tiles_n;
-  int64_t r, npad, kchunks, kfull, tiles, splits, splits_main, cper;
-  unsigned char *q, *sc;
+  int64_t r, npad, kchunks, kfull, tiles, splits, splits_main, cper, m_pad;
+  unsigned char *q, *sc, *gq;
   float *part;
 };
 
@@ -502,6 +513,8 @@ int fp8_plan(int64_t m, int64_t r, int64_t d, Arena &ws, Fp8Plan &P) {
   P.q = ws.take<unsigned char>((size_t)(P.kchunks * 8 * P.npad * 16));
   P.sc = ws.take<unsigned char>((size_t)(P.kchunks * P.npad));
   P.part = ws.take<float>((size_t)P.splits * m * d);
+  P.m_pad = (int64_t)P.tiles_m * kBM;
+  P.gq = ws.take<unsigned char>((size_t)(P.kchunks * P.m_pad * kBK));
   if (!ws.dry() && !ws.ok())
     return fail(PSK_ENOMEM, "workspace too small for the FP8 Gaussian GEMM");
   return 0;
@@ -510,15 +523,21 @@ int fp8_plan(int64_t m, int64_t r, int64_t d, Arena &ws, Fp8Plan &P) {
 int fp8_run(const Fp8Plan &P, int64_t m, int64_t d, uint64_t seed, double *C,
             hipStream_t st) {
   {
+    KTimer t("g_draw", st);
+    const int64_t thr = P.kchunks * P.m_pad * 4;
+    k_draw_g_e4m3<<<(unsigned)ceil_div(thr, (int64_t)256), 256, 0, st>>>(m, P.m_pad, P.r,
+                                                                        P.kchunks, seed, P.gq);
+  }
+  {
     KTimer t("gauss_gemm", st);
     if (P.splits_main > 0)
       k_gauss_gemm_fp8<false><<<(unsigned)(P.tiles * P.splits_main), kThreads, 0, st>>>(
-          m, d, P.r, P.npad, seed, P.q, P.sc, P.tiles_m, P.tiles_n, 0, P.kfull, P.cper, 0,
-          P.part);
+          m, d, P.r, P.npad, P.gq, P.m_pad, P.kchunks, P.q, P.sc, P.tiles_m, P.tiles_n, 0,
+          P.kfull, P.cper, 0, P.part);
     if (P.kfull < P.kchunks)
       k_gauss_gemm_fp8<true><<<(unsigned)P.tiles, kThreads, 0, st>>>(
-          m, d, P.r, P.npad, seed, P.q, P.sc, P.tiles_m, P.tiles_n, P.kfull, P.kchunks, 1,
-          (int)P.splits_main, P.part);
+          m, d, P.r, P.npad, P.gq, P.m_pad, P.kchunks, P.q, P.sc, P.tiles_m, P.tiles_n, P.kfull,
+          P.kchunks, 1, (int)P.splits_main, P.part);
   }
   {
     KTimer t("gemm_reduce", st);

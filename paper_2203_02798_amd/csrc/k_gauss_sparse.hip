@@ -9,8 +9,11 @@
 // the same product in the same precision as the dense kernels:
 //   FP64  G and S*A in FP64;
 //   BF16  G rounded to bfloat16, S*A as its two bfloat16 limbs hi + lo;
-//   FP8   both in OCP e4m3 with one E8M0 scale per 128-bucket block (per row
-//         of G, per column of S*A).
+//   FP8   both in OCP e4m3: S*A with one E8M0 scale per 128-bucket block
+//         of each column, G with the fixed scale 2^-6.
+// Only the 4-bucket quads of G that meet an entry of S*A are drawn: with
+// counter-based normals and G's rounding decided per value, the others are
+// never needed.
 // FP64 accumulates in FP64.  BF16 and FP8 accumulate in FP32 within a K
 // split, as the dense reduced-precision kernels do (each product is exact
 // inside the FMA; BF16's value hi + lo is rounded to FP32 where its limbs
@@ -107,15 +110,6 @@ __device__ __forceinline__ double e4m3_round(double v, int e) {
   }
   const int byte = __builtin_amdgcn_cvt_pk_fp8_f32(f, 0.0f, 0, false) & 0xff;
   return ldexp((double)__builtin_amdgcn_cvt_f32_fp8(byte, 0), e);
-}
-
-// e4m3_round of an FP32 value: v 2^-e is exact in FP32 (|v 2^-e| <= 448,
-// and the values of G lie far inside FP32's normal range), so one
-// hardware rounding gives the same byte
-__device__ __forceinline__ float e4m3_round_f32(float v, int e) {
-  const float x = ldexpf(v, -e);
-  const int byte = __builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xff;
-  return ldexpf(__builtin_amdgcn_cvt_f32_fp8(byte, 0), e);
 }
 
 // The value written for an S*A entry: BF16 keeps hi + lo, its two limbs
@@ -315,31 +309,39 @@ constexpr int kCscCols = 1024;  // columns of S*A the block sort takes at most
 // column's entries is the number of the column's buckets before its own:
 // a bitmap of buckets per column, its popcounts and a scan over the
 // columns give every entry its slot, with no dependence on timing.
+// Also qmask[4 k .. 4 k + 3]: the 4-bucket quads of the block that hold an
+// entry (bit j of word i: quad 32 i + j), the Philox blocks of G the product
+// has to draw for this block.
 template <int W>
 __global__ __launch_bounds__(512) void k_block_csc(const uint32_t *__restrict__ be,
                                                    const uint32_t *__restrict__ eb,
                                                    const int32_t *__restrict__ ec,
                                                    const double *__restrict__ ev, int64_t d,
                                                    uint32_t *__restrict__ sp,
-                                                   double *__restrict__ sv) {
+                                                   double *__restrict__ sv,
+                                                   uint32_t *__restrict__ qmask) {
   __shared__ uint32_t bits[kCscCols * W];   // [column][word]: buckets present
   __shared__ uint16_t wpre[kCscCols * W];   // buckets present in the words before
   __shared__ uint32_t ccnt[kCscCols];       // entries per column
   __shared__ uint32_t cst[kCscCols];        // exclusive scan of ccnt
+  __shared__ uint32_t qm[4];                // quads holding an entry
   const int tid = threadIdx.x;
   const int64_t k = blockIdx.x;
   const uint32_t lo = be[k], hi = be[k + 1];
   const uint32_t b0 = (uint32_t)(k * (32 * W));
   for (int64_t i = tid; i < d * W; i += 512) bits[i] = 0u;
+  if (tid < 4) qm[tid] = 0u;
   __syncthreads();
   for (uint32_t e = lo + tid; e < hi; e += 512) {
     const int32_t c = ec[e];
     if (c >= 0) {
       const uint32_t bo = eb[e] - b0;
       atomicOr(&bits[c * W + (bo >> 5)], 1u << (bo & 31));
+      atomicOr(&qm[bo >> 7], 1u << ((bo >> 2) & 31));
     }
   }
   __syncthreads();
+  if (tid < 4) qmask[4 * k + tid] = qm[tid];
   for (int64_t c = tid; c < d; c += 512) {
     uint32_t run = 0;
 #pragma unroll
@@ -386,6 +388,22 @@ __global__ __launch_bounds__(512) void k_block_csc(const uint32_t *__restrict__ 
   }
 }
 
+// position of the k-th (from 0) set bit of w, k < popcount(w): halve the
+// window five times, moving to its upper half when the lower one holds at
+// most k set bits
+__device__ __forceinline__ int select_bit(uint32_t w, uint32_t k) {
+  int pos = 0;
+#pragma unroll
+  for (int sh = 16; sh >= 1; sh >>= 1) {
+    const uint32_t c = (uint32_t)__popc((w >> pos) & ((1u << sh) - 1u));
+    if (k >= c) {
+      k -= c;
+      pos += sh;
+    }
+  }
+  return pos;
+}
+
 // G precision of the sparse product
 enum { kG64 = 0, kGbf16 = 1, kGfp8 = 2 };
 
@@ -415,7 +433,8 @@ static_assert(kStage / (kHeavy + 1) < kHeavyMax, "heavy list capacity");
 template <int GP, int DP, int BLK>
 __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     int64_t m, int64_t d, int64_t r, uint64_t seed, const uint32_t *__restrict__ be,
-    const uint32_t *__restrict__ sp, const double *__restrict__ sv, int tiles_m, int64_t bper,
+    const uint32_t *__restrict__ sp, const double *__restrict__ sv,
+    const uint32_t *__restrict__ qmask, int tiles_m, int64_t bper,
     double *__restrict__ part /* [splits][m][d] */) {
   typedef typename std::conditional<GP == kG64, double, float>::type GT;
   typedef GT AT;  // accumulator and staged value: FP64, or FP32 with G in FP32
@@ -450,22 +469,6 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
 #pragma unroll
   for (int i = 0; i < 16; ++i) acc[i] = AT(0);
   uint32_t tag = 0;  // one per staged turn, never kHole
-  // G item u of this thread: row ga_u, Philox block q_u of the block.  FP8
-  // takes the amax of a row over a 128-bucket scale block, 32 Philox blocks:
-  // a wavefront holds 64 / LQ rows of one scale block, LQ lanes per row, NIT
-  // items per lane; otherwise consecutive lanes take consecutive rows.
-  constexpr int LQ = 32 / NIT;
-  auto item = [&](int u, int &a, int &q) {
-    if (GP == kGfp8) {
-      const int w = tid >> 6, lane = tid & 63;
-      a = (w >> 2) * (64 / LQ) + lane / LQ;
-      q = (w & 3) * 32 + lane % LQ + LQ * u;
-    } else {
-      const int it = tid + kSThreads * u;
-      a = it % MT;
-      q = it / MT;
-    }
-  };
   // block bounds, loaded per lane (through vz, a zero the compiler cannot
   // see) so that they join the entries in the in-order vector load counter
   struct Bnd {
@@ -481,6 +484,15 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
   auto bounds = [&](int64_t k, Bnd &B) {
     B.lo = be[(k < k1 ? k : k1) + vz];
     B.hi = be[(k + 1 < k1 ? k + 1 : k1) + vz];
+  };
+  // occupied-quad masks of the next blocks in an LDS ring of four: word i of
+  // block k (none past the split) is loaded by thread i three steps ahead
+  // and stored at the end of the step's draw, before its barrier
+  __shared__ uint32_t qms[4][4];
+  auto qmask_word = [&](int64_t k) -> uint32_t {
+    const int64_t kq = k < k1 ? k : k1 - 1;
+    const uint32_t w = qmask[4 * kq + (tid & 3)];
+    return k < k1 ? w : 0u;
   };
   auto load = [&](uint32_t base, uint32_t hi, uint32_t *pp, double *vv) {
 #pragma unroll
@@ -570,54 +582,128 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
   };
   auto step = [&](int64_t kb, ESet &X, Bnd &BX, Bnd &BY) __attribute__((always_inline)) {
     const int64_t b0 = kb * BLK;
-    GT g[NIT][4];
+    // Only the quads that hold an entry are drawn (the others are never
+    // read): item it of the block is row it % MT of the (it / MT)-th
+    // occupied quad; thread tid takes items tid, tid + 1024, ...
+    uint32_t qw[4], qpre[4];
+    uint32_t nq = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      qw[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)qms[kb & 3][i]);
+      qpre[i] = nq;
+      nq += (uint32_t)__popc(qw[i]);
+    }
+    // the mask of block kb + 3, stored into the ring after the draw
+    uint32_t qnext = 0;
+    if (tid < 4) qnext = qmask_word(kb + 3);
+    const int nitems = (int)(nq * MT);
+    // row and quad of item u (recomputed at the store: fewer live registers)
+    auto item_of = [&](int u, int &a, int &q) __attribute__((always_inline)) {
+      const int it = tid + kSThreads * u;
+      a = it % MT;
+      // the (it / MT)-th occupied quad: its word, then its bit in the word
+      const uint32_t qi = (uint32_t)(it / MT);
+      int wi = 0;
+#pragma unroll
+      for (int i = 1; i < 4; ++i)
+        if (qi >= qpre[i]) wi = i;
+      uint32_t w = qw[0], left = qi - qpre[0];
+#pragma unroll
+      for (int i = 1; i < 4; ++i)
+        if (wi == i) {
+          w = qw[i];
+          left = qi - qpre[i];
+        }
+      q = 32 * wi + select_bit(w, left);
+    };
+    // the drawn values: FP64, or (BF16, FP8: exact in bfloat16) two
+    // bfloat16 per register
+    constexpr int GW = GP == kG64 ? 4 : 2;
+    typedef typename std::conditional<GP == kG64, double, uint32_t>::type GR;
+    GR g[NIT][GW];
+    // values within the window of a rounding midpoint (4 bits per item):
+    // redrawn in FP64 after the store, when g is no longer live
+    uint32_t nearm = 0;
 #pragma unroll
     for (int u = 0; u < NIT; ++u) {
-      int a, q;
-      item(u, a, q);
-      const int64_t ga = a0 + a, bq = b0 + 4 * q;
-      if (GP == kG64) {
-        double z[4] = {0.0, 0.0, 0.0, 0.0};
-        if (ga < m && bq < r) gauss4_f64((uint64_t)(bq >> 2), (uint32_t)ga, seed, z);
+      if (tid + kSThreads * u < nitems) {
+        int a, q;
+        item_of(u, a, q);
+        const int64_t ga = a0 + a, bq = b0 + 4 * q;
+        if constexpr (GP == kG64) {
+          double z[4] = {0.0, 0.0, 0.0, 0.0};
+          if (ga < m && bq < r) gauss4_f64((uint64_t)(bq >> 2), (uint32_t)ga, seed, z);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) g[u][t] = (GT)z[t];
-      } else {
-        float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (ga < m && bq < r) gauss4_f32((uint64_t)(bq >> 2), (uint32_t)ga, seed, z);
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-          if (bq + t >= r) z[t] = 0.0f;  // G ends at bucket r
-        if (GP == kGbf16) {
-#pragma unroll
-          for (int t = 0; t < 4; ++t) g[u][t] = (GT)(float)(__bf16)z[t];
+          for (int t = 0; t < 4; ++t) g[u][t] = z[t];
         } else {
+          float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (ga < m && bq < r) {
+            const u32x4 x = philox_g((uint64_t)(bq >> 2), (uint32_t)ga, seed);
+            if (GP == kGbf16) {
+              nearm |= gauss4_bf16_fast(x, z) << (4 * u);
+            } else {
+              // FP8: G's fixed scale, so a quad's rounding needs no other values
+              uint32_t nr;
+              const uint32_t by = gauss4_e4m3_fast(x, &nr);
+              nearm |= nr << (4 * u);
 #pragma unroll
-          for (int t = 0; t < 4; ++t) g[u][t] = (GT)z[t];
+              for (int t = 0; t < 4; ++t) z[t] = e4m3_g_value(by, t);
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (bq + t >= r) z[t] = 0.0f;  // G ends at bucket r
+          // bfloat16 patterns (exact: the values are bfloat16 or e4m3)
+          g[u][0] = (__float_as_uint(z[0]) >> 16) | (__float_as_uint(z[1]) & 0xFFFF0000u);
+          g[u][1] = (__float_as_uint(z[2]) >> 16) | (__float_as_uint(z[3]) & 0xFFFF0000u);
         }
       }
     }
-    if (GP == kGfp8) {
-      // amax of each row over its scale block: NIT items here, LQ lanes
-      float am = 0.0f;
-#pragma unroll
-      for (int u = 0; u < NIT; ++u)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) am = fmaxf(am, fabsf((float)g[u][t]));
-#pragma unroll
-      for (int off = LQ / 2; off > 0; off >>= 1) am = fmaxf(am, __shfl_xor(am, off, 64));
-      const int ex = e8m0_exp((double)am);
-#pragma unroll
-      for (int u = 0; u < NIT; ++u)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) g[u][t] = (GT)e4m3_round_f32((float)g[u][t], ex);
-    }
+    if (tid < 4) qms[(kb + 3) & 3][tid] = qnext;  // ring slot of block kb - 1, read
     __syncthreads();  // the previous block is done with Gb, the stage and crng
 #pragma unroll
-    for (int u = 0; u < NIT; ++u) {
-      int a, q;
-      item(u, a, q);
+    for (int u = 0; u < NIT; ++u)
+      if (tid + kSThreads * u < nitems) {
+        int a, q;
+        item_of(u, a, q);
+        GT gv[4];
+        if constexpr (GP == kG64) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) Gb[(4 * q + t) * GS + a] = g[u][t];
+          for (int t = 0; t < 4; ++t) gv[t] = (GT)g[u][t];
+        } else {
+          gv[0] = (GT)__uint_as_float(g[u][0] << 16);
+          gv[1] = (GT)__uint_as_float(g[u][0] & 0xFFFF0000u);
+          gv[2] = (GT)__uint_as_float(g[u][1] << 16);
+          gv[3] = (GT)__uint_as_float(g[u][1] & 0xFFFF0000u);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) Gb[(4 * q + t) * GS + a] = gv[t];
+      }
+    if constexpr (GP != kG64) {
+      // the FP64 decisions, written over this thread's own slots (made
+      // visible by the barrier after the stage)
+      if (__builtin_expect(nearm != 0u, 0)) {
+#pragma unroll 1
+        for (int u = 0; u < NIT; ++u) {
+          const uint32_t nb = (nearm >> (4 * u)) & 15u;
+          if (nb == 0u) continue;
+          int a, q;
+          item_of(u, a, q);
+          const int64_t ga = a0 + a, bq = b0 + 4 * q;
+          const u32x4 x = philox_g((uint64_t)(bq >> 2), (uint32_t)ga, seed);
+          float z[4];
+          if (GP == kGbf16) {
+            gauss4_bf16_fix(x, nb, z);
+          } else {
+            const uint32_t by = gauss4_e4m3_fix(x, nb, 0u);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) z[t] = e4m3_g_value(by, t);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (((nb >> t) & 1u) && bq + t < r) Gb[(4 * q + t) * GS + a] = (GT)z[t];
+        }
+      }
     }
     const uint32_t lo = X.lo, hi = X.hi;
     stage(X.p, X.v, hi - lo < (uint32_t)kStage ? hi - lo : (uint32_t)kStage);
@@ -636,6 +722,12 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
       consume();
     }
   };
+  if (tid < 4) {  // ring slots are block index mod 4
+    qms[k0 & 3][tid] = qmask_word(k0);
+    qms[(k0 + 1) & 3][tid] = qmask_word(k0 + 1);
+    qms[(k0 + 2) & 3][tid] = qmask_word(k0 + 2);
+  }
+  __syncthreads();
   Bnd BA, BB;
   ESet RA, RB;
   bounds(k0, BA);
@@ -741,6 +833,7 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
   double *ev = ws.take<double>((size_t)A.nnz + 1);
   uint32_t *sp = ws.take<uint32_t>((size_t)A.nnz + 1);
   double *sv = ws.take<double>((size_t)A.nnz + 1);
+  uint32_t *qmask = ws.take<uint32_t>((size_t)4 * nblk);
   double *part = ws.take<double>((size_t)splits * m * d);
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the sparse Gaussian product");
@@ -767,16 +860,16 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
     k_block_entries<<<(unsigned)ceil_div(nblk + 1, 256), 256, 0, st>>>(bptr, eoff, r, blk, nblk,
                                                                      be);
     if (blk == 256)
-      k_block_csc<8><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, sp, sv);
+      k_block_csc<8><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, sp, sv, qmask);
     else
-      k_block_csc<16><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, sp, sv);
+      k_block_csc<16><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, sp, sv, qmask);
   }
   {
     KTimer t("gauss_gemm", st);
     const unsigned grid = (unsigned)(tiles_m * splits);
 #define PSK_GSP(GP, DP, BLK)                                                                 \
-  k_gauss_sparse<GP, DP, BLK><<<grid, kSThreads, 0, st>>>(m, d, r, seed, be, sp, sv, tiles_m, \
-                                                         bper, part)
+  k_gauss_sparse<GP, DP, BLK><<<grid, kSThreads, 0, st>>>(m, d, r, seed, be, sp, sv, qmask, \
+                                                         tiles_m, bper, part)
 #define PSK_GSP_MT(GP, BLK)                   \
   do {                                        \
     if (d <= 512) PSK_GSP(GP, 512, BLK);      \

@@ -877,6 +877,14 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   double *res = ws.take<double>((size_t)n);  // residual of the refinement passes
   B.st = ws.take<LsqrState>(1);
   double *ratio = ws.take<double>(2);       // max |R_ii|, min |R_ii|
+  // the reduced-precision sketch's perturbation against the FP64 one, on
+  // request: that sketch kept (Chat), the FP64 sketch and its factor
+  const bool want_delta = own && o.want_delta != 0 && o.prec != PSK_PREC_F64;
+  double *Chat = want_delta ? ws.take<double>((size_t)m * d) : nullptr;
+  double *C64 = want_delta ? ws.take<double>((size_t)m * d) : nullptr;
+  double *R64 = want_delta ? ws.take<double>((size_t)d * d) : nullptr;
+  double *Ri64 = want_delta ? ws.take<double>((size_t)d * d) : nullptr;
+  double *dl = want_delta ? ws.take<double>(1) : nullptr;
   const size_t mk = ws.mark();
   int rc = 0;
   int *flag = nullptr;
@@ -900,16 +908,17 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   void *SA = nullptr;
   uint32_t *perm = nullptr, *bptr = nullptr;
   // the FP64 sketch (after a reduced-precision one), S*A formed here if needed
-  auto rebuild_f64 = [&]() -> int {
+  auto rebuild_f64 = [&](double *Cout) -> int {
     int e;
     if (sparse_ok)
-      return gauss_gemm_sparse(m, o.r, A, perm, bptr, o.seed, PSK_PREC_F64, C, ws, st);
-    if (fused) {
+      return gauss_gemm_sparse(m, o.r, A, perm, bptr, o.seed, PSK_PREC_F64, Cout, ws, st);
+    if (fused && !SA) {
       SA = ws.take<double>((size_t)o.r * d);
       if ((e = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st, true))) return e;
     }
-    return gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, PSK_F64, C, ws, st);
+    return gauss_gemm(m, o.r, d, o.seed, PSK_PREC_F64, SA, PSK_F64, Cout, ws, st);
   };
+  size_t mk_sketch = 0;  // scratch above S*A and the bins: the sketch's
   if (own) {
     // sketch and factor (their scratch is released afterwards); S*A (or the
     // binned rows it is formed from) stays until the precision decision so
@@ -919,6 +928,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     if (!fused && !sparse && (rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st, true)))
       return rc;
     const size_t mk2 = ws.mark();
+    mk_sketch = mk2;
     if (sparse)
       rc = gauss_gemm_sparse(m, o.r, A, perm, bptr, o.seed, o.prec, C, ws, st);
     else if (fused && o.prec == PSK_PREC_BF16)
@@ -930,34 +940,62 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     if (rc) return rc;
     ws.release(mk2);
     if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;
-    ws.release(mk2);
+    if (want_delta) {
+      // delta = ||(Chat - C64) R64^{-1}||_2 for the FP64 sketch C64 of the
+      // same S*A, its scratch above the factorization's (whose pivot flag is
+      // read below); S*A formed here (fused forms) stays for an escalation
+      if (!ws.dry())
+        PSK_HIP_TRY(hipMemcpyAsync(Chat, C, (size_t)m * d * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st));
+      if ((rc = rebuild_f64(C64))) return rc;
+      const size_t mk3 = ws.mark();
+      if ((rc = sketch_qr_impl(C64, m, d, R64, Ri64, ws, st))) return rc;
+      ws.release(mk3);
+      if ((rc = delta_from_factor(Chat, C64, Ri64, m, d, dl, ws, st))) return rc;
+      ws.release(mk3);
+    } else {
+      ws.release(mk2);
+    }
     if (may_escalate && ws.dry()) {
       // plan the FP64 rebuild as well
-      if ((rc = rebuild_f64())) return rc;
+      if ((rc = rebuild_f64(C))) return rc;
       ws.release(mk2);
     }
   }
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for lsq_solve");
+  // delta of the sketch LSQR is preconditioned with: 0 for the FP64 sketch,
+  // NaN when not measured (not requested, or the caller's R^{-1})
+  double delta_est = (own && o.prec == PSK_PREC_F64) ? 0.0 : NAN;
   if (own) {
     int hflag = 0;
     double hr[2] = {1.0, 1.0};
     k_diag_ratio<<<1, 256, 0, st>>>(R, d, ratio);
     PSK_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
     PSK_HIP_TRY(hipMemcpyAsync(hr, ratio, sizeof(hr), hipMemcpyDeviceToHost, st));
+    if (want_delta)
+      PSK_HIP_TRY(hipMemcpyAsync(&delta_est, dl, sizeof(double), hipMemcpyDeviceToHost, st));
     PSK_HIP_TRY(hipStreamSynchronize(st));
     // A reduced-precision sketch only preconditions well while its relative
     // error (about 1e-5 for the BF16 GEMM) times cond(A) stays small; the
     // diagonal ratio of R is a cheap lower estimate of cond(A).
     if (may_escalate && (hflag || !(hr[0] <= cond_limit * hr[1]))) {
+      // the first factorization's flag has been read: its scratch is free
+      ws.release(mk_sketch);
       const size_t mk2 = ws.mark();
-      if ((rc = rebuild_f64())) return rc;
+      if (want_delta) {
+        PSK_HIP_TRY(hipMemcpyAsync(C, C64, (size_t)m * d * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st));
+      } else if ((rc = rebuild_f64(C))) {
+        return rc;
+      }
       ws.release(mk2);
       if ((rc = sketch_qr_impl(C, m, d, R, Rinv, ws, st, &flag))) return rc;
       ws.release(mk2);
       PSK_HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
       PSK_HIP_TRY(hipStreamSynchronize(st));
       prec_used = PSK_PREC_F64;
+      delta_est = 0.0;  // LSQR runs on the FP64 sketch now
     }
     if (hflag) return fail(PSK_ERANK, "sketch is numerically rank deficient");
   }
@@ -1090,6 +1128,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     info->ne_resid = hs.test2;
     info->prec_used = own ? prec_used : -1;
     info->reserved = 0;
+    info->delta_est = delta_est;
   }
   if (!converged) return fail(PSK_ENOCONV, "LSQR reached max_iter before its tolerance");
   return 0;

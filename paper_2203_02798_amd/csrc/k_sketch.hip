@@ -274,6 +274,11 @@ __device__ __forceinline__ void store_out(TO *p, const TO (&x)[VW]) {
   }
 }
 
+// The U rows of a batch are loaded together and branch-free (a row past the
+// bucket, or columns past d, load an element of row 0 at column 0 and are
+// masked), so all of them are in flight at once, and the bin entries of the
+// next batch are loaded while this one is summed.  Rows are added in bin
+// order, in FP64.
 template <typename T, typename TO, int VW, int CH, int U>
 __global__ __launch_bounds__(256) void k_scatter_dense(
     const T *__restrict__ A, int64_t ld, int64_t d, int64_t r,
@@ -296,25 +301,35 @@ __global__ __launch_bounds__(256) void k_scatter_dense(
     for (int c = 0; c < CH; ++c)
 #pragma unroll
       for (int q = 0; q < VW; ++q) acc[c][q] = 0.0;
-    uint32_t j = j0;
-    for (; j + U <= j1; j += U) {
+    // column offsets of this lane's groups, clamped to 0 past d
+    int64_t coff[CH];
+    bool cok[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int64_t col = c0 + (int64_t)(c * 64 + lane) * VW;
+      cok[c] = col < d;
+      coff[c] = cok[c] ? col : 0;
+    }
+    uint32_t pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pv[u] = perm[(j0 + u < j1) ? j0 + u : lo];
+    for (uint32_t j = j0; j < j1; j += U) {
       T x[U][CH][VW];
-      uint32_t neg[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t pv = perm[j + u];
-        const int64_t row = (int64_t)(pv & 0x7fffffffu);
-        neg[u] = pv >> 31;
+        const bool rok = j + u < j1;
+        const int64_t row = rok ? (int64_t)(pv[u] & 0x7fffffffu) : 0;
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-          const int64_t col = c0 + (int64_t)(c * 64 + lane) * VW;
-          if (col < d) {
-            vload<T, VW>(A + row * ld + col, x[u][c]);
-          } else {
+        for (int c = 0; c < CH; ++c) vload<T, VW>(A + row * ld + coff[c], x[u][c]);
+      }
+      double sg[U];
 #pragma unroll
-            for (int q = 0; q < VW; ++q) x[u][c][q] = T(0);
-          }
-        }
+      for (int u = 0; u < U; ++u) sg[u] = (j + u < j1) ? ((pv[u] >> 31) ? -1.0 : 1.0) : 0.0;
+      // the next batch's bin entries
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t jn = j + U + u;
+        pv[u] = perm[jn < j1 ? jn : lo];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -322,33 +337,17 @@ __global__ __launch_bounds__(256) void k_scatter_dense(
         for (int c = 0; c < CH; ++c)
 #pragma unroll
           for (int q = 0; q < VW; ++q) {
-            const double xv = (double)x[u][c][q];
-            acc[c][q] += neg[u] ? -xv : xv;
+            const double xv = cok[c] ? (double)x[u][c][q] : 0.0;
+            acc[c][q] = fma(sg[u], xv, acc[c][q]);
           }
-    }
-    for (; j < j1; ++j) {
-      const uint32_t pv = perm[j];
-      const int64_t row = (int64_t)(pv & 0x7fffffffu);
-      const uint32_t ng = pv >> 31;
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        const int64_t col = c0 + (int64_t)(c * 64 + lane) * VW;
-        if (col < d) {
-          T xv[VW];
-          vload<T, VW>(A + row * ld + col, xv);
-#pragma unroll
-          for (int q = 0; q < VW; ++q) acc[c][q] += ng ? -(double)xv[q] : (double)xv[q];
-        }
-      }
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int64_t col = c0 + (int64_t)(c * 64 + lane) * VW;
-      if (col < d) {
+      if (cok[c]) {
         TO ov[VW];
 #pragma unroll
         for (int q = 0; q < VW; ++q) ov[q] = (TO)acc[c][q];
-        store_out<TO, VW>(orow + col, ov);
+        store_out<TO, VW>(orow + coff[c], ov);
       }
     }
   }

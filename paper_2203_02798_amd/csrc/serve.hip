@@ -16,6 +16,8 @@
 // Requests on different slots overlap on the device; each request's kernels
 // read only its own inputs and workspace, so its result does not depend on
 // what else runs.
+#include <math.h>
+
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -25,70 +27,15 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "server_book.hpp"
 
 namespace psk {
 namespace {
-
-constexpr size_t kAlign = 256;
 
 double now_s() {
   using namespace std::chrono;
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
-
-// First-fit allocator over [0, cap) with coalescing of free ranges.
-class PoolAlloc {
- public:
-  explicit PoolAlloc(size_t cap) : cap_(cap) {
-    if (cap_ > 0) free_[0] = cap_;
-  }
-  // offset of a block of `bytes`, or SIZE_MAX if none fits
-  size_t alloc(size_t bytes) {
-    bytes = (bytes + kAlign - 1) / kAlign * kAlign;
-    if (bytes == 0) bytes = kAlign;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        const size_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > bytes) free_[off + bytes] = len - bytes;
-        used_ += bytes;
-        if (used_ > peak_) peak_ = used_;
-        sizes_[off] = bytes;
-        return off;
-      }
-    }
-    return SIZE_MAX;
-  }
-  void release(size_t off) {
-    auto s = sizes_.find(off);
-    if (s == sizes_.end()) return;
-    size_t start = off, len = s->second;
-    sizes_.erase(s);
-    used_ -= len;
-    auto next = free_.find(start + len);  // merge with the following free range
-    if (next != free_.end()) {
-      len += next->second;
-      free_.erase(next);
-    }
-    auto it = free_.lower_bound(start);  // and with the preceding one
-    if (it != free_.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == start) {
-        start = prev->first;
-        len += prev->second;
-        free_.erase(prev);
-      }
-    }
-    free_[start] = len;
-  }
-  size_t peak() const { return peak_; }
-  size_t used() const { return used_; }
-
- private:
-  size_t cap_, used_ = 0, peak_ = 0;
-  std::map<size_t, size_t> free_;   // offset -> length
-  std::map<size_t, size_t> sizes_;  // allocated offset -> length
-};
 
 struct Job {
   psk_request req;
@@ -131,10 +78,9 @@ struct Server {
   std::vector<hipStream_t> streams;
   std::vector<std::thread> workers;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work;
   std::deque<Job *> queue;
-  std::map<int64_t, Job *> jobs;
-  int64_t next_ticket = 1;
+  TicketBoard<Job> jobs;
   int inflight = 0, inflight_peak = 0;
   int64_t submitted = 0, completed = 0;
   bool stop = false;
@@ -177,7 +123,7 @@ struct Server {
       alloc.release(job->ws_off);
       --inflight;
       ++completed;
-      cv_done.notify_all();
+      jobs.completed();
       cv_work.notify_all();
     }
   }
@@ -256,9 +202,8 @@ int psk_server_submit(psk_server *srv, const psk_request *q, int64_t *ticket) {
       delete job;
       return fail(PSK_EINVAL, "server is shutting down");
     }
-    job->ticket = s->next_ticket++;
     job->t_submit = now_s();
-    s->jobs[job->ticket] = job;
+    job->ticket = s->jobs.add(job);
     s->queue.push_back(job);
     ++s->submitted;
   }
@@ -277,34 +222,28 @@ static void fill_result(const Job *j, psk_result *res) {
   res->t_end = j->t_end;
   res->prec_used = j->req.op == PSK_REQ_LSQ ? j->info.prec_used : j->req.opts.prec;
   res->reserved = 0;
+  res->delta_est = j->req.op == PSK_REQ_LSQ ? j->info.delta_est : NAN;
+}
+
+static int ticket_status(int rc) {
+  if (rc == TicketBoard<Job>::kUnknown) return fail(PSK_EINVAL, "unknown ticket");
+  if (rc == TicketBoard<Job>::kClaimed)
+    return fail(PSK_EINVAL, "another thread is already waiting for this ticket");
+  return rc == TicketBoard<Job>::kPending ? PSK_PENDING : PSK_OK;
 }
 
 int psk_server_wait(psk_server *srv, int64_t ticket, psk_result *res) {
   if (!srv || !res) return fail(PSK_EINVAL, "NULL argument");
   Server *s = reinterpret_cast<Server *>(srv);
   std::unique_lock<std::mutex> lk(s->mu);
-  auto it = s->jobs.find(ticket);
-  if (it == s->jobs.end()) return fail(PSK_EINVAL, "unknown ticket");
-  Job *j = it->second;
-  s->cv_done.wait(lk, [&] { return j->done; });
-  fill_result(j, res);
-  s->jobs.erase(it);
-  delete j;
-  return PSK_OK;
+  return ticket_status(s->jobs.wait(lk, ticket, [&](const Job &j) { fill_result(&j, res); }));
 }
 
 int psk_server_poll(psk_server *srv, int64_t ticket, psk_result *res) {
   if (!srv || !res) return fail(PSK_EINVAL, "NULL argument");
   Server *s = reinterpret_cast<Server *>(srv);
   std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->jobs.find(ticket);
-  if (it == s->jobs.end()) return fail(PSK_EINVAL, "unknown ticket");
-  Job *j = it->second;
-  if (!j->done) return PSK_PENDING;
-  fill_result(j, res);
-  s->jobs.erase(it);
-  delete j;
-  return PSK_OK;
+  return ticket_status(s->jobs.poll(ticket, [&](const Job &j) { fill_result(&j, res); }));
 }
 
 int psk_server_stats(psk_server *srv, psk_server_stats_t *out) {
@@ -332,7 +271,7 @@ int psk_server_destroy(psk_server *srv) {
   s->cv_work.notify_all();
   for (auto &t : s->workers) t.join();
   for (auto st : s->streams) (void)hipStreamDestroy(st);
-  for (auto &kv : s->jobs) delete kv.second;
+  s->jobs.clear();
   delete s;
   return PSK_OK;
 }

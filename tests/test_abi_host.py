@@ -80,6 +80,17 @@ def test_workspace_planning(lib):
     assert st == 0 and b6 >= 2 * 400 * 100 * 8
     st, b7 = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=128, r=1024)
     assert st == 0 and b7 > 5000 * 8
+    # with want_delta (k != 0) a BF16 solve also holds the FP64 sketch and its
+    # factor; an FP64 solve has nothing to compare
+    st, b7d = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=128, r=1024, k=1, prec=L.PSK_PREC_BF16)
+    st2, b7b = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=128, r=1024, k=0, prec=L.PSK_PREC_BF16)
+    assert st == 0 and st2 == 0 and b7d >= b7b + 2 * 128 * 32 * 8
+    q2 = L.PskMat(); q2.n, q2.d = 128, 32
+    st, bd = _ws(L.PSK_OP_DELTA, q2)
+    assert st == 0 and bd >= 2 * 128 * 32 * 8
+    q2.n = 16
+    st, _ = _ws(L.PSK_OP_DELTA, q2)
+    assert st == -1  # m < d
     st, b8 = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=0, r=0)  # caller's own R^{-1}
     assert st == 0 and 5000 * 8 < b8 < b7
     st, _ = _ws(L.PSK_OP_LSQ, _dense(5000, 32), m=16, r=1024)  # m < d
