@@ -2,27 +2,27 @@
 """Benchmark of the sketch / Gram / leverage / least-squares hot path on one
 MI355X.
 
-One step is one pass of the whole path over the sparse workload (CSR A,
-1,000,000 x 500, density 1e-3, FP64; CountSketch r = 250,000 buckets then a
-Gaussian with m = 2,000 rows):
+Headline: one step is one pass of the path over the dense tall-skinny
+workload (A 4,000,000 x 256 FP32, singular values geometric from 1 to 1e-6,
+5% of rows scaled by 100; CountSketch r = 65,536 buckets, Gaussian m = 1,024
+rows) in the paper's arithmetic, FP64:
 
     C     = G*S*A                  sketch_gcs   (hash, binning, S*A, Gaussian GEMM)
     Gram  = A^T A                  gram
     R, R^-1 of C                   sketch_qr
     theta = rownorm^2(A R^-1)      rownorms_sq  (sketched leverage scores)
-    x     = argmin ||A x - b||     lsq_solve    (LSQR preconditioned by R^-1)
 
 Inputs are synthetic and seeded (the paper's matrices are random with
 unstated distributions) and are resident in HBM before timing starts.
-The FP64 plain path and the paths with the BF16 and FP8 Gaussian GEMMs are
-all timed (``--prec all``, the default); the BF16 path is the headline and
-the other two are reported beside it.  Prints ONE JSON line.  ``value`` is GB/s of A
-through the whole step (bytes of A = values + column indices + row
-pointers, per step, divided by the step time).  The dominant kernel (the
-Gaussian product; for this sparse workload k_gauss_sparse, bound by the
-VALU work of drawing G) is timed with HIP events on its own stream inside
-the library and reported as a roofline fraction; the CPU oracle is timed on
-a bounded sample on the host.
+``value`` is GB/s of A through the whole step (bytes of A per step divided
+by the step time).  The dominant kernel of the step is timed with HIP events
+on its own stream inside the library and reported as a roofline fraction
+against the FP64 matrix peak, on the method's own flops.  Beside it: the
+BF16 and FP8 sketches of the same matrix with their perturbation delta, the
+small dense workload's latency, the sparse workload (CSR 1e6 x 500) with
+least squares, the Zipf CSR 1e7 x 1000 FP8 sketch and leverage scores, the
+request server on the 512-request least-squares trace, and the CPU oracle
+timed on a bounded sample of the headline workload.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -38,45 +38,46 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 if HERE not in sys.path:
     sys.path.insert(0, HERE)
 
-WORKLOADS = {
-    # name: (kind, n, d, density, r, m)
-    "csr-1e6x500": ("csr", 1_000_000, 500, 1e-3, 250_000, 2000),
-    "dense-20000x50": ("dense", 20_000, 50, None, 2500, 200),
-}
+METRIC = "GB/s of A sketched (G·S·A) + LSQ solves/s, p50/p99 latency vs FP64 plain path"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
 PEAK_FP8_TFLOPS = 5000.0
+PEAK_HBM_GBS = 8000.0
 # VALU peak in lane-operations: the FP32 vector rate, 157.3 TFLOP/s at 256 CUs
-# and 2.4 GHz, is 128 FP32 FMA lanes per CU per clock (a wave64 v_fma_f32 in
-# two cycles per SIMD; psk_probe_valu_f32 reaches ~82% of it without packed
-# instructions), one lane-operation per FMA: 157.3 / 2 = 78.65 T/s
+# and 2.4 GHz, is 128 FP32 FMA lanes per CU per clock, one lane-operation per
+# FMA: 157.3 / 2 = 78.65 T/s
 PEAK_VALU_TOPS = 157.3 / 2
-# VALU lane-operations per Gaussian sample of the sparse product's G (BF16):
-# a Philox4x32-10 block and its Box-Muller pair of pairs give 4 samples for
-# 20 64-bit multiplies, 20 three-input XORs and 71 further operations
-# (uniforms, 2 log, 2 sqrt, sin/cos polynomials, products), log and sqrt at
-# half rate (+4), and 8 for the rounding to bfloat16: 123 per 4 samples
-VALU_OPS_PER_SAMPLE_BF16 = 123 / 4
 
-# HBM bytes per launch of the dominant kernel from hardware counters
-# (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, the factors measured on a copy
-# kernel of known size), valid only for the kernel source they were taken
-# on: the figure is dropped (null) as soon as the source hash differs.
+# Headline workload: dense coherent FP32 n x d, r buckets, m Gaussian rows
+HEAD = dict(n=4_000_000, d=256, r=65536, m=1024, smin=1e-6)
+
+# HBM bytes per launch of the headline's dominant kernels from hardware
+# counters (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale, the factors
+# measured on a copy kernel of known size), valid only for the kernel source
+# they were taken on: a figure is dropped (null) as soon as the source hash
+# differs.
 PMC_TRAFFIC = {
-    ("csr-1e6x500", "bf16"): {
-        "source": "paper_2203_02798_amd/csrc/k_gauss_sparse.hip",
-        "sha256_prefix": "813cd88f73adeb9b",
-        "fetch_kib": 23572.2, "write_kib": 31250.0,
+    "k_gram_syrk": {
+        "source": "paper_2203_02798_amd/csrc/k_dense.hip",
+        "sha256_prefix": "a7995ba52f2db5de",
+        "fetch_kib": 5524779.8, "write_kib": 65659.0,
         "fetch_scale": 2.000, "write_scale": 1.000,
-        "profile": "profiles/gauss_sparse_bf16_csr-1e6x500_pmc.md",
+        "profile": "profiles/step_dense-4e6x256_pmc.md",
+    },
+    "k_rownorm_bres": {
+        "source": "paper_2203_02798_amd/csrc/k_dense.hip",
+        "sha256_prefix": "a7995ba52f2db5de",
+        "fetch_kib": 3678979.5, "write_kib": 125012.1,
+        "fetch_scale": 2.000, "write_scale": 1.000,
+        "profile": "profiles/step_dense-4e6x256_pmc.md",
     },
 }
 
 
-def pmc_traffic(workload, prec):
+def pmc_traffic(kernel):
     import hashlib
-    t = PMC_TRAFFIC.get((workload, prec))
-    if t is None:
+    t = PMC_TRAFFIC.get(kernel)
+    if t is None or t["sha256_prefix"] is None:
         return None
     with open(os.path.join(HERE, t["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha256_prefix"]:
@@ -88,60 +89,309 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def a_bytes(a, kind):
-    if kind == "csr":
-        return a.nnz * (a.data.itemsize + 4) + (a.shape[0] + 1) * 8
-    return a.size * a.itemsize
+def csr_bytes(a):
+    """Everything the method reads of a CSR matrix: values, int32 column
+    indices, int64 row pointers."""
+    return a.nnz * (a.data.itemsize + 4) + (a.shape[0] + 1) * 8
 
 
-def make_inputs(name):
+def timed(torch, f, steps, warmup, stream=None):
+    """(mean wall seconds per call, per-call event milliseconds) of f."""
+    for _ in range(warmup):
+        f()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        f()
+        e1.record(stream)
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, lat
+
+
+# ---------------------------------------------------------------------------
+# headline: the FP64 step on the dense coherent 4e6 x 256 matrix
+# ---------------------------------------------------------------------------
+def headline(api, torch, A, steps, warmup, seed):
+    n, d, r, m = HEAD["n"], HEAD["d"], HEAD["r"], HEAD["m"]
+    nbytes = n * d * 4
+
+    def step():
+        C = api.sketch_gcs(A, m, r, seed, prec="f64")
+        Gm = api.gram(A)
+        R, Ri = api.sketch_qr(C)
+        th = api.rownorms_sq(A, Ri)
+        return C, Gm, Ri, th
+
+    log(f"[f64] warmup {warmup}")
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[f64] timing {steps} steps")
+    stream = torch.cuda.current_stream()
+    # inside the timed steps only the two dominant kernels are bracketed (each
+    # bracket costs host time); the per-stage breakdown comes from two further
+    # steps afterwards
+    with api.kernel_timing(only=("gram", "rownorm")) as kt:
+        wall, lat = timed(torch, step, steps, 0, stream)
+        kst = kt.stats()
+    with api.kernel_timing() as kt:
+        for _ in range(2):
+            out = step()
+        torch.cuda.synchronize()
+        per = {k: v[0] / 2 for k, v in kt.stats().items()}
+    th = out[3]
+    sketch_ms = sum(per.get(k, 0.0) for k in ("cs_bin", "cs_scatter", "gauss_gemm",
+                                                "gemm_reduce"))
+    lat = np.array(lat)
+    # method's own flops: the Gram matrix's d(d+1)/2 distinct dot products of
+    # length n (2 n d (d+1) / 2), the row norms' product with the triangular
+    # R^{-1} (sum_j 2 (j+1) per row) and the squares: n d (d+2); executed
+    # flops: the 16 x 16 blocks of the upper block triangle (Gram), the K
+    # chunks of the paired 32-column tiles up to each tile's extent (row norms)
+    flops = {"gram": n * d * (d + 1), "rownorm": n * d * (d + 2)}
+    tiles = (d + 31) // 32
+    exe = {"gram": n * ((d + 15) // 16) * ((d + 15) // 16 + 1) // 2 * 512,
+           "rownorm": n * 2 * 32 * 32 * sum(t + 1 for t in range(tiles))}
+    kern = {}
+    for name, kname in (("gram", "k_gram_syrk"), ("rownorm", "k_rownorm_bres")):
+        ms, cnt = kst.get(name, (0.0, 0))
+        launch = ms / max(cnt, 1)
+        ach = flops[name] / (launch * 1e-3) / 1e12 if launch > 0 else 0.0
+        kern[name] = {"kernel": kname, "launch_ms": launch, "launches": cnt,
+                      "flops_per_launch": flops[name], "achieved_TFs": ach,
+                      "frac": ach / PEAK_FP64_TFLOPS,
+                      "executed_flops_per_launch": exe[name],
+                      "executed_TFs": exe[name] / (launch * 1e-3) / 1e12 if launch > 0 else 0.0}
+    dom = max(kern, key=lambda k: kern[k]["launch_ms"])
+    k = kern[dom]
+    roof = {"bound": "mfma", "kernel": k["kernel"], "achieved": k["achieved_TFs"],
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": k["frac"],
+            "traffic": pmc_traffic(k["kernel"]), "traffic_unit": "bytes per launch",
+            "launch_ms": k["launch_ms"], "flops_per_launch": k["flops_per_launch"],
+            "flops_basis": "method's own flops (Gram: n d (d+1), symmetric; row norms: "
+                           "n d (d+2), triangular R^-1)",
+            "executed_TFs": k["executed_TFs"],
+            "executed_frac": k["executed_TFs"] / PEAK_FP64_TFLOPS}
+    # the S*A stage against HBM: A read once, S*A (FP64) written, bins
+    sa_bytes = nbytes + r * d * 8 + n * 4 * 2
+    scat = per.get("cs_scatter", 0.0)
+    res = {
+        "value": nbytes * steps / (wall * steps) / 1e9,
+        "ms_per_step": 1e3 * wall,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "sketch_gcs_ms": sketch_ms,
+        "sketch_gcs_gbs": nbytes / (sketch_ms * 1e-3) / 1e9 if sketch_ms > 0 else None,
+        "scatter_hbm": {"bytes": sa_bytes, "ms": scat,
+                        "GBs": sa_bytes / (scat * 1e-3) / 1e9 if scat > 0 else None,
+                        "frac": sa_bytes / (scat * 1e-3) / 1e9 / PEAK_HBM_GBS if scat > 0 else None,
+                        "stage_frac_with_binning":
+                            sa_bytes / ((scat + per.get("cs_bin", 0.0)) * 1e-3) / 1e9 /
+                            PEAK_HBM_GBS if scat > 0 else None},
+        "stage_ms": {kk: round(v, 4) for kk, v in sorted(per.items())},
+        "kernels": kern,
+        "roofline": roof,
+        "sum_theta": float(th.sum().item()),
+    }
+    return res
+
+
+def reduced_sketches(api, torch, A, steps, warmup, seed):
+    """The BF16 and FP8 sketches of the headline matrix: time per call, GB/s of
+    A, and delta = ||(C^ - C) R^{-1}||_2 against the FP64 sketch, with the
+    leverage bracket it allows; plus the JL step's effect on the row norms."""
+    n, d, r, m = HEAD["n"], HEAD["d"], HEAD["r"], HEAD["m"]
+    nbytes = n * d * 4
+    c64 = api.sketch_gcs(A, m, r, seed, prec="f64")
+    out = {}
+    for prec in ("bf16", "fp8"):
+        f = lambda: api.sketch_gcs(A, m, r, seed, prec=prec)
+        timed(torch, f, 0, warmup)
+        with api.kernel_timing() as kt:
+            wall, _ = timed(torch, f, steps, 0)
+            st = kt.stats()
+        ch = f()
+        delta = api.sketch_delta(ch, c64).item()
+        out[prec] = {"ms_per_call": 1e3 * wall, "gbs": nbytes / wall / 1e9,
+                     "delta": delta,
+                     "leverage_ratio_bound": (1 - delta) ** -2 - 1 if delta < 1 else None,
+                     "valid_delta_lt_half": delta < 0.5,
+                     "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(st.items())}}
+    return out
+
+
+def leverage_jl(api, torch, A, steps, warmup, seed, t=64):
+    """leverage_sketch (FP64 sketch) with and without the JL step on the
+    headline matrix: time per call and the row-norm product's time."""
+    n, d, r, m = HEAD["n"], HEAD["d"], HEAD["r"], HEAD["m"]
+    out = {"t": t}
+    th = {}
+    for tt in (0, t):
+        f = lambda: api.leverage_sketch(A, m, r, seed, t=tt)
+        timed(torch, f, 0, warmup)
+        with api.kernel_timing() as kt:
+            wall, _ = timed(torch, f, steps, 0)
+            st = kt.stats()
+        rn = st.get("rownorm", (0.0, 1))
+        rn_ms = rn[0] / max(rn[1], 1)
+        out[f"t{tt}"] = {"ms_per_call": 1e3 * wall, "rownorm_ms": rn_ms}
+        th[tt] = f()
+    ratio = (th[t] / th[0]).cpu().numpy()
+    out["jl_ratio"] = {"std": float(ratio.std()), "jl_std": float(np.sqrt(2.0 / t))}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the small dense workload: end-to-end latency
+# ---------------------------------------------------------------------------
+def small_latency(api, torch, steps=50, warmup=5):
     import synth
-    kind, n, d, dens, r, m = WORKLOADS[name]
-    if kind == "csr":
-        a = synth.csr_uniform(n, d, dens, seed=0)
-    else:
-        a = synth.dense_gaussian(n, d, seed=0)
+    n, d, r, m = 20000, 50, 2500, 200
+    a = synth.dense_gaussian(n, d, seed=0)
     rng = np.random.default_rng(1)
-    xt = rng.standard_normal(d)
-    b = a @ xt + 1e-3 * rng.standard_normal(n)
-    return kind, a, b, r, m
+    b = a @ rng.standard_normal(d) + 1e-3 * rng.standard_normal(n)
+    A = torch.from_numpy(a).cuda()
+    bd = torch.from_numpy(b).cuda()
+
+    def step():
+        C = api.sketch_gcs(A, m, r, 0)
+        api.gram(A)
+        _, Ri = api.sketch_qr(C)
+        api.rownorms_sq(A, Ri)
+        return api.lsq_solve(A, bd, Rinv=Ri, max_iter=200, refine=1, check_every=8)
+
+    wall, lat = timed(torch, step, steps, warmup)
+    x, info = step()
+    return {"workload": f"dense FP64 {n} x {d}, r = {r}, m = {m}", "steps": steps,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": 1e3 * wall, "lsq_iters": info["iters"],
+            "note": "one step: sketch, Gram, QR, row norms and LSQR; latency-bound "
+                    "(every stage is microseconds of work)"}
 
 
-def serving_trace_gpu(torch, num, seed, n_lo, n_hi, device):
-    """Synthetic least-squares requests drawn on the device: n log-uniform in
-    [n_lo, n_hi], d uniform over {32, 64, 128, 256}, condition number
-    log-uniform in [1, 1e8]; A = X diag(s) V^T with X ~ N(0,1)/sqrt(n), V the
-    Q factor of a Gaussian, s geometric from 1 to 1/cond; b = A x + 1e-3 e."""
-    rng = np.random.default_rng(seed)
-    reqs = []
-    for k in range(num):
-        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
-        d = int(rng.choice([32, 64, 128, 256]))
-        cond = float(np.exp(rng.uniform(0.0, np.log(1e8))))
-        g = torch.Generator(device=device)
-        g.manual_seed(seed * 100003 + k)
-        x = torch.randn(n, d, generator=g, device=device, dtype=torch.float64) / n ** 0.5
-        v, _ = torch.linalg.qr(torch.randn(d, d, generator=g, device=device,
-                                           dtype=torch.float64))
-        sv = torch.logspace(0.0, -np.log10(cond), d, device=device, dtype=torch.float64)
-        a = ((x * sv) @ v.T).contiguous()
-        xt = torch.randn(d, generator=g, device=device, dtype=torch.float64)
-        b = a @ xt + 1e-3 * torch.randn(n, generator=g, device=device, dtype=torch.float64)
-        reqs.append(dict(a=a, b=b, n=n, d=d, cond=cond, m=4 * d, r=min(d * d, n), seed=k))
-    torch.cuda.synchronize(device)
-    return reqs
+# ---------------------------------------------------------------------------
+# the sparse workload CSR 1e6 x 500: the step with least squares per precision
+# ---------------------------------------------------------------------------
+def csr_workload(api, torch, steps, warmup, seed):
+    import synth
+    n, d, dens, r, m = 1_000_000, 500, 1e-3, 250_000, 2000
+    a = synth.csr_uniform(n, d, dens, seed=0)
+    rng = np.random.default_rng(1)
+    b = a @ rng.standard_normal(d) + 1e-3 * rng.standard_normal(n)
+    A = api.CsrMatrix.from_scipy(a, device="cuda:0")
+    bd = torch.from_numpy(b).cuda()
+    nbytes = csr_bytes(a)
+    out = {"workload": f"CSR {n} x {d} FP64, density {dens}, r = {r}, m = {m}",
+           "a_bytes": nbytes}
+    c64 = api.sketch_gcs(A, m, r, seed)
+    for prec in ("f64", "bf16", "fp8"):
+        def step():
+            C = api.sketch_gcs(A, m, r, seed, prec=prec)
+            api.gram(A)
+            _, Ri = api.sketch_qr(C)
+            api.rownorms_sq(A, Ri)
+            return C, api.lsq_solve(A, bd, Rinv=Ri, max_iter=200, refine=1, check_every=8)
+        wall, lat = timed(torch, step, steps, warmup)
+        with api.kernel_timing() as kt:
+            C, (x, info) = step()
+            torch.cuda.synchronize()
+            st = kt.stats()
+        res = float(np.linalg.norm(b - a @ x.cpu().numpy()))
+        out[prec] = {"gbs": nbytes / wall / 1e9, "ms_per_step": 1e3 * wall,
+                     "solves_per_s": 1.0 / wall,
+                     "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)),
+                     "delta": api.sketch_delta(C, c64).item() if prec != "f64" else 0.0,
+                     "lsq": {"iters": info["iters"], "status": info["status"], "resid": res},
+                     "stage_ms": {k: round(v[0], 4) for k, v in sorted(st.items())}}
+    out["bf16_vs_fp64_step"] = out["f64"]["ms_per_step"] / out["bf16"]["ms_per_step"]
+    # the Gaussian product over S*A's nonzeros (BF16): bound by drawing G
+    return out, A, a, b, bd
 
 
-def serving_bench(api, torch, device, num=64, slots=8, pool_gb=16.0):
-    """Closed-loop runs (all requests queued at t = 0) of the request server
-    for the FP64 and BF16 sketch at two sketch sizes (m = 4d and 8d; r =
-    min(d^2, n) >= m), and an open-loop run (Poisson arrivals at 0.8x the best
-    FP64 rate) with the best BF16 configuration."""
-    reqs = serving_trace_gpu(torch, num, 0, 1e4, 2e5, device)
-    pool = int(pool_gb * (1 << 30))
+def gaussian_only(api, torch, A, m, seed, steps, warmup):
+    f = lambda: api.sketch_g(A, m, seed, prec="bf16")
+    wall, _ = timed(torch, f, steps, warmup)
+    return {"call": "sketch_g", "prec": "bf16", "m": m, "ms_per_call": 1e3 * wall}
 
-    def run(prec, mf, esc=0.0, arrivals=None):
-        with api.Server(pool, slots=slots, device=device) as srv:
+
+def direct_bench(api, torch, A, a, b, bd, m, r, seed, steps, warmup):
+    calls = {
+        "leverage_gram": lambda: api.leverage_gram(A),
+        "lsq_gram": lambda: api.lsq_gram(A, bd),
+        "lsq_sketch_solve_bf16": lambda: api.lsq_sketch_solve(A, bd, m, r, seed, prec="bf16"),
+    }
+    out = {}
+    for name, f in calls.items():
+        wall, _ = timed(torch, f, steps, warmup)
+        out[name] = {"ms_per_call": 1e3 * wall}
+    return out
+
+
+def css_bench(api, torch, A, d, r, seed, steps, warmup):
+    m = 2 * d
+    kk = max(d // 5, 1)
+    calls = {
+        f"css_select_k{kk}": lambda: api.css_select(A, m, r, kk, seed, prec="bf16"),
+        f"css_select_k{d}": lambda: api.css_select(A, m, r, d, seed, prec="bf16"),
+        f"leverage_css_k{kk}": lambda: api.leverage_css(A, m, r, kk, seed, prec="bf16"),
+    }
+    out = {"m": m, "r": r, "prec": "bf16"}
+    for name, f in calls.items():
+        wall, _ = timed(torch, f, steps, warmup)
+        out[name] = {"ms_per_call": 1e3 * wall}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the Zipf CSR 1e7 x 1000 FP32: FP8 sketch and leverage scores
+# ---------------------------------------------------------------------------
+def zipf_workload(api, torch, steps, warmup, seed):
+    import synth
+    n, d, dens, r, m = 10_000_000, 1000, 1e-4, 1_000_000, 4000
+    a = synth.csr_zipf(n, d, dens, seed=seed, dtype=np.float32)
+    A = api.CsrMatrix.from_scipy(a, device="cuda:0")
+    nbytes = csr_bytes(a)
+    out = {"workload": f"CSR {n} x {d} FP32, Zipf(1.5) rows, nnz {a.nnz}, "
+                       f"non-empty rows {int((np.diff(a.indptr) > 0).sum())}, r = {r}, m = {m}",
+           "a_bytes": nbytes}
+    c64 = api.sketch_gcs(A, m, r, seed)
+    for prec in ("fp8", "f64"):
+        f = lambda: api.sketch_gcs(A, m, r, seed, prec=prec)
+        timed(torch, f, 0, warmup)
+        with api.kernel_timing() as kt:
+            wall, _ = timed(torch, f, steps, 0)
+            st = kt.stats()
+        out[prec] = {"ms_per_call": 1e3 * wall, "gbs": nbytes / wall / 1e9,
+                     "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(st.items())}}
+    out["fp8"]["delta"] = api.sketch_delta(api.sketch_gcs(A, m, r, seed, prec="fp8"), c64).item()
+    f = lambda: api.leverage_sketch(A, m, r, seed, t=0, prec="fp8")
+    wall, _ = timed(torch, f, steps, warmup)
+    th = f()
+    out["leverage_fp8"] = {"ms_per_call": 1e3 * wall, "sum_theta": float(th.sum().item())}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# serving: 512 least-squares requests, Poisson arrivals, HBM-pool admission
+# ---------------------------------------------------------------------------
+def serving_bench(api, torch, num=512, slots=8, pools_gb=(32.0, 128.0), n_hi=1e6):
+    import synth
+    log(f"serving: drawing {num} requests on the device")
+    reqs = synth.lsq_trace_torch(num, 0, 1e4, n_hi, device="cuda:0")
+    torch.cuda.synchronize()
+    abytes = sum(q["a"].numel() * 8 for q in reqs)
+    kappa_edges = [1.0, 1e2, 1e4, 1e6, 1e8 + 1]
+
+    def run(prec, mf, pool_gb, arrivals=None, want_delta=False):
+        pool = int(pool_gb * (1 << 30))
+        with api.Server(pool, slots=slots, device="cuda:0") as srv:
             t0 = time.perf_counter()
             pend = []
             for k, q in enumerate(reqs):
@@ -152,278 +402,134 @@ def serving_bench(api, torch, device, num=64, slots=8, pool_gb=16.0):
                 m = mf * q["d"]
                 r = max(min(q["d"] * q["d"], q["n"]), m)
                 pend.append(srv.submit_lsq(q["a"], q["b"], m=m, r=r, seed=q["seed"],
-                                           prec=prec, escalate_cond=esc))
+                                           prec=prec, want_delta=want_delta))
             res = [srv.wait(t) for t, _ in pend]
             wall = time.perf_counter() - t0
             st = srv.stats()
         lat = np.array([1e3 * (r_["t_end"] - r_["t_submit"]) for r_ in res])
-        out = {"prec": prec, "m": f"{mf}d", "solves_per_s": num / wall,
+        out = {"prec": prec, "m": f"{mf}d", "pool_gb": pool_gb, "solves_per_s": num / wall,
                "p50_ms": float(np.percentile(lat, 50)),
                "p99_ms": float(np.percentile(lat, 99)), "wall_s": wall,
                "failed": sum(1 for r_ in res if r_["status"] != "PSK_OK"),
                "inflight_peak": st["inflight_peak"], "pool_peak_bytes": st["pool_peak"],
-               "lsqr_iters_mean": float(np.mean([r_["iters"] for r_ in res]))}
-        if prec == "bf16":
-            out["escalate_cond"] = esc if esc else 1e4
-            out["escalated_to_f64"] = int(sum(1 for r_ in res if r_["prec_used"] == "f64"))
-        return out, [x for _, x in pend]
+               "lsqr_iters_mean": float(np.mean([r_["iters"] for r_ in res])),
+               "escalated_to_f64": int(sum(1 for r_ in res if prec != "f64" and
+                                           r_["prec_used"] == "f64"))}
+        return out, res, [x for _, x in pend]
 
     runs = {}
     sols = {}
-    for prec, mf, esc in (("f64", 4, 0.0), ("f64", 8, 0.0), ("bf16", 4, 0.0),
-                          ("bf16", 8, 0.0), ("bf16", 8, 1e3), ("bf16", 16, 0.0)):
-        key = f"{prec}_m{mf}d" + ("_esc1e3" if esc else "")
-        log(f"serving: {num} requests, closed loop, {key}")
-        runs[key], sols[key] = run(prec, mf, esc)
+    for pool_gb in pools_gb:
+        for prec in ("f64", "bf16", "fp8"):
+            key = f"{prec}_m8d_pool{int(pool_gb)}g"
+            log(f"serving: closed loop {key}")
+            runs[key], _, sols[key] = run(prec, 8, pool_gb)
     ok = lambda k: runs[k]["failed"] == 0
-    best64 = max((k for k in runs if k.startswith("f64") and ok(k)),
-                 key=lambda k: runs[k]["solves_per_s"])
-    best16 = max((k for k in runs if k.startswith("bf16") and ok(k)),
-                 key=lambda k: runs[k]["solves_per_s"])
-    # residual of each solution, best BF16 vs best FP64 configuration
-    rel = []
-    for q, xa, xb in zip(reqs, sols[best64], sols[best16]):
-        ra = torch.linalg.vector_norm(q["b"] - q["a"] @ xa).item()
-        rb = torch.linalg.vector_norm(q["b"] - q["a"] @ xb).item()
-        rel.append(abs(rb - ra) / ra)
+    big = int(max(pools_gb))
+    best64 = f"f64_m8d_pool{big}g"
+    red = [k for k in runs if not k.startswith("f64") and k.endswith(f"pool{big}g") and ok(k)]
+    bestred = max(red, key=lambda k: runs[k]["solves_per_s"]) if red else None
+    # residuals of each reduced-precision solution against the FP64 one
+    rel = {}
+    for key in red:
+        worst = 0.0
+        for q, xa, xb in zip(reqs, sols[best64], sols[key]):
+            ra = torch.linalg.vector_norm(q["b"] - q["a"] @ xa).item()
+            rb = torch.linalg.vector_norm(q["b"] - q["a"] @ xb).item()
+            worst = max(worst, abs(rb - ra) / ra)
+        rel[key] = worst
+    # per condition-number bucket: delta, iterations, escalations (a separate
+    # pass with want_delta, not timed against the others)
+    buckets = {}
+    for prec in ("bf16", "fp8"):
+        log(f"serving: delta pass {prec}")
+        _, res, _ = run(prec, 8, float(big), want_delta=True)
+        for lo, hi in zip(kappa_edges[:-1], kappa_edges[1:]):
+            idx = [i for i, q in enumerate(reqs) if lo <= q["cond"] < hi]
+            if not idx:
+                continue
+            ds = [res[i]["delta_est"] for i in idx if res[i]["prec_used"] == prec]
+            key = f"{prec}_cond_{lo:.0e}_{hi:.0e}"
+            buckets[key] = {
+                "requests": len(idx),
+                "escalated_to_f64": int(sum(1 for i in idx if res[i]["prec_used"] == "f64")),
+                "lsqr_iters_mean": float(np.mean([res[i]["iters"] for i in idx])),
+                "delta_max_kept": float(max(ds)) if ds else None,
+                "delta_median_kept": float(np.median(ds)) if ds else None}
     rate = 0.8 * runs[best64]["solves_per_s"]
     arr = np.cumsum(np.random.default_rng(1).exponential(1.0 / rate, size=num))
-    prec, mf = runs[best16]["prec"], int(runs[best16]["m"][:-1])
-    esc = 1e3 if best16.endswith("esc1e3") else 0.0
-    log(f"serving: open loop, Poisson arrivals at {rate:.1f}/s, {best16}")
-    ol, _ = run(prec, mf, esc, arrivals=arr)
-    olf, _ = run("f64", int(runs[best64]["m"][:-1]), 0.0, arrivals=arr)
-    return {
-        "trace": (f"{num} synthetic LSQ requests, n log-uniform [1e4, 2e5], d in "
-                  "{32,64,128,256}, cond log-uniform [1, 1e8], r = max(min(d^2, n), m), "
-                  "A resident in HBM before submission"),
-        "slots": slots, "pool_bytes": pool,
+    log(f"serving: open loop at {rate:.1f}/s")
+    open_loop = {}
+    open_loop["f64"], _, _ = run("f64", 8, float(big), arrivals=arr)
+    if bestred:
+        pr = runs[bestred]["prec"]
+        open_loop[pr], _, _ = run(pr, 8, float(big), arrivals=arr)
+    out = {
+        "trace": (f"{num} synthetic LSQ requests, n log-uniform [1e4, {n_hi:.0e}], d in "
+                  "{32,64,128,256}, cond log-uniform [1, 1e8], b = A x + 1e-3 e, m = 8d, "
+                  "r = max(min(d^2, n), m); A resident in HBM before submission"),
+        "a_bytes_total": abytes, "slots": slots, "pools_gb": list(pools_gb),
         "closed_loop": runs,
-        "best_fp64": best64, "best_bf16": best16,
-        "bf16_vs_fp64_solves": runs[best16]["solves_per_s"] / runs[best64]["solves_per_s"],
-        "resid_rel_diff_max": float(max(rel)),
-        "open_loop": {"arrival_rate": rate, best16: ol, best64: olf},
+        "best_fp64": best64, "best_reduced": bestred,
+        "reduced_vs_fp64_solves": (runs[bestred]["solves_per_s"] /
+                                   runs[best64]["solves_per_s"]) if bestred else None,
+        "resid_rel_diff_max": rel,
+        "by_cond": buckets,
+        "open_loop": {"arrival_rate": rate, **open_loop},
     }
-
-
-def gaussian_only_bench(api, torch, A, m, n, d, nnz, seed, steps, warmup):
-    """G*A (sketch_g, the Gaussian-only sketch of CSR A, BF16 G) on the same
-    matrix: m n normals and one FMA per (row of G, nonzero of A), the same
-    kernel as the combined sketch with one bucket per row."""
-    for _ in range(warmup):
-        api.sketch_g(A, m, seed, prec="bf16")
-    torch.cuda.synchronize()
-    with api.kernel_timing() as kt:
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            api.sketch_g(A, m, seed, prec="bf16")
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / steps
-        stats = kt.stats()
-    gg_ms, gg_n = stats.get("gauss_gemm", (0.0, 0))
-    launch = gg_ms / max(gg_n, 1)
-    ops = m * n * VALU_OPS_PER_SAMPLE_BF16 + m * nnz
-    ach = ops / (launch * 1e-3) / 1e12 if launch > 0 else 0.0
-    return {"call": "sketch_g", "prec": "bf16", "m": m, "ms_per_call": 1e3 * wall,
-            "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(stats.items())},
-            "roofline": {"bound": "alu", "kernel": "k_gauss_sparse", "achieved": ach,
-                         "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-ops/s",
-                         "frac": ach / PEAK_VALU_TOPS, "launch_ms": launch,
-                         "samples_per_launch": m * n, "fma_per_launch": m * nnz}}
-
-
-def leverage_jl_bench(api, torch, steps, warmup, n=4_000_000, d=256, r=65536, m=1024,
-                      t=64, seed=0):
-    """leverage_sketch on the dense tall-skinny FP32 configuration (4,000,000 x
-    256, singular values geometric from 1 to 1e-6, 5% of rows scaled by 100),
-    with and without the JL step.  A = Z diag(s) V^T with Z Gaussian and V
-    orthogonal, generated on the device.  The sketch is FP64 (at cond 1e6 a
-    BF16 S A loses the small singular directions).  Reported: time per call,
-    the row-norm product's time (n d^2 against n d t multiply-adds), and the
-    spread of theta(t) / theta(0), which the JL bound keeps near
-    1 +- sqrt(2/t) per row."""
-    g = torch.Generator(device="cuda:0").manual_seed(seed)
-    v, _ = torch.linalg.qr(torch.randn(d, d, generator=g, device="cuda:0",
-                                       dtype=torch.float64))
-    s = torch.logspace(0, -6, d, dtype=torch.float64, device="cuda:0")
-    w = (s[:, None] * v.T).to(torch.float32)
-    A = torch.randn(n, d, generator=g, device="cuda:0", dtype=torch.float32) @ w
-    hot = torch.randperm(n, generator=g, device="cuda:0")[: n // 20]
-    A[hot] *= 100.0
-    torch.cuda.synchronize()
-    out = {"workload": f"dense FP32 {n} x {d}, r = {r}, m = {m}, sketch f64", "t": t}
-    th = {}
-    for tt in (0, t):
-        for _ in range(warmup):
-            api.leverage_sketch(A, m, r, seed, t=tt)
-        torch.cuda.synchronize()
-        with api.kernel_timing() as kt:
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                res = api.leverage_sketch(A, m, r, seed, t=tt)
-            torch.cuda.synchronize()
-            wall = (time.perf_counter() - t0) / steps
-            stats = kt.stats()
-        rn_ms = stats.get("rownorm", (0.0, 0))[0] / steps
-        k = tt if tt > 0 else d
-        out[f"t{tt}"] = {"ms_per_call": 1e3 * wall, "rownorm_ms": rn_ms,
-                         "rownorm_tflops": 2.0 * n * d * k / (rn_ms * 1e-3) / 1e12
-                         if rn_ms > 0 else None,
-                         "stage_ms": {kk: round(vv[0] / steps, 4)
-                                      for kk, vv in sorted(stats.items())}}
-        th[tt] = res
-    # the sketch alone in the configuration's own precision (BF16 G)
-    for _ in range(warmup):
-        api.sketch_gcs(A, m, r, seed, prec="bf16")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        api.sketch_gcs(A, m, r, seed, prec="bf16")
-    torch.cuda.synchronize()
-    sk = (time.perf_counter() - t0) / steps
-    out["sketch_gcs_bf16"] = {"ms_per_call": 1e3 * sk, "gbs": n * d * 4 / sk / 1e9}
-    ratio = (th[t] / th[0]).cpu().numpy()
-    out["jl_ratio"] = {"min": float(ratio.min()), "max": float(ratio.max()),
-                       "std": float(ratio.std()), "jl_std": float(np.sqrt(2.0 / t))}
-    out["sum_theta_t0"] = float(th[0].sum())
-    del A
+    del reqs
     torch.cuda.empty_cache()
     return out
 
 
-def css_bench(api, torch, A, d, r, seed, steps, warmup):
-    """Column subset selection on the bench matrix with the algorithm's own
-    sketch sizes (m = 2d Gaussian rows; r = d^2 buckets is the bench's r):
-    the first k pivots for k = d/5 and k = d, and Algorithm ls_hrn_exact's
-    leverage scores of the d/5 selected columns, BF16 Gaussian product."""
-    m = 2 * d
-    kk = max(d // 5, 1)
-    calls = {
-        f"css_select_k{kk}": lambda: api.css_select(A, m, r, kk, seed, prec="bf16"),
-        f"css_select_k{d}": lambda: api.css_select(A, m, r, d, seed, prec="bf16"),
-        f"leverage_css_k{kk}": lambda: api.leverage_css(A, m, r, kk, seed, prec="bf16"),
-    }
-    out = {"m": m, "r": r, "prec": "bf16"}
-    for name, f in calls.items():
-        for _ in range(warmup):
-            f()
-        torch.cuda.synchronize()
-        with api.kernel_timing() as kt:
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                f()
-            torch.cuda.synchronize()
-            wall = (time.perf_counter() - t0) / steps
-            stats = kt.stats()
-        out[name] = {"ms_per_call": 1e3 * wall,
-                     "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(stats.items())}}
-    return out
-
-
-def zipf_fp8_bench(api, torch, steps, warmup, n=10_000_000, d=1000, dens=1e-4, r=1_000_000,
-                   m=4000, seed=0):
-    """G*S*A with the FP8 Gaussian product on the Zipf-row CSR configuration
-    (10,000,000 x 1,000 FP32, density 1e-4, Zipf(1.5) row lengths, r = 1e6,
-    m = 4,000), A resident in HBM."""
-    import synth
-    a = synth.csr_zipf(n, d, dens, seed=seed, dtype=np.float32)
-    A = api.CsrMatrix.from_scipy(a, device="cuda:0")
-    for _ in range(warmup):
-        api.sketch_gcs(A, m, r, seed, prec="fp8")
-    torch.cuda.synchronize()
-    with api.kernel_timing() as kt:
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            api.sketch_gcs(A, m, r, seed, prec="fp8")
-        torch.cuda.synchronize()
-        wall = (time.perf_counter() - t0) / steps
-        stats = kt.stats()
-    nbytes = a_bytes(a, "csr")
-    return {"workload": f"CSR {n} x {d} FP32, Zipf rows, nnz {a.nnz}, r = {r}, m = {m}",
-            "ms_per_call": 1e3 * wall, "gbs": nbytes / wall / 1e9, "a_bytes": nbytes,
-            "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(stats.items())}}
-
-
-def direct_bench(api, torch, A, a, b, bd, m, r, seed, steps, warmup, lsqr_resid):
-    """The direct solvers on the same matrix: exact leverage scores and least
-    squares from the Gram matrix, and sketch-and-solve with the bench's
-    sketch (BF16 G), each timed alone, with the quality of its result."""
-    calls = {
-        "leverage_gram": lambda: api.leverage_gram(A),
-        "lsq_gram": lambda: api.lsq_gram(A, bd),
-        "lsq_sketch_solve_bf16": lambda: api.lsq_sketch_solve(A, bd, m, r, seed, prec="bf16"),
-    }
-    out = {}
-    for name, f in calls.items():
-        for _ in range(warmup):
-            f()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            res = f()
-        torch.cuda.synchronize()
-        out[name] = {"ms_per_call": 1e3 * (time.perf_counter() - t0) / steps}
-        v = res.cpu().numpy()
-        if name == "leverage_gram":
-            out[name]["sum_minus_d"] = float(v.sum() - a.shape[1])
-        else:
-            rn = float(np.linalg.norm(b - a @ v))
-            out[name]["resid"] = rn
-            out[name]["resid_vs_lsqr"] = rn / lsqr_resid
-    return out
-
-
-def cpu_baseline(kind, a, b, r, m, seed, budget_s=12.0):
-    """The oracle on the host: every stage in full except the Gaussian GEMM,
-    whose bucket batches (Algorithm countgauss_multiply) are timed on a
-    prefix until ~budget_s and scaled by the batch count."""
+# ---------------------------------------------------------------------------
+# the CPU oracle on a bounded sample of the headline workload
+# ---------------------------------------------------------------------------
+def cpu_baseline(A, seed, rows=500_000, budget_s=8.0):
+    """The oracle's FP64 step on the host: S*A, the Gram matrix and the row
+    norms on the first `rows` rows of the headline matrix (scaled by n/rows),
+    the Gaussian product's bucket batches on a prefix until ~budget_s
+    (scaled by the batch count), and the QR of the m x d sketch in full."""
     from oracle import gram as og
     from oracle import leverage as olev
     from oracle import sketch as osk
-    import scipy.linalg as sla
-    from scipy.sparse.linalg import LinearOperator, lsqr
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
+    n, d, r, m = HEAD["n"], HEAD["d"], HEAD["r"], HEAD["m"]
+    a = A[:rows].cpu().numpy().astype(np.float64)
+    scale = n / rows
     t = {}
     t0 = time.perf_counter()
     sa = osk.sketch_cs(a, r, seed)
-    t["sketch_cs"] = time.perf_counter() - t0
+    t["sketch_cs"] = (time.perf_counter() - t0) * scale
     batch = 4096
     nb = (r + batch - 1) // batch
-    c = np.zeros((m, sa.shape[1]))
+    c = np.zeros((m, d))
     t0 = time.perf_counter()
     done = 0
     for b0 in range(0, r, batch):
-        b1 = min(r, b0 + batch)
-        c += osk.gaussian_block(m, b0, b1, seed) @ sa[b0:b1]
+        c += osk.gaussian_block(m, b0, min(r, b0 + batch), seed) @ sa[b0:b0 + batch]
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
     t["gauss_gemm"] = (time.perf_counter() - t0) * nb / done
     t0 = time.perf_counter()
     og.gram(1.0, a)
-    t["gram"] = time.perf_counter() - t0
+    t["gram"] = (time.perf_counter() - t0) * scale
     t0 = time.perf_counter()
-    rr = olev.qr_r(c)  # C from the sampled batches: same shape, same QR cost
+    rr = olev.qr_r(c)
     ri = olev.tri_inv(rr)
     t["qr"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    n = a.shape[0]
-    for i0 in range(0, n, 200_000):
-        og.rownorms_sq(1.0, a[i0:i0 + 200_000], ri)
-    t["rownorms"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    op = LinearOperator(a.shape, matvec=lambda y: a @ (ri @ y),
-                        rmatvec=lambda u: ri.T @ (a.T @ u), dtype=np.float64)
-    y = lsqr(op, b, atol=1e-14, btol=1e-14, iter_lim=100)[0]
-    _ = ri @ y
-    t["lsq"] = time.perf_counter() - t0
+    og.rownorms_sq(1.0, a, ri)
+    t["rownorms"] = (time.perf_counter() - t0) * scale
     total = sum(t.values())
-    sample = (f"all stages in full except the Gaussian GEMM: {done} of {nb} bucket "
-              f"batches of {batch} timed and scaled")
+    sample = (f"first {rows} of {n} rows for S*A, Gram and row norms (times scaled by "
+              f"{scale:.0f}); {done} of {nb} Gaussian bucket batches of {batch} timed and "
+              f"scaled; QR of the {m} x {d} sketch in full")
     return total, cores, sample, t
 
 
@@ -432,23 +538,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="csr-1e6x500", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="all", choices=["f64", "bf16", "fp8", "all"],
-                    help="Gaussian GEMM precision; 'all' times the FP64 plain path, "
-                         "the BF16 path and the FP8 path and reports BF16 as the "
-                         "headline")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serving", action="store_true",
-                    help="skip the request-server measurement")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the Gaussian-only sketch, direct-solver, column-selection, Zipf FP8, JL "
-                         "leverage measurements "
-                         "(hardware-counter runs: one workload per kernel)")
+                    help="the headline step only (hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="instead of the benchmark, run 4 elementwise copies of MIB "
-                         "MiB (FP64) whose HBM bytes are known, to scale hardware "
-                         "FETCH_SIZE / WRITE_SIZE counters")
+                    help="instead of the benchmark, run 4 elementwise copies of MIB MiB "
+                         "(FP64) whose HBM bytes are known, to scale hardware FETCH_SIZE / "
+                         "WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -456,6 +554,7 @@ def main():
         sys.exit(2)
 
     import torch
+    import synth
     from paper_2203_02798_amd import api
 
     if args.copy_calibration:
@@ -469,128 +568,15 @@ def main():
                                                "launches": 4}}), flush=True)
         return
 
-    log(f"generating workload {args.workload}")
-    kind, a, b, r, m = make_inputs(args.workload)
-    n, d = a.shape
-    nbytes = a_bytes(a, kind)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if kind == "csr":
-        A = api.CsrMatrix.from_scipy(a, device=dev)
-    else:
-        A = torch.from_numpy(a).to(dev)
-    bd = torch.from_numpy(b).to(dev)
-    torch.cuda.synchronize()
-
+    torch.cuda.set_device(0)
     seed = args.seed
-
-    def run_path(prec):
-        def step():
-            C = api.sketch_gcs(A, m, r, seed, prec=prec)
-            Gm = api.gram(A)
-            R, Ri = api.sketch_qr(C)
-            th = api.rownorms_sq(A, Ri)
-            x, info = api.lsq_solve(A, bd, Rinv=Ri, max_iter=200, refine=1, check_every=8)
-            return C, Gm, th, x, info
-
-        log(f"[{prec}] warmup {args.warmup}")
-        for _ in range(args.warmup):
-            out = step()
-        torch.cuda.synchronize()
-        log(f"[{prec}] timing {args.steps} steps")
-        lat = []
-        stream = torch.cuda.current_stream(dev)
-        # inside the timed steps only the Gaussian product is bracketed (the
-        # roofline's launch time); every bracket costs host time, so the
-        # per-stage breakdown comes from two further steps afterwards
-        with api.kernel_timing(only=("gauss_gemm",)) as kt:
-            torch.cuda.synchronize()
-            t_start = time.perf_counter()
-            for _ in range(args.steps):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                out = step()
-                e1.record(stream)
-                e1.synchronize()
-                lat.append(e0.elapsed_time(e1))
-            torch.cuda.synchronize()
-            t_total = time.perf_counter() - t_start
-            gg_ms, gg_n = kt.stats().get("gauss_gemm", (0.0, 0))
-        n_stage = 2
-        with api.kernel_timing() as kt:
-            for _ in range(n_stage):
-                step()
-            torch.cuda.synchronize()
-            stats = kt.stats()
-        info = out[4]
-        lat = np.array(lat)
-        per = {k: v[0] / n_stage for k, v in stats.items()}
-        sketch_ms = sum(per.get(k, 0.0) for k in ("cs_bin", "cs_scatter", "sa_limbs",
-                                                   "sa_quant", "gauss_gemm", "gemm_reduce"))
-        # residual of the returned solution, for the FP64-vs-BF16 comparison
-        x = out[3].cpu().numpy()
-        res = float(np.linalg.norm(b - a @ x))
-        return {
-            "value": nbytes * args.steps / t_total / 1e9,
-            "ms_per_step": 1e3 * t_total / args.steps,
-            "solves_per_s": args.steps / t_total,
-            "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)),
-            "sketch_gcs_gbs": nbytes / (sketch_ms * 1e-3) / 1e9 if sketch_ms > 0 else None,
-            "stage_ms": {k: round(v, 4) for k, v in sorted(per.items())},
-            "lsq": {"iters": info["iters"], "status": info["status"], "resid": res},
-            "gg_avg_ms": gg_ms / max(gg_n, 1),
-            "sparse_product": "sa_entries" in stats,
-        }
-
-    paths = [args.prec] if args.prec != "all" else ["f64", "bf16", "fp8"]
-    res = {p: run_path(p) for p in paths}
-    head = "bf16" if "bf16" in res else paths[0]
-    hr = res[head]
-    flops = (2.0 * r - 1.0) * m * d
-    gg_avg = hr["gg_avg_ms"]
-    if hr["sparse_product"] and head == "bf16":
-        # k_gauss_sparse: bound by the VALU work of drawing G (m r samples)
-        # plus one FMA per (row of G, nonzero of S*A)
-        if kind == "csr":
-            h, _ = api.cs_hash(n, r, seed, device=dev)
-            rows = np.repeat(np.arange(n), np.diff(a.indptr))
-            keys = h.cpu().numpy().astype(np.int64)[rows] * d + a.indices
-            nnz_sa = int(np.unique(keys).size)
-        else:
-            nnz_sa = r * d
-        ops = m * r * VALU_OPS_PER_SAMPLE_BF16 + m * nnz_sa
-        achieved = ops / (gg_avg * 1e-3) / 1e12 if gg_avg > 0 else 0.0
-        roof = {"bound": "alu", "kernel": "k_gauss_sparse", "achieved": achieved,
-                "peak": PEAK_VALU_TOPS, "unit": "T VALU lane-ops/s",
-                "frac": achieved / PEAK_VALU_TOPS,
-                "traffic": pmc_traffic(args.workload, head),
-                "traffic_unit": "bytes per launch", "launch_ms": gg_avg,
-                "ops_per_launch": ops, "samples_per_launch": m * r,
-                "valu_ops_per_sample": VALU_OPS_PER_SAMPLE_BF16,
-                "nnz_sa": nnz_sa, "fma_per_launch": m * nnz_sa}
-    else:
-        peak = {"f64": PEAK_FP64_TFLOPS, "bf16": PEAK_BF16_TFLOPS,
-                "fp8": PEAK_FP8_TFLOPS}[head]
-        achieved = flops / (gg_avg * 1e-3) / 1e12 if gg_avg > 0 else 0.0
-        roof = {"bound": "mfma", "kernel": "gauss_gemm", "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "traffic_unit": "bytes per launch",
-                "launch_ms": gg_avg, "flops_per_launch": flops}
-    # the rates this device sustains (ceiling probes), beside the datasheet's
-    ceil = None
-    if not args.no_extras:
-        log("ceiling probes: copy, FP64 MFMA, VALU")
-        ceil = api.measure_ceilings(dev)
-        if roof["bound"] == "alu":
-            roof["measured_peak"] = ceil["valu_Tops"]
-        elif head == "f64":
-            roof["measured_peak"] = ceil["fp64_mfma_TFs"]
-        if "measured_peak" in roof:
-            roof["frac_measured"] = roof["achieved"] / roof["measured_peak"]
+    n, d, r, m = HEAD["n"], HEAD["d"], HEAD["r"], HEAD["m"]
+    log(f"generating the dense coherent FP32 {n} x {d} matrix on the device")
+    A = synth.dense_coherent_torch(n, d, seed=seed, smin=HEAD["smin"], device="cuda:0")
+    torch.cuda.synchronize()
+    hr = headline(api, torch, A, args.steps, args.warmup, seed)
     rec = {
-        "metric": "GB/s of A sketched (G·S·A) + LSQ solves/s, p50/p99 latency vs FP64 plain path",
+        "metric": METRIC,
         "value": hr["value"],
         "unit": "GB/s",
         "n_gpus": 1,
@@ -600,77 +586,59 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": head,
-        "dtype_detail": {"bf16": "Gaussian product with bf16 G and S*A as two bf16 limbs, "
-                                 "fp32 accumulation; hash, S*A, Gram, QR, row norms and "
-                                 "LSQR in f64",
-                         "fp8": "Gaussian GEMM fp8 e4m3 operands (per-128 E8M0 scales) "
-                                "with fp32 accumulation; the rest in f64",
-                         "f64": "f64 throughout"}[head],
+        "dtype": "f64",
+        "dtype_detail": "FP64 throughout: S*A summed in FP64 from the FP32 entries, G and "
+                        "the Gaussian product, Gram, QR and row norms in FP64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "d": d,
-                   "nnz": int(a.nnz) if kind == "csr" else n * d,
-                   "density": WORKLOADS[args.workload][3], "r": r, "m": m,
-                   "a_bytes": nbytes, "parallelism": "single-gpu"},
-        "solves_per_s": hr["solves_per_s"],
+        "config": {"workload": "dense-4e6x256", "n": n, "d": d, "a_dtype": "f32",
+                   "structure": "singular values geometric 1 .. 1e-6, 5% of rows x100",
+                   "r": r, "m": m, "a_bytes": n * d * 4, "parallelism": "single-gpu",
+                   "step": "sketch_gcs (f64) + gram + sketch_qr + rownorms_sq"},
         "p50_ms": hr["p50_ms"],
         "p99_ms": hr["p99_ms"],
         "sketch_gcs_gbs": hr["sketch_gcs_gbs"],
         "stage_ms": hr["stage_ms"],
-        "lsq": hr["lsq"],
-        "roofline": roof,
+        "scatter_hbm": hr["scatter_hbm"],
+        "kernels": hr["kernels"],
+        "roofline": hr["roofline"],
     }
-    if ceil is not None:
-        rec["ceilings"] = {**ceil, "datasheet": {"hbm_GBs": 8000.0,
+    if not args.no_extras:
+        log("BF16 / FP8 sketches of the headline matrix and their delta")
+        rec["reduced_sketches"] = reduced_sketches(api, torch, A, args.steps, args.warmup, seed)
+        log("leverage scores with the JL step")
+        rec["leverage_jl"] = leverage_jl(api, torch, A, args.steps, args.warmup, seed)
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        tot, cores, sample, parts = cpu_baseline(A, seed)
+        rec["cpu_baseline"] = {"value": n * d * 4 / tot / 1e9, "unit": "GB/s", "cores": cores,
+                               "kind": "oracle", "sample": sample,
+                               "stage_s": {k: round(v, 3) for k, v in parts.items()}}
+    del A
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("ceiling probes")
+        ceil = api.measure_ceilings("cuda:0")
+        rec["ceilings"] = {**ceil, "datasheet": {"hbm_GBs": PEAK_HBM_GBS,
                                                  "fp64_mfma_TFs": PEAK_FP64_TFLOPS,
                                                  "bf16_mfma_TFs": PEAK_BF16_TFLOPS,
                                                  "fp8_mfma_TFs": PEAK_FP8_TFLOPS,
-                                                 "valu_Tops": PEAK_VALU_TOPS},
-                           "probes": "psk_probe_copy (1 GiB read + 1 GiB written), "
-                                     "psk_probe_mfma_f64, psk_probe_mfma_lowp (bf16, fp8), "
-                                     "psk_probe_valu_f32; best of 3"}
-    keys = ("value", "ms_per_step", "solves_per_s", "p50_ms", "p99_ms", "sketch_gcs_gbs",
-            "stage_ms", "lsq")
-    if head != "f64" and "f64" in res:
-        f = res["f64"]
-        rec["fp64_path"] = {k: f[k] for k in keys}
-        rec["speedup_vs_fp64_path"] = f["ms_per_step"] / hr["ms_per_step"]
-    if head != "fp8" and "fp8" in res:
-        f = res["fp8"]
-        rec["fp8_path"] = {k: f[k] for k in keys}
-        gg = f["gg_avg_ms"]
-        rec["fp8_path"]["gauss_gemm_roofline"] = {
-            "achieved": flops / (gg * 1e-3) / 1e12 if gg > 0 else 0.0,
-            "peak": PEAK_FP8_TFLOPS, "unit": "TFLOP/s",
-            "frac": (flops / (gg * 1e-3) / 1e12) / PEAK_FP8_TFLOPS if gg > 0 else 0.0}
-        if ceil is not None and gg > 0:
-            g8 = rec["fp8_path"]["gauss_gemm_roofline"]
-            g8["measured_peak"] = ceil["fp8_mfma_TFs"]
-            g8["frac_measured"] = g8["achieved"] / ceil["fp8_mfma_TFs"]
-    if head == "bf16" and kind == "csr" and not args.no_extras:
-        rec["gaussian_only"] = gaussian_only_bench(api, torch, A, m, n, d, int(a.nnz), seed,
-                                                   args.steps, args.warmup)
-        rec["direct"] = direct_bench(api, torch, A, a, b, bd, m, r, seed, args.steps,
-                                     args.warmup, hr["lsq"]["resid"])
-        rec["css"] = css_bench(api, torch, A, d, r, seed, args.steps, args.warmup)
-        log("FP8 sketch of the Zipf CSR 10,000,000 x 1,000")
-        rec["zipf_fp8"] = zipf_fp8_bench(api, torch, args.steps, args.warmup)
-        log("leverage scores with the JL step, dense FP32 4,000,000 x 256")
-        rec["leverage_jl"] = leverage_jl_bench(api, torch, args.steps, args.warmup)
-        if ceil is not None:
-            for tt in ("t0", f"t{rec['leverage_jl']['t']}"):
-                tf = rec["leverage_jl"][tt]["rownorm_tflops"]
-                if tf:
-                    rec["leverage_jl"][tt]["rownorm_frac"] = tf / PEAK_FP64_TFLOPS
-                    rec["leverage_jl"][tt]["rownorm_frac_measured"] = tf / ceil["fp64_mfma_TFs"]
+                                                 "valu_Tops": PEAK_VALU_TOPS}}
+        log("small dense workload latency")
+        rec["small_dense"] = small_latency(api, torch)
+        log("sparse workload CSR 1e6 x 500")
+        csr, Ac, ac, bc, bdc = csr_workload(api, torch, args.steps, args.warmup, seed)
+        csr["gaussian_only"] = gaussian_only(api, torch, Ac, 2000, seed, args.steps, args.warmup)
+        csr["direct"] = direct_bench(api, torch, Ac, ac, bc, bdc, 2000, 250_000, seed,
+                                     args.steps, args.warmup)
+        csr["css"] = css_bench(api, torch, Ac, 500, 250_000, seed, args.steps, args.warmup)
+        rec["csr_1e6x500"] = csr
+        del Ac, bdc
+        torch.cuda.empty_cache()
+        log("Zipf CSR 1e7 x 1000 FP32")
+        rec["zipf_1e7x1000"] = zipf_workload(api, torch, args.steps, args.warmup, seed)
+        torch.cuda.empty_cache()
     if not args.no_serving:
-        rec["serving"] = serving_bench(api, torch, dev)
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        tot, cores, sample, parts = cpu_baseline(kind, a, b, r, m, seed)
-        rec["cpu_baseline"] = {"value": nbytes / tot / 1e9, "unit": "GB/s", "cores": cores,
-                               "kind": "oracle", "sample": sample,
-                               "stage_s": {k: round(v, 3) for k, v in parts.items()}}
+        rec["serving"] = serving_bench(api, torch)
     print(json.dumps(rec), flush=True)
 
 

@@ -549,6 +549,7 @@ int bres_launch(const psk_mat &Am, const double *B, int64_t k, double *part, int
   const int64_t need = ceil_div(tiles, (int64_t)8);  // 8 wavefronts per workgroup
   while (groups > 8 && groups / 2 >= need) groups /= 2;
   const unsigned nblk = (unsigned)(groups * tn);
+  KTimer timer("rownorm", st);
   k_rownorm_bres<TA, PAIR, VEC><<<nblk, kBresThreads, lds, st>>>(
       (const TA *)Am.values, Am.ld, n, d, B, k, tn, part);
   return 0;
@@ -590,9 +591,12 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
     double *part = ws.take<double>((size_t)tn * n);
     if (ws.dry()) return 0;
     if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for row norms");
-    k_dgemm<TA, double, false, false, 2, 2, 1, 2, EPI_ROWNORM, false>
-        <<<(unsigned)((int64_t)tm * tn), 256, 0, st>>>(n, k, d, A, Am.ld, B, k, tm, tn, d,
-                                                       part, n, 1.0, 0.0);
+    {
+      KTimer timer("rownorm", st);
+      k_dgemm<TA, double, false, false, 2, 2, 1, 2, EPI_ROWNORM, false>
+          <<<(unsigned)((int64_t)tm * tn), 256, 0, st>>>(n, k, d, A, Am.ld, B, k, tm, tn, d,
+                                                         part, n, 1.0, 0.0);
+    }
     k_rownorm_reduce<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(part, n, tn, alpha,
                                                                   beta, x);
   } else {
@@ -601,9 +605,12 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
     double *part = ws.take<double>((size_t)tn * n);
     if (ws.dry()) return 0;
     if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for row norms");
-    k_dgemm<TA, double, false, false, 2, 2, 1, 8, EPI_ROWNORM, false>
-        <<<(unsigned)((int64_t)tm * tn), 256, 0, st>>>(n, k, d, A, Am.ld, B, k, tm, tn, d,
-                                                       part, n, 1.0, 0.0);
+    {
+      KTimer timer("rownorm", st);
+      k_dgemm<TA, double, false, false, 2, 2, 1, 8, EPI_ROWNORM, false>
+          <<<(unsigned)((int64_t)tm * tn), 256, 0, st>>>(n, k, d, A, Am.ld, B, k, tm, tn, d,
+                                                         part, n, 1.0, 0.0);
+    }
     k_rownorm_reduce<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(part, n, tn, alpha,
                                                                   beta, x);
   }
@@ -777,12 +784,16 @@ int gram_syrk_launch(double alpha, const psk_mat &Am, double beta, void *C, bool
   nblk = ceil_div(nblk, (int64_t)8) * 8;  // whole XCD rounds for the remap
   const uintptr_t addr = (uintptr_t)Am.values;
   const bool vec = (Am.ld % 4 == 0) && (d % 4 == 0) && (addr % 16 == 0);
-  if (vec)
-    k_gram_syrk<TA, true><<<(unsigned)nblk, 256, 0, st>>>((const TA *)Am.values, Am.ld, n, d, T,
-                                                          U, slabs, rows_per, part);
-  else
-    k_gram_syrk<TA, false><<<(unsigned)nblk, 256, 0, st>>>((const TA *)Am.values, Am.ld, n, d,
-                                                           T, U, slabs, rows_per, part);
+  {
+    KTimer timer("gram", st);
+    if (vec)
+      k_gram_syrk<TA, true><<<(unsigned)nblk, 256, 0, st>>>((const TA *)Am.values, Am.ld, n, d,
+                                                            T, U, slabs, rows_per, part);
+    else
+      k_gram_syrk<TA, false><<<(unsigned)nblk, 256, 0, st>>>((const TA *)Am.values, Am.ld, n, d,
+                                                             T, U, slabs, rows_per, part);
+  }
+  KTimer rtimer("gram_reduce", st);
   const int64_t dd = d * d;
   dim3 g1((unsigned)ceil_div(dd, (int64_t)256), kGramGroups);
   k_gram_reduce1<<<g1, 256, 0, st>>>(part, d, T, U, slabs, gpart);
@@ -820,14 +831,12 @@ int dgemm(bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
 
 int gram_dense(double alpha, const psk_mat &A, double beta, void *C, Arena &ws,
                hipStream_t st, bool out_f64) {
-  KTimer timer("gram", st, !ws.dry());
   if (A.dtype == PSK_F32) return gram_syrk_launch<float>(alpha, A, beta, C, !out_f64, ws, st);
   return gram_syrk_launch<double>(alpha, A, beta, C, false, ws, st);
 }
 
 int rownorms_dense(double alpha, const psk_mat &A, const double *B, int64_t k,
                    double beta, double *x, Arena &ws, hipStream_t st) {
-  KTimer timer("rownorm", st, !ws.dry());
   if (A.dtype == PSK_F32) return rownorm_launch<float>(A, B, k, alpha, beta, x, ws, st);
   return rownorm_launch<double>(A, B, k, alpha, beta, x, ws, st);
 }

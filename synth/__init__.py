@@ -237,3 +237,50 @@ def serving_trace(num, seed=0, n_lo=1e4, n_hi=1e6, dims=(32, 64, 128, 256),
     return [dict(id=k, n=int(n[k]), d=int(d[k]), cond=float(cond[k]),
                  t_arrive=float(t[k]), seed=seed * 100003 + k)
             for k in range(num)]
+
+
+def dense_coherent_torch(n, d, seed=0, smin=1e-6, frac_scaled=0.05, scale=100.0,
+                         device="cuda:0"):
+    """The coherent dense structure drawn on the device (torch), FP32:
+    A = D Z diag(s) V^T with Z an n x d N(0, 1) matrix (not orthogonalised:
+    its condition number is 1 + O(sqrt(d/n))), V the Q factor of a d x d
+    Gaussian, s geometric from 1 to ``smin``, and D scaling
+    ``floor(frac_scaled*n)`` uniformly chosen rows by ``scale``.  For the
+    large configurations whose host generation would take minutes."""
+    import torch
+    g = torch.Generator(device=device).manual_seed(seed)
+    v, _ = torch.linalg.qr(torch.randn(d, d, generator=g, device=device, dtype=torch.float64))
+    sv = torch.logspace(0.0, float(np.log10(smin)), d, dtype=torch.float64, device=device)
+    w = (sv[:, None] * v.T).to(torch.float32)
+    a = torch.randn(n, d, generator=g, device=device, dtype=torch.float32) @ w
+    hot = torch.randperm(n, generator=g, device=device)[: int(np.floor(frac_scaled * n))]
+    a[hot] *= scale
+    return a
+
+
+def lsq_trace_torch(num, seed, n_lo, n_hi, d_choices=(32, 64, 128, 256), cond_hi=1e8,
+                    noise=1e-3, device="cuda:0"):
+    """Least-squares requests drawn on the device: n log-uniform in [n_lo,
+    n_hi], d uniform over d_choices, condition number log-uniform in
+    [1, cond_hi]; A = X diag(s) V^T with X ~ N(0,1)/sqrt(n), V the Q factor of
+    a Gaussian, s geometric from 1 to 1/cond; b = A x + noise * e.  Request
+    k is seeded by (seed, k)."""
+    import torch
+    rng = _rng(seed)
+    reqs = []
+    for k in range(num):
+        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+        d = int(rng.choice(list(d_choices)))
+        cond = float(np.exp(rng.uniform(0.0, np.log(cond_hi))))
+        g = torch.Generator(device=device)
+        g.manual_seed(seed * 100003 + k)
+        x = torch.randn(n, d, generator=g, device=device, dtype=torch.float64) / n ** 0.5
+        v, _ = torch.linalg.qr(torch.randn(d, d, generator=g, device=device,
+                                           dtype=torch.float64))
+        sv = torch.logspace(0.0, -np.log10(cond), d, device=device, dtype=torch.float64)
+        a = ((x * sv) @ v.T).contiguous()
+        del x
+        xt = torch.randn(d, generator=g, device=device, dtype=torch.float64)
+        b = a @ xt + noise * torch.randn(n, generator=g, device=device, dtype=torch.float64)
+        reqs.append(dict(a=a, b=b, n=n, d=d, cond=cond, seed=k))
+    return reqs
