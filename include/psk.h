@@ -267,6 +267,23 @@ int sketch_qr(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
 int sketch_delta(const double *Chat, const double *C, int64_t m, int64_t d, double *delta,
                  void *ws, size_t ws_bytes, void *stream);
 
+/* sketch_qr without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops and harnesses
+ * that forbid allocation): the same computation and the same results as
+ * sketch_qr, with the scratch in a static device array of
+ * PSK_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends (its address is looked up once per device, on the first call
+ * there).  Nothing is allocated by the call.  Every call on a GPU uses that
+ * GPU's one array: calls that overlap on one GPU (other threads, other
+ * streams) race and must be serialised by the caller.  The array keeps the
+ * last call's contents; the call sets every part it reads first.
+ * Errors: as sketch_qr, plus PSK_EUNSUPPORTED when m x d needs more scratch
+ * than PSK_NOALLOC_SCRATCH_BYTES (about 2 m d + 11 d^2 doubles: e.g. m = 2000,
+ * d = 500 fits), PSK_EDEVICE if the array's address cannot be found. */
+#define PSK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int sketch_qr_noalloc(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
+                      void *stream);
+
 /* Options and report of lsq_solve. */
 typedef struct psk_lsq_opts {
   const double *Rinv; /* optional d x d row-major FP64 R^{-1} of a   *

@@ -23,6 +23,7 @@ PSK_REQ_LSQ, PSK_REQ_LEVERAGE = 0, 1
 PSK_DENSE, PSK_CSR = 0, 1
 PSK_F64, PSK_F32 = 0, 1
 PSK_PROBE_BLOCKS = 4096
+PSK_NOALLOC_SCRATCH_BYTES = 64 << 20
 PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 (PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
  PSK_OP_LSQ, PSK_OP_SKETCH_G, PSK_OP_LEVERAGE_GRAM, PSK_OP_LSQ_GRAM,
@@ -32,7 +33,7 @@ PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq", "sketch_qr",
             "lsq_solve", "leverage_sketch", "css_select", "leverage_css", "leverage_gram",
-            "lsq_gram", "lsq_sketch_solve", "sketch_delta",
+            "lsq_gram", "lsq_sketch_solve", "sketch_delta", "sketch_qr_noalloc",
             "psk_probe_copy", "psk_probe_mfma_f64", "psk_probe_mfma_lowp",
             "psk_probe_valu_f32",
             "psk_timing_enable", "psk_timing_only", "psk_timing_reset",
@@ -158,6 +159,7 @@ _SIGS = {
     "rownorms_sq": ([_dbl, _PM, _vp, _i64, _dbl, _vp, _vp, ctypes.c_size_t, _vp],
                     ctypes.c_int),
     "sketch_qr": ([_vp, _i64, _i64, _vp, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "sketch_qr_noalloc": ([_vp, _i64, _i64, _vp, _vp, _vp], ctypes.c_int),
     "lsq_solve": ([_PM, _vp, _vp, ctypes.POINTER(PskLsqOpts), ctypes.POINTER(PskLsqInfo),
                    _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "leverage_sketch": ([_PM, _i64, _i64, _i64, _u64, ctypes.c_int, _vp, _vp, ctypes.c_size_t,

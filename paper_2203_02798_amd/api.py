@@ -292,6 +292,22 @@ def sketch_qr(C):
     return R, Ri
 
 
+def sketch_qr_noalloc(C, R=None, Rinv=None):
+    """(R, R^{-1}) as sketch_qr, with the library's static scratch instead of
+    a workspace (no device allocation inside the call; R and Rinv may be
+    passed in preallocated)."""
+    C = C.contiguous()
+    m, d = C.shape
+    dev = C.device
+    if R is None:
+        R = torch.empty((d, d), dtype=torch.float64, device=dev)
+    if Rinv is None:
+        Rinv = torch.empty((d, d), dtype=torch.float64, device=dev)
+    L.check(L.lib().sketch_qr_noalloc(C.data_ptr(), m, d, R.data_ptr(), Rinv.data_ptr(),
+                                      _stream(dev)), "sketch_qr_noalloc")
+    return R, Rinv
+
+
 _PREC_NAME = {L.PSK_PREC_F64: "f64", L.PSK_PREC_BF16: "bf16", L.PSK_PREC_FP8: "fp8", -1: None}
 
 
