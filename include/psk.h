@@ -30,13 +30,29 @@
  *   owned by the caller; the library never frees them and never allocates
  *   device memory.  Scratch space is passed in as (ws, ws_bytes); its minimum
  *   size comes from psk_workspace_size().  Its contents on entry do not matter.
- * - `stream` is a hipStream_t (NULL = the default stream).  Every call only
- *   enqueues work on that stream and returns; outputs are valid once the
- *   stream has reached that point.  lsq_solve is the one exception: it
- *   synchronises the stream to test convergence (documented there).
- * - Every call returns PSK_OK (0) or a negative psk_status; on error no work
- *   has been enqueued (argument checks happen first) unless the status is
- *   PSK_EDEVICE.  psk_last_error() gives a message for the calling thread.
+ * - `stream` is a hipStream_t (NULL = the default stream).  A call on dense A
+ *   only enqueues work on that stream and returns; outputs are valid once
+ *   the stream has reached that point.  Three things synchronise the stream
+ *   inside a call: the structure check of a CSR A (below), the rank and
+ *   finiteness checks of the calls that factor (lsq_solve, lsq_sketch_solve,
+ *   lsq_gram, leverage_gram, leverage_sketch, css_select, leverage_css) and
+ *   lsq_solve's convergence tests.
+ * - A CSR A is validated on the device before any kernel walks it: offsets
+ *   from 0 to nnz, never decreasing, column indices in [0, d) (the CSR
+ *   definition of Section 1).  One pass reads indptr and indices once; a
+ *   malformed A returns PSK_EINVAL with nothing else enqueued.  The stored
+ *   values are not part of this check (psk_check tests them on request).
+ * - Non-finite input: NaN and infinities propagate through the sums and
+ *   products of the stream-ordered calls (IEEE arithmetic) into their
+ *   outputs.  The calls that factor a sketch or a Gram matrix return
+ *   PSK_ENONFINITE when a pivot of the factorization, a squared row norm
+ *   they produce or LSQR's residual estimate is not finite: A or b held a
+ *   NaN or an infinity, or a sum overflowed.
+ * - Every call returns PSK_OK (0) or a negative psk_status; on an argument
+ *   error no work has been enqueued (argument checks happen first).  After
+ *   PSK_EDEVICE, PSK_ERANK, PSK_ENONFINITE or PSK_ENOCONV the call's outputs
+ *   are unspecified unless its comment says otherwise.  psk_last_error()
+ *   gives a message for the calling thread.
  * - Results are deterministic: identical inputs give bit-identical outputs,
  *   independent of other work on the device.  No floating-point atomic
  *   touches global memory; reduction orders across workgroups and K splits
@@ -77,6 +93,7 @@ typedef enum {
   PSK_ENOCONV = -5,      /* lsq_solve reached max_iter before its tolerance   */
   PSK_ERANK = -6,        /* sketch numerically rank deficient (R_jj tiny)     */
   PSK_EUNSUPPORTED = -7, /* shape outside the limits documented per call      */
+  PSK_ENONFINITE = -8,   /* NaN or infinity in the input or a factorization   */
   PSK_PENDING = 1        /* psk_server_poll: the request has not finished yet */
 } psk_status;
 
@@ -90,8 +107,9 @@ enum { PSK_F64 = 0, PSK_F32 = 1 };     /* psk_mat.dtype  */
  *        indices[k] in [0, d) and value values[k].  Columns inside a row may be
  *        in any order.  Duplicate columns inside a row are summed, but then
  *        bit-reproducibility of the affected outputs is not guaranteed.
- *        indptr[0] must be 0 and indptr[n] == nnz (checked on the host from
- *        the descriptor only; row contents are trusted). */
+ *        indptr[0] must be 0, indptr never decreasing, indptr[n] == nnz;
+ *        every call checks this and the index range on the device before
+ *        use (PSK_EINVAL). */
 typedef struct psk_mat {
   int32_t format;          /* PSK_DENSE or PSK_CSR              */
   int32_t dtype;           /* PSK_F64 or PSK_F32                */
@@ -143,7 +161,8 @@ enum {
   PSK_OP_LEVERAGE_SKETCH = 10,
   PSK_OP_CSS = 11,
   PSK_OP_LEVERAGE_CSS = 12,
-  PSK_OP_DELTA = 13
+  PSK_OP_DELTA = 13,
+  PSK_OP_CHECK = 14
 };
 
 /* Library version string (static storage). */
@@ -236,6 +255,18 @@ int gram(double alpha, const psk_mat *A, double beta, void *C,
 int rownorms_sq(double alpha, const psk_mat *A, const double *B, int64_t k,
                 double beta, double *x, void *ws, size_t ws_bytes,
                 void *stream);
+
+/* Validity of a matrix operand, as every call checks it and more: for CSR A
+ * the structure of the CSR definition (Section 1 notation: indptr[0] == 0,
+ * indptr never decreasing, indptr[n] == nnz, 0 <= indices[k] < d); with
+ * check_values != 0 also every stored value (CSR) or every element
+ * (dense, n x d at stride ld) finite.  One pass over indptr, indices (and
+ * values) on `stream`, then a synchronisation to read the result.
+ *   ws : psk_workspace_size(PSK_OP_CHECK) bytes (a result word).
+ * Returns PSK_OK, PSK_EINVAL (malformed CSR; checked before values),
+ * PSK_ENONFINITE (a NaN or an infinity), or as the descriptor checks of the
+ * other calls.  Dense A with check_values == 0 returns PSK_OK at once. */
+int psk_check(const psk_mat *A, int check_values, void *ws, size_t ws_bytes, void *stream);
 
 /* R and R^{-1} of an FP64 sketch C (m x d row-major, m >= d): C = Q*R with R
  * upper triangular, diag(R) > 0.  Computed by shifted Cholesky-QR (three
@@ -338,7 +369,9 @@ typedef struct psk_lsq_info {
  * convergence flag is copied to pinned host memory (a few pinned bytes per
  * concurrent solve, kept for the life of the process) and read while the
  * next group runs.  The call returns with the stream idle.
- * Errors: PSK_EINVAL, PSK_ENOMEM, PSK_ENOCONV (x still written), PSK_ERANK. */
+ * Errors: PSK_EINVAL, PSK_ENOMEM, PSK_ENOCONV (x still written), PSK_ERANK,
+ * PSK_ENONFINITE (a pivot of the sketch's factorization, or LSQR's norms
+ * read at a convergence test, not finite). */
 int lsq_solve(const psk_mat *A, const double *b, double *x,
               const psk_lsq_opts *opts, psk_lsq_info *info,
               void *ws, size_t ws_bytes, void *stream);
@@ -364,7 +397,7 @@ int lsq_solve(const psk_mat *A, const double *b, double *x,
  * NULL theta), PSK_EDTYPE
  * (prec, when m > 0), PSK_EUNSUPPORTED (d > 4096; as sketch_cs), PSK_ENOMEM,
  * PSK_ERANK (a Cholesky pivot of the factorization was not positive; theta
- * is still written). */
+ * is still written), PSK_ENONFINITE (a pivot or a score not finite). */
 int leverage_sketch(const psk_mat *A, int64_t m, int64_t r, int64_t t, uint64_t seed, int prec,
                     double *theta, void *ws, size_t ws_bytes, void *stream);
 
@@ -381,8 +414,10 @@ int leverage_sketch(const psk_mat *A, int64_t m, int64_t r, int64_t t, uint64_t 
 /* cols[0..k) = the first k pivots of the pivoted QR of B, in order (Algorithm
  * cgrrqr: the "top-k" columns of A).
  *   cols : k int32 (device, written).
+ * The sketch is checked for NaN and infinities first (one synchronisation).
  * Errors: PSK_EINVAL (shapes, k out of range, NULL cols), PSK_EDTYPE (prec,
- * when m > 0), PSK_EUNSUPPORTED (d > 4096; as sketch_cs), PSK_ENOMEM. */
+ * when m > 0), PSK_EUNSUPPORTED (d > 4096; as sketch_cs), PSK_ENOMEM,
+ * PSK_ENONFINITE (the sketch not finite; no pivot chosen). */
 int css_select(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,
                int32_t *cols, void *ws, size_t ws_bytes, void *stream);
 
@@ -394,7 +429,7 @@ int css_select(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t seed,
  *   NULL.
  * The call synchronises the stream once, to read the pivot flag.
  * Errors: as css_select, plus PSK_ERANK (A[:, K] numerically rank deficient;
- * theta still written). */
+ * theta still written), PSK_ENONFINITE (a pivot or a score not finite). */
 int leverage_css(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t seed, int prec,
                  double *theta, int32_t *cols, void *ws, size_t ws_bytes, void *stream);
 
@@ -412,14 +447,16 @@ int leverage_css(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t see
  * R and rownorms_sq(A, R^{-1}).  B squares the condition number: the scores
  * carry an error of about cond(A)^2 u.
  *   theta : n FP64 (device, written).
- * Errors: PSK_EINVAL, PSK_EUNSUPPORTED (d > 4096), PSK_ENOMEM, PSK_ERANK. */
+ * Errors: PSK_EINVAL, PSK_EUNSUPPORTED (d > 4096), PSK_ENOMEM, PSK_ERANK,
+ * PSK_ENONFINITE (a pivot or a score not finite). */
 int leverage_gram(const psk_mat *A, double *theta, void *ws, size_t ws_bytes, void *stream);
 
 /* x = argmin ||A x - b|| = B^{-1} A^T b, B = A^T A (Algorithm
  * least_squares_gram): Cholesky B = R^T R, c = A^T b (row-block partials in
  * a fixed order), x = R^{-1} R^{-T} c.  Accurate to about cond(A)^2 u.
  *   b : n FP64 (device);  x : d FP64 (device, written).
- * Errors: PSK_EINVAL, PSK_EUNSUPPORTED (d > 4096), PSK_ENOMEM, PSK_ERANK. */
+ * Errors: PSK_EINVAL, PSK_EUNSUPPORTED (d > 4096), PSK_ENOMEM, PSK_ERANK,
+ * PSK_ENONFINITE (a pivot or an entry of x not finite). */
 int lsq_gram(const psk_mat *A, const double *b, double *x, void *ws, size_t ws_bytes,
              void *stream);
 
@@ -433,7 +470,8 @@ int lsq_gram(const psk_mat *A, const double *b, double *x, void *ws, size_t ws_b
  *   m, r, seed, prec : as for sketch_gcs (d <= m <= 2^31 - 1, r >= 1).
  *   b : n FP64 (device);  x : d FP64 (device, written).
  * Errors: PSK_EINVAL (shapes, m < d), PSK_EDTYPE (prec), PSK_EUNSUPPORTED,
- * PSK_ENOMEM, PSK_ERANK. */
+ * PSK_ENOMEM, PSK_ERANK, PSK_ENONFINITE (a pivot or an entry of x not
+ * finite). */
 int lsq_sketch_solve(const psk_mat *A, const double *b, double *x, int64_t m, int64_t r,
                      uint64_t seed, int prec, void *ws, size_t ws_bytes, void *stream);
 
@@ -553,10 +591,16 @@ int psk_server_destroy(psk_server *server);
 /* ---- kernel timing (diagnostics) ----------------------------------------
  * When enabled, the library brackets its main kernels (and a few multi-kernel
  * regions) with HIP events recorded on the stream each one is launched on.
- * Names: "cs_bin" (hash + radix binning region), "cs_scatter" (S*A),
- * "gauss_gemm" (Gaussian GEMM kernel), "gemm_reduce" (its K-split sum),
- * "gram" (Gram kernel), "rownorm" (row-norm kernel), "sketch_qr" (whole
- * factorization region), "lsqr_pass" (one LSQR pass over A).
+ * Names: "check" (CSR structure / value check), "cs_bin" (hash + radix
+ * binning region), "cs_scatter" (S*A), "gauss_gemm" (Gaussian GEMM kernel,
+ * dense or sparse form), "gemm_reduce" (its K-split sum), "g_draw" (the FP8
+ * codes of G), "sa_entries" / "sa_limbs" / "sa_quant" (the nonzeros of S*A
+ * for the sparse product, in FP64, BF16 limbs or FP8), "cs_scatter_limbs" /
+ * "cs_scatter_quant" (S*A of CSR A straight into BF16 limbs / FP8 codes),
+ * "gram" (Gram kernel), "gram_reduce" (its slab sums), "rownorm" (row-norm
+ * kernel), "sketch_qr" (whole factorization region), "sketch_delta" (the
+ * perturbation estimate), "jl_normals" (the JL matrix), "qrcp" (column-
+ * pivoted QR of css_select), "lsqr_pass" (one LSQR pass over A).
  * psk_timing_collect waits for the recorded events and returns the summed
  * elapsed milliseconds and launch count of one name (0 and 0 if unseen).
  * psk_timing_names lists the names seen so far, comma separated (static

@@ -16,7 +16,7 @@ PSK_OK = 0
 STATUS_NAMES = {
     0: "PSK_OK", -1: "PSK_EINVAL", -2: "PSK_EDTYPE", -3: "PSK_ENOMEM",
     -4: "PSK_EDEVICE", -5: "PSK_ENOCONV", -6: "PSK_ERANK", -7: "PSK_EUNSUPPORTED",
-    1: "PSK_PENDING",
+    -8: "PSK_ENONFINITE", 1: "PSK_PENDING",
 }
 PSK_PENDING = 1
 PSK_REQ_LSQ, PSK_REQ_LEVERAGE = 0, 1
@@ -28,12 +28,13 @@ PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 (PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
  PSK_OP_LSQ, PSK_OP_SKETCH_G, PSK_OP_LEVERAGE_GRAM, PSK_OP_LSQ_GRAM,
  PSK_OP_LSQ_SKETCH, PSK_OP_LEVERAGE_SKETCH, PSK_OP_CSS, PSK_OP_LEVERAGE_CSS,
- PSK_OP_DELTA) = range(14)
+ PSK_OP_DELTA, PSK_OP_CHECK) = range(15)
+PSK_EINVAL, PSK_ERANK, PSK_ENONFINITE = -1, -6, -8
 
 EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq", "sketch_qr",
             "lsq_solve", "leverage_sketch", "css_select", "leverage_css", "leverage_gram",
-            "lsq_gram", "lsq_sketch_solve", "sketch_delta", "sketch_qr_noalloc",
+            "lsq_gram", "lsq_sketch_solve", "sketch_delta", "sketch_qr_noalloc", "psk_check",
             "psk_probe_copy", "psk_probe_mfma_f64", "psk_probe_mfma_lowp",
             "psk_probe_valu_f32",
             "psk_timing_enable", "psk_timing_only", "psk_timing_reset",
@@ -173,6 +174,7 @@ _SIGS = {
     "lsq_sketch_solve": ([_PM, _vp, _vp, _i64, _i64, _u64, ctypes.c_int, _vp, ctypes.c_size_t,
                           _vp], ctypes.c_int),
     "sketch_delta": ([_vp, _vp, _i64, _i64, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "psk_check": ([_PM, ctypes.c_int, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "psk_probe_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "psk_probe_mfma_f64": ([_i64, _vp, _vp], ctypes.c_int),
     "psk_probe_mfma_lowp": ([ctypes.c_int, _i64, _vp, _vp], ctypes.c_int),

@@ -116,6 +116,17 @@ def version():
     return L.lib().psk_version().decode()
 
 
+def check(A, values=False):
+    """psk_check: raise PskError (PSK_EINVAL) for a malformed CSR A and, with
+    values, (PSK_ENONFINITE) for a NaN or infinity among its entries."""
+    pm = _mat(A)
+    dev = _device(A)
+    nbytes = workspace_size(L.PSK_OP_CHECK, A)
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().psk_check(ctypes.byref(pm), int(bool(values)), ws.data_ptr(), ws.numel(),
+                              _stream(dev)), "psk_check")
+
+
 def cs_hash(count, r, seed, row0=0, device="cuda"):
     """(h int32[count], sign int8[count]) for rows row0 .. row0+count-1."""
     h = torch.empty(count, dtype=torch.int32, device=device)

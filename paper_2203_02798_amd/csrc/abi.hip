@@ -248,7 +248,15 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
   if (!A) return fail(PSK_EINVAL, "A is NULL");
   Arena ws;  // dry run
   int rc = 0;
+  // every call that walks a CSR A checks its structure first (its result
+  // word is released before the call's own scratch is taken)
+  if (op != PSK_OP_QR && op != PSK_OP_DELTA && op != PSK_OP_CHECK &&
+      (rc = validate_csr(*A, ws, nullptr)))
+    return rc;
   switch (op) {
+    case PSK_OP_CHECK:
+      rc = check_operand(*A, true, ws, nullptr);
+      break;
     case PSK_OP_SKETCH_CS:
       if ((rc = check_r(r))) return rc;
       rc = do_sketch_cs(*A, r, 0, nullptr, ws, nullptr);
@@ -345,10 +353,12 @@ int sketch_cs(const psk_mat *A, int64_t r, uint64_t seed, void *SA, void *wsp,
   if ((rc = check_r(r))) return rc;
   if (!SA) return fail(PSK_EINVAL, "SA is NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = do_sketch_cs(*A, r, seed, nullptr, plan, nullptr))) return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_CS)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return do_sketch_cs(*A, r, seed, SA, ws, as_stream(stream));
 }
 
@@ -362,10 +372,12 @@ int sketch_gcs(const psk_mat *A, int64_t m, int64_t r, uint64_t seed, int prec,
     return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
   if (!C) return fail(PSK_EINVAL, "C is NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = do_sketch_gcs(*A, m, r, seed, prec, nullptr, plan, nullptr))) return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_GCS)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return do_sketch_gcs(*A, m, r, seed, prec, C, ws, as_stream(stream));
 }
 
@@ -378,10 +390,12 @@ int sketch_g(const psk_mat *A, int64_t m, uint64_t seed, int prec, double *C, vo
     return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
   if (!C) return fail(PSK_EINVAL, "C is NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = do_sketch_g(*A, m, seed, prec, nullptr, plan, nullptr))) return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_G)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return do_sketch_g(*A, m, seed, prec, C, ws, as_stream(stream));
 }
 
@@ -390,10 +404,12 @@ int leverage_gram(const psk_mat *A, double *theta, void *wsp, size_t ws_bytes, v
   if (rc) return rc;
   if (!theta) return fail(PSK_EINVAL, "theta is NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = leverage_gram_impl(*A, nullptr, plan, nullptr))) return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LEVERAGE_GRAM)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return leverage_gram_impl(*A, theta, ws, as_stream(stream));
 }
 
@@ -403,10 +419,12 @@ int lsq_gram(const psk_mat *A, const double *b, double *x, void *wsp, size_t ws_
   if (rc) return rc;
   if (!b || !x) return fail(PSK_EINVAL, "b and x must be non-NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = lsq_gram_impl(*A, nullptr, nullptr, plan, nullptr))) return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LSQ_GRAM)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return lsq_gram_impl(*A, b, x, ws, as_stream(stream));
 }
 
@@ -421,11 +439,13 @@ int lsq_sketch_solve(const psk_mat *A, const double *b, double *x, int64_t m, in
     return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
   if (!b || !x) return fail(PSK_EINVAL, "b and x must be non-NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = lsq_sketch_solve_impl(*A, nullptr, nullptr, m, r, seed, prec, plan, nullptr)))
     return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LSQ_SKETCH)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return lsq_sketch_solve_impl(*A, b, x, m, r, seed, prec, ws, as_stream(stream));
 }
 
@@ -436,11 +456,13 @@ int leverage_sketch(const psk_mat *A, int64_t m, int64_t r, int64_t t, uint64_t 
   if ((rc = check_leverage_sketch(*A, m, r, t, prec))) return rc;
   if (!theta) return fail(PSK_EINVAL, "theta is NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = leverage_sketch_impl(*A, m, r, t, seed, prec, nullptr, true, plan, nullptr)))
     return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LEVERAGE_SKETCH)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return leverage_sketch_impl(*A, m, r, t, seed, prec, theta, true, ws, as_stream(stream));
 }
 
@@ -451,10 +473,12 @@ int css_select(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t seed,
   if ((rc = check_css(*A, m, r, k, prec))) return rc;
   if (!cols) return fail(PSK_EINVAL, "cols is NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = css_select_impl(*A, m, r, k, seed, prec, nullptr, plan, nullptr))) return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_CSS)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return css_select_impl(*A, m, r, k, seed, prec, cols, ws, as_stream(stream));
 }
 
@@ -465,12 +489,14 @@ int leverage_css(const psk_mat *A, int64_t m, int64_t r, int64_t k, uint64_t see
   if ((rc = check_css(*A, m, r, k, prec))) return rc;
   if (!theta) return fail(PSK_EINVAL, "theta is NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   // planned without the caller's cols, so the bound covers both forms
   if ((rc = leverage_css_impl(*A, m, r, k, seed, prec, nullptr, nullptr, plan, nullptr)))
     return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LEVERAGE_CSS)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return leverage_css_impl(*A, m, r, k, seed, prec, theta, cols, ws, as_stream(stream));
 }
 
@@ -480,12 +506,14 @@ int gram(double alpha, const psk_mat *A, double beta, void *C, void *wsp,
   if (rc) return rc;
   if (!C) return fail(PSK_EINVAL, "C is NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   rc = A->format == PSK_DENSE ? gram_dense(alpha, *A, beta, nullptr, plan, nullptr)
                               : gram_csr(alpha, *A, beta, nullptr, plan, nullptr);
   if (rc) return rc;
   if (ws_bytes < plan.peak || (plan.peak > 0 && !wsp))
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_GRAM)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return A->format == PSK_DENSE ? gram_dense(alpha, *A, beta, C, ws, as_stream(stream))
                                 : gram_csr(alpha, *A, beta, C, ws, as_stream(stream));
 }
@@ -497,6 +525,7 @@ int rownorms_sq(double alpha, const psk_mat *A, const double *B, int64_t k,
   if (k < 1) return fail(PSK_EINVAL, "k must be >= 1");
   if (!B || !x) return fail(PSK_EINVAL, "B and x must be non-NULL");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   rc = A->format == PSK_DENSE
            ? rownorms_dense(alpha, *A, nullptr, k, beta, nullptr, plan, nullptr)
            : rownorms_csr(alpha, *A, nullptr, k, beta, nullptr, plan, nullptr);
@@ -504,9 +533,22 @@ int rownorms_sq(double alpha, const psk_mat *A, const double *B, int64_t k,
   if (ws_bytes < plan.peak || (plan.peak > 0 && !wsp))
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_ROWNORMS)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return A->format == PSK_DENSE
              ? rownorms_dense(alpha, *A, B, k, beta, x, ws, as_stream(stream))
              : rownorms_csr(alpha, *A, B, k, beta, x, ws, as_stream(stream));
+}
+
+int psk_check(const psk_mat *A, int check_values, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if (A->format == PSK_DENSE && !check_values) return PSK_OK;
+  Arena plan;
+  if ((rc = check_operand(*A, check_values != 0, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_CHECK)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  return check_operand(*A, check_values != 0, ws, as_stream(stream));
 }
 
 int sketch_qr(const double *C, int64_t m, int64_t d, double *R, double *Rinv,
@@ -552,10 +594,12 @@ int lsq_solve(const psk_mat *A, const double *b, double *x, const psk_lsq_opts *
       o.prec != PSK_PREC_FP8)
     return fail(PSK_EDTYPE, "opts->prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
   Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
   if ((rc = lsq_impl(*A, nullptr, nullptr, o, nullptr, plan, nullptr))) return rc;
   if (!wsp || ws_bytes < plan.peak)
     return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_LSQ)");
   Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return lsq_impl(*A, b, x, o, info, ws, as_stream(stream));
 }
 

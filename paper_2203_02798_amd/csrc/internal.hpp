@@ -89,6 +89,25 @@ void scan_run(uint32_t *data, int64_t L, uint32_t *sums, hipStream_t st);
 int check_mat(const psk_mat *A);
 int check_r(int64_t r);
 
+// ---- operand validation (k_check.hip) ---------------------------------------
+// One pass over CSR A's offsets and indices (and, with values, over the stored
+// values of CSR or dense A), then one read of the result on the host (the
+// stream is synchronised): PSK_EINVAL for a malformed CSR structure,
+// PSK_ENONFINITE for a NaN or infinity, else 0.  A planning arena only
+// reserves the result word.
+int check_operand(const psk_mat &A, bool values, Arena &ws, hipStream_t st);
+// check_operand of the structure alone, for CSR A (dense A: nothing), with
+// its word released again; every entry point runs it before any kernel that
+// walks A.
+int validate_csr(const psk_mat &A, Arena &ws, hipStream_t st);
+// Bits of the status word the factorizations write (an int in device
+// memory, cleared by its owner): 1 a Cholesky pivot not positive, 2 a pivot
+// or a checked result not finite.  flag_nonfinite ORs 2 into *flag when one
+// of count FP64 values is NaN or infinite; factor_status turns the word read
+// back into PSK_ENONFINITE (bit 2, first), PSK_ERANK with rank_msg, or 0.
+void flag_nonfinite(const double *p, int64_t count, int *flag, hipStream_t st);
+int factor_status(int h, const char *rank_msg);
+
 // S*A and G*S*A end to end (binning, scatter, GEMM), abi.hip.
 // S*A in the dtype of A (FP64 sums rounded once), or as the FP64 sums
 int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws,

@@ -113,9 +113,9 @@ constexpr int kVb = 16 * 17;  // one 16 x 16 block inverse in LDS (row stride 17
 // applied to the identity leave L^{-1} = U^{-T} in z, lane l holding its
 // column l, i.e. row l of V = U^{-1}.  U overwrites the block's upper
 // triangle and V goes to Vb (row-major, stride 17).  Lanes 16..63 repeat
-// lanes 0..15 and store nothing.  Returns true when a pivot was not
-// positive (it is then replaced by 1).
-__device__ __forceinline__ bool factor16(double *__restrict__ T, int o,
+// lanes 0..15 and store nothing.  Returns bit 1 when a pivot was not
+// positive (it is then replaced by 1), bit 2 when one was NaN or infinite.
+__device__ __forceinline__ int factor16(double *__restrict__ T, int o,
                                          double *__restrict__ rowbuf,
                                          double *__restrict__ Vb) {
   const int l = threadIdx.x & 15;
@@ -126,11 +126,12 @@ __device__ __forceinline__ bool factor16(double *__restrict__ T, int o,
     c[i] = T[(o + i) * kLd + o + l];
     z[i] = (i == l) ? 1.0 : 0.0;
   }
-  bool bad = false;
+  int bad = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     double piv = readlane_f64(c[k], k);
-    bad |= !(piv > 0.0);
+    bad |= !(piv > 0.0) ? 1 : 0;
+    bad |= !(fabs(piv) <= 1.7976931348623157e308) ? 2 : 0;  // NaN or infinite
     piv = piv > 0.0 ? piv : 1.0;
     const double rs = rsqrt_acc(piv);
     const double u = (l >= k) ? c[k] * rs : 0.0;
@@ -211,7 +212,7 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
     if (i >= nb || j >= nb) T[i * kLd + j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  bool bad = false;
+  int bad = 0;
 #pragma unroll 1
   for (int kb = 0; kb < 4; ++kb) {
     const int o = 16 * kb;
@@ -320,7 +321,7 @@ __device__ __forceinline__ void factor_diag(CholSmem &S, int nb, int64_t d, int6
       X[(j0 + i) * d + j0 + j] = XT[i * kLd + j];
     }
   }
-  if (bad) atomicOr(flag, 1);
+  if (bad) atomicOr(flag, bad);
 }
 
 // acc (this thread's 4 x 4 of a 64 x 64 tile: rows 4*ty.., columns 4*tx..)

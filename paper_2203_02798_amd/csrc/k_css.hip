@@ -232,6 +232,7 @@ int css_select_impl(const psk_mat &A, int64_t m, int64_t r, int64_t k, uint64_t 
   double *Bt = ws.take<double>((size_t)rows * d);
   double *na = ws.take<double>((size_t)d);
   double *nb = ws.take<double>((size_t)d);
+  int *flag = ws.take<int>(2);
   const bool run = !ws.dry();
   if (run && !ws.ok()) return fail(PSK_ENOMEM, "workspace too small for css_select");
   const size_t mk = ws.mark();
@@ -239,6 +240,14 @@ int css_select_impl(const psk_mat &A, int64_t m, int64_t r, int64_t k, uint64_t 
   if ((rc = sketch_f64(A, m, r, seed, prec, C, ws, st))) return rc;
   ws.release(mk);
   if (!run) return 0;
+  // pivots chosen by norms with a NaN in them are meaningless: the sketch is
+  // checked first and read back before the selection runs
+  k_zero<<<1, 64, 0, st>>>(reinterpret_cast<double *>(flag), 1);
+  flag_nonfinite(C, rows * d, flag, st);
+  int h = 0;
+  PSK_HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  PSK_HIP_TRY(hipStreamSynchronize(st));
+  if ((rc = factor_status(h, ""))) return rc;
   KTimer timer("qrcp", st);
   const dim3 tg((unsigned)ceil_div(rows, (int64_t)kTile), (unsigned)ceil_div(d, (int64_t)kTile));
   k_transpose<<<tg, 256, 0, st>>>(C, rows, d, Bt);
@@ -287,11 +296,11 @@ int leverage_css_impl(const psk_mat &A, int64_t m, int64_t r, int64_t k, uint64_
   if (rc) return rc;
   if (!run) return 0;
   PSK_HIP_TRY(hipGetLastError());
+  flag_nonfinite(theta, A.n, flag, st);
   int h = 0;
   PSK_HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   PSK_HIP_TRY(hipStreamSynchronize(st));
-  if (h) return fail(PSK_ERANK, "a Cholesky pivot was not positive: the selected columns are numerically rank deficient");
-  return 0;
+  return factor_status(h, "a Cholesky pivot was not positive: the selected columns are numerically rank deficient");
 }
 
 }  // namespace psk

@@ -252,13 +252,14 @@ int gram_f64(const psk_mat &A, double *B, Arena &ws, hipStream_t st) {
                                : gram_csr(1.0, A, 0.0, B, ws, st, true);
 }
 
-// the pivot flag, read back once the stream reaches it
-int rank_check(const int *flag, hipStream_t st) {
+// the status word of the factorization (and of the finiteness check of the
+// result, count values at out), read back once the stream reaches it
+int rank_check(int *flag, const double *out, int64_t count, hipStream_t st) {
+  flag_nonfinite(out, count, flag, st);
   int h = 0;
   PSK_HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   PSK_HIP_TRY(hipStreamSynchronize(st));
-  if (h) return fail(PSK_ERANK, "a Cholesky pivot was not positive: A is numerically rank deficient");
-  return 0;
+  return factor_status(h, "a Cholesky pivot was not positive: A is numerically rank deficient");
 }
 
 }  // namespace
@@ -280,7 +281,7 @@ int leverage_gram_impl(const psk_mat &A, double *theta, Arena &ws, hipStream_t s
   rc = A.format == PSK_DENSE ? rownorms_dense(1.0, A, X, d, 0.0, theta, ws, st)
                              : rownorms_csr(1.0, A, X, d, 0.0, theta, ws, st);
   if (rc || ws.dry()) return rc;
-  return rank_check(flag, st);
+  return rank_check(flag, theta, A.n, st);
 }
 
 int lsq_gram_impl(const psk_mat &A, const double *b, double *x, Arena &ws, hipStream_t st) {
@@ -304,7 +305,7 @@ int lsq_gram_impl(const psk_mat &A, const double *b, double *x, Arena &ws, hipSt
   if (ws.dry()) return 0;
   apply_xxt(X, d, c, y, x, 0, st);
   PSK_HIP_TRY(hipGetLastError());
-  return rank_check(flag, st);
+  return rank_check(flag, x, d, st);
 }
 
 int lsq_sketch_solve_impl(const psk_mat &A, const double *b, double *x, int64_t m, int64_t r,
@@ -391,7 +392,7 @@ int lsq_sketch_solve_impl(const psk_mat &A, const double *b, double *x, int64_t 
   if (ws.dry()) return 0;
   apply_xxt(X, d, z, y, x, 1, st);
   PSK_HIP_TRY(hipGetLastError());
-  return rank_check(flag, st);
+  return rank_check(flag, x, d, st);
 }
 
 }  // namespace psk

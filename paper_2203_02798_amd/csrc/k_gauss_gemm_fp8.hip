@@ -46,18 +46,19 @@ constexpr int kScaleBytes = kBN;               // 512 scale bytes per chunk tile
 constexpr int kBufBytes = kDataBytes + kScaleBytes;
 
 // exponent e of the block scale: smallest integer with 448 * 2^e >= amax
-// (amax = f 2^x, f in [1/2, 1); 448 = 0.875 2^9), 0 for amax == 0
+// (amax = f 2^x, f in [1/2, 1); 448 = 0.875 2^9), 0 for amax == 0 and for
+// an infinite amax (the block then carries a NaN, see e4m3x2)
 __device__ __forceinline__ int scale_exp_f32(float amax) {
   int x;
   const float f = frexpf(amax, &x);
   const int e = (f <= 0.875f) ? x - 9 : x - 8;
-  return amax > 0.0f ? e : 0;
+  return (amax > 0.0f && amax <= 3.4028234663852886e38f) ? e : 0;
 }
 __device__ __forceinline__ int scale_exp_f64(double amax) {
   int x;
   const double f = frexp(amax, &x);
   const int e = (f <= 0.875) ? x - 9 : x - 8;
-  return amax > 0.0 ? e : 0;
+  return (amax > 0.0 && amax <= 1.7976931348623157e308) ? e : 0;
 }
 
 // FP32 of a double by round-to-odd (then a later RNE to e4m3 is a single
@@ -73,8 +74,11 @@ __device__ __forceinline__ float f32_odd(double v) {
   return f;
 }
 
-// two e4m3 bytes (RNE) packed in the low 16 bits
+// two e4m3 bytes (RNE) packed in the low 16 bits; a NaN or an infinity
+// becomes the e4m3 NaN, so a non-finite S*A entry reaches the product
 __device__ __forceinline__ uint32_t e4m3x2(float a, float b) {
+  a = fabsf(a) <= 3.4028234663852886e38f ? a : __builtin_nanf("");
+  b = fabsf(b) <= 3.4028234663852886e38f ? b : __builtin_nanf("");
   return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xFFFFu;
 }
 

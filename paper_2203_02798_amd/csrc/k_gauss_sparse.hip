@@ -88,12 +88,13 @@ __device__ __forceinline__ double bf16_round(double v) {
 }
 
 // exponent e of the E8M0 block scale: smallest integer with 448 * 2^e >= amax
-// (amax = f 2^x, f in [1/2, 1); 448 = 0.875 2^9), 0 for amax == 0, clamped
+// (amax = f 2^x, f in [1/2, 1); 448 = 0.875 2^9), 0 for amax == 0 or not
+// finite, clamped
 __device__ __forceinline__ int e8m0_exp(double amax) {
   int x;
   const double f = frexp(amax, &x);
   int e = (f <= 0.875) ? x - 9 : x - 8;
-  if (!(amax > 0.0)) e = 0;
+  if (!(amax > 0.0 && amax <= 1.7976931348623157e308)) e = 0;
   return e < -127 ? -127 : (e > 127 ? 127 : e);
 }
 
@@ -108,6 +109,7 @@ __device__ __forceinline__ double e4m3_round(double v, int e) {
     b |= 1u;
     f = __uint_as_float(b);
   }
+  f = fabsf(f) <= 3.4028234663852886e38f ? f : __builtin_nanf("");  // non-finite: NaN
   const int byte = __builtin_amdgcn_cvt_pk_fp8_f32(f, 0.0f, 0, false) & 0xff;
   return ldexp((double)__builtin_amdgcn_cvt_f32_fp8(byte, 0), e);
 }

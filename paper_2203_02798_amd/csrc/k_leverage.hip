@@ -86,11 +86,13 @@ int leverage_sketch_impl(const psk_mat &A, int64_t m, int64_t r, int64_t t, uint
   if (!run) return 0;
   PSK_HIP_TRY(hipGetLastError());
   if (!check_rank) return 0;
+  // a NaN or infinity of A that a reduced-precision sketch did not carry
+  // still reaches its row's score
+  flag_nonfinite(theta, A.n, flag, st);
   int h = 0;
   PSK_HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   PSK_HIP_TRY(hipStreamSynchronize(st));
-  if (h) return fail(PSK_ERANK, "a Cholesky pivot was not positive: the sketch is numerically rank deficient");
-  return 0;
+  return factor_status(h, "a Cholesky pivot was not positive: the sketch is numerically rank deficient");
 }
 
 }  // namespace psk

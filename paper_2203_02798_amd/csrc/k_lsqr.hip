@@ -979,6 +979,8 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     // A reduced-precision sketch only preconditions well while its relative
     // error (about 1e-5 for the BF16 GEMM) times cond(A) stays small; the
     // diagonal ratio of R is a cheap lower estimate of cond(A).
+    // a NaN or an infinity in the sketch is not cured by an FP64 one
+    if (hflag & 2) return factor_status(hflag, "");
     if (may_escalate && (hflag || !(hr[0] <= cond_limit * hr[1]))) {
       // the first factorization's flag has been read: its scratch is free
       ws.release(mk_sketch);
@@ -997,7 +999,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
       prec_used = PSK_PREC_F64;
       delta_est = 0.0;  // LSQR runs on the FP64 sketch now
     }
-    if (hflag) return fail(PSK_ERANK, "sketch is numerically rank deficient");
+    if ((rc = factor_status(hflag, "sketch is numerically rank deficient"))) return rc;
   }
   ws.release(mk);
 
@@ -1008,7 +1010,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   slot.held = true;
   k_zero<<<db, 256, 0, st>>>(x, d);
   int total_iters = 0;
-  bool converged = true;
+  bool converged = true, nonfinite = false;
   LsqrState hs{};
   double rate = 0.0;  // d log(stopping margin) / d iteration, from the last pass
   for (int pass = 0; pass <= o.refine; ++pass) {
@@ -1109,9 +1111,17 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
           done = true;
           break;
         }
+        // a NaN or an infinity in A or b makes the norms non-finite and the
+        // stopping test never true: stop at the first read that shows it
+        if (!std::isfinite(hs.bnorm) || !std::isfinite(hs.rnorm) ||
+            !std::isfinite(hs.anorm2)) {
+          nonfinite = true;
+          break;
+        }
       }
-      if (done) break;
+      if (done || nonfinite) break;
     }
+    if (nonfinite) break;
     // the groups still enqueued after the stop are no-ops; the stream
     // synchronisation below waits for them
     if (!done) converged = false;
@@ -1121,6 +1131,8 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
   }
   PSK_HIP_TRY(hipGetLastError());
   PSK_HIP_TRY(hipStreamSynchronize(st));
+  if (nonfinite)
+    return fail(PSK_ENONFINITE, "LSQR's norms are not finite: A or b holds a NaN or an infinity");
   if (info) {
     info->iters = total_iters;
     info->status = converged ? PSK_OK : PSK_ENOCONV;

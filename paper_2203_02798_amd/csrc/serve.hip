@@ -57,7 +57,8 @@ int leverage_run(const psk_request &q, Arena &ws, hipStream_t st) {
 
 int plan_request(const psk_request &q, size_t *bytes) {
   Arena plan;
-  int rc;
+  int rc = validate_csr(q.A, plan, nullptr);
+  if (rc) return rc;
   if (q.op == PSK_REQ_LSQ) {
     rc = lsq_impl(q.A, nullptr, nullptr, q.opts, nullptr, plan, nullptr);
   } else {
@@ -108,12 +109,12 @@ struct Server {
       lk.unlock();
       cv_work.notify_all();  // the next request may fit as well
       Arena ws = Arena::over(pool + job->ws_off, job->ws_bytes);
-      int rc;
-      if (job->req.op == PSK_REQ_LSQ) {
-        rc = lsq_impl(job->req.A, job->req.b, job->req.out, job->req.opts, &job->info, ws, st);
-      } else {
-        rc = leverage_run(job->req, ws, st);
-      }
+      // a malformed CSR A ends the request before any kernel walks it
+      int rc = validate_csr(job->req.A, ws, st);
+      if (!rc)
+        rc = job->req.op == PSK_REQ_LSQ ? lsq_impl(job->req.A, job->req.b, job->req.out,
+                                                   job->req.opts, &job->info, ws, st)
+                                        : leverage_run(job->req, ws, st);
       const hipError_t e = hipStreamSynchronize(st);
       if (!rc && e != hipSuccess) rc = fail(PSK_EDEVICE, hipGetErrorString(e));
       lk.lock();

@@ -244,3 +244,55 @@ def test_server_argument_checks_before_any_device_call(lib):
     t = C.c_int64()
     assert lib.psk_server_submit(None, None, C.byref(t)) == -1
     assert lib.psk_server_destroy(None) == -1
+
+
+def test_check_planning_and_arguments(lib):
+    """psk_check and the structure check every CSR call runs: a result word
+    of workspace, argument errors before any device work."""
+    st, c1 = _ws(L.PSK_OP_CHECK, _csr(1000, 64, 5000))
+    assert st == 0 and c1 >= 4
+    st, c2 = _ws(L.PSK_OP_CHECK, _dense(1000, 64))
+    assert st == 0 and c2 >= 4
+    # every op on CSR A reserves the word, so even the Gram of a CSR A that
+    # needs no other scratch asks for some
+    st, g = _ws(L.PSK_OP_GRAM, _csr(1000, 64, 5000))
+    assert st == 0 and g >= 4
+    assert lib.psk_check(None, 1, None, 0, None) == L.PSK_EINVAL
+    # dense A without the value check: nothing to do, no device touched
+    m = _dense(100, 8)
+    assert lib.psk_check(ctypes.byref(m), 0, None, 0, None) == L.PSK_OK
+    # a workspace too small is refused before the pass
+    m = _csr(100, 8, 10)
+    assert lib.psk_check(ctypes.byref(m), 0, None, 0, None) == -3
+    m = _csr(100, 8, -1)
+    assert lib.psk_check(ctypes.byref(m), 0, None, 0, None) == L.PSK_EINVAL
+    assert L.STATUS_NAMES[L.PSK_ENONFINITE] == "PSK_ENONFINITE"
+
+
+def test_every_entry_point_validates_csr_first():
+    """Static check of the C-ABI layer: every entry point that takes a matrix
+    A runs the CSR structure check on its workspace before anything else is
+    enqueued on the stream (the planning pass reserves its word too)."""
+    src = open(os.path.join(ROOT, "paper_2203_02798_amd", "csrc", "abi.hip")).read()
+    body = src.split('extern "C" {', 1)[1]
+    funcs = re.split(r"\nint (?=\w+\()", body)
+    seen = 0
+    for f in funcs:
+        if "check_mat(A)" not in f:
+            continue
+        name = f.split("(", 1)[0]
+        if name == "psk_check":  # the check itself
+            assert "check_operand(*A, check_values != 0, ws, as_stream(stream))" in f
+            continue
+        run = f.split("Arena ws = Arena::over(wsp, ws_bytes);\n", 1)
+        assert len(run) == 2, name
+        first = run[1].lstrip().splitlines()[0]
+        assert first.startswith("if ((rc = validate_csr(*A, ws, as_stream(stream))))"), name
+        plan = f.split("Arena plan;\n", 1)
+        assert len(plan) == 2 and plan[1].lstrip().startswith(
+            "if ((rc = validate_csr(*A, plan, nullptr)))"), name
+        seen += 1
+    assert seen >= 12
+    serve = open(os.path.join(ROOT, "paper_2203_02798_amd", "csrc", "serve.hip")).read()
+    assert "int rc = validate_csr(job->req.A, ws, st);" in serve
+    assert "int rc = validate_csr(q.A, plan, nullptr);" in serve

@@ -1,0 +1,250 @@
+"""Operand validation and non-finite reporting on the device.
+
+psk_check gets every malformed CSR form of the definition (Section 1
+notation), including offsets past nnz and indices far outside [0, d): it
+reads indptr, indices and values only within the lengths the descriptor
+states, so no form can send it out of bounds.  The other entry points get
+only malformed forms that stay inside the buffers (a first offset of 1, an
+end offset below nnz, an index equal to d with padded operands), and must
+refuse them with PSK_EINVAL before any kernel walks A.  Non-finite input must
+come back as PSK_ENONFINITE from every call that factors, and propagate into
+the outputs of the stream-ordered sketches."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from helpers import to_device
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+EINVAL, ENONFINITE = -1, -8
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_2203_02798_amd import api as a
+    return a
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _csr_parts(n=3000, d=40, density=0.05, seed=0):
+    a = sp.random(n, d, density=density, format="csr", random_state=seed, dtype=np.float64)
+    a.data = np.random.default_rng(seed).standard_normal(a.nnz)
+    # every row at least one entry and full column rank
+    a = (a + sp.eye(n, d, format="csr")).tocsr()
+    a.sort_indices()
+    return a
+
+
+def _dev_csr(api, ptr, idx, val, shape, dtype=torch.float64, pad=0):
+    """CsrMatrix from host arrays; pad > 0 leaves that many spare entries
+    after the index and value arrays (not part of the matrix)."""
+    dev = "cuda"
+    idx_t = torch.zeros(len(idx) + pad, dtype=torch.int32, device=dev)
+    val_t = torch.zeros(len(val) + pad, dtype=dtype, device=dev)
+    if len(idx):
+        idx_t[: len(idx)] = torch.as_tensor(np.asarray(idx, np.int32), device=dev)
+        val_t[: len(val)] = torch.as_tensor(np.asarray(val), device=dev).to(dtype)
+    return api.CsrMatrix(torch.as_tensor(np.asarray(ptr, np.int64), device=dev),
+                         idx_t[: len(idx)], val_t[: len(val)], shape)
+
+
+def _status(fn):
+    from paper_2203_02798_amd import _lib as L
+    try:
+        fn()
+    except L.PskError as e:
+        return e.status
+    return 0
+
+
+def test_psk_check_every_form(api):
+    a = _csr_parts()
+    n, d = a.shape
+    ptr, idx, val = a.indptr.astype(np.int64), a.indices.astype(np.int64), a.data
+    nnz = len(idx)
+    forms = {"well formed": (ptr, idx, val, 0)}
+    p = ptr.copy(); p[0] = 1
+    forms["first offset 1"] = (p, idx, val, EINVAL)
+    p = ptr.copy(); p[-1] = nnz - 1
+    forms["end below nnz"] = (p, idx, val, EINVAL)
+    p = ptr.copy(); p[-1] = nnz + 1000
+    forms["end past nnz"] = (p, idx, val, EINVAL)
+    p = ptr.copy(); p[n // 2] = nnz + 10 ** 9
+    forms["offset far past nnz"] = (p, idx, val, EINVAL)
+    p = ptr.copy(); p[n // 3] = -5
+    forms["negative offset"] = (p, idx, val, EINVAL)
+    p = ptr.copy(); p[7], p[8] = p[8], p[7]
+    if p[7] == p[8]:
+        p[8] -= 1
+    forms["decreasing pair"] = (p, idx, val, EINVAL)
+    for where, c in (("first", 0), ("middle", nnz // 2), ("last", nnz - 1)):
+        i2 = idx.copy(); i2[c] = d
+        forms[f"index d at {where}"] = (ptr, i2, val, EINVAL)
+    i2 = idx.copy(); i2[5] = -1
+    forms["index -1"] = (ptr, i2, val, EINVAL)
+    i2 = idx.copy(); i2[9] = 2 ** 31 - 1
+    forms["index int32 max"] = (ptr, i2, val, EINVAL)
+    for name, (p, i, v, want) in forms.items():
+        for dt in (torch.float64, torch.float32):
+            A = _dev_csr(api, p, i, v, (n, d), dtype=dt)
+            _say(f"psk_check {name} {dt}")
+            assert _status(lambda: api.check(A)) == want, name
+            assert _status(lambda: api.check(A, values=True)) == want, name
+    # values: NaN / +-inf anywhere; a float32 overflow of a finite double
+    for bad in (np.nan, np.inf, -np.inf):
+        for c in (0, nnz // 2, nnz - 1):
+            v2 = val.copy(); v2[c] = bad
+            A = _dev_csr(api, ptr, idx, v2, (n, d))
+            assert _status(lambda: api.check(A)) == 0
+            assert _status(lambda: api.check(A, values=True)) == ENONFINITE
+    v2 = val.copy(); v2[3] = 1e300
+    A64 = _dev_csr(api, ptr, idx, v2, (n, d))
+    A32 = api.CsrMatrix(A64.indptr, A64.indices, A64.values.float(), (n, d))
+    assert _status(lambda: api.check(A64, values=True)) == 0
+    assert _status(lambda: api.check(A32, values=True)) == ENONFINITE
+    # structure is reported before values
+    i2 = idx.copy(); i2[0] = d
+    v2 = val.copy(); v2[0] = np.nan
+    A = _dev_csr(api, ptr, i2, v2, (n, d))
+    assert _status(lambda: api.check(A, values=True)) == EINVAL
+    # no entries at all; empty rows
+    A = _dev_csr(api, np.zeros(n + 1), [], [], (n, d))
+    assert _status(lambda: api.check(A, values=True)) == 0
+    A = _dev_csr(api, np.r_[np.zeros(n), 1], [], [], (n, d))
+    assert _status(lambda: api.check(A)) == EINVAL
+
+
+def test_psk_check_dense(api):
+    x = torch.randn(5000, 37, dtype=torch.float64, device="cuda")
+    big = torch.zeros(5000, 48, dtype=torch.float64, device="cuda")
+    big[:, 37:] = float("nan")  # outside the matrix: columns past d in each row
+    big[:, :37] = x
+    view = big[:, :37]
+    assert _status(lambda: api.check(view, values=True)) == 0
+    for (i, j) in ((0, 0), (2500, 17), (4999, 36)):
+        y = x.clone(); y[i, j] = float("inf")
+        assert _status(lambda: api.check(y, values=True)) == ENONFINITE
+        assert _status(lambda: api.check(y)) == 0
+    y = x.float(); y[100, 3] = float("nan")
+    assert _status(lambda: api.check(y, values=True)) == ENONFINITE
+
+
+def _safe_malformed(api, a, pad=64):
+    """Malformed forms whose every access stays inside the buffers even if a
+    consumer ran: first offset 1, end offset nnz - 1, an index equal to d in
+    the middle of a row, all with padded arrays."""
+    n, d = a.shape
+    ptr, idx, val = a.indptr.astype(np.int64), a.indices.astype(np.int64), a.data
+    out = {}
+    p = ptr.copy(); p[0] = 1
+    out["first offset 1"] = _dev_csr(api, p, idx, val, (n, d), pad=pad)
+    p = ptr.copy(); p[-1] = len(idx) - 1
+    out["end nnz-1"] = _dev_csr(api, p, idx, val, (n, d), pad=pad)
+    i2 = idx.copy(); i2[len(idx) // 2] = d
+    out["index d"] = _dev_csr(api, ptr, i2, val, (n, d), pad=pad)
+    return out
+
+
+def test_entry_points_refuse_malformed_csr(api):
+    a = _csr_parts(n=4000, d=24)
+    n, d = a.shape
+    b = torch.randn(n, dtype=torch.float64, device="cuda")
+    Bp = torch.zeros(d + 1, d, dtype=torch.float64, device="cuda")  # one spare row
+    Bp[:d] = torch.eye(d, dtype=torch.float64, device="cuda")
+    B = Bp[:d]
+    calls = {
+        "sketch_cs": lambda A: api.sketch_cs(A, 512, 1),
+        "sketch_gcs f64": lambda A: api.sketch_gcs(A, 96, 512, 1),
+        "sketch_gcs bf16": lambda A: api.sketch_gcs(A, 96, 512, 1, prec="bf16"),
+        "sketch_gcs fp8": lambda A: api.sketch_gcs(A, 96, 512, 1, prec="fp8"),
+        "sketch_g": lambda A: api.sketch_g(A, 96, 1),
+        "gram": lambda A: api.gram(A),
+        "rownorms_sq": lambda A: api.rownorms_sq(A, B),
+        "leverage_sketch": lambda A: api.leverage_sketch(A, 96, 512, 1),
+        "leverage_gram": lambda A: api.leverage_gram(A),
+        "css_select": lambda A: api.css_select(A, 96, 512, 4, 1),
+        "leverage_css": lambda A: api.leverage_css(A, 96, 512, 4, 1),
+        "lsq_gram": lambda A: api.lsq_gram(A, b),
+        "lsq_sketch_solve": lambda A: api.lsq_sketch_solve(A, b, 96, 512, 1),
+        "lsq_solve": lambda A: api.lsq_solve(A, b, m=96, r=512, seed=1),
+    }
+    for form, A in _safe_malformed(api, a).items():
+        for name, call in calls.items():
+            _say(f"{name} on malformed CSR ({form})")
+            assert _status(lambda: call(A)) == EINVAL, (name, form)
+    # and the same calls accept the well-formed matrix
+    A = api.CsrMatrix.from_scipy(a)
+    for name, call in calls.items():
+        assert _status(lambda: call(A)) == 0, name
+    torch.cuda.synchronize()
+
+
+def test_server_refuses_malformed_csr(api):
+    a = _csr_parts(n=4000, d=24, seed=5)
+    n, d = a.shape
+    b = torch.randn(n, dtype=torch.float64, device="cuda")
+    bad = _safe_malformed(api, a)["index d"]
+    good = api.CsrMatrix.from_scipy(a)
+    with api.Server(1 << 28, slots=2) as srv:
+        t1, _ = srv.submit_lsq(bad, b, 96, 512, seed=1)
+        t2, x2 = srv.submit_lsq(good, b, 96, 512, seed=1)
+        t3, _ = srv.submit_leverage(bad, 96, 512, seed=1)
+        r1, r2, r3 = srv.wait(t1), srv.wait(t2), srv.wait(t3)
+    assert r1["status"] == "PSK_EINVAL" and r3["status"] == "PSK_EINVAL"
+    assert r2["status"] == "PSK_OK" and torch.isfinite(x2).all()
+
+
+def _dense_problem(n=6000, d=20, seed=3):
+    a, b, _ = synth.lsq_problem(n, d, 100.0, seed=seed)
+    return to_device(a), torch.as_tensor(b, device="cuda")
+
+
+def test_nonfinite_factoring_calls(api):
+    A, b = _dense_problem()
+    n, d = A.shape
+    for bad in (float("nan"), float("inf")):
+        An = A.clone(); An[n // 2, d // 3] = bad
+        bn = b.clone(); bn[7] = bad
+        Acsr = api.CsrMatrix.from_scipy(sp.csr_matrix(An.cpu().numpy()))
+        for prec in ("f64", "bf16", "fp8"):
+            _say(f"non-finite {bad} prec {prec}")
+            assert _status(lambda: api.leverage_sketch(An, 4 * d, 16 * d, 1, prec=prec)) \
+                == ENONFINITE
+            assert _status(lambda: api.lsq_solve(An, b, m=4 * d, r=16 * d, seed=1,
+                                                 prec=prec)) == ENONFINITE
+            assert _status(lambda: api.lsq_solve(A, bn, m=4 * d, r=16 * d, seed=1,
+                                                 prec=prec)) == ENONFINITE
+            assert _status(lambda: api.css_select(An, 4 * d, 16 * d, 3, 1, prec=prec)) \
+                == ENONFINITE
+            assert _status(lambda: api.lsq_sketch_solve(A, bn, 4 * d, 16 * d, 1, prec=prec)) \
+                == ENONFINITE
+        assert _status(lambda: api.leverage_sketch(Acsr, 4 * d, 16 * d, 1)) == ENONFINITE
+        assert _status(lambda: api.leverage_gram(An)) == ENONFINITE
+        assert _status(lambda: api.leverage_gram(Acsr)) == ENONFINITE
+        assert _status(lambda: api.lsq_gram(A, bn)) == ENONFINITE
+        assert _status(lambda: api.lsq_gram(An, b)) == ENONFINITE
+        assert _status(lambda: api.leverage_css(An, 4 * d, 16 * d, 3, 1)) == ENONFINITE
+    # the same calls on the finite problem succeed
+    assert _status(lambda: api.lsq_solve(A, b, m=4 * d, r=16 * d, seed=1)) == 0
+    assert _status(lambda: api.leverage_gram(A)) == 0
+    torch.cuda.synchronize()
+
+
+def test_nonfinite_propagates_into_sketches(api):
+    A, _ = _dense_problem(seed=9)
+    n, d = A.shape
+    An = A.clone(); An[123, 4] = float("nan")
+    for prec in ("f64", "bf16", "fp8"):
+        C = api.sketch_gcs(An, 4 * d, 16 * d, 2, prec=prec)
+        assert not torch.isfinite(C).all(), prec
+    SA = api.sketch_cs(An, 16 * d, 2)
+    assert torch.isnan(SA).any()
+    G = api.gram(An)
+    assert torch.isnan(G).any()
