@@ -127,14 +127,14 @@ def bucket_occupancy(n, r, seed):
 # ----------------------------------------------------------------------------
 # Gaussian matrix (generated in column blocks, never whole)
 # ----------------------------------------------------------------------------
-def gaussian_normals(m, b0, b1, seed, stream=1):
-    """Unscaled standard normals Z[a, b] for rows a < m, buckets b0 <= b < b1
-    (counter word 3 = stream)."""
+def gaussian_normals(m, b0, b1, seed, stream=1, a0=0):
+    """Unscaled standard normals Z[a, b] for rows a0 <= a < a0 + m, buckets
+    b0 <= b < b1 (counter word 3 = stream)."""
     if b1 <= b0 or m == 0:
         return np.zeros((m, max(b1 - b0, 0)))
     q0, q1 = b0 // 4, (b1 + 3) // 4
     q = np.arange(q0, q1, dtype=np.uint64)
-    a = np.arange(m, dtype=np.uint64)
+    a = np.arange(a0, a0 + m, dtype=np.uint64)
     ctr = np.zeros((m, q.size, 4), dtype=np.uint64)
     ctr[:, :, 0] = (q & np.uint64(0xFFFFFFFF))[None, :]
     ctr[:, :, 1] = (q >> np.uint64(32))[None, :]

@@ -126,6 +126,10 @@ def test_gaussian_column_blocks_consistent():
     for b0, b1 in [(0, 1), (1, 5), (3, 4), (5, 103), (50, 77)]:
         np.testing.assert_array_equal(osk.gaussian_normals(11, b0, b1, seed=4),
                                       full[:, b0:b1])
+    # and any row range: row a is drawn from counter word 2 = a alone
+    for a0, cnt in [(0, 3), (4, 7), (10, 1)]:
+        np.testing.assert_array_equal(osk.gaussian_normals(cnt, 0, 103, seed=4, a0=a0),
+                                      full[a0:a0 + cnt])
 
 
 def test_gaussian_embedding_isotropic():
