@@ -20,6 +20,9 @@ leverage QR of the sketch, R^{-1}, sketched and exact leverage scores
          (Alg. ``ls_approximate_drineas`` with QR instead of SVD).
 lsq      Least squares: LAPACK ground truth and sketch-and-precondition LSQR
          (Alg. ``least_squares_precondition``).
+osnap    OSNAP with s > 1 non-zeros per column (the generalisation of
+         CountSketch of Section 2's introduction), its S*A and G*S*A.
+css      Column subset selection by the pivoted QR of a sketch.
 
 Parity status: every function is pinned by a ``-m "not gpu"`` test in
 ``tests/test_oracle_*.py`` against something other than itself (published
