@@ -375,6 +375,31 @@ def zipf_workload(api, torch, steps, warmup, seed):
     wall, _ = timed(torch, f, steps, warmup)
     th = f()
     out["leverage_fp8"] = {"ms_per_call": 1e3 * wall, "sum_theta": float(th.sum().item())}
+    # OSNAP with s = 8 non-zeros per column at one eighth of the CountSketch
+    # rows: S*A costs s passes over the entries, the Gaussian product shrinks
+    # with r
+    s_os, r_os = 8, r // 8
+    osn = {"s": s_os, "r": r_os}
+    c64o = api.sketch_osnap(A, s_os, m, r_os, seed)
+    for prec in ("fp8", "f64"):
+        f = lambda: api.sketch_osnap(A, s_os, m, r_os, seed, prec=prec)
+        timed(torch, f, 0, warmup)
+        with api.kernel_timing() as kt:
+            wall, _ = timed(torch, f, steps, 0)
+            st = kt.stats()
+        osn[prec] = {"ms_per_call": 1e3 * wall, "gbs": nbytes / wall / 1e9,
+                     "stage_ms": {k: round(v[0] / steps, 4) for k, v in sorted(st.items())}}
+    osn["fp8"]["delta"] = api.sketch_delta(api.sketch_osnap(A, s_os, m, r_os, seed, prec="fp8"),
+                                           c64o).item()
+    del c64o
+
+    def lev_osnap():
+        _, ri = api.sketch_qr(api.sketch_osnap(A, s_os, m, r_os, seed, prec="fp8"))
+        return api.rownorms_sq(A, ri)
+    wall, _ = timed(torch, lev_osnap, steps, warmup)
+    osn["leverage_fp8"] = {"ms_per_call": 1e3 * wall,
+                           "sum_theta": float(lev_osnap().sum().item())}
+    out["osnap"] = osn
     return out
 
 

@@ -162,7 +162,8 @@ enum {
   PSK_OP_CSS = 11,
   PSK_OP_LEVERAGE_CSS = 12,
   PSK_OP_DELTA = 13,
-  PSK_OP_CHECK = 14
+  PSK_OP_CHECK = 14,
+  PSK_OP_SKETCH_OSNAP = 15   /* k = s, the non-zeros per column */
 };
 
 /* Library version string (static storage). */
@@ -179,10 +180,11 @@ const char *psk_last_error(void);
  *          LSQ_SKETCH, LEVERAGE_SKETCH, CSS, LEVERAGE_CSS; SKETCH_G reads m
  *          only);
  *   k    : columns of B (ROWNORMS), columns t of Pi (LEVERAGE_SKETCH),
- *          columns selected (CSS, LEVERAGE_CSS); for LSQ nonzero when the
- *          call will set opts->want_delta;
- *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_G, LSQ, LSQ_SKETCH, LEVERAGE_SKETCH,
- *          CSS, LEVERAGE_CSS).
+ *          columns selected (CSS, LEVERAGE_CSS), non-zeros s per column
+ *          (SKETCH_OSNAP); for LSQ nonzero when the call will set
+ *          opts->want_delta;
+ *   prec : PSK_PREC_* (SKETCH_GCS, SKETCH_OSNAP, SKETCH_G, LSQ, LSQ_SKETCH,
+ *          LEVERAGE_SKETCH, CSS, LEVERAGE_CSS).
  * For PSK_OP_LSQ, m == 0 sizes a call that passes its own opts->Rinv.
  * Arguments an op does not use are ignored. */
 int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r,
@@ -217,6 +219,47 @@ int sketch_cs(const psk_mat *A, int64_t r, uint64_t seed, void *SA,
  * Errors: as sketch_cs, plus PSK_EDTYPE for an unknown prec. */
 int sketch_gcs(const psk_mat *A, int64_t m, int64_t r, uint64_t seed,
                int prec, void *C, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- OSNAP with s > 1 non-zeros per column ------------------------------
+ * Section 2's introduction: CountSketch is the OSNAP with s = 1, and its
+ * data structures and products carry over to any OSNAP.  This library
+ * builds the block construction: the r rows of S form s blocks of r/s rows
+ * (s must divide r), and column i has one non-zero in each block, so its s
+ * non-zeros lie in s distinct rows; each equals sigma / sqrt(s).  Non-zero k
+ * of column i (k = 0 .. s-1) is drawn like the CountSketch hash with k in
+ * counter word 2:
+ *   x = Philox(ctr=(i lo32, i hi32, k, 0), key=(seed lo32, seed hi32)),
+ *   row = k (r/s) + floor((x1*2^32 + x0) * (r/s) / 2^64),
+ *   sigma = x2 even ? +1 : -1.
+ * s = 1 is the CountSketch of cs_hash / sketch_cs / sketch_gcs exactly.  Each
+ * column of S has unit norm, so E[S^T S] = I. */
+
+/* Rows and signs of the s non-zeros of columns row0 .. row0+count-1.
+ *   h    : count*s int32 rows in [0, r), non-zero k of column row0+i at
+ *          h[i*s + k]                                  (device, may be NULL)
+ *   sign : count*s int8 signs in {+1, -1}, same layout (device, may be NULL)
+ * Errors: PSK_EINVAL if count < 0, row0 < 0, r out of [1, 2^31), s < 1,
+ * s > r, r not a multiple of s, or count * s >= 2^40. */
+int osnap_hash(int64_t row0, int64_t count, int64_t s, int64_t r, uint64_t seed, int32_t *h,
+               int8_t *sign, void *stream);
+
+/* C = G*(S*A) (m > 0) or S*A (m == 0) with the OSNAP S of s non-zeros per
+ * column (Algorithms bcs_multiply and countgauss_multiply with this S).  The
+ * n*s (row, non-zero) pairs are binned by row of S exactly as sketch_cs bins
+ * rows (stable, each row of S lists its columns in increasing order); each
+ * row of S*A is the FP64 sum of its signed rows of A in that order times
+ * 1/sqrt(s), rounded once to the output type.  G is the same matrix as in
+ * sketch_gcs for (m, r, seed), applied to S*A as its FP64 operand in any of
+ * the three precisions.
+ *   s    : non-zeros per column, 1 <= s <= r, r % s == 0, n*s < 2^32.
+ *   C    : m x d row-major FP64 (m > 0), or r x d in the dtype of A (m == 0).
+ *   ws   : psk_workspace_size(PSK_OP_SKETCH_OSNAP, A, m, r, s, prec) bytes
+ *          (the bins of n*s pairs; for m > 0 also S*A, r x d FP64).
+ * s == 1 returns exactly what sketch_gcs returns.
+ * Errors: as sketch_gcs, plus PSK_EINVAL for s out of range and
+ * PSK_EUNSUPPORTED for n*s >= 2^32. */
+int sketch_osnap(const psk_mat *A, int64_t s, int64_t m, int64_t r, uint64_t seed, int prec,
+                 void *C, void *ws, size_t ws_bytes, void *stream);
 
 /* C = G*A (section "Gaussian sketching", Algorithm gaussian_sketch; csrjlt),
  * G the m x n Gaussian matrix with entries of variance 1/m.  Column i of G

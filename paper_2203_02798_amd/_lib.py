@@ -28,13 +28,13 @@ PSK_PREC_F64, PSK_PREC_BF16, PSK_PREC_FP8 = 0, 1, 2
 (PSK_OP_SKETCH_CS, PSK_OP_SKETCH_GCS, PSK_OP_GRAM, PSK_OP_ROWNORMS, PSK_OP_QR,
  PSK_OP_LSQ, PSK_OP_SKETCH_G, PSK_OP_LEVERAGE_GRAM, PSK_OP_LSQ_GRAM,
  PSK_OP_LSQ_SKETCH, PSK_OP_LEVERAGE_SKETCH, PSK_OP_CSS, PSK_OP_LEVERAGE_CSS,
- PSK_OP_DELTA, PSK_OP_CHECK) = range(15)
+ PSK_OP_DELTA, PSK_OP_CHECK, PSK_OP_SKETCH_OSNAP) = range(16)
 PSK_EINVAL, PSK_ERANK, PSK_ENONFINITE = -1, -6, -8
 
 EXPORTED = ["psk_version", "psk_last_error", "psk_workspace_size", "cs_hash",
             "sketch_cs", "sketch_gcs", "sketch_g", "gram", "rownorms_sq", "sketch_qr",
             "lsq_solve", "leverage_sketch", "css_select", "leverage_css", "leverage_gram",
-            "lsq_gram", "lsq_sketch_solve", "sketch_delta", "sketch_qr_noalloc", "psk_check",
+            "lsq_gram", "lsq_sketch_solve", "sketch_delta", "sketch_qr_noalloc", "psk_check", "osnap_hash", "sketch_osnap",
             "psk_probe_copy", "psk_probe_mfma_f64", "psk_probe_mfma_lowp",
             "psk_probe_valu_f32",
             "psk_timing_enable", "psk_timing_only", "psk_timing_reset",
@@ -175,6 +175,9 @@ _SIGS = {
                           _vp], ctypes.c_int),
     "sketch_delta": ([_vp, _vp, _i64, _i64, _vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "psk_check": ([_PM, ctypes.c_int, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+    "osnap_hash": ([_i64, _i64, _i64, _i64, _u64, _vp, _vp, _vp], ctypes.c_int),
+    "sketch_osnap": ([_PM, _i64, _i64, _i64, _u64, ctypes.c_int, _vp, _vp, ctypes.c_size_t,
+                      _vp], ctypes.c_int),
     "psk_probe_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "psk_probe_mfma_f64": ([_i64, _vp, _vp], ctypes.c_int),
     "psk_probe_mfma_lowp": ([ctypes.c_int, _i64, _vp, _vp], ctypes.c_int),

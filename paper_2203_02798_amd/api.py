@@ -166,6 +166,32 @@ def sketch_gcs(A, m, r, seed, prec="f64", out=None):
     return out
 
 
+def osnap_hash(count, s, r, seed, row0=0, device="cuda"):
+    """(h int32[count, s], sign int8[count, s]): the rows and signs of the s
+    non-zeros of columns row0 .. row0+count-1 of the OSNAP S."""
+    h = torch.empty((count, s), dtype=torch.int32, device=device)
+    sg = torch.empty((count, s), dtype=torch.int8, device=device)
+    L.check(L.lib().osnap_hash(row0, count, s, r, seed, h.data_ptr() if count else None,
+                               sg.data_ptr() if count else None,
+                               _stream(torch.device(device))), "osnap_hash")
+    return h, sg
+
+
+def sketch_osnap(A, s, m, r, seed, prec="f64", out=None):
+    """G*S*A (m x d, float64) or, with m == 0, S*A (r x d, dtype of A), S the
+    OSNAP with s non-zeros per column."""
+    pm = _mat(A)
+    dev = _device(A)
+    if out is None:
+        shape, dt = ((m, pm.d), torch.float64) if m > 0 else ((r, pm.d), A.dtype)
+        out = torch.empty(shape, dtype=dt, device=dev)
+    nbytes = workspace_size(L.PSK_OP_SKETCH_OSNAP, A, m=m, r=r, k=s, prec=prec)
+    ws = _ws(nbytes, dev)
+    L.check(L.lib().sketch_osnap(ctypes.byref(pm), s, m, r, seed, _PREC[prec], out.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _stream(dev)), "sketch_osnap")
+    return out
+
+
 def sketch_g(A, m, seed, prec="f64", out=None):
     """G*A (m x d, float64), G the m x n Gaussian of variance 1/m."""
     pm = _mat(A)

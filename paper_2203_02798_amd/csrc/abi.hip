@@ -142,6 +142,22 @@ int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int pre
   return gauss_gemm(m, r, A.d, seed, prec, SA, PSK_F64, (double *)C, ws, st);
 }
 
+int do_sketch_osnap(const psk_mat &A, int64_t s, int64_t m, int64_t r, uint64_t seed,
+                    int prec, void *C, Arena &ws, hipStream_t st) {
+  if (s == 1) return do_sketch_gcs(A, m, r, seed, prec, C, ws, st);
+  uint32_t *perm = nullptr, *bptr = nullptr;
+  int rc = osnap_bin(A.n, (uint32_t)s, (uint32_t)r, seed, ws, st, &perm, &bptr);
+  if (rc) return rc;
+  // each bucket's signed rows summed in FP64, times 1/sqrt(s) once
+  const double scale = 1.0 / sqrt((double)s);
+  const int64_t entries = A.n * s;
+  if (m == 0)
+    return cs_apply(A, (uint32_t)r, perm, bptr, C, ws, st, false, scale, entries);
+  void *SA = ws.take<double>((size_t)r * A.d);
+  if ((rc = cs_apply(A, (uint32_t)r, perm, bptr, SA, ws, st, true, scale, entries))) return rc;
+  return gauss_gemm(m, r, A.d, seed, prec, SA, PSK_F64, (double *)C, ws, st);
+}
+
 int do_sketch_g(const psk_mat &A, int64_t m, uint64_t seed, int prec, double *C, Arena &ws,
                 hipStream_t st) {
   if (A.format == PSK_CSR) {
@@ -217,6 +233,15 @@ const char *psk_timing_names(void) {
 
 const char *psk_last_error(void) { return g_last_error.c_str(); }
 
+// Shapes of an OSNAP: 1 <= s <= r with s | r, and n s < 2^32 (bin positions
+// are 32-bit).
+static int check_osnap(const psk_mat &A, int64_t s, int64_t r) {
+  if (s < 1 || s > r || r % s != 0)
+    return fail(PSK_EINVAL, "OSNAP needs 1 <= s <= r with s dividing r");
+  if (A.n * s >= ((int64_t)1 << 32)) return fail(PSK_EUNSUPPORTED, "OSNAP needs n * s < 2^32");
+  return 0;
+}
+
 // Shapes of leverage_sketch: the sketch has m >= d rows (G S A) or, with
 // m == 0, r >= d rows (S A); t >= 0 columns of Pi, d * t < 2^31.
 static int check_leverage_sketch(const psk_mat &A, int64_t m, int64_t r, int64_t t,
@@ -256,6 +281,12 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
   switch (op) {
     case PSK_OP_CHECK:
       rc = check_operand(*A, true, ws, nullptr);
+      break;
+    case PSK_OP_SKETCH_OSNAP:
+      if ((rc = check_r(r))) return rc;
+      if ((rc = check_osnap(*A, k, r))) return rc;
+      if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "m must be in [0, 2^31)");
+      rc = do_sketch_osnap(*A, k, m, r, 0, prec, nullptr, ws, nullptr);
       break;
     case PSK_OP_SKETCH_CS:
       if ((rc = check_r(r))) return rc;
@@ -379,6 +410,38 @@ int sketch_gcs(const psk_mat *A, int64_t m, int64_t r, uint64_t seed, int prec,
   Arena ws = Arena::over(wsp, ws_bytes);
   if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
   return do_sketch_gcs(*A, m, r, seed, prec, C, ws, as_stream(stream));
+}
+
+int osnap_hash(int64_t row0, int64_t count, int64_t s, int64_t r, uint64_t seed, int32_t *h,
+               int8_t *sign, void *stream) {
+  if (count < 0 || row0 < 0) return fail(PSK_EINVAL, "count and row0 must be >= 0");
+  int rc = check_r(r);
+  if (rc) return rc;
+  if (s < 1 || s > r || r % s != 0)
+    return fail(PSK_EINVAL, "OSNAP needs 1 <= s <= r with s dividing r");
+  if (count > (((int64_t)1 << 40) - 1) / s) return fail(PSK_EINVAL, "count * s must be < 2^40");
+  return osnap_hash_export(row0, count, (uint32_t)s, (uint32_t)r, seed, h, sign,
+                           as_stream(stream));
+}
+
+int sketch_osnap(const psk_mat *A, int64_t s, int64_t m, int64_t r, uint64_t seed, int prec,
+                 void *C, void *wsp, size_t ws_bytes, void *stream) {
+  int rc = check_mat(A);
+  if (rc) return rc;
+  if ((rc = check_r(r))) return rc;
+  if ((rc = check_osnap(*A, s, r))) return rc;
+  if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PSK_EINVAL, "m must be in [0, 2^31)");
+  if (m > 0 && prec != PSK_PREC_F64 && prec != PSK_PREC_BF16 && prec != PSK_PREC_FP8)
+    return fail(PSK_EDTYPE, "prec must be PSK_PREC_F64, PSK_PREC_BF16 or PSK_PREC_FP8");
+  if (!C) return fail(PSK_EINVAL, "C is NULL");
+  Arena plan;
+  if ((rc = validate_csr(*A, plan, nullptr))) return rc;
+  if ((rc = do_sketch_osnap(*A, s, m, r, seed, prec, nullptr, plan, nullptr))) return rc;
+  if (!wsp || ws_bytes < plan.peak)
+    return fail(PSK_ENOMEM, "workspace smaller than psk_workspace_size(PSK_OP_SKETCH_OSNAP)");
+  Arena ws = Arena::over(wsp, ws_bytes);
+  if ((rc = validate_csr(*A, ws, as_stream(stream)))) return rc;
+  return do_sketch_osnap(*A, s, m, r, seed, prec, C, ws, as_stream(stream));
 }
 
 int sketch_g(const psk_mat *A, int64_t m, uint64_t seed, int prec, double *C, void *wsp,

@@ -70,6 +70,20 @@ __host__ __device__ __forceinline__ void cs_hash_row(uint64_t i, uint32_t r, uin
   neg = x.x2 & 1u;
 }
 
+// Non-zero k (0 <= k < s) of column i of an OSNAP with s blocks of rb rows
+// (block construction): the CountSketch hash with k in counter word 2, its
+// range reduced to the block, offset to block k.  k = 0 with rb = r is
+// cs_hash_row.
+__host__ __device__ __forceinline__ void osnap_hash_nz(uint64_t i, uint32_t k, uint32_t rb,
+                                                       uint64_t seed, uint32_t &row,
+                                                       uint32_t &neg) {
+  const u32x4 x = philox4x32_10((uint32_t)i, (uint32_t)(i >> 32), k, 0u, (uint32_t)seed,
+                                (uint32_t)(seed >> 32));
+  const uint64_t X = ((uint64_t)x.x1 << 32) | x.x0;
+  row = k * rb + (uint32_t)(((unsigned __int128)X * (uint64_t)rb) >> 64);
+  neg = x.x2 & 1u;
+}
+
 // ---------------------------------------------------------------------------
 // Lean FP64 elementary functions for Box-Muller, on the ranges it needs.
 // Accuracy about 1e-16 relative; no branches.

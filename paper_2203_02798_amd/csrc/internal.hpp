@@ -73,10 +73,19 @@ int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
 int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
                    int32_t *h, int8_t *sign, hipStream_t st);
 // S*A into SA (r x d row-major): each bucket's rows summed in FP64 in bin
-// order, written in the dtype of A, or in FP64 with out_f64.
+// order, multiplied by scale, written in the dtype of A, or in FP64 with
+// out_f64.  entries: bin entries in all (n for CountSketch, n s for an
+// OSNAP; 0 means n), which sizes the split of long buckets.
 int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
              const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st,
-             bool out_f64 = false);
+             bool out_f64 = false, double scale = 1.0, int64_t entries = 0);
+// OSNAP with s non-zeros per row (block construction, s | r): bins of the
+// n s (row, non-zero) pairs, as cs_bin; the hash export writes count * s
+// rows and signs, non-zero k of row row0 + i at [i s + k].
+int osnap_bin(int64_t n, uint32_t s, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
+              uint32_t **perm, uint32_t **bptr);
+int osnap_hash_export(int64_t row0, int64_t count, uint32_t s, uint32_t r, uint64_t seed,
+                      int32_t *h, int8_t *sign, hipStream_t st);
 // Wavefronts per bucket cs_apply uses for n rows in r buckets (1 = one
 // wavefront sums a whole bucket).
 int cs_splits(int64_t n, int64_t r);
@@ -114,6 +123,10 @@ int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws
                  hipStream_t st, bool out_f64 = false);
 int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int prec,
                   void *C, Arena &ws, hipStream_t st);
+// G*S*A (m > 0) or S*A (m == 0) with the OSNAP S of s non-zeros per row;
+// s == 1 is do_sketch_gcs itself.
+int do_sketch_osnap(const psk_mat &A, int64_t s, int64_t m, int64_t r, uint64_t seed,
+                    int prec, void *C, Arena &ws, hipStream_t st);
 // C = G*A (sketch_g): the Gaussian GEMM with A as operand (dense), or the
 // sparse product over A's entries with one row per bucket (CSR)
 int do_sketch_g(const psk_mat &A, int64_t m, uint64_t seed, int prec, double *C, Arena &ws,

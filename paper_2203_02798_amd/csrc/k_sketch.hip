@@ -52,6 +52,38 @@ __global__ __launch_bounds__(256) void k_hash_keys(int64_t n, uint32_t r,
   vals[i] = (uint32_t)i | (neg << 31);
 }
 
+// OSNAP with s non-zeros per row of A (block construction): pair j = i s + k
+// is non-zero k of row i, so each row's s entries are adjacent and, after the
+// stable sort, every bucket lists its rows in increasing order
+__global__ __launch_bounds__(256) void k_hash_keys_osnap(int64_t pairs, uint32_t s,
+                                                         uint32_t rb, uint64_t seed,
+                                                         uint32_t *__restrict__ keys,
+                                                         uint32_t *__restrict__ vals) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= pairs) return;
+  const int64_t i = j / s;
+  const uint32_t k = (uint32_t)(j - i * s);
+  uint32_t b, neg;
+  osnap_hash_nz((uint64_t)i, k, rb, seed, b, neg);
+  keys[j] = b;
+  vals[j] = (uint32_t)i | (neg << 31);
+}
+
+__global__ __launch_bounds__(256) void k_hash_export_osnap(int64_t row0, int64_t pairs,
+                                                           uint32_t s, uint32_t rb,
+                                                           uint64_t seed,
+                                                           int32_t *__restrict__ h,
+                                                           int8_t *__restrict__ sign) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= pairs) return;
+  const int64_t i = j / s;
+  const uint32_t k = (uint32_t)(j - i * s);
+  uint32_t b, neg;
+  osnap_hash_nz((uint64_t)(row0 + i), k, rb, seed, b, neg);
+  if (h) h[j] = (int32_t)b;
+  if (sign) sign[j] = neg ? (int8_t)-1 : (int8_t)1;
+}
+
 // ---------------------------------------------------------------------------
 // radix sort pass: per-tile digit histogram (digit-major layout)
 // ---------------------------------------------------------------------------
@@ -283,7 +315,7 @@ template <typename T, typename TO, int VW, int CH, int U>
 __global__ __launch_bounds__(256) void k_scatter_dense(
     const T *__restrict__ A, int64_t ld, int64_t d, int64_t r,
     const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
-    int splits, TO *__restrict__ out) {
+    int splits, double scale, TO *__restrict__ out) {
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (wave >= r * splits) return;
   const int64_t b = wave / splits;
@@ -346,7 +378,7 @@ __global__ __launch_bounds__(256) void k_scatter_dense(
       if (cok[c]) {
         TO ov[VW];
 #pragma unroll
-        for (int q = 0; q < VW; ++q) ov[q] = (TO)acc[c][q];
+        for (int q = 0; q < VW; ++q) ov[q] = (TO)(acc[c][q] * scale);
         store_out<TO, VW>(orow + coff[c], ov);
       }
     }
@@ -363,7 +395,7 @@ __global__ __launch_bounds__(256) void k_scatter_csr(
     const T *__restrict__ vals, const int64_t *__restrict__ indptr,
     const int32_t *__restrict__ indices, int64_t d, int64_t dpad, int64_t r,
     const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
-    int splits, TO *__restrict__ out) {
+    int splits, double scale, TO *__restrict__ out) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *acc = reinterpret_cast<double *>(smem_raw) + (threadIdx.x >> 6) * dpad;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -382,7 +414,7 @@ __global__ __launch_bounds__(256) void k_scatter_csr(
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
   TO *orow = out + ((int64_t)s * r + b) * d;
-  for (int64_t c = lane; c < d; c += 64) orow[c] = (TO)acc[c];
+  for (int64_t c = lane; c < d; c += 64) orow[c] = (TO)(acc[c] * scale);
 }
 
 // SA[b, c] = sum over splits of partial[s, b, c] (FP64), splits in
@@ -390,12 +422,13 @@ __global__ __launch_bounds__(256) void k_scatter_csr(
 template <typename TO>
 __global__ __launch_bounds__(256) void k_combine_splits(const double *__restrict__ part,
                                                         int64_t rd, int splits,
+                                                        double scale,
                                                         TO *__restrict__ SA) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= rd) return;
   double acc = part[e];
   for (int s = 1; s < splits; ++s) acc += part[(int64_t)s * rd + e];
-  SA[e] = (TO)acc;
+  SA[e] = (TO)(acc * scale);
 }
 
 int choose_splits(int64_t n, int64_t r) {
@@ -412,26 +445,27 @@ int choose_splits(int64_t n, int64_t r) {
 
 template <typename T, typename TO, int VW>
 void launch_dense(const psk_mat &A, int64_t r, const uint32_t *perm,
-                  const uint32_t *bptr, int splits, TO *out, hipStream_t st) {
+                  const uint32_t *bptr, int splits, double scale, TO *out, hipStream_t st) {
   const int64_t waves = r * splits;
   const unsigned blocks = (unsigned)ceil_div(waves, 4);
   const int64_t span1 = 64 * VW;  // columns per lane group
   if (A.d <= span1)
     k_scatter_dense<T, TO, VW, 1, 8><<<blocks, 256, 0, st>>>(
-        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
+        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, scale, out);
   else if (A.d <= 2 * span1)
     k_scatter_dense<T, TO, VW, 2, 4><<<blocks, 256, 0, st>>>(
-        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
+        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, scale, out);
   else
     k_scatter_dense<T, TO, VW, 4, 4><<<blocks, 256, 0, st>>>(
-        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, out);
+        (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, scale, out);
 }
 
 // VW adjacent columns per lane where the rows of A and of the output allow
 // aligned vector accesses
 template <typename T, typename TO>
 void launch_dense_vw(const psk_mat &A, int64_t r, const uint32_t *perm,
-                     const uint32_t *bptr, int splits, TO *out, hipStream_t st) {
+                     const uint32_t *bptr, int splits, double scale, TO *out,
+                     hipStream_t st) {
   const uintptr_t addr = (uintptr_t)A.values, oaddr = (uintptr_t)out;
   constexpr int es = (int)sizeof(T), os = (int)sizeof(TO);
   const bool v4 = es == 4 && (A.d % 4 == 0) && (A.ld % 4 == 0) && (addr % 16 == 0) &&
@@ -439,10 +473,10 @@ void launch_dense_vw(const psk_mat &A, int64_t r, const uint32_t *perm,
   const bool v2 = (A.d % 2 == 0) && (A.ld % 2 == 0) && (addr % (2 * es) == 0) &&
                   oaddr % (2 * os) == 0;
   if constexpr (sizeof(T) == 4) {
-    if (v4) return launch_dense<T, TO, 4>(A, r, perm, bptr, splits, out, st);
+    if (v4) return launch_dense<T, TO, 4>(A, r, perm, bptr, splits, scale, out, st);
   }
-  if (v2) return launch_dense<T, TO, 2>(A, r, perm, bptr, splits, out, st);
-  launch_dense<T, TO, 1>(A, r, perm, bptr, splits, out, st);
+  if (v2) return launch_dense<T, TO, 2>(A, r, perm, bptr, splits, scale, out, st);
+  launch_dense<T, TO, 1>(A, r, perm, bptr, splits, scale, out, st);
 }
 
 // LDS of the CSR scatter: FP64 accumulators of wpb wavefronts
@@ -523,9 +557,37 @@ int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
   return 0;
 }
 
+int osnap_hash_export(int64_t row0, int64_t count, uint32_t s, uint32_t r, uint64_t seed,
+                      int32_t *h, int8_t *sign, hipStream_t st) {
+  const int64_t pairs = count * (int64_t)s;
+  if (pairs == 0) return 0;
+  k_hash_export_osnap<<<(unsigned)ceil_div(pairs, 256), 256, 0, st>>>(row0, pairs, s, r / s,
+                                                                       seed, h, sign);
+  PSK_HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+int osnap_bin(int64_t n, uint32_t s, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
+              uint32_t **perm, uint32_t **bptr) {
+  const int64_t pairs = n * (int64_t)s;
+  uint32_t *k0 = ws.take<uint32_t>(pairs);
+  uint32_t *v0 = ws.take<uint32_t>(pairs);
+  uint32_t *bp = ws.take<uint32_t>((size_t)r + 1);
+  KTimer timer("cs_bin", st, !ws.dry());
+  if (!ws.dry())
+    k_hash_keys_osnap<<<(unsigned)ceil_div(pairs, 256), 256, 0, st>>>(pairs, s, r / s, seed,
+                                                                       k0, v0);
+  uint32_t *sk = nullptr;
+  int rc = sort_pairs(k0, v0, pairs, r, ws, st, &sk, perm, bp);
+  if (rc) return rc;
+  *bptr = bp;
+  return 0;
+}
+
 int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
-             const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st, bool out_f64) {
-  const int splits = choose_splits(A.n, r);
+             const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st, bool out_f64,
+             double scale, int64_t entries) {
+  const int splits = choose_splits(entries > 0 ? entries : A.n, r);
   const bool o64 = out_f64 || A.dtype == PSK_F64;
   void *part = nullptr;
   if (splits > 1) part = ws.take<double>((size_t)splits * r * A.d);
@@ -536,17 +598,18 @@ int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for S*A");
   KTimer timer("cs_scatter", st);
   if (A.format == PSK_DENSE) {
+    // K-split partials are written unscaled; the combine applies the scale
     if (splits > 1) {
       if (A.dtype == PSK_F64)
-        launch_dense_vw<double, double>(A, r, perm, bptr, splits, (double *)part, st);
+        launch_dense_vw<double, double>(A, r, perm, bptr, splits, 1.0, (double *)part, st);
       else
-        launch_dense_vw<float, double>(A, r, perm, bptr, splits, (double *)part, st);
+        launch_dense_vw<float, double>(A, r, perm, bptr, splits, 1.0, (double *)part, st);
     } else if (A.dtype == PSK_F64) {
-      launch_dense_vw<double, double>(A, r, perm, bptr, 1, (double *)SA, st);
+      launch_dense_vw<double, double>(A, r, perm, bptr, 1, scale, (double *)SA, st);
     } else if (o64) {
-      launch_dense_vw<float, double>(A, r, perm, bptr, 1, (double *)SA, st);
+      launch_dense_vw<float, double>(A, r, perm, bptr, 1, scale, (double *)SA, st);
     } else {
-      launch_dense_vw<float, float>(A, r, perm, bptr, 1, (float *)SA, st);
+      launch_dense_vw<float, float>(A, r, perm, bptr, 1, scale, (float *)SA, st);
     }
   } else {
     int wpb = 4;
@@ -554,24 +617,24 @@ int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
     const size_t lds = (size_t)wpb * dpad * 8;
     const int64_t waves = (int64_t)r * splits;
     const unsigned blocks = (unsigned)ceil_div(waves, wpb);
-#define PSK_SCSR(T, TO, OUT)                                                               \
+#define PSK_SCSR(T, TO, OUT, SC)                                                           \
   do {                                                                                     \
     if (lds > 65536)                                                                       \
       PSK_HIP_TRY(hipFuncSetAttribute((const void *)k_scatter_csr<T, TO>,                  \
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)); \
     k_scatter_csr<T, TO><<<blocks, 64 * wpb, lds, st>>>((const T *)A.values, A.indptr,     \
                                                         A.indices, A.d, dpad, r, perm, bptr, \
-                                                        splits, (TO *)(OUT));              \
+                                                        splits, (SC), (TO *)(OUT));        \
   } while (0)
     if (splits > 1) {
-      if (A.dtype == PSK_F64) PSK_SCSR(double, double, part);
-      else PSK_SCSR(float, double, part);
+      if (A.dtype == PSK_F64) PSK_SCSR(double, double, part, 1.0);
+      else PSK_SCSR(float, double, part, 1.0);
     } else if (A.dtype == PSK_F64) {
-      PSK_SCSR(double, double, SA);
+      PSK_SCSR(double, double, SA, scale);
     } else if (o64) {
-      PSK_SCSR(float, double, SA);
+      PSK_SCSR(float, double, SA, scale);
     } else {
-      PSK_SCSR(float, float, SA);
+      PSK_SCSR(float, float, SA, scale);
     }
 #undef PSK_SCSR
   }
@@ -579,10 +642,10 @@ int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
     const int64_t rd = (int64_t)r * A.d;
     if (o64)
       k_combine_splits<double><<<(unsigned)ceil_div(rd, 256), 256, 0, st>>>(
-          (const double *)part, rd, splits, (double *)SA);
+          (const double *)part, rd, splits, scale, (double *)SA);
     else
       k_combine_splits<float><<<(unsigned)ceil_div(rd, 256), 256, 0, st>>>(
-          (const double *)part, rd, splits, (float *)SA);
+          (const double *)part, rd, splits, scale, (float *)SA);
   }
   PSK_HIP_TRY(hipGetLastError());
   return 0;

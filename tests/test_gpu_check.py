@@ -165,6 +165,7 @@ def test_entry_points_refuse_malformed_csr(api):
         "sketch_gcs bf16": lambda A: api.sketch_gcs(A, 96, 512, 1, prec="bf16"),
         "sketch_gcs fp8": lambda A: api.sketch_gcs(A, 96, 512, 1, prec="fp8"),
         "sketch_g": lambda A: api.sketch_g(A, 96, 1),
+        "sketch_osnap": lambda A: api.sketch_osnap(A, 4, 96, 512, 1),
         "gram": lambda A: api.gram(A),
         "rownorms_sq": lambda A: api.rownorms_sq(A, B),
         "leverage_sketch": lambda A: api.leverage_sketch(A, 96, 512, 1),
