@@ -406,7 +406,8 @@ def zipf_workload(api, torch, steps, warmup, seed):
 # ---------------------------------------------------------------------------
 # serving: 512 least-squares requests, Poisson arrivals, HBM-pool admission
 # ---------------------------------------------------------------------------
-def serving_bench(api, torch, num=512, slots=8, pools_gb=(32.0, 128.0), n_hi=1e6):
+def serving_bench(api, torch, num=512, slots=8, pools_gb=(32.0, 128.0), n_hi=1e6,
+                  mfs=(8, 32)):
     import synth
     log(f"serving: drawing {num} requests on the device")
     reqs = synth.lsq_trace_torch(num, 0, 1e4, n_hi, device="cuda:0")
@@ -444,16 +445,23 @@ def serving_bench(api, torch, num=512, slots=8, pools_gb=(32.0, 128.0), n_hi=1e6
 
     runs = {}
     sols = {}
-    for pool_gb in pools_gb:
-        for prec in ("f64", "bf16", "fp8"):
-            key = f"{prec}_m8d_pool{int(pool_gb)}g"
-            log(f"serving: closed loop {key}")
-            runs[key], _, sols[key] = run(prec, 8, pool_gb)
-    ok = lambda k: runs[k]["failed"] == 0
+    # every precision at m = 8d in each pool, and at m = 32d in the larger
+    # pool: a cheaper Gaussian product affords more sketch rows, which cut
+    # LSQR's iterations (cond(A R^-1) <= (1 + eps) / (1 - eps), eps ~ sqrt(d/m))
     big = int(max(pools_gb))
-    best64 = f"f64_m8d_pool{big}g"
-    red = [k for k in runs if not k.startswith("f64") and k.endswith(f"pool{big}g") and ok(k)]
+    grid = [(prec, 8, pool_gb) for pool_gb in pools_gb for prec in ("f64", "bf16", "fp8")]
+    grid += [(prec, mf, float(big)) for mf in mfs if mf != 8 for prec in ("f64", "bf16", "fp8")]
+    for prec, mf, pool_gb in grid:
+        key = f"{prec}_m{mf}d_pool{int(pool_gb)}g"
+        log(f"serving: closed loop {key}")
+        runs[key], _, sols[key] = run(prec, mf, pool_gb)
+    ok = lambda k: runs[k]["failed"] == 0
+    at_big = [k for k in runs if k.endswith(f"pool{big}g") and ok(k)]
+    best64 = max([k for k in at_big if k.startswith("f64")],
+                 key=lambda k: runs[k]["solves_per_s"])
+    red = [k for k in at_big if not k.startswith("f64")]
     bestred = max(red, key=lambda k: runs[k]["solves_per_s"]) if red else None
+    mf_of = lambda k: int(k.split("_m")[1].split("d_")[0])
     # residuals of each reduced-precision solution against the FP64 one
     rel = {}
     for key in red:
@@ -485,13 +493,14 @@ def serving_bench(api, torch, num=512, slots=8, pools_gb=(32.0, 128.0), n_hi=1e6
     arr = np.cumsum(np.random.default_rng(1).exponential(1.0 / rate, size=num))
     log(f"serving: open loop at {rate:.1f}/s")
     open_loop = {}
-    open_loop["f64"], _, _ = run("f64", 8, float(big), arrivals=arr)
+    open_loop["f64"], _, _ = run("f64", mf_of(best64), float(big), arrivals=arr)
     if bestred:
         pr = runs[bestred]["prec"]
-        open_loop[pr], _, _ = run(pr, 8, float(big), arrivals=arr)
+        open_loop[pr], _, _ = run(pr, mf_of(bestred), float(big), arrivals=arr)
     out = {
         "trace": (f"{num} synthetic LSQ requests, n log-uniform [1e4, {n_hi:.0e}], d in "
-                  "{32,64,128,256}, cond log-uniform [1, 1e8], b = A x + 1e-3 e, m = 8d, "
+                  "{32,64,128,256}, cond log-uniform [1, 1e8], b = A x + 1e-3 e, "
+                  f"m in {{{', '.join(f'{mf}d' for mf in mfs)}}}, "
                   "r = max(min(d^2, n), m); A resident in HBM before submission"),
         "a_bytes_total": abytes, "slots": slots, "pools_gb": list(pools_gb),
         "closed_loop": runs,
@@ -566,6 +575,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run the serving trace alone and print its record")
     ap.add_argument("--no-extras", action="store_true",
                     help="the headline step only (hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -594,6 +605,9 @@ def main():
         return
 
     torch.cuda.set_device(0)
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(api, torch)}), flush=True)
+        return
     seed = args.seed
     n, d, r, m = HEAD["n"], HEAD["d"], HEAD["r"], HEAD["m"]
     log(f"generating the dense coherent FP32 {n} x {d} matrix on the device")
