@@ -13,7 +13,9 @@
 //         of each column, G with the fixed scale 2^-6.
 // Only the 4-bucket quads of G that meet an entry of S*A are drawn: with
 // counter-based normals and G's rounding decided per value, the others are
-// never needed.
+// never needed.  The product walks G in blocks of QB such quads (QB = 128,
+// 64 with G in FP64) taken from the list of occupied quads in bucket order,
+// so the number of blocks follows the nonzeros of S*A, not r.
 // FP64 accumulates in FP64.  BF16 and FP8 accumulate in FP32 within a K
 // split, as the dense reduced-precision kernels do (each product is exact
 // inside the FMA; BF16's value hi + lo is rounded to FP32 where its limbs
@@ -30,9 +32,11 @@
 //                      unused slots as holes (column -1);
 //   k_entries_fp8      (FP8) the per-column, per-128-bucket scale and the
 //                      e4m3 rounding of the values;
-//   k_block_entries    the first slot of every G block (512 buckets; 256
-//                      for FP64);
-//   k_block_csc        each G block's entries sorted by (column, bucket),
+//   k_quad_flags + scan  the rank of every occupied 4-bucket quad;
+//   k_quad_list        the occupied quads in order, the G blocks of QB of
+//                      them, each block's first entry slot, the count;
+//   k_block_csc        each G block's entries sorted by (column, slot of
+//                      their bucket in the block: 4 rank + bucket mod 4),
 //                      packed with their column's run length;
 //   k_gauss_sparse     workgroup (32- or 16-row tile of C, a range of G
 //                      blocks): per block it draws G for its rows into LDS
@@ -63,15 +67,42 @@ __global__ __launch_bounds__(256) void k_row_nnz(const int64_t *__restrict__ ind
   rn[j] = v;
 }
 
-// be[k] = first entry slot of bucket block k of blk buckets (be[nblk] = total)
-__global__ __launch_bounds__(256) void k_block_entries(const uint32_t *__restrict__ bptr,
-                                                       const uint32_t *__restrict__ eoff,
-                                                       int64_t r, int64_t blk, int64_t nblk,
-                                                       uint32_t *__restrict__ be) {
-  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (k > nblk) return;
-  const int64_t b = k * blk < r ? k * blk : r;
-  be[k] = eoff[bptr[b]];
+// qf[q] = 1 when quad q (buckets 4q .. 4q + 3) holds an entry, else 0;
+// qf[nquads] = 0 (an exclusive scan then gives ranks and the count)
+__global__ __launch_bounds__(256) void k_quad_flags(const uint32_t *__restrict__ bptr,
+                                                    const uint32_t *__restrict__ eoff, int64_t r,
+                                                    int64_t nquads, uint32_t *__restrict__ qf) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q > nquads) return;
+  uint32_t f = 0u;
+  if (q < nquads) {
+    const int64_t b0 = 4 * q, b1 = b0 + 4 < r ? b0 + 4 : r;
+    f = eoff[bptr[b1]] > eoff[bptr[b0]] ? 1u : 0u;
+  }
+  qf[q] = f;
+}
+
+// From the scanned flags (qrank[q] = occupied quads before q, qrank[nquads]
+// = their count): qlist[rank] = q for every occupied quad; G block s holds
+// ranks QB s .. QB s + QB - 1 and its entries start at slot be[s] (the
+// quads between two occupied ones own no slots); be[blocks] = all slots.
+__global__ __launch_bounds__(256) void k_quad_list(const uint32_t *__restrict__ bptr,
+                                                   const uint32_t *__restrict__ eoff,
+                                                   const uint32_t *__restrict__ qrank, int64_t r,
+                                                   int64_t nquads, int qb,
+                                                   uint32_t *__restrict__ qlist,
+                                                   uint32_t *__restrict__ be) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q > nquads) return;
+  if (q == nquads) {
+    const uint32_t nb = (qrank[nquads] + (uint32_t)qb - 1u) / (uint32_t)qb;
+    be[nb] = eoff[bptr[r]];
+    return;
+  }
+  const uint32_t rk = qrank[q];
+  if (qrank[q + 1] == rk) return;  // empty quad
+  qlist[rk] = (uint32_t)q;
+  if (rk % (uint32_t)qb == 0u) be[rk / (uint32_t)qb] = eoff[bptr[4 * q]];
 }
 
 // bfloat16 (RNE) of a double in one rounding (round-to-odd to FP32 first)
@@ -305,45 +336,45 @@ __global__ __launch_bounds__(256) void k_entries_fp8(const uint32_t *__restrict_
 constexpr uint32_t kHole = 0xffffffffu;
 constexpr int kCscCols = 1024;  // columns of S*A the block sort takes at most
 
-// Entries of G block blockIdx.x (32 W buckets, slots be[k] .. be[k+1]) in
-// (column, bucket) order: the valid ones first, packed, then the holes.
-// Each bucket holds a column at most once, so an entry's place among its
-// column's entries is the number of the column's buckets before its own:
-// a bitmap of buckets per column, its popcounts and a scan over the
-// columns give every entry its slot, with no dependence on timing.
-// Also qmask[4 k .. 4 k + 3]: the 4-bucket quads of the block that hold an
-// entry (bit j of word i: quad 32 i + j), the Philox blocks of G the product
-// has to draw for this block.
-template <int W>
+// Entries of G block blockIdx.x (8 W occupied quads, slots be[k] ..
+// be[k+1]) in (column, bucket) order: the valid ones first, packed, then
+// the holes.  A bucket's place in the block is 4 (rank of its quad in the
+// block) + bucket mod 4, below 32 W.  Each bucket holds a column at most
+// once, so an entry's place among its column's entries is the number of the
+// column's buckets before its own: a bitmap of buckets per column, its
+// popcounts and a scan over the columns give every entry its slot, with no
+// dependence on timing.  Blocks past the count (qrank[nquads] quads) exit.
+template <int W, typename VT>
 __global__ __launch_bounds__(512) void k_block_csc(const uint32_t *__restrict__ be,
                                                    const uint32_t *__restrict__ eb,
                                                    const int32_t *__restrict__ ec,
                                                    const double *__restrict__ ev, int64_t d,
+                                                   const uint32_t *__restrict__ qrank,
+                                                   int64_t nquads,
                                                    uint32_t *__restrict__ sp,
-                                                   double *__restrict__ sv,
-                                                   uint32_t *__restrict__ qmask) {
+                                                   VT *__restrict__ sv) {
   __shared__ uint32_t bits[kCscCols * W];   // [column][word]: buckets present
   __shared__ uint16_t wpre[kCscCols * W];   // buckets present in the words before
   __shared__ uint32_t ccnt[kCscCols];       // entries per column
   __shared__ uint32_t cst[kCscCols];        // exclusive scan of ccnt
-  __shared__ uint32_t qm[4];                // quads holding an entry
   const int tid = threadIdx.x;
   const int64_t k = blockIdx.x;
+  const uint32_t nblk = (qrank[nquads] + (uint32_t)(8 * W) - 1u) / (uint32_t)(8 * W);
+  if ((uint32_t)k >= nblk) return;
   const uint32_t lo = be[k], hi = be[k + 1];
-  const uint32_t b0 = (uint32_t)(k * (32 * W));
+  const uint32_t r0 = (uint32_t)(k * (8 * W));  // rank of the block's first quad
+  // slot of bucket b in the block
+  auto slot_of = [&](uint32_t b) { return 4u * (qrank[b >> 2] - r0) + (b & 3u); };
   for (int64_t i = tid; i < d * W; i += 512) bits[i] = 0u;
-  if (tid < 4) qm[tid] = 0u;
   __syncthreads();
   for (uint32_t e = lo + tid; e < hi; e += 512) {
     const int32_t c = ec[e];
     if (c >= 0) {
-      const uint32_t bo = eb[e] - b0;
+      const uint32_t bo = slot_of(eb[e]);
       atomicOr(&bits[c * W + (bo >> 5)], 1u << (bo & 31));
-      atomicOr(&qm[bo >> 7], 1u << ((bo >> 2) & 31));
     }
   }
   __syncthreads();
-  if (tid < 4) qmask[4 * k + tid] = qm[tid];
   for (int64_t c = tid; c < d; c += 512) {
     uint32_t run = 0;
 #pragma unroll
@@ -375,54 +406,40 @@ __global__ __launch_bounds__(512) void k_block_csc(const uint32_t *__restrict__ 
   for (uint32_t e = lo + tid; e < hi; e += 512) {
     const int32_t c = ec[e];
     if (c >= 0) {
-      const uint32_t bo = eb[e] - b0, w = bo >> 5;
+      const uint32_t bo = slot_of(eb[e]), w = bo >> 5;
       const uint32_t rank =
           wpre[c * W + w] + (uint32_t)__popc(bits[c * W + w] & ((1u << (bo & 31)) - 1u));
       const uint32_t pos = lo + cst[c] + rank;
       sp[pos] = (uint32_t)c | (bo << 10) | ((ccnt[c] - rank) << 19) | ((rank == 0u) << 29);
-      sv[pos] = ev[e];
+      sv[pos] = (VT)ev[e];
     }
   }
   const uint32_t nv = cst[d - 1] + ccnt[d - 1];
   for (uint32_t p = lo + nv + tid; p < hi; p += 512) {
     sp[p] = kHole;
-    sv[p] = 0.0;
+    sv[p] = VT(0);
   }
-}
-
-// position of the k-th (from 0) set bit of w, k < popcount(w): halve the
-// window five times, moving to its upper half when the lower one holds at
-// most k set bits
-__device__ __forceinline__ int select_bit(uint32_t w, uint32_t k) {
-  int pos = 0;
-#pragma unroll
-  for (int sh = 16; sh >= 1; sh >>= 1) {
-    const uint32_t c = (uint32_t)__popc((w >> pos) & ((1u << sh) - 1u));
-    if (k >= c) {
-      k -= c;
-      pos += sh;
-    }
-  }
-  return pos;
 }
 
 // G precision of the sparse product
 enum { kG64 = 0, kGbf16 = 1, kGfp8 = 2 };
 
 constexpr int kSThreads = 1024;
-constexpr int kStage = 2 * kSThreads;  // entries of a block staged in LDS at once
+// entries of a block staged in LDS at once: 2048 with FP64 values, 4096
+// with FP32 ones (the same registers per thread)
+constexpr int kStageMax = 4 * kSThreads;
 // A column with more than kHeavy entries in a staged turn (a dense column
 // of A, or b appended to A) is summed by all threads together; a turn holds
-// at most kStage / (kHeavy + 1) < kHeavyMax such columns, so the list never
+// at most kStageMax / (kHeavy + 1) < kHeavyMax such columns, so the list never
 // overflows and which columns take that path depends on the data alone.
 constexpr int kHeavy = 32;
-constexpr int kHeavyMax = 64;
-static_assert(kStage / (kHeavy + 1) < kHeavyMax, "heavy list capacity");
+constexpr int kHeavyMax = 128;
+static_assert(kStageMax / (kHeavy + 1) < kHeavyMax, "heavy list capacity");
 
 // Workgroup (row tile mt, K split ks), 1024 threads: rows a0 .. a0 + MT of
-// C (MT = 16 1024 / DP) and the G blocks of BLK buckets ks bper .. ks bper +
-// bper - 1 (BLK = 512 with G in FP32, four FP8 scale blocks; 256 with G in
-// FP64).  Thread (h, j) = (tid / DP, tid % DP) holds C[a0 + 16 h + i, j],
+// C (MT = 16 1024 / DP) and the G blocks ks bper .. ks bper + bper - 1, a
+// block being QB = BLK / 4 occupied quads of buckets (BLK = 512 with G in
+// FP32, 256 with G in FP64; bper from the number of blocks, read here).  Thread (h, j) = (tid / DP, tid % DP) holds C[a0 + 16 h + i, j],
 // i < 16, in FP64 registers.  Per block: every thread draws its share of
 // the block of G into LDS (bucket-major, so one bucket's MT values are
 // contiguous); the block's entries, sorted by (column, bucket), are staged
@@ -431,25 +448,27 @@ static_assert(kStage / (kHeavy + 1) < kHeavyMax, "heavy list capacity");
 // (FP64, or FP32 when G is drawn in FP32).
 // So each element of C is summed by one thread, over buckets in ascending
 // order, with no atomics.  Entries are fetched two blocks ahead, the block
-// bounds three; a block of more than kStage entries is staged in turns.
+// bounds three; a block of more than KS entries is staged in turns.
 template <int GP, int DP, int BLK>
 __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     int64_t m, int64_t d, int64_t r, uint64_t seed, const uint32_t *__restrict__ be,
-    const uint32_t *__restrict__ sp, const double *__restrict__ sv,
-    const uint32_t *__restrict__ qmask, int tiles_m, int64_t bper,
+    const uint32_t *__restrict__ sp, const void *__restrict__ sv_raw,
+    const uint32_t *__restrict__ qlist, const uint32_t *__restrict__ nqp, int tiles_m,
     double *__restrict__ part /* [splits][m][d] */) {
   typedef typename std::conditional<GP == kG64, double, float>::type GT;
   typedef GT AT;  // accumulator and staged value: FP64, or FP32 with G in FP32
+  constexpr int KS = sizeof(AT) == 4 ? kStageMax : kStageMax / 2;
+  const AT *__restrict__ sv = reinterpret_cast<const AT *>(sv_raw);  // the sorted values
   constexpr int RG = kSThreads / DP;                // row groups
   constexpr int MT = 16 * RG;                       // tile rows
   constexpr int GS = MT + 16 / (int)sizeof(GT);     // LDS stride of a bucket of G
-  constexpr int kQ = BLK / 4;                       // Philox blocks per row of G
+  constexpr int kQ = BLK / 4;                       // quads (Philox blocks) per G block
   constexpr int NIT = MT * kQ / kSThreads;          // G items per thread
   static_assert(NIT >= 1 && MT * kQ % kSThreads == 0, "whole G items per thread");
-  static_assert(GP != kGfp8 || BLK == 4 * kBlk, "FP8 G blocks hold four scale blocks");
+  static_assert(kQ <= kSThreads, "one thread per quad of the block's list");
   __shared__ __align__(16) GT Gb[BLK * GS];
-  __shared__ uint32_t stp[kStage];
-  __shared__ AT stv[kStage];
+  __shared__ uint32_t stp[KS];
+  __shared__ AT stv[KS];
   __shared__ uint2 crng[DP];  // per column: tag, first staged slot | count << 16
   // heavy columns of the turn: column, first slot | count << 16; the count
   // alternates with the turn's parity so that it is cleared a turn ahead
@@ -460,9 +479,12 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
   const int tid = threadIdx.x;
   const int mt = (int)(blockIdx.x % tiles_m);
   const int64_t ks = blockIdx.x / tiles_m;
+  const int64_t splits = gridDim.x / tiles_m;
   const int64_t a0 = (int64_t)mt * MT;
-  const int64_t nblk = ceil_div(r, BLK);
-  const int64_t k0 = ks * bper;
+  const int64_t nq = (int64_t)nqp[0];  // occupied quads
+  const int64_t nblk = ceil_div(nq, (int64_t)kQ);
+  const int64_t bper = ceil_div(nblk, splits);
+  const int64_t k0 = ks * bper < nblk ? ks * bper : nblk;
   const int64_t k1 = k0 + bper < nblk ? k0 + bper : nblk;
   const int j = tid % DP, h = tid / DP;
   for (int i = tid; i < DP; i += kSThreads) crng[i] = make_uint2(kHole, 0u);
@@ -477,8 +499,8 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     uint32_t lo, hi;
   };
   struct ESet {
-    uint32_t p[kStage / kSThreads];
-    double v[kStage / kSThreads];
+    uint32_t p[KS / kSThreads];
+    AT v[KS / kSThreads];
     uint32_t lo, hi;
   };
   int vz;
@@ -487,18 +509,19 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     B.lo = be[(k < k1 ? k : k1) + vz];
     B.hi = be[(k + 1 < k1 ? k + 1 : k1) + vz];
   };
-  // occupied-quad masks of the next blocks in an LDS ring of four: word i of
-  // block k (none past the split) is loaded by thread i three steps ahead
-  // and stored at the end of the step's draw, before its barrier
-  __shared__ uint32_t qms[4][4];
-  auto qmask_word = [&](int64_t k) -> uint32_t {
-    const int64_t kq = k < k1 ? k : k1 - 1;
-    const uint32_t w = qmask[4 * kq + (tid & 3)];
-    return k < k1 ? w : 0u;
+  // the quads of the next blocks in an LDS ring of four: quad i of block k
+  // (0 past the split) is loaded by thread i three steps ahead and stored at
+  // the end of the step's draw, before its barrier
+  __shared__ uint32_t qring[4][kQ];
+  auto quad_of = [&](int64_t k) -> uint32_t {
+    const int64_t e = k * kQ + tid;
+    const int64_t ec2 = e < nq ? e : (nq > 0 ? nq - 1 : 0);
+    const uint32_t q = qlist[ec2];
+    return (k < k1 && e < nq) ? q : 0u;
   };
-  auto load = [&](uint32_t base, uint32_t hi, uint32_t *pp, double *vv) {
+  auto load = [&](uint32_t base, uint32_t hi, uint32_t *pp, AT *vv) {
 #pragma unroll
-    for (int s2 = 0; s2 < kStage / kSThreads; ++s2) {
+    for (int s2 = 0; s2 < KS / kSThreads; ++s2) {
       const uint32_t e = base + (uint32_t)(tid + kSThreads * s2);
       const uint32_t ei = e < hi ? e : (hi ? hi - 1 : 0u);  // clamped; masked when staged
       pp[s2] = sp[ei];
@@ -511,14 +534,14 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     R.hi = B.hi;
   };
   // stage one turn (nch entries) and its column ranges; barrier before and after
-  auto stage = [&](const uint32_t *pp, const double *vv, uint32_t nch)
+  auto stage = [&](const uint32_t *pp, const AT *vv, uint32_t nch)
                    __attribute__((always_inline)) {
 #pragma unroll
-    for (int s2 = 0; s2 < kStage / kSThreads; ++s2) {
+    for (int s2 = 0; s2 < KS / kSThreads; ++s2) {
       const int idx = tid + kSThreads * s2;
       const uint32_t pv = (uint32_t)idx < nch ? pp[s2] : kHole;
       stp[idx] = pv;
-      stv[idx] = (AT)vv[s2];
+      stv[idx] = vv[s2];
       if (pv != kHole && (((pv >> 29) & 1u) || idx == 0)) {
         const uint32_t left = (pv >> 19) & 1023u;
         const uint32_t room = nch - (uint32_t)idx;
@@ -583,41 +606,26 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     ++tag;
   };
   auto step = [&](int64_t kb, ESet &X, Bnd &BX, Bnd &BY) __attribute__((always_inline)) {
-    const int64_t b0 = kb * BLK;
-    // Only the quads that hold an entry are drawn (the others are never
-    // read): item it of the block is row it % MT of the (it / MT)-th
-    // occupied quad; thread tid takes items tid, tid + 1024, ...
-    uint32_t qw[4], qpre[4];
-    uint32_t nq = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      qw[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)qms[kb & 3][i]);
-      qpre[i] = nq;
-      nq += (uint32_t)__popc(qw[i]);
-    }
-    // the mask of block kb + 3, stored into the ring after the draw
+    // Block kb: the occupied quads kQ kb .. kQ kb + kQ - 1 of the list
+    // (fewer in the last block); item it of the block is row it % MT of its
+    // (it / MT)-th quad, drawn into the G slots 4 (it / MT) .. + 3; thread
+    // tid takes items tid, tid + 1024, ...
+    const int64_t qleft = nq - kb * kQ;
+    const int nqb = kb < k1 ? (int)(qleft < kQ ? qleft : kQ) : 0;
+    // the quads of block kb + 3, stored into the ring after the draw
     uint32_t qnext = 0;
-    if (tid < 4) qnext = qmask_word(kb + 3);
-    const int nitems = (int)(nq * MT);
-    // row and quad of item u (recomputed at the store: fewer live registers)
-    auto item_of = [&](int u, int &a, int &q) __attribute__((always_inline)) {
+    if (tid < kQ) qnext = quad_of(kb + 3);
+    const int nitems = nqb * MT;
+    const uint32_t *qr = qring[kb & 3];
+    // row, slot quad and first bucket of item u (r < 2^31: 32-bit)
+    auto item_of = [&](int u, int &a, int &q, uint32_t &bq) __attribute__((always_inline)) {
       const int it = tid + kSThreads * u;
       a = it % MT;
-      // the (it / MT)-th occupied quad: its word, then its bit in the word
-      const uint32_t qi = (uint32_t)(it / MT);
-      int wi = 0;
-#pragma unroll
-      for (int i = 1; i < 4; ++i)
-        if (qi >= qpre[i]) wi = i;
-      uint32_t w = qw[0], left = qi - qpre[0];
-#pragma unroll
-      for (int i = 1; i < 4; ++i)
-        if (wi == i) {
-          w = qw[i];
-          left = qi - qpre[i];
-        }
-      q = 32 * wi + select_bit(w, left);
+      q = it / MT;
+      bq = 4u * qr[q];
     };
+    const uint32_t ru = (uint32_t)r;
+    const int mi = (int)m, a0i = (int)a0;
     // the drawn values: FP64, or (BF16, FP8: exact in bfloat16) two
     // bfloat16 per register
     constexpr int GW = GP == kG64 ? 4 : 2;
@@ -630,16 +638,17 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
     for (int u = 0; u < NIT; ++u) {
       if (tid + kSThreads * u < nitems) {
         int a, q;
-        item_of(u, a, q);
-        const int64_t ga = a0 + a, bq = b0 + 4 * q;
+        uint32_t bq;
+        item_of(u, a, q, bq);
+        const int ga = a0i + a;
         if constexpr (GP == kG64) {
           double z[4] = {0.0, 0.0, 0.0, 0.0};
-          if (ga < m && bq < r) gauss4_f64((uint64_t)(bq >> 2), (uint32_t)ga, seed, z);
+          if (ga < mi && bq < ru) gauss4_f64((uint64_t)(bq >> 2), (uint32_t)ga, seed, z);
 #pragma unroll
           for (int t = 0; t < 4; ++t) g[u][t] = z[t];
         } else {
           float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-          if (ga < m && bq < r) {
+          if (ga < mi && bq < ru) {
             const u32x4 x = philox_g((uint64_t)(bq >> 2), (uint32_t)ga, seed);
             if (GP == kGbf16) {
               nearm |= gauss4_bf16_fast(x, z) << (4 * u);
@@ -654,20 +663,21 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
           }
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            if (bq + t >= r) z[t] = 0.0f;  // G ends at bucket r
+            if (bq + t >= ru) z[t] = 0.0f;  // G ends at bucket r
           // bfloat16 patterns (exact: the values are bfloat16 or e4m3)
           g[u][0] = (__float_as_uint(z[0]) >> 16) | (__float_as_uint(z[1]) & 0xFFFF0000u);
           g[u][1] = (__float_as_uint(z[2]) >> 16) | (__float_as_uint(z[3]) & 0xFFFF0000u);
         }
       }
     }
-    if (tid < 4) qms[(kb + 3) & 3][tid] = qnext;  // ring slot of block kb - 1, read
+    if (tid < kQ) qring[(kb + 3) & 3][tid] = qnext;  // ring slot of block kb - 1, read
     __syncthreads();  // the previous block is done with Gb, the stage and crng
 #pragma unroll
     for (int u = 0; u < NIT; ++u)
       if (tid + kSThreads * u < nitems) {
         int a, q;
-        item_of(u, a, q);
+        uint32_t bq;
+        item_of(u, a, q, bq);
         GT gv[4];
         if constexpr (GP == kG64) {
 #pragma unroll
@@ -690,8 +700,9 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
           const uint32_t nb = (nearm >> (4 * u)) & 15u;
           if (nb == 0u) continue;
           int a, q;
-          item_of(u, a, q);
-          const int64_t ga = a0 + a, bq = b0 + 4 * q;
+          uint32_t bq;
+          item_of(u, a, q, bq);
+          const int ga = a0i + a;
           const u32x4 x = philox_g((uint64_t)(bq >> 2), (uint32_t)ga, seed);
           float z[4];
           if (GP == kGbf16) {
@@ -703,31 +714,31 @@ __global__ __launch_bounds__(kSThreads) void k_gauss_sparse(
           }
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            if (((nb >> t) & 1u) && bq + t < r) Gb[(4 * q + t) * GS + a] = (GT)z[t];
+            if (((nb >> t) & 1u) && bq + t < ru) Gb[(4 * q + t) * GS + a] = (GT)z[t];
         }
       }
     }
     const uint32_t lo = X.lo, hi = X.hi;
-    stage(X.p, X.v, hi - lo < (uint32_t)kStage ? hi - lo : (uint32_t)kStage);
+    stage(X.p, X.v, hi - lo < (uint32_t)KS ? hi - lo : (uint32_t)KS);
     __syncthreads();
     bounds(kb + 3, BY);  // block kb + 3 is fetched in the next step
     fetch(BX, X);        // block kb + 2, bounds loaded in the previous step
     consume();
-    // more than kStage entries: the further turns, loaded here
-    for (uint32_t base = lo + kStage; base < hi; base += kStage) {
-      uint32_t pp[kStage / kSThreads];
-      double vv[kStage / kSThreads];
+    // more than KS entries: the further turns, loaded here
+    for (uint32_t base = lo + KS; base < hi; base += KS) {
+      uint32_t pp[KS / kSThreads];
+      AT vv[KS / kSThreads];
       load(base, hi, pp, vv);
       __syncthreads();
-      stage(pp, vv, hi - base < (uint32_t)kStage ? hi - base : (uint32_t)kStage);
+      stage(pp, vv, hi - base < (uint32_t)KS ? hi - base : (uint32_t)KS);
       __syncthreads();
       consume();
     }
   };
-  if (tid < 4) {  // ring slots are block index mod 4
-    qms[k0 & 3][tid] = qmask_word(k0);
-    qms[(k0 + 1) & 3][tid] = qmask_word(k0 + 1);
-    qms[(k0 + 2) & 3][tid] = qmask_word(k0 + 2);
+  if (tid < kQ) {  // ring slots are block index mod 4
+    qring[k0 & 3][tid] = quad_of(k0);
+    qring[(k0 + 1) & 3][tid] = quad_of(k0 + 1);
+    qring[(k0 + 2) & 3][tid] = quad_of(k0 + 2);
   }
   __syncthreads();
   Bnd BA, BB;
@@ -818,8 +829,9 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
   const int64_t n = A.n, d = A.d;
   const int mtr = d <= 512 ? 32 : 16;
   const int tiles_m = (int)ceil_div(m, mtr);
-  const int64_t blk = prec == PSK_PREC_F64 ? 256 : 4 * kBlk;  // buckets per G block
-  const int64_t nblk = ceil_div(r, blk);
+  const int64_t blk = prec == PSK_PREC_F64 ? 256 : 512;  // G slots (4 per quad) per block
+  const int64_t nquads = ceil_div(r, 4);
+  const int64_t nblk = ceil_div(nquads, blk / 4);  // blocks when every quad is occupied
   // one 1024-thread workgroup per CU: about 256 of them in all
   int64_t splits = 256 / tiles_m;
   if (splits > nblk / 4) splits = nblk / 4;
@@ -834,8 +846,13 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
   int32_t *ec = ws.take<int32_t>((size_t)A.nnz + 1);
   double *ev = ws.take<double>((size_t)A.nnz + 1);
   uint32_t *sp = ws.take<uint32_t>((size_t)A.nnz + 1);
-  double *sv = ws.take<double>((size_t)A.nnz + 1);
-  uint32_t *qmask = ws.take<uint32_t>((size_t)4 * nblk);
+  // the sorted values in the precision the product stages them in
+  void *sv = prec == PSK_PREC_F64 ? (void *)ws.take<double>((size_t)A.nnz + 1)
+                                  : (void *)ws.take<float>((size_t)A.nnz + 1);
+  uint32_t *qrank = ws.take<uint32_t>((size_t)nquads + 1);
+  uint32_t *qlist = ws.take<uint32_t>((size_t)nquads);
+  uint32_t *qsums = nullptr;
+  scan_plan(nquads + 1, ws, &qsums);
   double *part = ws.take<double>((size_t)splits * m * d);
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the sparse Gaussian product");
@@ -859,19 +876,23 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
     if (prec == PSK_PREC_FP8)
       k_entries_fp8<<<(unsigned)ceil_div(r, kBlk), 256, (size_t)d * 8, st>>>(bptr, eoff, r, d,
                                                                           ec, ev);
-    k_block_entries<<<(unsigned)ceil_div(nblk + 1, 256), 256, 0, st>>>(bptr, eoff, r, blk, nblk,
-                                                                     be);
+    const unsigned qg = (unsigned)ceil_div(nquads + 1, 256);
+    k_quad_flags<<<qg, 256, 0, st>>>(bptr, eoff, r, nquads, qrank);
+    scan_run(qrank, nquads + 1, qsums, st);
+    k_quad_list<<<qg, 256, 0, st>>>(bptr, eoff, qrank, r, nquads, (int)(blk / 4), qlist, be);
     if (blk == 256)
-      k_block_csc<8><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, sp, sv, qmask);
+      k_block_csc<8, double><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, qrank, nquads,
+                                                             sp, (double *)sv);
     else
-      k_block_csc<16><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, sp, sv, qmask);
+      k_block_csc<16, float><<<(unsigned)nblk, 512, 0, st>>>(be, eb, ec, ev, d, qrank, nquads,
+                                                             sp, (float *)sv);
   }
   {
     KTimer t("gauss_gemm", st);
     const unsigned grid = (unsigned)(tiles_m * splits);
 #define PSK_GSP(GP, DP, BLK)                                                                 \
-  k_gauss_sparse<GP, DP, BLK><<<grid, kSThreads, 0, st>>>(m, d, r, seed, be, sp, sv, qmask, \
-                                                         tiles_m, bper, part)
+  k_gauss_sparse<GP, DP, BLK><<<grid, kSThreads, 0, st>>>(m, d, r, seed, be, sp, sv, qlist, \
+                                                         qrank + nquads, tiles_m, part)
 #define PSK_GSP_MT(GP, BLK)                   \
   do {                                        \
     if (d <= 512) PSK_GSP(GP, 512, BLK);      \
