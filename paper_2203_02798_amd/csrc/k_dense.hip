@@ -354,7 +354,7 @@ __device__ __forceinline__ double raw4_get(const Raw4<TA> &v, int q) {
 // holds 32-column tiles of B: one (PAIR false), or two, tiles p and
 // T - 1 - p of the T = ceil(k / 32) tiles (PAIR true; one when they
 // coincide).  Its B columns (rows padded to a multiple of the K chunk with
-// zeros, row stride BNC + 4) are staged once; the 8 wavefronts then stream
+// zeros, row stride BNC + 4) are staged once; the 12 wavefronts then stream
 // row tiles of A (kBresMB blocks of 16 rows) straight from memory into the
 // MFMA operand registers (no LDS round trip and no barrier in the main loop)
 // and keep kBresMB x BNC/16 accumulator blocks.
@@ -373,7 +373,8 @@ __device__ __forceinline__ double raw4_get(const Raw4<TA> &v, int q) {
 // Workgroups form row groups of tn (one per slot) that sit on one XCD
 // (linear ids equal mod 8) and walk the same rows, so A is fetched into that
 // XCD's L2 about once for all tn slots.
-constexpr int kBresThreads = 512;
+constexpr int kBresThreads = 768;  // 12 wavefronts: three per SIMD
+constexpr int kBresWaves = kBresThreads / 64;
 constexpr int kBresMB = 2;  // 16-row blocks per wavefront tile
 constexpr int kBresRows = 16 * kBresMB;
 constexpr int kBresKW = 8;
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
   const int64_t kca = __builtin_amdgcn_readfirstlane((ext[0] + CK - 1) / CK);
   const int64_t kcb = __builtin_amdgcn_readfirstlane((ext[1] + CK - 1) / CK);
   const int64_t ntiles = (n + kBresRows - 1) / kBresRows;
-  for (int64_t t = group * 8 + wave; t < ntiles; t += ngroups * 8) {
+  for (int64_t t = group * kBresWaves + wave; t < ntiles; t += ngroups * kBresWaves) {
     const int64_t r0 = t * kBresRows;
     const TA *arow[MB];
     bool rin[MB];
@@ -546,7 +547,7 @@ int bres_launch(const psk_mat &Am, const double *B, int64_t k, double *part, int
   int64_t groups = 256 / tn;
   if (groups < 8) groups = 8;
   groups = (groups / 8) * 8;
-  const int64_t need = ceil_div(tiles, (int64_t)8);  // 8 wavefronts per workgroup
+  const int64_t need = ceil_div(tiles, (int64_t)kBresWaves);  // row tiles per wavefront round
   while (groups > 8 && groups / 2 >= need) groups /= 2;
   const unsigned nblk = (unsigned)(groups * tn);
   KTimer timer("rownorm", st);
@@ -635,18 +636,45 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
 // multiplied (10 of 16) and the others are mirrored when the tile is
 // written: the executed products are those of the upper triangle at the
 // 16 x 16 block level, n d (d + 16) flops for d a multiple of 64.
-// Rows past the slab and columns past d read as zero.  Slab s of tile t
-// writes its 64 x 64 partial (both triangles of a diagonal tile) to
-// part[s][t]; k_gram_reduce sums the slabs in order (no atomics).
-// Work item g = (slab g / U, tile g % U), U tiles; four per workgroup, and
-// workgroups of the same XCD (linear ids equal mod 8) take consecutive
-// items, so the tiles of one slab read its rows through one L2.
+// Rows past the slab and columns past d read as zero.
+// A diagonal tile does 10 of the 16 block products per row step, so its
+// slabs are 1.6 times as long (rows_d against rows_o rows): every work item
+// then costs about the same, and no SIMD waits on a pair of off-diagonal
+// items while others finish early.  The off-diagonal items come first,
+// (slab g / Uo, off-diagonal tile g % Uo), then the diagonal ones (slab,
+// tile (g' % T, g' % T)); four per workgroup, and workgroups of the same
+// XCD (linear ids equal mod 8) take consecutive items, so the tiles of one
+// slab read its rows through one L2.  Slab s of tile t writes its 64 x 64
+// partial (both triangles of a diagonal tile) to part at gram_part_off(t)
+// + s 4096; k_gram_reduce1 sums each tile's slabs in order (no atomics).
 constexpr int kGramPF = 4;  // row steps whose loads are in flight
+
+// (I, J), I < J, of off-diagonal tile o in row-major order
+__device__ __forceinline__ void gram_offdiag_tile(int o, int T, int &I, int &J) {
+  I = 0;
+  int rest = o;
+  while (rest >= T - 1 - I) {
+    rest -= T - 1 - I;
+    ++I;
+  }
+  J = I + 1 + rest;
+}
+
+// first partial of tile (I, J) (row-major upper triangle): the diagonal
+// tiles before it (I of them, one more when J > I) have sd slabs, the others
+// so slabs
+__host__ __device__ __forceinline__ int64_t gram_part_off(int I, int J, int T, int64_t so,
+                                                          int64_t sd) {
+  const int t = I * T - I * (I - 1) / 2 + (J - I);
+  const int nd = I + (J > I ? 1 : 0);
+  return ((int64_t)nd * sd + (int64_t)(t - nd) * so) * 4096;
+}
 
 template <typename TA, bool VEC>
 __global__ __launch_bounds__(256) void k_gram_syrk(const TA *__restrict__ A, int64_t ld,
-                                                   int64_t n, int64_t d, int T, int U,
-                                                   int64_t slabs, int64_t rows_per,
+                                                   int64_t n, int64_t d, int T,
+                                                   int64_t so, int64_t rows_o,
+                                                   int64_t sd, int64_t rows_d,
                                                    double *__restrict__ part) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, kq = lane >> 4;
@@ -654,16 +682,20 @@ __global__ __launch_bounds__(256) void k_gram_syrk(const TA *__restrict__ A, int
   int64_t lin = blockIdx.x;
   if ((nblk & 7) == 0) lin = (lin & 7) * (nblk >> 3) + (lin >> 3);
   const int64_t g = lin * 4 + wave;
-  if (g >= slabs * U) return;
-  const int64_t slab = g / U;
-  const int t = (int)(g - slab * U);
-  // tile t of the upper triangle in row-major order -> (I, J)
-  int I = 0, rest = t;
-  while (rest >= T - I) {
-    rest -= T - I;
-    ++I;
+  const int Uo = T * (T - 1) / 2;
+  const int64_t no = so * Uo;
+  if (g >= no + sd * T) return;
+  int I, J;
+  int64_t slab, rows_per;
+  if (g < no) {
+    slab = g / Uo;
+    gram_offdiag_tile((int)(g - slab * Uo), T, I, J);
+    rows_per = rows_o;
+  } else {
+    slab = (g - no) / T;
+    I = J = (int)(g - no - slab * T);
+    rows_per = rows_d;
   }
-  const int J = I + rest;
   const bool diag = I == J;
   const int64_t k_begin = slab * rows_per;
   int64_t k_end = k_begin + rows_per;
@@ -708,7 +740,7 @@ __global__ __launch_bounds__(256) void k_gram_syrk(const TA *__restrict__ A, int
   else run(std::false_type{});
   // lane (li, kq) holds rows kq + 4 e, column li of each block: the tile's
   // local element (4 (kq + 4 e) + a, 4 li + b)
-  double *o = part + (slab * U + t) * 4096;
+  double *o = part + gram_part_off(I, J, T, so, sd) + slab * 4096;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -729,7 +761,7 @@ __global__ __launch_bounds__(256) void k_gram_syrk(const TA *__restrict__ A, int
 constexpr int kGramGroups = 16;
 
 __global__ __launch_bounds__(256) void k_gram_reduce1(const double *__restrict__ part,
-                                                      int64_t d, int T, int U, int64_t slabs,
+                                                      int64_t d, int T, int64_t so, int64_t sd,
                                                       double *__restrict__ gpart) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t q = blockIdx.y;
@@ -741,11 +773,11 @@ __global__ __launch_bounds__(256) void k_gram_reduce1(const double *__restrict__
     c = x;
   }
   const int I = (int)(p / 64), J = (int)(c / 64);
-  const int t = I * T - I * (I - 1) / 2 + (J - I);
-  const int64_t off = (int64_t)t * 4096 + (p % 64) * 64 + (c % 64);
+  const int64_t slabs = I == J ? sd : so;
+  const int64_t off = gram_part_off(I, J, T, so, sd) + (p % 64) * 64 + (c % 64);
   const int64_t s0 = slabs * q / kGramGroups, s1 = slabs * (q + 1) / kGramGroups;
   double acc = 0.0;
-  for (int64_t s = s0; s < s1; ++s) acc += part[s * U * 4096 + off];
+  for (int64_t s = s0; s < s1; ++s) acc += part[off + s * 4096];
   gpart[q * d * d + e] = acc;
 }
 
@@ -769,17 +801,21 @@ int gram_syrk_launch(double alpha, const psk_mat &Am, double beta, void *C, bool
                      Arena &ws, hipStream_t st) {
   const int64_t n = Am.n, d = Am.d;
   const int T = (int)ceil_div(d, (int64_t)64);
-  const int U = T * (T + 1) / 2;
-  // about two wavefronts per SIMD in one round: 2048 work items
-  int64_t slabs = 2048 / U;
-  if (slabs < 8) slabs = 8;
-  int64_t rows_per = ceil_div(ceil_div(n, slabs), (int64_t)(4 * kGramPF)) * (4 * kGramPF);
-  slabs = ceil_div(n, rows_per);
-  double *part = ws.take<double>((size_t)slabs * U * 4096);
+  const int Uo = T * (T - 1) / 2;
+  // about two wavefronts per SIMD in one round: 2048 work items of equal
+  // cost, a diagonal item 10/16 of an off-diagonal one per row
+  constexpr int64_t kStep = 4 * kGramPF;
+  int64_t so = (int64_t)(2048.0 / (Uo + 0.625 * T));
+  if (so < 8) so = 8;
+  const int64_t rows_o = ceil_div(ceil_div(n, so), kStep) * kStep;
+  so = ceil_div(n, rows_o);
+  const int64_t rows_d = ceil_div((rows_o * 16) / 10, kStep) * kStep;
+  const int64_t sd = ceil_div(n, rows_d);
+  double *part = ws.take<double>((size_t)(so * Uo + sd * T) * 4096);
   double *gpart = ws.take<double>((size_t)kGramGroups * d * d);
   if (ws.dry()) return 0;
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the Gram matrix");
-  const int64_t items = slabs * U;
+  const int64_t items = so * Uo + sd * T;
   int64_t nblk = ceil_div(items, (int64_t)4);
   nblk = ceil_div(nblk, (int64_t)8) * 8;  // whole XCD rounds for the remap
   const uintptr_t addr = (uintptr_t)Am.values;
@@ -788,15 +824,15 @@ int gram_syrk_launch(double alpha, const psk_mat &Am, double beta, void *C, bool
     KTimer timer("gram", st);
     if (vec)
       k_gram_syrk<TA, true><<<(unsigned)nblk, 256, 0, st>>>((const TA *)Am.values, Am.ld, n, d,
-                                                            T, U, slabs, rows_per, part);
+                                                            T, so, rows_o, sd, rows_d, part);
     else
       k_gram_syrk<TA, false><<<(unsigned)nblk, 256, 0, st>>>((const TA *)Am.values, Am.ld, n, d,
-                                                             T, U, slabs, rows_per, part);
+                                                             T, so, rows_o, sd, rows_d, part);
   }
   KTimer rtimer("gram_reduce", st);
   const int64_t dd = d * d;
   dim3 g1((unsigned)ceil_div(dd, (int64_t)256), kGramGroups);
-  k_gram_reduce1<<<g1, 256, 0, st>>>(part, d, T, U, slabs, gpart);
+  k_gram_reduce1<<<g1, 256, 0, st>>>(part, d, T, so, sd, gpart);
   if (out_f32)
     k_gram_reduce2<float><<<(unsigned)ceil_div(dd, (int64_t)256), 256, 0, st>>>(
         gpart, dd, alpha, beta, (float *)C);
