@@ -111,6 +111,8 @@ def timed(torch, f, steps, warmup, stream=None):
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
     torch.cuda.synchronize()
+    if steps == 0:  # warm-up only
+        return 0.0, lat
     return (time.perf_counter() - t0) / steps, lat
 
 
