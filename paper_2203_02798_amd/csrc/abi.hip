@@ -110,7 +110,7 @@ static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s);
 int do_sketch_cs(const psk_mat &A, int64_t r, uint64_t seed, void *SA, Arena &ws,
                  hipStream_t st, bool out_f64) {
   uint32_t *perm = nullptr, *bptr = nullptr;
-  int rc = cs_bin(A.n, (uint32_t)r, seed, ws, st, &perm, &bptr);
+  int rc = cs_bin(A, (uint32_t)r, seed, ws, st, &perm, &bptr);
   if (rc) return rc;
   return cs_apply(A, (uint32_t)r, perm, bptr, SA, ws, st, out_f64);
 }
@@ -121,7 +121,7 @@ int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int pre
   if (gauss_sparse_pick(A, r, m, prec)) {
     // S*A is sparse: the product over its nonzeros
     uint32_t *perm = nullptr, *bptr = nullptr;
-    int rc = cs_bin(A.n, (uint32_t)r, seed, ws, st, &perm, &bptr);
+    int rc = cs_bin(A, (uint32_t)r, seed, ws, st, &perm, &bptr);
     if (rc) return rc;
     return gauss_gemm_sparse(m, r, A, perm, bptr, seed, prec, (double *)C, ws, st);
   }
@@ -130,7 +130,7 @@ int do_sketch_gcs(const psk_mat &A, int64_t m, int64_t r, uint64_t seed, int pre
   if (fb || f8) {
     // the BF16 limbs / FP8 bytes of S*A straight from the binned rows
     uint32_t *perm = nullptr, *bptr = nullptr;
-    int rc = cs_bin(A.n, (uint32_t)r, seed, ws, st, &perm, &bptr);
+    int rc = cs_bin(A, (uint32_t)r, seed, ws, st, &perm, &bptr);
     if (rc) return rc;
     if (fb) return gauss_gemm_bf16_csr(m, r, A, perm, bptr, seed, (double *)C, ws, st);
     return gauss_gemm_fp8_csr(m, r, A, perm, bptr, seed, (double *)C, ws, st);
@@ -146,7 +146,7 @@ int do_sketch_osnap(const psk_mat &A, int64_t s, int64_t m, int64_t r, uint64_t 
                     int prec, void *C, Arena &ws, hipStream_t st) {
   if (s == 1) return do_sketch_gcs(A, m, r, seed, prec, C, ws, st);
   uint32_t *perm = nullptr, *bptr = nullptr;
-  int rc = osnap_bin(A.n, (uint32_t)s, (uint32_t)r, seed, ws, st, &perm, &bptr);
+  int rc = osnap_bin(A, (uint32_t)s, (uint32_t)r, seed, ws, st, &perm, &bptr);
   if (rc) return rc;
   // each bucket's signed rows summed in FP64, times 1/sqrt(s) once
   const double scale = 1.0 / sqrt((double)s);

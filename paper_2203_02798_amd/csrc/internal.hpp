@@ -60,16 +60,20 @@ struct KTimer {
 };
 
 // ---- CountSketch (k_sketch.hip) ---------------------------------------------
-// Bins rows 0..n-1 by bucket: perm[j] (row | sign<<31) sorted by bucket,
-// stable; bptr[b] .. bptr[b+1] is bucket b's range.  Returns 0 or a status.
-int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
+// Bins the rows of A by bucket: perm[j] (row | sign<<31) sorted by bucket,
+// stable; bptr[b] .. bptr[b+1] is bucket b's range.  For CSR A only rows
+// holding an entry are binned, so bptr[r] may be below n and perm is valid
+// only below bptr[r].  Returns 0 or a status.
+int cs_bin(const psk_mat &A, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
            uint32_t **perm, uint32_t **bptr);
 // Stable LSD radix sort (8-bit digits) of (key, val) pairs with keys < r;
 // keys/vals are consumed (used as the first ping-pong buffers).  On return
 // *skeys/*svals point at the sorted arrays; with ptr != NULL, ptr[0..r] gets
-// the start of each key's run (ptr[r] = n).
+// the start of each key's run (ptr[r] = n).  With dn != NULL only the first
+// dn[0] <= n pairs (a count on the device) are sorted.
 int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
-               hipStream_t st, uint32_t **skeys, uint32_t **svals, uint32_t *ptr);
+               hipStream_t st, uint32_t **skeys, uint32_t **svals, uint32_t *ptr,
+               const uint32_t *dn = nullptr);
 int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
                    int32_t *h, int8_t *sign, hipStream_t st);
 // S*A into SA (r x d row-major): each bucket's rows summed in FP64 in bin
@@ -80,10 +84,11 @@ int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,
              const uint32_t *bptr, void *SA, Arena &ws, hipStream_t st,
              bool out_f64 = false, double scale = 1.0, int64_t entries = 0);
 // OSNAP with s non-zeros per row (block construction, s | r): bins of the
-// n s (row, non-zero) pairs, as cs_bin; the hash export writes count * s
-// rows and signs, non-zero k of row row0 + i at [i s + k].
-int osnap_bin(int64_t n, uint32_t s, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
-              uint32_t **perm, uint32_t **bptr);
+// n s (row, non-zero) pairs, as cs_bin (CSR A: of the rows holding an
+// entry); the hash export writes count * s rows and signs, non-zero k of
+// row row0 + i at [i s + k].
+int osnap_bin(const psk_mat &A, uint32_t s, uint32_t r, uint64_t seed, Arena &ws,
+              hipStream_t st, uint32_t **perm, uint32_t **bptr);
 int osnap_hash_export(int64_t row0, int64_t count, uint32_t s, uint32_t r, uint64_t seed,
                       int32_t *h, int8_t *sign, hipStream_t st);
 // Wavefronts per bucket cs_apply uses for n rows in r buckets (1 = one

@@ -53,14 +53,16 @@ namespace {
 
 constexpr int kBlk = 128;  // buckets per FP8 scale block
 
-// rn[j] = number of entries of the row at bin position j; rn[n] = 0
+// rn[j] = number of entries of the row at bin position j; 0 at and past
+// the binned count bptr[r] (at most n; rows without entries are not binned)
 __global__ __launch_bounds__(256) void k_row_nnz(const int64_t *__restrict__ indptr,
-                                                 const uint32_t *__restrict__ perm, int64_t n,
-                                                 uint32_t *__restrict__ rn) {
+                                                 const uint32_t *__restrict__ perm,
+                                                 const uint32_t *__restrict__ bptr, int64_t r,
+                                                 int64_t n, uint32_t *__restrict__ rn) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j > n) return;
   uint32_t v = 0;
-  if (j < n) {
+  if (j < (int64_t)bptr[r]) {
     const int64_t row = (int64_t)(perm[j] & 0x7fffffffu);
     v = (uint32_t)(indptr[row + 1] - indptr[row]);
   }
@@ -858,7 +860,7 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the sparse Gaussian product");
   {
     KTimer t("sa_entries", st);
-    k_row_nnz<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(A.indptr, perm, n, eoff);
+    k_row_nnz<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(A.indptr, perm, bptr, r, n, eoff);
     scan_run(eoff, n + 1, sums, st);
     const int64_t dpad = (d + 3) & ~(int64_t)3;
     const size_t lds = (size_t)4 * dpad * sizeof(double);

@@ -924,7 +924,7 @@ int lsq_impl(const psk_mat &A, const double *b, double *x, const psk_lsq_opts &o
     // binned rows it is formed from) stays until the precision decision so
     // that an FP64 rebuild can reuse it
     if (!fused && !sparse) SA = ws.take<double>((size_t)o.r * d);
-    if ((rc = cs_bin(n, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr))) return rc;
+    if ((rc = cs_bin(A, (uint32_t)o.r, o.seed, ws, st, &perm, &bptr))) return rc;
     if (!fused && !sparse && (rc = cs_apply(A, (uint32_t)o.r, perm, bptr, SA, ws, st, true)))
       return rc;
     const size_t mk2 = ws.mark();

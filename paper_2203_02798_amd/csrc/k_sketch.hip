@@ -84,16 +84,71 @@ __global__ __launch_bounds__(256) void k_hash_export_osnap(int64_t row0, int64_t
   if (sign) sign[j] = neg ? (int8_t)-1 : (int8_t)1;
 }
 
+// CSR A: only rows that hold an entry are binned (an empty row adds nothing
+// to any sum, so the bins and the sums of the others are unchanged).
+// f[i] = 1 when row i holds an entry (f[n] = 0); after an exclusive scan
+// k_row_compact lists them in order and writes their count.
+__global__ __launch_bounds__(256) void k_row_flags(const int64_t *__restrict__ indptr, int64_t n,
+                                                   uint32_t *__restrict__ f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  f[i] = (i < n && indptr[i + 1] > indptr[i]) ? 1u : 0u;
+}
+
+// cnt[0] = rows listed, cnt[1] = s times that (the pairs to bin)
+__global__ __launch_bounds__(256) void k_row_compact(const int64_t *__restrict__ indptr,
+                                                     const uint32_t *__restrict__ rank,
+                                                     int64_t n, uint32_t s,
+                                                     uint32_t *__restrict__ rows,
+                                                     uint32_t *__restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  if (i == n) {
+    cnt[0] = rank[n];
+    cnt[1] = rank[n] * s;
+    return;
+  }
+  if (indptr[i + 1] > indptr[i]) rows[rank[i]] = (uint32_t)i;
+}
+
+// (bucket, row | sign) pairs of the listed rows, s non-zeros each (s = 1:
+// the CountSketch hash, non-zero 0 with rb = r); cnt[0] rows listed
+__global__ __launch_bounds__(256) void k_hash_keys_rows(const uint32_t *__restrict__ rows,
+                                                        const uint32_t *__restrict__ cnt,
+                                                        uint32_t s, uint32_t rb, uint64_t seed,
+                                                        uint32_t *__restrict__ keys,
+                                                        uint32_t *__restrict__ vals) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= (int64_t)cnt[0] * s) return;
+  const int64_t q = j / s;
+  const uint32_t k = (uint32_t)(j - q * s);
+  const uint32_t i = rows[q];
+  uint32_t b, neg;
+  osnap_hash_nz((uint64_t)i, k, rb, seed, b, neg);
+  keys[j] = b;
+  vals[j] = i | (neg << 31);
+}
+
 // ---------------------------------------------------------------------------
 // radix sort pass: per-tile digit histogram (digit-major layout)
 // ---------------------------------------------------------------------------
+// The keys in use: n, or the count at dn (at most n) when given.
+__device__ __forceinline__ int64_t keys_in_use(int64_t n, const uint32_t *dn) {
+  return dn ? (int64_t)dn[0] : n;
+}
+
 __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
-    const uint32_t *__restrict__ keys, int64_t n, int shift, uint32_t mask,
-    uint32_t *__restrict__ hist, int64_t ntiles) {
+    const uint32_t *__restrict__ keys, int64_t n, const uint32_t *__restrict__ dn, int shift,
+    uint32_t mask, uint32_t *__restrict__ hist, int64_t ntiles) {
   __shared__ uint32_t h[kRadix];
+  n = keys_in_use(n, dn);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) {  // a tile past the keys in use: an empty histogram
+    hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = 0u;
+    return;
+  }
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll
   for (int it = 0; it < kSortItems; ++it) {
     const int64_t idx = base + it * kSortThreads + threadIdx.x;
@@ -106,10 +161,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
 // stable scatter of one tile, ranks from ballots
 __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-    int64_t n, int shift, int nbits, const uint32_t *__restrict__ offs,
-    int64_t ntiles, uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+    int64_t n, const uint32_t *__restrict__ dn, int shift, int nbits,
+    const uint32_t *__restrict__ offs, int64_t ntiles, uint32_t *__restrict__ kout,
+    uint32_t *__restrict__ vout) {
   __shared__ uint32_t run[kRadix];
   __shared__ uint32_t wc[4][kRadix];
+  n = keys_in_use(n, dn);
+  if ((int64_t)blockIdx.x * kSortTile >= n) return;  // nothing of this tile in use
   const int tid = threadIdx.x;
   const int w = tid >> 6;
   const int lane = tid & 63;
@@ -239,18 +297,38 @@ void scan_run_impl(uint32_t *data, int64_t L, uint32_t *sums, hipStream_t st) {
 
 // bucket b's range starts at the first sorted position whose key is >= b
 __global__ __launch_bounds__(256) void k_bucket_ptr(const uint32_t *__restrict__ skeys,
-                                                    int64_t n, uint32_t r,
-                                                    uint32_t *__restrict__ bptr) {
+                                                    int64_t n, const uint32_t *__restrict__ dn,
+                                                    uint32_t r, uint32_t *__restrict__ bptr) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  n = keys_in_use(n, dn);
   if (j > n) return;
   const int64_t prev = j > 0 ? (int64_t)skeys[j - 1] : -1;
   const int64_t cur = j < n ? (int64_t)skeys[j] : (int64_t)r;
   for (int64_t b = prev + 1; b <= cur; ++b) bptr[b] = (uint32_t)j;
 }
 
-__global__ void k_fill_identity_ptr(uint32_t *bptr, int64_t n) {
+// The same pointers with the key count on the device: one thread per
+// bucket b in [0, r], bptr[b] = the first position whose key is >= b
+// (a binary search, so the work stays bounded when the keys in use are few
+// and the buckets many).
+__global__ __launch_bounds__(256) void k_bucket_ptr_search(const uint32_t *__restrict__ skeys,
+                                                           const uint32_t *__restrict__ dn,
+                                                           uint32_t r,
+                                                           uint32_t *__restrict__ bptr) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > (int64_t)r) return;
+  uint32_t lo = 0, hi = dn[0];
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if ((int64_t)skeys[mid] < b) lo = mid + 1;
+    else hi = mid;
+  }
+  bptr[b] = lo;
+}
+
+__global__ void k_fill_identity_ptr(uint32_t *bptr, int64_t n, const uint32_t *dn) {
   bptr[0] = 0;
-  bptr[1] = (uint32_t)n;
+  bptr[1] = (uint32_t)keys_in_use(n, dn);
 }
 
 // ---------------------------------------------------------------------------
@@ -503,7 +581,8 @@ int cs_hash_export(int64_t row0, int64_t count, uint32_t r, uint64_t seed,
 }
 
 int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
-               hipStream_t st, uint32_t **skeys, uint32_t **svals, uint32_t *ptr) {
+               hipStream_t st, uint32_t **skeys, uint32_t **svals, uint32_t *ptr,
+               const uint32_t *dn) {
   int bits = 0;
   while (bits < 32 && ((uint64_t)1 << bits) < (uint64_t)r) ++bits;
   const int passes = (bits + 7) / 8;
@@ -521,39 +600,27 @@ int sort_pairs(uint32_t *keys, uint32_t *vals, int64_t n, uint32_t r, Arena &ws,
     const int shift = 8 * p;
     const int nb = (bits - shift) < 8 ? (bits - shift) : 8;
     const uint32_t mask = (1u << nb) - 1u;
-    k_radix_hist<<<(unsigned)ntiles, kSortThreads, 0, st>>>(kin, n, shift, mask, hist,
+    k_radix_hist<<<(unsigned)ntiles, kSortThreads, 0, st>>>(kin, n, dn, shift, mask, hist,
                                                             ntiles);
     scan_run_impl(hist, L, sums, st);
-    k_radix_scatter<<<(unsigned)ntiles, kSortThreads, 0, st>>>(kin, vin, n, shift, nb,
+    k_radix_scatter<<<(unsigned)ntiles, kSortThreads, 0, st>>>(kin, vin, n, dn, shift, nb,
                                                                hist, ntiles, kout, vout);
     uint32_t *t;
     t = kin; kin = kout; kout = t;
     t = vin; vin = vout; vout = t;
   }
   if (ptr) {
-    if (passes)
-      k_bucket_ptr<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(kin, n, r, ptr);
+    if (passes && dn)
+      k_bucket_ptr_search<<<(unsigned)ceil_div((int64_t)r + 1, 256), 256, 0, st>>>(kin, dn, r,
+                                                                                  ptr);
+    else if (passes)
+      k_bucket_ptr<<<(unsigned)ceil_div(n + 1, 256), 256, 0, st>>>(kin, n, nullptr, r, ptr);
     else
-      k_fill_identity_ptr<<<1, 1, 0, st>>>(ptr, n);
+      k_fill_identity_ptr<<<1, 1, 0, st>>>(ptr, n, dn);
   }
   PSK_HIP_TRY(hipGetLastError());
   *skeys = kin;
   *svals = vin;
-  return 0;
-}
-
-int cs_bin(int64_t n, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
-           uint32_t **perm, uint32_t **bptr) {
-  uint32_t *k0 = ws.take<uint32_t>(n);
-  uint32_t *v0 = ws.take<uint32_t>(n);
-  uint32_t *bp = ws.take<uint32_t>((size_t)r + 1);
-  KTimer timer("cs_bin", st, !ws.dry());
-  if (!ws.dry())
-    k_hash_keys<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, r, seed, k0, v0);
-  uint32_t *sk = nullptr;
-  int rc = sort_pairs(k0, v0, n, r, ws, st, &sk, perm, bp);
-  if (rc) return rc;
-  *bptr = bp;
   return 0;
 }
 
@@ -567,21 +634,58 @@ int osnap_hash_export(int64_t row0, int64_t count, uint32_t s, uint32_t r, uint6
   return 0;
 }
 
-int osnap_bin(int64_t n, uint32_t s, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
-              uint32_t **perm, uint32_t **bptr) {
+// Bins of the (row, non-zero) pairs: s per row (s = 1 for CountSketch,
+// rb = r / s rows of S per block).  For CSR A only the rows holding an
+// entry are listed first (their count stays on the device and bounds the
+// sort), so a matrix with many empty rows sorts only the others.
+static int bin_pairs(const psk_mat &A, uint32_t s, uint32_t r, uint64_t seed, Arena &ws,
+                     hipStream_t st, uint32_t **perm, uint32_t **bptr) {
+  const int64_t n = A.n;
   const int64_t pairs = n * (int64_t)s;
+  const bool compact = A.format == PSK_CSR;
   uint32_t *k0 = ws.take<uint32_t>(pairs);
   uint32_t *v0 = ws.take<uint32_t>(pairs);
   uint32_t *bp = ws.take<uint32_t>((size_t)r + 1);
+  uint32_t *rank = nullptr, *rows = nullptr, *cnt = nullptr, *sums = nullptr;
+  if (compact) {
+    rank = ws.take<uint32_t>((size_t)n + 1);
+    rows = ws.take<uint32_t>((size_t)n);
+    cnt = ws.take<uint32_t>(2);
+    scan_plan_impl(n + 1, ws, &sums);
+  }
+  if (!ws.dry() && !ws.ok()) return fail(PSK_ENOMEM, "workspace too small for the binning");
   KTimer timer("cs_bin", st, !ws.dry());
-  if (!ws.dry())
-    k_hash_keys_osnap<<<(unsigned)ceil_div(pairs, 256), 256, 0, st>>>(pairs, s, r / s, seed,
-                                                                       k0, v0);
+  if (!ws.dry()) {
+    if (compact) {
+      const unsigned g = (unsigned)ceil_div(n + 1, 256);
+      k_row_flags<<<g, 256, 0, st>>>(A.indptr, n, rank);
+      scan_run_impl(rank, n + 1, sums, st);
+      k_row_compact<<<g, 256, 0, st>>>(A.indptr, rank, n, s, rows, cnt);
+      k_hash_keys_rows<<<(unsigned)ceil_div(pairs, 256), 256, 0, st>>>(rows, cnt, s, r / s,
+                                                                        seed, k0, v0);
+    } else if (s == 1) {
+      k_hash_keys<<<(unsigned)ceil_div(n, 256), 256, 0, st>>>(n, r, seed, k0, v0);
+    } else {
+      k_hash_keys_osnap<<<(unsigned)ceil_div(pairs, 256), 256, 0, st>>>(pairs, s, r / s, seed,
+                                                                         k0, v0);
+    }
+  }
   uint32_t *sk = nullptr;
-  int rc = sort_pairs(k0, v0, pairs, r, ws, st, &sk, perm, bp);
+  // for CSR A the pairs of the listed rows (cnt[1]) bound the sort
+  const int rc = sort_pairs(k0, v0, pairs, r, ws, st, &sk, perm, bp, compact ? cnt + 1 : nullptr);
   if (rc) return rc;
   *bptr = bp;
   return 0;
+}
+
+int cs_bin(const psk_mat &A, uint32_t r, uint64_t seed, Arena &ws, hipStream_t st,
+           uint32_t **perm, uint32_t **bptr) {
+  return bin_pairs(A, 1u, r, seed, ws, st, perm, bptr);
+}
+
+int osnap_bin(const psk_mat &A, uint32_t s, uint32_t r, uint64_t seed, Arena &ws,
+              hipStream_t st, uint32_t **perm, uint32_t **bptr) {
+  return bin_pairs(A, s, r, seed, ws, st, perm, bptr);
 }
 
 int cs_apply(const psk_mat &A, uint32_t r, const uint32_t *perm,

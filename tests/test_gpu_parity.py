@@ -152,6 +152,46 @@ def test_sketch_cs_csr_empty_rows_and_empty_matrix(api):
     assert np.all(sa == 0)
 
 
+@pytest.mark.parametrize("prec", ["f64", "bf16", "fp8"])
+def test_csr_mostly_empty_rows(api, prec):
+    """CSR A is binned over the rows that hold an entry only: a Zipf matrix
+    with a few percent of its rows occupied gives the oracle's G*S*A in every
+    precision and OSNAP S*A (s = 4) in bin order bit for bit on integers;
+    an all-empty matrix and one whose only entries sit in its first and last
+    rows give zero and the oracle's values."""
+    from oracle import osnap as oo
+    tol = {"f64": 1e-13, "bf16": 1e-4, "fp8": 1e-4}[prec]
+    ref_gcs = {"f64": lambda a, m, r, s: osk.sketch_gcs(a, m, r, s),
+               "bf16": osk.sketch_gcs_bf16_reference,
+               "fp8": osk.sketch_gcs_fp8_reference}[prec]
+    a = synth.csr_zipf(400_000, 120, 1e-3, seed=11, dtype=np.float32)
+    occupied = int((np.diff(a.indptr) > 0).sum())
+    _say(f"mostly empty {prec}: n={a.shape[0]} occupied={occupied} nnz={a.nnz}")
+    assert occupied < a.shape[0] // 20
+    A = to_device(a)
+    for m, r in ((96, 4096), (33, 50000)):
+        c = api.sketch_gcs(A, m, r, seed=8, prec=prec).cpu().numpy()
+        e = rel_fro(c, ref_gcs(a, m, r, 8))
+        _say(f"  G S A m={m} r={r}: {e:.3e}")
+        assert e <= tol
+    small = synth.csr_integer(2000, 30, 0.1, seed=3)
+    srow = np.repeat(np.arange(2000), np.diff(small.indptr))
+    place = np.sort(np.random.default_rng(3).choice(200_000, 2000, replace=False))
+    ai = synth.csr_from_parts(200_000, 30, place[srow], small.indices, small.data)
+    for s, r in ((4, 1024), (1, 777)):
+        got = api.sketch_osnap(to_device(ai), s, 0, r, seed=5).cpu().numpy()
+        np.testing.assert_array_equal(got, oo.sketch_osnap(ai, r, s, 5))
+    z = synth.csr_from_parts(70_000, 12, [], [], [])
+    assert np.all(api.sketch_osnap(to_device(z), 4, 0, 256, seed=1).cpu().numpy() == 0)
+    assert np.all(api.sketch_osnap(to_device(z), 4, 16, 256, seed=1, prec=prec).cpu().numpy()
+                  == 0)
+    ends = synth.csr_from_parts(70_000, 12, [0, 0, 69_999], [2, 11, 5], [1.0, -3.0, 2.0])
+    np.testing.assert_array_equal(api.sketch_osnap(to_device(ends), 2, 0, 64, seed=4).cpu().numpy(),
+                                  oo.sketch_osnap(ends, 64, 2, 4))
+    c = api.sketch_gcs(to_device(ends), 9, 64, seed=4, prec=prec).cpu().numpy()
+    assert rel_fro(c, ref_gcs(ends, 9, 64, 4)) <= tol
+
+
 # ---------------------------------------------------------------------------
 # G*S*A (FP64)
 # ---------------------------------------------------------------------------
