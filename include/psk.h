@@ -40,7 +40,8 @@
  * - A CSR A is validated on the device before any kernel walks it: offsets
  *   from 0 to nnz, never decreasing, column indices in [0, d) (the CSR
  *   definition of Section 1).  One pass reads indptr and indices once; a
- *   malformed A returns PSK_EINVAL with nothing else enqueued.  The stored
+ *   malformed A returns PSK_EINVAL with nothing else enqueued.  A matrix
+ *   flagged PSK_MAT_CHECKED (accepted by psk_check before) skips this pass.  The stored
  *   values are not part of this check (psk_check tests them on request).
  * - Non-finite input: NaN and infinities propagate through the sums and
  *   products of the stream-ordered calls (IEEE arithmetic) into their
@@ -109,7 +110,14 @@ enum { PSK_F64 = 0, PSK_F32 = 1 };     /* psk_mat.dtype  */
  *        bit-reproducibility of the affected outputs is not guaranteed.
  *        indptr[0] must be 0, indptr never decreasing, indptr[n] == nnz;
  *        every call checks this and the index range on the device before
- *        use (PSK_EINVAL). */
+ *        use (PSK_EINVAL), unless flags holds PSK_MAT_CHECKED.
+ * flags: 0, or PSK_MAT_CHECKED for a CSR matrix that psk_check has accepted
+ *        and whose indptr and indices have not changed since: the calls then
+ *        skip their own structure check and the stream synchronisation it
+ *        needs.  The flag is the caller's promise; a malformed matrix passed
+ *        with it is read out of bounds.  Ignored for dense A.  Any other bit,
+ *        or a nonzero reserved word, is PSK_EINVAL. */
+enum { PSK_MAT_CHECKED = 1 };          /* psk_mat.flags  */
 typedef struct psk_mat {
   int32_t format;          /* PSK_DENSE or PSK_CSR              */
   int32_t dtype;           /* PSK_F64 or PSK_F32                */
@@ -120,6 +128,8 @@ typedef struct psk_mat {
   const void *values;      /* dense: >= (n-1)*ld+d elements; CSR: nnz elements */
   const int64_t *indptr;   /* CSR: n+1 row offsets              */
   const int32_t *indices;  /* CSR: nnz column indices           */
+  uint32_t flags;          /* 0 or PSK_MAT_CHECKED              */
+  uint32_t reserved;       /* 0                                 */
 } psk_mat;
 
 /* ---- precision of the Gaussian GEMM of sketch_gcs / lsq_solve ---------- */

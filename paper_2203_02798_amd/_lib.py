@@ -21,6 +21,7 @@ STATUS_NAMES = {
 PSK_PENDING = 1
 PSK_REQ_LSQ, PSK_REQ_LEVERAGE = 0, 1
 PSK_DENSE, PSK_CSR = 0, 1
+PSK_MAT_CHECKED = 1
 PSK_F64, PSK_F32 = 0, 1
 PSK_PROBE_BLOCKS = 4096
 PSK_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -54,6 +55,8 @@ class PskMat(ctypes.Structure):
         ("values", ctypes.c_void_p),
         ("indptr", ctypes.c_void_p),
         ("indices", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 

@@ -26,11 +26,14 @@ _PREC = {"f64": L.PSK_PREC_F64, "bf16": L.PSK_PREC_BF16, "fp8": L.PSK_PREC_FP8}
 @dataclass
 class CsrMatrix:
     """CSR matrix on the device: int64 indptr (n+1), int32 indices, values
-    (float64 or float32), 0-based."""
+    (float64 or float32), 0-based.  ``checked`` (set by ``check(A,
+    mark=True)``) passes PSK_MAT_CHECKED, so the calls skip their own
+    structure check; clear it after changing indptr or indices."""
     indptr: torch.Tensor
     indices: torch.Tensor
     values: torch.Tensor
     shape: tuple
+    checked: bool = False
 
     @property
     def device(self):
@@ -72,6 +75,7 @@ def _mat(A):
         m.values = A.values.data_ptr() if m.nnz else None
         m.indptr = A.indptr.data_ptr()
         m.indices = A.indices.data_ptr() if m.nnz else None
+        m.flags = L.PSK_MAT_CHECKED if A.checked else 0
         return m
     if not isinstance(A, torch.Tensor) or A.dim() != 2:
         raise TypeError("A must be a 2-D device tensor or a CsrMatrix")
@@ -116,15 +120,19 @@ def version():
     return L.lib().psk_version().decode()
 
 
-def check(A, values=False):
+def check(A, values=False, mark=False):
     """psk_check: raise PskError (PSK_EINVAL) for a malformed CSR A and, with
-    values, (PSK_ENONFINITE) for a NaN or infinity among its entries."""
+    values, (PSK_ENONFINITE) for a NaN or infinity among its entries.  With
+    mark, a CSR A that passes gets ``A.checked = True`` (PSK_MAT_CHECKED in
+    later calls)."""
     pm = _mat(A)
     dev = _device(A)
     nbytes = workspace_size(L.PSK_OP_CHECK, A)
     ws = _ws(nbytes, dev)
     L.check(L.lib().psk_check(ctypes.byref(pm), int(bool(values)), ws.data_ptr(), ws.numel(),
                               _stream(dev)), "psk_check")
+    if mark and isinstance(A, CsrMatrix):
+        A.checked = True
 
 
 def cs_hash(count, r, seed, row0=0, device="cuda"):

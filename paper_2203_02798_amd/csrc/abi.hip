@@ -85,6 +85,8 @@ int check_mat(const psk_mat *A) {
     return fail(PSK_EDTYPE, "A->dtype must be PSK_F64 or PSK_F32");
   if (A->n < 1 || A->d < 1) return fail(PSK_EINVAL, "A must have n >= 1 and d >= 1");
   if (A->n >= ((int64_t)1 << 31)) return fail(PSK_EUNSUPPORTED, "n must be < 2^31");
+  if ((A->flags & ~(uint32_t)PSK_MAT_CHECKED) != 0u || A->reserved != 0u)
+    return fail(PSK_EINVAL, "A->flags may hold PSK_MAT_CHECKED only; A->reserved must be 0");
   if (A->format == PSK_DENSE) {
     if (A->ld < A->d) return fail(PSK_EINVAL, "dense A needs ld >= d");
     if (!A->values) return fail(PSK_EINVAL, "A->values is NULL");
@@ -271,6 +273,8 @@ int psk_workspace_size(int op, const psk_mat *A, int64_t m, int64_t r, int64_t k
                        int prec, size_t *bytes) {
   if (!bytes) return fail(PSK_EINVAL, "bytes is NULL");
   if (!A) return fail(PSK_EINVAL, "A is NULL");
+  if ((A->flags & ~(uint32_t)PSK_MAT_CHECKED) != 0u || A->reserved != 0u)
+    return fail(PSK_EINVAL, "A->flags may hold PSK_MAT_CHECKED only; A->reserved must be 0");
   Arena ws;  // dry run
   int rc = 0;
   // every call that walks a CSR A checks its structure first (its result

@@ -163,7 +163,9 @@ int factor_status(int h, const char *rank_msg) {
 }
 
 int validate_csr(const psk_mat &A, Arena &ws, hipStream_t st) {
-  if (A.format != PSK_CSR) return 0;
+  // dense A has no structure to check; a CSR matrix flagged as checked was
+  // accepted by psk_check before, on the caller's word
+  if (A.format != PSK_CSR || (A.flags & PSK_MAT_CHECKED)) return 0;
   const size_t mk = ws.mark();
   const int rc = check_operand(A, false, ws, st);
   ws.release(mk);

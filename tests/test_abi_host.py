@@ -269,6 +269,34 @@ def test_check_planning_and_arguments(lib):
     assert L.STATUS_NAMES[L.PSK_ENONFINITE] == "PSK_ENONFINITE"
 
 
+def test_checked_flag(lib):
+    """PSK_MAT_CHECKED skips the per-call structure check, so a flagged CSR A
+    never plans more than without it; any other flag bit or a nonzero reserved
+    word is refused before any device work, for dense A as well."""
+    plain = _csr(1000, 64, 5000)
+    flagged = _csr(1000, 64, 5000)
+    flagged.flags = L.PSK_MAT_CHECKED
+    st, g0 = _ws(L.PSK_OP_GRAM, plain)
+    st1, g1 = _ws(L.PSK_OP_GRAM, flagged)
+    assert st == 0 and st1 == 0 and g1 <= g0
+    for op in (L.PSK_OP_SKETCH_CS, L.PSK_OP_SKETCH_GCS, L.PSK_OP_ROWNORMS):
+        st, a = _ws(op, plain, m=64, r=512, k=8)
+        st1, b = _ws(op, flagged, m=64, r=512, k=8)
+        assert st == 0 and st1 == 0 and b <= a
+    # psk_check itself always runs its pass: it still needs the word
+    st, c = _ws(L.PSK_OP_CHECK, flagged)
+    assert st == 0 and c >= 4
+    for bad in (_csr(1000, 64, 5000), _dense(1000, 64)):
+        bad.flags = 2
+        assert _ws(L.PSK_OP_GRAM, bad)[0] == L.PSK_EINVAL
+        bad.flags, bad.reserved = 0, 1
+        assert _ws(L.PSK_OP_GRAM, bad)[0] == L.PSK_EINVAL
+        assert lib.psk_check(ctypes.byref(bad), 0, None, 0, None) == L.PSK_EINVAL
+    d = _dense(100, 8)
+    d.flags = L.PSK_MAT_CHECKED  # ignored for dense A
+    assert lib.psk_check(ctypes.byref(d), 0, None, 0, None) == L.PSK_OK
+
+
 def test_every_entry_point_validates_csr_first():
     """Static check of the C-ABI layer: every entry point that takes a matrix
     A runs the CSR structure check on its workspace before anything else is

@@ -202,6 +202,46 @@ def test_server_refuses_malformed_csr(api):
     assert r2["status"] == "PSK_OK" and torch.isfinite(x2).all()
 
 
+def test_checked_flag_skips_the_check_only(api):
+    """check(A, mark=True) sets PSK_MAT_CHECKED on a CSR matrix that passes:
+    later calls skip their structure pass (no 'check' stage is timed) and
+    give bit-identical results; a malformed matrix is refused and stays
+    unmarked."""
+    a = _csr_parts(n=20000, d=48, seed=2)
+    n, d = a.shape
+    b = torch.randn(n, dtype=torch.float64, device="cuda")
+    bad = _safe_malformed(api, a)["index d"]
+    assert _status(lambda: api.check(bad, mark=True)) == EINVAL and not bad.checked
+
+    def run(A):
+        with api.kernel_timing() as kt:
+            c = api.sketch_gcs(A, 96, 4096, 3, prec="bf16")
+            g = api.gram(A)
+            _, ri = api.sketch_qr(api.sketch_gcs(A, 96, 4096, 3))
+            th = api.rownorms_sq(A, ri)
+            x, info = api.lsq_solve(A, b, m=96, r=4096, seed=3)
+            torch.cuda.synchronize()
+            names = set(kt.stats())
+        return (c, g, th, x), info, names
+
+    A = api.CsrMatrix.from_scipy(a)
+    ref, info0, names0 = run(A)
+    assert "check" in names0
+    api.check(A, mark=True)
+    assert A.checked
+    got, info1, names1 = run(A)
+    assert "check" not in names1
+    for u, v in zip(ref, got):
+        assert torch.equal(u, v)
+    assert info0["iters"] == info1["iters"]
+    plain = api.CsrMatrix.from_scipy(a)
+    with api.Server(1 << 27, slots=2) as srv:
+        t1, x1 = srv.submit_lsq(plain, b, 96, 4096, seed=3)
+        t2, x2 = srv.submit_lsq(A, b, 96, 4096, seed=3)
+        assert srv.wait(t1)["status"] == "PSK_OK" and srv.wait(t2)["status"] == "PSK_OK"
+    assert torch.equal(x1, x2)
+
+
 def _dense_problem(n=6000, d=20, seed=3):
     a, b, _ = synth.lsq_problem(n, d, 100.0, seed=seed)
     return to_device(a), torch.as_tensor(b, device="cuda")
