@@ -678,6 +678,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-only", action="store_true",
                     help="run the serving trace alone and print its record")
+    ap.add_argument("--csr-only", action="store_true",
+                    help="run the CSR 1e6 x 500 workload alone and print its record "
+                         "(hardware-counter runs of the sparse products)")
     ap.add_argument("--no-extras", action="store_true",
                     help="the headline step only (hardware-counter runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -708,6 +711,10 @@ def main():
     torch.cuda.set_device(0)
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(api, torch)}), flush=True)
+        return
+    if args.csr_only:
+        csr, *_ = csr_workload(api, torch, args.steps, args.warmup, args.seed)
+        print(json.dumps({"csr_1e6x500": csr}), flush=True)
         return
     seed = args.seed
     n, d, r, m = HEAD["n"], HEAD["d"], HEAD["r"], HEAD["m"]

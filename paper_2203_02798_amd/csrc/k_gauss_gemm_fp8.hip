@@ -334,7 +334,11 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
     const unsigned char *__restrict__ q, const unsigned char *__restrict__ sc, int tiles_m,
     int tiles_n, int64_t c0, int64_t kend, int64_t cper, int ks0,
     float *__restrict__ out /* [splits][m][d] */) {
-  __shared__ __align__(16) unsigned char smem[2 * kBufBytes];
+  // the two chunk buffers as separate objects: the compiler can then tell a
+  // copy into one from the reads of the other and need not wait for the
+  // copy before reading
+  __shared__ __align__(16) unsigned char smem0[kBufBytes];
+  __shared__ __align__(16) unsigned char smem1[kBufBytes];
 
   const int64_t nblk = (int64_t)gridDim.x;
   int64_t lin = blockIdx.x;
@@ -367,8 +371,7 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
       (void *)(q + cb * chunk_data), (short)0, (int)(nch * chunk_data), 0x00020000);
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       (void *)(sc + cb * chunk_sc), (short)0, (int)(nch * chunk_sc), 0x00020000);
-  auto copy_chunk = [&](int64_t crel, int buf) {
-    unsigned char *base = smem + buf * kBufBytes;
+  auto copy_chunk = [&](int64_t crel, unsigned char *base) __attribute__((always_inline)) {
     // 64 KiB of data: 64 pieces of 1 KiB, wave w takes pieces w, w+8, ...
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
@@ -406,20 +409,28 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
     return a;
   };
 
-  v8i a_cur;
-  int sa_cur = 127;
+  // G's fragments are read once (L2 misses): they are fetched two chunks
+  // ahead, S*A's (shared by the row tiles of the split, on one XCD) one
+  // chunk ahead into the other LDS buffer
+  v8i a_cur, a_n1;
+  int sa_cur = 127, sa_n1 = 127;
   if (nch > 0) {
-    copy_chunk(0, 0);
+    copy_chunk(0, smem0);
     a_cur = make_a(cb, sa_cur);
+    a_n1 = make_a(cb + 1, sa_n1);
     __builtin_amdgcn_s_waitcnt(0);
   }
   __syncthreads();
-  for (int64_t c = 0; c < nch; ++c) {
-    const int buf = (int)(c & 1);
-    copy_chunk(c + 1, buf ^ 1);  // past the split: range check reads zeros
-    int sa_next;
-    const v8i a_next = make_a(cb + c + 1, sa_next);
-    const unsigned char *bb = smem + buf * kBufBytes;
+  // chunk c from cur while chunk c + 1 is copied into nxt
+  auto chunk = [&](int64_t c, const unsigned char *bb, unsigned char *nxt)
+                   __attribute__((always_inline)) {
+    copy_chunk(c + 1, nxt);  // past the split: range check reads zeros
+    // the two fragment loads of chunk c + 2 are issued after the copies,
+    // so that the wait below can leave them in flight
+    __builtin_amdgcn_sched_barrier(0);
+    int sa_n2;
+    const v8i a_n2 = make_a(cb + c + 2, sa_n2);
+    __builtin_amdgcn_sched_barrier(0);
     const unsigned char *lo = bb + (2 * g) * kPartBytes + li * 16;      // bytes 0..15
     const unsigned char *hi = bb + (2 * g + 1) * kPartBytes + li * 16;  // bytes 16..31
     const uint4 *scp = reinterpret_cast<const uint4 *>(bb + kDataBytes + li * kNB);
@@ -451,10 +462,18 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gemm_fp8(
           break;
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);
+    // this wave's copies of chunk c + 1 have landed: vmcnt(2) (expcnt and
+    // lgkmcnt not waited for), only chunk c + 2's two fragment loads remain
+    __builtin_amdgcn_s_waitcnt(0x0F72);
     __syncthreads();
-    a_cur = a_next;
-    sa_cur = sa_next;
+    a_cur = a_n1;
+    sa_cur = sa_n1;
+    a_n1 = a_n2;
+    sa_n1 = sa_n2;
+  };
+  for (int64_t c = 0; c < nch; c += 2) {
+    chunk(c, smem0, smem1);
+    if (c + 1 < nch) chunk(c + 1, smem1, smem0);
   }
 
   // accumulator element e of block nb: row 4 g + e, column li
