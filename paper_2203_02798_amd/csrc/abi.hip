@@ -155,6 +155,10 @@ int do_sketch_osnap(const psk_mat &A, int64_t s, int64_t m, int64_t r, uint64_t 
   const int64_t entries = A.n * s;
   if (m == 0)
     return cs_apply(A, (uint32_t)r, perm, bptr, C, ws, st, false, scale, entries);
+  // CSR A whose S*A is sparse: the product over its nonzeros, formed from
+  // the same bins with the same sums
+  if (gauss_sparse_pick(A, r, m, prec, s))
+    return gauss_gemm_sparse(m, r, A, perm, bptr, seed, prec, (double *)C, ws, st, s, scale);
   void *SA = ws.take<double>((size_t)r * A.d);
   if ((rc = cs_apply(A, (uint32_t)r, perm, bptr, SA, ws, st, true, scale, entries))) return rc;
   return gauss_gemm(m, r, A.d, seed, prec, SA, PSK_F64, (double *)C, ws, st);

@@ -168,16 +168,19 @@ int gauss_gemm_fp8_csr(int64_t m, int64_t r, const psk_mat &A, const uint32_t *p
 // it is the kernel to use (FP8 keeps the fused dense FP8 GEMM unless A has
 // fewer than r d / 512 nonzeros: above that its MFMA contraction costs less
 // than the sparse product's per-nonzero updates).
-bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m);
-bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec);
+// per_row: bin entries per row of A (1 for CountSketch, s for an OSNAP)
+bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m, int64_t per_row = 1);
+bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec, int64_t per_row = 1);
 // the product's own limits (CSR, d <= 1023, sizes); gauss_gemm_sparse checks
 // only these, the callers choose when it is worth taking
-bool gauss_sparse_fits(const psk_mat &A);
+bool gauss_sparse_fits(const psk_mat &A, int64_t per_row = 1);
 // one row per bucket, in row order, sign +1: the bins of S = identity
 int identity_bins(int64_t n, Arena &ws, uint32_t **perm, uint32_t **bptr, hipStream_t st);
+// per_row, sa_scale: the OSNAP's bins of n s (row, non-zero) pairs and its
+// 1/sqrt(s), applied to each bucket's sum as S*A is formed
 int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
                       const uint32_t *bptr, uint64_t seed, int prec, double *C, Arena &ws,
-                      hipStream_t st);
+                      hipStream_t st, int64_t per_row = 1, double sa_scale = 1.0);
 
 // ---- FP64 dense kernels (k_dense.hip) --------------------------------------
 // C (d x d, out_dtype) = alpha * A^T A + beta * C for dense A.

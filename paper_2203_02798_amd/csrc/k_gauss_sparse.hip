@@ -163,8 +163,9 @@ __device__ void bucket_entries_wave(const T *__restrict__ vals, const int64_t *_
                                     const int32_t *__restrict__ indices,
                                     const uint32_t *__restrict__ perm, uint32_t j0, uint32_t j1,
                                     uint32_t e0, uint32_t cap, int64_t b, int64_t d,
-                                    int64_t dpad, double *acc, uint32_t *__restrict__ eb,
-                                    int32_t *__restrict__ ec, double *__restrict__ ev) {
+                                    int64_t dpad, double scale, double *acc,
+                                    uint32_t *__restrict__ eb, int32_t *__restrict__ ec,
+                                    double *__restrict__ ev) {
   const int lane = (int)(threadIdx.x & 63u);
   for (int64_t c = lane; c < dpad; c += 64) acc[c] = 0.0;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -182,7 +183,7 @@ __device__ void bucket_entries_wave(const T *__restrict__ vals, const int64_t *_
       const uint32_t pos = e0 + cnt + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
       eb[pos] = (uint32_t)b;
       ec[pos] = (int32_t)c;
-      ev[pos] = entry_value<LIMBS>(v);
+      ev[pos] = entry_value<LIMBS>(v * scale);
     }
     cnt += (uint32_t)__popcll(mask);
   }
@@ -205,12 +206,14 @@ constexpr int kLaneEnt = 8;  // entries a bucket may have for the lane path
 // then the holes.  Buckets with more entries are taken afterwards, one at a
 // time, by their wavefront through a dense LDS row (bucket_entries_wave).
 // BF16: the value written is hi + lo (the two limbs); otherwise S*A itself.
+// Each bucket's sum is multiplied by scale once (1 for CountSketch, 1/sqrt(s)
+// for an OSNAP's bins of (row, non-zero) pairs), as S*A itself is formed.
 template <typename T, bool LIMBS>
 __global__ __launch_bounds__(256) void k_sa_entries(
     const T *__restrict__ vals, const int64_t *__restrict__ indptr,
     const int32_t *__restrict__ indices, int64_t d, int64_t dpad, int64_t r,
     const uint32_t *__restrict__ perm, const uint32_t *__restrict__ bptr,
-    const uint32_t *__restrict__ eoff, uint32_t *__restrict__ eb,
+    const uint32_t *__restrict__ eoff, double scale, uint32_t *__restrict__ eb,
     int32_t *__restrict__ ec, double *__restrict__ ev) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int lane = (int)(threadIdx.x & 63u);
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(256) void k_sa_entries(
       if (k < n && v != 0.0) {
         eb[e0 + pos] = (uint32_t)b;
         ec[e0 + pos] = col[k];
-        ev[e0 + pos] = entry_value<LIMBS>(v);
+        ev[e0 + pos] = entry_value<LIMBS>(v * scale);
         ++pos;
       }
     }
@@ -298,7 +301,7 @@ __global__ __launch_bounds__(256) void k_sa_entries(
     const uint32_t be0 = __shfl(e0, i, 64), bcap = __shfl(cap, i, 64);
     const int64_t bb = b - lane + i;
     bucket_entries_wave<T, LIMBS>(vals, indptr, indices, perm, bj0, bj1, be0, bcap, bb, d, dpad,
-                                  acc, eb, ec, ev);
+                                  scale, acc, eb, ec, ev);
   }
 }
 
@@ -785,21 +788,26 @@ __global__ __launch_bounds__(256) void k_sparse_reduce(const double *__restrict_
 
 }  // namespace
 
-bool gauss_sparse_fits(const psk_mat &A) {
+bool gauss_sparse_fits(const psk_mat &A, int64_t per_row) {
   if (A.format != PSK_CSR) return false;
   // the dense bucket rows of the entry kernel: 4 x d accumulators in 64 KiB of LDS
   if ((size_t)4 * ((A.d + 3) & ~(int64_t)3) * sizeof(double) > 65536) return false;
   if (A.d > 1023) return false;
-  return A.nnz < ((int64_t)1 << 31) && A.n < ((int64_t)1 << 31);
+  // bin entries (n per_row) and entry slots (nnz per_row) in 32 bits
+  return A.nnz * per_row < ((int64_t)1 << 31) && A.n * per_row < ((int64_t)1 << 31);
 }
 
-bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m) {
-  if (m <= 0 || !gauss_sparse_fits(A)) return false;
+bool gauss_sparse_ok(const psk_mat &A, int64_t r, int64_t m, int64_t per_row) {
+  if (m <= 0 || !gauss_sparse_fits(A, per_row)) return false;
   // S*A from the binned rows has the bits of S*A from cs_apply when no
   // bucket's rows are split
-  if (cs_splits(A.n, r) != 1) return false;
-  // S*A sparse enough: at most one nonzero in 32 of its r x d entries
-  return A.nnz * 32 <= r * A.d;
+  if (cs_splits(A.n * per_row, r) != 1) return false;
+  // S*A (at most nnz per_row nonzeros) no denser than 1 in 32 of its r x d
+  // entries (measured: in FP64 at 1/16 the product over the nonzeros is
+  // already slower than the dense GEMM, at 1/8 forty times slower; its
+  // contraction reads G from LDS once per nonzero and waits on the longest
+  // column run of each wavefront)
+  return A.nnz * per_row * 32 <= r * A.d;
 }
 
 int identity_bins(int64_t n, Arena &ws, uint32_t **perm, uint32_t **bptr, hipStream_t st) {
@@ -812,23 +820,28 @@ int identity_bins(int64_t n, Arena &ws, uint32_t **perm, uint32_t **bptr, hipStr
   return 0;
 }
 
-bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec) {
-  if (!gauss_sparse_ok(A, r, m)) return false;
+bool gauss_sparse_pick(const psk_mat &A, int64_t r, int64_t m, int prec, int64_t per_row) {
+  if (!gauss_sparse_ok(A, r, m, per_row)) return false;
+  const int64_t nz = A.nnz * per_row;  // bound on the nonzeros of S*A
+  if (prec != PSK_PREC_FP8) return true;
   // FP8: both forms draw the same m r normals; the dense form adds the FP8
   // MFMA contraction over all r d entries and the scatter of S*A, the sparse
   // form m FP32 updates per nonzero.  Measured crossover near 1/500 of r d
   // (CSR 1e7 x 1000 at 1e-3 of r d: sparse 8.1 ms, dense 11.2 ms; CSR
   // 1e6 x 500 at 4e-3: sparse 1.09 ms, dense 1.00 ms).
-  if (prec == PSK_PREC_FP8 && fp8_csr_fusable(A, r)) return A.nnz * 512 <= r * A.d;
-  return true;
+  // FP8 (its dense form fused from the bins, or from S*A for an OSNAP)
+  return nz * 512 <= r * A.d;
 }
 
 int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *perm,
                       const uint32_t *bptr, uint64_t seed, int prec, double *C, Arena &ws,
-                      hipStream_t st) {
-  if (m <= 0 || !gauss_sparse_fits(A))
+                      hipStream_t st, int64_t per_row, double sa_scale) {
+  if (m <= 0 || !gauss_sparse_fits(A, per_row))
     return fail(PSK_EUNSUPPORTED, "sparse Gaussian product: CSR, d <= 1023, nnz < 2^31");
-  const int64_t n = A.n, d = A.d;
+  // bin entries: n (CountSketch) or n per_row (OSNAP pairs); entry slots
+  // likewise nnz per_row
+  const int64_t n = A.n * per_row, d = A.d;
+  const int64_t nslots = A.nnz * per_row;
   const int mtr = d <= 512 ? 32 : 16;
   const int tiles_m = (int)ceil_div(m, mtr);
   const int64_t blk = prec == PSK_PREC_F64 ? 256 : 512;  // G slots (4 per quad) per block
@@ -844,13 +857,13 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
   uint32_t *be = ws.take<uint32_t>((size_t)nblk + 1);
   uint32_t *sums = nullptr;
   scan_plan(n + 1, ws, &sums);
-  uint32_t *eb = ws.take<uint32_t>((size_t)A.nnz + 1);
-  int32_t *ec = ws.take<int32_t>((size_t)A.nnz + 1);
-  double *ev = ws.take<double>((size_t)A.nnz + 1);
-  uint32_t *sp = ws.take<uint32_t>((size_t)A.nnz + 1);
+  uint32_t *eb = ws.take<uint32_t>((size_t)nslots + 1);
+  int32_t *ec = ws.take<int32_t>((size_t)nslots + 1);
+  double *ev = ws.take<double>((size_t)nslots + 1);
+  uint32_t *sp = ws.take<uint32_t>((size_t)nslots + 1);
   // the sorted values in the precision the product stages them in
-  void *sv = prec == PSK_PREC_F64 ? (void *)ws.take<double>((size_t)A.nnz + 1)
-                                  : (void *)ws.take<float>((size_t)A.nnz + 1);
+  void *sv = prec == PSK_PREC_F64 ? (void *)ws.take<double>((size_t)nslots + 1)
+                                  : (void *)ws.take<float>((size_t)nslots + 1);
   uint32_t *qrank = ws.take<uint32_t>((size_t)nquads + 1);
   uint32_t *qlist = ws.take<uint32_t>((size_t)nquads);
   uint32_t *qsums = nullptr;
@@ -868,7 +881,7 @@ int gauss_gemm_sparse(int64_t m, int64_t r, const psk_mat &A, const uint32_t *pe
     const bool limbs = prec == PSK_PREC_BF16;
 #define PSK_SAE(TT, LB)                                                                   \
   k_sa_entries<TT, LB><<<nb, 256, lds, st>>>((const TT *)A.values, A.indptr, A.indices, d, \
-                                              dpad, r, perm, bptr, eoff, eb, ec, ev)
+                                              dpad, r, perm, bptr, eoff, sa_scale, eb, ec, ev)
     if (A.dtype == PSK_F64) {
       if (limbs) PSK_SAE(double, true); else PSK_SAE(double, false);
     } else {

@@ -105,6 +105,29 @@ def test_sketch_osnap_gaussian(api, kind, s):
             assert rel_fro(c, ref64) <= (1e-2 if prec == "bf16" else 1e-1)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_sketch_osnap_gaussian_over_nonzeros(api, dtype):
+    """CSR A whose OSNAP S*A is sparse (s nnz(A) at most r d / 32): the FP64
+    and BF16 Gaussian products run over the nonzeros of S*A, formed from the
+    OSNAP's bins with 1/sqrt(s) applied to each bucket sum (FP8 keeps its
+    dense form above r d / 512); every precision against its definition
+    (FP64 to 1e-13, BF16 and FP8 against the quantised references at
+    1e-4)."""
+    n, d, r, m, s = 200_000, 64, 65536, 96, 4
+    a = synth.csr_uniform(n, d, 1e-3, seed=12, dtype=dtype)
+    assert a.nnz * s * 32 <= r * d
+    A = to_device(a)
+    sa = oo.sketch_osnap(a, r, s, 3)
+    ref64 = oo.sketch_gosnap(a, m, r, s, 3)
+    for prec, tol in (("f64", 1e-13), ("bf16", 1e-4), ("fp8", 1e-4)):
+        c = api.sketch_osnap(A, s, m, r, seed=3, prec=prec).cpu().numpy()
+        ref = {"f64": ref64, "bf16": osk.gauss_product_bf16_reference(sa, m, 3),
+               "fp8": osk.gauss_product_fp8_reference(sa, m, 3)}[prec]
+        e = rel_fro(c, ref)
+        _say(f"G S A osnap over nonzeros {np.dtype(dtype).name} {prec}: {e:.3e}")
+        assert e <= tol
+
+
 def test_osnap_leverage_on_coherent_rows(api):
     """d rows of leverage 1 (scaled identity rows) inside a Gaussian block,
     r = 8 d: the scores from S*A with OSNAP s = 8 match the oracle's scores
