@@ -13,6 +13,10 @@
 // * Row norms: Algorithm squared_row_norms: Bt = B B^T once, then per row
 //   sum_{k,j} V_k V_j Bt[J_j, J_k].  Short rows take one lane each; rows
 //   longer than 32 entries are taken by the whole wavefront (lanes over k).
+//   That costs a row nnz^2 scattered reads of Bt; a row with more than
+//   max(32, k/8) entries costs less as the product itself, ||V B[J, :]||^2
+//   (nnz contiguous rows of B, k values each): such rows are listed and
+//   taken by k_rownorm_csr_long, a workgroup per row.
 #include "internal.hpp"
 
 namespace psk {
@@ -76,18 +80,30 @@ __global__ __launch_bounds__(256) void k_gram_csc(
   }
 }
 
+// nlong[0] = 0 (the list of rows for the product form)
+__global__ void k_clear_count(uint32_t *__restrict__ nlong) {
+  if (threadIdx.x == 0) nlong[0] = 0u;
+}
+
+// Rows of more than tl entries are only listed here (longlist, nlong); the
+// order of the list does not matter, each row's value is computed alone.
 template <typename T>
 __global__ __launch_bounds__(256) void k_rownorm_csr(
     const T *__restrict__ vals, const int64_t *__restrict__ indptr,
     const int32_t *__restrict__ indices, int64_t n, int64_t d,
-    const double *__restrict__ Bt, double alpha, double beta, double *__restrict__ x) {
+    const double *__restrict__ Bt, double alpha, double beta, double *__restrict__ x,
+    int64_t tl, uint32_t *__restrict__ longlist, uint32_t *__restrict__ nlong) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  const bool have = i < n;
+  bool have = i < n;
   int64_t p0 = 0, p1 = 0;
   if (have) {
     p0 = indptr[i];
     p1 = indptr[i + 1];
+  }
+  if (have && p1 - p0 > tl) {
+    longlist[atomicAdd(nlong, 1u)] = (uint32_t)i;
+    have = false;
   }
   const bool longrow = have && (p1 - p0) > 32;
   if (have && !longrow) {
@@ -118,6 +134,65 @@ __global__ __launch_bounds__(256) void k_rownorm_csr(
     }
     part = wave_sum(part);
     if (lane == 0) x[row] = beta != 0.0 ? alpha * part + beta * x[row] : alpha * part;
+  }
+}
+
+// The listed rows as the product itself: workgroup per row (grid-stride
+// over the list), thread t holds y_j = sum_p V_p B[J_p, j] for its columns
+// j = t + 256 q, q < Q (k <= 256 Q), the entries taken in row order, kU at a
+// time with their rows of B loaded together; then ||y||^2 summed in a
+// fixed order (thread, wavefront, workgroup).
+constexpr int kRnU = 8;  // entries whose B rows are in flight together
+template <typename T, int Q>
+__global__ __launch_bounds__(256) void k_rownorm_csr_long(
+    const T *__restrict__ vals, const int64_t *__restrict__ indptr,
+    const int32_t *__restrict__ indices, const uint32_t *__restrict__ longlist,
+    const uint32_t *__restrict__ nlong, const double *__restrict__ B, int64_t k, double alpha,
+    double beta, double *__restrict__ x) {
+  __shared__ double red[4];
+  const int tid = threadIdx.x;
+  const uint32_t cnt = nlong[0];
+  for (uint32_t l = blockIdx.x; l < cnt; l += gridDim.x) {
+    const int64_t i = (int64_t)longlist[l];
+    const int64_t p0 = indptr[i], p1 = indptr[i + 1];
+    double y[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) y[q] = 0.0;
+    for (int64_t p = p0; p < p1; p += kRnU) {
+      double v[kRnU];
+      int64_t c[kRnU];
+#pragma unroll
+      for (int u = 0; u < kRnU; ++u) {
+        const bool ok = p + u < p1;
+        const int64_t pu = ok ? p + u : p0;  // clamped, value zeroed
+        v[u] = ok ? (double)vals[pu] : 0.0;
+        c[u] = indices[pu];
+      }
+      double b[kRnU][Q];
+#pragma unroll
+      for (int u = 0; u < kRnU; ++u)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int64_t j = tid + 256 * q;
+          b[u][q] = B[c[u] * k + (j < k ? j : 0)];
+        }
+#pragma unroll
+      for (int u = 0; u < kRnU; ++u)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) y[q] = fma(v[u], b[u][q], y[q]);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (tid + 256 * q < k) s = fma(y[q], y[q], s);
+    s = wave_sum(s);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) {
+      const double t = ((red[0] + red[1]) + red[2]) + red[3];
+      x[i] = beta != 0.0 ? alpha * t + beta * x[i] : alpha * t;
+    }
+    __syncthreads();  // red is reused by the next row
   }
 }
 
@@ -169,6 +244,10 @@ int rownorms_csr(double alpha, const psk_mat &A, const double *B, int64_t k,
   const int64_t d = A.d;
   if (d > 8192) return fail(PSK_EUNSUPPORTED, "CSR row norms support d <= 8192");
   double *Bt = ws.take<double>((size_t)d * d);
+  // rows for the product form: more than max(32, k/8) entries (k <= 2048)
+  const int64_t tl = k <= 2048 ? (k / 8 > 32 ? k / 8 : 32) : INT64_MAX;
+  uint32_t *longlist = ws.take<uint32_t>((size_t)A.n);
+  uint32_t *nlong = ws.take<uint32_t>(1);
   // B * B^T (d x d) with the FP64 GEMM
   int rc = dgemm(false, true, d, d, k, 1.0, B, k, B, k, 0.0, Bt, d, ws, st);
   if (rc) return rc;
@@ -176,12 +255,25 @@ int rownorms_csr(double alpha, const psk_mat &A, const double *B, int64_t k,
   if (!ws.ok()) return fail(PSK_ENOMEM, "workspace too small for CSR row norms");
   const unsigned blocks = (unsigned)ceil_div(A.n, 256);
   KTimer timer("rownorm", st);
-  if (A.dtype == PSK_F64)
-    k_rownorm_csr<double><<<blocks, 256, 0, st>>>((const double *)A.values, A.indptr,
-                                                  A.indices, A.n, d, Bt, alpha, beta, x);
-  else
-    k_rownorm_csr<float><<<blocks, 256, 0, st>>>((const float *)A.values, A.indptr,
-                                                 A.indices, A.n, d, Bt, alpha, beta, x);
+  k_clear_count<<<1, 64, 0, st>>>(nlong);
+#define PSK_RNC(T)                                                                         \
+  k_rownorm_csr<T><<<blocks, 256, 0, st>>>((const T *)A.values, A.indptr, A.indices, A.n, d, \
+                                           Bt, alpha, beta, x, tl, longlist, nlong)
+  if (A.dtype == PSK_F64) PSK_RNC(double); else PSK_RNC(float);
+#undef PSK_RNC
+  if (tl != INT64_MAX) {
+    // a fixed grid walks the listed rows (their count stays on the device)
+    const unsigned lb = 2048;
+#define PSK_RNL(T, Q)                                                                   \
+  k_rownorm_csr_long<T, Q><<<lb, 256, 0, st>>>((const T *)A.values, A.indptr, A.indices, \
+                                              longlist, nlong, B, k, alpha, beta, x)
+    if (A.dtype == PSK_F64) {
+      if (k <= 1024) PSK_RNL(double, 4); else PSK_RNL(double, 8);
+    } else {
+      if (k <= 1024) PSK_RNL(float, 4); else PSK_RNL(float, 8);
+    }
+#undef PSK_RNL
+  }
   PSK_HIP_TRY(hipGetLastError());
   return 0;
 }
