@@ -540,6 +540,10 @@ def _rownorm_check(xh, a, b, alpha=1.0, beta=0.0, x0=None):
 @pytest.mark.parametrize("kind,n,d,k", [("dense", 20000, 50, 50), ("dense", 5000, 130, 257),
                                         ("dense32", 7000, 256, 256), ("csr", 100000, 500, 500),
                                         ("csrzipf", 20000, 300, 64),
+                                        # Zipf rows past max(32, k/8) entries as the
+                                        # product a_i B, k above 1024 (8 columns a thread)
+                                        ("csrzipf", 20000, 1200, 1500),
+                                        ("csrzipf32", 20000, 900, 700),
                                         # ragged row tiles and k around the 64-column form
                                         ("dense", 9001, 70, 33), ("dense32", 3001, 256, 64),
                                         ("dense", 4097, 33, 65),
@@ -554,6 +558,8 @@ def test_rownorms_sq(api, kind, n, d, k):
         a = synth.csr_uniform(n, d, 1e-3, seed=2)
     elif kind == "csrzipf":
         a = synth.csr_zipf(n, d, 1e-2, seed=2, dtype=np.float64)
+    elif kind == "csrzipf32":
+        a = synth.csr_zipf(n, d, 1e-2, seed=2, dtype=np.float32)
     elif kind == "dense32":
         a = synth.dense_gaussian(n, d, seed=2, dtype=np.float32)
     else:
@@ -595,6 +601,18 @@ def test_rownorms_alpha_beta(api):
     a = synth.dense_gaussian(3000, 20, seed=4)
     b = synth.dense_gaussian(20, 20, seed=5)
     x0 = synth.dense_gaussian(3000, 1, seed=6)[:, 0]
+    xd = torch.from_numpy(x0.copy()).cuda()
+    api.rownorms_sq(to_device(a), torch.from_numpy(b).cuda(), alpha=0.5, beta=2.0, x=xd)
+    _rownorm_check(xd.cpu().numpy(), a, b, 0.5, 2.0, x0)
+
+
+def test_rownorms_alpha_beta_csr_long_rows(api):
+    """alpha/beta on CSR rows of every form: one lane, one wavefront
+    (quadratic form with B B^T) and the listed long rows (the product)."""
+    a = synth.csr_zipf(6000, 300, 2e-2, seed=4, dtype=np.float64)
+    assert a.getnnz(axis=1).max() > 300 // 8
+    b = synth.dense_gaussian(300, 300, seed=5)
+    x0 = synth.dense_gaussian(6000, 1, seed=6)[:, 0]
     xd = torch.from_numpy(x0.copy()).cuda()
     api.rownorms_sq(to_device(a), torch.from_numpy(b).cuda(), alpha=0.5, beta=2.0, x=xd)
     _rownorm_check(xd.cpu().numpy(), a, b, 0.5, 2.0, x0)
