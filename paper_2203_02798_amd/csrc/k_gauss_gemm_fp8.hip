@@ -16,7 +16,8 @@
 // group g is taken here to be bucket 32 g + j for both G and S*A, so each
 // product pairs a normal with the S*A entry of the same bucket.  Quantised
 // S*A is stored as [chunk][g][half][column][16 bytes] (written by
-// k_sa_fp8, or for CSR A by k_scatter_csr_fp8 from the binned rows), so the 16 lanes of a group read 256 contiguous bytes per load;
+// k_sa_fp8, or for CSR A by k_scatter_csr_fp8 from the binned rows), so
+// the 16 lanes of a group read 256 contiguous bytes per load;
 // its scale bytes as [chunk][512-column tile][column % 16][column / 16 % 32]
 // so that each lane reads the 32 scales of its 32 column blocks as 8 dwords
 // and selects the byte with the instruction's opsel.

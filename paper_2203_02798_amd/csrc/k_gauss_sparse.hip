@@ -444,8 +444,9 @@ static_assert(kStageMax / (kHeavy + 1) < kHeavyMax, "heavy list capacity");
 // Workgroup (row tile mt, K split ks), 1024 threads: rows a0 .. a0 + MT of
 // C (MT = 16 1024 / DP) and the G blocks ks bper .. ks bper + bper - 1, a
 // block being QB = BLK / 4 occupied quads of buckets (BLK = 512 with G in
-// FP32, 256 with G in FP64; bper from the number of blocks, read here).  Thread (h, j) = (tid / DP, tid % DP) holds C[a0 + 16 h + i, j],
-// i < 16, in FP64 registers.  Per block: every thread draws its share of
+// FP32, 256 with G in FP64; bper from the number of blocks, read here).
+// Thread (h, j) = (tid / DP, tid % DP) holds C[a0 + 16 h + i, j], i < 16, in
+// FP64 registers.  Per block: every thread draws its share of
 // the block of G into LDS (bucket-major, so one bucket's MT values are
 // contiguous); the block's entries, sorted by (column, bucket), are staged
 // in LDS with, per column, the range of its entries; thread (h, j) then

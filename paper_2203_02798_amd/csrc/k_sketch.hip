@@ -672,7 +672,8 @@ static int bin_pairs(const psk_mat &A, uint32_t s, uint32_t r, uint64_t seed, Ar
   }
   uint32_t *sk = nullptr;
   // for CSR A the pairs of the listed rows (cnt[1]) bound the sort
-  const int rc = sort_pairs(k0, v0, pairs, r, ws, st, &sk, perm, bp, compact ? cnt + 1 : nullptr);
+  const int rc =
+      sort_pairs(k0, v0, pairs, r, ws, st, &sk, perm, bp, compact ? cnt + 1 : nullptr);
   if (rc) return rc;
   *bptr = bp;
   return 0;
