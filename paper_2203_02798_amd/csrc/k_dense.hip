@@ -484,18 +484,25 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
                                                                  0, 0, 0);
       }
     };
-    // chunks c0 .. c1 - 1, the next chunk's A loaded while one is multiplied
+    // chunks c0 .. c1 - 1, the next chunk's A loaded while one is multiplied.
+    // The loads are unconditional (past the last chunk they reload it, and
+    // the copy goes unused): with the same loads in flight on every path,
+    // a step waits for its own chunk only, not for the one loading behind it.
     auto run = [&](auto hm, int64_t c0, int64_t c1) __attribute__((always_inline)) {
       if (c0 >= c1) return;
+      const int64_t cl = c1 - 1;
       RawChunk a0, a1;
       load(c0, a0);
-      for (int64_t c = c0; c < c1; c += 2) {
-        if (c + 1 < c1) load(c + 1, a1);
+      int64_t c = c0;
+      for (; c + 1 < c1; c += 2) {
+        load(c + 1, a1);
+        __builtin_amdgcn_sched_barrier(0);  // keep the next chunk's loads ahead of this step
         step(hm, c, a0);
-        if (c + 1 >= c1) break;
-        if (c + 2 < c1) load(c + 2, a0);
+        load(c + 2 < c1 ? c + 2 : cl, a0);
+        __builtin_amdgcn_sched_barrier(0);
         step(hm, c + 1, a1);
       }
+      if (c < c1) step(hm, c, a0);  // an odd count: the last chunk, already loaded
     };
     using HBoth = std::integral_constant<int, 3>;
     using HA = std::integral_constant<int, 1>;

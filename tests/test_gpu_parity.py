@@ -576,7 +576,12 @@ def test_rownorms_sq(api, kind, n, d, k):
     ("dense32", 3000, 128, 128, "lower"),   # full extent everywhere
     ("dense", 3000, 64, 64, "zerotile"),    # one 32-column tile of B all zero
     ("dense32", 3000, 400, 100, "upper"),   # single (unpaired) 32-column tiles
-    ("dense", 2000, 70, 20, "upper")])      # k <= 32: one tile
+    ("dense", 2000, 70, 20, "upper"),       # k <= 32: one tile
+    # zero lower-left quarters of the diagonal 32 x 32 blocks (16 x 16 block
+    # upper triangular): the diagonal chunks skip them; one quarter holding
+    # a nonzero (that tile takes its diagonal chunk whole)
+    ("dense32", 7000, 256, 256, "upper16"), ("dense", 3000, 128, 128, "upper16"),
+    ("dense", 5003, 200, 200, "quarterhit"), ("dense32", 3000, 400, 100, "upper16")])
 def test_rownorms_sq_structured_b(api, kind, n, d, k, shape):
     """B with trailing zero rows per column (triangular, banded, zero tiles):
     the kernel skips the K chunks past each tile's extent, which must give
@@ -591,6 +596,12 @@ def test_rownorms_sq_structured_b(api, kind, n, d, k, shape):
         b = np.tril(b)
     elif shape == "band":
         b[40:, :] = 0.0
+    elif shape == "upper16":
+        i, j = np.indices(b.shape)
+        b[i // 16 > j // 16] = 0.0
+    elif shape == "quarterhit":
+        b = np.triu(b)
+        b[32 * 2 + 20, 32 * 2 + 3] = 1.5
     else:
         b[:, 32:64] = 0.0
     x = api.rownorms_sq(to_device(a), torch.from_numpy(b).cuda()).cpu().numpy()
