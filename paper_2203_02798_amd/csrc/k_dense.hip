@@ -654,7 +654,13 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
 // slab read its rows through one L2.  Slab s of tile t writes its 64 x 64
 // partial (both triangles of a diagonal tile) to part at gram_part_off(t)
 // + s 4096; k_gram_reduce1 sums each tile's slabs in order (no atomics).
-constexpr int kGramPF = 4;  // row steps whose loads are in flight
+// Row steps whose loads are in flight: 8 for aligned FP32 rows (8 VGPRs a
+// step; FP32 4e6 x 256: 4.71 ms at 4, 4.60 at 6, 4.54 at 8, 4.85 at 10), 4
+// for the others, whose wider slots would leave one wavefront per SIMD.
+template <typename TA, bool VEC>
+constexpr int gram_pf() {
+  return sizeof(TA) == 4 && VEC ? 8 : 4;
+}
 
 // (I, J), I < J, of off-diagonal tile o in row-major order
 __device__ __forceinline__ void gram_offdiag_tile(int o, int T, int &I, int &J) {
@@ -713,6 +719,7 @@ __global__ __launch_bounds__(256) void k_gram_syrk(const TA *__restrict__ A, int
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+  constexpr int kGramPF = gram_pf<TA, VEC>();
   auto run = [&](auto dg) __attribute__((always_inline)) {
     constexpr bool DG = decltype(dg)::value;
     Raw4<TA> xa[kGramPF], xb[kGramPF];
@@ -809,9 +816,12 @@ int gram_syrk_launch(double alpha, const psk_mat &Am, double beta, void *C, bool
   const int64_t n = Am.n, d = Am.d;
   const int T = (int)ceil_div(d, (int64_t)64);
   const int Uo = T * (T - 1) / 2;
+  const uintptr_t addr = (uintptr_t)Am.values;
+  const bool vec = (Am.ld % 4 == 0) && (d % 4 == 0) && (addr % 16 == 0);
   // about two wavefronts per SIMD in one round: 2048 work items of equal
-  // cost, a diagonal item 10/16 of an off-diagonal one per row
-  constexpr int64_t kStep = 4 * kGramPF;
+  // cost, a diagonal item 10/16 of an off-diagonal one per row; slabs of
+  // whole loop iterations
+  const int64_t kStep = 4 * (vec ? gram_pf<TA, true>() : gram_pf<TA, false>());
   int64_t so = (int64_t)(2048.0 / (Uo + 0.625 * T));
   if (so < 8) so = 8;
   const int64_t rows_o = ceil_div(ceil_div(n, so), kStep) * kStep;
@@ -825,8 +835,6 @@ int gram_syrk_launch(double alpha, const psk_mat &Am, double beta, void *C, bool
   const int64_t items = so * Uo + sd * T;
   int64_t nblk = ceil_div(items, (int64_t)4);
   nblk = ceil_div(nblk, (int64_t)8) * 8;  // whole XCD rounds for the remap
-  const uintptr_t addr = (uintptr_t)Am.values;
-  const bool vec = (Am.ld % 4 == 0) && (d % 4 == 0) && (addr % 16 == 0);
   {
     KTimer timer("gram", st);
     if (vec)
