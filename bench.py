@@ -178,11 +178,13 @@ def headline(api, torch, A, steps, warmup, seed):
     # length n (2 n d (d+1) / 2), the row norms' product with the triangular
     # R^{-1} (sum_j 2 (j+1) per row) and the squares: n d (d+2); executed
     # flops: the 16 x 16 blocks of the upper block triangle (Gram), the K
-    # chunks of the paired 32-column tiles up to each tile's extent (row norms)
+    # chunks of the paired 32-column tiles up to each tile's extent, less the
+    # zero quarter of each diagonal chunk inside d (row norms)
     flops = {"gram": n * d * (d + 1), "rownorm": n * d * (d + 2)}
     tiles = (d + 31) // 32
     exe = {"gram": n * ((d + 15) // 16) * ((d + 15) // 16 + 1) // 2 * 512,
-           "rownorm": n * 2 * 32 * 32 * sum(t + 1 for t in range(tiles))}
+           "rownorm": int(n * 2 * 32 * 32 * sum(t + 1 - (0.25 if 32 * t + 32 <= d else 0.0)
+                                                 for t in range(tiles)))}
     kern = {}
     for name, kname in (("gram", "k_gram_syrk"), ("rownorm", "k_rownorm_bres")):
         ms, cnt = kst.get(name, (0.0, 0))

@@ -369,6 +369,15 @@ __device__ __forceinline__ double raw4_get(const Raw4<TA> &v, int q) {
 // k0 + kBresKW kq + s of A at step s, and B row k0 + kBresKW kq + s: the same
 // permutation of the chunk on both operands, so one lane reads kBresKW
 // consecutive elements of its row.
+// The diagonal 32 x 32 block of a triangular B is half zeros.  When the
+// staging finds the lower-left 16 x 16 quarter of a tile's diagonal block
+// zero (its rows 16 .. 31 in the tile's first 16 columns) and that block is
+// the tile's last chunk (and inside the d columns), the chunk is taken in
+// another order: one swap of lane halves per pair of elements (lanes
+// kq = 0, 1 exchange element s + 4 for element s of kq = 2, 3) gives steps
+// 0 .. 3 the chunk's first 16 rows and steps 4 .. 7 its last 16, row
+// 16 h + 8 (kq & 1) + 4 (kq >> 1) + s at step 4 h + s, so the products of
+// the tile's first column block skip steps 4 .. 7 there.
 // part[slot * n + row] = the row's squared norm over the slot's columns.
 // Workgroups form row groups of tn (one per slot) that sit on one XCD
 // (linear ids equal mod 8) and walk the same rows, so A is fetched into that
@@ -387,6 +396,7 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
   static_assert(!VEC || sizeof(TA) == 4, "vector loads are for FP32 A");
   extern __shared__ double Bs[];
   __shared__ int ext[2];
+  __shared__ int nzq[2];  // a nonzero in the lower-left quarter of the tile's diagonal block
   constexpr int BNC = PAIR ? 2 * kBresTile : kBresTile;
   constexpr int LDB = BNC + 4;
   constexpr int NB = BNC / 16;
@@ -408,28 +418,49 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
   const int64_t c0b = (PAIR && tb != nt) ? tb * kBresTile : -1;
   const int64_t kch = (d + CK - 1) / CK;
   const int64_t drows = kch * CK;
-  if (tid < 2) ext[tid] = 0;
+  if (tid < 2) {
+    ext[tid] = 0;
+    nzq[tid] = 0;
+  }
   __syncthreads();
   int exa = 0, exb = 0;
+  bool qa = false, qb = false;
   for (int64_t e = tid; e < drows * BNC; e += kBresThreads) {
     const int64_t kk = e / BNC;
     const int jj = (int)(e - kk * BNC);
     const bool hb = jj >= kBresTile;
     const int64_t cb = hb ? c0b : c0a;
-    const int64_t col = cb + (hb ? jj - kBresTile : jj);
+    const int jt = hb ? jj - kBresTile : jj;
+    const int64_t col = cb + jt;
     const double v = (cb >= 0 && kk < d && col < k) ? B[kk * k + col] : 0.0;
     Bs[kk * LDB + jj] = v;
     if (v != 0.0) {  // NaN counts as nonzero
-      if (hb) exb = (int)kk + 1;
-      else exa = (int)kk + 1;
+      const bool quarter = jt < 16 && kk >= cb + 16 && kk < cb + kBresTile;
+      if (hb) {
+        exb = (int)kk + 1;
+        qb = qb || quarter;
+      } else {
+        exa = (int)kk + 1;
+        qa = qa || quarter;
+      }
     }
   }
   if (exa) atomicMax(&ext[0], exa);
   if (exb) atomicMax(&ext[1], exb);
+  if (qa) atomicOr(&nzq[0], 1);
+  if (qb) atomicOr(&nzq[1], 1);
   __syncthreads();
   // K chunks each tile needs (uniform over the workgroup)
   const int64_t kca = __builtin_amdgcn_readfirstlane((ext[0] + CK - 1) / CK);
   const int64_t kcb = __builtin_amdgcn_readfirstlane((ext[1] + CK - 1) / CK);
+  // the diagonal chunk of each tile (chunk index = tile index, a chunk
+  // spanning one tile's rows) when its quarter is zero and its columns of A
+  // are inside d; -1: none
+  static_assert(CK == kBresTile, "a K chunk spans one tile's rows");
+  const int64_t dga =
+      (__builtin_amdgcn_readfirstlane(nzq[0]) || c0a + kBresTile > d) ? -1 : (int64_t)nt;
+  const int64_t dgb =
+      (c0b < 0 || __builtin_amdgcn_readfirstlane(nzq[1]) || c0b + kBresTile > d) ? -1 : tb;
   const int64_t ntiles = (n + kBresRows - 1) / kBresRows;
   for (int64_t t = group * kBresWaves + wave; t < ntiles; t += ngroups * kBresWaves) {
     const int64_t r0 = t * kBresRows;
@@ -460,49 +491,110 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
           raw4_load<TA, VEC>(arow[mb], 0, d, 0, rin[mb], kb + 4 * q, a[mb][q]);
     };
     // one K chunk for the blocks of the tiles in HM (bit 0: first tile,
-    // bit 1: second tile)
-    auto step = [&](auto hm, int64_t c, const RawChunk &raw) __attribute__((always_inline)) {
+    // bit 1: second tile); DG 1 / 2: a diagonal chunk in the swapped order,
+    // the first column block of the first / second tile skipping steps 4 .. 7
+    // (every element inside A: no masks; a row past n read row 0 and feeds
+    // only its own outputs, which are not stored)
+    auto step = [&](auto hm, auto dg, int64_t c, const RawChunk &raw)
+                    __attribute__((always_inline)) {
       constexpr int HM = decltype(hm)::value;
+      constexpr int DG = decltype(dg)::value;
       double a[MB][KW];
+      if constexpr (DG == 0) {
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb)
+        for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-        for (int s = 0; s < KW; ++s) a[mb][s] = raw4_get(raw[mb][s / 4], s % 4);
+          for (int s = 0; s < KW; ++s) a[mb][s] = raw4_get(raw[mb][s / 4], s % 4);
+      } else {
+        static_assert(KW == 8, "the swap pairs elements s and s + 4");
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const TA x = raw[mb][0].x[s], y = raw[mb][1].x[s];
+            if constexpr (sizeof(TA) == 4) {
+              const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x),
+                                                              __float_as_uint(y), false, false);
+              a[mb][s] = (double)__uint_as_float(r[0]);
+              a[mb][4 + s] = (double)__uint_as_float(r[1]);
+            } else {
+              const uint64_t xb = (uint64_t)__double_as_longlong(x);
+              const uint64_t yb = (uint64_t)__double_as_longlong(y);
+              const auto rl = __builtin_amdgcn_permlane32_swap((uint32_t)xb, (uint32_t)yb, false,
+                                                               false);
+              const auto rh = __builtin_amdgcn_permlane32_swap((uint32_t)(xb >> 32),
+                                                               (uint32_t)(yb >> 32), false, false);
+              a[mb][s] = __longlong_as_double((long long)(((uint64_t)rh[0] << 32) | rl[0]));
+              a[mb][4 + s] = __longlong_as_double((long long)(((uint64_t)rh[1] << 32) | rl[1]));
+            }
+          }
+      }
 #pragma unroll
       for (int s = 0; s < KW; ++s) {
-        const double *brow = Bs + (c * CK + KW * kq + s) * LDB + li;
+        const int64_t kr = DG == 0 ? c * CK + KW * kq + s
+                                   : c * CK + 16 * (s / 4) + 8 * (kq & 1) + 4 * (kq >> 1) + s % 4;
+        const double *brow = Bs + kr * LDB + li;
+        auto on = [&](int nb) {
+          return ((HM >> (nb / NBH)) & 1) && !(DG && s >= 4 && nb == (DG - 1) * NBH);
+        };
         double bv[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
-          if ((HM >> (nb / NBH)) & 1) bv[nb] = brow[nb * 16];
+          if (on(nb)) bv[nb] = brow[nb * 16];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
-            if ((HM >> (nb / NBH)) & 1)
+            if (on(nb))
               acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[mb][s], bv[nb], acc[mb][nb],
                                                                  0, 0, 0);
       }
     };
+    using D0 = std::integral_constant<int, 0>;
     // chunks c0 .. c1 - 1, the next chunk's A loaded while one is multiplied.
     // The loads are unconditional (past the last chunk they reload it, and
     // the copy goes unused): with the same loads in flight on every path,
     // a step waits for its own chunk only, not for the one loading behind it.
+    // A phase whose last chunk is the diagonal chunk of its first tile
+    // (HM 3, 1) or of its second (HM 2) takes that chunk last, loaded in the
+    // same pipeline (its loads are those of any chunk).
     auto run = [&](auto hm, int64_t c0, int64_t c1) __attribute__((always_inline)) {
+      constexpr int HM = decltype(hm)::value;
+      using DGT = std::integral_constant<int, HM == 2 ? 2 : 1>;
       if (c0 >= c1) return;
+      const bool dg = c1 - 1 == (HM == 2 ? dgb : dga);
+      const int64_t ce = dg ? c1 - 1 : c1;  // chunks before ce: all products
       const int64_t cl = c1 - 1;
       RawChunk a0, a1;
       load(c0, a0);
       int64_t c = c0;
-      for (; c + 1 < c1; c += 2) {
+      for (; c + 1 < ce; c += 2) {
         load(c + 1, a1);
         __builtin_amdgcn_sched_barrier(0);  // keep the next chunk's loads ahead of this step
-        step(hm, c, a0);
+        step(hm, D0{}, c, a0);
         load(c + 2 < c1 ? c + 2 : cl, a0);
         __builtin_amdgcn_sched_barrier(0);
-        step(hm, c + 1, a1);
+        step(hm, D0{}, c + 1, a1);
       }
-      if (c < c1) step(hm, c, a0);  // an odd count: the last chunk, already loaded
+      // c = ce - 1: one more chunk (a0), the next one (the diagonal chunk,
+      // or a reload) loading into a1 meanwhile; c = ce: a0 holds the
+      // diagonal chunk when there is one
+      const bool in1 = c < ce;
+      if (in1) {
+        load(c + 1 < c1 ? c + 1 : cl, a1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(hm, D0{}, c, a0);
+      }
+      if (dg) {
+        RawChunk ad;
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+          for (int q = 0; q < KW / 4; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ad[mb][q].x[e] = in1 ? a1[mb][q].x[e] : a0[mb][q].x[e];
+        step(hm, DGT{}, ce, ad);
+      }
     };
     using HBoth = std::integral_constant<int, 3>;
     using HA = std::integral_constant<int, 1>;
