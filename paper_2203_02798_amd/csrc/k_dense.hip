@@ -746,12 +746,15 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
 // slab read its rows through one L2.  Slab s of tile t writes its 64 x 64
 // partial (both triangles of a diagonal tile) to part at gram_part_off(t)
 // + s 4096; k_gram_reduce1 sums each tile's slabs in order (no atomics).
-// Row steps whose loads are in flight: 8 for aligned FP32 rows (8 VGPRs a
-// step; FP32 4e6 x 256: 4.71 ms at 4, 4.60 at 6, 4.54 at 8, 4.85 at 10), 4
-// for the others, whose wider slots would leave one wavefront per SIMD.
+// Row steps whose loads are in flight.  Four keep a wavefront at 206
+// registers (its 128 accumulators and 78 VGPRs), so beside the kernel's two
+// wavefronts per SIMD one wavefront of a memory-bound kernel on another
+// stream (the sketch's scatter, 92) still fits.  Eight run the Gram alone 4%
+// faster (FP32 4e6 x 256: 4.71 ms at 4, 4.54 at 8) but take 240 and shut
+// those out: the sketch-beside-Gram step then takes 11.33 ms against 11.17.
 template <typename TA, bool VEC>
 constexpr int gram_pf() {
-  return sizeof(TA) == 4 && VEC ? 8 : 4;
+  return 4;
 }
 
 // (I, J), I < J, of off-diagonal tile o in row-major order
