@@ -493,8 +493,8 @@ __global__ __launch_bounds__(kBresThreads) void k_rownorm_bres(
     // one K chunk for the blocks of the tiles in HM (bit 0: first tile,
     // bit 1: second tile); DG 1 / 2: a diagonal chunk in the swapped order,
     // the first column block of the first / second tile skipping steps 4 .. 7
-    // (every element inside A: no masks; a row past n read row 0 and feeds
-    // only its own outputs, which are not stored)
+    // (every element inside A: no masks; a row past n reads row 0 and
+    // feeds only its own outputs, which are not stored)
     auto step = [&](auto hm, auto dg, int64_t c, const RawChunk &raw)
                     __attribute__((always_inline)) {
       constexpr int HM = decltype(hm)::value;
@@ -752,10 +752,7 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
 // stream (the sketch's scatter, 92) still fits.  Eight run the Gram alone 4%
 // faster (FP32 4e6 x 256: 4.71 ms at 4, 4.54 at 8) but take 240 and shut
 // those out: the sketch-beside-Gram step then takes 11.33 ms against 11.17.
-template <typename TA, bool VEC>
-constexpr int gram_pf() {
-  return 4;
-}
+constexpr int kGramPF = 4;
 
 // (I, J), I < J, of off-diagonal tile o in row-major order
 __device__ __forceinline__ void gram_offdiag_tile(int o, int T, int &I, int &J) {
@@ -814,7 +811,6 @@ __global__ __launch_bounds__(256) void k_gram_syrk(const TA *__restrict__ A, int
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-  constexpr int kGramPF = gram_pf<TA, VEC>();
   auto run = [&](auto dg) __attribute__((always_inline)) {
     constexpr bool DG = decltype(dg)::value;
     Raw4<TA> xa[kGramPF], xb[kGramPF];
@@ -916,7 +912,7 @@ int gram_syrk_launch(double alpha, const psk_mat &Am, double beta, void *C, bool
   // about two wavefronts per SIMD in one round: 2048 work items of equal
   // cost, a diagonal item 10/16 of an off-diagonal one per row; slabs of
   // whole loop iterations
-  const int64_t kStep = 4 * (vec ? gram_pf<TA, true>() : gram_pf<TA, false>());
+  constexpr int64_t kStep = 4 * kGramPF;
   int64_t so = (int64_t)(2048.0 / (Uo + 0.625 * T));
   if (so < 8) so = 8;
   const int64_t rows_o = ceil_div(ceil_div(n, so), kStep) * kStep;
