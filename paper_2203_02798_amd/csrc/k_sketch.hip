@@ -158,55 +158,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// stable scatter of one tile, ranks from ballots
-__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
-    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-    int64_t n, const uint32_t *__restrict__ dn, int shift, int nbits,
-    const uint32_t *__restrict__ offs, int64_t ntiles, uint32_t *__restrict__ kout,
-    uint32_t *__restrict__ vout) {
-  __shared__ uint32_t run[kRadix];
-  __shared__ uint32_t wc[4][kRadix];
-  n = keys_in_use(n, dn);
-  if ((int64_t)blockIdx.x * kSortTile >= n) return;  // nothing of this tile in use
-  const int tid = threadIdx.x;
-  const int w = tid >> 6;
-  const int lane = tid & 63;
-  run[tid] = offs[(int64_t)tid * ntiles + blockIdx.x];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) wc[q][tid] = 0;
-  __syncthreads();
-  const uint32_t mask = (1u << nbits) - 1u;
-  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  for (int it = 0; it < kSortItems; ++it) {
-    const int64_t idx = base + it * kSortThreads + tid;
-    const bool valid = idx < n;
-    const uint32_t k = valid ? kin[idx] : 0u;
-    const uint32_t v = valid ? vin[idx] : 0u;
-    const uint32_t dg = (k >> shift) & mask;
-    uint64_t peers = __ballot(valid);
-    for (int b = 0; b < nbits; ++b) {
-      const bool bit = (dg >> b) & 1u;
-      const uint64_t bb = __ballot(bit);
-      peers &= bit ? bb : ~bb;
-    }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wc[w][dg] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = run[dg] + rank;
-      for (int q = 0; q < w; ++q) pos += wc[q][dg];
-      kout[pos] = k;
-      vout[pos] = v;
-    }
-    __syncthreads();
-    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) wc[q][tid] = 0;
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------------------
 // exclusive scan of uint32 (three kernels: tile scan, scan of tile sums, add)
 // ---------------------------------------------------------------------------
@@ -231,6 +182,79 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t t, uint32_t &total)
   }
   __syncthreads();
   return pre + inc - t;
+}
+
+// Stable scatter of one tile.  Ranks come from wavefront ballots as the
+// keys are read (tile order within each digit); each key is first placed in
+// LDS at its digit's tile-local run, then the tile is written out run by
+// run, consecutive threads to consecutive addresses of a digit's run in
+// kout / vout (instead of every key straight to its own run).  The tile's
+// count of a digit is the difference of two neighbouring scanned offsets.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    int64_t n, const uint32_t *__restrict__ dn, int shift, int nbits,
+    const uint32_t *__restrict__ offs, int64_t ntiles, uint32_t *__restrict__ kout,
+    uint32_t *__restrict__ vout) {
+  __shared__ uint32_t lrun[kRadix];    // next tile-local position of each digit
+  __shared__ uint32_t lstart[kRadix];  // tile-local start of each digit's run
+  __shared__ uint32_t goff[kRadix];    // where this tile's run of each digit goes
+  __shared__ uint32_t wc[4][kRadix];
+  __shared__ uint32_t sk[kSortTile], sv[kSortTile];
+  n = keys_in_use(n, dn);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) return;  // nothing of this tile in use
+  const int tid = threadIdx.x;
+  const int w = tid >> 6;
+  const int lane = tid & 63;
+  const int64_t L = (int64_t)kRadix * ntiles;
+  const int64_t o = (int64_t)tid * ntiles + blockIdx.x;
+  const uint32_t g0 = offs[o];
+  const uint32_t g1 = o + 1 < L ? offs[o + 1] : (uint32_t)n;
+  uint32_t total;
+  const uint32_t ls = block_excl_scan(g1 - g0, total);
+  goff[tid] = g0;
+  lstart[tid] = ls;
+  lrun[tid] = ls;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) wc[q][tid] = 0;
+  __syncthreads();
+  const uint32_t mask = (1u << nbits) - 1u;
+  const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t idx = base + it * kSortThreads + tid;
+    const bool valid = idx < n;
+    const uint32_t k = valid ? kin[idx] : 0u;
+    const uint32_t v = valid ? vin[idx] : 0u;
+    const uint32_t dg = (k >> shift) & mask;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < nbits; ++b) {
+      const bool bit = (dg >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wc[w][dg] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = lrun[dg] + rank;
+      for (int q = 0; q < w; ++q) pos += wc[q][dg];
+      sk[pos] = k;
+      sv[pos] = v;
+    }
+    __syncthreads();
+    lrun[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wc[q][tid] = 0;
+    __syncthreads();
+  }
+  const int cnt = (int)(n - base < kSortTile ? n - base : kSortTile);
+  for (int e = tid; e < cnt; e += kSortThreads) {
+    const uint32_t k = sk[e];
+    const uint32_t dg = (k >> shift) & mask;
+    const uint32_t pos = goff[dg] + ((uint32_t)e - lstart[dg]);
+    kout[pos] = k;
+    vout[pos] = sv[e];
+  }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(uint32_t *__restrict__ data,
