@@ -273,8 +273,12 @@ __global__ __launch_bounds__(64 * kCsrWaves, 4) void k_pass_csr(
   }
 }
 
-// dense rows: wavefront per row, lane owns columns lane + 64k (k < KC)
-template <typename T, bool INIT, int KC>
+// dense rows: wavefront per row, lane owns columns lane + 64k (k < KC);
+// a wavefront takes RB of its rows (every fourth of the workgroup's) at a
+// time, with their entries of u, so that short rows still keep a few KiB
+// per wavefront in flight (launch_dense_pass picks RB).  A row past the
+// workgroup's reads the batch's first row and counts as zero.
+template <typename T, bool INIT, int KC, int RB>
 __global__ __launch_bounds__(256) void k_pass_dense(
     const T *__restrict__ A, int64_t ld, int64_t n, int64_t d,
     const double *__restrict__ vhat, const double *__restrict__ rhs,
@@ -296,65 +300,54 @@ __global__ __launch_bounds__(256) void k_pass_dense(
     tacc[k] = 0.0;
   }
   double b2 = 0.0;
-  int64_t i = rb0 + wave;
-  for (; i + 4 < rb1; i += 8) {
-    double x0[KC], x1[KC];
-    const T *ra = A + i * ld;
-    const T *rb = A + (i + 4) * ld;
+  for (int64_t i = rb0 + wave; i < rb1; i += 4 * RB) {
+    double x[RB][KC], uo[RB];
+    bool ok[RB];
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-      const int64_t c = lane + 64 * k;
-      x0[k] = c < d ? (double)ra[c] : 0.0;
-      x1[k] = c < d ? (double)rb[c] : 0.0;
-    }
-    double u0, u1;
-    if (INIT) {
-      u0 = rhs[i];
-      u1 = rhs[i + 4];
-    } else {
-      double d0 = 0.0, d1 = 0.0;
+    for (int r = 0; r < RB; ++r) {
+      ok[r] = i + 4 * r < rb1;
+      const int64_t row = ok[r] ? i + 4 * r : i;
+      const T *ra = A + row * ld;
 #pragma unroll
       for (int k = 0; k < KC; ++k) {
-        d0 += x0[k] * vh[k];
-        d1 += x1[k] * vh[k];
+        const int64_t c = lane + 64 * k;
+        x[r][k] = (ok[r] && c < d) ? (double)ra[c] : 0.0;
+      }
+      uo[r] = INIT ? rhs[row] : u[row];
+    }
+    double uu[RB];
+    if (INIT) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) uu[r] = ok[r] ? uo[r] : 0.0;
+    } else {
+      double dt[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        dt[r] = 0.0;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) dt[r] += x[r][k] * vh[k];
       }
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        d0 += __shfl_xor(d0, off, 64);
-        d1 += __shfl_xor(d1, off, 64);
-      }
-      u0 = d0 - au * u[i];
-      u1 = d1 - au * u[i + 4];
+      for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) dt[r] += __shfl_xor(dt[r], off, 64);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) uu[r] = ok[r] ? dt[r] - au * uo[r] : 0.0;
     }
     if (lane == 0) {
-      u[i] = u0;
-      u[i + 4] = u1;
-    }
-    b2 += u0 * u0 + u1 * u1;
 #pragma unroll
-    for (int k = 0; k < KC; ++k) tacc[k] += x0[k] * u0 + x1[k] * u1;
-  }
-  for (; i < rb1; i += 4) {
-    double x0[KC];
-    const T *ra = A + i * ld;
+      for (int r = 0; r < RB; ++r)
+        if (ok[r]) u[i + 4 * r] = uu[r];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) b2 += uu[r] * uu[r];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-      const int64_t c = lane + 64 * k;
-      x0[k] = c < d ? (double)ra[c] : 0.0;
-    }
-    double u0;
-    if (INIT) {
-      u0 = rhs[i];
-    } else {
-      double d0 = 0.0;
+      double t = 0.0;
 #pragma unroll
-      for (int k = 0; k < KC; ++k) d0 += x0[k] * vh[k];
-      u0 = wave_sum(d0) - au * u[i];
+      for (int r = 0; r < RB; ++r) t += x[r][k] * uu[r];
+      tacc[k] += t;
     }
-    if (lane == 0) u[i] = u0;
-    b2 += u0 * u0;
-#pragma unroll
-    for (int k = 0; k < KC; ++k) tacc[k] += x0[k] * u0;
   }
 #pragma unroll
   for (int k = 0; k < KC; ++k) tl[wave][lane + 64 * k] = tacc[k];
@@ -795,14 +788,24 @@ void launch_dense_pass(const psk_mat &A, const LsqBufs &B, const double *rhs,
                        hipStream_t s) {
   const T *a = (const T *)A.values;
   const int64_t d = A.d;
-#define PSK_DP(KC)                                                                      \
-  k_pass_dense<T, INIT, KC><<<kPassBlocks, 256, 0, s>>>(a, A.ld, A.n, d, B.vhat, rhs, B.u, \
-                                                        B.st, B.part_t, B.part_b2)
-  if (d <= 64) PSK_DP(1);
-  else if (d <= 128) PSK_DP(2);
-  else if (d <= 256) PSK_DP(4);
-  else if (d <= 512) PSK_DP(8);
-  else PSK_DP(16);
+  // rows per wavefront batch (FP64, n = 1e6: d = 32 135 us a pass with 8
+  // against 166 with 2; n = 2e4, d = 50: 10.1 us with 2 against 11.4 with
+  // 8, a wavefront then holding about ten rows; d = 128: 4 better than 2)
+#define PSK_DP(KC, RB)                                                                  \
+  k_pass_dense<T, INIT, KC, RB><<<kPassBlocks, 256, 0, s>>>(a, A.ld, A.n, d, B.vhat, rhs, \
+                                                            B.u, B.st, B.part_t, B.part_b2)
+  if (d <= 64) {
+    if (A.n >= 65536) PSK_DP(1, 8);
+    else PSK_DP(1, 2);
+  } else if (d <= 128) {
+    PSK_DP(2, 4);
+  } else if (d <= 256) {
+    PSK_DP(4, 2);
+  } else if (d <= 512) {
+    PSK_DP(8, 2);
+  } else {
+    PSK_DP(16, 2);
+  }
 #undef PSK_DP
 }
 
