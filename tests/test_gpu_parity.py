@@ -959,17 +959,23 @@ def test_kernel_timing_records_launches(api):
     assert st["cs_scatter"][1] == 1 and st["cs_bin"][1] == 1
 
 
-@pytest.mark.parametrize("kind,cond", [("dense", 1e3), ("dense", 1e8), ("csr", 1e2)])
-def test_lsq_solve_matches_lapack(api, kind, cond):
-    n, d = 20000, 32
+@pytest.mark.parametrize("kind,n,d,cond,r", [
+    ("dense", 20000, 32, 1e3, None), ("dense", 20000, 32, 1e8, None),
+    ("csr", 20000, 32, 1e2, None),
+    # the dense pass's row batches: eight rows a wavefront (d <= 64, n >=
+    # 65,536; ragged n), and the widths past 256 columns (two rows)
+    ("dense", 100003, 48, 1e6, None), ("dense", 30001, 300, 1e3, 2400),
+    ("dense", 20000, 600, 1e2, 4800)])
+def test_lsq_solve_matches_lapack(api, kind, n, d, cond, r):
+    _say(f"lsq {kind} n={n} d={d} cond={cond:g}")
     if kind == "csr":
         a = synth.csr_uniform(n, d, 0.2, seed=2)
         xt = np.random.default_rng(0).standard_normal(d)
         b = a @ xt + 1e-3 * np.random.default_rng(1).standard_normal(n)
     else:
         a, b, _ = synth.lsq_problem(n, d, cond, seed=2)
-    x, info = api.lsq_solve(to_device(a), torch.from_numpy(b).cuda(), m=4 * d, r=d * d,
-                            seed=3)
+    x, info = api.lsq_solve(to_device(a), torch.from_numpy(b).cuda(), m=4 * d,
+                            r=d * d if r is None else r, seed=3)
     _say(f"lsq {kind} cond={cond}: {info}")
     x = x.cpu().numpy()
     xs = olsq.lstsq(a, b)
