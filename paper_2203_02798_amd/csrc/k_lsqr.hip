@@ -284,7 +284,9 @@ __global__ __launch_bounds__(256) void k_pass_dense(
     const double *__restrict__ vhat, const double *__restrict__ rhs,
     double *__restrict__ u, const LsqrState *__restrict__ st,
     double *__restrict__ part_t, double *__restrict__ part_b2) {
-  if (!INIT && st->done) return;
+  // the stop flag is read now and tested once vhat and the first batch of
+  // rows are in flight (nothing is written before the test)
+  const int stop = INIT ? 0 : st->done;
   __shared__ double tl[4][64 * KC];
   __shared__ double b2s[4];
   const int wave = threadIdx.x >> 6;
@@ -299,10 +301,9 @@ __global__ __launch_bounds__(256) void k_pass_dense(
     vh[k] = (!INIT && c < d) ? vhat[c] : 0.0;
     tacc[k] = 0.0;
   }
-  double b2 = 0.0;
-  for (int64_t i = rb0 + wave; i < rb1; i += 4 * RB) {
-    double x[RB][KC], uo[RB];
-    bool ok[RB];
+  double x[RB][KC], uo[RB];
+  bool ok[RB];
+  auto fetch = [&](int64_t i) __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       ok[r] = i + 4 * r < rb1;
@@ -315,6 +316,12 @@ __global__ __launch_bounds__(256) void k_pass_dense(
       }
       uo[r] = INIT ? rhs[row] : u[row];
     }
+  };
+  int64_t i = rb0 + wave;
+  if (i < rb1) fetch(i);
+  if (stop) return;
+  double b2 = 0.0;
+  for (; i < rb1; i += 4 * RB) {
     double uu[RB];
     if (INIT) {
 #pragma unroll
@@ -348,6 +355,7 @@ __global__ __launch_bounds__(256) void k_pass_dense(
       for (int r = 0; r < RB; ++r) t += x[r][k] * uu[r];
       tacc[k] += t;
     }
+    if (i + 4 * RB < rb1) fetch(i + 4 * RB);
   }
 #pragma unroll
   for (int k = 0; k < KC; ++k) tl[wave][lane + 64 * k] = tacc[k];
