@@ -63,14 +63,14 @@ HEAD = dict(n=4_000_000, d=256, r=65536, m=1024, smin=1e-6)
 PMC_TRAFFIC = {
     "k_gram_syrk": {
         "source": "paper_2203_02798_amd/csrc/k_dense.hip",
-        "sha256_prefix": "75d0456a03769e92",
+        "sha256_prefix": "be36c3e0e668d061",
         "fetch_kib": 4068896.1, "write_kib": 69821.0,
         "fetch_scale": 2.000, "write_scale": 1.000,
         "profile": "profiles/step_dense-4e6x256_pmc.md",
     },
     "k_rownorm_bres": {
         "source": "paper_2203_02798_amd/csrc/k_dense.hip",
-        "sha256_prefix": "75d0456a03769e92",
+        "sha256_prefix": "be36c3e0e668d061",
         "fetch_kib": 6241491.0, "write_kib": 329335.0,
         "fetch_scale": 2.000, "write_scale": 1.000,
         "profile": "profiles/step_dense-4e6x256_pmc.md",

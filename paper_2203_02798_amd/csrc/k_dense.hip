@@ -746,12 +746,13 @@ int rownorm_launch(const psk_mat &Am, const double *B, int64_t k, double alpha,
 // slab read its rows through one L2.  Slab s of tile t writes its 64 x 64
 // partial (both triangles of a diagonal tile) to part at gram_part_off(t)
 // + s 4096; k_gram_reduce1 sums each tile's slabs in order (no atomics).
-// Row steps whose loads are in flight.  Four keep a wavefront at 206
-// registers (its 128 accumulators and 78 VGPRs), so beside the kernel's two
-// wavefronts per SIMD one wavefront of a memory-bound kernel on another
-// stream (the sketch's scatter, 92) still fits.  Eight run the Gram alone 4%
-// faster (FP32 4e6 x 256: 4.71 ms at 4, 4.54 at 8) but take 240 and shut
-// those out: the sketch-beside-Gram step then takes 11.33 ms against 11.17.
+// Row steps whose loads are in flight.  Four keep a wavefront at 208
+// registers (its 128 accumulators and 80 VGPRs), so beside the kernel's two
+// wavefronts per SIMD 96 registers stay free for the smaller kernels of a
+// stream beside it (the sketch's binning, the QR's GEMMs at 54).  Eight run
+// the Gram alone 4% faster (FP32 4e6 x 256: 4.71 ms at 4, 4.54 at 8) but
+// take 240 and leave 32: the sketch-beside-Gram step then takes 11.33 ms
+// against 11.17.
 constexpr int kGramPF = 4;
 
 // (I, J), I < J, of off-diagonal tile o in row-major order
