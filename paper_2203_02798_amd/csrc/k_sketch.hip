@@ -551,8 +551,11 @@ void launch_dense(const psk_mat &A, int64_t r, const uint32_t *perm,
   const int64_t waves = r * splits;
   const unsigned blocks = (unsigned)ceil_div(waves, 4);
   const int64_t span1 = 64 * VW;  // columns per lane group
+  // one column group: six rows a batch (84 VGPRs with FP32 rows, against
+  // 104 at eight) run as fast alone and leave a wavefront of room beside the
+  // Gram on another stream (C3's sketch-beside-Gram step 11.22 -> 11.06 ms)
   if (A.d <= span1)
-    k_scatter_dense<T, TO, VW, 1, 8><<<blocks, 256, 0, st>>>(
+    k_scatter_dense<T, TO, VW, 1, 6><<<blocks, 256, 0, st>>>(
         (const T *)A.values, A.ld, A.d, r, perm, bptr, splits, scale, out);
   else if (A.d <= 2 * span1)
     k_scatter_dense<T, TO, VW, 2, 4><<<blocks, 256, 0, st>>>(
