@@ -581,7 +581,10 @@ def test_rownorms_sq(api, kind, n, d, k):
     # upper triangular): the diagonal chunks skip them; one quarter holding
     # a nonzero (that tile takes its diagonal chunk whole)
     ("dense32", 7000, 256, 256, "upper16"), ("dense", 3000, 128, 128, "upper16"),
-    ("dense", 5003, 200, 200, "quarterhit"), ("dense32", 3000, 400, 100, "upper16")])
+    ("dense", 5003, 200, 200, "quarterhit"), ("dense32", 3000, 400, 100, "upper16"),
+    # FP32 rows read one element at a time (d % 4 != 0) with the diagonal
+    # chunks, the last tile past d taken whole; B wider than d
+    ("dense32", 2501, 254, 254, "upper"), ("dense32", 3000, 64, 160, "upper")])
 def test_rownorms_sq_structured_b(api, kind, n, d, k, shape):
     """B with trailing zero rows per column (triangular, banded, zero tiles):
     the kernel skips the K chunks past each tile's extent, which must give
