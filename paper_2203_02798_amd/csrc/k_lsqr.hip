@@ -747,23 +747,38 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ Rinv,
 #pragma unroll
   for (int k = 0; k < kMaxK; ++k) rv[k] = k < K ? Rinv[i * d + jj0 + kPhases * k] : 0.0;
   const double beta = st->beta_new;
+  // entries j = tid + 256 q; for d <= 512 both of a thread's entries load
+  // their partials at once (one round of memory latency instead of two)
+  constexpr int kSl = NBV <= 512 / kVRows ? 2 : 1;
   double a2 = 0.0;
-  for (int64_t j = tid; j < d; j += 256) {
+  for (int64_t j0 = tid; j0 < d; j0 += 256 * kSl) {
     // the shares of workgroups b <= j / kVRows, loaded unconditionally
-    // (row index clamped) and summed in order
-    const int nbj = (int)(j / kVRows) + 1;
-    double pv[NBV];
+    // (row index and j clamped) and summed in order
+    double pv[kSl][NBV], vj[kSl];
 #pragma unroll
-    for (int b = 0; b < NBV; ++b)
-      pv[b] = vpart[(int64_t)(b < nbj ? b : nbj - 1) * d + j];
-    const double vj = init ? 0.0 : v_in[j];
-    double sv = 0.0;
+    for (int q = 0; q < kSl; ++q) {
+      const int64_t j = j0 + 256 * q;
+      const int64_t jc = j < d ? j : d - 1;
+      const int nbj = (int)(jc / kVRows) + 1;
 #pragma unroll
-    for (int b = 0; b < NBV; ++b)
-      if (b < nbj) sv += pv[b];
-    const double val = init ? sv : sv - beta * vj;
-    vn[j] = val;
-    a2 += val * val;
+      for (int b = 0; b < NBV; ++b)
+        pv[q][b] = vpart[(int64_t)(b < nbj ? b : nbj - 1) * d + jc];
+      vj[q] = init ? 0.0 : v_in[jc];
+    }
+#pragma unroll
+    for (int q = 0; q < kSl; ++q) {
+      const int64_t j = j0 + 256 * q;
+      if (j < d) {
+        const int nbj = (int)(j / kVRows) + 1;
+        double sv = 0.0;
+#pragma unroll
+        for (int b = 0; b < NBV; ++b)
+          if (b < nbj) sv += pv[q][b];
+        const double val = init ? sv : sv - beta * vj[q];
+        vn[j] = val;
+        a2 += val * val;
+      }
+    }
   }
   a2 = wave_sum(a2);
   if ((tid & 63) == 0) a2red[tid >> 6] = a2;
