@@ -24,6 +24,12 @@ constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per block
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 4096 per block
+// the sort's kernels give each thread one digit (histogram, offsets, runs),
+// keep per-wavefront digit counts for four wavefronts, and call the block
+// scan, which is sized for kScanThreads
+static_assert(kRadix == kSortThreads && kSortThreads == kScanThreads,
+              "one thread per digit in the sort and scan kernels");
+static_assert(kSortThreads == 4 * 64, "the scatter's per-wavefront counts assume four wavefronts");
 
 // ---------------------------------------------------------------------------
 // hash
