@@ -42,29 +42,76 @@ __device__ double block_sum(double v, double *red) {
   return t;
 }
 
-// M <- M / ||M||_F (M = 0 stays 0); one workgroup
-__global__ __launch_bounds__(256) void k_frob_normalise(double *__restrict__ M, int64_t len) {
+// M <- M / ||M||_F (M = 0 stays 0) in two launches: k_frob_parts sums the
+// squares of kNrmParts equal slices of M, one workgroup each; k_frob_scale
+// adds the slice sums (one wavefront's fixed butterfly, the same in every
+// workgroup) and scales M.
+constexpr int kNrmParts = 64;
+
+__global__ __launch_bounds__(256) void k_frob_parts(const double *__restrict__ M, int64_t len,
+                                                    double *__restrict__ part) {
   __shared__ double red[4];
+  const int64_t per = ceil_div(len, (int64_t)kNrmParts);
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < len ? lo + per : len;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < len; i += 256) s += M[i] * M[i];
-  const double nrm = sqrt(block_sum(s, red));
-  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  for (int64_t i = threadIdx.x; i < len; i += 256) M[i] *= inv;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += M[i] * M[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// delta = sqrt(v^T W v / v^T v) for v the column of M of largest norm
-// (0 when M is 0); one workgroup
-__global__ __launch_bounds__(256) void k_rayleigh(const double *__restrict__ M,
-                                                  const double *__restrict__ W, int64_t d,
-                                                  double *__restrict__ delta) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(256) void k_frob_scale(double *__restrict__ M, int64_t len,
+                                                    const double *__restrict__ part) {
+  static_assert(kNrmParts == 64, "one partial per lane");
+  const double t = wave_sum(part[threadIdx.x & 63]);
+  const double nrm = sqrt(t);
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * 256)
+    M[i] *= inv;
+}
+
+// Squared column norms of M in kColSlices row slices: workgroup (x, y) takes
+// columns 64 x .. 64 x + 63 (lanes) over the rows of slice y, its four
+// wavefronts every fourth row, and writes the slice's sums (wavefronts in
+// order) to cnp[y][j].
+constexpr int kColSlices = 16;
+
+__global__ __launch_bounds__(256) void k_col_norms(const double *__restrict__ M, int64_t d,
+                                                   double *__restrict__ cnp) {
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t per = ceil_div(d, (int64_t)kColSlices);
+  const int64_t lo = (int64_t)blockIdx.y * per;
+  const int64_t hi = lo + per < d ? lo + per : d;
+  double s = 0.0;
+  if (j < d)
+    for (int64_t i = lo + w; i < hi; i += 4) {
+      const double v = M[i * d + j];
+      s += v * v;
+    }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && j < d) cnp[blockIdx.y * d + j] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// The Rayleigh quotient's terms for v = the column of M of largest norm (the
+// first such column on ties; the slices' sums added in slice order): every
+// workgroup finds that column the same way, then each wavefront takes one
+// row i of W, lanes along the row, and writes qv[i] = v_i (W v)_i and
+// qv[d + i] = v_i^2.
+__global__ __launch_bounds__(256) void k_rayleigh_rows(const double *__restrict__ M,
+                                                       const double *__restrict__ W, int64_t d,
+                                                       const double *__restrict__ cnp,
+                                                       double *__restrict__ qv) {
   __shared__ double best_s[256];
   __shared__ int best_j[256];
   double bs = -1.0;
   int bj = 0;
   for (int64_t j = threadIdx.x; j < d; j += 256) {
     double s = 0.0;
-    for (int64_t i = 0; i < d; ++i) s += M[i * d + j] * M[i * d + j];
+    for (int q = 0; q < kColSlices; ++q) s += cnp[q * d + j];
     if (s > bs) {
       bs = s;
       bj = (int)j;
@@ -81,19 +128,39 @@ __global__ __launch_bounds__(256) void k_rayleigh(const double *__restrict__ M,
       }
   }
   __syncthreads();
-  const int j = best_j[0];
-  // v = M[:, j]; q = v^T W v, nv = v^T v
+  const int64_t j = best_j[0];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 4 + w;
+  if (i >= d) return;
+  double acc = 0.0;
+  for (int64_t k = lane; k < d; k += 64) acc += W[i * d + k] * M[k * d + j];
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const double vi = M[i * d + j];
+    qv[i] = vi * acc;
+    qv[d + i] = vi * vi;
+  }
+}
+
+// delta = sqrt(v^T W v / v^T v) from the row terms (0 when v is 0); one
+// workgroup, fixed order
+__global__ __launch_bounds__(256) void k_rayleigh_final(const double *__restrict__ qv,
+                                                        int64_t d, double *__restrict__ delta) {
+  __shared__ double red[4];
   double q = 0.0, nv = 0.0;
   for (int64_t i = threadIdx.x; i < d; i += 256) {
-    const double vi = M[i * d + j];
-    double wv = 0.0;
-    for (int64_t k = 0; k < d; ++k) wv += W[i * d + k] * M[k * d + j];
-    q += vi * wv;
-    nv += vi * vi;
+    q += qv[i];
+    nv += qv[d + i];
   }
   q = block_sum(q, red);
   nv = block_sum(nv, red);
   if (threadIdx.x == 0) *delta = nv > 0.0 ? sqrt(fmax(q / nv, 0.0)) : 0.0;
+}
+
+void frob_normalise(double *M, int64_t len, double *part, hipStream_t st) {
+  k_frob_parts<<<kNrmParts, 256, 0, st>>>(M, len, part);
+  const int64_t nb = ceil_div(len, (int64_t)256);
+  k_frob_scale<<<(unsigned)(nb < 2048 ? nb : 2048), 256, 0, st>>>(M, len, part);
 }
 
 }  // namespace
@@ -105,6 +172,9 @@ int delta_from_factor(const double *Chat, const double *C, const double *Ri, int
   double *W = ws.take<double>((size_t)d * d);
   double *M0 = ws.take<double>((size_t)d * d);
   double *M1 = ws.take<double>((size_t)d * d);
+  double *part = ws.take<double>(kNrmParts);
+  double *cnp = ws.take<double>((size_t)kColSlices * d);
+  double *qv = ws.take<double>((size_t)2 * d);
   const bool run = !ws.dry();
   if (run && !ws.ok()) return fail(PSK_ENOMEM, "workspace too small for sketch_delta");
   const size_t mk = ws.mark();
@@ -121,19 +191,21 @@ int delta_from_factor(const double *Chat, const double *C, const double *Ri, int
   if (run) {
     PSK_HIP_TRY(hipMemcpyAsync(M0, W, (size_t)d * d * sizeof(double), hipMemcpyDeviceToDevice,
                                st));
-    k_frob_normalise<<<1, 256, 0, st>>>(M0, d * d);
+    frob_normalise(M0, d * d, part, st);
   }
   double *a = M0, *b = M1;
   for (int i = 0; i < kSquarings; ++i) {
     if ((rc = dgemm(false, false, d, d, d, 1.0, a, d, a, d, 0.0, b, d, ws, st))) return rc;
     ws.release(mk);
-    if (run) k_frob_normalise<<<1, 256, 0, st>>>(b, d * d);
+    if (run) frob_normalise(b, d * d, part, st);
     double *t = a;
     a = b;
     b = t;
   }
   if (run) {
-    k_rayleigh<<<1, 256, 0, st>>>(a, W, d, delta);
+    k_col_norms<<<dim3((unsigned)ceil_div(d, (int64_t)64), kColSlices), 256, 0, st>>>(a, d, cnp);
+    k_rayleigh_rows<<<(unsigned)ceil_div(d, (int64_t)4), 256, 0, st>>>(a, W, d, cnp, qv);
+    k_rayleigh_final<<<1, 256, 0, st>>>(qv, d, delta);
     PSK_HIP_TRY(hipGetLastError());
   }
   return 0;
