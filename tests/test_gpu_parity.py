@@ -759,6 +759,21 @@ def test_sketch_delta_vs_oracle(api, prec, kind, n, d, m, r):
     assert dd < 0.5
 
 
+@pytest.mark.parametrize("m,d", [(5, 1), (7, 3), (2400, 1100)])
+def test_sketch_delta_shapes(api, m, d):
+    """delta at the size extremes (one column; a few; d above 1024 and not a
+    multiple of 64, so several column blocks and several columns per
+    thread in the choice of the dominant column) against the oracle's exact
+    value, for C^ = C + E with a random E of relative size 1e-3."""
+    rng = np.random.default_rng(m + d)
+    c = rng.standard_normal((m, d))
+    ch = c + 1e-3 * rng.standard_normal((m, d))
+    dd = api.sketch_delta(torch.from_numpy(ch).cuda(), torch.from_numpy(c).cuda()).item()
+    do = olev.sketch_perturbation(ch, c)
+    _say(f"sketch_delta m={m} d={d}: device {dd:.9e} oracle {do:.9e}")
+    assert do * (1 - 1e-6) <= dd <= do * (1 + 1e-9)
+
+
 def test_sketch_delta_closed_forms(api):
     c = torch.from_numpy(osk.sketch_gcs(synth.dense_gaussian(4000, 30, seed=1), 90, 600, 2))
     c = c.cuda()
