@@ -752,18 +752,20 @@ __global__ __launch_bounds__(256) void k_update(const double *__restrict__ Rinv,
   constexpr int kSl = NBV <= 512 / kVRows ? 2 : 1;
   double a2 = 0.0;
   for (int64_t j0 = tid; j0 < d; j0 += 256 * kSl) {
-    // the shares of workgroups b <= j / kVRows, loaded unconditionally
-    // (row index and j clamped) and summed in order
+    // the shares of workgroups b <= j / kVRows, loaded unconditionally for
+    // j < d (row index clamped) and summed in order; an entry j >= d loads
+    // nothing and is not used
     double pv[kSl][NBV], vj[kSl];
 #pragma unroll
     for (int q = 0; q < kSl; ++q) {
       const int64_t j = j0 + 256 * q;
-      const int64_t jc = j < d ? j : d - 1;
-      const int nbj = (int)(jc / kVRows) + 1;
+      if (j < d) {
+        const int nbj = (int)(j / kVRows) + 1;
 #pragma unroll
-      for (int b = 0; b < NBV; ++b)
-        pv[q][b] = vpart[(int64_t)(b < nbj ? b : nbj - 1) * d + jc];
-      vj[q] = init ? 0.0 : v_in[jc];
+        for (int b = 0; b < NBV; ++b)
+          pv[q][b] = vpart[(int64_t)(b < nbj ? b : nbj - 1) * d + j];
+        vj[q] = init ? 0.0 : v_in[j];
+      }
     }
 #pragma unroll
     for (int q = 0; q < kSl; ++q) {
