@@ -355,11 +355,18 @@ def csr_workload(api, torch, steps, warmup, seed):
             torch.cuda.synchronize()
             st = kt.stats()
         res = float(np.linalg.norm(b - a @ x.cpu().numpy()))
+        delta, delta_ms = 0.0, None
+        if prec != "f64":
+            # the perturbation against the FP64 sketch (outside the step),
+            # and what one such call costs (its QR of C included)
+            delta = api.sketch_delta(C, c64).item()
+            dwall, _ = timed(torch, lambda: api.sketch_delta(C, c64), 3, 1)
+            delta_ms = 1e3 * dwall
         out[prec] = {"gbs": nbytes / wall / 1e9, "ms_per_step": 1e3 * wall,
                      "solves_per_s": 1.0 / wall,
                      "p50_ms": float(np.percentile(lat, 50)),
                      "p99_ms": float(np.percentile(lat, 99)),
-                     "delta": api.sketch_delta(C, c64).item() if prec != "f64" else 0.0,
+                     "delta": delta, "delta_ms": delta_ms,
                      "lsq": {"iters": info["iters"], "status": info["status"], "resid": res},
                      "stage_ms": {k: round(v[0], 4) for k, v in sorted(st.items())}}
     out["bf16_vs_fp64_step"] = out["f64"]["ms_per_step"] / out["bf16"]["ms_per_step"]
